@@ -1,0 +1,390 @@
+"""The oracle: a plain FP64 CPU reference for the SPH neighbour loops.
+
+TEST INFRASTRUCTURE ONLY. Only the tests, the smoke check and the CPU-baseline
+leg of the benchmark import this package. It never imports the library
+package and the library never imports it; the seeded input generators are the
+only code both use, and they hold none of the method's arithmetic.
+
+The arithmetic lives in ``sph_oracle.c`` (one plain loop per definition of the
+paper's Section 3). This module marshals arrays, drives the per-particle
+Newton-Raphson iteration on the smoothing length, and produces neighbour
+candidate lists:
+
+* ``mode="brute"`` -- every receiver is tested against every particle.
+* ``mode="tree"``  -- a scipy k-d tree supplies an ascending superset of the
+  neighbours (radius padded by 1e-9 relative); the C code applies the same
+  exact membership test as in brute mode, so both modes are bit-identical.
+
+Parity note: every function here is pinned by the tests in
+``tests/test_oracle_*.py`` against closed forms, invariants and brute force.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+from dataclasses import dataclass, field
+from typing import Optional
+
+import numpy as np
+
+from . import build as _build
+
+_LIB = None
+
+_dp = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+_ip = np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")
+_i32p = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
+
+
+def _nullable(p):
+    """ctypes argtype that accepts None or a contiguous array."""
+    class _N:
+        @classmethod
+        def from_param(cls, obj):
+            if obj is None:
+                return None
+            return p.from_param(obj)
+    return _N
+
+
+def lib():
+    global _LIB
+    if _LIB is None:
+        path = _build.LIB
+        if not os.path.exists(path):
+            _build.build()
+        L = C.CDLL(path)
+        L.or_wc2_array.argtypes = [C.c_int64, _dp, _dp, C.c_double, _dp, _dp, _dp]
+        L.or_wc2_array.restype = None
+        L.or_density.argtypes = ([C.c_int64] + [_dp] * 8 + [_dp, C.c_int, C.c_double, C.c_int64,
+                                 _nullable(_ip), _nullable(_ip), _nullable(_ip)] + [_dp] * 8 + [_ip])
+        L.or_density.restype = C.c_int64
+        L.or_h_update.argtypes = [C.c_int64, _dp, _dp, _dp, C.c_double, C.c_double, C.c_double,
+                                  _dp, _i32p]
+        L.or_h_update.restype = None
+        L.or_ghost.argtypes = ([C.c_int64] + [_dp] * 8 + [C.c_double, C.c_double] + [_dp] * 7)
+        L.or_ghost.restype = None
+        L.or_force.argtypes = ([C.c_int64] + [_dp] * 16 + [_dp, C.c_int, C.c_double, C.c_double,
+                               C.c_int64, _nullable(_ip), _nullable(_ip), _nullable(_ip)]
+                               + [_dp] * 5 + [_ip])
+        L.or_force.restype = C.c_int64
+        L.or_sums.argtypes = [C.c_int64] + [_dp] * 8 + [_dp]
+        L.or_sums.restype = None
+        _LIB = L
+    return _LIB
+
+
+@dataclass
+class Params:
+    """Method parameters, with the paper's values where it gives them."""
+
+    box: tuple = (1.0, 1.0, 1.0)
+    periodic: bool = True
+    # H = gamma_k h; sqrt(15)/2 makes h twice the kernel's standard deviation.
+    gamma_k: float = math.sqrt(15.0) / 2.0
+    eta: float = 1.2348
+    gamma_gas: float = 5.0 / 3.0   # ratio of specific heats (Section 8, gas gamma 5/3)
+    beta_v: float = 3.0            # signal-velocity constant (Section 3.2)
+    eps_b: float = 1e-4            # Balsara switch regulariser (Section 3.2)
+    h_tol: float = 1e-4            # relative Newton-Raphson tolerance (Section 3.1)
+    max_iter: int = 30
+    h_max: Optional[float] = None  # default: min(box) / (3 gamma_k) * (1 - 1e-6)
+
+    def hmax(self) -> float:
+        if self.h_max is not None:
+            return float(self.h_max)
+        return min(self.box) / (3.0 * self.gamma_k) * (1.0 - 1e-6)
+
+
+def _f64(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def _pos(ps):
+    return _f64(ps.x), _f64(ps.y), _f64(ps.z)
+
+
+def _recv_arr(recv, n):
+    if recv is None:
+        return None, n
+    r = np.ascontiguousarray(np.asarray(recv, dtype=np.int64))
+    return r, int(r.shape[0])
+
+
+def wc2(r, h, gamma_k=Params.gamma_k):
+    """Vectorised W, dW/dr, dW/dh of the Wendland C2 kernel."""
+    r = _f64(np.atleast_1d(r))
+    h = _f64(np.broadcast_to(np.asarray(h, dtype=np.float64), r.shape))
+    w = np.empty_like(r)
+    d1 = np.empty_like(r)
+    d2 = np.empty_like(r)
+    lib().or_wc2_array(r.shape[0], r, h, float(gamma_k), w, d1, d2)
+    return w, d1, d2
+
+
+# ---------------------------------------------------------------------------
+# Candidate lists (k-d tree supersets; the C code decides membership).
+# ---------------------------------------------------------------------------
+
+def _wrapped_positions(ps, periodic):
+    p = np.stack(_pos(ps), axis=1)
+    if periodic:
+        b = np.asarray(ps.box, dtype=np.float64)
+        p = np.mod(p, b)
+        p = np.where(p >= b, p - b, p)
+    return p
+
+
+def _tree(p, ps, periodic):
+    from scipy.spatial import cKDTree
+    return cKDTree(p, boxsize=np.asarray(ps.box, dtype=np.float64) if periodic else None)
+
+
+def _pairs(lists, k_offset=0):
+    lens = np.fromiter((len(l) for l in lists), count=len(lists), dtype=np.int64)
+    if lens.sum() == 0:
+        return np.zeros(0, np.int64), np.zeros(0, np.int64)
+    idx = np.concatenate([np.asarray(l, dtype=np.int64) for l in lists if len(l)])
+    k = np.repeat(np.arange(len(lists), dtype=np.int64) + k_offset, lens)
+    return k, idx
+
+
+def _csr(k, idx, nrecv, n):
+    key = np.unique(k * np.int64(n) + idx)
+    kk = key // n
+    jj = key - kk * n
+    off = np.zeros(nrecv + 1, np.int64)
+    np.add.at(off, kk + 1, 1)
+    off = np.cumsum(off)
+    return np.ascontiguousarray(off), np.ascontiguousarray(jj)
+
+
+_PAD = 1.0 + 1e-9
+
+
+def density_candidates(ps, h, params: Params, recv):
+    """Ascending superset of {j : |x_i - x_j| < H_i} for each receiver."""
+    p = _wrapped_positions(ps, params.periodic)
+    tree = _tree(p, ps, params.periodic)
+    ri = np.arange(ps.n) if recv is None else np.asarray(recv)
+    H = params.gamma_k * np.asarray(h, dtype=np.float64)
+    ks, js = [], []
+    chunk = 65536
+    for s in range(0, len(ri), chunk):
+        sl = ri[s:s + chunk]
+        lists = tree.query_ball_point(p[sl], H[sl] * _PAD, return_sorted=True)
+        k, j = _pairs(lists, s)
+        ks.append(k)
+        js.append(j)
+    return _csr(np.concatenate(ks), np.concatenate(js), len(ri), ps.n)
+
+
+def force_candidates(ps, h, params: Params, recv):
+    """Ascending superset of {j : |x_i - x_j| < max(H_i, H_j)}: the H_i part
+    from one tree query, the H_j part from trees over bands of H (factor 2)."""
+    p = _wrapped_positions(ps, params.periodic)
+    H = params.gamma_k * np.asarray(h, dtype=np.float64)
+    ri = np.arange(ps.n) if recv is None else np.asarray(recv)
+    tree = _tree(p, ps, params.periodic)
+    ks, js = [], []
+    chunk = 65536
+    for s in range(0, len(ri), chunk):
+        sl = ri[s:s + chunk]
+        k, j = _pairs(tree.query_ball_point(p[sl], H[sl] * _PAD, return_sorted=True), s)
+        ks.append(k)
+        js.append(j)
+    lo = float(H.min())
+    band = np.floor(np.log2(H / lo)).astype(np.int64)
+    for b in np.unique(band):
+        members = np.nonzero(band == b)[0]
+        sub = _tree(p[members], ps, params.periodic)
+        rb = float(H[members].max()) * _PAD
+        for s in range(0, len(ri), chunk):
+            sl = ri[s:s + chunk]
+            lists = sub.query_ball_point(p[sl], rb)
+            k, j = _pairs(lists, s)
+            ks.append(k)
+            js.append(members[j])
+    return _csr(np.concatenate(ks), np.concatenate(js), len(ri), ps.n)
+
+
+def _resolve_mode(mode, n):
+    if mode == "auto":
+        return "brute" if n <= 8192 else "tree"
+    return mode
+
+
+# ---------------------------------------------------------------------------
+# The passes.
+# ---------------------------------------------------------------------------
+
+def density(ps, h, params: Params, recv=None, mode="auto"):
+    """Density sums at the given h for the receivers (Section 3.1)."""
+    mode = _resolve_mode(mode, ps.n)
+    h = _f64(h)
+    r, nrecv = _recv_arr(recv, ps.n)
+    off = idx = None
+    if mode == "tree":
+        off, idx = density_candidates(ps, h, params, r)
+    out = {k: np.zeros(nrecv) for k in ("rho", "rho_dh", "n", "n_dh", "div_sum",
+                                        "curl_x", "curl_y", "curl_z")}
+    nngb = np.zeros(nrecv, np.int64)
+    x, y, z = _pos(ps)
+    total = lib().or_density(ps.n, x, y, z, _f64(ps.vx), _f64(ps.vy), _f64(ps.vz), _f64(ps.m), h,
+                             _f64(ps.box), int(params.periodic), float(params.gamma_k), nrecv, r,
+                             off, idx, out["rho"], out["rho_dh"], out["n"], out["n_dh"],
+                             out["div_sum"], out["curl_x"], out["curl_y"], out["curl_z"], nngb)
+    out["nngb"] = nngb
+    out["total"] = int(total)
+    return out
+
+
+def h_update(h, nd, nd_dh, params: Params):
+    h = _f64(h)
+    hn = np.empty_like(h)
+    conv = np.empty(h.shape[0], np.int32)
+    lib().or_h_update(h.shape[0], h, _f64(nd), _f64(nd_dh), float(params.eta),
+                      float(params.h_tol), float(params.hmax()), hn, conv)
+    return hn, conv.astype(bool)
+
+
+def ghost(dens, u, h, params: Params):
+    """Pressure, sound speed, f-factor, Balsara switch and A = f P / rho^2."""
+    n = dens["rho"].shape[0]
+    out = {k: np.zeros(n) for k in ("f", "P", "c", "balsara", "A", "div_v", "curl_v")}
+    lib().or_ghost(n, _f64(dens["rho"]), _f64(dens["rho_dh"]), _f64(dens["div_sum"]),
+                   _f64(dens["curl_x"]), _f64(dens["curl_y"]), _f64(dens["curl_z"]), _f64(u),
+                   _f64(h), float(params.gamma_gas), float(params.eps_b), out["f"], out["P"],
+                   out["c"], out["balsara"], out["A"], out["div_v"], out["curl_v"])
+    return out
+
+
+def solve_h(ps, params: Params, recv=None, mode="auto", h0=None):
+    """Per-particle Newton-Raphson on n(h) h^3 = eta^3 (Section 3.1).
+
+    Each receiver iterates independently (its sums depend only on its own h).
+    Returns the final h (the one the returned sums were evaluated at), the
+    density sums there, a converged flag and the number of passes used.
+    """
+    mode = _resolve_mode(mode, ps.n)
+    ri = np.arange(ps.n) if recv is None else np.asarray(recv, dtype=np.int64)
+    nr = ri.shape[0]
+    h_all = _f64(ps.h if h0 is None else h0).copy()
+    h_all = np.minimum(h_all, params.hmax())
+    h = h_all[ri].copy()
+    conv = np.zeros(nr, bool)
+    dens = None
+    todo = np.arange(nr)
+    iters = np.zeros(nr, np.int32)
+    passes = 0
+    while todo.size and passes < params.max_iter:
+        passes += 1
+        h_all[ri[todo]] = h[todo]
+        d = density(ps, h_all, params, recv=ri[todo], mode=mode)
+        if dens is None:
+            dens = {k: np.zeros(nr, dtype=v.dtype) for k, v in d.items() if k != "total"}
+        for k, v in d.items():
+            if k != "total":
+                dens[k][todo] = v
+        iters[todo] += 1
+        hn, c = h_update(h[todo], d["n"], d["n_dh"], params)
+        conv[todo] = c
+        last = passes == params.max_iter
+        # A receiver still unconverged after the last allowed pass keeps the
+        # h its sums were evaluated at.
+        if not last:
+            h[todo] = hn
+        todo = todo[~c]
+    return h, dens, conv, iters, passes
+
+
+def force(ps, h, gst, dens_rho, params: Params, recv=None, mode="auto"):
+    """Accelerations, du/dt and signal velocity for the receivers (Sections
+    3.2, 3.3). ``gst`` and ``dens_rho`` hold every particle's ghost state
+    (only neighbours' entries are read)."""
+    mode = _resolve_mode(mode, ps.n)
+    h = _f64(h)
+    r, nrecv = _recv_arr(recv, ps.n)
+    off = idx = None
+    if mode == "tree":
+        off, idx = force_candidates(ps, h, params, r)
+    out = {k: np.zeros(nrecv) for k in ("ax", "ay", "az", "du", "vsig")}
+    nf = np.zeros(nrecv, np.int64)
+    x, y, z = _pos(ps)
+    total = lib().or_force(ps.n, x, y, z, _f64(ps.vx), _f64(ps.vy), _f64(ps.vz), _f64(ps.m),
+                           _f64(ps.u), h, _f64(dens_rho), _f64(gst["P"]), _f64(gst["c"]),
+                           _f64(gst["f"]), _f64(gst["balsara"]), _f64(ps.alpha_v),
+                           _f64(ps.alpha_c), _f64(ps.box), int(params.periodic),
+                           float(params.gamma_k), float(params.beta_v), nrecv, r, off, idx,
+                           out["ax"], out["ay"], out["az"], out["du"], out["vsig"], nf)
+    out["nforce"] = nf
+    out["total"] = int(total)
+    return out
+
+
+def sums(m, vx, vy, vz, ax, ay, az, du):
+    out = np.zeros(6)
+    lib().or_sums(len(m), _f64(m), _f64(vx), _f64(vy), _f64(vz), _f64(ax), _f64(ay), _f64(az),
+                  _f64(du), out)
+    return out
+
+
+def force_needed(ps, h, params: Params, recv, mode="auto"):
+    """Receivers plus every particle inside their force neighbourhoods."""
+    mode = _resolve_mode(mode, ps.n)
+    if recv is None:
+        return np.arange(ps.n)
+    if mode == "brute":
+        return np.arange(ps.n)
+    off, idx = force_candidates(ps, _f64(h), params, np.asarray(recv, np.int64))
+    return np.unique(np.concatenate([np.asarray(recv, np.int64), idx]))
+
+
+def fixed_h_step(ps, params: Params, recv=None, mode="auto", h=None):
+    """Density, ghost and force at the given (input) h, no iteration.
+
+    Density and ghost are evaluated for the receivers and everything in their
+    force neighbourhoods; the force for the receivers only. Entries of
+    particles outside that set are NaN so any stray read shows up.
+    """
+    h = _f64(ps.h if h is None else h)
+    need = force_needed(ps, h, params, recv, mode)
+    d = density(ps, h, params, recv=need, mode=mode)
+    g = ghost(d, _f64(ps.u)[need], h[need], params)
+    full = {k: np.full(ps.n, np.nan) for k in ("P", "c", "f", "balsara")}
+    rho = np.full(ps.n, np.nan)
+    for k in full:
+        full[k][need] = g[k]
+    rho[need] = d["rho"]
+    fo = force(ps, h, full, rho, params, recv=recv, mode=mode)
+    ri = np.arange(ps.n) if recv is None else np.asarray(recv, np.int64)
+    pos = np.searchsorted(need, ri)
+    res = {"h": h[ri]}
+    for k, v in d.items():
+        if k != "total":
+            res[k] = v[pos]
+    for k, v in g.items():
+        res[k] = v[pos]
+    for k, v in fo.items():
+        if k != "total":
+            res[k] = v
+    res["n_dens_total"] = int(res["nngb"].sum())
+    res["n_force_total"] = fo["total"]
+    return res
+
+
+def nr_step(ps, params: Params, mode="auto"):
+    """Full step on every particle: h iteration with its density passes,
+    ghost, force and the global sums."""
+    h, dens, conv, iters, passes = solve_h(ps, params, mode=mode)
+    g = ghost(dens, ps.u, h, params)
+    fo = force(ps, h, g, dens["rho"], params, mode=mode)
+    res = {"h": h, "converged": conv, "iters": iters, "passes": passes}
+    res.update({k: v for k, v in dens.items()})
+    res.update(g)
+    res.update({k: v for k, v in fo.items() if k != "total"})
+    res["sums"] = sums(ps.m, ps.vx, ps.vy, ps.vz, fo["ax"], fo["ay"], fo["az"], fo["du"])
+    res["n_dens_total"] = int(dens["nngb"].sum())
+    res["n_force_total"] = fo["total"]
+    return res

@@ -1,0 +1,329 @@
+/*
+ * sph_oracle.c -- the oracle for the SPH neighbour loops.
+ *
+ * TEST INFRASTRUCTURE ONLY. This file is a plain, slow, obviously correct
+ * FP64 CPU implementation of what the density, ghost and force passes
+ * compute, written from the definitions in the paper (Schaller et al.,
+ * "SWIFT", Section 3). Only the test suite, the smoke check and the CPU
+ * baseline leg of the benchmark load it. It shares no code, header or
+ * constant with the HIP library, and the library never calls it.
+ *
+ * Every receiver i is summed over its neighbours j in increasing index
+ * order, one pair at a time, with no blocking or reordering. The neighbour
+ * set is either every particle (brute force, cand_off == NULL) or an
+ * ascending candidate list per receiver (produced by the Python layer from a
+ * k-d tree as a superset); in both cases the exact membership test below
+ * decides, so both modes give bit-identical results.
+ *
+ * Readings of the paper taken here (each one also listed in the design notes):
+ *  - kernel: Wendland C2 in 3D, W(r,h) = 21/(2 pi H^3) (4u^5 - 15u^4 + 20u^3
+ *    - 10u^2 + 1), u = r/H, H = gamma_k h (Sections 3.1 and 4.1); gamma_k is
+ *    a parameter (sqrt(15)/2 for h = twice the kernel's standard deviation).
+ *  - the self term is included in rho, n and their h-derivatives and excluded
+ *    from the neighbour count; j is a neighbour of i iff r_ij < H_i (strict).
+ *  - velocity divergence and curl use the difference form v_j - v_i in the
+ *    paper's smoothed-derivative estimators; the curl is that of the kernel
+ *    interpolant, grad W x v (only its magnitude enters the Balsara switch).
+ *  - f_i = [1 + h_i/(3 rho_i) d rho_i/dh]^-1 (the inverse is the one written
+ *    in the comoving section).
+ *  - viscosity: alpha_ij = mean(alpha_V) * mean(B) (the symmetric form of the
+ *    default scheme), nu_ij uses the mean density 0.5(rho_i + rho_j), and the
+ *    kernel-gradient factor of both the momentum and the energy terms is
+ *    G_ij = f_i W'(r,h_i) + f_j W'(r,h_j), which makes the pair exchange
+ *    conserve momentum and energy exactly.
+ *  - conduction: scalar radial gradient G_ij, v_c uses rho_i + rho_j.
+ *  - force neighbours: j != i with r_ij < max(H_i, H_j).
+ */
+#include <math.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#define OR_PI 3.14159265358979323846
+
+/* Wendland C2, 3D (Section 4.1 prints the polynomial; Section 3.1 defines
+ * W(r,h) = h^-3 w(r/h) with the cut-off H = gamma_k h). Returns W, dW/dr and
+ * dW/dh = -(3/h) W - (r/h) dW/dr (the summand of the paper's dn/dh). */
+void or_wc2(double r, double h, double gamma_k, double *w, double *dwdr, double *dwdh)
+{
+    double H = gamma_k * h;
+    double u = r / H;
+    if (!(u < 1.0)) {
+        *w = 0.0;
+        *dwdr = 0.0;
+        *dwdh = 0.0;
+        return;
+    }
+    double u2 = u * u, u3 = u2 * u, u4 = u3 * u, u5 = u4 * u;
+    double poly = 4.0 * u5 - 15.0 * u4 + 20.0 * u3 - 10.0 * u2 + 1.0;
+    double dpoly = 20.0 * u4 - 60.0 * u3 + 60.0 * u2 - 20.0 * u;
+    double norm = 21.0 / (2.0 * OR_PI * H * H * H);
+    *w = norm * poly;
+    *dwdr = norm * dpoly / H;
+    *dwdh = -3.0 / h * (*w) - r / h * (*dwdr);
+}
+
+void or_wc2_array(int64_t n, const double *r, const double *h, double gamma_k,
+                  double *w, double *dwdr, double *dwdh)
+{
+    for (int64_t k = 0; k < n; ++k)
+        or_wc2(r[k], h[k], gamma_k, &w[k], &dwdr[k], &dwdh[k]);
+}
+
+/* Minimum-image separation along one axis of a periodic box. */
+static double min_image(double d, double L, int periodic)
+{
+    if (!periodic)
+        return d;
+    return d - L * nearbyint(d / L);
+}
+
+/*
+ * Density pass (Section 3.1: number density, its h-derivative, mass density;
+ * smoothed divergence and curl of v). For receiver k (particle i = recv[k],
+ * or i = k when recv is NULL):
+ *   n_i      = sum_j W(r_ij, h_i)                (self included)
+ *   dn_i/dh  = sum_j dW/dh(r_ij, h_i)
+ *   rho_i    = sum_j m_j W(r_ij, h_i)
+ *   drho_i/dh= sum_j m_j dW/dh(r_ij, h_i)
+ *   div_sum  = sum_{j!=i} m_j (v_j - v_i) . grad_i W_ij
+ *   curl_sum = sum_{j!=i} m_j grad_i W_ij x (v_j - v_i)
+ *   nngb_i   = #{ j != i : r_ij < H_i }
+ * with grad_i W_ij = dW/dr (r_ij, h_i) x_ij / r_ij and x_ij = x_i - x_j
+ * (minimum image). Returns the total neighbour count.
+ */
+int64_t or_density(int64_t n, const double *x, const double *y, const double *z,
+                   const double *vx, const double *vy, const double *vz,
+                   const double *m, const double *h, const double *box, int periodic,
+                   double gamma_k, int64_t nrecv, const int64_t *recv,
+                   const int64_t *cand_off, const int64_t *cand_idx,
+                   double *rho, double *rho_dh, double *nd, double *nd_dh,
+                   double *div_sum, double *curl_x, double *curl_y, double *curl_z,
+                   int64_t *nngb)
+{
+    int64_t total = 0;
+#pragma omp parallel for schedule(dynamic, 16) reduction(+ : total)
+    for (int64_t k = 0; k < nrecv; ++k) {
+        int64_t i = recv ? recv[k] : k;
+        double hi = h[i], Hi = gamma_k * hi;
+        double s_rho = 0, s_rho_dh = 0, s_n = 0, s_n_dh = 0;
+        double s_div = 0, s_cx = 0, s_cy = 0, s_cz = 0;
+        int64_t cnt = 0;
+        int64_t jb = cand_off ? cand_off[k] : 0;
+        int64_t je = cand_off ? cand_off[k + 1] : n;
+        for (int64_t q = jb; q < je; ++q) {
+            int64_t j = cand_off ? cand_idx[q] : q;
+            double dx = min_image(x[i] - x[j], box[0], periodic);
+            double dy = min_image(y[i] - y[j], box[1], periodic);
+            double dz = min_image(z[i] - z[j], box[2], periodic);
+            double r = sqrt(dx * dx + dy * dy + dz * dz);
+            if (!(r < Hi))
+                continue;
+            double w, dwdr, dwdh;
+            or_wc2(r, hi, gamma_k, &w, &dwdr, &dwdh);
+            s_n += w;
+            s_n_dh += dwdh;
+            s_rho += m[j] * w;
+            s_rho_dh += m[j] * dwdh;
+            if (j == i)
+                continue;
+            cnt += 1;
+            if (r > 0.0) {
+                double gx = dwdr * dx / r, gy = dwdr * dy / r, gz = dwdr * dz / r;
+                double wx = vx[j] - vx[i], wy = vy[j] - vy[i], wz = vz[j] - vz[i];
+                s_div += m[j] * (wx * gx + wy * gy + wz * gz);
+                /* curl of the interpolant: grad W x (v_j - v_i) */
+                s_cx += m[j] * (gy * wz - gz * wy);
+                s_cy += m[j] * (gz * wx - gx * wz);
+                s_cz += m[j] * (gx * wy - gy * wx);
+            }
+        }
+        rho[k] = s_rho;
+        rho_dh[k] = s_rho_dh;
+        nd[k] = s_n;
+        nd_dh[k] = s_n_dh;
+        div_sum[k] = s_div;
+        curl_x[k] = s_cx;
+        curl_y[k] = s_cy;
+        curl_z[k] = s_cz;
+        nngb[k] = cnt;
+        total += cnt;
+    }
+    return total;
+}
+
+/*
+ * One Newton-Raphson update of h on the partition-of-unity condition
+ * (Section 3.1): F(h) = n(h) h^3 - eta^3 = 0, F'(h) = h^3 dn/dh + 3 h^2 n.
+ * The step is limited to [h/2, 2h] and to h <= h_max; when F' is not
+ * positive the step is a halving or doubling in the direction of -F. The
+ * particle is converged when the step is below h_tol * h; its h then stays
+ * at the value the sums were evaluated at.
+ */
+void or_h_update(int64_t n, const double *h, const double *nd, const double *nd_dh,
+                 double eta, double h_tol, double h_max, double *h_new, int32_t *converged)
+{
+    for (int64_t k = 0; k < n; ++k) {
+        double hk = h[k];
+        double F = nd[k] * hk * hk * hk - eta * eta * eta;
+        double dF = hk * hk * hk * nd_dh[k] + 3.0 * hk * hk * nd[k];
+        double hn;
+        if (dF > 0.0 && isfinite(F / dF))
+            hn = hk - F / dF;
+        else
+            hn = (F < 0.0) ? 2.0 * hk : 0.5 * hk;
+        if (hn < 0.5 * hk)
+            hn = 0.5 * hk;
+        if (hn > 2.0 * hk)
+            hn = 2.0 * hk;
+        if (hn > h_max)
+            hn = h_max;
+        if (fabs(hn - hk) < h_tol * hk) {
+            converged[k] = 1;
+            h_new[k] = hk;
+        } else {
+            converged[k] = 0;
+            h_new[k] = hn;
+        }
+    }
+}
+
+/*
+ * Ghost (Section 3.1 equation of state; Section 3.2 f-factor and Balsara
+ * switch): from the density sums at the final h,
+ *   P = (gamma - 1) u rho,  c = sqrt(gamma P / rho),
+ *   f = 1 / (1 + h/(3 rho) drho/dh),
+ *   div v = div_sum / rho,  |curl v| = |curl_sum| / rho,
+ *   B = |div v| / (|div v| + |curl v| + eps c / h),
+ *   A = f P / rho^2.
+ */
+void or_ghost(int64_t n, const double *rho, const double *rho_dh, const double *div_sum,
+              const double *curl_x, const double *curl_y, const double *curl_z,
+              const double *u, const double *h, double gamma_gas, double eps_b,
+              double *f, double *P, double *c, double *balsara, double *A,
+              double *div_v, double *curl_v)
+{
+    for (int64_t k = 0; k < n; ++k) {
+        double r = rho[k];
+        P[k] = (gamma_gas - 1.0) * u[k] * r;
+        c[k] = sqrt(gamma_gas * P[k] / r);
+        f[k] = 1.0 / (1.0 + h[k] / (3.0 * r) * rho_dh[k]);
+        div_v[k] = div_sum[k] / r;
+        curl_v[k] = sqrt(curl_x[k] * curl_x[k] + curl_y[k] * curl_y[k] + curl_z[k] * curl_z[k]) / r;
+        double ad = fabs(div_v[k]);
+        balsara[k] = ad / (ad + curl_v[k] + eps_b * c[k] / h[k]);
+        A[k] = f[k] * P[k] / (r * r);
+    }
+}
+
+/*
+ * Force pass (Section 3.2 density-energy equations of motion, artificial
+ * viscosity with the Balsara switch, Section 3.3 symmetric alpha_ij and the
+ * artificial conduction term). For receiver i and every j != i with
+ * r_ij < max(H_i, H_j):
+ *   g_i = dW/dr(r_ij, h_i), g_j = dW/dr(r_ij, h_j)   (zero outside support)
+ *   e = x_ij / r_ij, v_ij = v_i - v_j
+ *   mu = min(0, v_ij . x_ij) / r_ij
+ *   vsig_ij = c_i + c_j - beta mu
+ *   alpha_ij = (alpha_V,i + alpha_V,j)/2 * (B_i + B_j)/2
+ *   nu = -alpha_ij mu vsig_ij / (0.5 (rho_i + rho_j))
+ *   G = f_i g_i + f_j g_j
+ *   a_i  -= m_j [A_i g_i + A_j g_j + nu G / 2] e          (A = f P / rho^2)
+ *   du_i += m_j [A_i g_i + nu G / 4] (v_ij . e)
+ *   du_i += m_j alpha_c,ij v_c,ij (u_i - u_j) G / (rho_i + rho_j)
+ *   alpha_c,ij = (P_i alpha_c,i + P_j alpha_c,j) / (P_i + P_j)
+ *   v_c,ij = |v_ij . e| + sqrt(2 |P_i - P_j| / (rho_i + rho_j))
+ *   vsig_i = max(2 c_i, max_j vsig_ij)
+ * Coincident pairs (r = 0) are counted but add nothing (every term carries
+ * a kernel gradient, which vanishes at r = 0). Returns the total count.
+ */
+int64_t or_force(int64_t n, const double *x, const double *y, const double *z,
+                 const double *vx, const double *vy, const double *vz,
+                 const double *m, const double *u, const double *h,
+                 const double *rho, const double *P, const double *c, const double *f,
+                 const double *balsara, const double *alpha_v, const double *alpha_c,
+                 const double *box, int periodic, double gamma_k, double beta_v,
+                 int64_t nrecv, const int64_t *recv,
+                 const int64_t *cand_off, const int64_t *cand_idx,
+                 double *ax, double *ay, double *az, double *du, double *vsig, int64_t *nforce)
+{
+    int64_t total = 0;
+#pragma omp parallel for schedule(dynamic, 16) reduction(+ : total)
+    for (int64_t k = 0; k < nrecv; ++k) {
+        int64_t i = recv ? recv[k] : k;
+        double Hi = gamma_k * h[i];
+        double Ai = f[i] * P[i] / (rho[i] * rho[i]);
+        double s_ax = 0, s_ay = 0, s_az = 0, s_du = 0;
+        double s_vsig = 2.0 * c[i];
+        int64_t cnt = 0;
+        int64_t jb = cand_off ? cand_off[k] : 0;
+        int64_t je = cand_off ? cand_off[k + 1] : n;
+        for (int64_t q = jb; q < je; ++q) {
+            int64_t j = cand_off ? cand_idx[q] : q;
+            if (j == i)
+                continue;
+            double Hj = gamma_k * h[j];
+            double dx = min_image(x[i] - x[j], box[0], periodic);
+            double dy = min_image(y[i] - y[j], box[1], periodic);
+            double dz = min_image(z[i] - z[j], box[2], periodic);
+            double r = sqrt(dx * dx + dy * dy + dz * dz);
+            double Hmax = Hi > Hj ? Hi : Hj;
+            if (!(r < Hmax))
+                continue;
+            cnt += 1;
+            if (!(r > 0.0))
+                continue;
+            double w, gi, gj, dwdh;
+            or_wc2(r, h[i], gamma_k, &w, &gi, &dwdh);
+            or_wc2(r, h[j], gamma_k, &w, &gj, &dwdh);
+            double ex = dx / r, ey = dy / r, ez = dz / r;
+            double wx = vx[i] - vx[j], wy = vy[i] - vy[j], wz = vz[i] - vz[j];
+            double vdotx = wx * dx + wy * dy + wz * dz;
+            double vdote = wx * ex + wy * ey + wz * ez;
+            double mu = vdotx < 0.0 ? vdotx / r : 0.0;
+            double vsig_ij = c[i] + c[j] - beta_v * mu;
+            double alpha_ij = 0.5 * (alpha_v[i] + alpha_v[j]) * 0.5 * (balsara[i] + balsara[j]);
+            double nu = -alpha_ij * mu * vsig_ij / (0.5 * (rho[i] + rho[j]));
+            double Aj = f[j] * P[j] / (rho[j] * rho[j]);
+            double G = f[i] * gi + f[j] * gj;
+            double acc = Ai * gi + Aj * gj + 0.5 * nu * G;
+            s_ax -= m[j] * acc * ex;
+            s_ay -= m[j] * acc * ey;
+            s_az -= m[j] * acc * ez;
+            s_du += m[j] * (Ai * gi + 0.25 * nu * G) * vdote;
+            double psum = P[i] + P[j];
+            double alpha_c_ij = psum > 0.0 ? (P[i] * alpha_c[i] + P[j] * alpha_c[j]) / psum : 0.0;
+            double v_c = fabs(vdote) + sqrt(2.0 * fabs(P[i] - P[j]) / (rho[i] + rho[j]));
+            s_du += m[j] * alpha_c_ij * v_c * (u[i] - u[j]) * G / (rho[i] + rho[j]);
+            if (vsig_ij > s_vsig)
+                s_vsig = vsig_ij;
+        }
+        ax[k] = s_ax;
+        ay[k] = s_ay;
+        az[k] = s_az;
+        du[k] = s_du;
+        vsig[k] = s_vsig;
+        nforce[k] = cnt;
+        total += cnt;
+    }
+    return total;
+}
+
+/* Global conservation sums (the end-of-step reduction of Section 2):
+ * out[0..2] = sum m a, out[3] = sum m (v.a + du/dt),
+ * out[4] = sum m |a|, out[5] = sum m |du/dt|. Plain sequential FP64 sums. */
+void or_sums(int64_t n, const double *m, const double *vx, const double *vy, const double *vz,
+             const double *ax, const double *ay, const double *az, const double *du,
+             double *out)
+{
+    double s[6] = {0, 0, 0, 0, 0, 0};
+    for (int64_t k = 0; k < n; ++k) {
+        s[0] += m[k] * ax[k];
+        s[1] += m[k] * ay[k];
+        s[2] += m[k] * az[k];
+        s[3] += m[k] * (vx[k] * ax[k] + vy[k] * ay[k] + vz[k] * az[k] + du[k]);
+        s[4] += m[k] * sqrt(ax[k] * ax[k] + ay[k] * ay[k] + az[k] * az[k]);
+        s[5] += m[k] * fabs(du[k]);
+    }
+    for (int q = 0; q < 6; ++q)
+        out[q] = s[q];
+}
