@@ -1,0 +1,235 @@
+#!/usr/bin/env python3
+"""Benchmark: SPH pair interactions per second (density + force) on one GPU.
+
+One step = the whole hot path on device-resident inputs: every density pass of
+the smoothing-length iteration (from the initial h), the ghost passes, the
+force pass and the FP64 global sums (sphx_step through the C-ABI). Grid and
+task builds are timed separately, outside the step.
+
+value = (N_dens + N_force) / seconds per step, with
+  N_dens  = sum_i #{j != i : r_ij < H_i}            at the final h,
+  N_force = sum_i #{j != i : r_ij < max(H_i, H_j)}  (active receivers only).
+
+Prints one JSON line. See the design notes for the roofline accounting.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# FP32 FLOPs per accepted directed interaction, counted from the formulas as
+# the kernels evaluate them (FMA = 2, sqrt/rsqrt/rcp = 1; compares, min/max and
+# selects not counted).
+FLOP_DENSITY = 51
+FLOP_FORCE = 84
+PEAK_FP32_TFLOPS = 157.3  # MI355X published FP32 vector peak
+PEAK_HBM_GBS = 8000.0
+
+CONFIGS = {
+    "small": ("4,096-particle jittered lattice (16^3), u=1", lambda inp: inp.config_small(1)),
+    "sedov": ("Sedov blast, 64^3 = 262,144 particles on a jittered lattice",
+              lambda inp: inp.config_sedov(2)),
+    "clustered": ("clustered box, 128^3 = 2,097,152 particles, lognormal sigma=2, P(k)~k^-2",
+                  lambda inp: inp.config_clustered(3)),
+    "large": ("large clustered box, 256^3 = 16,777,216 particles, lognormal sigma=2.5, "
+              "~10% active", lambda inp: inp.config_large(5)),
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(ps, params_cls, n_recv, seed=0):
+    """The oracle (FP64, C + OpenMP, k-d tree candidates) timed on the host
+    for a bounded random sample of receivers: one density pass over the
+    receivers and every particle in their force neighbourhoods, the ghost, and
+    one force pass over the receivers. Candidate generation is excluded, as
+    the grid and task builds are on the GPU side."""
+    import numpy as np
+    import oracle
+    P = params_cls()
+    rng = np.random.default_rng(seed)
+    recv = np.sort(rng.choice(ps.n, size=min(n_recv, ps.n), replace=False))
+    h = np.asarray(ps.h, np.float64)
+    need = oracle.force_needed(ps, h, P, recv, mode="tree")
+    doff, didx = oracle.density_candidates(ps, h, P, need)
+    foff, fidx = oracle.force_candidates(ps, h, P, recv)
+    L = oracle.lib()
+    f64 = lambda a: np.ascontiguousarray(np.asarray(a, np.float64))
+    x, y, z = f64(ps.x), f64(ps.y), f64(ps.z)
+    vx, vy, vz, m, u = f64(ps.vx), f64(ps.vy), f64(ps.vz), f64(ps.m), f64(ps.u)
+    av, ac, box = f64(ps.alpha_v), f64(ps.alpha_c), f64(ps.box)
+    nd = len(need)
+    d = {k: np.zeros(nd) for k in ("rho", "rho_dh", "n", "n_dh", "div", "cx", "cy", "cz")}
+    nngb = np.zeros(nd, np.int64)
+    g = {k: np.zeros(nd) for k in ("f", "P", "c", "B", "A", "dv", "cv")}
+    full = {k: np.full(ps.n, np.nan) for k in ("rho", "P", "c", "f", "B")}
+    fo = {k: np.zeros(len(recv)) for k in ("ax", "ay", "az", "du", "vs")}
+    nf = np.zeros(len(recv), np.int64)
+    t0 = time.perf_counter()
+    tot_d = L.or_density(ps.n, x, y, z, vx, vy, vz, m, h, box, 1, P.gamma_k, nd,
+                         np.ascontiguousarray(need, np.int64), doff, didx, d["rho"], d["rho_dh"],
+                         d["n"], d["n_dh"], d["div"], d["cx"], d["cy"], d["cz"], nngb)
+    L.or_ghost(nd, d["rho"], d["rho_dh"], d["div"], d["cx"], d["cy"], d["cz"], u[need], h[need],
+               P.gamma_gas, P.eps_b, g["f"], g["P"], g["c"], g["B"], g["A"], g["dv"], g["cv"])
+    full["rho"][need] = d["rho"]
+    for k in ("P", "c", "f", "B"):
+        full[k][need] = g[k]
+    tot_f = L.or_force(ps.n, x, y, z, vx, vy, vz, m, u, h, full["rho"], full["P"], full["c"],
+                       full["f"], full["B"], av, ac, box, 1, P.gamma_k, P.beta_v, len(recv),
+                       np.ascontiguousarray(recv, np.int64), foff, fidx, fo["ax"], fo["ay"],
+                       fo["az"], fo["du"], fo["vs"], nf)
+    dt = time.perf_counter() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": (tot_d + tot_f) / dt, "unit": "interactions/s", "cores": cores,
+            "kind": "oracle",
+            "sample": "%d random receivers: density for them and their %d force neighbours "
+                      "(%d interactions), force for the receivers (%d interactions); %.1f s" % (
+                          len(recv), nd - len(recv), tot_d, tot_f, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", default="clustered", choices=sorted(CONFIGS))
+    ap.add_argument("--cpu-receivers", type=int, default=4096)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(got --gpus %d)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2305_13380_amd import inputs, sphx
+
+    desc, make = CONFIGS[args.config]
+    t0 = time.perf_counter()
+    ps = make(inputs)
+    log("bench: %s: N=%d generated in %.1f s" % (args.config, ps.n, time.perf_counter() - t0))
+
+    dev = "cuda:0"
+    ctx = sphx.Context(sphx.default_params(), 0)
+    dp = sphx.DeviceParticles.from_set(ps, dev)
+    out = sphx.Outputs(ps.n, dev)
+    h0 = dp.t["h"].clone()
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+
+    t0 = time.perf_counter()
+    grid = sphx.Grid(ctx, dp)
+    torch.cuda.synchronize()
+    t_grid = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    tasks = sphx.Tasks(ctx, grid, dp)
+    torch.cuda.synchronize()
+    t_tasks = time.perf_counter() - t0
+    log("bench: grid %.1f ms (%d leaves), tasks %.1f ms (%d tasks)" % (
+        t_grid * 1e3, grid.n_leaves, t_tasks * 1e3, tasks.count))
+
+    def one_step():
+        dp.t["h"].copy_(h0)
+        return sphx.step(ctx, grid, tasks, dp, out)
+
+    for w in range(args.warmup):
+        st, info = one_step()
+        log("bench: warmup %d: passes=%d rebuilds=%d" % (w, info.passes, info.task_rebuilds))
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    start.record(stream)
+    infos = []
+    for k in range(args.steps):
+        st, info = one_step()
+        infos.append((info.passes, info.task_rebuilds, info.unconverged))
+    stop.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ctx.profile(False)
+    t_ev = start.elapsed_time(stop) / 1e3
+    ms_step = t_ev / args.steps * 1e3
+    dens_ms, dens_n = ctx.profile_read(0)
+    force_ms, force_n = ctx.profile_read(1)
+    log("bench: %d steps in %.3f s (events) / %.3f s (wall); density kernel %.2f ms over %d "
+        "launches, force kernel %.2f ms over %d launches" % (
+            args.steps, t_ev, wall, dens_ms, dens_n, force_ms, force_n))
+
+    nngb = out.d["nngb"].to(torch.int64)
+    nf = out.f["nforce"].to(torch.int64)
+    if dp.t["active"] is not None:
+        act = dp.t["active"].bool()
+        n_dens = int(nngb[act].sum())
+        n_force = int(nf[act].sum())
+    else:
+        n_dens = int(nngb.sum())
+        n_force = int(nf.sum())
+    inter = n_dens + n_force
+    value = inter / (t_ev / args.steps)
+    sums = out.sums.cpu().numpy()
+    mom = float(np.abs(sums[:3]).max() / max(sums[4], 1e-300))
+    en = float(abs(sums[3]) / max(sums[4] + sums[5], 1e-300))
+
+    # Dominant kernel (by total time) and its algorithmic FLOP rate per launch.
+    f_avg = force_ms / max(force_n, 1) / 1e3
+    force_flops = n_force * FLOP_FORCE
+    d_avg = dens_ms / max(dens_n, 1) / 1e3
+    if force_ms >= dens_ms:
+        achieved = force_flops / f_avg / 1e12
+        kern = "k_force"
+        per_launch = force_flops
+    else:
+        # density launches revisit only unconverged particles after the first
+        # pass; count the final-h interactions once per step over the launches
+        per_launch = n_dens * FLOP_DENSITY * args.steps / max(dens_n, 1)
+        achieved = per_launch / d_avg / 1e12
+        kern = "k_density"
+    passes = sorted(set(p for p, _, _ in infos))
+    line = {
+        "metric": "SPH pair interactions/s (density+force) at 1 GPU",
+        "value": value,
+        "unit": "interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": desc, "n_particles": ps.n, "seed": ps.meta.get("seed"),
+                   "kernel": "Wendland C2", "eta": ps.eta, "h_tol": 1e-4,
+                   "positions": "f64 (cell offsets f64, pair arithmetic f32)",
+                   "n_dens": n_dens, "n_force": n_force, "density_passes": passes,
+                   "task_rebuilds_per_step": infos[-1][1], "unconverged": infos[-1][2],
+                   "n_leaves": grid.n_leaves, "n_tasks": tasks.count,
+                   "grid_build_ms": t_grid * 1e3, "tasks_build_ms": t_tasks * 1e3,
+                   "density_kernel_ms_per_step": dens_ms / args.steps,
+                   "force_kernel_ms_per_step": force_ms / args.steps,
+                   "momentum_err_rel": mom, "energy_err_rel": en},
+        "roofline": {"bound": "alu", "kernel": kern, "achieved": achieved,
+                     "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                     "flop_per_launch": per_launch},
+    }
+    if not args.no_cpu_baseline:
+        log("bench: timing the oracle on the host ...")
+        import oracle
+        line["cpu_baseline"] = cpu_baseline(ps, oracle.Params, args.cpu_receivers)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,246 @@
+/*
+ * sphx.h -- C-ABI of the SPH neighbour-loop library for AMD MI355X (gfx950).
+ *
+ * The library evaluates the data-parallel hot path of smoothed particle
+ * hydrodynamics as described in Section 3 of Schaller et al., "SWIFT: A
+ * modern highly-parallel gravity and smoothed particle hydrodynamics solver"
+ * (arXiv 2305.13380), over self and pair tasks of a spatial cell structure
+ * (Section 2.2, "nested grids"):
+ *
+ *   grid build   Morton sort of the particles and leaf cells (<= leaf_max
+ *                particles each, aligned octree blocks), Section 2.2 and the
+ *                depth-first binning of Section 9.1;
+ *   tasks build  self/pair task list of leaf cells whose bounding boxes are
+ *                within a search radius, Section 2.2 and 9.1;
+ *   density      number density, its h-derivative, mass density and its
+ *                h-derivative, neighbour count, velocity divergence and curl
+ *                sums (Section 3.1, "Constructing the number density" and
+ *                "Creating general smoothed quantities");
+ *   ghost        one Newton-Raphson update of h on n (h/eta)^3 = 1 (Section
+ *                3.1), then pressure, sound speed, f-factor, Balsara switch
+ *                (Section 3.2) for converged particles;
+ *   force        accelerations, du/dt and signal velocity of the density-energy
+ *                equations of motion with Balsara-switched artificial
+ *                viscosity and artificial conduction (Sections 3.2 and 3.3),
+ *                plus FP64 global momentum and energy sums.
+ *
+ * Conventions shared by every call:
+ *   - Device pointers. Every particle and output array is a contiguous device
+ *     allocation owned by the caller (structure of arrays, one value per
+ *     particle, in the caller's particle order). The library owns only the
+ *     opaque handles and their device workspace.
+ *   - Streams. `stream` is a hipStream_t (NULL = the default stream). Every
+ *     call enqueues work asynchronously; only the calls documented as
+ *     synchronising wait for the device.
+ *   - Status. 0 = OK, negative = error (nothing useful was produced, the
+ *     message is in sphx_last_error()), positive = bit set of warnings
+ *     (results are valid).
+ *   - Inputs are never written, except h, which sphx_ghost and sphx_step
+ *     update in place.
+ *   - Threading. A context may be used by one host thread at a time.
+ */
+#ifndef SPHX_H
+#define SPHX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t sphx_status;
+
+#define SPHX_OK 0
+#define SPHX_E_INVALID (-1)       /* bad argument or non-finite / out-of-range input */
+#define SPHX_E_OOM (-2)           /* device allocation failed */
+#define SPHX_E_HIP (-3)           /* a HIP runtime call failed */
+#define SPHX_E_STATE (-4)         /* handle used out of order (e.g. grid of another ctx) */
+#define SPHX_W_NOT_CONVERGED 1    /* some h did not converge within max_iter passes */
+#define SPHX_W_H_CLAMPED 2        /* some h were limited to h_max */
+#define SPHX_W_REBUILD 4          /* an h outgrew its task list; tasks were (or must be) rebuilt */
+
+/* Method parameters. sphx_params_default() fills the paper's values. */
+typedef struct sphx_params {
+    double box[3];      /* box edge lengths; particles live in [0, box) */
+    int32_t periodic;   /* 1: periodic box (minimum image), 0: open */
+    int32_t max_iter;   /* max density passes of the h iteration (default 30) */
+    double gamma_k;     /* kernel support H = gamma_k h (Wendland C2: sqrt(15)/2) */
+    double eta;         /* smoothing scale of n (h/eta)^3 = 1 (Section 3.1) */
+    double h_tol;       /* relative NR tolerance (Section 3.1: 1e-4) */
+    double h_max;       /* cap on h; <= 0 selects min(box)/(3 gamma_k)(1-1e-6) */
+    double gamma_gas;   /* ratio of specific heats (5/3) */
+    double beta_v;      /* signal velocity constant beta (Section 3.2: 3) */
+    double eps_balsara; /* Balsara switch regulariser (Section 3.2: 1e-4) */
+    double skin;        /* relative enlargement of task search radii (default 0.1) */
+    int32_t leaf_max;   /* particles per leaf cell, 8..64 (default 64) */
+    int32_t reserved;
+} sphx_params;
+
+/* Particle-carried inputs (Section 3.1): positions FP64, the rest FP32. */
+typedef struct sphx_particles {
+    int64_t n;
+    const double *x, *y, *z;
+    const float *vx, *vy, *vz;
+    const float *m;        /* mass */
+    const float *u;        /* internal energy per unit mass */
+    float *h;              /* smoothing length; read, and updated by ghost/step */
+    const float *alpha_v;  /* per-particle viscosity coefficient alpha_V,i */
+    const float *alpha_c;  /* per-particle conduction coefficient alpha_c,i */
+    const uint8_t *active; /* NULL: all active; else receivers are those with 1 */
+} sphx_particles;
+
+/* Density-pass outputs (caller order, FP32 unless noted). Sums include the
+ * self term; nngb excludes it. div_sum/curl_* are the raw sums
+ * sum_j m_j (v_j - v_i).grad_i W_ij and sum_j m_j grad_i W_ij x (v_j - v_i). */
+typedef struct sphx_density_out {
+    float *rho, *rho_dh, *n, *n_dh;
+    float *div_sum, *curl_x, *curl_y, *curl_z;
+    int32_t *nngb;
+} sphx_density_out;
+
+/* Ghost outputs (caller order). converged: 1 once h has converged. */
+typedef struct sphx_ghost_out {
+    float *f, *P, *c, *balsara, *A, *div_v, *curl_v;
+    uint8_t *converged;
+} sphx_ghost_out;
+
+/* Force outputs (caller order). nforce may be NULL. */
+typedef struct sphx_force_out {
+    float *ax, *ay, *az, *du_dt, *v_sig;
+    int32_t *nforce;
+} sphx_force_out;
+
+/* Counters in a caller-provided device array of 4 int32, zeroed by the caller
+ * before each density pass: [0] particles still unconverged after the ghost,
+ * [1] particles whose new H exceeds their leaf's task radius (rebuild the
+ * tasks before the next pass), [2] particles finalised at h_max, [3]
+ * receivers of the density pass whose H exceeded the task radius. */
+#define SPHX_COUNTERS 4
+
+/* Result of sphx_step. */
+typedef struct sphx_step_info {
+    int32_t passes;            /* density passes run */
+    int32_t task_rebuilds;     /* task-list rebuilds during the iteration */
+    int32_t unconverged;       /* particles not converged after max_iter */
+    int32_t clamped;           /* particles at h_max */
+    int64_t n_leaves;
+    int64_t n_tasks;
+} sphx_step_info;
+
+typedef struct sphx_ctx sphx_ctx;
+typedef struct sphx_grid sphx_grid;
+typedef struct sphx_tasks sphx_tasks;
+
+/* Fill *p with the defaults: unit periodic box, gamma_k = sqrt(15)/2,
+ * eta = 1.2348, h_tol = 1e-4, max_iter = 30, gamma_gas = 5/3, beta_v = 3,
+ * eps_balsara = 1e-4, skin = 0.1, leaf_max = 64, h_max automatic. */
+void sphx_params_default(sphx_params *p);
+
+/* Create a context on HIP device `hip_device` (makes it current for the
+ * calling thread). Validates *p: E_INVALID for non-positive box, eta, h_tol,
+ * max_iter, gamma_k, or leaf_max outside 8..64. *out is owned by the caller
+ * and released with sphx_ctx_destroy. */
+sphx_status sphx_ctx_create(const sphx_params *p, int hip_device, sphx_ctx **out);
+void sphx_ctx_destroy(sphx_ctx *ctx);
+
+/* Upper bound of the device bytes a grid plus its tasks take for n particles
+ * (used to admit requests against an HBM budget). Host only, no device call. */
+size_t sphx_workspace_bytes(const sphx_params *p, int64_t n);
+
+/* Grid build (Section 2.2 cells, Section 9.1 binning): validates the inputs
+ * on the device (E_INVALID on non-finite positions, positions outside
+ * [0, box) for open boxes, h <= 0, h > h_max or non-finite, m <= 0, u < 0),
+ * sorts the
+ * particles by 63-bit Morton key of their FP64 position, splits the sorted
+ * order into leaf cells (maximal aligned octree blocks with <= leaf_max
+ * particles), and stores per leaf its FP64 origin and extent and per
+ * particle its FP32 position relative to its leaf origin. Positions,
+ * velocities, masses, u and alpha are copied at this point; later changes to
+ * them need a new grid. Synchronises the stream (reads back the leaf count).
+ * *out is released with sphx_grid_destroy. */
+sphx_status sphx_grid_build(sphx_ctx *ctx, const sphx_particles *in, void *stream,
+                            sphx_grid **out);
+void sphx_grid_destroy(sphx_grid *grid);
+
+/* Tasks build (Section 2.2 self and pair tasks): for every leaf, the list of
+ * leaves (with periodic shift) whose bounding box lies within
+ * max(H_i-leaf, H_j-leaf) * (1 + skin) of its own, H taken from the current
+ * h. Each task carries the FP32 offset between the two leaf origins, formed
+ * in FP64. Synchronises the stream (reads back the task count). *out is
+ * released with sphx_tasks_destroy. Calling it again with an existing *out
+ * rebuilds in place. */
+sphx_status sphx_tasks_build(sphx_ctx *ctx, sphx_grid *grid, const sphx_particles *in,
+                             void *stream, sphx_tasks **out);
+void sphx_tasks_destroy(sphx_tasks *tasks);
+
+/* Mark every active particle as needing a density pass (start of an h
+ * iteration). sphx_grid_build does this too. Asynchronous. */
+sphx_status sphx_iter_reset(sphx_ctx *ctx, sphx_grid *grid, const sphx_particles *in,
+                            void *stream);
+
+/* Density pass (Section 3.1) at the current h for every particle marked as
+ * needing one: writes the sums of sphx_density_out for those particles only.
+ * The task list must cover every marked particle's H (true right after
+ * sphx_tasks_build with the current h). A marked particle whose H exceeds its
+ * leaf's task radius is counted in d_counters[3] (if d_counters != NULL); its
+ * sums are then incomplete and the tasks must be rebuilt. Asynchronous. */
+sphx_status sphx_density(sphx_ctx *ctx, const sphx_grid *grid, const sphx_tasks *tasks,
+                         const sphx_particles *in, sphx_density_out *out, int32_t *d_counters,
+                         void *stream);
+
+/* Ghost (Section 3.1 NR update; Sections 3.1-3.2 EOS, f-factor, Balsara): for
+ * every particle marked as needing a pass, one Newton-Raphson step of h on
+ * F(h) = n h^3 - eta^3 from the sums in *dens; the step is limited to
+ * [h/2, 2h] and h_max. A particle whose step is below h_tol*h is converged:
+ * it keeps the h its sums were evaluated at, its ghost outputs are written
+ * and its mark is cleared. Otherwise its h (caller array) is replaced by the
+ * new value, unless final_pass != 0, in which case it keeps its h and is
+ * reported unconverged. Adds to d_counters (see SPHX_COUNTERS).
+ * Asynchronous. */
+sphx_status sphx_ghost(sphx_ctx *ctx, sphx_grid *grid, const sphx_tasks *tasks,
+                       sphx_particles *in, const sphx_density_out *dens, sphx_ghost_out *out,
+                       int32_t *d_counters, int32_t final_pass, void *stream);
+
+/* Force pass (Sections 3.2-3.3) for every active particle, over all j != i
+ * with r_ij < max(H_i, H_j). Reads the ghost state (rho from *dens; f, P, c,
+ * balsara from *gst) of every particle, including inactive ones. If
+ * d_sums6 != NULL it receives, in FP64, sum m a (3), sum m (v.a + du/dt),
+ * sum m |a|, sum m |du/dt| over the active particles. Asynchronous. */
+sphx_status sphx_force(sphx_ctx *ctx, const sphx_grid *grid, const sphx_tasks *tasks,
+                       const sphx_particles *in, const sphx_density_out *dens,
+                       const sphx_ghost_out *gst, sphx_force_out *out, double *d_sums6,
+                       void *stream);
+
+/* One step on an existing grid: the h iteration (density + ghost passes
+ * until every active particle has converged or max_iter passes ran; the task
+ * list is rebuilt in place whenever an h outgrows its task radius, and a
+ * density pass that ran on a stale list is repeated), then the force pass and
+ * the FP64 sums. *tasks is built first if NULL (release it with
+ * sphx_tasks_destroy). Synchronises the stream once per density pass. *info
+ * may be NULL. Warnings: W_NOT_CONVERGED, W_H_CLAMPED. */
+sphx_status sphx_step(sphx_ctx *ctx, sphx_grid *grid, sphx_tasks **tasks, sphx_particles *in,
+                      sphx_density_out *dens, sphx_ghost_out *gst, sphx_force_out *out,
+                      double *d_sums6, void *stream, sphx_step_info *info);
+
+/* Kernel timing for measurement tools. sphx_profile_enable(ctx, 1) clears the
+ * statistics and starts recording a pair of HIP events around every launch of
+ * the density kernel (kernel 0) and the force kernel (kernel 1), on the
+ * stream the kernel is launched on; 0 stops recording. sphx_profile_read
+ * waits for the recorded events and returns the summed kernel time in
+ * milliseconds and the number of launches since the last enable. */
+sphx_status sphx_profile_enable(sphx_ctx *ctx, int32_t enable);
+sphx_status sphx_profile_read(sphx_ctx *ctx, int32_t kernel, double *total_ms, int64_t *launches);
+
+/* Leaf and task counts of a grid / task list (host values). */
+int64_t sphx_grid_leaves(const sphx_grid *grid);
+int64_t sphx_tasks_count(const sphx_tasks *tasks);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char *sphx_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPHX_H */

@@ -1,0 +1,367 @@
+// C-ABI entry points of the sphx library: argument validation, ownership of
+// the opaque handles, and the host side of the h iteration.
+#include <math.h>
+#include <string.h>
+
+#include <string>
+
+#include "sphx_internal.h"
+
+namespace sphx {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+hipError_t Profiler::begin(int k, hipStream_t s)
+{
+    if (!on)
+        return hipSuccess;
+    if (used[k] == pool[k].size()) {
+        Rec r;
+        hipError_t e = hipEventCreate(&r.a);
+        if (e != hipSuccess)
+            return e;
+        e = hipEventCreate(&r.b);
+        if (e != hipSuccess)
+            return e;
+        pool[k].push_back(r);
+    }
+    return hipEventRecord(pool[k][used[k]].a, s);
+}
+
+hipError_t Profiler::end(int k, hipStream_t s)
+{
+    if (!on)
+        return hipSuccess;
+    hipError_t e = hipEventRecord(pool[k][used[k]].b, s);
+    ++used[k];
+    return e;
+}
+
+static hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+static sphx_status check_particles(const sphx_particles *in, bool need_h_write)
+{
+    if (!in) {
+        set_error("particles: NULL");
+        return SPHX_E_INVALID;
+    }
+    if (in->n < 0 || in->n > int64_t(INT32_MAX) - 1) {
+        set_error("particles: n must be in [0, 2^31 - 2]");
+        return SPHX_E_INVALID;
+    }
+    if (in->n == 0)
+        return SPHX_OK;
+    const void *req[] = {in->x, in->y, in->z, in->vx, in->vy, in->vz, in->m, in->u, in->h,
+                         in->alpha_v, in->alpha_c};
+    for (const void *p : req)
+        if (!p) {
+            set_error("particles: a required array pointer is NULL");
+            return SPHX_E_INVALID;
+        }
+    (void)need_h_write;
+    return SPHX_OK;
+}
+
+static sphx_status check_handles(const sphx_ctx *ctx, const sphx_grid *g, const sphx_tasks *t,
+                                 const sphx_particles *in)
+{
+    if (!ctx || !g) {
+        set_error("NULL context or grid");
+        return SPHX_E_INVALID;
+    }
+    if (g->ctx != ctx) {
+        set_error("grid belongs to another context");
+        return SPHX_E_STATE;
+    }
+    if (t && t->grid != g) {
+        set_error("task list belongs to another grid");
+        return SPHX_E_STATE;
+    }
+    if (in && in->n != g->n) {
+        set_error("particle count differs from the grid's");
+        return SPHX_E_INVALID;
+    }
+    return SPHX_OK;
+}
+
+}  // namespace sphx
+
+using namespace sphx;
+
+extern "C" {
+
+void sphx_params_default(sphx_params *p)
+{
+    if (!p)
+        return;
+    memset(p, 0, sizeof(*p));
+    p->box[0] = p->box[1] = p->box[2] = 1.0;
+    p->periodic = 1;
+    p->max_iter = 30;
+    p->gamma_k = sqrt(15.0) / 2.0;
+    p->eta = 1.2348;
+    p->h_tol = 1e-4;
+    p->h_max = 0.0;
+    p->gamma_gas = 5.0 / 3.0;
+    p->beta_v = 3.0;
+    p->eps_balsara = 1e-4;
+    p->skin = 0.1;
+    p->leaf_max = 64;
+}
+
+const char *sphx_last_error(void) { return g_last_error.c_str(); }
+
+sphx_status sphx_ctx_create(const sphx_params *p, int hip_device, sphx_ctx **out)
+{
+    if (!p || !out) {
+        set_error("sphx_ctx_create: NULL argument");
+        return SPHX_E_INVALID;
+    }
+    *out = nullptr;
+    for (int a = 0; a < 3; ++a)
+        if (!(p->box[a] > 0.0) || !isfinite(p->box[a])) {
+            set_error("sphx_ctx_create: box lengths must be positive and finite");
+            return SPHX_E_INVALID;
+        }
+    if (!(p->eta > 0.0) || !(p->h_tol > 0.0) || p->max_iter < 1 || !(p->gamma_k > 0.0) ||
+        p->leaf_max < 8 || p->leaf_max > kLeafMax || !(p->skin >= 0.0) || !(p->gamma_gas > 1.0)) {
+        set_error("sphx_ctx_create: invalid eta, h_tol, max_iter, gamma_k, gamma_gas, skin or "
+                  "leaf_max (8..64)");
+        return SPHX_E_INVALID;
+    }
+    int ndev = 0;
+    SPHX_HIP(hipGetDeviceCount(&ndev));
+    if (hip_device < 0 || hip_device >= ndev) {
+        set_error("sphx_ctx_create: no such HIP device");
+        return SPHX_E_INVALID;
+    }
+    SPHX_HIP(hipSetDevice(hip_device));
+    sphx_ctx *c = new sphx_ctx();
+    c->prof = new Profiler();
+    c->p = *p;
+    c->device = hip_device;
+    double lmin = fmin(p->box[0], fmin(p->box[1], p->box[2]));
+    double auto_max = lmin / (3.0 * p->gamma_k) * (1.0 - 1e-6);
+    c->h_max = p->h_max > 0.0 ? fmin(p->h_max, auto_max) : auto_max;
+    if (hipMalloc(&c->d_counters, SPHX_COUNTERS * sizeof(int32_t)) != hipSuccess ||
+        hipMalloc(&c->d_sums, 8 * sizeof(double)) != hipSuccess) {
+        (void)hipFree(c->d_counters);
+        delete c->prof;
+        delete c;
+        set_error("sphx_ctx_create: out of device memory");
+        return SPHX_E_OOM;
+    }
+    *out = c;
+    return SPHX_OK;
+}
+
+void sphx_ctx_destroy(sphx_ctx *ctx)
+{
+    if (!ctx)
+        return;
+    (void)hipFree(ctx->d_counters);
+    (void)hipFree(ctx->d_sums);
+    for (auto &v : ctx->prof->pool)
+        for (auto &r : v) {
+            (void)hipEventDestroy(r.a);
+            (void)hipEventDestroy(r.b);
+        }
+    delete ctx->prof;
+    delete ctx;
+}
+
+size_t sphx_workspace_bytes(const sphx_params *p, int64_t n)
+{
+    (void)p;
+    if (n < 0)
+        return 0;
+    return grid_bytes(n) + tasks_bytes(n);
+}
+
+sphx_status sphx_grid_build(sphx_ctx *ctx, const sphx_particles *in, void *stream,
+                            sphx_grid **out)
+{
+    if (!ctx || !out) {
+        set_error("sphx_grid_build: NULL argument");
+        return SPHX_E_INVALID;
+    }
+    SPHX_TRY(check_particles(in, false));
+    SPHX_HIP(hipSetDevice(ctx->device));
+    return grid_build(ctx, in, as_stream(stream), out);
+}
+
+void sphx_grid_destroy(sphx_grid *grid) { grid_free(grid); }
+
+sphx_status sphx_tasks_build(sphx_ctx *ctx, sphx_grid *grid, const sphx_particles *in,
+                             void *stream, sphx_tasks **out)
+{
+    if (!out) {
+        set_error("sphx_tasks_build: NULL argument");
+        return SPHX_E_INVALID;
+    }
+    SPHX_TRY(check_handles(ctx, grid, *out, in));
+    SPHX_TRY(check_particles(in, false));
+    SPHX_HIP(hipSetDevice(ctx->device));
+    return tasks_build(ctx, grid, in, as_stream(stream), out);
+}
+
+void sphx_tasks_destroy(sphx_tasks *tasks) { tasks_free(tasks); }
+
+sphx_status sphx_iter_reset(sphx_ctx *ctx, sphx_grid *grid, const sphx_particles *in,
+                            void *stream)
+{
+    SPHX_TRY(check_handles(ctx, grid, nullptr, in));
+    SPHX_TRY(check_particles(in, false));
+    return iter_reset(grid, in, as_stream(stream));
+}
+
+sphx_status sphx_density(sphx_ctx *ctx, const sphx_grid *grid, const sphx_tasks *tasks,
+                         const sphx_particles *in, sphx_density_out *out, int32_t *d_counters,
+                         void *stream)
+{
+    SPHX_TRY(check_handles(ctx, grid, tasks, in));
+    SPHX_TRY(check_particles(in, false));
+    if (!tasks || !out || (in->n && (!out->rho || !out->rho_dh || !out->n || !out->n_dh ||
+                                      !out->div_sum || !out->curl_x || !out->curl_y ||
+                                      !out->curl_z || !out->nngb))) {
+        set_error("sphx_density: NULL task list or output array");
+        return SPHX_E_INVALID;
+    }
+    return density_launch(ctx, grid, tasks, in, out, d_counters, as_stream(stream));
+}
+
+sphx_status sphx_ghost(sphx_ctx *ctx, sphx_grid *grid, const sphx_tasks *tasks,
+                       sphx_particles *in, const sphx_density_out *dens, sphx_ghost_out *out,
+                       int32_t *d_counters, int32_t final_pass, void *stream)
+{
+    SPHX_TRY(check_handles(ctx, grid, tasks, in));
+    SPHX_TRY(check_particles(in, true));
+    if (!tasks || !dens || !out ||
+        (in->n && (!out->f || !out->P || !out->c || !out->balsara || !out->A || !out->div_v ||
+                   !out->curl_v || !out->converged))) {
+        set_error("sphx_ghost: NULL task list, density or output array");
+        return SPHX_E_INVALID;
+    }
+    return ghost_launch(ctx, grid, tasks, in, dens, out, d_counters, final_pass,
+                        as_stream(stream));
+}
+
+sphx_status sphx_force(sphx_ctx *ctx, const sphx_grid *grid, const sphx_tasks *tasks,
+                       const sphx_particles *in, const sphx_density_out *dens,
+                       const sphx_ghost_out *gst, sphx_force_out *out, double *d_sums6,
+                       void *stream)
+{
+    SPHX_TRY(check_handles(ctx, grid, tasks, in));
+    SPHX_TRY(check_particles(in, false));
+    if (!tasks || !dens || !gst || !out ||
+        (in->n && (!out->ax || !out->ay || !out->az || !out->du_dt || !out->v_sig || !dens->rho ||
+                   !gst->P || !gst->c || !gst->f || !gst->balsara || !gst->A))) {
+        set_error("sphx_force: NULL task list, state or output array");
+        return SPHX_E_INVALID;
+    }
+    return force_launch(ctx, grid, tasks, in, dens, gst, out, d_sums6, as_stream(stream));
+}
+
+sphx_status sphx_step(sphx_ctx *ctx, sphx_grid *grid, sphx_tasks **tasks, sphx_particles *in,
+                      sphx_density_out *dens, sphx_ghost_out *gst, sphx_force_out *out,
+                      double *d_sums6, void *stream, sphx_step_info *info)
+{
+    if (!tasks) {
+        set_error("sphx_step: NULL task-list pointer");
+        return SPHX_E_INVALID;
+    }
+    SPHX_TRY(check_handles(ctx, grid, *tasks, in));
+    SPHX_TRY(check_particles(in, true));
+    hipStream_t s = as_stream(stream);
+    SPHX_HIP(hipSetDevice(ctx->device));
+    sphx_step_info local;
+    memset(&local, 0, sizeof(local));
+    if (!*tasks)
+        SPHX_TRY(tasks_build(ctx, grid, in, s, tasks));
+    SPHX_TRY(iter_reset(grid, in, s));
+    int32_t h_counters[SPHX_COUNTERS] = {0, 0, 0, 0};
+    int32_t *dc = ctx->d_counters;
+    const int max_iter = ctx->p.max_iter;
+    int pass = 0, stale_repeats = 0;
+    while (pass < max_iter) {
+        SPHX_HIP(hipMemsetAsync(dc, 0, SPHX_COUNTERS * sizeof(int32_t), s));
+        SPHX_TRY(sphx_density(ctx, grid, *tasks, in, dens, dc, stream));
+        const int final_pass = (pass + 1 == max_iter) ? 1 : 0;
+        SPHX_TRY(sphx_ghost(ctx, grid, *tasks, in, dens, gst, dc, final_pass, stream));
+        SPHX_HIP(hipMemcpyAsync(h_counters, dc, sizeof(h_counters), hipMemcpyDeviceToHost, s));
+        SPHX_HIP(hipStreamSynchronize(s));
+        if (h_counters[3] > 0) {
+            // The pass ran on a stale task list and the ghost skipped it.
+            if (++stale_repeats > 4) {
+                set_error("sphx_step: task list keeps going stale");
+                return SPHX_E_STATE;
+            }
+            SPHX_TRY(tasks_build(ctx, grid, in, s, tasks));
+            local.task_rebuilds++;
+            continue;
+        }
+        ++pass;
+        local.clamped += h_counters[2];
+        if (h_counters[0] == 0)
+            break;
+        if (final_pass) {
+            local.unconverged = h_counters[0];
+            break;
+        }
+        if (h_counters[1] > 0) {
+            SPHX_TRY(tasks_build(ctx, grid, in, s, tasks));
+            local.task_rebuilds++;
+        }
+    }
+    local.passes = pass;
+    SPHX_TRY(sphx_force(ctx, grid, *tasks, in, dens, gst, out, d_sums6, stream));
+    local.n_leaves = grid->n_leaves;
+    local.n_tasks = (*tasks)->n_tasks;
+    if (info)
+        *info = local;
+    sphx_status w = SPHX_OK;
+    if (local.unconverged)
+        w |= SPHX_W_NOT_CONVERGED;
+    if (local.clamped)
+        w |= SPHX_W_H_CLAMPED;
+    return w;
+}
+
+sphx_status sphx_profile_enable(sphx_ctx *ctx, int32_t enable)
+{
+    if (!ctx) {
+        set_error("sphx_profile_enable: NULL context");
+        return SPHX_E_INVALID;
+    }
+    ctx->prof->on = enable != 0;
+    if (enable)
+        ctx->prof->used[0] = ctx->prof->used[1] = 0;
+    return SPHX_OK;
+}
+
+sphx_status sphx_profile_read(sphx_ctx *ctx, int32_t kernel, double *total_ms, int64_t *launches)
+{
+    if (!ctx || kernel < 0 || kernel > 1 || !total_ms || !launches) {
+        set_error("sphx_profile_read: invalid argument");
+        return SPHX_E_INVALID;
+    }
+    double t = 0.0;
+    Profiler &P = *ctx->prof;
+    for (size_t k = 0; k < P.used[kernel]; ++k) {
+        SPHX_HIP(hipEventSynchronize(P.pool[kernel][k].b));
+        float ms = 0.f;
+        SPHX_HIP(hipEventElapsedTime(&ms, P.pool[kernel][k].a, P.pool[kernel][k].b));
+        t += ms;
+    }
+    *total_ms = t;
+    *launches = int64_t(P.used[kernel]);
+    return SPHX_OK;
+}
+
+int64_t sphx_grid_leaves(const sphx_grid *grid) { return grid ? grid->n_leaves : -1; }
+
+int64_t sphx_tasks_count(const sphx_tasks *tasks) { return tasks ? tasks->n_tasks : -1; }
+
+}  // extern "C"

@@ -1,0 +1,394 @@
+// Grid build: Morton sort and leaf cells (Section 2.2 nested grids; Section
+// 9.1 depth-first binning, here as a radix sort on a 63-bit Morton key, whose
+// order is a depth-first order of the octree).
+#include <rocprim/device/device_radix_sort.hpp>
+#include <rocprim/device/device_scan.hpp>
+
+#include "sphx_internal.h"
+
+namespace sphx {
+namespace {
+
+__device__ __forceinline__ double wrap_coord(double x, double L, int periodic)
+{
+    if (!periodic)
+        return x;
+    double w = x - L * floor(x / L);
+    return w >= L ? w - L : w;  // floor rounding can leave w == L
+}
+
+// Spread the low 21 bits of v so that bit k moves to bit 3k.
+__device__ __forceinline__ uint64_t spread3(uint64_t v)
+{
+    v &= 0x1fffffull;
+    v = (v | (v << 32)) & 0x1f00000000ffffull;
+    v = (v | (v << 16)) & 0x1f0000ff0000ffull;
+    v = (v | (v << 8)) & 0x100f00f00f00f00full;
+    v = (v | (v << 4)) & 0x10c30c30c30c30c3ull;
+    v = (v | (v << 2)) & 0x1249249249249249ull;
+    return v;
+}
+
+__device__ __forceinline__ uint64_t quantise(double x, double L)
+{
+    double q = floor(x / L * double(1 << kMortonBits));
+    if (!(q >= 0.0))
+        q = 0.0;
+    const double top = double((1 << kMortonBits) - 1);
+    if (q > top)
+        q = top;
+    return uint64_t(q);
+}
+
+// Validate the inputs and compute the Morton keys of the wrapped positions.
+__global__ void k_keys(int64_t n, const double *__restrict__ x, const double *__restrict__ y,
+                       const double *__restrict__ z, const float *__restrict__ h,
+                       const float *__restrict__ m, const float *__restrict__ u, float h_max,
+                       double Lx, double Ly, double Lz, int periodic, uint64_t *__restrict__ keys,
+                       int32_t *__restrict__ idx, int32_t *__restrict__ bad)
+{
+    int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    double px = x[i], py = y[i], pz = z[i];
+    float hi = h[i], mi = m[i], ui = u[i];
+    bool ok = isfinite(px) && isfinite(py) && isfinite(pz) && isfinite(hi) && hi > 0.0f &&
+              hi <= h_max &&
+              isfinite(mi) && mi > 0.0f && isfinite(ui) && ui >= 0.0f;
+    if (!periodic)
+        ok = ok && px >= 0.0 && px < Lx && py >= 0.0 && py < Ly && pz >= 0.0 && pz < Lz;
+    if (!ok)
+        atomicAdd(bad, 1);
+    px = wrap_coord(px, Lx, periodic);
+    py = wrap_coord(py, Ly, periodic);
+    pz = wrap_coord(pz, Lz, periodic);
+    uint64_t k = (spread3(quantise(px, Lx)) << 2) | (spread3(quantise(py, Ly)) << 1) |
+                 spread3(quantise(pz, Lz));
+    keys[i] = k;
+    idx[i] = int32_t(i);
+}
+
+// Index of the first position in [lo, hi) whose key prefix (key >> shift) is
+// >= p (keys are sorted, so prefixes are non-decreasing).
+__device__ __forceinline__ int64_t lower_prefix(const uint64_t *k, int64_t lo, int64_t hi,
+                                                uint64_t p, int shift)
+{
+    while (lo < hi) {
+        int64_t mid = (lo + hi) >> 1;
+        if ((k[mid] >> shift) < p)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// Leaf cells are the maximal aligned octree blocks holding <= cap particles.
+// Sorted positions s-1 and s share a leaf exactly when their deepest common
+// octree block holds <= cap particles; that block's population is measured
+// inside a window of 2 cap + 2 sorted keys around s (a population above cap
+// always shows as more than cap keys inside the window).
+__global__ void k_leaf_flags(int64_t n, const uint64_t *__restrict__ k, int cap,
+                             uint32_t *__restrict__ flag)
+{
+    int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (s >= n)
+        return;
+    if (s == 0) {
+        flag[0] = 1;
+        return;
+    }
+    uint64_t a = k[s - 1], b = k[s];
+    uint64_t d = a ^ b;
+    int common_levels = d ? (__clzll(int64_t(d)) - 1) / 3 : kMortonBits;
+    if (common_levels > kMortonBits)
+        common_levels = kMortonBits;
+    int shift = 3 * (kMortonBits - common_levels);
+    uint64_t p = b >> shift;
+    int64_t wlo = s - 1 - cap;
+    if (wlo < 0)
+        wlo = 0;
+    int64_t whi = s + cap + 1;
+    if (whi > n)
+        whi = n;
+    int64_t lo = lower_prefix(k, wlo, s, p, shift);
+    int64_t hi = (p + 1 > p) ? lower_prefix(k, s, whi, p + 1, shift) : whi;
+    flag[s] = (hi - lo > cap) ? 1u : 0u;
+}
+
+// leaf_of[s] = inclusive_scan(flag)[s] - 1; leaf_start[leaf] = first s.
+__global__ void k_leaf_index(int64_t n, const uint32_t *__restrict__ flag,
+                             const uint32_t *__restrict__ incl, int32_t *__restrict__ leaf_of,
+                             int32_t *__restrict__ leaf_start, int32_t *__restrict__ n_leaves)
+{
+    int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (s >= n)
+        return;
+    int32_t L = int32_t(incl[s]) - 1;
+    leaf_of[s] = L;
+    if (flag[s])
+        leaf_start[L] = int32_t(s);
+    if (s == n - 1) {
+        leaf_start[L + 1] = int32_t(n);
+        *n_leaves = L + 1;
+    }
+}
+
+__device__ __forceinline__ double wave_min(double v)
+{
+    for (int o = 32; o > 0; o >>= 1)
+        v = fmin(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v)
+{
+    for (int o = 32; o > 0; o >>= 1)
+        v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// One wave per leaf: FP64 bounding box of the leaf's particles (origin = min
+// corner), then each particle's FP32 position relative to that origin and the
+// sorted copies of the other inputs.
+__global__ __launch_bounds__(64) void k_leaf_setup(
+    int64_t n_leaves, const int32_t *__restrict__ leaf_start, const int32_t *__restrict__ perm,
+    const double *__restrict__ x, const double *__restrict__ y, const double *__restrict__ z,
+    const float *__restrict__ vx, const float *__restrict__ vy, const float *__restrict__ vz,
+    const float *__restrict__ m, const float *__restrict__ u, const float *__restrict__ av,
+    const float *__restrict__ ac, double Lx, double Ly, double Lz, int periodic,
+    double *__restrict__ org, double *__restrict__ node_lo, double *__restrict__ node_hi,
+    float4 *__restrict__ q0, float4 *__restrict__ q1, float2 *__restrict__ qa)
+{
+    int64_t L = blockIdx.x;
+    if (L >= n_leaves)
+        return;
+    int lane = threadIdx.x;
+    int32_t s0 = leaf_start[L], cnt = leaf_start[L + 1] - s0;
+    bool valid = lane < cnt;
+    int32_t s = s0 + (valid ? lane : 0);
+    int32_t i = perm[s];
+    double px = wrap_coord(x[i], Lx, periodic);
+    double py = wrap_coord(y[i], Ly, periodic);
+    double pz = wrap_coord(z[i], Lz, periodic);
+    double lox = wave_min(px), loy = wave_min(py), loz = wave_min(pz);
+    double hix = wave_max(px), hiy = wave_max(py), hiz = wave_max(pz);
+    if (lane == 0) {
+        org[3 * L + 0] = lox;
+        org[3 * L + 1] = loy;
+        org[3 * L + 2] = loz;
+        node_lo[3 * L + 0] = lox;
+        node_lo[3 * L + 1] = loy;
+        node_lo[3 * L + 2] = loz;
+        node_hi[3 * L + 0] = hix;
+        node_hi[3 * L + 1] = hiy;
+        node_hi[3 * L + 2] = hiz;
+    }
+    if (valid) {
+        q0[s] = make_float4(float(px - lox), float(py - loy), float(pz - loz), m[i]);
+        q1[s] = make_float4(vx[i], vy[i], vz[i], u[i]);
+        qa[s] = make_float2(av[i], ac[i]);
+    }
+}
+
+// Tree over the leaves: node c of level l+1 covers nodes [8c, 8c+8) of level l.
+__global__ void k_tree_level(int64_t cnt_up, int64_t cnt_dn, const double *__restrict__ lo_dn,
+                             const double *__restrict__ hi_dn, double *__restrict__ lo_up,
+                             double *__restrict__ hi_up)
+{
+    int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (c >= cnt_up)
+        return;
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    int64_t e = (c + 1) * kTreeFan;
+    if (e > cnt_dn)
+        e = cnt_dn;
+    for (int64_t k = c * kTreeFan; k < e; ++k)
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = fmin(lo[a], lo_dn[3 * k + a]);
+            hi[a] = fmax(hi[a], hi_dn[3 * k + a]);
+        }
+    for (int a = 0; a < 3; ++a) {
+        lo_up[3 * c + a] = lo[a];
+        hi_up[3 * c + a] = hi[a];
+    }
+}
+
+__global__ void k_need_reset(int64_t n, const int32_t *__restrict__ perm,
+                             const uint8_t *__restrict__ active, uint8_t *__restrict__ need)
+{
+    int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (s >= n)
+        return;
+    need[s] = active ? (active[perm[s]] ? 1 : 0) : 1;
+}
+
+template <class T>
+sphx_status dalloc(T **p, size_t count)
+{
+    *p = nullptr;
+    if (count == 0)
+        count = 1;
+    SPHX_HIP(hipMalloc((void **)p, count * sizeof(T)));
+    return SPHX_OK;
+}
+
+inline unsigned blocks(int64_t n, int t) { return unsigned((n + t - 1) / t); }
+
+}  // namespace
+
+size_t grid_bytes(int64_t n)
+{
+    // per particle: keys x2, perm/idx, leaf_of, flags x2, q0, q1, qa, need, g0, g1
+    size_t per = 8 * 2 + 4 * 2 + 4 + 4 * 2 + 16 * 2 + 8 + 1 + 16 * 2;
+    // per leaf (at most n leaves): start, origin, tree nodes (~8/7 of the
+    // leaves: lo, hi, radius), partial sums
+    size_t per_leaf = 4 + 24 + (48 + 4) * 8 / 7 + 1 + 48;
+    size_t sort_tmp = size_t(n) * 16 + (1 << 20);
+    return size_t(n) * (per + per_leaf) + sort_tmp + (1 << 16);
+}
+
+void grid_free(sphx_grid *g)
+{
+    if (!g)
+        return;
+    void *ptrs[] = {g->keys,    g->perm,     g->leaf_of,  g->q0,      g->q1,     g->qa,
+                    g->need,    g->g0,       g->g1,       g->leaf_start, g->leaf_org, g->node_lo,
+                    g->node_hi, g->node_r,   g->fsum,     g->sort_tmp, g->keys_in, g->idx_in,
+                    g->flags,   g->d_status};
+    for (void *p : ptrs)
+        if (p)
+            (void)hipFree(p);
+    delete g;
+}
+
+sphx_status iter_reset(sphx_grid *g, const sphx_particles *in, hipStream_t s)
+{
+    if (g->n == 0)
+        return SPHX_OK;
+    k_need_reset<<<blocks(g->n, 256), 256, 0, s>>>(g->n, g->perm, in->active, g->need);
+    SPHX_HIP(hipGetLastError());
+    return SPHX_OK;
+}
+
+sphx_status grid_build(sphx_ctx *ctx, const sphx_particles *in, hipStream_t s, sphx_grid **out)
+{
+    const sphx_params &P = ctx->p;
+    const int64_t n = in->n;
+    sphx_grid *g = new sphx_grid();
+    *out = nullptr;
+    g->ctx = ctx;
+    g->n = n;
+    struct Guard {
+        sphx_grid *g;
+        bool keep = false;
+        ~Guard()
+        {
+            if (!keep)
+                grid_free(g);
+        }
+    } guard{g};
+
+    SPHX_TRY(dalloc(&g->d_status, 4));
+    SPHX_HIP(hipMemsetAsync(g->d_status, 0, 4 * sizeof(int32_t), s));
+    SPHX_TRY(dalloc(&g->keys, n));
+    SPHX_TRY(dalloc(&g->keys_in, n));
+    SPHX_TRY(dalloc(&g->perm, n));
+    SPHX_TRY(dalloc(&g->idx_in, n));
+    SPHX_TRY(dalloc(&g->leaf_of, n));
+    SPHX_TRY(dalloc(&g->flags, 2 * n));
+    SPHX_TRY(dalloc(&g->q0, n));
+    SPHX_TRY(dalloc(&g->q1, n));
+    SPHX_TRY(dalloc(&g->qa, n));
+    SPHX_TRY(dalloc(&g->need, n));
+    SPHX_TRY(dalloc(&g->g0, n));
+    SPHX_TRY(dalloc(&g->g1, n));
+
+    if (n == 0) {
+        g->n_leaves = 0;
+        g->n_levels = 0;
+        SPHX_TRY(dalloc(&g->leaf_start, 1));
+        SPHX_HIP(hipMemsetAsync(g->leaf_start, 0, sizeof(int32_t), s));
+        guard.keep = true;
+        *out = g;
+        return SPHX_OK;
+    }
+
+    k_keys<<<blocks(n, 256), 256, 0, s>>>(n, in->x, in->y, in->z, in->h, in->m, in->u,
+                                           float(ctx->h_max), P.box[0],
+                                           P.box[1], P.box[2], P.periodic, g->keys_in, g->idx_in,
+                                           g->d_status);
+    SPHX_HIP(hipGetLastError());
+
+    // Stable LSD radix sort of (key, caller index) on the 63 key bits.
+    size_t tmp = 0;
+    SPHX_HIP(rocprim::radix_sort_pairs(nullptr, tmp, g->keys_in, g->keys, g->idx_in, g->perm,
+                                       size_t(n), 0, 63, s));
+    size_t tmp2 = 0;
+    SPHX_HIP(rocprim::inclusive_scan(nullptr, tmp2, g->flags, g->flags + n, size_t(n),
+                                     rocprim::plus<uint32_t>(), s));
+    g->sort_tmp_bytes = tmp > tmp2 ? tmp : tmp2;
+    SPHX_HIP(hipMalloc(&g->sort_tmp, g->sort_tmp_bytes));
+    SPHX_HIP(rocprim::radix_sort_pairs(g->sort_tmp, tmp, g->keys_in, g->keys, g->idx_in, g->perm,
+                                       size_t(n), 0, 63, s));
+
+    const int cap = P.leaf_max;
+    k_leaf_flags<<<blocks(n, 256), 256, 0, s>>>(n, g->keys, cap, g->flags);
+    SPHX_HIP(hipGetLastError());
+    SPHX_HIP(rocprim::inclusive_scan(g->sort_tmp, tmp2, g->flags, g->flags + n, size_t(n),
+                                     rocprim::plus<uint32_t>(), s));
+    // leaf_start needs n_leaves + 1 entries; n is an upper bound on n_leaves.
+    SPHX_TRY(dalloc(&g->leaf_start, n + 1));
+    k_leaf_index<<<blocks(n, 256), 256, 0, s>>>(n, g->flags, g->flags + n, g->leaf_of,
+                                                g->leaf_start, g->d_status + 1);
+    SPHX_HIP(hipGetLastError());
+    int32_t st[2];
+    SPHX_HIP(hipMemcpyAsync(st, g->d_status, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    SPHX_HIP(hipStreamSynchronize(s));
+    if (st[0] != 0) {
+        set_error("sphx_grid_build: " + std::to_string(st[0]) +
+                  " particles with non-finite or out-of-range x, h (0 < h <= h_max), m or u");
+        return SPHX_E_INVALID;
+    }
+    const int64_t nl = st[1];
+    g->n_leaves = nl;
+
+    // Tree levels over the leaves.
+    int64_t off = 0, cnt = nl;
+    int lev = 0;
+    while (true) {
+        g->level_off[lev] = off;
+        g->level_cnt[lev] = cnt;
+        off += cnt;
+        ++lev;
+        if (cnt <= 1 || lev == kMaxLevels)
+            break;
+        cnt = (cnt + kTreeFan - 1) / kTreeFan;
+    }
+    g->n_levels = lev;
+    g->n_nodes = off;
+    SPHX_TRY(dalloc(&g->leaf_org, 3 * nl));
+    SPHX_TRY(dalloc(&g->node_lo, 3 * off));
+    SPHX_TRY(dalloc(&g->node_hi, 3 * off));
+    SPHX_TRY(dalloc(&g->node_r, off));
+    SPHX_TRY(dalloc(&g->fsum, 6 * nl));
+
+    k_leaf_setup<<<unsigned(nl), 64, 0, s>>>(nl, g->leaf_start, g->perm, in->x, in->y, in->z,
+                                             in->vx, in->vy, in->vz, in->m, in->u, in->alpha_v,
+                                             in->alpha_c, P.box[0], P.box[1], P.box[2],
+                                             P.periodic, g->leaf_org, g->node_lo, g->node_hi,
+                                             g->q0, g->q1, g->qa);
+    SPHX_HIP(hipGetLastError());
+    for (int l = 0; l + 1 < g->n_levels; ++l) {
+        int64_t up = g->level_cnt[l + 1];
+        k_tree_level<<<blocks(up, 128), 128, 0, s>>>(
+            up, g->level_cnt[l], g->node_lo + 3 * g->level_off[l], g->node_hi + 3 * g->level_off[l],
+            g->node_lo + 3 * g->level_off[l + 1], g->node_hi + 3 * g->level_off[l + 1]);
+        SPHX_HIP(hipGetLastError());
+    }
+    SPHX_TRY(iter_reset(g, in, s));
+    guard.keep = true;
+    *out = g;
+    return SPHX_OK;
+}
+
+}  // namespace sphx

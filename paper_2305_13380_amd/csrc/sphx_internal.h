@@ -1,0 +1,171 @@
+// Internal state and helpers of the sphx library (not part of the C-ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "sphx.h"
+
+// ---------------------------------------------------------------------------
+// Error reporting (thread-local message behind sphx_last_error()).
+// ---------------------------------------------------------------------------
+namespace sphx {
+
+void set_error(const std::string &msg);
+
+#define SPHX_HIP(call)                                                                   \
+    do {                                                                                 \
+        hipError_t e_ = (call);                                                          \
+        if (e_ != hipSuccess) {                                                          \
+            ::sphx::set_error(std::string(#call) + ": " + hipGetErrorString(e_));        \
+            return e_ == hipErrorOutOfMemory ? SPHX_E_OOM : SPHX_E_HIP;                  \
+        }                                                                                \
+    } while (0)
+
+#define SPHX_TRY(expr)                                                                   \
+    do {                                                                                 \
+        sphx_status s_ = (expr);                                                         \
+        if (s_ < 0)                                                                      \
+            return s_;                                                                   \
+    } while (0)
+
+// One wave64 processes one leaf cell of at most kLeafMax particles.
+constexpr int kWave = 64;
+constexpr int kLeafMax = 64;
+constexpr int kTreeFan = 8;     // tree over leaves: groups of 8 consecutive nodes
+constexpr int kMaxLevels = 24;
+constexpr int kMortonBits = 21; // bits per axis of the 63-bit Morton key
+
+// Kernel constants of the Wendland C2 kernel: W = kW H^-3 (1-u)^4 (1+4u),
+// dW/dr = -kD H^-4 u (1-u)^3.
+constexpr float kW = 3.3422538049298023f;  // 21 / (2 pi)
+constexpr float kD = 66.845076098596050f;  // 210 / pi
+
+// Task record: j leaf and the FP32 offset origin_j + shift - origin_i.
+struct Task {
+    int32_t j;
+    float ox, oy, oz;
+};
+
+}  // namespace sphx
+
+namespace sphx {
+// Event pairs recorded around kernel launches while profiling is enabled.
+struct Profiler {
+    bool on = false;
+    struct Rec {
+        hipEvent_t a, b;
+    };
+    std::vector<Rec> pool[2];
+    size_t used[2] = {0, 0};
+    hipError_t begin(int k, hipStream_t s);
+    hipError_t end(int k, hipStream_t s);
+};
+}  // namespace sphx
+
+struct sphx_ctx {
+    sphx_params p;
+    sphx::Profiler *prof;
+    int device;
+    double h_max;
+    int32_t *d_counters;  // scratch counters used by sphx_step
+    double *d_sums;       // scratch FP64 sums used by sphx_step when the caller passes none
+};
+
+struct sphx_grid {
+    sphx_ctx *ctx;
+    int64_t n;
+    int64_t n_leaves;
+    int n_levels;
+    int64_t level_off[sphx::kMaxLevels];  // node offset of each tree level (level 0 = leaves)
+    int64_t level_cnt[sphx::kMaxLevels];
+    int64_t n_nodes;
+
+    // per sorted particle
+    uint64_t *keys;     // sorted Morton keys
+    int32_t *perm;      // sorted index -> caller index
+    int32_t *leaf_of;   // sorted index -> leaf
+    float4 *q0;         // x, y, z relative to the leaf origin; m
+    float4 *q1;         // vx, vy, vz, u
+    float2 *qa;         // alpha_v, alpha_c
+    uint8_t *need;      // 1: needs a density pass
+    float4 *g0;         // force-pass state: h, rho, P, c
+    float4 *g1;         // force-pass state: f, balsara, A, 0
+
+    // per leaf
+    int32_t *leaf_start;  // n_leaves + 1
+    double *leaf_org;     // 3 * n_leaves, FP64 origin (minimum corner of the particles' box)
+
+    // per tree node (all levels)
+    double *node_lo;    // 3 * n_nodes
+    double *node_hi;    // 3 * n_nodes
+    float *node_r;      // search radius of the node (max over its leaves), from tasks build
+
+    double *fsum;       // 6 * n_leaves FP64 partial sums of the force pass
+
+    // build scratch
+    void *sort_tmp;
+    size_t sort_tmp_bytes;
+    uint64_t *keys_in;
+    int32_t *idx_in;
+    uint32_t *flags;
+    int32_t *d_status;  // [0] invalid-input count, [1] leaf count
+};
+
+struct sphx_tasks {
+    sphx_grid *grid;
+    int64_t n_tasks;
+    int64_t cap;
+    int32_t *off;       // n_leaves + 1
+    sphx::Task *task;   // n_tasks
+    int32_t *count;     // n_leaves (scratch)
+    float *radius;      // per leaf: (1 + skin) * max H at build time
+    void *scan_tmp;
+    size_t scan_tmp_bytes;
+};
+
+namespace sphx {
+
+// grid.hip
+sphx_status grid_build(sphx_ctx *ctx, const sphx_particles *in, hipStream_t s, sphx_grid **out);
+void grid_free(sphx_grid *g);
+sphx_status iter_reset(sphx_grid *g, const sphx_particles *in, hipStream_t s);
+size_t grid_bytes(int64_t n);
+
+// tasks.hip
+sphx_status tasks_build(sphx_ctx *ctx, sphx_grid *g, const sphx_particles *in, hipStream_t s,
+                        sphx_tasks **out);
+void tasks_free(sphx_tasks *t);
+size_t tasks_bytes(int64_t n);
+
+// density.hip
+sphx_status density_launch(const sphx_ctx *ctx, const sphx_grid *g, const sphx_tasks *t,
+                           const sphx_particles *in, const sphx_density_out *out,
+                           int32_t *counters, hipStream_t s);
+
+// ghost.hip
+sphx_status ghost_launch(const sphx_ctx *ctx, sphx_grid *g, const sphx_tasks *t,
+                         sphx_particles *in, const sphx_density_out *d, const sphx_ghost_out *o,
+                         int32_t *counters, int final_pass, hipStream_t s);
+
+// force.hip
+sphx_status force_launch(const sphx_ctx *ctx, const sphx_grid *g, const sphx_tasks *t,
+                         const sphx_particles *in, const sphx_density_out *d,
+                         const sphx_ghost_out *gs, const sphx_force_out *o, double *sums6,
+                         hipStream_t s);
+
+// Blocks are dealt round-robin to the 8 XCDs of the MI355X; remap so that each
+// XCD works on a contiguous range of leaves (which share neighbour data in
+// that XCD's L2).
+__device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t nblocks_padded)
+{
+    const int64_t per = nblocks_padded >> 3;
+    return (b & 7) * per + (b >> 3);
+}
+
+inline int64_t pad8(int64_t n) { return (n + 7) & ~int64_t(7); }
+
+}  // namespace sphx

@@ -1,0 +1,302 @@
+// Tasks build: for each leaf cell, the self task and the pair tasks with every
+// leaf whose bounding box lies within the larger of the two search radii
+// (Section 2.2: self and pair tasks; interactions happen at the level whose
+// cell size matches the local search radius). The search walks a tree of
+// bounding boxes over the Morton-ordered leaves once per rebuild; the
+// neighbour loops themselves never walk it.
+#include <rocprim/device/device_scan.hpp>
+
+#include "sphx_internal.h"
+
+// The count and fill kernels below must reach identical decisions: keep the
+// compiler from contracting the box-distance arithmetic differently in each.
+#pragma clang fp contract(off)
+
+namespace sphx {
+namespace {
+
+inline unsigned blocks(int64_t n, int t) { return unsigned((n + t - 1) / t); }
+
+__device__ __forceinline__ float wave_maxf(float v)
+{
+    for (int o = 32; o > 0; o >>= 1)
+        v = fmaxf(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// One wave per leaf: radius = (1 + skin) * gamma_k * max h over the leaf.
+__global__ __launch_bounds__(64) void k_leaf_radius(int64_t n_leaves,
+                                                    const int32_t *__restrict__ leaf_start,
+                                                    const int32_t *__restrict__ perm,
+                                                    const float *__restrict__ h, float scale,
+                                                    float *__restrict__ node_r,
+                                                    float *__restrict__ radius)
+{
+    int64_t L = blockIdx.x;
+    if (L >= n_leaves)
+        return;
+    int lane = threadIdx.x;
+    int32_t s0 = leaf_start[L], cnt = leaf_start[L + 1] - s0;
+    float v = lane < cnt ? h[perm[s0 + lane]] : 0.0f;
+    v = wave_maxf(v) * scale;
+    if (lane == 0) {
+        node_r[L] = v;
+        radius[L] = v;
+    }
+}
+
+__global__ void k_tree_radius(int64_t cnt_up, int64_t cnt_dn, const float *__restrict__ r_dn,
+                              float *__restrict__ r_up)
+{
+    int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (c >= cnt_up)
+        return;
+    int64_t e = (c + 1) * kTreeFan;
+    if (e > cnt_dn)
+        e = cnt_dn;
+    float r = 0.0f;
+    for (int64_t k = c * kTreeFan; k < e; ++k)
+        r = fmaxf(r, r_dn[k]);
+    r_up[c] = r;
+}
+
+struct TreeView {
+    const double *lo, *hi;
+    const float *r;
+    int64_t level_off[kMaxLevels];
+    int64_t level_cnt[kMaxLevels];
+    int n_levels;
+    double L[3];
+    int periodic;
+};
+
+// Gap between [alo, ahi] and [blo, bhi] + s*L along one axis, for the shifts
+// s in {-1, 0, 1} (periodic) or {0}.
+__device__ __forceinline__ void axis_gaps(double alo, double ahi, double blo, double bhi,
+                                          double L, int periodic, double g[3])
+{
+    for (int k = 0; k < 3; ++k) {
+        double sh = double(k - 1) * L;
+        if (!periodic && k != 1) {
+            g[k] = INFINITY;
+            continue;
+        }
+        double a = blo + sh - ahi, b = alo - (bhi + sh);
+        double d = a > b ? a : b;
+        g[k] = d > 0.0 ? d : 0.0;
+    }
+}
+
+// Walk the tree for leaf `I`; for every leaf J (ascending) and shift whose box
+// gap is below max(R_I, R_J), call emit(J, sx, sy, sz).
+template <class Emit>
+__device__ void walk(const TreeView &T, int64_t I, Emit &&emit)
+{
+    const double *ilo = T.lo + 3 * I, *ihi = T.hi + 3 * I;
+    const double alo[3] = {ilo[0], ilo[1], ilo[2]}, ahi[3] = {ihi[0], ihi[1], ihi[2]};
+    const float RI = T.r[I];
+    // stack of (level, node) packed as level * 2^40 + node
+    int64_t stack[kTreeFan * kMaxLevels + 8];
+    int sp = 0;
+    const int top = T.n_levels - 1;
+    for (int64_t c = T.level_cnt[top] - 1; c >= 0; --c)
+        stack[sp++] = (int64_t(top) << 40) | c;
+    while (sp > 0) {
+        int64_t e = stack[--sp];
+        int lev = int(e >> 40);
+        int64_t c = e & ((int64_t(1) << 40) - 1);
+        int64_t node = T.level_off[lev] + c;
+        double R = fmax(double(RI), double(T.r[node]));
+        double R2 = R * R;
+        double g[3][3];
+        double d2 = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            axis_gaps(alo[a], ahi[a], T.lo[3 * node + a], T.hi[3 * node + a], T.L[a], T.periodic,
+                      g[a]);
+            double m = fmin(g[a][0], fmin(g[a][1], g[a][2]));
+            d2 += m * m;
+        }
+        if (!(d2 < R2))
+            continue;
+        if (lev == 0) {
+            for (int sx = 0; sx < 3; ++sx) {
+                if (!(g[0][sx] < R))
+                    continue;
+                for (int sy = 0; sy < 3; ++sy) {
+                    if (!(g[1][sy] < R))
+                        continue;
+                    for (int sz = 0; sz < 3; ++sz) {
+                        if (!(g[2][sz] < R))
+                            continue;
+                        double dd = g[0][sx] * g[0][sx] + g[1][sy] * g[1][sy] + g[2][sz] * g[2][sz];
+                        if (dd < R2)
+                            emit(c, sx - 1, sy - 1, sz - 1);
+                    }
+                }
+            }
+            continue;
+        }
+        int64_t b = c * kTreeFan, e2 = b + kTreeFan;
+        if (e2 > T.level_cnt[lev - 1])
+            e2 = T.level_cnt[lev - 1];
+        for (int64_t k = e2 - 1; k >= b; --k)
+            stack[sp++] = (int64_t(lev - 1) << 40) | k;
+    }
+}
+
+__global__ void k_task_count(int64_t n_leaves, TreeView T, int32_t *__restrict__ count)
+{
+    int64_t I = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (I >= n_leaves)
+        return;
+    int32_t c = 0;
+    walk(T, I, [&](int64_t, int, int, int) { ++c; });
+    count[I] = c;
+}
+
+__global__ void k_task_fill(int64_t n_leaves, TreeView T, const double *__restrict__ org,
+                            const int32_t *__restrict__ off, Task *__restrict__ task)
+{
+    int64_t I = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (I >= n_leaves)
+        return;
+    int32_t w = off[I];
+    const int32_t w_end = off[I + 1];
+    const double ox = org[3 * I], oy = org[3 * I + 1], oz = org[3 * I + 2];
+    walk(T, I, [&](int64_t J, int sx, int sy, int sz) {
+        Task t;
+        t.j = int32_t(J);
+        // origin_j + shift - origin_i, formed in FP64, stored in FP32
+        t.ox = float(org[3 * J] + double(sx) * T.L[0] - ox);
+        t.oy = float(org[3 * J + 1] + double(sy) * T.L[1] - oy);
+        t.oz = float(org[3 * J + 2] + double(sz) * T.L[2] - oz);
+        if (w < w_end)
+            task[w++] = t;
+    });
+}
+
+}  // namespace
+
+size_t tasks_bytes(int64_t n)
+{
+    // Budget ~40 tasks per leaf and one leaf per 16 particles, plus per-leaf arrays.
+    int64_t leaves = n / 16 + 1;
+    return size_t(leaves) * (40 * sizeof(Task) + 4 * 3) + (1 << 20);
+}
+
+void tasks_free(sphx_tasks *t)
+{
+    if (!t)
+        return;
+    void *ptrs[] = {t->off, t->task, t->count, t->radius, t->scan_tmp};
+    for (void *p : ptrs)
+        if (p)
+            (void)hipFree(p);
+    delete t;
+}
+
+sphx_status tasks_build(sphx_ctx *ctx, sphx_grid *g, const sphx_particles *in, hipStream_t s,
+                        sphx_tasks **out)
+{
+    sphx_tasks *t = *out;
+    const int64_t nl = g->n_leaves;
+    if (t && t->grid != g) {
+        set_error("sphx_tasks_build: task list belongs to another grid");
+        return SPHX_E_STATE;
+    }
+    bool fresh = false;
+    if (!t) {
+        t = new sphx_tasks();
+        t->grid = g;
+        fresh = true;
+        auto fail = [&](sphx_status st) {
+            tasks_free(t);
+            return st;
+        };
+        if (hipMalloc(&t->off, (nl + 1) * sizeof(int32_t)) != hipSuccess ||
+            hipMalloc(&t->count, (nl + 1) * sizeof(int32_t)) != hipSuccess ||
+            hipMalloc(&t->radius, (nl + 1) * sizeof(float)) != hipSuccess) {
+            set_error("sphx_tasks_build: out of device memory");
+            return fail(SPHX_E_OOM);
+        }
+        size_t tmp = 0;
+        if (rocprim::exclusive_scan(nullptr, tmp, t->count, t->off, 0, size_t(nl + 1),
+                                    rocprim::plus<int32_t>(), s) != hipSuccess ||
+            hipMalloc(&t->scan_tmp, tmp + 16) != hipSuccess) {
+            set_error("sphx_tasks_build: scan workspace");
+            return fail(SPHX_E_OOM);
+        }
+        t->scan_tmp_bytes = tmp;
+    }
+    struct Guard {
+        sphx_tasks *t;
+        bool fresh;
+        bool keep = false;
+        ~Guard()
+        {
+            if (fresh && !keep)
+                tasks_free(t);
+        }
+    } guard{t, fresh};
+
+    if (nl == 0) {
+        t->n_tasks = 0;
+        SPHX_HIP(hipMemsetAsync(t->off, 0, sizeof(int32_t), s));
+        guard.keep = true;
+        *out = t;
+        return SPHX_OK;
+    }
+    const float scale = float(ctx->p.gamma_k * (1.0 + ctx->p.skin));
+    k_leaf_radius<<<unsigned(nl), 64, 0, s>>>(nl, g->leaf_start, g->perm, in->h, scale, g->node_r,
+                                              t->radius);
+    SPHX_HIP(hipGetLastError());
+    for (int l = 0; l + 1 < g->n_levels; ++l) {
+        int64_t up = g->level_cnt[l + 1];
+        k_tree_radius<<<blocks(up, 128), 128, 0, s>>>(up, g->level_cnt[l],
+                                                        g->node_r + g->level_off[l],
+                                                        g->node_r + g->level_off[l + 1]);
+        SPHX_HIP(hipGetLastError());
+    }
+    TreeView T;
+    T.lo = g->node_lo;
+    T.hi = g->node_hi;
+    T.r = g->node_r;
+    for (int l = 0; l < kMaxLevels; ++l) {
+        T.level_off[l] = l < g->n_levels ? g->level_off[l] : 0;
+        T.level_cnt[l] = l < g->n_levels ? g->level_cnt[l] : 0;
+    }
+    T.n_levels = g->n_levels;
+    for (int a = 0; a < 3; ++a)
+        T.L[a] = ctx->p.box[a];
+    T.periodic = ctx->p.periodic;
+
+    SPHX_HIP(hipMemsetAsync(t->count + nl, 0, sizeof(int32_t), s));
+    k_task_count<<<blocks(nl, 64), 64, 0, s>>>(nl, T, t->count);
+    SPHX_HIP(hipGetLastError());
+    size_t tmp = t->scan_tmp_bytes;
+    SPHX_HIP(rocprim::exclusive_scan(t->scan_tmp, tmp, t->count, t->off, 0, size_t(nl + 1),
+                                     rocprim::plus<int32_t>(), s));
+    int32_t total = 0;
+    SPHX_HIP(hipMemcpyAsync(&total, t->off + nl, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    SPHX_HIP(hipStreamSynchronize(s));
+    if (total < 0) {
+        set_error("sphx_tasks_build: task count overflow");
+        return SPHX_E_INVALID;
+    }
+    if (int64_t(total) > t->cap) {
+        if (t->task)
+            SPHX_HIP(hipFree(t->task));
+        t->task = nullptr;
+        int64_t cap = int64_t(total) + int64_t(total) / 4 + 64;
+        SPHX_HIP(hipMalloc(&t->task, size_t(cap) * sizeof(Task)));
+        t->cap = cap;
+    }
+    t->n_tasks = total;
+    k_task_fill<<<blocks(nl, 64), 64, 0, s>>>(nl, T, g->leaf_org, t->off, t->task);
+    SPHX_HIP(hipGetLastError());
+    guard.keep = true;
+    *out = t;
+    return SPHX_OK;
+}
+
+}  // namespace sphx

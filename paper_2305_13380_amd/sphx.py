@@ -1,0 +1,336 @@
+"""ctypes binding of libsphx.so (the C-ABI declared in include/sphx.h).
+
+Argument marshalling only: every step of the hot path runs in the library's
+HIP kernels. PyTorch provides device memory (tensors) and streams. Importing
+this module loads the library and raises if it has not been built: there is
+no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsphx.so")
+
+OK = 0
+E_INVALID, E_OOM, E_HIP, E_STATE = -1, -2, -3, -4
+W_NOT_CONVERGED, W_H_CLAMPED, W_REBUILD = 1, 2, 4
+COUNTERS = 4
+
+
+class SphxError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("sphx status %d: %s" % (status, msg))
+        self.status = status
+
+
+class Params(C.Structure):
+    _fields_ = [("box", C.c_double * 3), ("periodic", C.c_int32), ("max_iter", C.c_int32),
+                ("gamma_k", C.c_double), ("eta", C.c_double), ("h_tol", C.c_double),
+                ("h_max", C.c_double), ("gamma_gas", C.c_double), ("beta_v", C.c_double),
+                ("eps_balsara", C.c_double), ("skin", C.c_double), ("leaf_max", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
+class Particles(C.Structure):
+    _fields_ = [("n", C.c_int64)] + [(k, C.c_void_p) for k in (
+        "x", "y", "z", "vx", "vy", "vz", "m", "u", "h", "alpha_v", "alpha_c", "active")]
+
+
+class DensityOut(C.Structure):
+    _fields_ = [(k, C.c_void_p) for k in (
+        "rho", "rho_dh", "n", "n_dh", "div_sum", "curl_x", "curl_y", "curl_z", "nngb")]
+
+
+class GhostOut(C.Structure):
+    _fields_ = [(k, C.c_void_p) for k in (
+        "f", "P", "c", "balsara", "A", "div_v", "curl_v", "converged")]
+
+
+class ForceOut(C.Structure):
+    _fields_ = [(k, C.c_void_p) for k in ("ax", "ay", "az", "du_dt", "v_sig", "nforce")]
+
+
+class StepInfo(C.Structure):
+    _fields_ = [("passes", C.c_int32), ("task_rebuilds", C.c_int32), ("unconverged", C.c_int32),
+                ("clamped", C.c_int32), ("n_leaves", C.c_int64), ("n_tasks", C.c_int64)]
+
+
+SYMBOLS = ("sphx_params_default", "sphx_ctx_create", "sphx_ctx_destroy", "sphx_workspace_bytes",
+           "sphx_grid_build", "sphx_grid_destroy", "sphx_tasks_build", "sphx_tasks_destroy",
+           "sphx_iter_reset", "sphx_density", "sphx_ghost", "sphx_force", "sphx_step",
+           "sphx_grid_leaves", "sphx_tasks_count", "sphx_last_error", "sphx_profile_enable",
+           "sphx_profile_read")
+
+_LIB = None
+
+
+def _load():
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libsphx.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+    L = C.CDLL(LIB_PATH)
+    vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
+    P = C.POINTER
+    L.sphx_params_default.argtypes = [P(Params)]
+    L.sphx_params_default.restype = None
+    L.sphx_ctx_create.argtypes = [P(Params), C.c_int, P(vp)]
+    L.sphx_ctx_destroy.argtypes = [vp]
+    L.sphx_ctx_destroy.restype = None
+    L.sphx_workspace_bytes.argtypes = [P(Params), i64]
+    L.sphx_workspace_bytes.restype = C.c_size_t
+    L.sphx_grid_build.argtypes = [vp, P(Particles), vp, P(vp)]
+    L.sphx_grid_destroy.argtypes = [vp]
+    L.sphx_grid_destroy.restype = None
+    L.sphx_tasks_build.argtypes = [vp, vp, P(Particles), vp, P(vp)]
+    L.sphx_tasks_destroy.argtypes = [vp]
+    L.sphx_tasks_destroy.restype = None
+    L.sphx_iter_reset.argtypes = [vp, vp, P(Particles), vp]
+    L.sphx_density.argtypes = [vp, vp, vp, P(Particles), P(DensityOut), vp, vp]
+    L.sphx_ghost.argtypes = [vp, vp, vp, P(Particles), P(DensityOut), P(GhostOut), vp, i32, vp]
+    L.sphx_force.argtypes = [vp, vp, vp, P(Particles), P(DensityOut), P(GhostOut), P(ForceOut),
+                             vp, vp]
+    L.sphx_step.argtypes = [vp, vp, P(vp), P(Particles), P(DensityOut), P(GhostOut),
+                            P(ForceOut), vp, vp, P(StepInfo)]
+    L.sphx_grid_leaves.argtypes = [vp]
+    L.sphx_grid_leaves.restype = i64
+    L.sphx_tasks_count.argtypes = [vp]
+    L.sphx_tasks_count.restype = i64
+    L.sphx_profile_enable.argtypes = [vp, i32]
+    L.sphx_profile_enable.restype = i32
+    L.sphx_profile_read.argtypes = [vp, i32, P(C.c_double), P(i64)]
+    L.sphx_profile_read.restype = i32
+    L.sphx_last_error.argtypes = []
+    L.sphx_last_error.restype = C.c_char_p
+    for name in ("sphx_ctx_create", "sphx_grid_build", "sphx_tasks_build", "sphx_iter_reset",
+                 "sphx_density", "sphx_ghost", "sphx_force", "sphx_step"):
+        getattr(L, name).restype = i32
+    _LIB = L
+    return L
+
+
+lib = _load()
+
+
+def last_error() -> str:
+    return lib.sphx_last_error().decode()
+
+
+def _check(status):
+    if status < 0:
+        raise SphxError(status, last_error())
+    return status
+
+
+def default_params(**kw) -> Params:
+    p = Params()
+    lib.sphx_params_default(C.byref(p))
+    for k, v in kw.items():
+        if k == "box":
+            p.box = (C.c_double * 3)(*v)
+        else:
+            setattr(p, k, v)
+    return p
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+class Context:
+    def __init__(self, params: Optional[Params] = None, device: int = 0):
+        self.params = params if params is not None else default_params()
+        self.device = device
+        h = C.c_void_p()
+        _check(lib.sphx_ctx_create(C.byref(self.params), device, C.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if self.handle:
+            lib.sphx_ctx_destroy(self.handle)
+            self.handle = None
+
+    __del__ = close
+
+    def profile(self, enable: bool):
+        _check(lib.sphx_profile_enable(self.handle, 1 if enable else 0))
+
+    def profile_read(self, kernel: int):
+        """(total milliseconds, launches) of kernel 0 (density) or 1 (force)."""
+        ms, n = C.c_double(), C.c_int64()
+        _check(lib.sphx_profile_read(self.handle, kernel, C.byref(ms), C.byref(n)))
+        return ms.value, n.value
+
+    def workspace_bytes(self, n: int) -> int:
+        return int(lib.sphx_workspace_bytes(C.byref(self.params), int(n)))
+
+
+@dataclass
+class DeviceParticles:
+    """Device-resident particle arrays (torch tensors) and their C view."""
+    t: dict
+    n: int
+
+    @classmethod
+    def from_set(cls, ps, device="cuda"):
+        import torch
+        t = {}
+        for k in ("x", "y", "z"):
+            t[k] = torch.from_numpy(np.ascontiguousarray(getattr(ps, k), np.float64)).to(device)
+        for k in ("vx", "vy", "vz", "m", "u", "h", "alpha_v", "alpha_c"):
+            t[k] = torch.from_numpy(np.ascontiguousarray(getattr(ps, k), np.float32)).to(device)
+        t["active"] = None if ps.active is None else torch.from_numpy(
+            np.ascontiguousarray(ps.active, np.uint8)).to(device)
+        return cls(t, ps.n)
+
+    def view(self) -> Particles:
+        p = Particles()
+        p.n = self.n
+        for k in ("x", "y", "z", "vx", "vy", "vz", "m", "u", "h", "alpha_v", "alpha_c", "active"):
+            setattr(p, k, _ptr(self.t[k]))
+        return p
+
+
+DENS_F32 = ("rho", "rho_dh", "n", "n_dh", "div_sum", "curl_x", "curl_y", "curl_z")
+GHOST_F32 = ("f", "P", "c", "balsara", "A", "div_v", "curl_v")
+FORCE_F32 = ("ax", "ay", "az", "du_dt", "v_sig")
+
+
+class Outputs:
+    """Caller-owned output arrays for the density, ghost and force passes."""
+
+    def __init__(self, n, device="cuda"):
+        import torch
+        f = lambda: torch.full((n,), float("nan"), dtype=torch.float32, device=device)
+        self.d = {k: f() for k in DENS_F32}
+        self.d["nngb"] = torch.full((n,), -1, dtype=torch.int32, device=device)
+        self.g = {k: f() for k in GHOST_F32}
+        self.g["converged"] = torch.zeros((n,), dtype=torch.uint8, device=device)
+        self.f = {k: f() for k in FORCE_F32}
+        self.f["nforce"] = torch.full((n,), -1, dtype=torch.int32, device=device)
+        self.counters = torch.zeros((COUNTERS,), dtype=torch.int32, device=device)
+        self.sums = torch.zeros((6,), dtype=torch.float64, device=device)
+
+    def dens_view(self):
+        o = DensityOut()
+        for k in DENS_F32 + ("nngb",):
+            setattr(o, k, _ptr(self.d[k]))
+        return o
+
+    def ghost_view(self):
+        o = GhostOut()
+        for k in GHOST_F32 + ("converged",):
+            setattr(o, k, _ptr(self.g[k]))
+        return o
+
+    def force_view(self):
+        o = ForceOut()
+        for k in FORCE_F32 + ("nforce",):
+            setattr(o, k, _ptr(self.f[k]))
+        return o
+
+
+class Grid:
+    def __init__(self, ctx: Context, parts: DeviceParticles, stream=None):
+        self.ctx = ctx
+        self.pv = parts.view()
+        h = C.c_void_p()
+        _check(lib.sphx_grid_build(ctx.handle, C.byref(self.pv), _stream(stream), C.byref(h)))
+        self.handle = h
+
+    @property
+    def n_leaves(self):
+        return int(lib.sphx_grid_leaves(self.handle))
+
+    def close(self):
+        if self.handle:
+            lib.sphx_grid_destroy(self.handle)
+            self.handle = None
+
+    __del__ = close
+
+
+class Tasks:
+    def __init__(self, ctx: Context, grid: Grid, parts: DeviceParticles, stream=None):
+        self.ctx = ctx
+        self.grid = grid
+        self.handle = C.c_void_p()
+        self.build(parts, stream)
+
+    def build(self, parts: DeviceParticles, stream=None):
+        pv = parts.view()
+        _check(lib.sphx_tasks_build(self.ctx.handle, self.grid.handle, C.byref(pv),
+                                    _stream(stream), C.byref(self.handle)))
+
+    @property
+    def count(self):
+        return int(lib.sphx_tasks_count(self.handle))
+
+    def close(self):
+        if self.handle:
+            lib.sphx_tasks_destroy(self.handle)
+            self.handle = None
+
+    __del__ = close
+
+
+def iter_reset(ctx, grid, parts, stream=None):
+    pv = parts.view()
+    return _check(lib.sphx_iter_reset(ctx.handle, grid.handle, C.byref(pv), _stream(stream)))
+
+
+def density(ctx, grid, tasks, parts, out: Outputs, counters=True, stream=None):
+    pv = parts.view()
+    dv = out.dens_view()
+    return _check(lib.sphx_density(ctx.handle, grid.handle, tasks.handle, C.byref(pv),
+                                   C.byref(dv), _ptr(out.counters) if counters else None,
+                                   _stream(stream)))
+
+
+def ghost(ctx, grid, tasks, parts, out: Outputs, final_pass=False, counters=True, stream=None):
+    pv = parts.view()
+    dv, gv = out.dens_view(), out.ghost_view()
+    return _check(lib.sphx_ghost(ctx.handle, grid.handle, tasks.handle, C.byref(pv), C.byref(dv),
+                                 C.byref(gv), _ptr(out.counters) if counters else None,
+                                 1 if final_pass else 0, _stream(stream)))
+
+
+def force(ctx, grid, tasks, parts, out: Outputs, sums=True, stream=None):
+    pv = parts.view()
+    dv, gv, fv = out.dens_view(), out.ghost_view(), out.force_view()
+    return _check(lib.sphx_force(ctx.handle, grid.handle, tasks.handle, C.byref(pv), C.byref(dv),
+                                 C.byref(gv), C.byref(fv), _ptr(out.sums) if sums else None,
+                                 _stream(stream)))
+
+
+def step(ctx, grid, tasks: Tasks, parts, out: Outputs, stream=None):
+    pv = parts.view()
+    dv, gv, fv = out.dens_view(), out.ghost_view(), out.force_view()
+    info = StepInfo()
+    st = _check(lib.sphx_step(ctx.handle, grid.handle, C.byref(tasks.handle), C.byref(pv),
+                              C.byref(dv), C.byref(gv), C.byref(fv), _ptr(out.sums),
+                              _stream(stream), C.byref(info)))
+    return st, info
+
+
+def fixed_h_pass(ctx, grid, tasks, parts, out: Outputs, stream=None):
+    """Density at the current h, ghost finalisation without changing h (one
+    final pass), force: the three loops at a fixed h."""
+    iter_reset(ctx, grid, parts, stream)
+    out.counters.zero_()
+    density(ctx, grid, tasks, parts, out, stream=stream)
+    ghost(ctx, grid, tasks, parts, out, final_pass=True, stream=stream)
+    force(ctx, grid, tasks, parts, out, stream=stream)

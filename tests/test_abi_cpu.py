@@ -1,0 +1,79 @@
+"""Host-side checks of the C-ABI library (no GPU needed): it loads, exports
+every entry point the header declares, fills the paper's defaults, and
+rejects invalid parameters before touching a device."""
+import ctypes as C
+import math
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sphx.h")
+
+
+@pytest.fixture(scope="module")
+def sphx():
+    from paper_2305_13380_amd import build
+    if not os.path.exists(build.LIB):
+        build.build()
+    from paper_2305_13380_amd import sphx as mod
+    return mod
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return set(re.findall(r"\b(sphx_[a-z0-9_]+)\s*\(", text))
+
+
+def test_header_declares_the_boundary_calls():
+    names = declared_functions()
+    for must in ("sphx_ctx_create", "sphx_ctx_destroy", "sphx_workspace_bytes", "sphx_grid_build",
+                 "sphx_tasks_build", "sphx_density", "sphx_ghost", "sphx_force", "sphx_step",
+                 "sphx_grid_destroy", "sphx_tasks_destroy", "sphx_last_error"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol(sphx):
+    lib = C.CDLL(sphx.LIB_PATH)
+    for name in sorted(declared_functions()):
+        assert hasattr(lib, name), name
+    assert declared_functions() <= set(sphx.SYMBOLS)
+
+
+def test_default_params_are_the_papers(sphx):
+    p = sphx.default_params()
+    assert tuple(p.box) == (1.0, 1.0, 1.0) and p.periodic == 1
+    assert p.h_tol == 1e-4 and p.beta_v == 3.0 and p.eps_balsara == 1e-4
+    assert abs(p.gamma_gas - 5.0 / 3.0) < 1e-15
+    assert abs(p.gamma_k - math.sqrt(15.0) / 2.0) < 1e-15
+    assert p.eta == 1.2348 and p.leaf_max == 64 and p.max_iter == 30
+
+
+@pytest.mark.parametrize("field,value", [("eta", 0.0), ("h_tol", -1.0), ("max_iter", 0),
+                                         ("leaf_max", 4), ("leaf_max", 65), ("gamma_k", 0.0),
+                                         ("box", (1.0, 0.0, 1.0)), ("gamma_gas", 1.0)])
+def test_ctx_create_rejects_invalid_params(sphx, field, value):
+    p = sphx.default_params(**{field: value})
+    h = C.c_void_p()
+    st = sphx.lib.sphx_ctx_create(C.byref(p), 0, C.byref(h))
+    assert st == sphx.E_INVALID
+    assert sphx.last_error()
+    assert not h.value
+
+
+def test_workspace_bytes_grows_with_n(sphx):
+    p = sphx.default_params()
+    a = sphx.lib.sphx_workspace_bytes(C.byref(p), 1000)
+    b = sphx.lib.sphx_workspace_bytes(C.byref(p), 1_000_000)
+    assert 0 < a < b
+    assert b < 1_000_000 * 2000  # a few hundred bytes per particle
+    assert sphx.lib.sphx_workspace_bytes(C.byref(p), -1) == 0
+
+
+def test_null_arguments_are_errors(sphx):
+    assert sphx.lib.sphx_ctx_create(None, 0, None) == sphx.E_INVALID
+    assert sphx.lib.sphx_grid_build(None, None, None, None) == sphx.E_INVALID
+    assert sphx.lib.sphx_step(None, None, None, None, None, None, None, None, None,
+                              None) == sphx.E_INVALID
