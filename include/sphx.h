@@ -191,13 +191,16 @@ sphx_status sphx_density(sphx_ctx *ctx, const sphx_grid *grid, const sphx_tasks 
 
 /* Ghost (Section 3.1 NR update; Sections 3.1-3.2 EOS, f-factor, Balsara): for
  * every particle marked as needing a pass, one Newton-Raphson step of h on
- * F(h) = n h^3 - eta^3 from the sums in *dens; the step is limited to
- * [h/2, 2h] and h_max. A particle whose step is below h_tol*h is converged:
- * it keeps the h its sums were evaluated at, its ghost outputs are written
- * and its mark is cleared. Otherwise its h (caller array) is replaced by the
- * new value, unless final_pass != 0, in which case it keeps its h and is
- * reported unconverged. Adds to d_counters (see SPHX_COUNTERS).
- * Asynchronous. */
+ * F(h) = n h^3 - eta^3 from the sums of the last sphx_density pass on this
+ * grid (the values it wrote to *dens, also kept in the grid's workspace in
+ * sorted order, together with the h they were evaluated at); the step is
+ * limited to [h/2, 2h] and h_max. A particle whose step is below h_tol*h is
+ * converged: it keeps that h, its ghost outputs are written and its mark is
+ * cleared. Otherwise its h (caller array) is replaced by the new value,
+ * unless final_pass != 0, in which case it keeps its h, its ghost outputs are
+ * written and it is reported unconverged. Adds to d_counters (see
+ * SPHX_COUNTERS; may be NULL). Does nothing when d_counters[3] > 0 (the
+ * preceding density pass ran on a stale task list). Asynchronous. */
 sphx_status sphx_ghost(sphx_ctx *ctx, sphx_grid *grid, const sphx_tasks *tasks,
                        sphx_particles *in, const sphx_density_out *dens, sphx_ghost_out *out,
                        int32_t *d_counters, int32_t final_pass, void *stream);

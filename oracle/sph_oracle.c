@@ -153,28 +153,34 @@ int64_t or_density(int64_t n, const double *x, const double *y, const double *z,
 
 /*
  * One Newton-Raphson update of h on the partition-of-unity condition
- * (Section 3.1): F(h) = n(h) h^3 - eta^3 = 0, F'(h) = h^3 dn/dh + 3 h^2 n.
- * The step is limited to [h/2, 2h] and to h <= h_max; when F' is not
- * positive the step is a halving or doubling in the direction of -F. The
- * particle is converged when the step is below h_tol * h; its h then stays
- * at the value the sums were evaluated at.
+ * (Section 3.1), n(h) (h/eta)^3 = 1, taken in the variable ln h:
+ *   G(ln h) = ln(n h^3 / eta^3) = 0,   dG/d ln h = 3 + (h/n) dn/dh,
+ *   ln h_new = ln h - G / G'.
+ * (The paper names the method and the condition, not the variable; in ln h a
+ * uniform medium converges in one step from any start.) The step is limited
+ * to a factor 2 either way and to h <= h_max; when G' is not positive the
+ * step is a halving or doubling in the direction of -G. The particle is
+ * converged when the change is below h_tol * h; its h then stays at the value
+ * the sums were evaluated at.
  */
 void or_h_update(int64_t n, const double *h, const double *nd, const double *nd_dh,
                  double eta, double h_tol, double h_max, double *h_new, int32_t *converged)
 {
+    const double ln2 = log(2.0);
     for (int64_t k = 0; k < n; ++k) {
         double hk = h[k];
-        double F = nd[k] * hk * hk * hk - eta * eta * eta;
-        double dF = hk * hk * hk * nd_dh[k] + 3.0 * hk * hk * nd[k];
-        double hn;
-        if (dF > 0.0 && isfinite(F / dF))
-            hn = hk - F / dF;
+        double G = log(nd[k] * hk * hk * hk / (eta * eta * eta));
+        double dG = 3.0 + hk * nd_dh[k] / nd[k];
+        double step;
+        if (dG > 0.0 && isfinite(G / dG))
+            step = -G / dG;
         else
-            hn = (F < 0.0) ? 2.0 * hk : 0.5 * hk;
-        if (hn < 0.5 * hk)
-            hn = 0.5 * hk;
-        if (hn > 2.0 * hk)
-            hn = 2.0 * hk;
+            step = (G < 0.0) ? ln2 : -ln2;
+        if (step > ln2)
+            step = ln2;
+        if (step < -ln2)
+            step = -ln2;
+        double hn = hk * exp(step);
         if (hn > h_max)
             hn = h_max;
         if (fabs(hn - hk) < h_tol * hk) {

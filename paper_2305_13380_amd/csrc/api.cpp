@@ -204,6 +204,7 @@ sphx_status sphx_tasks_build(sphx_ctx *ctx, sphx_grid *grid, const sphx_particle
     SPHX_TRY(check_handles(ctx, grid, *out, in));
     SPHX_TRY(check_particles(in, false));
     SPHX_HIP(hipSetDevice(ctx->device));
+    SPHX_TRY(refresh_h(grid, in, as_stream(stream)));
     return tasks_build(ctx, grid, in, as_stream(stream), out);
 }
 
@@ -229,6 +230,8 @@ sphx_status sphx_density(sphx_ctx *ctx, const sphx_grid *grid, const sphx_tasks 
         set_error("sphx_density: NULL task list or output array");
         return SPHX_E_INVALID;
     }
+    // the caller may have changed h since the last pass
+    SPHX_TRY(refresh_h(const_cast<sphx_grid *>(grid), in, as_stream(stream)));
     return density_launch(ctx, grid, tasks, in, out, d_counters, as_stream(stream));
 }
 
@@ -287,9 +290,9 @@ sphx_status sphx_step(sphx_ctx *ctx, sphx_grid *grid, sphx_tasks **tasks, sphx_p
     int pass = 0, stale_repeats = 0;
     while (pass < max_iter) {
         SPHX_HIP(hipMemsetAsync(dc, 0, SPHX_COUNTERS * sizeof(int32_t), s));
-        SPHX_TRY(sphx_density(ctx, grid, *tasks, in, dens, dc, stream));
+        SPHX_TRY(density_launch(ctx, grid, *tasks, in, dens, dc, s));
         const int final_pass = (pass + 1 == max_iter) ? 1 : 0;
-        SPHX_TRY(sphx_ghost(ctx, grid, *tasks, in, dens, gst, dc, final_pass, stream));
+        SPHX_TRY(ghost_launch(ctx, grid, *tasks, in, dens, gst, dc, final_pass, s));
         SPHX_HIP(hipMemcpyAsync(h_counters, dc, sizeof(h_counters), hipMemcpyDeviceToHost, s));
         SPHX_HIP(hipStreamSynchronize(s));
         if (h_counters[3] > 0) {

@@ -1,113 +1,243 @@
 // Density pass (Section 3.1): number density, mass density, their
 // h-derivatives, neighbour count, and the velocity divergence and curl sums.
-//
-// One wave64 per receiving leaf (one particle per lane). Each task's source
-// leaf is staged in LDS with the task's FP32 origin offset already applied,
-// so every lane works on small cell-relative FP32 coordinates; LDS reads of
-// the source particle are wave-uniform (broadcast). Each receiver sums its
-// sources in a fixed order (task order, then source order), so results do not
-// depend on scheduling.
-#include "sphx_internal.h"
+// The loop structure (cull, candidate buffer, per-lane lists) is described in
+// pairs.h. A block of NW waves serves one receiving cell: wave w takes the
+// w-th contiguous share of the cell's tasks, and the shares' partial sums are
+// added in wave order at the end (a fixed order, so results stay
+// reproducible).
+#include "pairs.h"
 
 namespace sphx {
 namespace {
 
-__global__ __launch_bounds__(64) void k_density(
+constexpr int kSums = 9;  // Sw, Smw, Sud, Smud, Sdiv, Scx, Scy, Scz, count
+
+template <int CAP, int NW>
+__global__ __launch_bounds__(64 * NW) void k_density(
     int64_t n_leaves, int64_t nb_padded, const int32_t *__restrict__ leaf_start,
     const int32_t *__restrict__ perm, const float4 *__restrict__ q0,
-    const float4 *__restrict__ q1, const uint8_t *__restrict__ need, const float *__restrict__ h,
+    const float4 *__restrict__ q1, const uint8_t *__restrict__ need, const float *__restrict__ hs,
     const float *__restrict__ radius, const int32_t *__restrict__ toff,
     const Task *__restrict__ task, float gamma_k, float *__restrict__ o_rho,
     float *__restrict__ o_rho_dh, float *__restrict__ o_n, float *__restrict__ o_n_dh,
     float *__restrict__ o_div, float *__restrict__ o_cx, float *__restrict__ o_cy,
-    float *__restrict__ o_cz, int32_t *__restrict__ o_nngb, int32_t *__restrict__ counters)
+    float *__restrict__ o_cz, int32_t *__restrict__ o_nngb, float4 *__restrict__ d0,
+    float4 *__restrict__ d1, int32_t *__restrict__ counters)
 {
     const int64_t L = xcd_remap(blockIdx.x, nb_padded);
     if (L >= n_leaves)
         return;
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
     const int32_t s0 = leaf_start[L];
     const int32_t cnt = leaf_start[L + 1] - s0;
     const bool valid = lane < cnt;
     const int32_t s = s0 + (valid ? lane : 0);
     const bool act = valid && need[s];
     if (!__any(act))
-        return;
+        return;  // the same for every wave of the block
 
-    __shared__ float4 jp[kLeafMax];
-    __shared__ float4 jv[kLeafMax];
+    __shared__ float4 cp_all[NW][CAP];  // candidate x, y, z (receiver cell frame), m
+    __shared__ float4 cv_all[NW][CAP];  // candidate vx, vy, vz
+    __shared__ uint32_t lst_all[NW][kListStride * 16];
+    float4 *cp = cp_all[w];
+    float4 *cv = cv_all[w];
+    uint8_t *lst = reinterpret_cast<uint8_t *>(lst_all[w]);
+    uint8_t *my_list = lst + lane * kListStride;
 
     const float4 pi = q0[s];
     const float4 vi = q1[s];
     const int32_t gi = perm[s];
-    const float hi = act ? h[gi] : 1.0f;
+    const float hi = act ? hs[s] : 1.0f;
     const float H = gamma_k * hi;
-    const float H2 = H * H;
-    const float invH = 1.0f / H;
-    if (act && H > radius[L] && counters)
+    const float H2 = act ? H * H : -1.0f;
+    const float invH = fast_rcp(H);
+    if (w == 0 && act && H > radius[L] && counters)
         atomicAdd(counters + 3, 1);
 
-    float Sw = 0.f, Smw = 0.f, Sud = 0.f, Smud = 0.f;
-    float Sdiv = 0.f, Scx = 0.f, Scy = 0.f, Scz = 0.f;
-    int32_t nn = 0;
+    // Bounding box of the receivers that need work, and their largest radius.
+    const float inf = __builtin_inff();
+    float3 lo = make_float3(act ? pi.x : inf, act ? pi.y : inf, act ? pi.z : inf);
+    float3 hb = make_float3(act ? pi.x : -inf, act ? pi.y : -inf, act ? pi.z : -inf);
+    lo.x = wave_minf(lo.x);
+    lo.y = wave_minf(lo.y);
+    lo.z = wave_minf(lo.z);
+    hb.x = wave_maxf(hb.x);
+    hb.y = wave_maxf(hb.y);
+    hb.z = wave_maxf(hb.z);
+    const float R = wave_maxf(act ? H : 0.0f);
+    const float R2 = R * R;
 
-    const int32_t t0 = toff[L], t1 = toff[L + 1];
-    for (int32_t t = t0; t < t1; ++t) {
-        const Task T = task[t];
-        const int32_t j0 = leaf_start[T.j];
-        const int32_t jc = leaf_start[T.j + 1] - j0;
-        __syncthreads();
-        if (lane < jc) {
-            float4 p = q0[j0 + lane];
-            jp[lane] = make_float4(p.x + T.ox, p.y + T.oy, p.z + T.oz, p.w);
-            jv[lane] = q1[j0 + lane];
+    float S[kSums] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    int nc = 0;   // buffered candidates (wave-uniform)
+    int myn = 0;  // this lane's list length (its own particle is listed too)
+
+    auto pair = [&](int c) __attribute__((always_inline)) {
+        const float4 p = cp[c];
+        const float4 v = cv[c];
+        const float dx = pi.x - p.x, dy = pi.y - p.y, dz = pi.z - p.z;
+        const float r2 = dx * dx + dy * dy + dz * dz;
+        const float u = fast_sqrt(r2) * invH;
+        const float t1u = 1.0f - u;
+        const float t2 = t1u * t1u;
+        const float t3 = t2 * t1u;
+        const float wk = t2 * t2 * (1.0f + 4.0f * u);
+        const float ud = u * u * t3;
+        S[0] += wk;
+        S[1] += p.w * wk;
+        S[2] += ud;
+        S[3] += p.w * ud;
+        S[8] += 1.0f;
+        const float dvx = v.x - vi.x, dvy = v.y - vi.y, dvz = v.z - vi.z;
+        const float mt3 = p.w * t3;
+        S[4] += mt3 * (dvx * dx + dvy * dy + dvz * dz);
+        S[5] += mt3 * (dy * dvz - dz * dvy);
+        S[6] += mt3 * (dz * dvx - dx * dvz);
+        S[7] += mt3 * (dx * dvy - dy * dvx);
+    };
+    auto compute = [&]() __attribute__((always_inline)) {
+        for (int k = 0; __any(k < myn); k += 4) {
+            const uint32_t four = *reinterpret_cast<const uint32_t *>(my_list + k);
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (k + q < myn)
+                    pair(int((four >> (8 * q)) & 0xffu));
         }
-        __syncthreads();
-        for (int k = 0; k < jc; ++k) {
-            const float4 p = jp[k];
-            const float dx = pi.x - p.x, dy = pi.y - p.y, dz = pi.z - p.z;
-            const float r2 = dx * dx + dy * dy + dz * dz;
-            if (act && r2 < H2) {
-                const float r = sqrtf(r2);
-                const float u = r * invH;
-                const float t1u = 1.0f - u;
-                const float t2 = t1u * t1u;
-                const float t3 = t2 * t1u;
-                const float w = t2 * t2 * (1.0f + 4.0f * u);
-                const float ud = u * u * t3;
-                Sw += w;
-                Smw += p.w * w;
-                Sud += ud;
-                Smud += p.w * ud;
-                if (j0 + k != s) {
-                    ++nn;
-                    const float4 v = jv[k];
-                    const float dvx = v.x - vi.x, dvy = v.y - vi.y, dvz = v.z - vi.z;
-                    const float mt3 = p.w * t3;
-                    Sdiv += mt3 * (dvx * dx + dvy * dy + dvz * dz);
-                    Scx += mt3 * (dy * dvz - dz * dvy);
-                    Scy += mt3 * (dz * dvx - dx * dvz);
-                    Scz += mt3 * (dx * dvy - dy * dvx);
-                }
+        myn = 0;
+    };
+    auto accept = [&](int c, const float4 &p) __attribute__((always_inline)) {
+        const float dx = pi.x - p.x, dy = pi.y - p.y, dz = pi.z - p.z;
+        const float r2 = dx * dx + dy * dy + dz * dz;
+        if (r2 < H2) {
+            my_list[myn] = uint8_t(c);
+            ++myn;
+        }
+    };
+    auto flush = [&]() __attribute__((always_inline)) {
+        wave_sync();
+        int c = 0;
+        for (; c + 4 <= nc; c += 4) {
+            const float4 p0 = cp[c], p1 = cp[c + 1], p2 = cp[c + 2], p3 = cp[c + 3];
+            accept(c, p0);
+            accept(c + 1, p1);
+            accept(c + 2, p2);
+            accept(c + 3, p3);
+            if (__any(myn > kListMax - 4))
+                compute();
+        }
+        for (; c < nc; ++c)
+            accept(c, cp[c]);
+        compute();
+        wave_sync();
+        nc = 0;
+    };
+
+    // Append the kept sources of one task to the candidate buffer.
+    auto emit = [&](const float4 &p, const float4 &v, bool keep) __attribute__((always_inline)) {
+        const uint64_t mask = __ballot(keep);
+        if (mask == 0)
+            return;
+        const int tot = __popcll(mask);
+        if (nc + tot > CAP)
+            flush();
+        const int pos = nc + lanes_below(mask);
+        if (keep) {
+            cp[pos] = p;
+            cv[pos] = v;
+        }
+        nc += tot;
+    };
+
+    // This wave's share of the cell's tasks.
+    const int32_t ta = toff[L], tn = toff[L + 1] - ta;
+    const int32_t t_begin = ta + int32_t((int64_t(tn) * w) / NW);
+    const int32_t t_end = ta + int32_t((int64_t(tn) * (w + 1)) / NW);
+    for (int32_t tb = t_begin; tb < t_end; tb += 64) {
+        const int nb = min(64, t_end - tb);
+        TaskRegs tr;
+        tr.load(task, tb + lane, lane < nb);
+        for (int u = 0; u < nb; u += 4) {
+            int j0[4], jc[4];
+            float ox[4], oy[4], oz[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int k = min(u + q, nb - 1);
+                j0[q] = bcast(tr.a.x, k);
+                jc[q] = (u + q < nb) ? bcast(tr.a.y, k) : 0;
+                ox[q] = bcastf(tr.b.x, k);
+                oy[q] = bcastf(tr.b.y, k);
+                oz[q] = bcastf(tr.b.z, k);
             }
+            float4 p[4];
+            bool keep[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                p[q] = lane < jc[q] ? q0[j0[q] + lane] : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                p[q].x += ox[q];
+                p[q].y += oy[q];
+                p[q].z += oz[q];
+                keep[q] = lane < jc[q] && box_dist2(p[q].x, p[q].y, p[q].z, lo, hb) < R2;
+            }
+            float4 v[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                v[q] = keep[q] ? q1[j0[q] + lane] : make_float4(0.f, 0.f, 0.f, 0.f);
+            emit(p[0], v[0], keep[0]);
+            emit(p[1], v[1], keep[1]);
+            emit(p[2], v[2], keep[2]);
+            emit(p[3], v[3], keep[3]);
         }
+    }
+    if (nc > 0)
+        flush();
+
+    if (NW > 1) {
+        // Add the other waves' partial sums to wave 0's, in wave order.
+        __syncthreads();
+        float *red = reinterpret_cast<float *>(cp_all);
+        if (w > 0)
+            for (int k = 0; k < kSums; ++k)
+                red[((w - 1) * kSums + k) * 64 + lane] = S[k];
+        __syncthreads();
+        if (w > 0)
+            return;
+        for (int w2 = 1; w2 < NW; ++w2)
+            for (int k = 0; k < kSums; ++k)
+                S[k] += red[((w2 - 1) * kSums + k) * 64 + lane];
     }
     if (!act)
         return;
+    // The receiver's own particle went through the loop as a pair at r = 0:
+    // it contributes W(0) to n and rho and nothing to the gradient sums; it
+    // is not a neighbour.
+    const float Sw = S[0];
+    const float Smw = S[1];
     // W = kW H^-3 (1-u)^4 (1+4u); dW/dh = -(H^-3/h)(3 kW w - kD u^2 (1-u)^3);
-    // grad_i W = dW/dr x_ij / r with dW/dr / r = -kD H^-5 (1-u)^3.
+    // grad_i W = (dW/dr / r) x_ij with dW/dr / r = -kD H^-5 (1-u)^3.
     const float invH3 = invH * invH * invH;
     const float invH5 = invH3 * invH * invH;
-    const float ih = 1.0f / hi;
-    o_n[gi] = kW * invH3 * Sw;
-    o_rho[gi] = kW * invH3 * Smw;
-    o_n_dh[gi] = -invH3 * ih * (3.0f * kW * Sw - kD * Sud);
-    o_rho_dh[gi] = -invH3 * ih * (3.0f * kW * Smw - kD * Smud);
-    o_div[gi] = -kD * invH5 * Sdiv;
-    o_cx[gi] = -kD * invH5 * Scx;
-    o_cy[gi] = -kD * invH5 * Scy;
-    o_cz[gi] = -kD * invH5 * Scz;
-    o_nngb[gi] = nn;
+    const float ih = fast_rcp(hi);
+    const float n_ = kW * invH3 * Sw;
+    const float rho = kW * invH3 * Smw;
+    const float n_dh = -invH3 * ih * (3.0f * kW * Sw - kD * S[2]);
+    const float rho_dh = -invH3 * ih * (3.0f * kW * Smw - kD * S[3]);
+    const float dv = -kD * invH5 * S[4];
+    const float cx = -kD * invH5 * S[5];
+    const float cy = -kD * invH5 * S[6];
+    const float cz = -kD * invH5 * S[7];
+    d0[s] = make_float4(n_, n_dh, rho, rho_dh);
+    d1[s] = make_float4(dv, cx, cy, cz);
+    o_n[gi] = n_;
+    o_rho[gi] = rho;
+    o_n_dh[gi] = n_dh;
+    o_rho_dh[gi] = rho_dh;
+    o_div[gi] = dv;
+    o_cx[gi] = cx;
+    o_cy[gi] = cy;
+    o_cz[gi] = cz;
+    o_nngb[gi] = int32_t(S[8]) - 1;
 }
 
 }  // namespace
@@ -119,11 +249,12 @@ sphx_status density_launch(const sphx_ctx *ctx, const sphx_grid *g, const sphx_t
     if (g->n_leaves == 0)
         return SPHX_OK;
     const int64_t nbp = pad8(g->n_leaves);
+    constexpr int NW = 2;
     SPHX_HIP(ctx->prof->begin(0, s));
-    k_density<<<unsigned(nbp), 64, 0, s>>>(
-        g->n_leaves, nbp, g->leaf_start, g->perm, g->q0, g->q1, g->need, in->h, t->radius, t->off,
+    k_density<kCap, NW><<<unsigned(nbp), 64 * NW, 0, s>>>(
+        g->n_leaves, nbp, g->leaf_start, g->perm, g->q0, g->q1, g->need, g->hs, t->radius, t->off,
         t->task, float(ctx->p.gamma_k), o->rho, o->rho_dh, o->n, o->n_dh, o->div_sum, o->curl_x,
-        o->curl_y, o->curl_z, o->nngb, counters);
+        o->curl_y, o->curl_z, o->nngb, g->d0, g->d1, counters);
     SPHX_HIP(hipGetLastError());
     SPHX_HIP(ctx->prof->end(0, s));
     return SPHX_OK;

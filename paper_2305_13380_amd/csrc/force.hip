@@ -2,13 +2,14 @@
 // Balsara-switched artificial viscosity; Section 3.3 symmetric alpha_ij and
 // artificial conduction) and the FP64 global momentum / energy sums.
 //
-// One wave64 per receiving leaf; each task's source leaf is staged in LDS in
-// the receiver leaf's frame together with the per-source quantities every
-// pair term needs, so the inner loop reads wave-uniform LDS addresses.
-#include "sphx_internal.h"
+// The loop structure (cull, candidate buffer, per-lane lists) is described in
+// pairs.h; the force set of receiver i is every j != i with r_ij < max(H_i, H_j).
+#include "pairs.h"
 
 namespace sphx {
 namespace {
+
+constexpr int kCapForce = 128;
 
 // Sorted copies of the ghost state every source needs: (h, rho, P, c) and
 // (f, B, A, 0).
@@ -34,7 +35,10 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
-__global__ __launch_bounds__(64) void k_force(
+constexpr int kFSums = 6;  // ax, ay, az, du, vsig, count
+
+template <int CAP, int NW>
+__global__ __launch_bounds__(64 * NW) void k_force(
     int64_t n_leaves, int64_t nb_padded, const int32_t *__restrict__ leaf_start,
     const int32_t *__restrict__ perm, const float4 *__restrict__ q0,
     const float4 *__restrict__ q1, const float2 *__restrict__ qa, const float4 *__restrict__ g0,
@@ -47,7 +51,8 @@ __global__ __launch_bounds__(64) void k_force(
     const int64_t L = xcd_remap(blockIdx.x, nb_padded);
     if (L >= n_leaves)
         return;
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
     const int32_t s0 = leaf_start[L];
     const int32_t cnt = leaf_start[L + 1] - s0;
     const bool valid = lane < cnt;
@@ -55,16 +60,21 @@ __global__ __launch_bounds__(64) void k_force(
     const int32_t gi = perm[s];
     const bool act = valid && (active ? active[gi] != 0 : true);
     if (!__any(act)) {
-        if (lane < 6)
+        if (w == 0 && lane < 6)
             fsum[6 * L + lane] = 0.0;
         return;
     }
 
-    __shared__ float4 sp[kLeafMax];  // x, y, z (receiver frame), m
-    __shared__ float4 sv[kLeafMax];  // vx, vy, vz, H^2
-    __shared__ float4 sa[kLeafMax];  // 1/H, c, rho, P
-    __shared__ float4 sb[kLeafMax];  // f, A, B, alpha_v
-    __shared__ float2 sc[kLeafMax];  // alpha_c P, u
+    __shared__ float4 cp_all[NW][CAP];  // x, y, z (receiver cell frame), H^2
+    __shared__ float4 cv_all[NW][CAP];  // vx, vy, vz, m
+    __shared__ float4 ca_all[NW][CAP];  // 1/H, c, rho, P
+    __shared__ float4 cb_all[NW][CAP];  // f, A, B, alpha_v
+    __shared__ float2 cc_all[NW][CAP];  // alpha_c P, u
+    __shared__ uint32_t lst_all[NW][kListStride * 16];
+    float4 *cp = cp_all[w], *cv = cv_all[w], *ca = ca_all[w], *cb = cb_all[w];
+    float2 *cc = cc_all[w];
+    uint8_t *lst = reinterpret_cast<uint8_t *>(lst_all[w]);
+    uint8_t *my_list = lst + lane * kListStride;
 
     const float4 pi = q0[s];
     const float4 vi = q1[s];  // w = u
@@ -72,93 +82,209 @@ __global__ __launch_bounds__(64) void k_force(
     const float4 gi0 = g0[s];  // h, rho, P, c
     const float4 gi1 = g1[s];  // f, B, A
     const float Hi = gamma_k * gi0.x;
-    const float Hi2 = Hi * Hi;
-    const float invHi = 1.0f / Hi;
+    const float Hi2 = act ? Hi * Hi : -1.0f;
+    const float invHi = fast_rcp(Hi);
     const float invHi4 = (invHi * invHi) * (invHi * invHi);
     const float rhoi = gi0.y, Pi = gi0.z, ci = gi0.w;
     const float fi = gi1.x, Bi = gi1.y, Ai = gi1.z;
     const float acPi = ai.y * Pi;
 
+    const float inf = __builtin_inff();
+    float3 lo = make_float3(act ? pi.x : inf, act ? pi.y : inf, act ? pi.z : inf);
+    float3 hb = make_float3(act ? pi.x : -inf, act ? pi.y : -inf, act ? pi.z : -inf);
+    lo.x = wave_minf(lo.x);
+    lo.y = wave_minf(lo.y);
+    lo.z = wave_minf(lo.z);
+    hb.x = wave_maxf(hb.x);
+    hb.y = wave_maxf(hb.y);
+    hb.z = wave_maxf(hb.z);
+    const float R = wave_maxf(act ? Hi : 0.0f);
+    const float R2 = R * R;
+
     float ax = 0.f, ay = 0.f, az = 0.f, du = 0.f;
     float vsig = 2.0f * ci;
     int32_t nf = 0;
+    int nc = 0;
+    int myn = 0;  // this lane's list length (its own particle is listed too)
 
-    const int32_t t0 = toff[L], t1 = toff[L + 1];
-    for (int32_t t = t0; t < t1; ++t) {
-        const Task T = task[t];
-        const int32_t j0 = leaf_start[T.j];
-        const int32_t jc = leaf_start[T.j + 1] - j0;
-        __syncthreads();
-        if (lane < jc) {
-            const int32_t sj = j0 + lane;
-            const float4 p = q0[sj];
+    auto pair = [&](int c) __attribute__((always_inline)) {
+        const float4 p = cp[c];
+        const float dx = pi.x - p.x, dy = pi.y - p.y, dz = pi.z - p.z;
+        const float r2 = dx * dx + dy * dy + dz * dz;
+        ++nf;
+        if (r2 > 0.0f) {
+            const float4 v = cv[c];
+            const float4 a = ca[c];
+            const float4 b = cb[c];
+            const float2 c2 = cc[c];
+            const float rinv = fast_rsq(r2);
+            const float r = r2 * rinv;
+            const float ui = r * invHi;
+            const float ti = fmaxf(1.0f - ui, 0.0f);
+            const float gi = -kD * invHi4 * ui * (ti * ti * ti);
+            const float uj = r * a.x;
+            const float tj = fmaxf(1.0f - uj, 0.0f);
+            const float ij2 = a.x * a.x;
+            const float gj = -kD * (ij2 * ij2) * uj * (tj * tj * tj);
+            const float ex = dx * rinv, ey = dy * rinv, ez = dz * rinv;
+            const float dvx = vi.x - v.x, dvy = vi.y - v.y, dvz = vi.z - v.z;
+            const float vdote = dvx * ex + dvy * ey + dvz * ez;
+            const float mu = vdote < 0.0f ? vdote : 0.0f;
+            const float vs = ci + a.y - beta * mu;
+            vsig = fmaxf(vsig, vs);
+            const float alpha = 0.25f * (ai.x + b.w) * (Bi + b.z);
+            const float irs = fast_rcp(rhoi + a.z);
+            const float nu = -2.0f * alpha * mu * vs * irs;
+            const float G = fi * gi + b.x * gj;
+            const float acc = Ai * gi + b.y * gj + 0.5f * nu * G;
+            const float m = v.w;
+            ax -= m * acc * ex;
+            ay -= m * acc * ey;
+            az -= m * acc * ez;
+            du += m * (Ai * gi + 0.25f * nu * G) * vdote;
+            const float psum = Pi + a.w;
+            const float ac = psum > 0.0f ? (acPi + c2.x) * fast_rcp(psum) : 0.0f;
+            const float vc = fabsf(vdote) + fast_sqrt(2.0f * fabsf(Pi - a.w) * irs);
+            du += m * ac * vc * (vi.w - c2.y) * G * irs;
+        }
+    };
+    auto compute = [&]() __attribute__((always_inline)) {
+        for (int k = 0; __any(k < myn); k += 4) {
+            const uint32_t four = *reinterpret_cast<const uint32_t *>(my_list + k);
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (k + q < myn)
+                    pair(int((four >> (8 * q)) & 0xffu));
+        }
+        myn = 0;
+    };
+    auto accept = [&](int c, const float4 &p) __attribute__((always_inline)) {
+        const float dx = pi.x - p.x, dy = pi.y - p.y, dz = pi.z - p.z;
+        const float r2 = dx * dx + dy * dy + dz * dz;
+        if (act && r2 < fmaxf(Hi2, p.w)) {
+            my_list[myn] = uint8_t(c);
+            ++myn;
+        }
+    };
+    auto flush = [&]() __attribute__((always_inline)) {
+        wave_sync();
+        int c = 0;
+        for (; c + 4 <= nc; c += 4) {
+            const float4 p0 = cp[c], p1 = cp[c + 1], p2 = cp[c + 2], p3 = cp[c + 3];
+            accept(c, p0);
+            accept(c + 1, p1);
+            accept(c + 2, p2);
+            accept(c + 3, p3);
+            if (__any(myn > kListMax - 4))
+                compute();
+        }
+        for (; c < nc; ++c)
+            accept(c, cp[c]);
+        compute();
+        wave_sync();
+        nc = 0;
+    };
+
+    // Append the kept sources of one task to the candidate buffer.
+    auto emit = [&](const float4 &p, float Hj, bool keep, int j0) __attribute__((always_inline)) {
+        const uint64_t mask = __ballot(keep);
+        if (mask == 0)
+            return;
+        const int tot = __popcll(mask);
+        if (nc + tot > CAP)
+            flush();
+        const int pos = nc + lanes_below(mask);
+        if (keep) {
+            const int sj = j0 + lane;
             const float4 v = q1[sj];
             const float2 a = qa[sj];
             const float4 h0 = g0[sj];
             const float4 h1 = g1[sj];
-            const float Hj = gamma_k * h0.x;
-            sp[lane] = make_float4(p.x + T.ox, p.y + T.oy, p.z + T.oz, p.w);
-            sv[lane] = make_float4(v.x, v.y, v.z, Hj * Hj);
-            sa[lane] = make_float4(1.0f / Hj, h0.w, h0.y, h0.z);
-            sb[lane] = make_float4(h1.x, h1.z, h1.y, a.x);
-            sc[lane] = make_float2(a.y * h0.z, v.w);
+            cp[pos] = make_float4(p.x, p.y, p.z, Hj * Hj);
+            cv[pos] = make_float4(v.x, v.y, v.z, p.w);
+            ca[pos] = make_float4(fast_rcp(Hj), h0.w, h0.y, h0.z);
+            cb[pos] = make_float4(h1.x, h1.z, h1.y, a.x);
+            cc[pos] = make_float2(a.y * h0.z, v.w);
         }
-        __syncthreads();
-        for (int k = 0; k < jc; ++k) {
-            const float4 p = sp[k];
-            const float dx = pi.x - p.x, dy = pi.y - p.y, dz = pi.z - p.z;
-            const float r2 = dx * dx + dy * dy + dz * dz;
-            const float4 v = sv[k];
-            if (act && r2 < fmaxf(Hi2, v.w) && j0 + k != s) {
-                ++nf;
-                if (r2 > 0.0f) {
-                    const float rinv = rsqrtf(r2);
-                    const float r = r2 * rinv;
-                    const float4 a = sa[k];
-                    const float4 b = sb[k];
-                    const float2 c2 = sc[k];
-                    const float ui = r * invHi;
-                    const float ti = fmaxf(1.0f - ui, 0.0f);
-                    const float gi = -kD * invHi4 * ui * (ti * ti * ti);
-                    const float uj = r * a.x;
-                    const float tj = fmaxf(1.0f - uj, 0.0f);
-                    const float ij2 = a.x * a.x;
-                    const float gj = -kD * (ij2 * ij2) * uj * (tj * tj * tj);
-                    const float ex = dx * rinv, ey = dy * rinv, ez = dz * rinv;
-                    const float dvx = vi.x - v.x, dvy = vi.y - v.y, dvz = vi.z - v.z;
-                    const float vdote = dvx * ex + dvy * ey + dvz * ez;
-                    const float mu = vdote < 0.0f ? vdote : 0.0f;
-                    const float vs = ci + a.y - beta * mu;
-                    vsig = fmaxf(vsig, vs);
-                    const float alpha = 0.25f * (ai.x + b.w) * (Bi + b.z);
-                    const float irs = 1.0f / (rhoi + a.z);
-                    const float nu = -2.0f * alpha * mu * vs * irs;
-                    const float G = fi * gi + b.x * gj;
-                    const float acc = Ai * gi + b.y * gj + 0.5f * nu * G;
-                    const float m = p.w;
-                    ax -= m * acc * ex;
-                    ay -= m * acc * ey;
-                    az -= m * acc * ez;
-                    du += m * (Ai * gi + 0.25f * nu * G) * vdote;
-                    const float psum = Pi + a.w;
-                    const float ac = psum > 0.0f ? (acPi + c2.x) / psum : 0.0f;
-                    const float vc = fabsf(vdote) + sqrtf(2.0f * fabsf(Pi - a.w) * irs);
-                    du += m * ac * vc * (vi.w - c2.y) * G * irs;
-                }
+        nc += tot;
+    };
+
+    const int32_t ta = toff[L], tn = toff[L + 1] - ta;
+    const int32_t t_begin = ta + int32_t((int64_t(tn) * w) / NW);
+    const int32_t t_end = ta + int32_t((int64_t(tn) * (w + 1)) / NW);
+    for (int32_t tb = t_begin; tb < t_end; tb += 64) {
+        const int nb = min(64, t_end - tb);
+        TaskRegs tr;
+        tr.load(task, tb + lane, lane < nb);
+        for (int u = 0; u < nb; u += 4) {
+            int j0[4], jc[4];
+            float ox[4], oy[4], oz[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int k = min(u + q, nb - 1);
+                j0[q] = bcast(tr.a.x, k);
+                jc[q] = (u + q < nb) ? bcast(tr.a.y, k) : 0;
+                ox[q] = bcastf(tr.b.x, k);
+                oy[q] = bcastf(tr.b.y, k);
+                oz[q] = bcastf(tr.b.z, k);
             }
+            float4 p[4];
+            float hj[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const bool in = lane < jc[q];
+                p[q] = in ? q0[j0[q] + lane] : make_float4(0.f, 0.f, 0.f, 0.f);
+                hj[q] = in ? g0[j0[q] + lane].x : 0.0f;
+            }
+            bool keep[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                p[q].x += ox[q];
+                p[q].y += oy[q];
+                p[q].z += oz[q];
+                const float Hj = gamma_k * hj[q];
+                hj[q] = Hj;
+                keep[q] = lane < jc[q] &&
+                          box_dist2(p[q].x, p[q].y, p[q].z, lo, hb) < fmaxf(R2, Hj * Hj);
+            }
+            emit(p[0], hj[0], keep[0], j0[0]);
+            emit(p[1], hj[1], keep[1], j0[1]);
+            emit(p[2], hj[2], keep[2], j0[2]);
+            emit(p[3], hj[3], keep[3], j0[3]);
+        }
+    }
+    if (nc > 0)
+        flush();
+
+    // the receiver's own particle was listed as a pair at r = 0 and counted
+    float F[kFSums] = {ax, ay, az, du, vsig, float(nf - (w == 0 && act ? 1 : 0))};
+    if (NW > 1) {
+        __syncthreads();
+        float *red = reinterpret_cast<float *>(cp_all);
+        if (w > 0)
+            for (int k = 0; k < kFSums; ++k)
+                red[((w - 1) * kFSums + k) * 64 + lane] = F[k];
+        __syncthreads();
+        if (w > 0)
+            return;
+        for (int w2 = 1; w2 < NW; ++w2) {
+            for (int k = 0; k < 4; ++k)
+                F[k] += red[((w2 - 1) * kFSums + k) * 64 + lane];
+            F[4] = fmaxf(F[4], red[((w2 - 1) * kFSums + 4) * 64 + lane]);
+            F[5] += red[((w2 - 1) * kFSums + 5) * 64 + lane];
         }
     }
     double m0 = 0, m1 = 0, m2 = 0, e = 0, sa_ = 0, sd = 0;
     if (act) {
-        o_ax[gi] = ax;
-        o_ay[gi] = ay;
-        o_az[gi] = az;
-        o_du[gi] = du;
-        o_vsig[gi] = vsig;
+        o_ax[gi] = F[0];
+        o_ay[gi] = F[1];
+        o_az[gi] = F[2];
+        o_du[gi] = F[3];
+        o_vsig[gi] = F[4];
         if (o_nf)
-            o_nf[gi] = nf;
+            o_nf[gi] = int32_t(F[5]);
         const double mi = pi.w;
-        const double dax = ax, day = ay, daz = az, ddu = du;
+        const double dax = F[0], day = F[1], daz = F[2], ddu = F[3];
         m0 = mi * dax;
         m1 = mi * day;
         m2 = mi * daz;
@@ -225,7 +351,8 @@ sphx_status force_launch(const sphx_ctx *ctx, const sphx_grid *g, const sphx_tas
     SPHX_HIP(hipGetLastError());
     const int64_t nbp = pad8(g->n_leaves);
     SPHX_HIP(ctx->prof->begin(1, s));
-    k_force<<<unsigned(nbp), 64, 0, s>>>(
+    constexpr int NW = 2;
+    k_force<kCapForce, NW><<<unsigned(nbp), 64 * NW, 0, s>>>(
         g->n_leaves, nbp, g->leaf_start, g->perm, g->q0, g->q1, g->qa, g->g0, g->g1, in->active,
         t->off, t->task, float(ctx->p.gamma_k), float(ctx->p.beta_v), o->ax, o->ay, o->az,
         o->du_dt, o->v_sig, o->nforce, g->fsum);

@@ -68,6 +68,14 @@ __global__ void k_keys(int64_t n, const double *__restrict__ x, const double *__
     idx[i] = int32_t(i);
 }
 
+// Number of leading 3-bit levels two Morton keys share (21 when equal).
+__device__ __forceinline__ int common_levels(uint64_t a, uint64_t b)
+{
+    uint64_t d = a ^ b;
+    int c = d ? (__clzll(int64_t(d)) - 1) / 3 : kMortonBits;
+    return c > kMortonBits ? kMortonBits : c;
+}
+
 // Index of the first position in [lo, hi) whose key prefix (key >> shift) is
 // >= p (keys are sorted, so prefixes are non-decreasing).
 __device__ __forceinline__ int64_t lower_prefix(const uint64_t *k, int64_t lo, int64_t hi,
@@ -98,13 +106,9 @@ __global__ void k_leaf_flags(int64_t n, const uint64_t *__restrict__ k, int cap,
         flag[0] = 1;
         return;
     }
-    uint64_t a = k[s - 1], b = k[s];
-    uint64_t d = a ^ b;
-    int common_levels = d ? (__clzll(int64_t(d)) - 1) / 3 : kMortonBits;
-    if (common_levels > kMortonBits)
-        common_levels = kMortonBits;
-    int shift = 3 * (kMortonBits - common_levels);
-    uint64_t p = b >> shift;
+    const uint64_t b = k[s];
+    const int shift = 3 * (kMortonBits - common_levels(k[s - 1], b));
+    const uint64_t p = b >> shift;
     int64_t wlo = s - 1 - cap;
     if (wlo < 0)
         wlo = 0;
@@ -112,7 +116,7 @@ __global__ void k_leaf_flags(int64_t n, const uint64_t *__restrict__ k, int cap,
     if (whi > n)
         whi = n;
     int64_t lo = lower_prefix(k, wlo, s, p, shift);
-    int64_t hi = (p + 1 > p) ? lower_prefix(k, s, whi, p + 1, shift) : whi;
+    int64_t hi = lower_prefix(k, s, whi, p + 1, shift);
     flag[s] = (hi - lo > cap) ? 1u : 0u;
 }
 
@@ -132,6 +136,96 @@ __global__ void k_leaf_index(int64_t n, const uint32_t *__restrict__ flag,
         leaf_start[L + 1] = int32_t(n);
         *n_leaves = L + 1;
     }
+}
+
+// Start of every octree leaf: oct_start[leaf] = first sorted index.
+__global__ void k_oct_index(int64_t n, const uint32_t *__restrict__ flag,
+                            const uint32_t *__restrict__ incl, int32_t *__restrict__ oct_start,
+                            int32_t *__restrict__ n_oct)
+{
+    int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (s >= n)
+        return;
+    if (flag[s])
+        oct_start[incl[s] - 1] = int32_t(s);
+    if (s == n - 1) {
+        oct_start[incl[s]] = int32_t(n);
+        *n_oct = int32_t(incl[s]);
+    }
+}
+
+// Parent block of every octree leaf: the deeper of the deepest common blocks
+// across its two boundaries (both hold more than cap particles; the deeper
+// one is the leaf's parent). Level -1: the leaf is the whole set.
+__global__ void k_oct_parent(int64_t n, const uint64_t *__restrict__ k,
+                             const int32_t *__restrict__ oct_start,
+                             const int32_t *__restrict__ n_oct, int32_t *__restrict__ par_lvl,
+                             uint64_t *__restrict__ par_pfx)
+{
+    int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (q >= *n_oct)
+        return;
+    int64_t a = oct_start[q], b = oct_start[q + 1];
+    int lv = -1;
+    if (a > 0)
+        lv = common_levels(k[a - 1], k[a]);
+    if (b < n) {
+        int l2 = common_levels(k[b - 1], k[b]);
+        lv = l2 > lv ? l2 : lv;
+    }
+    par_lvl[q] = lv;
+    par_pfx[q] = lv < 0 ? 0 : (k[a] >> (3 * (kMortonBits - lv)));
+}
+
+// Cells: runs of consecutive sibling octree leaves packed greedily up to cap
+// particles (siblings share one parent block, so a cell stays compact).
+// Leaves of one parent are at most 8, except below the finest key level
+// (identical keys), where they are single particles packed by position.
+__global__ void k_pack_cells(int64_t n, const uint64_t *__restrict__ k,
+                             const int32_t *__restrict__ oct_start,
+                             const int32_t *__restrict__ n_oct,
+                             const int32_t *__restrict__ par_lvl,
+                             const uint64_t *__restrict__ par_pfx,
+                             const uint32_t *__restrict__ oct_incl, int cap,
+                             uint32_t *__restrict__ cell_flag)
+{
+    int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (q >= *n_oct)
+        return;
+    const int lv = par_lvl[q];
+    const uint64_t pf = par_pfx[q];
+    bool start;
+    if (lv == kMortonBits) {
+        // identical keys: leaves are single particles
+        int64_t a = oct_start[q];
+        int64_t lo = 0, hi = a;
+        while (lo < hi) {
+            int64_t mid = (lo + hi) >> 1;
+            if (k[mid] < k[a])
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+        int64_t run_first_leaf = int64_t(oct_incl[lo]) - 1;
+        start = ((q - run_first_leaf) % cap) == 0;
+    } else {
+        int64_t r = q;
+        while (r > 0 && q - r < 8 && par_lvl[r - 1] == lv && par_pfx[r - 1] == pf && lv >= 0)
+            --r;
+        int acc = 0;
+        start = true;
+        for (int64_t t = r; t <= q; ++t) {
+            int sz = oct_start[t + 1] - oct_start[t];
+            if (t == r || acc + sz > cap) {
+                acc = sz;
+                start = true;
+            } else {
+                acc += sz;
+                start = false;
+            }
+        }
+    }
+    cell_flag[oct_start[q]] = start ? 1u : 0u;
 }
 
 __device__ __forceinline__ double wave_min(double v)
@@ -213,13 +307,19 @@ __global__ void k_tree_level(int64_t cnt_up, int64_t cnt_dn, const double *__res
     }
 }
 
-__global__ void k_need_reset(int64_t n, const int32_t *__restrict__ perm,
-                             const uint8_t *__restrict__ active, uint8_t *__restrict__ need)
+// Start of an h iteration: mark the active particles and copy h into sorted
+// order (with mark == nullptr only the copy).
+__global__ void k_iter_reset(int64_t n, const int32_t *__restrict__ perm,
+                             const uint8_t *__restrict__ active, const float *__restrict__ h,
+                             uint8_t *__restrict__ need, float *__restrict__ hs)
 {
     int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (s >= n)
         return;
-    need[s] = active ? (active[perm[s]] ? 1 : 0) : 1;
+    const int32_t i = perm[s];
+    hs[s] = h[i];
+    if (need)
+        need[s] = active ? (active[i] ? 1 : 0) : 1;
 }
 
 template <class T>
@@ -239,7 +339,7 @@ inline unsigned blocks(int64_t n, int t) { return unsigned((n + t - 1) / t); }
 size_t grid_bytes(int64_t n)
 {
     // per particle: keys x2, perm/idx, leaf_of, flags x2, q0, q1, qa, need, g0, g1
-    size_t per = 8 * 2 + 4 * 2 + 4 + 4 * 2 + 16 * 2 + 8 + 1 + 16 * 2;
+    size_t per = 8 * 2 + 4 * 2 + 4 + 4 * 2 + 16 * 2 + 8 + 1 + 16 * 2 + 4 + 32;
     // per leaf (at most n leaves): start, origin, tree nodes (~8/7 of the
     // leaves: lo, hi, radius), partial sums
     size_t per_leaf = 4 + 24 + (48 + 4) * 8 / 7 + 1 + 48;
@@ -254,7 +354,7 @@ void grid_free(sphx_grid *g)
     void *ptrs[] = {g->keys,    g->perm,     g->leaf_of,  g->q0,      g->q1,     g->qa,
                     g->need,    g->g0,       g->g1,       g->leaf_start, g->leaf_org, g->node_lo,
                     g->node_hi, g->node_r,   g->fsum,     g->sort_tmp, g->keys_in, g->idx_in,
-                    g->flags,   g->d_status};
+                    g->flags,   g->d_status, g->hs,       g->d0,       g->d1};
     for (void *p : ptrs)
         if (p)
             (void)hipFree(p);
@@ -265,7 +365,18 @@ sphx_status iter_reset(sphx_grid *g, const sphx_particles *in, hipStream_t s)
 {
     if (g->n == 0)
         return SPHX_OK;
-    k_need_reset<<<blocks(g->n, 256), 256, 0, s>>>(g->n, g->perm, in->active, g->need);
+    k_iter_reset<<<blocks(g->n, 256), 256, 0, s>>>(g->n, g->perm, in->active, in->h, g->need,
+                                                    g->hs);
+    SPHX_HIP(hipGetLastError());
+    return SPHX_OK;
+}
+
+sphx_status refresh_h(sphx_grid *g, const sphx_particles *in, hipStream_t s)
+{
+    if (g->n == 0)
+        return SPHX_OK;
+    k_iter_reset<<<blocks(g->n, 256), 256, 0, s>>>(g->n, g->perm, in->active, in->h, nullptr,
+                                                    g->hs);
     SPHX_HIP(hipGetLastError());
     return SPHX_OK;
 }
@@ -302,6 +413,9 @@ sphx_status grid_build(sphx_ctx *ctx, const sphx_particles *in, hipStream_t s, s
     SPHX_TRY(dalloc(&g->need, n));
     SPHX_TRY(dalloc(&g->g0, n));
     SPHX_TRY(dalloc(&g->g1, n));
+    SPHX_TRY(dalloc(&g->hs, n));
+    SPHX_TRY(dalloc(&g->d0, n));
+    SPHX_TRY(dalloc(&g->d1, n));
 
     if (n == 0) {
         g->n_leaves = 0;
@@ -336,8 +450,43 @@ sphx_status grid_build(sphx_ctx *ctx, const sphx_particles *in, hipStream_t s, s
     SPHX_HIP(hipGetLastError());
     SPHX_HIP(rocprim::inclusive_scan(g->sort_tmp, tmp2, g->flags, g->flags + n, size_t(n),
                                      rocprim::plus<uint32_t>(), s));
-    // leaf_start needs n_leaves + 1 entries; n is an upper bound on n_leaves.
+    // Octree leaves -> parents -> packed cells. flags[0, n) holds the leaf
+    // starts, flags[n, 2n) their inclusive scan; the cell starts then reuse
+    // flags[0, n) (cleared first) and their scan flags[n, 2n).
     SPHX_TRY(dalloc(&g->leaf_start, n + 1));
+    int32_t *par_lvl = nullptr;
+    uint64_t *par_pfx = nullptr;
+    SPHX_TRY(dalloc(&par_lvl, n));
+    if (hipMalloc(&par_pfx, size_t(n) * sizeof(uint64_t)) != hipSuccess) {
+        (void)hipFree(par_lvl);
+        set_error("sphx_grid_build: out of device memory");
+        return SPHX_E_OOM;
+    }
+    struct Tmp {
+        void *a, *b;
+        ~Tmp()
+        {
+            (void)hipFree(a);
+            (void)hipFree(b);
+        }
+    } tmp_guard{par_lvl, par_pfx};
+    k_oct_index<<<blocks(n, 256), 256, 0, s>>>(n, g->flags, g->flags + n, g->leaf_start,
+                                               g->d_status + 2);
+    SPHX_HIP(hipGetLastError());
+    k_oct_parent<<<blocks(n, 256), 256, 0, s>>>(n, g->keys, g->leaf_start, g->d_status + 2,
+                                                par_lvl, par_pfx);
+    SPHX_HIP(hipGetLastError());
+    // keep the leaf scan for the identical-key case: copy it out of the way
+    SPHX_HIP(hipMemcpyAsync(g->keys_in, g->flags + n, size_t(n) * sizeof(uint32_t),
+                            hipMemcpyDeviceToDevice, s));
+    SPHX_HIP(hipMemsetAsync(g->flags, 0, size_t(n) * sizeof(uint32_t), s));
+    k_pack_cells<<<blocks(n, 256), 256, 0, s>>>(n, g->keys, g->leaf_start, g->d_status + 2,
+                                                par_lvl, par_pfx,
+                                                reinterpret_cast<uint32_t *>(g->keys_in), cap,
+                                                g->flags);
+    SPHX_HIP(hipGetLastError());
+    SPHX_HIP(rocprim::inclusive_scan(g->sort_tmp, tmp2, g->flags, g->flags + n, size_t(n),
+                                     rocprim::plus<uint32_t>(), s));
     k_leaf_index<<<blocks(n, 256), 256, 0, s>>>(n, g->flags, g->flags + n, g->leaf_of,
                                                 g->leaf_start, g->d_status + 1);
     SPHX_HIP(hipGetLastError());

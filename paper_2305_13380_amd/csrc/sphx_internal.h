@@ -44,10 +44,15 @@ constexpr int kMortonBits = 21; // bits per axis of the 63-bit Morton key
 constexpr float kW = 3.3422538049298023f;  // 21 / (2 pi)
 constexpr float kD = 66.845076098596050f;  // 210 / pi
 
-// Task record: j leaf and the FP32 offset origin_j + shift - origin_i.
-struct Task {
+// Task record: the source cell (its first sorted index and count), whether it
+// is the receiving cell itself without a periodic shift, and the FP32 offset
+// origin_j + shift - origin_i (formed in FP64).
+struct alignas(16) Task {
+    int32_t j0;
+    int32_t jc;
+    int32_t self;
     int32_t j;
-    float ox, oy, oz;
+    float ox, oy, oz, pad;
 };
 
 }  // namespace sphx
@@ -92,6 +97,10 @@ struct sphx_grid {
     float4 *q1;         // vx, vy, vz, u
     float2 *qa;         // alpha_v, alpha_c
     uint8_t *need;      // 1: needs a density pass
+    float *hs;          // h in sorted order (kept equal to the caller's h by iter_reset,
+                        // refresh_h and the ghost)
+    float4 *d0;         // density sums in sorted order: n, dn/dh, rho, drho/dh
+    float4 *d1;         // div_sum, curl_x, curl_y, curl_z
     float4 *g0;         // force-pass state: h, rho, P, c
     float4 *g1;         // force-pass state: f, balsara, A, 0
 
@@ -123,6 +132,7 @@ struct sphx_tasks {
     sphx::Task *task;   // n_tasks
     int32_t *count;     // n_leaves (scratch)
     float *radius;      // per leaf: (1 + skin) * max H at build time
+    uint8_t *overflow;  // per leaf: 1 when the serial walk built its list
     void *scan_tmp;
     size_t scan_tmp_bytes;
 };
@@ -133,6 +143,7 @@ namespace sphx {
 sphx_status grid_build(sphx_ctx *ctx, const sphx_particles *in, hipStream_t s, sphx_grid **out);
 void grid_free(sphx_grid *g);
 sphx_status iter_reset(sphx_grid *g, const sphx_particles *in, hipStream_t s);
+sphx_status refresh_h(sphx_grid *g, const sphx_particles *in, hipStream_t s);
 size_t grid_bytes(int64_t n);
 
 // tasks.hip

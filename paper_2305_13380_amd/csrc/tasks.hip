@@ -17,6 +17,12 @@ namespace {
 
 inline unsigned blocks(int64_t n, int t) { return unsigned((n + t - 1) / t); }
 
+__device__ __forceinline__ int lanes_below64(uint64_t mask)
+{
+    return __builtin_amdgcn_mbcnt_hi(uint32_t(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo(uint32_t(mask), 0));
+}
+
 __device__ __forceinline__ float wave_maxf(float v)
 {
     for (int o = 32; o > 0; o >>= 1)
@@ -27,8 +33,7 @@ __device__ __forceinline__ float wave_maxf(float v)
 // One wave per leaf: radius = (1 + skin) * gamma_k * max h over the leaf.
 __global__ __launch_bounds__(64) void k_leaf_radius(int64_t n_leaves,
                                                     const int32_t *__restrict__ leaf_start,
-                                                    const int32_t *__restrict__ perm,
-                                                    const float *__restrict__ h, float scale,
+                                                    const float *__restrict__ hs, float scale,
                                                     float *__restrict__ node_r,
                                                     float *__restrict__ radius)
 {
@@ -37,7 +42,7 @@ __global__ __launch_bounds__(64) void k_leaf_radius(int64_t n_leaves,
         return;
     int lane = threadIdx.x;
     int32_t s0 = leaf_start[L], cnt = leaf_start[L + 1] - s0;
-    float v = lane < cnt ? h[perm[s0 + lane]] : 0.0f;
+    float v = lane < cnt ? hs[s0 + lane] : 0.0f;
     v = wave_maxf(v) * scale;
     if (lane == 0) {
         node_r[L] = v;
@@ -87,6 +92,49 @@ __device__ __forceinline__ void axis_gaps(double alo, double ahi, double blo, do
     }
 }
 
+// Gaps of `node` to the receiving box per axis and shift; returns whether the
+// node can hold a cell within max(R_I, R_node) of the box.
+__device__ __forceinline__ bool node_near(const TreeView &T, const double alo[3],
+                                          const double ahi[3], float RI, int64_t node,
+                                          double g[3][3], double &R)
+{
+    R = fmax(double(RI), double(T.r[node]));
+    double d2 = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        axis_gaps(alo[a], ahi[a], T.lo[3 * node + a], T.hi[3 * node + a], T.L[a], T.periodic,
+                  g[a]);
+        double m = fmin(g[a][0], fmin(g[a][1], g[a][2]));
+        d2 += m * m;
+    }
+    return d2 < R * R;
+}
+
+// Emit the tasks of one cell that passed node_near, in shift order.
+template <class Emit>
+__device__ __forceinline__ int emit_shifts(const double g[3][3], double R, Emit &&emit)
+{
+    const double R2 = R * R;
+    int n = 0;
+    for (int sx = 0; sx < 3; ++sx) {
+        if (!(g[0][sx] < R))
+            continue;
+        for (int sy = 0; sy < 3; ++sy) {
+            if (!(g[1][sy] < R))
+                continue;
+            for (int sz = 0; sz < 3; ++sz) {
+                if (!(g[2][sz] < R))
+                    continue;
+                double dd = g[0][sx] * g[0][sx] + g[1][sy] * g[1][sy] + g[2][sz] * g[2][sz];
+                if (dd < R2) {
+                    emit(n, sx - 1, sy - 1, sz - 1);
+                    ++n;
+                }
+            }
+        }
+    }
+    return n;
+}
+
 // Walk the tree for leaf `I`; for every leaf J (ascending) and shift whose box
 // gap is below max(R_I, R_J), call emit(J, sx, sy, sz).
 template <class Emit>
@@ -106,34 +154,12 @@ __device__ void walk(const TreeView &T, int64_t I, Emit &&emit)
         int lev = int(e >> 40);
         int64_t c = e & ((int64_t(1) << 40) - 1);
         int64_t node = T.level_off[lev] + c;
-        double R = fmax(double(RI), double(T.r[node]));
-        double R2 = R * R;
+        double R;
         double g[3][3];
-        double d2 = 0.0;
-        for (int a = 0; a < 3; ++a) {
-            axis_gaps(alo[a], ahi[a], T.lo[3 * node + a], T.hi[3 * node + a], T.L[a], T.periodic,
-                      g[a]);
-            double m = fmin(g[a][0], fmin(g[a][1], g[a][2]));
-            d2 += m * m;
-        }
-        if (!(d2 < R2))
+        if (!node_near(T, alo, ahi, RI, node, g, R))
             continue;
         if (lev == 0) {
-            for (int sx = 0; sx < 3; ++sx) {
-                if (!(g[0][sx] < R))
-                    continue;
-                for (int sy = 0; sy < 3; ++sy) {
-                    if (!(g[1][sy] < R))
-                        continue;
-                    for (int sz = 0; sz < 3; ++sz) {
-                        if (!(g[2][sz] < R))
-                            continue;
-                        double dd = g[0][sx] * g[0][sx] + g[1][sy] * g[1][sy] + g[2][sz] * g[2][sz];
-                        if (dd < R2)
-                            emit(c, sx - 1, sy - 1, sz - 1);
-                    }
-                }
-            }
+            emit_shifts(g, R, [&](int, int sx, int sy, int sz) { emit(c, sx, sy, sz); });
             continue;
         }
         int64_t b = c * kTreeFan, e2 = b + kTreeFan;
@@ -144,10 +170,13 @@ __device__ void walk(const TreeView &T, int64_t I, Emit &&emit)
     }
 }
 
-__global__ void k_task_count(int64_t n_leaves, TreeView T, int32_t *__restrict__ count)
+// Serial walks (one thread per cell), used for the cells whose breadth-first
+// frontier did not fit in LDS.
+__global__ void k_task_count(int64_t n_leaves, TreeView T, const uint8_t *__restrict__ overflow,
+                             int32_t *__restrict__ count)
 {
     int64_t I = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (I >= n_leaves)
+    if (I >= n_leaves || !overflow[I])
         return;
     int32_t c = 0;
     walk(T, I, [&](int64_t, int, int, int) { ++c; });
@@ -155,10 +184,12 @@ __global__ void k_task_count(int64_t n_leaves, TreeView T, int32_t *__restrict__
 }
 
 __global__ void k_task_fill(int64_t n_leaves, TreeView T, const double *__restrict__ org,
+                            const int32_t *__restrict__ leaf_start,
+                            const uint8_t *__restrict__ overflow,
                             const int32_t *__restrict__ off, Task *__restrict__ task)
 {
     int64_t I = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (I >= n_leaves)
+    if (I >= n_leaves || !overflow[I])
         return;
     int32_t w = off[I];
     const int32_t w_end = off[I + 1];
@@ -166,6 +197,10 @@ __global__ void k_task_fill(int64_t n_leaves, TreeView T, const double *__restri
     walk(T, I, [&](int64_t J, int sx, int sy, int sz) {
         Task t;
         t.j = int32_t(J);
+        t.j0 = leaf_start[J];
+        t.jc = leaf_start[J + 1] - t.j0;
+        t.self = (J == I && sx == 0 && sy == 0 && sz == 0) ? 1 : 0;
+        t.pad = 0.0f;
         // origin_j + shift - origin_i, formed in FP64, stored in FP32
         t.ox = float(org[3 * J] + double(sx) * T.L[0] - ox);
         t.oy = float(org[3 * J + 1] + double(sy) * T.L[1] - oy);
@@ -173,6 +208,140 @@ __global__ void k_task_fill(int64_t n_leaves, TreeView T, const double *__restri
         if (w < w_end)
             task[w++] = t;
     });
+}
+
+constexpr int kFront = 1024;  // breadth-first frontier capacity (nodes) per cell
+
+// Exclusive prefix sum over the wave of small non-negative counts (< 32),
+// built from one ballot per bit; returns the prefix, sets `total`.
+__device__ __forceinline__ int wave_prefix_small(int v, int &total)
+{
+    const uint64_t below = (uint64_t(1) << (threadIdx.x & 63)) - 1;
+    int pre = 0;
+    total = 0;
+    for (int b = 0; b < 5; ++b) {
+        const uint64_t m = __ballot((v >> b) & 1);
+        pre += __popcll(m & below) << b;
+        total += __popcll(m) << b;
+    }
+    return pre;
+}
+
+// One wave per receiving cell: level-by-level walk of the tree, 8 frontier
+// nodes x 8 children tested per step by the 64 lanes; survivors keep their
+// ascending order, so the cells (and their shifts) come out in the same order
+// as in the serial walk. A frontier that would exceed kFront marks the cell
+// for the serial walk instead.
+template <bool FILL>
+__global__ __launch_bounds__(64) void k_task_bfs(int64_t n_leaves, TreeView T,
+                                                 const double *__restrict__ org,
+                                                 const int32_t *__restrict__ leaf_start,
+                                                 const int32_t *__restrict__ off,
+                                                 int32_t *__restrict__ count,
+                                                 uint8_t *__restrict__ overflow,
+                                                 Task *__restrict__ task)
+{
+    const int64_t I = blockIdx.x;
+    if (I >= n_leaves)
+        return;
+    if (FILL && overflow[I])
+        return;
+    const int lane = threadIdx.x;
+    __shared__ int32_t front[2][kFront];
+    const double alo[3] = {T.lo[3 * I], T.lo[3 * I + 1], T.lo[3 * I + 2]};
+    const double ahi[3] = {T.hi[3 * I], T.hi[3 * I + 1], T.hi[3 * I + 2]};
+    const float RI = T.r[I];
+    const int top = T.n_levels - 1;
+    int cur = 0;
+    int ncur = int(T.level_cnt[top]);
+    if (ncur > kFront) {
+        if (!FILL && lane == 0) {
+            overflow[I] = 1;
+            count[I] = 0;
+        }
+        return;
+    }
+    for (int k = lane; k < ncur; k += 64)
+        front[0][k] = k;
+    int emitted = 0;
+    const int32_t wbase = FILL ? off[I] : 0;
+    const double oxi = org[3 * I], oyi = org[3 * I + 1], ozi = org[3 * I + 2];
+    for (int lev = top; lev >= 0; --lev) {
+        __syncthreads();
+        if (lev == 0) {
+            for (int base = 0; base < ncur; base += 64) {
+                const int idx = base + lane;
+                int nt = 0;
+                double g[3][3], R = 0.0;
+                int32_t J = 0;
+                bool near = false;
+                if (idx < ncur) {
+                    J = front[cur][idx];
+                    near = node_near(T, alo, ahi, RI, J, g, R);
+                    if (near)
+                        nt = emit_shifts(g, R, [](int, int, int, int) {});
+                }
+                int tot;
+                const int pre = wave_prefix_small(nt, tot);
+                if (FILL && nt > 0) {
+                    const int32_t j0 = leaf_start[J];
+                    const int32_t jc = leaf_start[J + 1] - j0;
+                    emit_shifts(g, R, [&](int k, int sx, int sy, int sz) {
+                        Task t;
+                        t.j = J;
+                        t.j0 = j0;
+                        t.jc = jc;
+                        t.self = (J == I && sx == 0 && sy == 0 && sz == 0) ? 1 : 0;
+                        t.ox = float(org[3 * J] + double(sx) * T.L[0] - oxi);
+                        t.oy = float(org[3 * J + 1] + double(sy) * T.L[1] - oyi);
+                        t.oz = float(org[3 * J + 2] + double(sz) * T.L[2] - ozi);
+                        t.pad = 0.0f;
+                        task[wbase + emitted + pre + k] = t;
+                    });
+                }
+                emitted += tot;
+            }
+            break;
+        }
+        // expand the frontier into the surviving children at level lev - 1
+        const int64_t cnt_dn = T.level_cnt[lev - 1];
+        const int64_t off_dn = T.level_off[lev - 1];
+        int nnext = 0;
+        bool over = false;
+        for (int base = 0; base < ncur; base += 8) {
+            const int k = base + (lane >> 3);
+            const int c = lane & 7;
+            bool keep = false;
+            int64_t child = 0;
+            if (k < ncur) {
+                child = int64_t(front[cur][k]) * kTreeFan + c;
+                if (child < cnt_dn) {
+                    double g[3][3], R;
+                    keep = node_near(T, alo, ahi, RI, off_dn + child, g, R);
+                }
+            }
+            const uint64_t mask = __ballot(keep);
+            const int tot = __popcll(mask);
+            if (nnext + tot > kFront) {
+                over = true;
+                break;
+            }
+            if (keep)
+                front[cur ^ 1][nnext + lanes_below64(mask)] = int32_t(child);
+            nnext += tot;
+        }
+        if (over) {
+            if (!FILL && lane == 0) {
+                overflow[I] = 1;
+                count[I] = 0;
+            }
+            return;
+        }
+        cur ^= 1;
+        ncur = nnext;
+    }
+    if (!FILL && lane == 0)
+        count[I] = emitted;
 }
 
 }  // namespace
@@ -188,7 +357,7 @@ void tasks_free(sphx_tasks *t)
 {
     if (!t)
         return;
-    void *ptrs[] = {t->off, t->task, t->count, t->radius, t->scan_tmp};
+    void *ptrs[] = {t->off, t->task, t->count, t->radius, t->scan_tmp, t->overflow};
     for (void *p : ptrs)
         if (p)
             (void)hipFree(p);
@@ -215,7 +384,8 @@ sphx_status tasks_build(sphx_ctx *ctx, sphx_grid *g, const sphx_particles *in, h
         };
         if (hipMalloc(&t->off, (nl + 1) * sizeof(int32_t)) != hipSuccess ||
             hipMalloc(&t->count, (nl + 1) * sizeof(int32_t)) != hipSuccess ||
-            hipMalloc(&t->radius, (nl + 1) * sizeof(float)) != hipSuccess) {
+            hipMalloc(&t->radius, (nl + 1) * sizeof(float)) != hipSuccess ||
+            hipMalloc(&t->overflow, (nl + 1) * sizeof(uint8_t)) != hipSuccess) {
             set_error("sphx_tasks_build: out of device memory");
             return fail(SPHX_E_OOM);
         }
@@ -247,7 +417,8 @@ sphx_status tasks_build(sphx_ctx *ctx, sphx_grid *g, const sphx_particles *in, h
         return SPHX_OK;
     }
     const float scale = float(ctx->p.gamma_k * (1.0 + ctx->p.skin));
-    k_leaf_radius<<<unsigned(nl), 64, 0, s>>>(nl, g->leaf_start, g->perm, in->h, scale, g->node_r,
+    (void)in;
+    k_leaf_radius<<<unsigned(nl), 64, 0, s>>>(nl, g->leaf_start, g->hs, scale, g->node_r,
                                               t->radius);
     SPHX_HIP(hipGetLastError());
     for (int l = 0; l + 1 < g->n_levels; ++l) {
@@ -271,7 +442,11 @@ sphx_status tasks_build(sphx_ctx *ctx, sphx_grid *g, const sphx_particles *in, h
     T.periodic = ctx->p.periodic;
 
     SPHX_HIP(hipMemsetAsync(t->count + nl, 0, sizeof(int32_t), s));
-    k_task_count<<<blocks(nl, 64), 64, 0, s>>>(nl, T, t->count);
+    SPHX_HIP(hipMemsetAsync(t->overflow, 0, size_t(nl) * sizeof(uint8_t), s));
+    k_task_bfs<false><<<unsigned(nl), 64, 0, s>>>(nl, T, g->leaf_org, g->leaf_start, t->off,
+                                                  t->count, t->overflow, t->task);
+    SPHX_HIP(hipGetLastError());
+    k_task_count<<<blocks(nl, 64), 64, 0, s>>>(nl, T, t->overflow, t->count);
     SPHX_HIP(hipGetLastError());
     size_t tmp = t->scan_tmp_bytes;
     SPHX_HIP(rocprim::exclusive_scan(t->scan_tmp, tmp, t->count, t->off, 0, size_t(nl + 1),
@@ -292,7 +467,11 @@ sphx_status tasks_build(sphx_ctx *ctx, sphx_grid *g, const sphx_particles *in, h
         t->cap = cap;
     }
     t->n_tasks = total;
-    k_task_fill<<<blocks(nl, 64), 64, 0, s>>>(nl, T, g->leaf_org, t->off, t->task);
+    k_task_bfs<true><<<unsigned(nl), 64, 0, s>>>(nl, T, g->leaf_org, g->leaf_start, t->off,
+                                                 t->count, t->overflow, t->task);
+    SPHX_HIP(hipGetLastError());
+    k_task_fill<<<blocks(nl, 64), 64, 0, s>>>(nl, T, g->leaf_org, g->leaf_start, t->overflow,
+                                              t->off, t->task);
     SPHX_HIP(hipGetLastError());
     guard.keep = true;
     *out = t;

@@ -151,6 +151,8 @@ def _stream(stream):
 
 
 class Context:
+    handle = None
+
     def __init__(self, params: Optional[Params] = None, device: int = 0):
         self.params = params if params is not None else default_params()
         self.device = device
@@ -244,6 +246,8 @@ class Outputs:
 
 
 class Grid:
+    handle = None
+
     def __init__(self, ctx: Context, parts: DeviceParticles, stream=None):
         self.ctx = ctx
         self.pv = parts.view()
@@ -264,6 +268,8 @@ class Grid:
 
 
 class Tasks:
+    handle = None
+
     def __init__(self, ctx: Context, grid: Grid, parts: DeviceParticles, stream=None):
         self.ctx = ctx
         self.grid = grid
