@@ -93,6 +93,63 @@ def cpu_baseline(ps, params_cls, n_recv, seed=0):
                           len(recv), nd - len(recv), tot_d, tot_f, dt)}
 
 
+def replay_density_units(sphx, ctx, grid, tasks, dp, out, h0):
+    """Re-run one step pass by pass through the C-ABI (same decisions as
+    sphx_step) and return, per density launch, the interactions it computed:
+    the neighbour counts of the particles it processed. The step is
+    deterministic, so these are the units of every timed step's launches."""
+    import torch
+    n = dp.n
+    dp.t["h"].copy_(h0)
+    sphx.iter_reset(ctx, grid, dp)
+    out.g["converged"].zero_()
+    act = dp.t["active"].bool() if dp.t["active"] is not None else torch.ones(
+        n, dtype=torch.bool, device=dp.t["h"].device)
+    units = []
+    max_iter = ctx.params.max_iter
+    p = 0
+    while p < max_iter:
+        processed = act & (out.g["converged"] == 0)
+        out.counters.zero_()
+        sphx.density(ctx, grid, tasks, dp, out)
+        final = p + 1 == max_iter
+        sphx.ghost(ctx, grid, tasks, dp, out, final_pass=final)
+        c = out.counters.cpu().numpy()
+        units.append(int(out.d["nngb"][processed].to(torch.int64).sum()))
+        if c[3] > 0:
+            tasks.build(dp)
+            continue
+        p += 1
+        if c[0] == 0 or final:
+            break
+        if c[1] > 0:
+            tasks.build(dp)
+    return units
+
+
+def measured_traffic(config, kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (profiles/traffic_<config>.json: FETCH_SIZE and WRITE_SIZE scaled by a
+    plain copy of known size), or None when the summary is missing or the
+    kernel's sources changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic_%s.json" % config)
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path)).get(kernel)
+    if not rec:
+        return None
+    base = os.path.join(ROOT, "paper_2305_13380_amd", "csrc")
+    srcs = {"k_density": ["density.hip", "pairs.h", "sphx_internal.h"],
+            "k_force": ["force.hip", "pairs.h", "sphx_internal.h"]}[kernel]
+    hsh = hashlib.sha256()
+    for f in srcs:
+        hsh.update(open(os.path.join(base, f), "rb").read())
+    if hsh.hexdigest()[:16] != rec["source_hash"]:
+        return None
+    return rec["mean_bytes_per_launch"]
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -101,7 +158,19 @@ def main():
     ap.add_argument("--config", default="clustered", choices=sorted(CONFIGS))
     ap.add_argument("--cpu-receivers", type=int, default=4096)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (to scale HBM byte counters)")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        nbytes = args.calibrate_copy << 20
+        a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda:0").fill_(1.0)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes}))
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(got --gpus %d)" % args.gpus, file=sys.stderr)
@@ -181,20 +250,21 @@ def main():
     mom = float(np.abs(sums[:3]).max() / max(sums[4], 1e-300))
     en = float(abs(sums[3]) / max(sums[4] + sums[5], 1e-300))
 
-    # Dominant kernel (by total time) and its algorithmic FLOP rate per launch.
-    f_avg = force_ms / max(force_n, 1) / 1e3
-    force_flops = n_force * FLOP_FORCE
-    d_avg = dens_ms / max(dens_n, 1) / 1e3
-    if force_ms >= dens_ms:
-        achieved = force_flops / f_avg / 1e12
-        kern = "k_force"
-        per_launch = force_flops
+    # Algorithmic FLOP rates of the two neighbour-loop kernels: interactions
+    # each launch computes times the FLOPs per interaction, over the kernel's
+    # own event-timed duration in the timed steps.
+    units = replay_density_units(sphx, ctx, grid, tasks, dp, out, h0)
+    dens_flops_step = sum(units) * FLOP_DENSITY
+    dens_ms_step = dens_ms / args.steps
+    force_ms_step = force_ms / args.steps
+    dens_rate = dens_flops_step / (dens_ms_step / 1e3) / 1e12
+    force_rate = n_force * FLOP_FORCE / (force_ms_step / 1e3) / 1e12
+    if dens_ms_step >= force_ms_step:
+        kern, achieved = "k_density", dens_rate
+        per_launch = dens_flops_step / max(len(units), 1)
     else:
-        # density launches revisit only unconverged particles after the first
-        # pass; count the final-h interactions once per step over the launches
-        per_launch = n_dens * FLOP_DENSITY * args.steps / max(dens_n, 1)
-        achieved = per_launch / d_avg / 1e12
-        kern = "k_density"
+        kern, achieved = "k_force", force_rate
+        per_launch = n_force * FLOP_FORCE
     passes = sorted(set(p for p, _, _ in infos))
     line = {
         "metric": "SPH pair interactions/s (density+force) at 1 GPU",
@@ -218,10 +288,13 @@ def main():
                    "grid_build_ms": t_grid * 1e3, "tasks_build_ms": t_tasks * 1e3,
                    "density_kernel_ms_per_step": dens_ms / args.steps,
                    "force_kernel_ms_per_step": force_ms / args.steps,
-                   "momentum_err_rel": mom, "energy_err_rel": en},
+                   "momentum_err_rel": mom, "energy_err_rel": en,
+                   "density_interactions_per_launch": units,
+                   "density_tflops": dens_rate, "force_tflops": force_rate},
         "roofline": {"bound": "alu", "kernel": kern, "achieved": achieved,
                      "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                     "frac": achieved / PEAK_FP32_TFLOPS,
+                     "traffic": measured_traffic(args.config, kern),
                      "flop_per_launch": per_launch},
     }
     if not args.no_cpu_baseline:
