@@ -136,9 +136,24 @@ def _wrapped_positions(ps, periodic):
     return p
 
 
-def _tree(p, ps, periodic):
+_TREE_CACHE = {}
+
+
+def _tree(p, ps, periodic, cache=True):
+    """k-d tree over positions p; the tree over a whole particle set is kept
+    for reuse while the set's position arrays are the same objects."""
     from scipy.spatial import cKDTree
-    return cKDTree(p, boxsize=np.asarray(ps.box, dtype=np.float64) if periodic else None)
+    key = None
+    if cache and p.shape[0] == ps.n:
+        key = (id(ps.x), id(ps.y), id(ps.z), ps.n, bool(periodic), tuple(ps.box),
+               float(ps.x[: 8].sum() + ps.y[-8:].sum() + ps.z[ps.n // 2]))
+        hit = _TREE_CACHE.get("last")
+        if hit is not None and hit[0] == key:
+            return hit[1]
+    t = cKDTree(p, boxsize=np.asarray(ps.box, dtype=np.float64) if periodic else None)
+    if key is not None:
+        _TREE_CACHE["last"] = (key, t)
+    return t
 
 
 def _pairs(lists, k_offset=0):
@@ -198,7 +213,7 @@ def force_candidates(ps, h, params: Params, recv):
     band = np.floor(np.log2(H / lo)).astype(np.int64)
     for b in np.unique(band):
         members = np.nonzero(band == b)[0]
-        sub = _tree(p[members], ps, params.periodic)
+        sub = _tree(p[members], ps, params.periodic, cache=False)
         rb = float(H[members].max()) * _PAD
         for s in range(0, len(ri), chunk):
             sl = ri[s:s + chunk]
@@ -299,7 +314,7 @@ def solve_h(ps, params: Params, recv=None, mode="auto", h0=None):
     return h, dens, conv, iters, passes
 
 
-def force(ps, h, gst, dens_rho, params: Params, recv=None, mode="auto"):
+def force(ps, h, gst, dens_rho, params: Params, recv=None, mode="auto", cand=None):
     """Accelerations, du/dt and signal velocity for the receivers (Sections
     3.2, 3.3). ``gst`` and ``dens_rho`` hold every particle's ghost state
     (only neighbours' entries are read)."""
@@ -308,7 +323,7 @@ def force(ps, h, gst, dens_rho, params: Params, recv=None, mode="auto"):
     r, nrecv = _recv_arr(recv, ps.n)
     off = idx = None
     if mode == "tree":
-        off, idx = force_candidates(ps, h, params, r)
+        off, idx = cand if cand is not None else force_candidates(ps, h, params, r)
     out = {k: np.zeros(nrecv) for k in ("ax", "ay", "az", "du", "vsig")}
     nf = np.zeros(nrecv, np.int64)
     x, y, z = _pos(ps)
@@ -330,14 +345,15 @@ def sums(m, vx, vy, vz, ax, ay, az, du):
     return out
 
 
-def force_needed(ps, h, params: Params, recv, mode="auto"):
+def force_needed(ps, h, params: Params, recv, mode="auto", cand=None):
     """Receivers plus every particle inside their force neighbourhoods."""
     mode = _resolve_mode(mode, ps.n)
     if recv is None:
         return np.arange(ps.n)
     if mode == "brute":
         return np.arange(ps.n)
-    off, idx = force_candidates(ps, _f64(h), params, np.asarray(recv, np.int64))
+    off, idx = cand if cand is not None else force_candidates(
+        ps, _f64(h), params, np.asarray(recv, np.int64))
     return np.unique(np.concatenate([np.asarray(recv, np.int64), idx]))
 
 
@@ -349,7 +365,10 @@ def fixed_h_step(ps, params: Params, recv=None, mode="auto", h=None):
     particles outside that set are NaN so any stray read shows up.
     """
     h = _f64(ps.h if h is None else h)
-    need = force_needed(ps, h, params, recv, mode)
+    cand = None
+    if recv is not None and _resolve_mode(mode, ps.n) == "tree":
+        cand = force_candidates(ps, h, params, np.asarray(recv, np.int64))
+    need = force_needed(ps, h, params, recv, mode, cand=cand)
     d = density(ps, h, params, recv=need, mode=mode)
     g = ghost(d, _f64(ps.u)[need], h[need], params)
     full = {k: np.full(ps.n, np.nan) for k in ("P", "c", "f", "balsara")}
@@ -357,7 +376,7 @@ def fixed_h_step(ps, params: Params, recv=None, mode="auto", h=None):
     for k in full:
         full[k][need] = g[k]
     rho[need] = d["rho"]
-    fo = force(ps, h, full, rho, params, recv=recv, mode=mode)
+    fo = force(ps, h, full, rho, params, recv=recv, mode=mode, cand=cand)
     ri = np.arange(ps.n) if recv is None else np.asarray(recv, np.int64)
     pos = np.searchsorted(need, ri)
     res = {"h": h[ri]}

@@ -232,7 +232,7 @@ void or_ghost(int64_t n, const double *rho, const double *rho_dh, const double *
  *   vsig_ij = c_i + c_j - beta mu
  *   alpha_ij = (alpha_V,i + alpha_V,j)/2 * (B_i + B_j)/2
  *   nu = -alpha_ij mu vsig_ij / (0.5 (rho_i + rho_j))
- *   G = f_i g_i + f_j g_j
+ *   G = f_i g_i + f_j g_j      (each term only inside its own support)
  *   a_i  -= m_j [A_i g_i + A_j g_j + nu G / 2] e          (A = f P / rho^2)
  *   du_i += m_j [A_i g_i + nu G / 4] (v_ij . e)
  *   du_i += m_j alpha_c,ij v_c,ij (u_i - u_j) G / (rho_i + rho_j)
@@ -290,12 +290,16 @@ int64_t or_force(int64_t n, const double *x, const double *y, const double *z,
             double alpha_ij = 0.5 * (alpha_v[i] + alpha_v[j]) * 0.5 * (balsara[i] + balsara[j]);
             double nu = -alpha_ij * mu * vsig_ij / (0.5 * (rho[i] + rho[j]));
             double Aj = f[j] * P[j] / (rho[j] * rho[j]);
-            double G = f[i] * gi + f[j] * gj;
-            double acc = Ai * gi + Aj * gj + 0.5 * nu * G;
+            /* a kernel term outside its own support is zero (W' = 0 there),
+             * also when the particle's f is infinite (alone in its support) */
+            double fgi = r < Hi ? f[i] * gi : 0.0, Agi = r < Hi ? Ai * gi : 0.0;
+            double fgj = r < Hj ? f[j] * gj : 0.0, Agj = r < Hj ? Aj * gj : 0.0;
+            double G = fgi + fgj;
+            double acc = Agi + Agj + 0.5 * nu * G;
             s_ax -= m[j] * acc * ex;
             s_ay -= m[j] * acc * ey;
             s_az -= m[j] * acc * ez;
-            s_du += m[j] * (Ai * gi + 0.25 * nu * G) * vdote;
+            s_du += m[j] * (Agi + 0.25 * nu * G) * vdote;
             double psum = P[i] + P[j];
             double alpha_c_ij = psum > 0.0 ? (P[i] * alpha_c[i] + P[j] * alpha_c[j]) / psum : 0.0;
             double v_c = fabs(vdote) + sqrt(2.0 * fabs(P[i] - P[j]) / (rho[i] + rho[j]));

@@ -227,7 +227,12 @@ __global__ __launch_bounds__(64 * NW) void k_density(
     const float cx = -kD * invH5 * S[5];
     const float cy = -kD * invH5 * S[6];
     const float cz = -kD * invH5 * S[7];
-    d0[s] = make_float4(n_, n_dh, rho, rho_dh);
+    // For the ghost, the two ratios it needs in a form free of cancellation:
+    // G' = 3 + h n'/n = kD Sud / (kW Sw) and 1 + h rho'/(3 rho) = kD Smud /
+    // (3 kW Smw) (the self term cancels exactly in both).
+    const float gp = (kD * S[2]) / (kW * Sw);
+    const float fden = (kD * S[3]) / (3.0f * kW * Smw);
+    d0[s] = make_float4(n_, gp, rho, fden);
     d1[s] = make_float4(dv, cx, cy, cz);
     o_n[gi] = n_;
     o_rho[gi] = rho;

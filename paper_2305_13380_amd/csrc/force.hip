@@ -135,13 +135,17 @@ __global__ __launch_bounds__(64 * NW) void k_force(
             const float alpha = 0.25f * (ai.x + b.w) * (Bi + b.z);
             const float irs = fast_rcp(rhoi + a.z);
             const float nu = -2.0f * alpha * mu * vs * irs;
-            const float G = fi * gi + b.x * gj;
-            const float acc = Ai * gi + b.y * gj + 0.5f * nu * G;
+            // a kernel term outside its own support is zero, also when f is
+            // infinite (a particle alone in its support at a fixed h)
+            const float fgi = ui < 1.0f ? fi * gi : 0.0f, Agi = ui < 1.0f ? Ai * gi : 0.0f;
+            const float fgj = uj < 1.0f ? b.x * gj : 0.0f, Agj = uj < 1.0f ? b.y * gj : 0.0f;
+            const float G = fgi + fgj;
+            const float acc = Agi + Agj + 0.5f * nu * G;
             const float m = v.w;
             ax -= m * acc * ex;
             ay -= m * acc * ey;
             az -= m * acc * ez;
-            du += m * (Ai * gi + 0.25f * nu * G) * vdote;
+            du += m * (Agi + 0.25f * nu * G) * vdote;
             const float psum = Pi + a.w;
             const float ac = psum > 0.0f ? (acPi + c2.x) * fast_rcp(psum) : 0.0f;
             const float vc = fabsf(vdote) + fast_sqrt(2.0f * fabsf(Pi - a.w) * irs);

@@ -26,13 +26,13 @@ __global__ void k_ghost(int64_t n, const int32_t *__restrict__ perm,
     bool unconv = false, rebuild = false, clamped = false;
     if (work) {
         const float hh = hs[s];
-        const float4 a = d0[s];  // n, dn/dh, rho, drho/dh
-        const float nd = a.x, ndh = a.y;
+        const float4 a = d0[s];  // n, G' = 3 + h n'/n, rho, 1 + h rho'/(3 rho)
+        const float nd = a.x;
         // Newton-Raphson in ln h on G = ln(n h^3 / eta^3), G' = 3 + h n'/n,
         // with the step limited to a factor 2; in base-2 logarithms:
         // log2(h_new / h) = -log2(n h^3 / eta^3) / G'.
         const float G2 = __log2f(nd * (hh * hh * hh) * inv_eta3);
-        const float dG = 3.0f + hh * ndh / nd;
+        const float dG = a.y;
         float e = -G2 / dG;
         if (!(dG > 0.0f) || !isfinite(e))
             e = G2 < 0.0f ? 1.0f : -1.0f;
@@ -57,7 +57,7 @@ __global__ void k_ghost(int64_t n, const int32_t *__restrict__ perm,
             const float u = q1[s].w;
             const float P = (gamma_gas - 1.0f) * u * rho;
             const float c = sqrtf(gamma_gas * (gamma_gas - 1.0f) * u);
-            const float f = 1.0f / (1.0f + hh * a.w / (3.0f * rho));
+            const float f = 1.0f / a.w;
             const float irho = 1.0f / rho;
             const float div = b.x * irho;
             const float curl = sqrtf(b.y * b.y + b.z * b.z + b.w * b.w) * irho;

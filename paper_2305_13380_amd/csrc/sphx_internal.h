@@ -99,7 +99,7 @@ struct sphx_grid {
     uint8_t *need;      // 1: needs a density pass
     float *hs;          // h in sorted order (kept equal to the caller's h by iter_reset,
                         // refresh_h and the ghost)
-    float4 *d0;         // density sums in sorted order: n, dn/dh, rho, drho/dh
+    float4 *d0;         // density results in sorted order: n, 3 + h n'/n, rho, 1 + h rho'/(3 rho)
     float4 *d1;         // div_sum, curl_x, curl_y, curl_z
     float4 *g0;         // force-pass state: h, rho, P, c
     float4 *g1;         // force-pass state: f, balsara, A, 0

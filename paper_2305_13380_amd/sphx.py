@@ -161,9 +161,9 @@ class Context:
         self.handle = h
 
     def close(self):
-        if self.handle:
+        if self.handle and lib is not None:  # lib is None at interpreter shutdown
             lib.sphx_ctx_destroy(self.handle)
-            self.handle = None
+        self.handle = None
 
     __del__ = close
 
@@ -260,9 +260,9 @@ class Grid:
         return int(lib.sphx_grid_leaves(self.handle))
 
     def close(self):
-        if self.handle:
+        if self.handle and lib is not None:  # lib is None at interpreter shutdown
             lib.sphx_grid_destroy(self.handle)
-            self.handle = None
+        self.handle = None
 
     __del__ = close
 
@@ -286,9 +286,9 @@ class Tasks:
         return int(lib.sphx_tasks_count(self.handle))
 
     def close(self):
-        if self.handle:
+        if self.handle and lib is not None:  # lib is None at interpreter shutdown
             lib.sphx_tasks_destroy(self.handle)
-            self.handle = None
+        self.handle = None
 
     __del__ = close
 

@@ -1,0 +1,137 @@
+"""GPU parity at the full workload sizes, in the launch configuration bench.py
+times: the GPU runs the whole box; the oracle evaluates a seeded random sample
+of receivers against all N sources (k-d tree candidates, exact test in FP64).
+
+* fixed h: density, ghost and force of the sampled receivers element by
+  element at the tolerances of the small cases;
+* full step: the sampled receivers' converged h against the oracle's own
+  Newton-Raphson solve, plus the FP64 conservation sums of the whole box.
+"""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2305_13380_amd import inputs
+
+from helpers import RHO_TOL, check_density, check_force, check_ghost, gpu_fixed_h, gpu_step
+
+pytestmark = pytest.mark.gpu
+P = oracle.Params()
+
+
+def log(*a):
+    print(*a, flush=True)
+
+
+def sample(n, k, seed):
+    return np.sort(np.random.default_rng(seed).choice(n, size=min(k, n), replace=False))
+
+
+def fixed_h_case(ps, k, seed, where):
+    t0 = time.time()
+    g = gpu_fixed_h(ps)
+    log("%s: GPU fixed-h pass on N=%d done (%.1f s)" % (where, ps.n, time.time() - t0))
+    assert g["counters"][3] == 0
+    recv = sample(ps.n, k, seed)
+    ref = oracle.fixed_h_step(ps, P, recv=recv, mode="tree")
+    log("%s: oracle on %d receivers done (%.1f s)" % (where, len(recv), time.time() - t0))
+    h = ps.h.astype(np.float64)
+    check_density(g, ref, ps, h, recv, P, where)
+    check_ghost(g, ref, recv, where)
+    check_force(g, ref, ps, h, recv, P, where)
+
+
+def step_case(ps, k, seed, where):
+    t0 = time.time()
+    g = gpu_step(ps)
+    info = g["info"]
+    log("%s: GPU step done: passes=%d rebuilds=%d (%.1f s)" % (
+        where, info.passes, info.task_rebuilds, time.time() - t0))
+    assert g["status"] >= 0 and info.unconverged == 0
+    recv = sample(ps.n, k, seed)
+    hr, dens, conv, _, passes = oracle.solve_h(ps, P, recv=recv, mode="tree")
+    log("%s: oracle h solve of %d receivers, %d passes (%.1f s)" % (
+        where, len(recv), passes, time.time() - t0))
+    assert conv.all()
+    hg = g["h"][recv].astype(np.float64)
+    dh = np.abs(hg - hr) / hr
+    assert np.all(dh <= 2 * P.h_tol), "%s h: worst %.3g" % (where, dh.max())
+    sens = np.abs(hr * dens["rho_dh"] / dens["rho"])
+    rho = g["rho"][recv].astype(np.float64)
+    assert np.all(np.abs(rho - dens["rho"]) <= (RHO_TOL + 1.5 * sens * dh) * dens["rho"])
+    s = g["sums"]
+    assert np.abs(s[:3]).max() < 1e-5 * s[4]
+    v = np.sqrt(np.mean(ps.vx.astype(np.float64) ** 2 + ps.vy ** 2 + ps.vz ** 2))
+    assert abs(s[3]) < 1e-5 * (s[4] * max(v, 1e-6) + s[5])
+    log("%s: max |dh|/h = %.2e, median %.2e" % (where, dh.max(), np.median(dh)))
+
+
+def test_sedov_full_size_fixed_h():
+    fixed_h_case(inputs.config_sedov(2), 2048, 11, "sedov 64^3 fixed h")
+
+
+def test_sedov_full_size_step():
+    step_case(inputs.config_sedov(2), 2048, 12, "sedov 64^3 step")
+
+
+def test_clustered_full_size_fixed_h():
+    fixed_h_case(inputs.config_clustered(3), 2048, 13, "clustered 128^3 fixed h")
+
+
+def test_clustered_full_size_step():
+    step_case(inputs.config_clustered(3), 1024, 14, "clustered 128^3 step")
+
+
+def test_large_active_full_size_fixed_h():
+    """16.8M particles, ~10% active: an all-active fixed-h pass supplies every
+    particle's state, then the active-only pass recomputes the active ones;
+    the sampled active receivers are checked against the oracle."""
+    import torch
+    from paper_2305_13380_amd import sphx
+    where = "large 256^3 active"
+    t0 = time.time()
+    ps = inputs.config_large(5)
+    log("%s: generated N=%d, active %d (%.1f s)" % (where, ps.n, int(ps.active.sum()),
+                                                   time.time() - t0))
+    ctx = sphx.Context()
+    all_on = ps.copy()
+    all_on.active = None
+    dp = sphx.DeviceParticles.from_set(all_on)
+    out = sphx.Outputs(ps.n)
+    grid = sphx.Grid(ctx, dp)
+    tasks = sphx.Tasks(ctx, grid, dp)
+    sphx.fixed_h_pass(ctx, grid, tasks, dp, out)
+    dp.t["active"] = torch.from_numpy(ps.active).cuda()
+    out.f["ax"].fill_(float("nan"))
+    sphx.fixed_h_pass(ctx, grid, tasks, dp, out)
+    torch.cuda.synchronize()
+    log("%s: GPU passes done (%.1f s)" % (where, time.time() - t0))
+    act = np.nonzero(ps.active)[0]
+    ax = out.f["ax"].cpu().numpy()
+    assert np.all(np.isfinite(ax[act]))
+    assert np.all(np.isnan(ax[np.nonzero(ps.active == 0)[0][:1000]]))  # inactive: untouched
+    g = {k: v.cpu().numpy() for k, v in {**out.d, **out.g, **out.f}.items()}
+    # Receivers: active particles in a central cube. A receiver's fixed-h
+    # results depend only on particles within 2 H_max of it, so the oracle is
+    # given every particle within 3 H_max of the cube (indices kept in
+    # ascending order, which leaves its sums bit-identical to a full-box run).
+    Hmax = P.gamma_k * float(ps.h.max())
+    pos = ps.positions()
+    c, half = 0.5, 0.04
+    inner = np.all(np.abs(pos - c) < half, axis=1)
+    region = np.nonzero(np.all(np.abs(pos - c) < half + 3 * Hmax, axis=1))[0]
+    cand = np.nonzero(inner & (ps.active == 1))[0]
+    recv_full = np.sort(np.random.default_rng(15).choice(cand, size=min(512, cand.size),
+                                                          replace=False))
+    sub = ps.subset(region)
+    recv = np.searchsorted(region, recv_full)
+    ref = oracle.fixed_h_step(sub, P, recv=recv, mode="tree")
+    log("%s: oracle on %d receivers (%d particles in region) done (%.1f s)" % (
+        where, len(recv), len(region), time.time() - t0))
+    gs = {k: v[region] for k, v in g.items()}
+    h = sub.h.astype(np.float64)
+    check_density(gs, ref, sub, h, recv, P, where)
+    check_ghost(gs, ref, recv, where)
+    check_force(gs, ref, sub, h, recv, P, where)
