@@ -10,7 +10,13 @@ value = (N_dens + N_force) / seconds per step, with
   N_dens  = sum_i #{j != i : r_ij < H_i}            at the final h,
   N_force = sum_i #{j != i : r_ij < max(H_i, H_j)}  (active receivers only).
 
-Prints one JSON line. See the design notes for the roofline accounting.
+Then (unless --no-serving) the serving stream of 512 independent boxes of
+10^3..10^6 particles is run through the continuous-batching server and through
+the plain per-call form: saturated throughput, and p50/p99 latency under
+Poisson arrivals at 0.5 and 0.8 of the served form's saturated rate
+(top-level p50_ms/p99_ms are the served form at 0.8).
+
+Prints one JSON line.
 """
 import argparse
 import json
@@ -127,6 +133,71 @@ def replay_density_units(sphx, ctx, grid, tasks, dp, out, h0):
     return units
 
 
+def serving_bench(slots, n_req, seed=4):
+    """The serving stream: n_req independent periodic boxes (N log-uniform in
+    [1e3, 1e6], lattice or lognormal by a seeded coin) with inputs resident in
+    HBM. Runs it saturated (all requests queued at t=0) with `slots` slots and
+    with one slot (the plain per-call form), then with seeded Poisson arrivals
+    at 0.5 and 0.8 times the served form's saturated request rate, for both
+    forms. Latency = completion - arrival."""
+    import numpy as np
+    import torch
+    from paper_2305_13380_amd import inputs, serve, sphx
+    t0 = time.perf_counter()
+    sizes, lattice = inputs.serving_sizes(n_req, seed)
+    dev = []
+    for k in range(n_req):
+        dev.append(sphx.DeviceParticles.from_set(
+            inputs.serving_request(k, int(sizes[k]), bool(lattice[k]), seed), "cuda:0"))
+    torch.cuda.synchronize()
+    n_tot = sum(d.n for d in dev)
+    log("bench: serving: %d requests, %d particles generated and uploaded in %.1f s" % (
+        n_req, n_tot, time.perf_counter() - t0))
+    servers = {"served": serve.Server(n_slots=slots), "per_call": serve.Server(n_slots=1)}
+    warm = [(k, 0.0, dev[k].n) for k in range(min(16, n_req))]
+    for srv in servers.values():
+        srv.run(warm, lambda k: dev[k])
+
+    def run(form, rate):
+        if rate is None:
+            arr = np.zeros(n_req)
+        else:
+            rng = np.random.default_rng(seed + 7919)
+            arr = np.cumsum(rng.exponential(1.0 / rate, n_req))
+        spec = [(k, float(arr[k]), dev[k].n) for k in range(n_req)]
+        res = servers[form].run(spec, lambda k: dev[k])
+        bad = [r for r in res if r.error is not None or r.status < 0]
+        if bad:
+            raise RuntimeError("serving: request %d failed: %s" % (bad[0].rid, bad[0].error))
+        span = max(r.done for r in res) - (0.0 if rate is None else float(arr[0]))
+        q = serve.percentiles(res)
+        rec = {"requests_per_s": n_req / span, "interactions_per_s":
+               sum(r.interactions for r in res) / span, "makespan_s": span,
+               "p50_ms": q["p50_s"] * 1e3, "p99_ms": q["p99_s"] * 1e3,
+               "peak_running": servers[form].peak_running}
+        if rate is not None:
+            rec["arrival_rate_per_s"] = rate
+        log("bench: serving %s rate=%s: %s" % (form, rate, json.dumps(rec)))
+        return rec, res
+
+    out = {"requests": n_req, "particles": n_tot, "slots": slots, "seed": seed,
+           "inputs": "resident in HBM; each request builds its grid and tasks, runs the "
+                     "h iteration, ghost, force and FP64 sums, and copies back its "
+                     "interaction counts"}
+    sat, res_sat = run("served", None)
+    sat1, _ = run("per_call", None)
+    out["saturated"] = {"served": sat, "per_call": sat1,
+                        "speedup": sat["requests_per_s"] / sat1["requests_per_s"]}
+    out["interactions"] = sum(r.interactions for r in res_sat)
+    for frac in (0.5, 0.8):
+        rate = frac * sat["requests_per_s"]
+        out["poisson_%.1f" % frac] = {"served": run("served", rate)[0],
+                                      "per_call": run("per_call", rate)[0]}
+    for srv in servers.values():
+        srv.close()
+    return out
+
+
 def measured_traffic(config, kernel):
     """HBM bytes per launch of `kernel` from the committed counter summary
     (profiles/traffic_<config>.json: FETCH_SIZE and WRITE_SIZE scaled by a
@@ -158,6 +229,10 @@ def main():
     ap.add_argument("--config", default="clustered", choices=sorted(CONFIGS))
     ap.add_argument("--cpu-receivers", type=int, default=4096)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serving", action="store_true",
+                    help="skip the serving-stream latency measurement")
+    ap.add_argument("--serving-requests", type=int, default=512)
+    ap.add_argument("--serving-slots", type=int, default=8)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (to scale HBM byte counters)")
     args = ap.parse_args()
@@ -297,6 +372,12 @@ def main():
                      "traffic": measured_traffic(args.config, kern),
                      "flop_per_launch": per_launch},
     }
+    del grid, tasks, out
+    if not args.no_serving:
+        sv = serving_bench(args.serving_slots, args.serving_requests)
+        line["serving"] = sv
+        line["p50_ms"] = sv["poisson_0.8"]["served"]["p50_ms"]
+        line["p99_ms"] = sv["poisson_0.8"]["served"]["p99_ms"]
     if not args.no_cpu_baseline:
         log("bench: timing the oracle on the host ...")
         import oracle

@@ -158,6 +158,8 @@ size_t sphx_workspace_bytes(const sphx_params *p, int64_t n);
  * particle its FP32 position relative to its leaf origin. Positions,
  * velocities, masses, u and alpha are copied at this point; later changes to
  * them need a new grid. Synchronises the stream (reads back the leaf count).
+ * The workspace is allocated stream-ordered on `stream` and released on it
+ * by sphx_grid_destroy, which must be called before that stream is destroyed.
  * *out is released with sphx_grid_destroy. */
 sphx_status sphx_grid_build(sphx_ctx *ctx, const sphx_particles *in, void *stream,
                             sphx_grid **out);
@@ -168,8 +170,8 @@ void sphx_grid_destroy(sphx_grid *grid);
  * max(H_i-leaf, H_j-leaf) * (1 + skin) of its own, H taken from the current
  * h. Each task carries the FP32 offset between the two leaf origins, formed
  * in FP64. Synchronises the stream (reads back the task count). *out is
- * released with sphx_tasks_destroy. Calling it again with an existing *out
- * rebuilds in place. */
+ * released with sphx_tasks_destroy (on the stream of its last build, which must
+ * still exist). Calling it again with an existing *out rebuilds in place. */
 sphx_status sphx_tasks_build(sphx_ctx *ctx, sphx_grid *grid, const sphx_particles *in,
                              void *stream, sphx_tasks **out);
 void sphx_tasks_destroy(sphx_tasks *tasks);

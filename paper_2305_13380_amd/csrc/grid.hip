@@ -323,12 +323,12 @@ __global__ void k_iter_reset(int64_t n, const int32_t *__restrict__ perm,
 }
 
 template <class T>
-sphx_status dalloc(T **p, size_t count)
+sphx_status dalloc(T **p, size_t count, hipStream_t s)
 {
     *p = nullptr;
     if (count == 0)
         count = 1;
-    SPHX_HIP(hipMalloc((void **)p, count * sizeof(T)));
+    SPHX_HIP(dmalloc((void **)p, count * sizeof(T), s));
     return SPHX_OK;
 }
 
@@ -356,8 +356,7 @@ void grid_free(sphx_grid *g)
                     g->node_hi, g->node_r,   g->fsum,     g->sort_tmp, g->keys_in, g->idx_in,
                     g->flags,   g->d_status, g->hs,       g->d0,       g->d1};
     for (void *p : ptrs)
-        if (p)
-            (void)hipFree(p);
+        dfree(p, g->stream);
     delete g;
 }
 
@@ -388,6 +387,7 @@ sphx_status grid_build(sphx_ctx *ctx, const sphx_particles *in, hipStream_t s, s
     sphx_grid *g = new sphx_grid();
     *out = nullptr;
     g->ctx = ctx;
+    g->stream = s;
     g->n = n;
     struct Guard {
         sphx_grid *g;
@@ -399,28 +399,28 @@ sphx_status grid_build(sphx_ctx *ctx, const sphx_particles *in, hipStream_t s, s
         }
     } guard{g};
 
-    SPHX_TRY(dalloc(&g->d_status, 4));
+    SPHX_TRY(dalloc(&g->d_status, 4, s));
     SPHX_HIP(hipMemsetAsync(g->d_status, 0, 4 * sizeof(int32_t), s));
-    SPHX_TRY(dalloc(&g->keys, n));
-    SPHX_TRY(dalloc(&g->keys_in, n));
-    SPHX_TRY(dalloc(&g->perm, n));
-    SPHX_TRY(dalloc(&g->idx_in, n));
-    SPHX_TRY(dalloc(&g->leaf_of, n));
-    SPHX_TRY(dalloc(&g->flags, 2 * n));
-    SPHX_TRY(dalloc(&g->q0, n));
-    SPHX_TRY(dalloc(&g->q1, n));
-    SPHX_TRY(dalloc(&g->qa, n));
-    SPHX_TRY(dalloc(&g->need, n));
-    SPHX_TRY(dalloc(&g->g0, n));
-    SPHX_TRY(dalloc(&g->g1, n));
-    SPHX_TRY(dalloc(&g->hs, n));
-    SPHX_TRY(dalloc(&g->d0, n));
-    SPHX_TRY(dalloc(&g->d1, n));
+    SPHX_TRY(dalloc(&g->keys, n, s));
+    SPHX_TRY(dalloc(&g->keys_in, n, s));
+    SPHX_TRY(dalloc(&g->perm, n, s));
+    SPHX_TRY(dalloc(&g->idx_in, n, s));
+    SPHX_TRY(dalloc(&g->leaf_of, n, s));
+    SPHX_TRY(dalloc(&g->flags, 2 * n, s));
+    SPHX_TRY(dalloc(&g->q0, n, s));
+    SPHX_TRY(dalloc(&g->q1, n, s));
+    SPHX_TRY(dalloc(&g->qa, n, s));
+    SPHX_TRY(dalloc(&g->need, n, s));
+    SPHX_TRY(dalloc(&g->g0, n, s));
+    SPHX_TRY(dalloc(&g->g1, n, s));
+    SPHX_TRY(dalloc(&g->hs, n, s));
+    SPHX_TRY(dalloc(&g->d0, n, s));
+    SPHX_TRY(dalloc(&g->d1, n, s));
 
     if (n == 0) {
         g->n_leaves = 0;
         g->n_levels = 0;
-        SPHX_TRY(dalloc(&g->leaf_start, 1));
+        SPHX_TRY(dalloc(&g->leaf_start, 1, s));
         SPHX_HIP(hipMemsetAsync(g->leaf_start, 0, sizeof(int32_t), s));
         guard.keep = true;
         *out = g;
@@ -441,7 +441,7 @@ sphx_status grid_build(sphx_ctx *ctx, const sphx_particles *in, hipStream_t s, s
     SPHX_HIP(rocprim::inclusive_scan(nullptr, tmp2, g->flags, g->flags + n, size_t(n),
                                      rocprim::plus<uint32_t>(), s));
     g->sort_tmp_bytes = tmp > tmp2 ? tmp : tmp2;
-    SPHX_HIP(hipMalloc(&g->sort_tmp, g->sort_tmp_bytes));
+    SPHX_HIP(dmalloc(&g->sort_tmp, g->sort_tmp_bytes, s));
     SPHX_HIP(rocprim::radix_sort_pairs(g->sort_tmp, tmp, g->keys_in, g->keys, g->idx_in, g->perm,
                                        size_t(n), 0, 63, s));
 
@@ -453,23 +453,24 @@ sphx_status grid_build(sphx_ctx *ctx, const sphx_particles *in, hipStream_t s, s
     // Octree leaves -> parents -> packed cells. flags[0, n) holds the leaf
     // starts, flags[n, 2n) their inclusive scan; the cell starts then reuse
     // flags[0, n) (cleared first) and their scan flags[n, 2n).
-    SPHX_TRY(dalloc(&g->leaf_start, n + 1));
+    SPHX_TRY(dalloc(&g->leaf_start, n + 1, s));
     int32_t *par_lvl = nullptr;
     uint64_t *par_pfx = nullptr;
-    SPHX_TRY(dalloc(&par_lvl, n));
-    if (hipMalloc(&par_pfx, size_t(n) * sizeof(uint64_t)) != hipSuccess) {
-        (void)hipFree(par_lvl);
+    SPHX_TRY(dalloc(&par_lvl, n, s));
+    if (dmalloc((void **)&par_pfx, size_t(n) * sizeof(uint64_t), s) != hipSuccess) {
+        dfree(par_lvl, s);
         set_error("sphx_grid_build: out of device memory");
         return SPHX_E_OOM;
     }
     struct Tmp {
         void *a, *b;
+        hipStream_t s;
         ~Tmp()
         {
-            (void)hipFree(a);
-            (void)hipFree(b);
+            dfree(a, s);
+            dfree(b, s);
         }
-    } tmp_guard{par_lvl, par_pfx};
+    } tmp_guard{par_lvl, par_pfx, s};
     k_oct_index<<<blocks(n, 256), 256, 0, s>>>(n, g->flags, g->flags + n, g->leaf_start,
                                                g->d_status + 2);
     SPHX_HIP(hipGetLastError());
@@ -515,11 +516,11 @@ sphx_status grid_build(sphx_ctx *ctx, const sphx_particles *in, hipStream_t s, s
     }
     g->n_levels = lev;
     g->n_nodes = off;
-    SPHX_TRY(dalloc(&g->leaf_org, 3 * nl));
-    SPHX_TRY(dalloc(&g->node_lo, 3 * off));
-    SPHX_TRY(dalloc(&g->node_hi, 3 * off));
-    SPHX_TRY(dalloc(&g->node_r, off));
-    SPHX_TRY(dalloc(&g->fsum, 6 * nl));
+    SPHX_TRY(dalloc(&g->leaf_org, 3 * nl, s));
+    SPHX_TRY(dalloc(&g->node_lo, 3 * off, s));
+    SPHX_TRY(dalloc(&g->node_hi, 3 * off, s));
+    SPHX_TRY(dalloc(&g->node_r, off, s));
+    SPHX_TRY(dalloc(&g->fsum, 6 * nl, s));
 
     k_leaf_setup<<<unsigned(nl), 64, 0, s>>>(nl, g->leaf_start, g->perm, in->x, in->y, in->z,
                                              in->vx, in->vy, in->vz, in->m, in->u, in->alpha_v,

@@ -82,6 +82,7 @@ struct sphx_ctx {
 
 struct sphx_grid {
     sphx_ctx *ctx;
+    hipStream_t stream;  // the stream the grid was built on (its memory is freed there)
     int64_t n;
     int64_t n_leaves;
     int n_levels;
@@ -126,6 +127,7 @@ struct sphx_grid {
 
 struct sphx_tasks {
     sphx_grid *grid;
+    hipStream_t stream;  // the stream of the last build (its memory is freed there)
     int64_t n_tasks;
     int64_t cap;
     int32_t *off;       // n_leaves + 1
@@ -178,5 +180,18 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t nblocks_padded)
 }
 
 inline int64_t pad8(int64_t n) { return (n + 7) & ~int64_t(7); }
+
+// Grids and task lists allocate their workspace stream-ordered on the stream
+// they are built on (no device-wide synchronisation, so requests built on
+// different streams overlap) and release it on that stream.
+inline hipError_t dmalloc(void **p, size_t bytes, hipStream_t s)
+{
+    return hipMallocAsync(p, bytes ? bytes : 16, s);
+}
+inline void dfree(void *p, hipStream_t s)
+{
+    if (p)
+        (void)hipFreeAsync(p, s);
+}
 
 }  // namespace sphx

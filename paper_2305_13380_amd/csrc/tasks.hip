@@ -359,8 +359,7 @@ void tasks_free(sphx_tasks *t)
         return;
     void *ptrs[] = {t->off, t->task, t->count, t->radius, t->scan_tmp, t->overflow};
     for (void *p : ptrs)
-        if (p)
-            (void)hipFree(p);
+        dfree(p, t->stream);
     delete t;
 }
 
@@ -373,26 +372,29 @@ sphx_status tasks_build(sphx_ctx *ctx, sphx_grid *g, const sphx_particles *in, h
         set_error("sphx_tasks_build: task list belongs to another grid");
         return SPHX_E_STATE;
     }
+    if (t)
+        t->stream = s;
     bool fresh = false;
     if (!t) {
         t = new sphx_tasks();
         t->grid = g;
+        t->stream = s;
         fresh = true;
         auto fail = [&](sphx_status st) {
             tasks_free(t);
             return st;
         };
-        if (hipMalloc(&t->off, (nl + 1) * sizeof(int32_t)) != hipSuccess ||
-            hipMalloc(&t->count, (nl + 1) * sizeof(int32_t)) != hipSuccess ||
-            hipMalloc(&t->radius, (nl + 1) * sizeof(float)) != hipSuccess ||
-            hipMalloc(&t->overflow, (nl + 1) * sizeof(uint8_t)) != hipSuccess) {
+        if (dmalloc((void **)&t->off, (nl + 1) * sizeof(int32_t), s) != hipSuccess ||
+            dmalloc((void **)&t->count, (nl + 1) * sizeof(int32_t), s) != hipSuccess ||
+            dmalloc((void **)&t->radius, (nl + 1) * sizeof(float), s) != hipSuccess ||
+            dmalloc((void **)&t->overflow, (nl + 1) * sizeof(uint8_t), s) != hipSuccess) {
             set_error("sphx_tasks_build: out of device memory");
             return fail(SPHX_E_OOM);
         }
         size_t tmp = 0;
         if (rocprim::exclusive_scan(nullptr, tmp, t->count, t->off, 0, size_t(nl + 1),
                                     rocprim::plus<int32_t>(), s) != hipSuccess ||
-            hipMalloc(&t->scan_tmp, tmp + 16) != hipSuccess) {
+            dmalloc(&t->scan_tmp, tmp + 16, s) != hipSuccess) {
             set_error("sphx_tasks_build: scan workspace");
             return fail(SPHX_E_OOM);
         }
@@ -459,11 +461,10 @@ sphx_status tasks_build(sphx_ctx *ctx, sphx_grid *g, const sphx_particles *in, h
         return SPHX_E_INVALID;
     }
     if (int64_t(total) > t->cap) {
-        if (t->task)
-            SPHX_HIP(hipFree(t->task));
+        dfree(t->task, s);
         t->task = nullptr;
         int64_t cap = int64_t(total) + int64_t(total) / 4 + 64;
-        SPHX_HIP(hipMalloc(&t->task, size_t(cap) * sizeof(Task)));
+        SPHX_HIP(dmalloc((void **)&t->task, size_t(cap) * sizeof(Task), s));
         t->cap = cap;
     }
     t->n_tasks = total;

@@ -76,6 +76,11 @@ def _load():
         return _LIB
     if not os.path.exists(LIB_PATH):
         raise ImportError("libsphx.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+    # torch ships its own HIP runtime under the same soname. Loading torch
+    # first makes the loader bind the library to that runtime, so the streams
+    # and memory torch hands over belong to the runtime the library calls;
+    # loaded the other way round the process would hold two HIP runtimes.
+    import torch  # noqa: F401
     L = C.CDLL(LIB_PATH)
     vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
     P = C.POINTER

@@ -77,3 +77,18 @@ def test_null_arguments_are_errors(sphx):
     assert sphx.lib.sphx_grid_build(None, None, None, None) == sphx.E_INVALID
     assert sphx.lib.sphx_step(None, None, None, None, None, None, None, None, None,
                               None) == sphx.E_INVALID
+
+
+def test_one_hip_runtime_in_the_process(sphx):
+    """Importing the binding alone leaves exactly one HIP runtime mapped (the
+    one torch's streams and allocations belong to)."""
+    import subprocess
+    import sys
+    code = ("from paper_2305_13380_amd import sphx\n"
+            "maps = open('/proc/self/maps').read().splitlines()\n"
+            "print(sorted(set(l.split()[-1] for l in maps if 'libamdhip64' in l)))\n")
+    out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True,
+                         timeout=300, check=True).stdout.strip()
+    import ast
+    paths = ast.literal_eval(out)
+    assert len(paths) == 1, paths
