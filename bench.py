@@ -99,40 +99,6 @@ def cpu_baseline(ps, params_cls, n_recv, seed=0):
                           len(recv), nd - len(recv), tot_d, tot_f, dt)}
 
 
-def replay_density_units(sphx, ctx, grid, tasks, dp, out, h0):
-    """Re-run one step pass by pass through the C-ABI (same decisions as
-    sphx_step) and return, per density launch, the interactions it computed:
-    the neighbour counts of the particles it processed. The step is
-    deterministic, so these are the units of every timed step's launches."""
-    import torch
-    n = dp.n
-    dp.t["h"].copy_(h0)
-    sphx.iter_reset(ctx, grid, dp)
-    out.g["converged"].zero_()
-    act = dp.t["active"].bool() if dp.t["active"] is not None else torch.ones(
-        n, dtype=torch.bool, device=dp.t["h"].device)
-    units = []
-    max_iter = ctx.params.max_iter
-    p = 0
-    while p < max_iter:
-        processed = act & (out.g["converged"] == 0)
-        out.counters.zero_()
-        sphx.density(ctx, grid, tasks, dp, out)
-        final = p + 1 == max_iter
-        sphx.ghost(ctx, grid, tasks, dp, out, final_pass=final)
-        c = out.counters.cpu().numpy()
-        units.append(int(out.d["nngb"][processed].to(torch.int64).sum()))
-        if c[3] > 0:
-            tasks.build(dp)
-            continue
-        p += 1
-        if c[0] == 0 or final:
-            break
-        if c[1] > 0:
-            tasks.build(dp)
-    return units
-
-
 def serving_bench(slots, n_req, seed=4):
     """The serving stream: n_req independent periodic boxes (N log-uniform in
     [1e3, 1e6], lattice or lognormal by a seeded coin) with inputs resident in
@@ -306,9 +272,12 @@ def main():
     ms_step = t_ev / args.steps * 1e3
     dens_ms, dens_n = ctx.profile_read(0)
     force_ms, force_n = ctx.profile_read(1)
-    log("bench: %d steps in %.3f s (events) / %.3f s (wall); density kernel %.2f ms over %d "
-        "launches, force kernel %.2f ms over %d launches" % (
-            args.steps, t_ev, wall, dens_ms, dens_n, force_ms, force_n))
+    dlist_ms, dlist_n = ctx.profile_read(2)
+    build_ms, build_n = ctx.profile_read(3)
+    log("bench: %d steps in %.3f s (events) / %.3f s (wall); cell-pair density %.2f ms over %d "
+        "launches, list density %.2f ms over %d, list build %.2f ms over %d, force %.2f ms "
+        "over %d" % (args.steps, t_ev, wall, dens_ms, dens_n, dlist_ms, dlist_n, build_ms,
+                     build_n, force_ms, force_n))
 
     nngb = out.d["nngb"].to(torch.int64)
     nf = out.f["nforce"].to(torch.int64)
@@ -325,21 +294,19 @@ def main():
     mom = float(np.abs(sums[:3]).max() / max(sums[4], 1e-300))
     en = float(abs(sums[3]) / max(sums[4] + sums[5], 1e-300))
 
-    # Algorithmic FLOP rates of the two neighbour-loop kernels: interactions
-    # each launch computes times the FLOPs per interaction, over the kernel's
-    # own event-timed duration in the timed steps.
-    units = replay_density_units(sphx, ctx, grid, tasks, dp, out, h0)
-    dens_flops_step = sum(units) * FLOP_DENSITY
-    dens_ms_step = dens_ms / args.steps
-    force_ms_step = force_ms / args.steps
-    dens_rate = dens_flops_step / (dens_ms_step / 1e3) / 1e12
-    force_rate = n_force * FLOP_FORCE / (force_ms_step / 1e3) / 1e12
-    if dens_ms_step >= force_ms_step:
-        kern, achieved = "k_density", dens_rate
-        per_launch = dens_flops_step / max(len(units), 1)
-    else:
-        kern, achieved = "k_force", force_rate
-        per_launch = n_force * FLOP_FORCE
+    # Algorithmic FLOP rates of the neighbour-loop kernels: the interactions
+    # each computes per step (the step is deterministic, so every timed step
+    # computes the same) times the FLOPs per interaction, over the kernel's own
+    # event-timed duration per step.
+    S = args.steps
+    kern_units = {"k_density": (info.pairs_cellpair * FLOP_DENSITY, dens_ms / S, dens_n / S),
+                  "k_dens_list": (info.pairs_list * FLOP_DENSITY, dlist_ms / S, dlist_n / S),
+                  "k_force": (n_force * FLOP_FORCE, force_ms / S, force_n / S)}
+    rates = {k: (f / (ms / 1e3) / 1e12 if ms > 0 else 0.0) for k, (f, ms, _) in kern_units.items()}
+    kern = max(kern_units, key=lambda k: kern_units[k][1])
+    flops_step, _, launches_step = kern_units[kern]
+    achieved = rates[kern]
+    per_launch = flops_step / max(launches_step, 1)
     passes = sorted(set(p for p, _, _ in infos))
     line = {
         "metric": "SPH pair interactions/s (density+force) at 1 GPU",
@@ -361,11 +328,15 @@ def main():
                    "task_rebuilds_per_step": infos[-1][1], "unconverged": infos[-1][2],
                    "n_leaves": grid.n_leaves, "n_tasks": tasks.count,
                    "grid_build_ms": t_grid * 1e3, "tasks_build_ms": t_tasks * 1e3,
-                   "density_kernel_ms_per_step": dens_ms / args.steps,
-                   "force_kernel_ms_per_step": force_ms / args.steps,
-                   "momentum_err_rel": mom, "energy_err_rel": en,
-                   "density_interactions_per_launch": units,
-                   "density_tflops": dens_rate, "force_tflops": force_rate},
+                   "kernel_ms_per_step": {"k_density": dens_ms / S, "k_dens_list": dlist_ms / S,
+                                          "k_list_build": build_ms / S, "k_force": force_ms / S},
+                   "kernel_tflops": rates,
+                   "density_pairs_per_step": {"cell_pair": info.pairs_cellpair,
+                                              "list": info.pairs_list},
+                   "list_builds_per_step": info.list_builds,
+                   "list_fallback_receiver_passes": info.list_fallback,
+                   "list_entries": info.list_entries,
+                   "momentum_err_rel": mom, "energy_err_rel": en},
         "roofline": {"bound": "alu", "kernel": kern, "achieved": achieved,
                      "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS,

@@ -74,7 +74,9 @@ typedef struct sphx_params {
     double eps_balsara; /* Balsara switch regulariser (Section 3.2: 1e-4) */
     double skin;        /* relative enlargement of task search radii (default 0.1) */
     int32_t leaf_max;   /* particles per leaf cell, 8..64 (default 64) */
-    int32_t reserved;
+    int32_t neighbour_lists; /* sphx_step: 1 reuses per-receiver neighbour lists within
+                                radius (1 + skin) H over the passes after the first; 0
+                                (default) runs the cell-pair loop in every pass */
 } sphx_params;
 
 /* Particle-carried inputs (Section 3.1): positions FP64, the rest FP32. */
@@ -126,6 +128,12 @@ typedef struct sphx_step_info {
     int32_t clamped;           /* particles at h_max */
     int64_t n_leaves;
     int64_t n_tasks;
+    int32_t list_builds;       /* neighbour-list builds during the iteration */
+    int32_t list_fallback;     /* receiver passes that outgrew their list (cell-pair loop) */
+    int64_t list_entries;      /* entries of the last list build (with block padding) */
+    int64_t pairs_cellpair;    /* density interactions (self excluded) computed by the
+                                  cell-pair loop over all passes */
+    int64_t pairs_list;        /* ... and by the neighbour-list loop */
 } sphx_step_info;
 
 typedef struct sphx_ctx sphx_ctx;
@@ -230,8 +238,10 @@ sphx_status sphx_step(sphx_ctx *ctx, sphx_grid *grid, sphx_tasks **tasks, sphx_p
 
 /* Kernel timing for measurement tools. sphx_profile_enable(ctx, 1) clears the
  * statistics and starts recording a pair of HIP events around every launch of
- * the density kernel (kernel 0) and the force kernel (kernel 1), on the
- * stream the kernel is launched on; 0 stops recording. sphx_profile_read
+ * the cell-pair density kernel (kernel 0), the force kernel (kernel 1), the
+ * list density kernel (kernel 2) and the neighbour-list build (kernel 3: its
+ * counting pass with the offset scan, and its filling pass), on the stream
+ * the kernel is launched on; 0 stops recording. sphx_profile_read
  * waits for the recorded events and returns the summed kernel time in
  * milliseconds and the number of launches since the last enable. */
 sphx_status sphx_profile_enable(sphx_ctx *ctx, int32_t enable);

@@ -108,6 +108,7 @@ void sphx_params_default(sphx_params *p)
     p->beta_v = 3.0;
     p->eps_balsara = 1e-4;
     p->skin = 0.1;
+    p->neighbour_lists = 0;
     p->leaf_max = 64;
 }
 
@@ -145,7 +146,7 @@ sphx_status sphx_ctx_create(const sphx_params *p, int hip_device, sphx_ctx **out
     double lmin = fmin(p->box[0], fmin(p->box[1], p->box[2]));
     double auto_max = lmin / (3.0 * p->gamma_k) * (1.0 - 1e-6);
     c->h_max = p->h_max > 0.0 ? fmin(p->h_max, auto_max) : auto_max;
-    if (hipMalloc(&c->d_counters, SPHX_COUNTERS * sizeof(int32_t)) != hipSuccess ||
+    if (hipMalloc(&c->d_counters, kStepCounterBytes) != hipSuccess ||
         hipMalloc(&c->d_sums, 8 * sizeof(double)) != hipSuccess) {
         (void)hipFree(c->d_counters);
         delete c->prof;
@@ -174,10 +175,9 @@ void sphx_ctx_destroy(sphx_ctx *ctx)
 
 size_t sphx_workspace_bytes(const sphx_params *p, int64_t n)
 {
-    (void)p;
     if (n < 0)
         return 0;
-    return grid_bytes(n) + tasks_bytes(n);
+    return grid_bytes(n) + tasks_bytes(n) + ((p && p->neighbour_lists == 0) ? 0 : lists_bytes(n));
 }
 
 sphx_status sphx_grid_build(sphx_ctx *ctx, const sphx_particles *in, void *stream,
@@ -232,7 +232,7 @@ sphx_status sphx_density(sphx_ctx *ctx, const sphx_grid *grid, const sphx_tasks 
     }
     // the caller may have changed h since the last pass
     SPHX_TRY(refresh_h(const_cast<sphx_grid *>(grid), in, as_stream(stream)));
-    return density_launch(ctx, grid, tasks, in, out, d_counters, as_stream(stream));
+    return density_launch(ctx, grid, tasks, in, out, d_counters, false, as_stream(stream));
 }
 
 sphx_status sphx_ghost(sphx_ctx *ctx, sphx_grid *grid, const sphx_tasks *tasks,
@@ -247,7 +247,7 @@ sphx_status sphx_ghost(sphx_ctx *ctx, sphx_grid *grid, const sphx_tasks *tasks,
         set_error("sphx_ghost: NULL task list, density or output array");
         return SPHX_E_INVALID;
     }
-    return ghost_launch(ctx, grid, tasks, in, dens, out, d_counters, final_pass,
+    return ghost_launch(ctx, grid, tasks, in, dens, out, d_counters, final_pass, false, nullptr,
                         as_stream(stream));
 }
 
@@ -284,17 +284,32 @@ sphx_status sphx_step(sphx_ctx *ctx, sphx_grid *grid, sphx_tasks **tasks, sphx_p
     if (!*tasks)
         SPHX_TRY(tasks_build(ctx, grid, in, s, tasks));
     SPHX_TRY(iter_reset(grid, in, s));
-    int32_t h_counters[SPHX_COUNTERS] = {0, 0, 0, 0};
+    alignas(8) unsigned char h_buf[kStepCounterBytes];
+    int32_t h_counters[kStepCounters] = {0, 0, 0, 0, 0, 0, 0, 0};
     int32_t *dc = ctx->d_counters;
+    unsigned long long *d_units =
+        reinterpret_cast<unsigned long long *>(reinterpret_cast<char *>(dc) + kStepUnitsOffset);
+    SPHX_HIP(hipMemsetAsync(d_units, 0, 2 * sizeof(unsigned long long), s));
     const int max_iter = ctx->p.max_iter;
+    bool want_lists = ctx->p.neighbour_lists != 0;
+    // lists: the neighbour lists are current (built on this task list, for
+    // the receivers of the current pass); beyond: receivers of the next pass
+    // whose H outgrew their list (they take the cell-pair loop).
+    bool lists = false;
+    int64_t beyond = 0;
     int pass = 0, stale_repeats = 0;
     while (pass < max_iter) {
-        SPHX_HIP(hipMemsetAsync(dc, 0, SPHX_COUNTERS * sizeof(int32_t), s));
-        SPHX_TRY(density_launch(ctx, grid, *tasks, in, dens, dc, s));
+        SPHX_HIP(hipMemsetAsync(dc, 0, kStepCounters * sizeof(int32_t), s));
+        if (!lists || beyond > 0)
+            SPHX_TRY(density_launch(ctx, grid, *tasks, in, dens, dc, lists, s));
+        if (lists)
+            SPHX_TRY(density_list_launch(ctx, grid, *tasks, dens, s));
         const int final_pass = (pass + 1 == max_iter) ? 1 : 0;
-        SPHX_TRY(ghost_launch(ctx, grid, *tasks, in, dens, gst, dc, final_pass, s));
-        SPHX_HIP(hipMemcpyAsync(h_counters, dc, sizeof(h_counters), hipMemcpyDeviceToHost, s));
+        SPHX_TRY(ghost_launch(ctx, grid, *tasks, in, dens, gst, dc, final_pass, lists, d_units,
+                              s));
+        SPHX_HIP(hipMemcpyAsync(h_buf, dc, kStepCounterBytes, hipMemcpyDeviceToHost, s));
         SPHX_HIP(hipStreamSynchronize(s));
+        memcpy(h_counters, h_buf, sizeof(h_counters));
         if (h_counters[3] > 0) {
             // The pass ran on a stale task list and the ghost skipped it.
             if (++stale_repeats > 4) {
@@ -303,6 +318,7 @@ sphx_status sphx_step(sphx_ctx *ctx, sphx_grid *grid, sphx_tasks **tasks, sphx_p
             }
             SPHX_TRY(tasks_build(ctx, grid, in, s, tasks));
             local.task_rebuilds++;
+            lists = false;
             continue;
         }
         ++pass;
@@ -316,9 +332,32 @@ sphx_status sphx_step(sphx_ctx *ctx, sphx_grid *grid, sphx_tasks **tasks, sphx_p
         if (h_counters[1] > 0) {
             SPHX_TRY(tasks_build(ctx, grid, in, s, tasks));
             local.task_rebuilds++;
+            lists = false;  // list entries name tasks of the old list
+        }
+        beyond = lists ? h_counters[4] : 0;
+        if (lists)
+            local.list_fallback += h_counters[4];
+        // (Re)build the lists after the first pass, after a task rebuild, and
+        // when many receivers have outgrown theirs.
+        if (want_lists && (!lists || beyond > h_counters[0] / 4)) {
+            bool ok = false;
+            SPHX_TRY(list_build(ctx, grid, *tasks, s, &ok));
+            lists = ok;
+            want_lists = ok;  // no memory or too many tasks: cell-pair loop from here on
+            beyond = 0;
+            if (ok) {
+                local.list_builds++;
+                local.list_entries = grid->lst_total;
+            }
         }
     }
     local.passes = pass;
+    {
+        unsigned long long u[2];
+        memcpy(u, h_buf + kStepUnitsOffset, sizeof(u));
+        local.pairs_cellpair = int64_t(u[0]);
+        local.pairs_list = int64_t(u[1]);
+    }
     SPHX_TRY(sphx_force(ctx, grid, *tasks, in, dens, gst, out, d_sums6, stream));
     local.n_leaves = grid->n_leaves;
     local.n_tasks = (*tasks)->n_tasks;
@@ -340,13 +379,14 @@ sphx_status sphx_profile_enable(sphx_ctx *ctx, int32_t enable)
     }
     ctx->prof->on = enable != 0;
     if (enable)
-        ctx->prof->used[0] = ctx->prof->used[1] = 0;
+        for (int k = 0; k < Profiler::kKinds; ++k)
+            ctx->prof->used[k] = 0;
     return SPHX_OK;
 }
 
 sphx_status sphx_profile_read(sphx_ctx *ctx, int32_t kernel, double *total_ms, int64_t *launches)
 {
-    if (!ctx || kernel < 0 || kernel > 1 || !total_ms || !launches) {
+    if (!ctx || kernel < 0 || kernel >= Profiler::kKinds || !total_ms || !launches) {
         set_error("sphx_profile_read: invalid argument");
         return SPHX_E_INVALID;
     }

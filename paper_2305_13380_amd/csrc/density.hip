@@ -1,10 +1,15 @@
 // Density pass (Section 3.1): number density, mass density, their
 // h-derivatives, neighbour count, and the velocity divergence and curl sums.
-// The loop structure (cull, candidate buffer, per-lane lists) is described in
-// pairs.h. A block of NW waves serves one receiving cell: wave w takes the
-// w-th contiguous share of the cell's tasks, and the shares' partial sums are
-// added in wave order at the end (a fixed order, so results stay
-// reproducible).
+//
+// Two loops compute the same sums:
+// * k_density, over cell pairs: the loop structure (cull, candidate buffer,
+//   per-lane lists) is described in pairs.h. A block of NW waves serves one
+//   receiving cell: wave w takes the w-th contiguous share of the cell's
+//   tasks, and the shares' partial sums are added in wave order at the end (a
+//   fixed order, so results stay reproducible).
+// * k_dens_list, over per-receiver neighbour lists (built by lists.hip for the
+//   later passes of the h iteration): one lane per receiver, 64 consecutive
+//   receivers per wave, each lane walking its own list in its fixed order.
 #include "pairs.h"
 
 namespace sphx {
@@ -12,17 +17,89 @@ namespace {
 
 constexpr int kSums = 9;  // Sw, Smw, Sud, Smud, Sdiv, Scx, Scy, Scz, count
 
+// Where a receiver's results go: the caller's arrays (caller order) and the
+// sorted-order state the ghost reads.
+struct DensOut {
+    float *rho, *rho_dh, *n, *n_dh, *div, *cx, *cy, *cz;
+    int32_t *nngb;
+    float4 *d0, *d1;
+};
+
+// Contributions of one directed pair; p and v are the source's position (in
+// the receiver's frame) and mass, and its velocity. u = r / H. With on =
+// false the pair adds nothing (its inputs must be finite): the loops evaluate
+// several list entries at once without branching.
+__device__ __forceinline__ void dens_pair(float (&S)[kSums], const float4 &pi, const float4 &vi,
+                                          float invH, const float4 &p, const float4 &v, bool on)
+{
+    const float dx = pi.x - p.x, dy = pi.y - p.y, dz = pi.z - p.z;
+    const float r2 = dx * dx + dy * dy + dz * dz;
+    const float u = fast_sqrt(r2) * invH;
+    const float t1u = 1.0f - u;
+    const float t2 = t1u * t1u;
+    const float t3 = t2 * t1u;
+    const float wk = on ? t2 * t2 * (1.0f + 4.0f * u) : 0.0f;
+    const float ud = on ? u * u * t3 : 0.0f;
+    S[0] += wk;
+    S[1] += p.w * wk;
+    S[2] += ud;
+    S[3] += p.w * ud;
+    S[8] += on ? 1.0f : 0.0f;
+    const float dvx = v.x - vi.x, dvy = v.y - vi.y, dvz = v.z - vi.z;
+    const float mt3 = on ? p.w * t3 : 0.0f;
+    S[4] += mt3 * (dvx * dx + dvy * dy + dvz * dz);
+    S[5] += mt3 * (dy * dvz - dz * dvy);
+    S[6] += mt3 * (dz * dvx - dx * dvz);
+    S[7] += mt3 * (dx * dvy - dy * dvx);
+}
+
+// A receiver's results from its sums. Its own particle went through the loop
+// as a pair at r = 0: it contributes W(0) to n and rho and nothing to the
+// gradient sums; it is not a neighbour.
+__device__ __forceinline__ void dens_finish(const float (&S)[kSums], float hi, float invH,
+                                            int64_t s, int32_t gi, const DensOut &o)
+{
+    const float Sw = S[0];
+    const float Smw = S[1];
+    // W = kW H^-3 (1-u)^4 (1+4u); dW/dh = -(H^-3/h)(3 kW w - kD u^2 (1-u)^3);
+    // grad_i W = (dW/dr / r) x_ij with dW/dr / r = -kD H^-5 (1-u)^3.
+    const float invH3 = invH * invH * invH;
+    const float invH5 = invH3 * invH * invH;
+    const float ih = fast_rcp(hi);
+    const float n_ = kW * invH3 * Sw;
+    const float rho = kW * invH3 * Smw;
+    const float n_dh = -invH3 * ih * (3.0f * kW * Sw - kD * S[2]);
+    const float rho_dh = -invH3 * ih * (3.0f * kW * Smw - kD * S[3]);
+    const float dv = -kD * invH5 * S[4];
+    const float cx = -kD * invH5 * S[5];
+    const float cy = -kD * invH5 * S[6];
+    const float cz = -kD * invH5 * S[7];
+    // For the ghost, the two ratios it needs in a form free of cancellation:
+    // G' = 3 + h n'/n = kD Sud / (kW Sw) and 1 + h rho'/(3 rho) = kD Smud /
+    // (3 kW Smw) (the self term cancels exactly in both).
+    const float gp = (kD * S[2]) / (kW * Sw);
+    const float fden = (kD * S[3]) / (3.0f * kW * Smw);
+    o.d0[s] = make_float4(n_, gp, rho, fden);
+    o.d1[s] = make_float4(dv, cx, cy, cz);
+    o.n[gi] = n_;
+    o.rho[gi] = rho;
+    o.n_dh[gi] = n_dh;
+    o.rho_dh[gi] = rho_dh;
+    o.div[gi] = dv;
+    o.cx[gi] = cx;
+    o.cy[gi] = cy;
+    o.cz[gi] = cz;
+    o.nngb[gi] = int32_t(S[8]) - 1;
+}
+
 template <int CAP, int NW>
 __global__ __launch_bounds__(64 * NW) void k_density(
     int64_t n_leaves, int64_t nb_padded, const int32_t *__restrict__ leaf_start,
     const int32_t *__restrict__ perm, const float4 *__restrict__ q0,
     const float4 *__restrict__ q1, const uint8_t *__restrict__ need, const float *__restrict__ hs,
     const float *__restrict__ radius, const int32_t *__restrict__ toff,
-    const Task *__restrict__ task, float gamma_k, float *__restrict__ o_rho,
-    float *__restrict__ o_rho_dh, float *__restrict__ o_n, float *__restrict__ o_n_dh,
-    float *__restrict__ o_div, float *__restrict__ o_cx, float *__restrict__ o_cy,
-    float *__restrict__ o_cz, int32_t *__restrict__ o_nngb, float4 *__restrict__ d0,
-    float4 *__restrict__ d1, int32_t *__restrict__ counters)
+    const Task *__restrict__ task, float gamma_k, const float *__restrict__ lrad, DensOut o,
+    int32_t *__restrict__ counters)
 {
     const int64_t L = xcd_remap(blockIdx.x, nb_padded);
     if (L >= n_leaves)
@@ -33,7 +110,9 @@ __global__ __launch_bounds__(64 * NW) void k_density(
     const int32_t cnt = leaf_start[L + 1] - s0;
     const bool valid = lane < cnt;
     const int32_t s = s0 + (valid ? lane : 0);
-    const bool act = valid && need[s];
+    const float hi0 = hs[s];
+    // With lists, this loop serves only the receivers whose H outgrew theirs.
+    const bool act = valid && need[s] && (!lrad || gamma_k * hi0 > lrad[s]);
     if (!__any(act))
         return;  // the same for every wave of the block
 
@@ -48,7 +127,7 @@ __global__ __launch_bounds__(64 * NW) void k_density(
     const float4 pi = q0[s];
     const float4 vi = q1[s];
     const int32_t gi = perm[s];
-    const float hi = act ? hs[s] : 1.0f;
+    const float hi = act ? hi0 : 1.0f;
     const float H = gamma_k * hi;
     const float H2 = act ? H * H : -1.0f;
     const float invH = fast_rcp(H);
@@ -72,46 +151,33 @@ __global__ __launch_bounds__(64 * NW) void k_density(
     int nc = 0;   // buffered candidates (wave-uniform)
     int myn = 0;  // this lane's list length (its own particle is listed too)
 
-    auto pair = [&](int c) __attribute__((always_inline)) {
-        const float4 p = cp[c];
-        const float4 v = cv[c];
-        const float dx = pi.x - p.x, dy = pi.y - p.y, dz = pi.z - p.z;
-        const float r2 = dx * dx + dy * dy + dz * dz;
-        const float u = fast_sqrt(r2) * invH;
-        const float t1u = 1.0f - u;
-        const float t2 = t1u * t1u;
-        const float t3 = t2 * t1u;
-        const float wk = t2 * t2 * (1.0f + 4.0f * u);
-        const float ud = u * u * t3;
-        S[0] += wk;
-        S[1] += p.w * wk;
-        S[2] += ud;
-        S[3] += p.w * ud;
-        S[8] += 1.0f;
-        const float dvx = v.x - vi.x, dvy = v.y - vi.y, dvz = v.z - vi.z;
-        const float mt3 = p.w * t3;
-        S[4] += mt3 * (dvx * dx + dvy * dy + dvz * dz);
-        S[5] += mt3 * (dy * dvz - dz * dvy);
-        S[6] += mt3 * (dz * dvx - dx * dvz);
-        S[7] += mt3 * (dx * dvy - dy * dvx);
-    };
+    // Four list entries at a time, without branches: entries past a lane's
+    // list length read slot 0 (a candidate of the current buffer, so finite
+    // data) and add nothing.
     auto compute = [&]() __attribute__((always_inline)) {
         for (int k = 0; __any(k < myn); k += 4) {
             const uint32_t four = *reinterpret_cast<const uint32_t *>(my_list + k);
+            float4 p[4], v[4];
+            bool on[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                on[q] = k + q < myn;
+                const int c = on[q] ? int((four >> (8 * q)) & 0xffu) : 0;
+                p[q] = cp[c];
+                v[q] = cv[c];
+            }
 #pragma unroll
             for (int q = 0; q < 4; ++q)
-                if (k + q < myn)
-                    pair(int((four >> (8 * q)) & 0xffu));
+                dens_pair(S, pi, vi, invH, p[q], v[q], on[q]);
         }
         myn = 0;
     };
+    // The slot is always written; it is kept (the length advanced) only
+    // when the candidate lies inside H.
     auto accept = [&](int c, const float4 &p) __attribute__((always_inline)) {
-        const float dx = pi.x - p.x, dy = pi.y - p.y, dz = pi.z - p.z;
-        const float r2 = dx * dx + dy * dy + dz * dz;
-        if (r2 < H2) {
-            my_list[myn] = uint8_t(c);
-            ++myn;
-        }
+        const float r2 = dist2(pi.x - p.x, pi.y - p.y, pi.z - p.z);
+        my_list[myn] = uint8_t(c);
+        myn += r2 < H2 ? 1 : 0;
     };
     auto flush = [&]() __attribute__((always_inline)) {
         wave_sync();
@@ -209,59 +275,116 @@ __global__ __launch_bounds__(64 * NW) void k_density(
     }
     if (!act)
         return;
-    // The receiver's own particle went through the loop as a pair at r = 0:
-    // it contributes W(0) to n and rho and nothing to the gradient sums; it
-    // is not a neighbour.
-    const float Sw = S[0];
-    const float Smw = S[1];
-    // W = kW H^-3 (1-u)^4 (1+4u); dW/dh = -(H^-3/h)(3 kW w - kD u^2 (1-u)^3);
-    // grad_i W = (dW/dr / r) x_ij with dW/dr / r = -kD H^-5 (1-u)^3.
-    const float invH3 = invH * invH * invH;
-    const float invH5 = invH3 * invH * invH;
-    const float ih = fast_rcp(hi);
-    const float n_ = kW * invH3 * Sw;
-    const float rho = kW * invH3 * Smw;
-    const float n_dh = -invH3 * ih * (3.0f * kW * Sw - kD * S[2]);
-    const float rho_dh = -invH3 * ih * (3.0f * kW * Smw - kD * S[3]);
-    const float dv = -kD * invH5 * S[4];
-    const float cx = -kD * invH5 * S[5];
-    const float cy = -kD * invH5 * S[6];
-    const float cz = -kD * invH5 * S[7];
-    // For the ghost, the two ratios it needs in a form free of cancellation:
-    // G' = 3 + h n'/n = kD Sud / (kW Sw) and 1 + h rho'/(3 rho) = kD Smud /
-    // (3 kW Smw) (the self term cancels exactly in both).
-    const float gp = (kD * S[2]) / (kW * Sw);
-    const float fden = (kD * S[3]) / (3.0f * kW * Smw);
-    d0[s] = make_float4(n_, gp, rho, fden);
-    d1[s] = make_float4(dv, cx, cy, cz);
-    o_n[gi] = n_;
-    o_rho[gi] = rho;
-    o_n_dh[gi] = n_dh;
-    o_rho_dh[gi] = rho_dh;
-    o_div[gi] = dv;
-    o_cx[gi] = cx;
-    o_cy[gi] = cy;
-    o_cz[gi] = cz;
-    o_nngb[gi] = int32_t(S[8]) - 1;
+    dens_finish(S, hi, invH, s, gi, o);
+}
+
+// List pass: lane = receiver s = 64 b + lane of 64-block b. Entries decode to
+// (task, source index in its leaf); the task's offset half gives the source's
+// first sorted index and the FP32 offset into the receiver's frame. Entries
+// lie within the list radius (>= H); the r < H test is redone here, with
+// the same arithmetic as the cell-pair loop.
+__global__ __launch_bounds__(256) void k_dens_list(
+    int64_t n, int64_t nwg_padded, const uint8_t *__restrict__ need,
+    const float *__restrict__ hs, const float *__restrict__ lrad,
+    const int32_t *__restrict__ leaf_of, const int32_t *__restrict__ perm,
+    const int32_t *__restrict__ toff, const Task *__restrict__ task,
+    const float4 *__restrict__ q0, const float4 *__restrict__ q1,
+    const int32_t *__restrict__ lcnt, const int64_t *__restrict__ lboff,
+    const uint32_t *__restrict__ lst, float gamma_k, DensOut o)
+{
+    const int64_t wg = xcd_remap(blockIdx.x, nwg_padded);
+    const int lane = threadIdx.x & 63;
+    const int64_t b = wg * 4 + (threadIdx.x >> 6);
+    const int64_t s_raw = b * 64 + lane;
+    const bool valid = s_raw < n;
+    const int64_t s = valid ? s_raw : 0;
+    const float hi0 = hs[s];
+    const bool act = valid && need[s] && gamma_k * hi0 <= lrad[s];
+    if (!__any(act))
+        return;  // no block-wide barrier in this kernel
+    const int len = act ? lcnt[s] : 0;
+    const float4 pi = q0[s];
+    const float4 vi = q1[s];
+    const float hi = act ? hi0 : 1.0f;
+    const float H = gamma_k * hi;
+    const float H2 = act ? H * H : -1.0f;
+    const float invH = fast_rcp(H);
+    const int32_t ta = act ? toff[leaf_of[s]] : 0;  // task 0 exists whenever n > 0
+    const uint32_t *my = lst + lboff[b] + lane;
+    const float4 *thalf = reinterpret_cast<const float4 *>(task) + 1;  // stride 2
+
+    float S[kSums] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    constexpr int U = 4;
+    for (int k = 0; __any(k < len); k += U) {
+        uint32_t e[U];
+#pragma unroll
+        for (int q = 0; q < U; ++q)
+            e[q] = (k + q < len) ? my[int64_t(k + q) * 64] : 0u;
+        float4 T[U];
+#pragma unroll
+        for (int q = 0; q < U; ++q)
+            T[q] = thalf[2 * int64_t(ta + int32_t(e[q] >> kListCodeShift))];
+        float4 p[U], v[U];
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            const int32_t j = __float_as_int(T[q].w) + int32_t(e[q] & 63u);
+            p[q] = q0[j];
+            v[q] = q1[j];
+        }
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            p[q].x += T[q].x;
+            p[q].y += T[q].y;
+            p[q].z += T[q].z;
+            const float r2 = dist2(pi.x - p[q].x, pi.y - p[q].y, pi.z - p[q].z);
+            dens_pair(S, pi, vi, invH, p[q], v[q], k + q < len && r2 < H2);
+        }
+    }
+    if (!act)
+        return;
+    dens_finish(S, hi, invH, s, perm[s], o);
 }
 
 }  // namespace
 
+static DensOut dens_out(const sphx_grid *g, const sphx_density_out *o)
+{
+    return DensOut{o->rho,    o->rho_dh, o->n,      o->n_dh,  o->div_sum, o->curl_x,
+                   o->curl_y, o->curl_z, o->nngb,   g->d0,    g->d1};
+}
+
 sphx_status density_launch(const sphx_ctx *ctx, const sphx_grid *g, const sphx_tasks *t,
                            const sphx_particles *in, const sphx_density_out *o,
-                           int32_t *counters, hipStream_t s)
+                           int32_t *counters, bool use_lists, hipStream_t s)
 {
     if (g->n_leaves == 0)
         return SPHX_OK;
     const int64_t nbp = pad8(g->n_leaves);
-    constexpr int NW = 2;
+    // One wave per cell measured fastest (the waves of a multi-wave block
+    // would split the cell's tasks, and the per-lane lists get shorter).
+    constexpr int NW = 1;
     SPHX_HIP(ctx->prof->begin(0, s));
     k_density<kCap, NW><<<unsigned(nbp), 64 * NW, 0, s>>>(
         g->n_leaves, nbp, g->leaf_start, g->perm, g->q0, g->q1, g->need, g->hs, t->radius, t->off,
-        t->task, float(ctx->p.gamma_k), o->rho, o->rho_dh, o->n, o->n_dh, o->div_sum, o->curl_x,
-        o->curl_y, o->curl_z, o->nngb, g->d0, g->d1, counters);
+        t->task, float(ctx->p.gamma_k), use_lists ? g->lrad : nullptr, dens_out(g, o), counters);
     SPHX_HIP(hipGetLastError());
     SPHX_HIP(ctx->prof->end(0, s));
+    return SPHX_OK;
+}
+
+sphx_status density_list_launch(const sphx_ctx *ctx, const sphx_grid *g, const sphx_tasks *t,
+                                const sphx_density_out *o, hipStream_t s)
+{
+    if (g->n == 0)
+        return SPHX_OK;
+    const int64_t nwg = (g->n + 255) / 256;
+    const int64_t nwgp = pad8(nwg);
+    SPHX_HIP(ctx->prof->begin(2, s));
+    k_dens_list<<<unsigned(nwgp), 256, 0, s>>>(
+        g->n, nwgp, g->need, g->hs, g->lrad, g->leaf_of, g->perm, t->off, t->task, g->q0, g->q1,
+        g->lcnt, g->lboff, g->lst, float(ctx->p.gamma_k), dens_out(g, o));
+    SPHX_HIP(hipGetLastError());
+    SPHX_HIP(ctx->prof->end(2, s));
     return SPHX_OK;
 }
 

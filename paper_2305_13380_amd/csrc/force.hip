@@ -107,68 +107,69 @@ __global__ __launch_bounds__(64 * NW) void k_force(
     int nc = 0;
     int myn = 0;  // this lane's list length (its own particle is listed too)
 
-    auto pair = [&](int c) __attribute__((always_inline)) {
+    // One listed pair; with on = false (past the lane's list, or its own
+    // particle) it adds nothing: every accumulation is a select, so the
+    // entries need no branches and may hold any data.
+    auto pair = [&](int c, bool listed) __attribute__((always_inline)) {
         const float4 p = cp[c];
         const float dx = pi.x - p.x, dy = pi.y - p.y, dz = pi.z - p.z;
         const float r2 = dx * dx + dy * dy + dz * dz;
-        ++nf;
-        if (r2 > 0.0f) {
-            const float4 v = cv[c];
-            const float4 a = ca[c];
-            const float4 b = cb[c];
-            const float2 c2 = cc[c];
-            const float rinv = fast_rsq(r2);
-            const float r = r2 * rinv;
-            const float ui = r * invHi;
-            const float ti = fmaxf(1.0f - ui, 0.0f);
-            const float gi = -kD * invHi4 * ui * (ti * ti * ti);
-            const float uj = r * a.x;
-            const float tj = fmaxf(1.0f - uj, 0.0f);
-            const float ij2 = a.x * a.x;
-            const float gj = -kD * (ij2 * ij2) * uj * (tj * tj * tj);
-            const float ex = dx * rinv, ey = dy * rinv, ez = dz * rinv;
-            const float dvx = vi.x - v.x, dvy = vi.y - v.y, dvz = vi.z - v.z;
-            const float vdote = dvx * ex + dvy * ey + dvz * ez;
-            const float mu = vdote < 0.0f ? vdote : 0.0f;
-            const float vs = ci + a.y - beta * mu;
-            vsig = fmaxf(vsig, vs);
-            const float alpha = 0.25f * (ai.x + b.w) * (Bi + b.z);
-            const float irs = fast_rcp(rhoi + a.z);
-            const float nu = -2.0f * alpha * mu * vs * irs;
-            // a kernel term outside its own support is zero, also when f is
-            // infinite (a particle alone in its support at a fixed h)
-            const float fgi = ui < 1.0f ? fi * gi : 0.0f, Agi = ui < 1.0f ? Ai * gi : 0.0f;
-            const float fgj = uj < 1.0f ? b.x * gj : 0.0f, Agj = uj < 1.0f ? b.y * gj : 0.0f;
-            const float G = fgi + fgj;
-            const float acc = Agi + Agj + 0.5f * nu * G;
-            const float m = v.w;
-            ax -= m * acc * ex;
-            ay -= m * acc * ey;
-            az -= m * acc * ez;
-            du += m * (Agi + 0.25f * nu * G) * vdote;
-            const float psum = Pi + a.w;
-            const float ac = psum > 0.0f ? (acPi + c2.x) * fast_rcp(psum) : 0.0f;
-            const float vc = fabsf(vdote) + fast_sqrt(2.0f * fabsf(Pi - a.w) * irs);
-            du += m * ac * vc * (vi.w - c2.y) * G * irs;
-        }
+        nf += listed ? 1 : 0;
+        const bool on = listed && r2 > 0.0f;
+        const float4 v = cv[c];
+        const float4 a = ca[c];
+        const float4 b = cb[c];
+        const float2 c2 = cc[c];
+        const float rinv = fast_rsq(r2);
+        const float r = r2 * rinv;
+        const float ui = r * invHi;
+        const float ti = fmaxf(1.0f - ui, 0.0f);
+        const float gi = -kD * invHi4 * ui * (ti * ti * ti);
+        const float uj = r * a.x;
+        const float tj = fmaxf(1.0f - uj, 0.0f);
+        const float ij2 = a.x * a.x;
+        const float gj = -kD * (ij2 * ij2) * uj * (tj * tj * tj);
+        const float ex = dx * rinv, ey = dy * rinv, ez = dz * rinv;
+        const float dvx = vi.x - v.x, dvy = vi.y - v.y, dvz = vi.z - v.z;
+        const float vdote = dvx * ex + dvy * ey + dvz * ez;
+        const float mu = vdote < 0.0f ? vdote : 0.0f;
+        const float vs = ci + a.y - beta * mu;
+        vsig = on ? fmaxf(vsig, vs) : vsig;
+        const float alpha = 0.25f * (ai.x + b.w) * (Bi + b.z);
+        const float irs = fast_rcp(rhoi + a.z);
+        const float nu = -2.0f * alpha * mu * vs * irs;
+        // a kernel term outside its own support is zero, also when f is
+        // infinite (a particle alone in its support at a fixed h)
+        const float fgi = ui < 1.0f ? fi * gi : 0.0f, Agi = ui < 1.0f ? Ai * gi : 0.0f;
+        const float fgj = uj < 1.0f ? b.x * gj : 0.0f, Agj = uj < 1.0f ? b.y * gj : 0.0f;
+        const float G = fgi + fgj;
+        const float acc = Agi + Agj + 0.5f * nu * G;
+        const float m = v.w;
+        const float psum = Pi + a.w;
+        const float ac = psum > 0.0f ? (acPi + c2.x) * fast_rcp(psum) : 0.0f;
+        const float vc = fabsf(vdote) + fast_sqrt(2.0f * fabsf(Pi - a.w) * irs);
+        const float dui = m * (Agi + 0.25f * nu * G) * vdote + m * ac * vc * (vi.w - c2.y) * G * irs;
+        ax = on ? ax - m * acc * ex : ax;
+        ay = on ? ay - m * acc * ey : ay;
+        az = on ? az - m * acc * ez : az;
+        du = on ? du + dui : du;
     };
     auto compute = [&]() __attribute__((always_inline)) {
         for (int k = 0; __any(k < myn); k += 4) {
             const uint32_t four = *reinterpret_cast<const uint32_t *>(my_list + k);
 #pragma unroll
             for (int q = 0; q < 4; ++q)
-                if (k + q < myn)
-                    pair(int((four >> (8 * q)) & 0xffu));
+                pair(int((four >> (8 * q)) & 0xffu), k + q < myn);
         }
         myn = 0;
     };
+    // The slot is always written; it is kept (the length advanced) only
+    // when the pair lies inside max(H_i, H_j).
     auto accept = [&](int c, const float4 &p) __attribute__((always_inline)) {
         const float dx = pi.x - p.x, dy = pi.y - p.y, dz = pi.z - p.z;
         const float r2 = dx * dx + dy * dy + dz * dz;
-        if (act && r2 < fmaxf(Hi2, p.w)) {
-            my_list[myn] = uint8_t(c);
-            ++myn;
-        }
+        my_list[myn] = uint8_t(c);
+        myn += (act && r2 < fmaxf(Hi2, p.w)) ? 1 : 0;
     };
     auto flush = [&]() __attribute__((always_inline)) {
         wave_sync();

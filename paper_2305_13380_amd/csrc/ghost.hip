@@ -1,30 +1,42 @@
 // Ghost (Section 3.1 Newton-Raphson on the partition condition, equation of
-// state; Section 3.2 f-factor and Balsara switch). One thread per particle
-// needing a pass, in sorted order (the density kernel leaves its sums in
-// sorted order too); everything in FP32.
+// state; Section 3.2 f-factor and Balsara switch). Particles needing a pass,
+// in sorted order (the density kernel leaves its sums in sorted order too),
+// over a grid-stride loop; everything in FP32. The iteration's counters are
+// reduced per block and added with one atomic per block and counter (atomics
+// from every wave on the same few words serialise in L2).
+#include <algorithm>
+
 #include "sphx_internal.h"
 
 namespace sphx {
 namespace {
 
-__global__ void k_ghost(int64_t n, const int32_t *__restrict__ perm,
+constexpr int kGhostThreads = 256;
+constexpr int kGhostMaxBlocks = 1024;
+
+__global__ __launch_bounds__(kGhostThreads) void k_ghost(int64_t n, const int32_t *__restrict__ perm,
                         const int32_t *__restrict__ leaf_of, uint8_t *__restrict__ need,
                         float *__restrict__ h, float *__restrict__ hs,
                         const float4 *__restrict__ q1, const float *__restrict__ radius,
+                        const float *__restrict__ lrad,
                         const float4 *__restrict__ d0, const float4 *__restrict__ d1, float inv_eta3,
                         float h_tol, float h_max, float gamma_k, float gamma_gas, float eps_b,
-                        int final_pass, float *__restrict__ o_f, float *__restrict__ o_P,
+                        int final_pass, const int32_t *__restrict__ nngb,
+                        unsigned long long *__restrict__ units, float *__restrict__ o_f,
+                        float *__restrict__ o_P,
                         float *__restrict__ o_c, float *__restrict__ o_B,
                         float *__restrict__ o_A, float *__restrict__ o_div,
                         float *__restrict__ o_curl, uint8_t *__restrict__ o_conv,
                         int32_t *__restrict__ counters)
 {
-    const int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     // A density pass that ran with a stale task list is not used.
     const bool stale = counters && counters[3] > 0;
-    const bool work = s < n && !stale && need[s];
-    bool unconv = false, rebuild = false, clamped = false;
-    if (work) {
+    int n_unconv = 0, n_rebuild = 0, n_clamped = 0, n_beyond = 0;
+    unsigned long long pairs_cell = 0, pairs_list = 0;  // interactions of this pass, by loop
+    const int64_t stride = int64_t(gridDim.x) * kGhostThreads;
+    for (int64_t s = int64_t(blockIdx.x) * kGhostThreads + threadIdx.x; s < n; s += stride) {
+        if (stale || !need[s])
+            continue;
         const float hh = hs[s];
         const float4 a = d0[s];  // n, G' = 3 + h n'/n, rho, 1 + h rho'/(3 rho)
         const float nd = a.x;
@@ -41,17 +53,26 @@ __global__ void k_ghost(int64_t n, const int32_t *__restrict__ perm,
         hn = fminf(hn, h_max);
         const bool conv = fabsf(hn - hh) < h_tol * hh;
         const int32_t i = perm[s];
-        unconv = !conv;
+        n_unconv += conv ? 0 : 1;
+        if (units) {
+            const int c = nngb[i];
+            if (lrad && gamma_k * hh <= lrad[s])
+                pairs_list += c;
+            else
+                pairs_cell += c;
+        }
         if (!conv && !final_pass) {
             h[i] = hn;
             hs[s] = hn;
             o_conv[i] = 0;
-            rebuild = gamma_k * hn > radius[leaf_of[s]];
+            n_rebuild += gamma_k * hn > radius[leaf_of[s]] ? 1 : 0;
+            // with neighbour lists: the next pass cannot use this one's list
+            n_beyond += (lrad && gamma_k * hn > lrad[s]) ? 1 : 0;
         } else {
             // Converged, or out of passes: finalise at the h the sums belong to.
             need[s] = 0;
             o_conv[i] = conv ? 1 : 0;
-            clamped = hh >= h_max;
+            n_clamped += hh >= h_max ? 1 : 0;
             const float4 b = d1[s];  // div_sum, curl_x, curl_y, curl_z
             const float rho = a.z;
             const float u = q1[s].w;
@@ -71,16 +92,34 @@ __global__ void k_ghost(int64_t n, const int32_t *__restrict__ perm,
             o_curl[i] = curl;
         }
     }
-    // one atomic per wave and counter
-    if (counters) {
-        const uint64_t mu = __ballot(unconv), mr = __ballot(rebuild), mc = __ballot(clamped);
-        if ((threadIdx.x & 63) == 0) {
-            if (mu)
-                atomicAdd(counters + 0, int(__popcll(mu)));
-            if (mr)
-                atomicAdd(counters + 1, int(__popcll(mr)));
-            if (mc)
-                atomicAdd(counters + 2, int(__popcll(mc)));
+    if (!counters && !units)
+        return;
+    // block reduction: waves by shuffles, then across the block's waves in LDS
+    unsigned long long v[6] = {(unsigned long long)n_unconv, (unsigned long long)n_rebuild,
+                               (unsigned long long)n_clamped, (unsigned long long)n_beyond,
+                               pairs_cell, pairs_list};
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+        for (int o = 32; o > 0; o >>= 1)
+            v[k] += __shfl_xor(v[k], o, 64);
+    __shared__ unsigned long long red[kGhostThreads / 64][6];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0)
+        for (int k = 0; k < 6; ++k)
+            red[wv][k] = v[k];
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        const int k = threadIdx.x;
+        unsigned long long t = 0;
+        for (int w2 = 0; w2 < kGhostThreads / 64; ++w2)
+            t += red[w2][k];
+        if (t) {
+            if (k < 4) {
+                if (counters)
+                    atomicAdd(counters + (k == 3 ? 4 : k), int(t));
+            } else if (units) {
+                atomicAdd(units + (k - 4), t);
+            }
         }
     }
 }
@@ -89,17 +128,21 @@ __global__ void k_ghost(int64_t n, const int32_t *__restrict__ perm,
 
 sphx_status ghost_launch(const sphx_ctx *ctx, sphx_grid *g, const sphx_tasks *t,
                          sphx_particles *in, const sphx_density_out *d, const sphx_ghost_out *o,
-                         int32_t *counters, int final_pass, hipStream_t s)
+                         int32_t *counters, int final_pass, bool use_lists,
+                         unsigned long long *units, hipStream_t s)
 {
     if (g->n == 0)
         return SPHX_OK;
     const sphx_params &P = ctx->p;
     const float inv_eta3 = float(1.0 / (P.eta * P.eta * P.eta));
-    k_ghost<<<unsigned((g->n + 255) / 256), 256, 0, s>>>(
-        g->n, g->perm, g->leaf_of, g->need, in->h, g->hs, g->q1, t->radius, g->d0, g->d1, inv_eta3,
+    const int64_t nblk = std::min<int64_t>((g->n + kGhostThreads - 1) / kGhostThreads,
+                                           kGhostMaxBlocks);
+    k_ghost<<<unsigned(nblk), kGhostThreads, 0, s>>>(
+        g->n, g->perm, g->leaf_of, g->need, in->h, g->hs, g->q1, t->radius,
+        use_lists ? g->lrad : nullptr, g->d0, g->d1, inv_eta3,
         float(P.h_tol),
         float(ctx->h_max), float(P.gamma_k), float(P.gamma_gas), float(P.eps_balsara),
-        final_pass, o->f, o->P, o->c, o->balsara, o->A, o->div_v, o->curl_v, o->converged,
+        final_pass, d->nngb, units, o->f, o->P, o->c, o->balsara, o->A, o->div_v, o->curl_v, o->converged,
         counters);
     SPHX_HIP(hipGetLastError());
     return SPHX_OK;

@@ -354,7 +354,8 @@ void grid_free(sphx_grid *g)
     void *ptrs[] = {g->keys,    g->perm,     g->leaf_of,  g->q0,      g->q1,     g->qa,
                     g->need,    g->g0,       g->g1,       g->leaf_start, g->leaf_org, g->node_lo,
                     g->node_hi, g->node_r,   g->fsum,     g->sort_tmp, g->keys_in, g->idx_in,
-                    g->flags,   g->d_status, g->hs,       g->d0,       g->d1};
+                    g->flags,   g->d_status, g->hs,       g->d0,       g->d1,
+                    g->lrad,    g->lcnt,     g->lcap,     g->lboff,    g->lst,    g->lscan_tmp};
     for (void *p : ptrs)
         dfree(p, g->stream);
     delete g;

@@ -90,13 +90,21 @@ struct TaskRegs {
     }
 };
 
+// Squared distance of a pair for the neighbour tests, with one fixed
+// association and fused operations, so that the cell-pair loops, the list
+// build and the list loops take identical decisions.
+__device__ __forceinline__ float dist2(float dx, float dy, float dz)
+{
+    return __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
+}
+
 // Squared distance from p to the box [lo, hi].
 __device__ __forceinline__ float box_dist2(float px, float py, float pz, float3 lo, float3 hi)
 {
     float dx = fmaxf(fmaxf(lo.x - px, px - hi.x), 0.0f);
     float dy = fmaxf(fmaxf(lo.y - py, py - hi.y), 0.0f);
     float dz = fmaxf(fmaxf(lo.z - pz, pz - hi.z), 0.0f);
-    return dx * dx + dy * dy + dz * dz;
+    return dist2(dx, dy, dz);
 }
 
 }  // namespace sphx

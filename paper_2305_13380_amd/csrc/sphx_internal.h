@@ -46,14 +46,29 @@ constexpr float kD = 66.845076098596050f;  // 210 / pi
 
 // Task record: the source cell (its first sorted index and count), whether it
 // is the receiving cell itself without a periodic shift, and the FP32 offset
-// origin_j + shift - origin_i (formed in FP64).
+// origin_j + shift - origin_i (formed in FP64). The second half repeats j0, so
+// that it alone (16 bytes) locates a source particle in the receiver's frame.
 struct alignas(16) Task {
     int32_t j0;
     int32_t jc;
     int32_t self;
     int32_t j;
-    float ox, oy, oz, pad;
+    float ox, oy, oz;
+    int32_t j0b;  // == j0
 };
+
+// Neighbour-list entry: (task index - the receiving leaf's first task) << 6 |
+// index of the source within its leaf.
+constexpr int kListCodeShift = 6;
+constexpr int64_t kListMaxTasks = int64_t(1) << 26;  // task counts beyond this: no lists
+
+// Counters of sphx_step's own array: the public four, then [4] receivers whose
+// H outgrew their neighbour list; followed (at byte kStepUnitsOffset) by two
+// 64-bit sums over the step: density interactions computed by the cell-pair
+// loop and by the list loop.
+constexpr int kStepCounters = 8;
+constexpr size_t kStepUnitsOffset = kStepCounters * sizeof(int32_t);
+constexpr size_t kStepCounterBytes = kStepUnitsOffset + 2 * sizeof(unsigned long long);
 
 }  // namespace sphx
 
@@ -64,8 +79,9 @@ struct Profiler {
     struct Rec {
         hipEvent_t a, b;
     };
-    std::vector<Rec> pool[2];
-    size_t used[2] = {0, 0};
+    static constexpr int kKinds = 4;  // density cell-pair, force, density list, list build
+    std::vector<Rec> pool[kKinds];
+    size_t used[kKinds] = {0, 0, 0, 0};
     hipError_t begin(int k, hipStream_t s);
     hipError_t end(int k, hipStream_t s);
 };
@@ -116,6 +132,19 @@ struct sphx_grid {
 
     double *fsum;       // 6 * n_leaves FP64 partial sums of the force pass
 
+    // Per-receiver neighbour lists of the h iteration (sorted order). The
+    // receivers of 64-block b (sorted indices 64b .. 64b+63) own entries
+    // lst[lboff[b] + k * 64 + lane], k < lcnt[s]: every j within lrad[s] of s.
+    float *lrad;        // n: list radius (0: no list)
+    int32_t *lcnt;      // n: entries
+    int64_t *lcap;      // n_blocks + 1: 64 * max entries over the block (scratch)
+    int64_t *lboff;     // n_blocks + 1: first entry of each block; [n_blocks] = total
+    uint32_t *lst;      // lst_cap entries
+    int64_t lst_cap;
+    int64_t lst_total;
+    void *lscan_tmp;
+    size_t lscan_bytes;
+
     // build scratch
     void *sort_tmp;
     size_t sort_tmp_bytes;
@@ -155,14 +184,28 @@ void tasks_free(sphx_tasks *t);
 size_t tasks_bytes(int64_t n);
 
 // density.hip
+// Cell-pair density pass over the receivers that need one; with use_lists,
+// only over those whose H exceeds their list radius.
 sphx_status density_launch(const sphx_ctx *ctx, const sphx_grid *g, const sphx_tasks *t,
                            const sphx_particles *in, const sphx_density_out *out,
-                           int32_t *counters, hipStream_t s);
+                           int32_t *counters, bool use_lists, hipStream_t s);
+// List density pass over the receivers that need one and fit their lists.
+sphx_status density_list_launch(const sphx_ctx *ctx, const sphx_grid *g, const sphx_tasks *t,
+                                const sphx_density_out *out, hipStream_t s);
+
+// lists.hip
+// Builds the neighbour lists of every receiver that needs a pass (radius
+// min((1 + skin) H, leaf task radius)); *ok = false when the task list is too
+// large for list entries (the caller stays on the cell-pair path).
+sphx_status list_build(const sphx_ctx *ctx, sphx_grid *g, const sphx_tasks *t, hipStream_t s,
+                       bool *ok);
+size_t lists_bytes(int64_t n);
 
 // ghost.hip
 sphx_status ghost_launch(const sphx_ctx *ctx, sphx_grid *g, const sphx_tasks *t,
                          sphx_particles *in, const sphx_density_out *d, const sphx_ghost_out *o,
-                         int32_t *counters, int final_pass, hipStream_t s);
+                         int32_t *counters, int final_pass, bool use_lists,
+                         unsigned long long *units, hipStream_t s);
 
 // force.hip
 sphx_status force_launch(const sphx_ctx *ctx, const sphx_grid *g, const sphx_tasks *t,

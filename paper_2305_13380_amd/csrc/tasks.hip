@@ -200,7 +200,7 @@ __global__ void k_task_fill(int64_t n_leaves, TreeView T, const double *__restri
         t.j0 = leaf_start[J];
         t.jc = leaf_start[J + 1] - t.j0;
         t.self = (J == I && sx == 0 && sy == 0 && sz == 0) ? 1 : 0;
-        t.pad = 0.0f;
+        t.j0b = t.j0;
         // origin_j + shift - origin_i, formed in FP64, stored in FP32
         t.ox = float(org[3 * J] + double(sx) * T.L[0] - ox);
         t.oy = float(org[3 * J + 1] + double(sy) * T.L[1] - oy);
@@ -295,7 +295,7 @@ __global__ __launch_bounds__(64) void k_task_bfs(int64_t n_leaves, TreeView T,
                         t.ox = float(org[3 * J] + double(sx) * T.L[0] - oxi);
                         t.oy = float(org[3 * J + 1] + double(sy) * T.L[1] - oyi);
                         t.oz = float(org[3 * J + 2] + double(sz) * T.L[2] - ozi);
-                        t.pad = 0.0f;
+                        t.j0b = j0;
                         task[wbase + emitted + pre + k] = t;
                     });
                 }

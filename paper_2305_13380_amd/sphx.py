@@ -34,7 +34,7 @@ class Params(C.Structure):
                 ("gamma_k", C.c_double), ("eta", C.c_double), ("h_tol", C.c_double),
                 ("h_max", C.c_double), ("gamma_gas", C.c_double), ("beta_v", C.c_double),
                 ("eps_balsara", C.c_double), ("skin", C.c_double), ("leaf_max", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("neighbour_lists", C.c_int32)]
 
 
 class Particles(C.Structure):
@@ -58,7 +58,10 @@ class ForceOut(C.Structure):
 
 class StepInfo(C.Structure):
     _fields_ = [("passes", C.c_int32), ("task_rebuilds", C.c_int32), ("unconverged", C.c_int32),
-                ("clamped", C.c_int32), ("n_leaves", C.c_int64), ("n_tasks", C.c_int64)]
+                ("clamped", C.c_int32), ("n_leaves", C.c_int64), ("n_tasks", C.c_int64),
+                ("list_builds", C.c_int32), ("list_fallback", C.c_int32),
+                ("list_entries", C.c_int64), ("pairs_cellpair", C.c_int64),
+                ("pairs_list", C.c_int64)]
 
 
 SYMBOLS = ("sphx_params_default", "sphx_ctx_create", "sphx_ctx_destroy", "sphx_workspace_bytes",

@@ -47,16 +47,39 @@ def compare_step(g, ref, where, force_tol=None):
     return dh
 
 
+_REF = {}
+
+
+def oracle_step(case):
+    if case not in _REF:
+        _REF[case] = (CASES[case](),)
+        _REF[case] += (oracle.nr_step(_REF[case][0], P, mode="auto"),)
+    return _REF[case]
+
+
+# sphx_step variants: the cell-pair loop in every pass (default), neighbour
+# lists after the first pass, and lists without skin (every growth of h
+# sends the receiver back to the cell-pair loop or forces a list rebuild).
+VARIANTS = {"lists": {"neighbour_lists": 1}, "cellpair": {"neighbour_lists": 0},
+            "skin0": {"neighbour_lists": 1, "skin": 0.0}}
+
+
+@pytest.mark.parametrize("variant", sorted(VARIANTS))
 @pytest.mark.parametrize("case", sorted(CASES))
-def test_step_matches_oracle_iteration(case):
-    ps = CASES[case]()
-    print("step case:", case, "N=%d" % ps.n, flush=True)
-    g = gpu_step(ps)
-    ref = oracle.nr_step(ps, P, mode="auto")
-    assert g["status"] >= 0 and g["info"].unconverged == 0
+def test_step_matches_oracle_iteration(case, variant):
+    ps, ref = oracle_step(case)
+    print("step case:", case, variant, "N=%d" % ps.n, flush=True)
+    g = gpu_step(ps, params=VARIANTS[variant])
+    info = g["info"]
+    assert g["status"] >= 0 and info.unconverged == 0
+    if variant == "cellpair" or info.passes == 1:
+        assert info.list_builds == 0
+    else:
+        assert info.list_builds >= 1 and info.list_entries >= ps.n
     dh = compare_step(g, ref, case)
-    print("  passes gpu=%d oracle=%d, max |dh|/h=%.2e, median %.2e" % (
-        g["info"].passes, ref["passes"], dh.max(), np.median(dh)), flush=True)
+    print("  passes gpu=%d oracle=%d, list builds %d, fallback %d, max |dh|/h=%.2e, "
+          "median %.2e" % (info.passes, ref["passes"], info.list_builds, info.list_fallback,
+                           dh.max(), np.median(dh)), flush=True)
     s = g["sums"]
     assert np.abs(s[:3]).max() < 2e-5 * s[4]
     assert abs(s[3]) < 2e-5 * (s[4] * rms(np.stack([ps.vx, ps.vy, ps.vz])) * 3 + s[5] + 1e-300)
@@ -73,8 +96,8 @@ def test_step_is_bitwise_repeatable():
 def test_step_rebuilds_tasks_when_h_grows():
     ps = inputs.lattice_box(14, 3, u="logu")
     ps.h *= np.float32(0.45)  # the iteration must more than double h
-    g = gpu_step(ps)
-    assert g["info"].task_rebuilds >= 1
+    g = gpu_step(ps, params={"neighbour_lists": 1})
+    assert g["info"].task_rebuilds >= 1 and g["info"].list_builds >= 1
     ref = oracle.nr_step(ps, P, mode="brute")
     compare_step(g, ref, "grow")
 
