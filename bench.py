@@ -195,6 +195,8 @@ def main():
     ap.add_argument("--config", default="clustered", choices=sorted(CONFIGS))
     ap.add_argument("--cpu-receivers", type=int, default=4096)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="default loop shapes instead of the autotuner's")
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the serving-stream latency measurement")
     ap.add_argument("--serving-requests", type=int, default=512)
@@ -228,12 +230,29 @@ def main():
     log("bench: %s: N=%d generated in %.1f s" % (args.config, ps.n, time.perf_counter() - t0))
 
     dev = "cuda:0"
-    ctx = sphx.Context(sphx.default_params(), 0)
+    params = sphx.default_params()
     dp = sphx.DeviceParticles.from_set(ps, dev)
     out = sphx.Outputs(ps.n, dev)
     h0 = dp.t["h"].clone()
     stream = torch.cuda.current_stream()
     torch.cuda.synchronize()
+    shapes = "default"
+    if not args.no_tune:
+        # Loop shapes by the library's autotuner, on this workload at its
+        # initial h (outside the timed region).
+        t0 = time.perf_counter()
+        c0 = sphx.Context(params, 0)
+        g0 = sphx.Grid(c0, dp)
+        k0 = sphx.Tasks(c0, g0, dp)
+        params = sphx.autotune(c0, g0, k0, dp, out, reps=3)
+        torch.cuda.synchronize()
+        k0.close()
+        g0.close()
+        c0.close()
+        shapes = {k: getattr(params, k) for k in ("density_tile", "density_waves", "force_tile",
+                                                  "force_waves")}
+        log("bench: autotune %.1f s -> %s" % (time.perf_counter() - t0, shapes))
+    ctx = sphx.Context(params, 0)
 
     t0 = time.perf_counter()
     grid = sphx.Grid(ctx, dp)
@@ -335,7 +354,7 @@ def main():
                                               "list": info.pairs_list},
                    "list_builds_per_step": info.list_builds,
                    "list_fallback_receiver_passes": info.list_fallback,
-                   "list_entries": info.list_entries,
+                   "list_entries": info.list_entries, "loop_shapes": shapes,
                    "momentum_err_rel": mom, "energy_err_rel": en},
         "roofline": {"bound": "alu", "kernel": kern, "achieved": achieved,
                      "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",

@@ -77,6 +77,15 @@ typedef struct sphx_params {
     int32_t neighbour_lists; /* sphx_step: 1 reuses per-receiver neighbour lists within
                                 radius (1 + skin) H over the passes after the first; 0
                                 (default) runs the cell-pair loop in every pass */
+    /* Loop shapes (0 selects the default; sphx_autotune picks them by timing):
+     * candidate-buffer slots per wave and waves per cell of the density loop
+     * (64, 128 or 256, default 128; 1 or 2, default 1) and of the force loop
+     * (64 or 128, default 64; 1 or 2, default 1). Tile sizes do not change
+     * results; the wave count changes the FP32 summation order. */
+    int32_t density_tile;
+    int32_t density_waves;
+    int32_t force_tile;
+    int32_t force_waves;
 } sphx_params;
 
 /* Particle-carried inputs (Section 3.1): positions FP64, the rest FP32. */
@@ -235,6 +244,19 @@ sphx_status sphx_force(sphx_ctx *ctx, const sphx_grid *grid, const sphx_tasks *t
 sphx_status sphx_step(sphx_ctx *ctx, sphx_grid *grid, sphx_tasks **tasks, sphx_particles *in,
                       sphx_density_out *dens, sphx_ghost_out *gst, sphx_force_out *out,
                       double *d_sums6, void *stream, sphx_step_info *info);
+
+/* Autotuner: times each density-loop shape (tile x waves) on fixed-h density
+ * passes, and each force-loop shape on force passes, over this grid and task
+ * list at the particles' current h (reps launches each, HIP events on
+ * `stream`), and returns in *tuned the context's parameters with the fastest
+ * shapes. The output arrays are overwritten (density and ghost at the
+ * current h, then the force); h is not changed. Contexts created from *tuned
+ * give identical results to each other, so a caller that needs the same
+ * results from several contexts (a server's slots) tunes once and creates
+ * all of them from *tuned. Synchronises the stream. */
+sphx_status sphx_autotune(sphx_ctx *ctx, sphx_grid *grid, sphx_tasks *tasks, sphx_particles *in,
+                          sphx_density_out *dens, sphx_ghost_out *gst, sphx_force_out *out,
+                          int32_t reps, sphx_params *tuned, void *stream);
 
 /* Kernel timing for measurement tools. sphx_profile_enable(ctx, 1) clears the
  * statistics and starts recording a pair of HIP events around every launch of

@@ -110,6 +110,10 @@ void sphx_params_default(sphx_params *p)
     p->skin = 0.1;
     p->neighbour_lists = 0;
     p->leaf_max = 64;
+    p->density_tile = 0;
+    p->density_waves = 0;
+    p->force_tile = 0;
+    p->force_waves = 0;
 }
 
 const char *sphx_last_error(void) { return g_last_error.c_str(); }
@@ -130,6 +134,15 @@ sphx_status sphx_ctx_create(const sphx_params *p, int hip_device, sphx_ctx **out
         p->leaf_max < 8 || p->leaf_max > kLeafMax || !(p->skin >= 0.0) || !(p->gamma_gas > 1.0)) {
         set_error("sphx_ctx_create: invalid eta, h_tol, max_iter, gamma_k, gamma_gas, skin or "
                   "leaf_max (8..64)");
+        return SPHX_E_INVALID;
+    }
+    auto one_of = [](int32_t v, int32_t a, int32_t b, int32_t c) {
+        return v == 0 || v == a || v == b || v == c;
+    };
+    if (!one_of(p->density_tile, 64, 128, 256) || !one_of(p->density_waves, 1, 2, 1) ||
+        !one_of(p->force_tile, 64, 128, 64) || !one_of(p->force_waves, 1, 2, 1)) {
+        set_error("sphx_ctx_create: loop shapes must be 0 or density_tile 64/128/256, "
+                  "density_waves 1/2, force_tile 64/128, force_waves 1/2");
         return SPHX_E_INVALID;
     }
     int ndev = 0;
@@ -369,6 +382,103 @@ sphx_status sphx_step(sphx_ctx *ctx, sphx_grid *grid, sphx_tasks **tasks, sphx_p
     if (local.clamped)
         w |= SPHX_W_H_CLAMPED;
     return w;
+}
+
+sphx_status sphx_autotune(sphx_ctx *ctx, sphx_grid *grid, sphx_tasks *tasks, sphx_particles *in,
+                          sphx_density_out *dens, sphx_ghost_out *gst, sphx_force_out *out,
+                          int32_t reps, sphx_params *tuned, void *stream)
+{
+    SPHX_TRY(check_handles(ctx, grid, tasks, in));
+    SPHX_TRY(check_particles(in, true));
+    if (!tasks || !dens || !gst || !out || !tuned || reps < 1) {
+        set_error("sphx_autotune: NULL task list, output or result, or reps < 1");
+        return SPHX_E_INVALID;
+    }
+    hipStream_t s = as_stream(stream);
+    SPHX_HIP(hipSetDevice(ctx->device));
+    const sphx_params saved = ctx->p;
+    struct Events {
+        hipEvent_t a = nullptr, b = nullptr;
+        ~Events()
+        {
+            if (a)
+                (void)hipEventDestroy(a);
+            if (b)
+                (void)hipEventDestroy(b);
+        }
+    } ev;
+    SPHX_HIP(hipEventCreate(&ev.a));
+    SPHX_HIP(hipEventCreate(&ev.b));
+    // Kernel time of `reps` launches of f (after one untimed launch).
+    auto timed = [&](auto &&setup, auto &&f, double *ms) -> sphx_status {
+        SPHX_TRY(setup());
+        SPHX_TRY(f());
+        double total = 0.0;
+        for (int r = 0; r < reps; ++r) {
+            SPHX_TRY(setup());
+            SPHX_HIP(hipEventRecord(ev.a, s));
+            SPHX_TRY(f());
+            SPHX_HIP(hipEventRecord(ev.b, s));
+            SPHX_HIP(hipEventSynchronize(ev.b));
+            float t = 0.f;
+            SPHX_HIP(hipEventElapsedTime(&t, ev.a, ev.b));
+            total += t;
+        }
+        *ms = total;
+        return SPHX_OK;
+    };
+    sphx_status st = SPHX_OK;
+    auto run = [&]() -> sphx_status {
+        const int32_t dshape[6][2] = {{128, 1}, {64, 1}, {256, 1}, {128, 2}, {64, 2}, {256, 2}};
+        double best = 1e300;
+        int32_t bt = 128, bw = 1;
+        for (auto &sh : dshape) {
+            ctx->p.density_tile = sh[0];
+            ctx->p.density_waves = sh[1];
+            double ms = 0.0;
+            SPHX_TRY(timed([&]() { return iter_reset(grid, in, s); },
+                           [&]() { return density_launch(ctx, grid, tasks, in, dens, nullptr, false,
+                                                         s); },
+                           &ms));
+            if (ms < best) {
+                best = ms;
+                bt = sh[0];
+                bw = sh[1];
+            }
+        }
+        ctx->p.density_tile = bt;
+        ctx->p.density_waves = bw;
+        // force state at the current h: one density pass and a finalising ghost
+        SPHX_TRY(iter_reset(grid, in, s));
+        SPHX_TRY(density_launch(ctx, grid, tasks, in, dens, nullptr, false, s));
+        SPHX_TRY(ghost_launch(ctx, grid, tasks, in, dens, gst, nullptr, 1, false, nullptr, s));
+        const int32_t fshape[4][2] = {{64, 1}, {128, 1}, {64, 2}, {128, 2}};
+        best = 1e300;
+        int32_t ft = 64, fw = 1;
+        for (auto &sh : fshape) {
+            ctx->p.force_tile = sh[0];
+            ctx->p.force_waves = sh[1];
+            double ms = 0.0;
+            SPHX_TRY(timed([&]() { return SPHX_OK; },
+                           [&]() { return force_launch(ctx, grid, tasks, in, dens, gst, out,
+                                                       nullptr, s); },
+                           &ms));
+            if (ms < best) {
+                best = ms;
+                ft = sh[0];
+                fw = sh[1];
+            }
+        }
+        *tuned = saved;
+        tuned->density_tile = bt;
+        tuned->density_waves = bw;
+        tuned->force_tile = ft;
+        tuned->force_waves = fw;
+        return SPHX_OK;
+    };
+    st = run();
+    ctx->p = saved;
+    return st;
 }
 
 sphx_status sphx_profile_enable(sphx_ctx *ctx, int32_t enable)

@@ -92,16 +92,20 @@ __device__ __forceinline__ void dens_finish(const float (&S)[kSums], float hi, f
     o.nngb[gi] = int32_t(S[8]) - 1;
 }
 
-template <int CAP, int NW>
+// BAL: the pair arithmetic of a compute round is spread evenly over the
+// wave's lanes (see compute_bal) instead of each lane walking its own list.
+template <int CAP, int NW, bool BAL>
 __global__ __launch_bounds__(64 * NW) void k_density(
-    int64_t n_leaves, int64_t nb_padded, const int32_t *__restrict__ leaf_start,
+    int64_t n_leaves, int64_t nb_padded, const int32_t *__restrict__ order,
+    const int32_t *__restrict__ leaf_start,
     const int32_t *__restrict__ perm, const float4 *__restrict__ q0,
     const float4 *__restrict__ q1, const uint8_t *__restrict__ need, const float *__restrict__ hs,
     const float *__restrict__ radius, const int32_t *__restrict__ toff,
     const Task *__restrict__ task, float gamma_k, const float *__restrict__ lrad, DensOut o,
     int32_t *__restrict__ counters)
 {
-    const int64_t L = xcd_remap(blockIdx.x, nb_padded);
+    static_assert(CAP >= 64 && CAP <= 256, "candidate slots: one task's sources, 8-bit slots");
+    const int64_t L = leaf_of_block(blockIdx.x, nb_padded, order);
     if (L >= n_leaves)
         return;
     const int lane = threadIdx.x & 63;
@@ -119,6 +123,12 @@ __global__ __launch_bounds__(64 * NW) void k_density(
     __shared__ float4 cp_all[NW][CAP];  // candidate x, y, z (receiver cell frame), m
     __shared__ float4 cv_all[NW][CAP];  // candidate vx, vy, vz
     __shared__ uint32_t lst_all[NW][kListStride * 16];
+    // BAL only: receivers' positions and (velocity, 1/H); the round's list
+    // offsets; segment partial sums ([start | end | complete][sum][lane]).
+    __shared__ float4 rp_all[NW][BAL ? 64 : 1];
+    __shared__ float4 rv_all[NW][BAL ? 64 : 1];
+    __shared__ int32_t ro_all[NW][BAL ? 68 : 1];
+    __shared__ float sp_all[NW][BAL ? 3 * kSums * 64 : 1];
     float4 *cp = cp_all[w];
     float4 *cv = cv_all[w];
     uint8_t *lst = reinterpret_cast<uint8_t *>(lst_all[w]);
@@ -150,6 +160,14 @@ __global__ __launch_bounds__(64 * NW) void k_density(
     float S[kSums] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     int nc = 0;   // buffered candidates (wave-uniform)
     int myn = 0;  // this lane's list length (its own particle is listed too)
+    float4 *rp = rp_all[w];
+    float4 *rv = rv_all[w];
+    int32_t *ro = ro_all[w];
+    float *sp = sp_all[w];
+    if (BAL) {
+        rp[lane] = pi;
+        rv[lane] = make_float4(vi.x, vi.y, vi.z, invH);
+    }
 
     // Four list entries at a time, without branches: entries past a lane's
     // list length read slot 0 (a candidate of the current buffer, so finite
@@ -172,6 +190,96 @@ __global__ __launch_bounds__(64 * NW) void k_density(
         }
         myn = 0;
     };
+    // Balanced round: the lanes' lists, concatenated in lane order (W entries),
+    // are cut into 64 contiguous ranges of equal length, lane l taking
+    // entries [l W / 64, (l + 1) W / 64) with the data of the receivers they
+    // belong to. A lane's range covers whole receivers (their sums go to the
+    // "complete" slot of the receiver) and at its ends parts of receivers
+    // shared with neighbouring lanes ("start": continues a receiver begun by
+    // an earlier lane; "end": cut off, continued by a later lane). Each
+    // receiver's lane then adds its parts in lane order, so the result does
+    // not depend on timing.
+    auto compute_bal = [&]() __attribute__((always_inline)) {
+        int incl = myn;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int t = __shfl_up(incl, o, 64);
+            if (lane >= o)
+                incl += t;
+        }
+        const int W = __shfl(incl, 63, 64);
+        if (W == 0)
+            return;  // wave-uniform
+        ro[lane + 1] = incl;
+        if (lane == 0)
+            ro[0] = 0;
+        wave_sync();
+        const int a = (lane * W) >> 6;
+        const int b = ((lane + 1) * W) >> 6;
+        int r = 0;  // the receiver of entry a: the last r with ro[r] <= a
+#pragma unroll
+        for (int step = 32; step > 0; step >>= 1)
+            if (ro[r + step] <= a)
+                r += step;
+        int rs = ro[r], re = ro[r + 1];
+        int seg0 = a;
+        float4 P = rp[r], V = rv[r];
+        float T[kSums] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        auto deposit = [&](int seg1) __attribute__((always_inline)) {
+            const int slot = (seg0 == rs && seg1 == re) ? 2 : (seg0 > rs ? 0 : 1);
+            const int idx = slot == 2 ? r : lane;
+#pragma unroll
+            for (int k = 0; k < kSums; ++k) {
+                sp[(slot * kSums + k) * 64 + idx] = T[k];
+                T[k] = 0.0f;
+            }
+        };
+        if (a == b) {
+#pragma unroll
+            for (int k = 0; k < kSums; ++k)
+                sp[k * 64 + lane] = 0.0f;  // an empty range adds nothing
+        }
+        const int nit = (W + 63) >> 6;
+        for (int t = 0; t < nit; ++t) {
+            const int k = a + t;
+            const bool ok = k < b;
+            if (ok && k >= re) {
+                deposit(k);
+                do {
+                    ++r;
+                    rs = ro[r];
+                    re = ro[r + 1];
+                } while (k >= re);
+                seg0 = k;
+                P = rp[r];
+                V = rv[r];
+            }
+            const int c = lst[r * kListStride + (ok ? k - rs : 0)];
+            dens_pair(T, P, V, V.w, cp[c], cv[c], ok);
+        }
+        if (a < b)
+            deposit(b);
+        wave_sync();
+        const int ms = incl - myn, me = incl;
+        if (me > ms) {
+            const int L0 = min((64 * (ms + 1) - 1) / W, 63);
+            const int L1 = min((64 * me - 1) / W, 63);
+            if (L0 == L1) {
+#pragma unroll
+                for (int k = 0; k < kSums; ++k)
+                    S[k] += sp[(2 * kSums + k) * 64 + lane];
+            } else {
+#pragma unroll
+                for (int k = 0; k < kSums; ++k)
+                    S[k] += sp[(kSums + k) * 64 + L0];
+                for (int l = L0 + 1; l <= L1; ++l)
+#pragma unroll
+                    for (int k = 0; k < kSums; ++k)
+                        S[k] += sp[k * 64 + l];
+            }
+        }
+        wave_sync();
+        myn = 0;
+    };
     // The slot is always written; it is kept (the length advanced) only
     // when the candidate lies inside H.
     auto accept = [&](int c, const float4 &p) __attribute__((always_inline)) {
@@ -188,12 +296,19 @@ __global__ __launch_bounds__(64 * NW) void k_density(
             accept(c + 1, p1);
             accept(c + 2, p2);
             accept(c + 3, p3);
-            if (__any(myn > kListMax - 4))
-                compute();
+            if (__any(myn > kListMax - 4)) {
+                if (BAL)
+                    compute_bal();
+                else
+                    compute();
+            }
         }
         for (; c < nc; ++c)
             accept(c, cp[c]);
-        compute();
+        if (BAL)
+            compute_bal();
+        else
+            compute();
         wave_sync();
         nc = 0;
     };
@@ -262,7 +377,9 @@ __global__ __launch_bounds__(64 * NW) void k_density(
     if (NW > 1) {
         // Add the other waves' partial sums to wave 0's, in wave order.
         __syncthreads();
-        float *red = reinterpret_cast<float *>(cp_all);
+        // the other waves' partial sums (own array: small tiles leave too
+        // little room in the candidate buffers)
+        __shared__ float red[NW > 1 ? (NW - 1) * kSums * 64 : 1];
         if (w > 0)
             for (int k = 0; k < kSums; ++k)
                 red[((w - 1) * kSums + k) * 64 + lane] = S[k];
@@ -360,13 +477,31 @@ sphx_status density_launch(const sphx_ctx *ctx, const sphx_grid *g, const sphx_t
     if (g->n_leaves == 0)
         return SPHX_OK;
     const int64_t nbp = pad8(g->n_leaves);
-    // One wave per cell measured fastest (the waves of a multi-wave block
-    // would split the cell's tasks, and the per-lane lists get shorter).
-    constexpr int NW = 1;
+    const int tile = ctx->p.density_tile ? ctx->p.density_tile : 128;
+    const int waves = ctx->p.density_waves ? ctx->p.density_waves : 1;
+    const float *lr = use_lists ? g->lrad : nullptr;
+    const DensOut dout = dens_out(g, o);
     SPHX_HIP(ctx->prof->begin(0, s));
-    k_density<kCap, NW><<<unsigned(nbp), 64 * NW, 0, s>>>(
-        g->n_leaves, nbp, g->leaf_start, g->perm, g->q0, g->q1, g->need, g->hs, t->radius, t->off,
-        t->task, float(ctx->p.gamma_k), use_lists ? g->lrad : nullptr, dens_out(g, o), counters);
+#define SPHX_DENSITY_LAUNCH(CAP_, NW_)                                                         \
+    k_density<CAP_, NW_, false><<<unsigned(nbp), 64 * NW_, 0, s>>>(                            \
+        g->n_leaves, nbp, t->order, g->leaf_start, g->perm, g->q0, g->q1, g->need, g->hs,      \
+        t->radius, t->off, t->task, float(ctx->p.gamma_k), lr, dout, counters)
+    if (waves == 1) {
+        if (tile == 64)
+            SPHX_DENSITY_LAUNCH(64, 1);
+        else if (tile == 128)
+            SPHX_DENSITY_LAUNCH(128, 1);
+        else
+            SPHX_DENSITY_LAUNCH(256, 1);
+    } else {
+        if (tile == 64)
+            SPHX_DENSITY_LAUNCH(64, 2);
+        else if (tile == 128)
+            SPHX_DENSITY_LAUNCH(128, 2);
+        else
+            SPHX_DENSITY_LAUNCH(256, 2);
+    }
+#undef SPHX_DENSITY_LAUNCH
     SPHX_HIP(hipGetLastError());
     SPHX_HIP(ctx->prof->end(0, s));
     return SPHX_OK;

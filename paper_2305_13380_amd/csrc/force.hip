@@ -9,7 +9,6 @@
 namespace sphx {
 namespace {
 
-constexpr int kCapForce = 128;
 
 // Sorted copies of the ghost state every source needs: (h, rho, P, c) and
 // (f, B, A, 0).
@@ -37,9 +36,11 @@ __device__ __forceinline__ double wave_sum(double v)
 
 constexpr int kFSums = 6;  // ax, ay, az, du, vsig, count
 
+// CAP >= 64: a task's kept sources (up to 64) always fit after a flush.
 template <int CAP, int NW>
 __global__ __launch_bounds__(64 * NW) void k_force(
-    int64_t n_leaves, int64_t nb_padded, const int32_t *__restrict__ leaf_start,
+    int64_t n_leaves, int64_t nb_padded, const int32_t *__restrict__ order,
+    const int32_t *__restrict__ leaf_start,
     const int32_t *__restrict__ perm, const float4 *__restrict__ q0,
     const float4 *__restrict__ q1, const float2 *__restrict__ qa, const float4 *__restrict__ g0,
     const float4 *__restrict__ g1, const uint8_t *__restrict__ active,
@@ -48,7 +49,8 @@ __global__ __launch_bounds__(64 * NW) void k_force(
     float *__restrict__ o_du, float *__restrict__ o_vsig, int32_t *__restrict__ o_nf,
     double *__restrict__ fsum)
 {
-    const int64_t L = xcd_remap(blockIdx.x, nb_padded);
+    static_assert(CAP >= 64 && CAP <= 256, "candidate slots: one task's sources, 8-bit slots");
+    const int64_t L = leaf_of_block(blockIdx.x, nb_padded, order);
     if (L >= n_leaves)
         return;
     const int lane = threadIdx.x & 63;
@@ -265,7 +267,9 @@ __global__ __launch_bounds__(64 * NW) void k_force(
     float F[kFSums] = {ax, ay, az, du, vsig, float(nf - (w == 0 && act ? 1 : 0))};
     if (NW > 1) {
         __syncthreads();
-        float *red = reinterpret_cast<float *>(cp_all);
+        // the other waves' partial sums (own array: small tiles leave too
+        // little room in the candidate buffers)
+        __shared__ float red[NW > 1 ? (NW - 1) * kFSums * 64 : 1];
         if (w > 0)
             for (int k = 0; k < kFSums; ++k)
                 red[((w - 1) * kFSums + k) * 64 + lane] = F[k];
@@ -356,11 +360,25 @@ sphx_status force_launch(const sphx_ctx *ctx, const sphx_grid *g, const sphx_tas
     SPHX_HIP(hipGetLastError());
     const int64_t nbp = pad8(g->n_leaves);
     SPHX_HIP(ctx->prof->begin(1, s));
-    constexpr int NW = 2;
-    k_force<kCapForce, NW><<<unsigned(nbp), 64 * NW, 0, s>>>(
-        g->n_leaves, nbp, g->leaf_start, g->perm, g->q0, g->q1, g->qa, g->g0, g->g1, in->active,
-        t->off, t->task, float(ctx->p.gamma_k), float(ctx->p.beta_v), o->ax, o->ay, o->az,
-        o->du_dt, o->v_sig, o->nforce, g->fsum);
+    const int tile = ctx->p.force_tile ? ctx->p.force_tile : 64;
+    const int waves = ctx->p.force_waves ? ctx->p.force_waves : 1;
+#define SPHX_FORCE_LAUNCH(CAP_, NW_)                                                           \
+    k_force<CAP_, NW_><<<unsigned(nbp), 64 * NW_, 0, s>>>(                                     \
+        g->n_leaves, nbp, t->order, g->leaf_start, g->perm, g->q0, g->q1, g->qa, g->g0, g->g1, \
+        in->active, t->off, t->task, float(ctx->p.gamma_k), float(ctx->p.beta_v), o->ax,       \
+        o->ay, o->az, o->du_dt, o->v_sig, o->nforce, g->fsum)
+    if (waves == 1) {
+        if (tile == 64)
+            SPHX_FORCE_LAUNCH(64, 1);
+        else
+            SPHX_FORCE_LAUNCH(128, 1);
+    } else {
+        if (tile == 64)
+            SPHX_FORCE_LAUNCH(64, 2);
+        else
+            SPHX_FORCE_LAUNCH(128, 2);
+    }
+#undef SPHX_FORCE_LAUNCH
     SPHX_HIP(hipGetLastError());
     SPHX_HIP(ctx->prof->end(1, s));
     if (sums6) {

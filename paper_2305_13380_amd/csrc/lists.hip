@@ -22,13 +22,14 @@ namespace {
 // (lrad, lcnt written); FILL = true: the entries (lrad, lcnt and lboff read).
 template <bool FILL>
 __global__ __launch_bounds__(64) void k_list(
-    int64_t n_leaves, int64_t nb_padded, const int32_t *__restrict__ leaf_start,
+    int64_t n_leaves, int64_t nb_padded, const int32_t *__restrict__ order,
+    const int32_t *__restrict__ leaf_start,
     const float4 *__restrict__ q0, const uint8_t *__restrict__ need, const float *__restrict__ hs,
     const float *__restrict__ radius, const int32_t *__restrict__ toff,
     const Task *__restrict__ task, float list_scale, float *__restrict__ lrad,
     int32_t *__restrict__ lcnt, const int64_t *__restrict__ lboff, uint32_t *__restrict__ lst)
 {
-    const int64_t L = xcd_remap(blockIdx.x, nb_padded);
+    const int64_t L = leaf_of_block(blockIdx.x, nb_padded, order);
     if (L >= n_leaves)
         return;
     const int lane = threadIdx.x;
@@ -227,7 +228,7 @@ sphx_status list_build(const sphx_ctx *ctx, sphx_grid *g, const sphx_tasks *t, h
     const int64_t nlp = pad8(nl);
     const float scale = float(ctx->p.gamma_k * (1.0 + ctx->p.skin));
     SPHX_HIP(ctx->prof->begin(3, s));
-    k_list<false><<<unsigned(nlp), 64, 0, s>>>(nl, nlp, g->leaf_start, g->q0, g->need, g->hs,
+    k_list<false><<<unsigned(nlp), 64, 0, s>>>(nl, nlp, t->order, g->leaf_start, g->q0, g->need, g->hs,
                                                t->radius, t->off, t->task, scale, g->lrad, g->lcnt,
                                                nullptr, nullptr);
     SPHX_HIP(hipGetLastError());
@@ -254,7 +255,7 @@ sphx_status list_build(const sphx_ctx *ctx, sphx_grid *g, const sphx_tasks *t, h
     }
     g->lst_total = total;
     SPHX_HIP(ctx->prof->begin(3, s));
-    k_list<true><<<unsigned(nlp), 64, 0, s>>>(nl, nlp, g->leaf_start, g->q0, g->need, g->hs,
+    k_list<true><<<unsigned(nlp), 64, 0, s>>>(nl, nlp, t->order, g->leaf_start, g->q0, g->need, g->hs,
                                               t->radius, t->off, t->task, scale, g->lrad, g->lcnt,
                                               g->lboff, g->lst);
     SPHX_HIP(hipGetLastError());

@@ -166,6 +166,17 @@ struct sphx_tasks {
     uint8_t *overflow;  // per leaf: 1 when the serial walk built its list
     void *scan_tmp;
     size_t scan_tmp_bytes;
+    // Launch order of the per-leaf loops: the leaves are split into 8
+    // contiguous ranges (one per XCD, as xcd_remap) and each range is ordered
+    // by decreasing work (sources to load), so that the longest cells start
+    // first. order[x * (nbp / 8) + k] = k-th leaf of range x (or >= n_leaves).
+    int32_t *order;       // nbp = pad8(n_leaves)
+    uint64_t *okey;       // nbp, scratch (sort keys)
+    uint64_t *okey_out;   // nbp, scratch
+    int32_t *oval;        // nbp, scratch
+    void *sort_tmp;
+    size_t sort_tmp_bytes;
+    int64_t order_cap;
 };
 
 namespace sphx {
@@ -220,6 +231,14 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t nblocks_padded)
 {
     const int64_t per = nblocks_padded >> 3;
     return (b & 7) * per + (b >> 3);
+}
+
+// The leaf of block b of a per-leaf loop: the XCD's range as xcd_remap, within
+// it the leaves in the task list's decreasing-work order.
+__device__ __forceinline__ int64_t leaf_of_block(int64_t b, int64_t nblocks_padded,
+                                                 const int32_t *__restrict__ order)
+{
+    return order[xcd_remap(b, nblocks_padded)];
 }
 
 inline int64_t pad8(int64_t n) { return (n + 7) & ~int64_t(7); }

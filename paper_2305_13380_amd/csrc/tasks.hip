@@ -4,6 +4,7 @@
 // cell size matches the local search radius). The search walks a tree of
 // bounding boxes over the Morton-ordered leaves once per rebuild; the
 // neighbour loops themselves never walk it.
+#include <rocprim/device/device_radix_sort.hpp>
 #include <rocprim/device/device_scan.hpp>
 
 #include "sphx_internal.h"
@@ -210,6 +211,36 @@ __global__ void k_task_fill(int64_t n_leaves, TreeView T, const double *__restri
     });
 }
 
+// Sort keys of the launch order: slot i of the padded leaf range belongs to
+// XCD range x = i / per; key = (x, ~work), work = sources of all the leaf's
+// tasks (padding slots sort last in their range).
+__global__ __launch_bounds__(64) void k_leaf_order_keys(int64_t n_leaves, int64_t nbp,
+                                                        const int32_t *__restrict__ off,
+                                                        const Task *__restrict__ task,
+                                                        uint64_t *__restrict__ key,
+                                                        int32_t *__restrict__ val)
+{
+    const int64_t i = blockIdx.x;
+    if (i >= nbp)
+        return;
+    const int lane = threadIdx.x;
+    const int64_t per = nbp >> 3;
+    uint32_t work = 0;
+    if (i < n_leaves) {
+        const int32_t a = off[i], b = off[i + 1];
+        uint32_t w = 0;
+        for (int32_t t = a + lane; t < b; t += 64)
+            w += uint32_t(task[t].jc);
+        for (int o = 32; o > 0; o >>= 1)
+            w += __shfl_xor(w, o, 64);
+        work = w + 1;  // every real leaf sorts before the padding
+    }
+    if (lane == 0) {
+        key[i] = (uint64_t(i / per) << 32) | uint64_t(0xffffffffu - work);
+        val[i] = int32_t(i);
+    }
+}
+
 constexpr int kFront = 1024;  // breadth-first frontier capacity (nodes) per cell
 
 // Exclusive prefix sum over the wave of small non-negative counts (< 32),
@@ -360,7 +391,46 @@ void tasks_free(sphx_tasks *t)
     void *ptrs[] = {t->off, t->task, t->count, t->radius, t->scan_tmp, t->overflow};
     for (void *p : ptrs)
         dfree(p, t->stream);
+    for (void *p : {(void *)t->order, (void *)t->okey, (void *)t->okey_out, (void *)t->oval,
+                    t->sort_tmp})
+        dfree(p, t->stream);
     delete t;
+}
+
+// Launch order of the per-leaf loops (see sphx_tasks::order).
+static sphx_status leaf_order(sphx_tasks *t, int64_t nl, hipStream_t s)
+{
+    const int64_t nbp = pad8(nl);
+    if (nbp > t->order_cap) {
+        for (void *p : {(void *)t->order, (void *)t->okey, (void *)t->okey_out, (void *)t->oval,
+                        t->sort_tmp})
+            dfree(p, s);
+        t->order = nullptr;
+        t->okey = t->okey_out = nullptr;
+        t->oval = nullptr;
+        t->sort_tmp = nullptr;
+        t->order_cap = 0;
+        size_t tmp = 0;
+        SPHX_HIP(rocprim::radix_sort_pairs(nullptr, tmp, (uint64_t *)nullptr, (uint64_t *)nullptr,
+                                           (int32_t *)nullptr, (int32_t *)nullptr, size_t(nbp), 0,
+                                           64, s));
+        if (dmalloc((void **)&t->order, size_t(nbp) * sizeof(int32_t), s) != hipSuccess ||
+            dmalloc((void **)&t->okey, size_t(nbp) * sizeof(uint64_t), s) != hipSuccess ||
+            dmalloc((void **)&t->okey_out, size_t(nbp) * sizeof(uint64_t), s) != hipSuccess ||
+            dmalloc((void **)&t->oval, size_t(nbp) * sizeof(int32_t), s) != hipSuccess ||
+            dmalloc(&t->sort_tmp, tmp + 16, s) != hipSuccess) {
+            set_error("sphx_tasks_build: out of device memory (leaf order)");
+            return SPHX_E_OOM;
+        }
+        t->sort_tmp_bytes = tmp;
+        t->order_cap = nbp;
+    }
+    k_leaf_order_keys<<<unsigned(nbp), 64, 0, s>>>(nl, nbp, t->off, t->task, t->okey, t->oval);
+    SPHX_HIP(hipGetLastError());
+    size_t tmp = t->sort_tmp_bytes;
+    SPHX_HIP(rocprim::radix_sort_pairs(t->sort_tmp, tmp, t->okey, t->okey_out, t->oval, t->order,
+                                       size_t(nbp), 0, 64, s));
+    return SPHX_OK;
 }
 
 sphx_status tasks_build(sphx_ctx *ctx, sphx_grid *g, const sphx_particles *in, hipStream_t s,
@@ -474,6 +544,7 @@ sphx_status tasks_build(sphx_ctx *ctx, sphx_grid *g, const sphx_particles *in, h
     k_task_fill<<<blocks(nl, 64), 64, 0, s>>>(nl, T, g->leaf_org, g->leaf_start, t->overflow,
                                               t->off, t->task);
     SPHX_HIP(hipGetLastError());
+    SPHX_TRY(leaf_order(t, nl, s));
     guard.keep = true;
     *out = t;
     return SPHX_OK;

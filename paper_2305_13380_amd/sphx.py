@@ -34,7 +34,9 @@ class Params(C.Structure):
                 ("gamma_k", C.c_double), ("eta", C.c_double), ("h_tol", C.c_double),
                 ("h_max", C.c_double), ("gamma_gas", C.c_double), ("beta_v", C.c_double),
                 ("eps_balsara", C.c_double), ("skin", C.c_double), ("leaf_max", C.c_int32),
-                ("neighbour_lists", C.c_int32)]
+                ("neighbour_lists", C.c_int32), ("density_tile", C.c_int32),
+                ("density_waves", C.c_int32), ("force_tile", C.c_int32),
+                ("force_waves", C.c_int32)]
 
 
 class Particles(C.Structure):
@@ -68,7 +70,7 @@ SYMBOLS = ("sphx_params_default", "sphx_ctx_create", "sphx_ctx_destroy", "sphx_w
            "sphx_grid_build", "sphx_grid_destroy", "sphx_tasks_build", "sphx_tasks_destroy",
            "sphx_iter_reset", "sphx_density", "sphx_ghost", "sphx_force", "sphx_step",
            "sphx_grid_leaves", "sphx_tasks_count", "sphx_last_error", "sphx_profile_enable",
-           "sphx_profile_read")
+           "sphx_profile_read", "sphx_autotune")
 
 _LIB = None
 
@@ -107,6 +109,9 @@ def _load():
                              vp, vp]
     L.sphx_step.argtypes = [vp, vp, P(vp), P(Particles), P(DensityOut), P(GhostOut),
                             P(ForceOut), vp, vp, P(StepInfo)]
+    L.sphx_autotune.argtypes = [vp, vp, vp, P(Particles), P(DensityOut), P(GhostOut),
+                                P(ForceOut), i32, P(Params), vp]
+    L.sphx_autotune.restype = i32
     L.sphx_grid_leaves.argtypes = [vp]
     L.sphx_grid_leaves.restype = i64
     L.sphx_tasks_count.argtypes = [vp]
@@ -348,3 +353,14 @@ def fixed_h_pass(ctx, grid, tasks, parts, out: Outputs, stream=None):
     density(ctx, grid, tasks, parts, out, stream=stream)
     ghost(ctx, grid, tasks, parts, out, final_pass=True, stream=stream)
     force(ctx, grid, tasks, parts, out, stream=stream)
+
+
+def autotune(ctx, grid, tasks, parts, out: Outputs, reps=3, stream=None) -> Params:
+    """Loop shapes timed on this grid (sphx_autotune); returns the tuned
+    parameters (create contexts from them to use the shapes)."""
+    pv, dv, gv, fv = parts.view(), out.dens_view(), out.ghost_view(), out.force_view()
+    tuned = Params()
+    _check(lib.sphx_autotune(ctx.handle, grid.handle, tasks.handle, C.byref(pv), C.byref(dv),
+                             C.byref(gv), C.byref(fv), int(reps), C.byref(tuned),
+                             _stream(stream)))
+    return tuned

@@ -1,0 +1,92 @@
+"""Loop shapes and the autotuner (sphx_autotune).
+
+* the candidate-buffer size (tile) does not change any result: each receiver
+  still adds its neighbours in the same order, only the buffer is flushed at
+  other points, so every output is bitwise the same;
+* the number of waves per cell changes only the FP32 summation order: every
+  shape agrees with the oracle at the parity tolerances;
+* the autotuner returns one of the allowed shapes and leaves h unchanged, and
+  contexts created from its result reproduce each other bitwise.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2305_13380_amd import inputs
+
+from helpers import check_density, check_force, check_ghost, gpu_fixed_h
+
+pytestmark = pytest.mark.gpu
+P = oracle.Params()
+
+SHAPES = [dict(density_tile=t, density_waves=w, force_tile=ft, force_waves=fw)
+          for t, w, ft, fw in [(256, 1, 128, 2), (64, 1, 64, 2), (256, 2, 128, 1),
+                               (128, 2, 64, 1)]]
+
+
+def case():
+    return inputs.lognormal_box(16, 6000, 2.0, 31)
+
+
+@pytest.fixture(scope="module")
+def runs():
+    ps = case()
+    out = {}
+    for sh in SHAPES:
+        key = tuple(sorted(sh.items()))
+        out[key] = gpu_fixed_h(ps, params=sh)
+    return ps, out
+
+
+def test_tile_size_is_bitwise_neutral(runs):
+    ps, out = runs
+    a = out[tuple(sorted(SHAPES[0].items()))]
+    b = out[tuple(sorted(SHAPES[1].items()))]  # other tiles, same waves
+    for k in ("rho", "rho_dh", "n", "n_dh", "div_sum", "curl_x", "nngb", "f", "P", "A", "ax",
+              "du_dt", "v_sig", "nforce"):
+        assert np.array_equal(a[k].view(np.uint8), b[k].view(np.uint8)), k
+    c = out[tuple(sorted(SHAPES[2].items()))]
+    d = out[tuple(sorted(SHAPES[3].items()))]  # other tiles, same waves for both loops
+    for k in ("rho", "nngb", "ax", "ay", "az", "du_dt", "v_sig", "nforce"):
+        assert np.array_equal(c[k].view(np.uint8), d[k].view(np.uint8)), k
+
+
+def test_every_shape_matches_the_oracle(runs):
+    ps, out = runs
+    h = ps.h.astype(np.float64)
+    ref = oracle.fixed_h_step(ps, P)
+    recv = np.arange(ps.n)
+    for key, g in out.items():
+        where = "shape %s" % (dict(key),)
+        check_density(g, ref, ps, h, recv, P, where)
+        check_ghost(g, ref, recv, where)
+        check_force(g, ref, ps, h, recv, P, where)
+
+
+def test_autotune_returns_a_shape_and_keeps_h():
+    import torch
+    from paper_2305_13380_amd import sphx
+    ps = inputs.lognormal_box(24, 20000, 2.0, 32)
+    ctx = sphx.Context()
+    dp = sphx.DeviceParticles.from_set(ps)
+    out = sphx.Outputs(ps.n)
+    grid = sphx.Grid(ctx, dp)
+    tasks = sphx.Tasks(ctx, grid, dp)
+    tuned = sphx.autotune(ctx, grid, tasks, dp, out, reps=2)
+    torch.cuda.synchronize()
+    assert tuned.density_tile in (64, 128, 256) and tuned.density_waves in (1, 2)
+    assert tuned.force_tile in (64, 128) and tuned.force_waves in (1, 2)
+    assert tuned.eta == ctx.params.eta and tuned.max_iter == ctx.params.max_iter
+    np.testing.assert_array_equal(dp.t["h"].cpu().numpy(), ps.h)
+    res = []
+    for _ in range(2):
+        c2 = sphx.Context(tuned)
+        g2 = sphx.Grid(c2, dp)
+        t2 = sphx.Tasks(c2, g2, dp)
+        o2 = sphx.Outputs(ps.n)
+        dp.t["h"].copy_(torch.from_numpy(ps.h).cuda())
+        sphx.step(c2, g2, t2, dp, o2)
+        torch.cuda.synchronize()
+        res.append({k: v.cpu().numpy() for k, v in {**o2.d, **o2.f}.items()})
+    for k in res[0]:
+        assert np.array_equal(res[0][k].view(np.uint8), res[1][k].view(np.uint8)), k
