@@ -195,6 +195,9 @@ def main():
     ap.add_argument("--config", default="clustered", choices=sorted(CONFIGS))
     ap.add_argument("--cpu-receivers", type=int, default=4096)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--graph", type=int, default=-1, metavar="K",
+                    help="captured passes per step (HIP graph); 0: pass by pass; "
+                         "-1 (default): the passes of a warm-up step if it needed no task rebuild")
     ap.add_argument("--no-tune", action="store_true",
                     help="default loop shapes instead of the autotuner's")
     ap.add_argument("--no-serving", action="store_true",
@@ -252,8 +255,43 @@ def main():
         shapes = {k: getattr(params, k) for k in ("density_tile", "density_waves", "force_tile",
                                                   "force_waves")}
         log("bench: autotune %.1f s -> %s" % (time.perf_counter() - t0, shapes))
-    ctx = sphx.Context(params, 0)
+    def run_steps(c, g, t, k):
+        infos = []
+        for _ in range(k):
+            dp.t["h"].copy_(h0)
+            st, info = sphx.step(c, g, t, dp, out)
+            infos.append(info)
+        return infos
 
+    # Pass by pass: warm-up, and the kernel durations (HIP events around every
+    # neighbour-loop launch on the stream it runs on).
+    params.graph_passes = 0
+    ctxp = sphx.Context(params, 0)
+    gridp = sphx.Grid(ctxp, dp)
+    tasksp = sphx.Tasks(ctxp, gridp, dp)
+    for w, info in enumerate(run_steps(ctxp, gridp, tasksp, max(args.warmup, 1))):
+        log("bench: warmup %d: passes=%d rebuilds=%d" % (w, info.passes, info.task_rebuilds))
+    # Captured passes: as many as the step needs when it needs no task rebuild
+    # (a rebuild ends the captured part early), else pass by pass.
+    graph_k = args.graph
+    if graph_k < 0:
+        graph_k = info.passes if info.task_rebuilds == 0 else 0
+    torch.cuda.synchronize()
+    ctxp.profile(True)
+    run_steps(ctxp, gridp, tasksp, args.steps)
+    torch.cuda.synchronize()
+    ctxp.profile(False)
+    dens_ms, dens_n = ctxp.profile_read(0)
+    force_ms, force_n = ctxp.profile_read(1)
+    dlist_ms, dlist_n = ctxp.profile_read(2)
+    build_ms, build_n = ctxp.profile_read(3)
+    tasksp.close()
+    gridp.close()
+    ctxp.close()
+
+    # The timed steps.
+    params.graph_passes = graph_k
+    ctx = sphx.Context(params, 0)
     t0 = time.perf_counter()
     grid = sphx.Grid(ctx, dp)
     torch.cuda.synchronize()
@@ -262,37 +300,22 @@ def main():
     tasks = sphx.Tasks(ctx, grid, dp)
     torch.cuda.synchronize()
     t_tasks = time.perf_counter() - t0
-    log("bench: grid %.1f ms (%d leaves), tasks %.1f ms (%d tasks)" % (
-        t_grid * 1e3, grid.n_leaves, t_tasks * 1e3, tasks.count))
-
-    def one_step():
-        dp.t["h"].copy_(h0)
-        return sphx.step(ctx, grid, tasks, dp, out)
-
-    for w in range(args.warmup):
-        st, info = one_step()
-        log("bench: warmup %d: passes=%d rebuilds=%d" % (w, info.passes, info.task_rebuilds))
+    log("bench: grid %.1f ms (%d leaves), tasks %.1f ms (%d tasks), %d captured passes" % (
+        t_grid * 1e3, grid.n_leaves, t_tasks * 1e3, tasks.count, graph_k))
+    run_steps(ctx, grid, tasks, 1)  # (captures the graph)
     torch.cuda.synchronize()
-    ctx.profile(True)
     start = torch.cuda.Event(enable_timing=True)
     stop = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
     start.record(stream)
-    infos = []
-    for k in range(args.steps):
-        st, info = one_step()
-        infos.append((info.passes, info.task_rebuilds, info.unconverged))
+    infos = run_steps(ctx, grid, tasks, args.steps)
     stop.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    ctx.profile(False)
     t_ev = start.elapsed_time(stop) / 1e3
     ms_step = t_ev / args.steps * 1e3
-    dens_ms, dens_n = ctx.profile_read(0)
-    force_ms, force_n = ctx.profile_read(1)
-    dlist_ms, dlist_n = ctx.profile_read(2)
-    build_ms, build_n = ctx.profile_read(3)
+    info = infos[-1]
+    infos = [(i.passes, i.task_rebuilds, i.unconverged) for i in infos]
     log("bench: %d steps in %.3f s (events) / %.3f s (wall); cell-pair density %.2f ms over %d "
         "launches, list density %.2f ms over %d, list build %.2f ms over %d, force %.2f ms "
         "over %d" % (args.steps, t_ev, wall, dens_ms, dens_n, dlist_ms, dlist_n, build_ms,
@@ -355,6 +378,7 @@ def main():
                    "list_builds_per_step": info.list_builds,
                    "list_fallback_receiver_passes": info.list_fallback,
                    "list_entries": info.list_entries, "loop_shapes": shapes,
+                   "graph_passes": graph_k,
                    "momentum_err_rel": mom, "energy_err_rel": en},
         "roofline": {"bound": "alu", "kernel": kern, "achieved": achieved,
                      "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",

@@ -86,6 +86,14 @@ typedef struct sphx_params {
     int32_t density_waves;
     int32_t force_tile;
     int32_t force_waves;
+    /* sphx_step: > 0 captures the first graph_passes passes of the h iteration
+     * and the force pass as one HIP graph (replayed while the handles and
+     * arrays stay the same; one readback instead of one per pass); the step
+     * continues pass by pass when the iteration needs more passes or a task
+     * rebuild. Results are identical to graph_passes = 0 (default 0; not
+     * combined with neighbour_lists). */
+    int32_t graph_passes;
+    int32_t reserved;
 } sphx_params;
 
 /* Particle-carried inputs (Section 3.1): positions FP64, the rest FP32. */

@@ -1,3 +1,4 @@
+#include <algorithm>
 // C-ABI entry points of the sphx library: argument validation, ownership of
 // the opaque handles, and the host side of the h iteration.
 #include <math.h>
@@ -114,6 +115,8 @@ void sphx_params_default(sphx_params *p)
     p->density_waves = 0;
     p->force_tile = 0;
     p->force_waves = 0;
+    p->graph_passes = 0;
+    p->reserved = 0;
 }
 
 const char *sphx_last_error(void) { return g_last_error.c_str(); }
@@ -143,6 +146,10 @@ sphx_status sphx_ctx_create(const sphx_params *p, int hip_device, sphx_ctx **out
         !one_of(p->force_tile, 64, 128, 64) || !one_of(p->force_waves, 1, 2, 1)) {
         set_error("sphx_ctx_create: loop shapes must be 0 or density_tile 64/128/256, "
                   "density_waves 1/2, force_tile 64/128, force_waves 1/2");
+        return SPHX_E_INVALID;
+    }
+    if (p->graph_passes < 0 || p->graph_passes > 64) {
+        set_error("sphx_ctx_create: graph_passes must be 0..64");
         return SPHX_E_INVALID;
     }
     int ndev = 0;
@@ -175,6 +182,7 @@ void sphx_ctx_destroy(sphx_ctx *ctx)
 {
     if (!ctx)
         return;
+    step_graph_free(ctx->graph);
     (void)hipFree(ctx->d_counters);
     (void)hipFree(ctx->d_sums);
     for (auto &v : ctx->prof->pool)
@@ -296,8 +304,8 @@ sphx_status sphx_step(sphx_ctx *ctx, sphx_grid *grid, sphx_tasks **tasks, sphx_p
     memset(&local, 0, sizeof(local));
     if (!*tasks)
         SPHX_TRY(tasks_build(ctx, grid, in, s, tasks));
-    SPHX_TRY(iter_reset(grid, in, s));
     alignas(8) unsigned char h_buf[kStepCounterBytes];
+    memset(h_buf, 0, sizeof(h_buf));
     int32_t h_counters[kStepCounters] = {0, 0, 0, 0, 0, 0, 0, 0};
     int32_t *dc = ctx->d_counters;
     unsigned long long *d_units =
@@ -305,12 +313,42 @@ sphx_status sphx_step(sphx_ctx *ctx, sphx_grid *grid, sphx_tasks **tasks, sphx_p
     SPHX_HIP(hipMemsetAsync(d_units, 0, 2 * sizeof(unsigned long long), s));
     const int max_iter = ctx->p.max_iter;
     bool want_lists = ctx->p.neighbour_lists != 0;
+    int pass = 0;
+    const int graph_passes = std::min(ctx->p.graph_passes, max_iter);
+    if (graph_passes > 0 && !want_lists && grid->n_leaves > 0) {
+        bool done = false, stale = false, rebuild = false;
+        SPHX_TRY(step_graph_run(ctx, grid, *tasks, in, dens, gst, out, d_sums6, graph_passes, s,
+                                &local, &pass, &done, &stale, &rebuild));
+        if (done) {
+            local.passes = pass;
+            local.n_leaves = grid->n_leaves;
+            local.n_tasks = (*tasks)->n_tasks;
+            if (info)
+                *info = local;
+            sphx_status w = SPHX_OK;
+            if (local.unconverged)
+                w |= SPHX_W_NOT_CONVERGED;
+            if (local.clamped)
+                w |= SPHX_W_H_CLAMPED;
+            return w;
+        }
+        // The iteration goes on pass by pass from the state the graph left.
+        if (stale || rebuild) {
+            SPHX_TRY(tasks_build(ctx, grid, in, s, tasks));
+            local.task_rebuilds++;
+        }
+        unsigned long long u[2] = {(unsigned long long)local.pairs_cellpair,
+                                   (unsigned long long)local.pairs_list};
+        memcpy(h_buf + kStepUnitsOffset, u, sizeof(u));
+    } else {
+        SPHX_TRY(iter_reset(grid, in, s));
+    }
     // lists: the neighbour lists are current (built on this task list, for
     // the receivers of the current pass); beyond: receivers of the next pass
     // whose H outgrew their list (they take the cell-pair loop).
     bool lists = false;
     int64_t beyond = 0;
-    int pass = 0, stale_repeats = 0;
+    int stale_repeats = 0;
     while (pass < max_iter) {
         SPHX_HIP(hipMemsetAsync(dc, 0, kStepCounters * sizeof(int32_t), s));
         if (!lists || beyond > 0)

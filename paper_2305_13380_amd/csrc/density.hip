@@ -102,8 +102,10 @@ __global__ __launch_bounds__(64 * NW) void k_density(
     const float4 *__restrict__ q1, const uint8_t *__restrict__ need, const float *__restrict__ hs,
     const float *__restrict__ radius, const int32_t *__restrict__ toff,
     const Task *__restrict__ task, float gamma_k, const float *__restrict__ lrad, DensOut o,
-    int32_t *__restrict__ counters)
+    int32_t *__restrict__ counters, const int32_t *__restrict__ skip)
 {
+    if (skip && *skip)
+        return;  // a captured pass with nothing left to do
     static_assert(CAP >= 64 && CAP <= 256, "candidate slots: one task's sources, 8-bit slots");
     const int64_t L = leaf_of_block(blockIdx.x, nb_padded, order);
     if (L >= n_leaves)
@@ -472,7 +474,7 @@ static DensOut dens_out(const sphx_grid *g, const sphx_density_out *o)
 
 sphx_status density_launch(const sphx_ctx *ctx, const sphx_grid *g, const sphx_tasks *t,
                            const sphx_particles *in, const sphx_density_out *o,
-                           int32_t *counters, bool use_lists, hipStream_t s)
+                           int32_t *counters, bool use_lists, hipStream_t s, const int32_t *skip)
 {
     if (g->n_leaves == 0)
         return SPHX_OK;
@@ -485,7 +487,7 @@ sphx_status density_launch(const sphx_ctx *ctx, const sphx_grid *g, const sphx_t
 #define SPHX_DENSITY_LAUNCH(CAP_, NW_)                                                         \
     k_density<CAP_, NW_, false><<<unsigned(nbp), 64 * NW_, 0, s>>>(                            \
         g->n_leaves, nbp, t->order, g->leaf_start, g->perm, g->q0, g->q1, g->need, g->hs,      \
-        t->radius, t->off, t->task, float(ctx->p.gamma_k), lr, dout, counters)
+        t->radius, t->off, t->task, float(ctx->p.gamma_k), lr, dout, counters, skip)
     if (waves == 1) {
         if (tile == 64)
             SPHX_DENSITY_LAUNCH(64, 1);

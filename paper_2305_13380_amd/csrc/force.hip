@@ -47,8 +47,10 @@ __global__ __launch_bounds__(64 * NW) void k_force(
     const int32_t *__restrict__ toff, const Task *__restrict__ task, float gamma_k, float beta,
     float *__restrict__ o_ax, float *__restrict__ o_ay, float *__restrict__ o_az,
     float *__restrict__ o_du, float *__restrict__ o_vsig, int32_t *__restrict__ o_nf,
-    double *__restrict__ fsum)
+    double *__restrict__ fsum, const int32_t *__restrict__ gate)
 {
+    if (gate && *gate)
+        return;  // a captured step whose iteration is not finished
     static_assert(CAP >= 64 && CAP <= 256, "candidate slots: one task's sources, 8-bit slots");
     const int64_t L = leaf_of_block(blockIdx.x, nb_padded, order);
     if (L >= n_leaves)
@@ -321,8 +323,11 @@ __global__ __launch_bounds__(64 * NW) void k_force(
 // Fixed-order FP64 reduction of the per-leaf partial sums (one block).
 __global__ __launch_bounds__(256) void k_sum_leaves(int64_t n_leaves,
                                                     const double *__restrict__ fsum,
-                                                    double *__restrict__ out)
+                                                    double *__restrict__ out,
+                                                    const int32_t *__restrict__ gate)
 {
+    if (gate && *gate)
+        return;
     __shared__ double red[6][256];
     const int t = threadIdx.x;
     double a[6] = {0, 0, 0, 0, 0, 0};
@@ -347,7 +352,7 @@ __global__ __launch_bounds__(256) void k_sum_leaves(int64_t n_leaves,
 sphx_status force_launch(const sphx_ctx *ctx, const sphx_grid *g, const sphx_tasks *t,
                          const sphx_particles *in, const sphx_density_out *d,
                          const sphx_ghost_out *gs, const sphx_force_out *o, double *sums6,
-                         hipStream_t s)
+                         hipStream_t s, const int32_t *gate)
 {
     if (g->n_leaves == 0) {
         if (sums6)
@@ -366,7 +371,7 @@ sphx_status force_launch(const sphx_ctx *ctx, const sphx_grid *g, const sphx_tas
     k_force<CAP_, NW_><<<unsigned(nbp), 64 * NW_, 0, s>>>(                                     \
         g->n_leaves, nbp, t->order, g->leaf_start, g->perm, g->q0, g->q1, g->qa, g->g0, g->g1, \
         in->active, t->off, t->task, float(ctx->p.gamma_k), float(ctx->p.beta_v), o->ax,       \
-        o->ay, o->az, o->du_dt, o->v_sig, o->nforce, g->fsum)
+        o->ay, o->az, o->du_dt, o->v_sig, o->nforce, g->fsum, gate)
     if (waves == 1) {
         if (tile == 64)
             SPHX_FORCE_LAUNCH(64, 1);
@@ -382,7 +387,7 @@ sphx_status force_launch(const sphx_ctx *ctx, const sphx_grid *g, const sphx_tas
     SPHX_HIP(hipGetLastError());
     SPHX_HIP(ctx->prof->end(1, s));
     if (sums6) {
-        k_sum_leaves<<<1, 256, 0, s>>>(g->n_leaves, g->fsum, sums6);
+        k_sum_leaves<<<1, 256, 0, s>>>(g->n_leaves, g->fsum, sums6, gate);
         SPHX_HIP(hipGetLastError());
     }
     return SPHX_OK;

@@ -27,8 +27,10 @@ __global__ __launch_bounds__(kGhostThreads) void k_ghost(int64_t n, const int32_
                         float *__restrict__ o_c, float *__restrict__ o_B,
                         float *__restrict__ o_A, float *__restrict__ o_div,
                         float *__restrict__ o_curl, uint8_t *__restrict__ o_conv,
-                        int32_t *__restrict__ counters)
+                        int32_t *__restrict__ counters, const int32_t *__restrict__ skip)
 {
+    if (skip && *skip)
+        return;  // a captured pass with nothing left to do
     // A density pass that ran with a stale task list is not used.
     const bool stale = counters && counters[3] > 0;
     int n_unconv = 0, n_rebuild = 0, n_clamped = 0, n_beyond = 0;
@@ -129,7 +131,7 @@ __global__ __launch_bounds__(kGhostThreads) void k_ghost(int64_t n, const int32_
 sphx_status ghost_launch(const sphx_ctx *ctx, sphx_grid *g, const sphx_tasks *t,
                          sphx_particles *in, const sphx_density_out *d, const sphx_ghost_out *o,
                          int32_t *counters, int final_pass, bool use_lists,
-                         unsigned long long *units, hipStream_t s)
+                         unsigned long long *units, hipStream_t s, const int32_t *skip)
 {
     if (g->n == 0)
         return SPHX_OK;
@@ -143,7 +145,7 @@ sphx_status ghost_launch(const sphx_ctx *ctx, sphx_grid *g, const sphx_tasks *t,
         float(P.h_tol),
         float(ctx->h_max), float(P.gamma_k), float(P.gamma_gas), float(P.eps_balsara),
         final_pass, d->nngb, units, o->f, o->P, o->c, o->balsara, o->A, o->div_v, o->curl_v, o->converged,
-        counters);
+        counters, skip);
     SPHX_HIP(hipGetLastError());
     return SPHX_OK;
 }

@@ -87,6 +87,9 @@ struct Profiler {
 };
 }  // namespace sphx
 
+namespace sphx {
+struct StepGraph;
+}
 struct sphx_ctx {
     sphx_params p;
     sphx::Profiler *prof;
@@ -94,6 +97,7 @@ struct sphx_ctx {
     double h_max;
     int32_t *d_counters;  // scratch counters used by sphx_step
     double *d_sums;       // scratch FP64 sums used by sphx_step when the caller passes none
+    sphx::StepGraph *graph = nullptr;  // captured step (graph_passes > 0)
 };
 
 struct sphx_grid {
@@ -199,7 +203,8 @@ size_t tasks_bytes(int64_t n);
 // only over those whose H exceeds their list radius.
 sphx_status density_launch(const sphx_ctx *ctx, const sphx_grid *g, const sphx_tasks *t,
                            const sphx_particles *in, const sphx_density_out *out,
-                           int32_t *counters, bool use_lists, hipStream_t s);
+                           int32_t *counters, bool use_lists, hipStream_t s,
+                           const int32_t *skip = nullptr);
 // List density pass over the receivers that need one and fit their lists.
 sphx_status density_list_launch(const sphx_ctx *ctx, const sphx_grid *g, const sphx_tasks *t,
                                 const sphx_density_out *out, hipStream_t s);
@@ -216,13 +221,30 @@ size_t lists_bytes(int64_t n);
 sphx_status ghost_launch(const sphx_ctx *ctx, sphx_grid *g, const sphx_tasks *t,
                          sphx_particles *in, const sphx_density_out *d, const sphx_ghost_out *o,
                          int32_t *counters, int final_pass, bool use_lists,
-                         unsigned long long *units, hipStream_t s);
+                         unsigned long long *units, hipStream_t s,
+                         const int32_t *skip = nullptr);
 
 // force.hip
 sphx_status force_launch(const sphx_ctx *ctx, const sphx_grid *g, const sphx_tasks *t,
                          const sphx_particles *in, const sphx_density_out *d,
                          const sphx_ghost_out *gs, const sphx_force_out *o, double *sums6,
-                         hipStream_t s);
+                         hipStream_t s, const int32_t *gate = nullptr);
+
+// graph.hip
+// Captured step: the h iteration's first `passes` passes and a gated force
+// pass as one HIP graph, replayed while the handles and arrays stay the same.
+// On return *done = true when the step is complete (converged, or finalised
+// by the last allowed pass) with force and sums computed; otherwise *pass
+// is the number of passes applied, *stale whether a pass met a stale task
+// list, *rebuild whether the last applied pass asked for a task rebuild, and
+// the caller continues the iteration from there.
+struct StepGraph;
+void step_graph_free(StepGraph *g);
+sphx_status step_graph_run(sphx_ctx *ctx, sphx_grid *grid, sphx_tasks *t, const sphx_particles *in,
+                           const sphx_density_out *dens, const sphx_ghost_out *gst,
+                           const sphx_force_out *out, double *sums6, int passes, hipStream_t s,
+                           sphx_step_info *info, int *pass, bool *done, bool *stale,
+                           bool *rebuild);
 
 // Blocks are dealt round-robin to the 8 XCDs of the MI355X; remap so that each
 // XCD works on a contiguous range of leaves (which share neighbour data in

@@ -36,7 +36,8 @@ class Params(C.Structure):
                 ("eps_balsara", C.c_double), ("skin", C.c_double), ("leaf_max", C.c_int32),
                 ("neighbour_lists", C.c_int32), ("density_tile", C.c_int32),
                 ("density_waves", C.c_int32), ("force_tile", C.c_int32),
-                ("force_waves", C.c_int32)]
+                ("force_waves", C.c_int32), ("graph_passes", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class Particles(C.Structure):
