@@ -92,9 +92,7 @@ __device__ __forceinline__ void dens_finish(const float (&S)[kSums], float hi, f
     o.nngb[gi] = int32_t(S[8]) - 1;
 }
 
-// BAL: the pair arithmetic of a compute round is spread evenly over the
-// wave's lanes (see compute_bal) instead of each lane walking its own list.
-template <int CAP, int NW, bool BAL>
+template <int CAP, int NW>
 __global__ __launch_bounds__(64 * NW) void k_density(
     int64_t n_leaves, int64_t nb_padded, const int32_t *__restrict__ order,
     const int32_t *__restrict__ leaf_start,
@@ -125,12 +123,6 @@ __global__ __launch_bounds__(64 * NW) void k_density(
     __shared__ float4 cp_all[NW][CAP];  // candidate x, y, z (receiver cell frame), m
     __shared__ float4 cv_all[NW][CAP];  // candidate vx, vy, vz
     __shared__ uint32_t lst_all[NW][kListStride * 16];
-    // BAL only: receivers' positions and (velocity, 1/H); the round's list
-    // offsets; segment partial sums ([start | end | complete][sum][lane]).
-    __shared__ float4 rp_all[NW][BAL ? 64 : 1];
-    __shared__ float4 rv_all[NW][BAL ? 64 : 1];
-    __shared__ int32_t ro_all[NW][BAL ? 68 : 1];
-    __shared__ float sp_all[NW][BAL ? 3 * kSums * 64 : 1];
     float4 *cp = cp_all[w];
     float4 *cv = cv_all[w];
     uint8_t *lst = reinterpret_cast<uint8_t *>(lst_all[w]);
@@ -162,14 +154,6 @@ __global__ __launch_bounds__(64 * NW) void k_density(
     float S[kSums] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     int nc = 0;   // buffered candidates (wave-uniform)
     int myn = 0;  // this lane's list length (its own particle is listed too)
-    float4 *rp = rp_all[w];
-    float4 *rv = rv_all[w];
-    int32_t *ro = ro_all[w];
-    float *sp = sp_all[w];
-    if (BAL) {
-        rp[lane] = pi;
-        rv[lane] = make_float4(vi.x, vi.y, vi.z, invH);
-    }
 
     // Four list entries at a time, without branches: entries past a lane's
     // list length read slot 0 (a candidate of the current buffer, so finite
@@ -192,96 +176,6 @@ __global__ __launch_bounds__(64 * NW) void k_density(
         }
         myn = 0;
     };
-    // Balanced round: the lanes' lists, concatenated in lane order (W entries),
-    // are cut into 64 contiguous ranges of equal length, lane l taking
-    // entries [l W / 64, (l + 1) W / 64) with the data of the receivers they
-    // belong to. A lane's range covers whole receivers (their sums go to the
-    // "complete" slot of the receiver) and at its ends parts of receivers
-    // shared with neighbouring lanes ("start": continues a receiver begun by
-    // an earlier lane; "end": cut off, continued by a later lane). Each
-    // receiver's lane then adds its parts in lane order, so the result does
-    // not depend on timing.
-    auto compute_bal = [&]() __attribute__((always_inline)) {
-        int incl = myn;
-        for (int o = 1; o < 64; o <<= 1) {
-            const int t = __shfl_up(incl, o, 64);
-            if (lane >= o)
-                incl += t;
-        }
-        const int W = __shfl(incl, 63, 64);
-        if (W == 0)
-            return;  // wave-uniform
-        ro[lane + 1] = incl;
-        if (lane == 0)
-            ro[0] = 0;
-        wave_sync();
-        const int a = (lane * W) >> 6;
-        const int b = ((lane + 1) * W) >> 6;
-        int r = 0;  // the receiver of entry a: the last r with ro[r] <= a
-#pragma unroll
-        for (int step = 32; step > 0; step >>= 1)
-            if (ro[r + step] <= a)
-                r += step;
-        int rs = ro[r], re = ro[r + 1];
-        int seg0 = a;
-        float4 P = rp[r], V = rv[r];
-        float T[kSums] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-        auto deposit = [&](int seg1) __attribute__((always_inline)) {
-            const int slot = (seg0 == rs && seg1 == re) ? 2 : (seg0 > rs ? 0 : 1);
-            const int idx = slot == 2 ? r : lane;
-#pragma unroll
-            for (int k = 0; k < kSums; ++k) {
-                sp[(slot * kSums + k) * 64 + idx] = T[k];
-                T[k] = 0.0f;
-            }
-        };
-        if (a == b) {
-#pragma unroll
-            for (int k = 0; k < kSums; ++k)
-                sp[k * 64 + lane] = 0.0f;  // an empty range adds nothing
-        }
-        const int nit = (W + 63) >> 6;
-        for (int t = 0; t < nit; ++t) {
-            const int k = a + t;
-            const bool ok = k < b;
-            if (ok && k >= re) {
-                deposit(k);
-                do {
-                    ++r;
-                    rs = ro[r];
-                    re = ro[r + 1];
-                } while (k >= re);
-                seg0 = k;
-                P = rp[r];
-                V = rv[r];
-            }
-            const int c = lst[r * kListStride + (ok ? k - rs : 0)];
-            dens_pair(T, P, V, V.w, cp[c], cv[c], ok);
-        }
-        if (a < b)
-            deposit(b);
-        wave_sync();
-        const int ms = incl - myn, me = incl;
-        if (me > ms) {
-            const int L0 = min((64 * (ms + 1) - 1) / W, 63);
-            const int L1 = min((64 * me - 1) / W, 63);
-            if (L0 == L1) {
-#pragma unroll
-                for (int k = 0; k < kSums; ++k)
-                    S[k] += sp[(2 * kSums + k) * 64 + lane];
-            } else {
-#pragma unroll
-                for (int k = 0; k < kSums; ++k)
-                    S[k] += sp[(kSums + k) * 64 + L0];
-                for (int l = L0 + 1; l <= L1; ++l)
-#pragma unroll
-                    for (int k = 0; k < kSums; ++k)
-                        S[k] += sp[k * 64 + l];
-            }
-        }
-        wave_sync();
-        myn = 0;
-    };
     // The slot is always written; it is kept (the length advanced) only
     // when the candidate lies inside H.
     auto accept = [&](int c, const float4 &p) __attribute__((always_inline)) {
@@ -298,19 +192,12 @@ __global__ __launch_bounds__(64 * NW) void k_density(
             accept(c + 1, p1);
             accept(c + 2, p2);
             accept(c + 3, p3);
-            if (__any(myn > kListMax - 4)) {
-                if (BAL)
-                    compute_bal();
-                else
-                    compute();
-            }
+            if (__any(myn > kListMax - 4))
+                compute();
         }
         for (; c < nc; ++c)
             accept(c, cp[c]);
-        if (BAL)
-            compute_bal();
-        else
-            compute();
+        compute();
         wave_sync();
         nc = 0;
     };
@@ -485,7 +372,7 @@ sphx_status density_launch(const sphx_ctx *ctx, const sphx_grid *g, const sphx_t
     const DensOut dout = dens_out(g, o);
     SPHX_HIP(ctx->prof->begin(0, s));
 #define SPHX_DENSITY_LAUNCH(CAP_, NW_)                                                         \
-    k_density<CAP_, NW_, false><<<unsigned(nbp), 64 * NW_, 0, s>>>(                            \
+    k_density<CAP_, NW_><<<unsigned(nbp), 64 * NW_, 0, s>>>(                            \
         g->n_leaves, nbp, t->order, g->leaf_start, g->perm, g->q0, g->q1, g->need, g->hs,      \
         t->radius, t->off, t->task, float(ctx->p.gamma_k), lr, dout, counters, skip)
     if (waves == 1) {
