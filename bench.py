@@ -198,6 +198,10 @@ def main():
     ap.add_argument("--graph", type=int, default=-1, metavar="K",
                     help="captured passes per step (HIP graph); 0: pass by pass; "
                          "-1 (default): the passes of a warm-up step if it needed no task rebuild")
+    ap.add_argument("--skin", type=float, default=0.1,
+                    help="relative enlargement of the task search radii")
+    ap.add_argument("--leaf-max", type=int, default=64,
+                    help="particles per leaf cell (8..64)")
     ap.add_argument("--no-tune", action="store_true",
                     help="default loop shapes instead of the autotuner's")
     ap.add_argument("--no-serving", action="store_true",
@@ -233,7 +237,7 @@ def main():
     log("bench: %s: N=%d generated in %.1f s" % (args.config, ps.n, time.perf_counter() - t0))
 
     dev = "cuda:0"
-    params = sphx.default_params()
+    params = sphx.default_params(leaf_max=args.leaf_max, skin=args.skin)
     dp = sphx.DeviceParticles.from_set(ps, dev)
     out = sphx.Outputs(ps.n, dev)
     h0 = dp.t["h"].clone()
@@ -252,8 +256,8 @@ def main():
         k0.close()
         g0.close()
         c0.close()
-        shapes = {k: getattr(params, k) for k in ("density_tile", "density_waves", "force_tile",
-                                                  "force_waves")}
+        shapes = {k: getattr(params, k) for k in ("density_tile", "density_waves",
+                                                  "density_balance", "force_tile", "force_waves")}
         log("bench: autotune %.1f s -> %s" % (time.perf_counter() - t0, shapes))
     def run_steps(c, g, t, k):
         infos = []
@@ -378,7 +382,7 @@ def main():
                    "list_builds_per_step": info.list_builds,
                    "list_fallback_receiver_passes": info.list_fallback,
                    "list_entries": info.list_entries, "loop_shapes": shapes,
-                   "graph_passes": graph_k,
+                   "graph_passes": graph_k, "leaf_max": args.leaf_max, "skin": args.skin,
                    "momentum_err_rel": mom, "energy_err_rel": en},
         "roofline": {"bound": "alu", "kernel": kern, "achieved": achieved,
                      "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",

@@ -93,7 +93,10 @@ typedef struct sphx_params {
      * rebuild. Results are identical to graph_passes = 0 (default 0; not
      * combined with neighbour_lists). */
     int32_t graph_passes;
-    int32_t reserved;
+    /* Density loop: 1 spreads each compute round's pair work evenly over the
+     * wave's lanes (lists cut into chunks of one receiver each), 0 (default)
+     * lets every lane walk its own list. Changes the FP32 summation order. */
+    int32_t density_balance;
 } sphx_params;
 
 /* Particle-carried inputs (Section 3.1): positions FP64, the rest FP32. */

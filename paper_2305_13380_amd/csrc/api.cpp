@@ -116,7 +116,7 @@ void sphx_params_default(sphx_params *p)
     p->force_tile = 0;
     p->force_waves = 0;
     p->graph_passes = 0;
-    p->reserved = 0;
+    p->density_balance = 0;
 }
 
 const char *sphx_last_error(void) { return g_last_error.c_str(); }
@@ -148,8 +148,9 @@ sphx_status sphx_ctx_create(const sphx_params *p, int hip_device, sphx_ctx **out
                   "density_waves 1/2, force_tile 64/128, force_waves 1/2");
         return SPHX_E_INVALID;
     }
-    if (p->graph_passes < 0 || p->graph_passes > 64) {
-        set_error("sphx_ctx_create: graph_passes must be 0..64");
+    if (p->graph_passes < 0 || p->graph_passes > 64 || p->density_balance < 0 ||
+        p->density_balance > 1) {
+        set_error("sphx_ctx_create: graph_passes must be 0..64 and density_balance 0 or 1");
         return SPHX_E_INVALID;
     }
     int ndev = 0;
@@ -467,12 +468,15 @@ sphx_status sphx_autotune(sphx_ctx *ctx, sphx_grid *grid, sphx_tasks *tasks, sph
     };
     sphx_status st = SPHX_OK;
     auto run = [&]() -> sphx_status {
-        const int32_t dshape[6][2] = {{128, 1}, {64, 1}, {256, 1}, {128, 2}, {64, 2}, {256, 2}};
+        // tile, waves, balance
+        const int32_t dshape[8][3] = {{128, 1, 0}, {64, 1, 0}, {256, 1, 0}, {128, 2, 0},
+                                      {64, 2, 0},  {128, 1, 1}, {64, 1, 1}, {256, 1, 1}};
         double best = 1e300;
-        int32_t bt = 128, bw = 1;
+        int32_t bt = 128, bw = 1, bb = 0;
         for (auto &sh : dshape) {
             ctx->p.density_tile = sh[0];
             ctx->p.density_waves = sh[1];
+            ctx->p.density_balance = sh[2];
             double ms = 0.0;
             SPHX_TRY(timed([&]() { return iter_reset(grid, in, s); },
                            [&]() { return density_launch(ctx, grid, tasks, in, dens, nullptr, false,
@@ -482,10 +486,12 @@ sphx_status sphx_autotune(sphx_ctx *ctx, sphx_grid *grid, sphx_tasks *tasks, sph
                 best = ms;
                 bt = sh[0];
                 bw = sh[1];
+                bb = sh[2];
             }
         }
         ctx->p.density_tile = bt;
         ctx->p.density_waves = bw;
+        ctx->p.density_balance = bb;
         // force state at the current h: one density pass and a finalising ghost
         SPHX_TRY(iter_reset(grid, in, s));
         SPHX_TRY(density_launch(ctx, grid, tasks, in, dens, nullptr, false, s));
@@ -510,6 +516,7 @@ sphx_status sphx_autotune(sphx_ctx *ctx, sphx_grid *grid, sphx_tasks *tasks, sph
         *tuned = saved;
         tuned->density_tile = bt;
         tuned->density_waves = bw;
+        tuned->density_balance = bb;
         tuned->force_tile = ft;
         tuned->force_waves = fw;
         return SPHX_OK;

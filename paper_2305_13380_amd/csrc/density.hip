@@ -92,15 +92,19 @@ __device__ __forceinline__ void dens_finish(const float (&S)[kSums], float hi, f
     o.nngb[gi] = int32_t(S[8]) - 1;
 }
 
-template <int CAP, int NW>
+// BAL: compute rounds cut the lanes' lists into chunks of one receiver each
+// and spread them over the lanes (compute_bal) instead of each lane walking
+// its own list.
+template <int CAP, int NW, bool BAL>
 __global__ __launch_bounds__(64 * NW) void k_density(
     int64_t n_leaves, int64_t nb_padded, const int32_t *__restrict__ order,
     const int32_t *__restrict__ leaf_start,
     const int32_t *__restrict__ perm, const float4 *__restrict__ q0,
     const float4 *__restrict__ q1, const uint8_t *__restrict__ need, const float *__restrict__ hs,
     const float *__restrict__ radius, const int32_t *__restrict__ toff,
-    const Task *__restrict__ task, float gamma_k, const float *__restrict__ lrad, DensOut o,
-    int32_t *__restrict__ counters, const int32_t *__restrict__ skip)
+    const Task *__restrict__ task, const float4 *__restrict__ ext, float gamma_k,
+    const float *__restrict__ lrad, DensOut o, int32_t *__restrict__ counters,
+    const int32_t *__restrict__ skip)
 {
     if (skip && *skip)
         return;  // a captured pass with nothing left to do
@@ -123,6 +127,12 @@ __global__ __launch_bounds__(64 * NW) void k_density(
     __shared__ float4 cp_all[NW][CAP];  // candidate x, y, z (receiver cell frame), m
     __shared__ float4 cv_all[NW][CAP];  // candidate vx, vy, vz
     __shared__ uint32_t lst_all[NW][kListStride * 16];
+    // BAL only: the receivers' positions and (velocity, 1/H), each receiver's
+    // first chunk of the round, and the chunks' partial sums ([sum][slot]).
+    __shared__ float4 rp_all[NW][BAL ? 64 : 1];
+    __shared__ float4 rv_all[NW][BAL ? 64 : 1];
+    __shared__ int32_t cb_all[NW][BAL ? 68 : 1];
+    __shared__ float pt_all[NW][BAL ? kSums * 64 : 1];
     float4 *cp = cp_all[w];
     float4 *cv = cv_all[w];
     uint8_t *lst = reinterpret_cast<uint8_t *>(lst_all[w]);
@@ -154,6 +164,14 @@ __global__ __launch_bounds__(64 * NW) void k_density(
     float S[kSums] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     int nc = 0;   // buffered candidates (wave-uniform)
     int myn = 0;  // this lane's list length (its own particle is listed too)
+    float4 *rp = rp_all[w];
+    float4 *rv = rv_all[w];
+    int32_t *cb = cb_all[w];
+    float *pt = pt_all[w];
+    if (BAL) {
+        rp[lane] = pi;
+        rv[lane] = make_float4(vi.x, vi.y, vi.z, invH);
+    }
 
     // Four list entries at a time, without branches: entries past a lane's
     // list length read slot 0 (a candidate of the current buffer, so finite
@@ -176,6 +194,84 @@ __global__ __launch_bounds__(64 * NW) void k_density(
         }
         myn = 0;
     };
+    // Balanced round. The lists are cut into chunks of C entries (C a multiple
+    // of 4) of one receiver each, numbered receiver by receiver; lane l takes
+    // chunk j*64 + l in sub-round j and runs it like compute() with that
+    // receiver's data. C is the candidate with the least work (sub-rounds x C)
+    // among W/64, W/48, W/32 and the longest list. Each chunk's sums go to an
+    // LDS slot; the receiver's lane adds its chunks in chunk order, so the
+    // result does not depend on timing.
+    auto compute_bal = [&]() __attribute__((always_inline)) {
+        wave_sync();  // the other lanes' lists are read below
+        const int W = wave_sumi(myn);
+        if (W == 0)
+            return;  // wave-uniform
+        const int mx = wave_maxi(myn);
+        int C = 0, T = 0, cost = 0x7fffffff;
+        const int cand[4] = {(W + 63) / 64, (W + 47) / 48, (W + 31) / 32, mx};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int Cq = (cand[q] + 3) & ~3;
+            const int Tq = wave_sumi((myn + Cq - 1) / Cq);
+            const int cq = ((Tq + 63) / 64) * Cq;
+            if (cq < cost) {
+                cost = cq;
+                C = Cq;
+                T = Tq;
+            }
+        }
+        const int nch = (myn + C - 1) / C;
+        int incl = nch;  // inclusive prefix of the chunk counts
+        for (int o = 1; o < 64; o <<= 1) {
+            const int t = __shfl_up(incl, o, 64);
+            if (lane >= o)
+                incl += t;
+        }
+        cb[lane + 1] = incl;
+        if (lane == 0)
+            cb[0] = 0;
+        wave_sync();
+        for (int j0 = 0; j0 < T; j0 += 64) {
+            const int id = j0 + lane;
+            int r = 0;  // the receiver of chunk id: the last r with cb[r] <= id
+#pragma unroll
+            for (int step = 32; step > 0; step >>= 1)
+                if (cb[r + step] <= id)
+                    r += step;
+            const int mr = __shfl(myn, r, 64);
+            const int k0 = (id - cb[r]) * C;
+            const int len = id < T ? min(C, mr - k0) : 0;
+            const float4 P = rp[r], V = rv[r];
+            const uint8_t *rl = lst + r * kListStride + (id < T ? k0 : 0);
+            float Tc[kSums] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+            for (int k = 0; __any(k < len); k += 4) {
+                const uint32_t four = k < len ? *reinterpret_cast<const uint32_t *>(rl + k) : 0u;
+                float4 p[4], v[4];
+                bool on[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    on[q] = k + q < len;
+                    const int c = on[q] ? int((four >> (8 * q)) & 0xffu) : 0;
+                    p[q] = cp[c];
+                    v[q] = cv[c];
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    dens_pair(Tc, P, V, V.w, p[q], v[q], on[q]);
+            }
+#pragma unroll
+            for (int k = 0; k < kSums; ++k)
+                pt[k * 64 + lane] = Tc[k];
+            wave_sync();
+            const int c0 = max(incl - nch, j0), c1 = min(incl, j0 + 64);
+            for (int c = c0; c < c1; ++c)
+#pragma unroll
+                for (int k = 0; k < kSums; ++k)
+                    S[k] += pt[k * 64 + (c - j0)];
+            wave_sync();
+        }
+        myn = 0;
+    };
     // The slot is always written; it is kept (the length advanced) only
     // when the candidate lies inside H.
     auto accept = [&](int c, const float4 &p) __attribute__((always_inline)) {
@@ -192,12 +288,19 @@ __global__ __launch_bounds__(64 * NW) void k_density(
             accept(c + 1, p1);
             accept(c + 2, p2);
             accept(c + 3, p3);
-            if (__any(myn > kListMax - 4))
-                compute();
+            if (__any(myn > kListMax - 4)) {
+                if (BAL)
+                    compute_bal();
+                else
+                    compute();
+            }
         }
         for (; c < nc; ++c)
             accept(c, cp[c]);
-        compute();
+        if (BAL)
+            compute_bal();
+        else
+            compute();
         wave_sync();
         nc = 0;
     };
@@ -226,6 +329,9 @@ __global__ __launch_bounds__(64 * NW) void k_density(
         const int nb = min(64, t_end - tb);
         TaskRegs tr;
         tr.load(task, tb + lane, lane < nb);
+        // whole source cells beyond R of the receivers' box are skipped
+        if (lane < nb && task_box_dist2(tr.b.x, tr.b.y, tr.b.z, ext[tr.a.w], lo, hb) >= R2)
+            tr.a.y = 0;
         for (int u = 0; u < nb; u += 4) {
             int j0[4], jc[4];
             float ox[4], oy[4], oz[4];
@@ -368,27 +474,36 @@ sphx_status density_launch(const sphx_ctx *ctx, const sphx_grid *g, const sphx_t
     const int64_t nbp = pad8(g->n_leaves);
     const int tile = ctx->p.density_tile ? ctx->p.density_tile : 128;
     const int waves = ctx->p.density_waves ? ctx->p.density_waves : 1;
+    const bool bal = ctx->p.density_balance == 1;
     const float *lr = use_lists ? g->lrad : nullptr;
     const DensOut dout = dens_out(g, o);
     SPHX_HIP(ctx->prof->begin(0, s));
-#define SPHX_DENSITY_LAUNCH(CAP_, NW_)                                                         \
-    k_density<CAP_, NW_><<<unsigned(nbp), 64 * NW_, 0, s>>>(                            \
+#define SPHX_DENSITY_LAUNCH(CAP_, NW_, BAL_)                                                   \
+    k_density<CAP_, NW_, BAL_><<<unsigned(nbp), 64 * NW_, 0, s>>>(                             \
         g->n_leaves, nbp, t->order, g->leaf_start, g->perm, g->q0, g->q1, g->need, g->hs,      \
-        t->radius, t->off, t->task, float(ctx->p.gamma_k), lr, dout, counters, skip)
-    if (waves == 1) {
+        t->radius, t->off, t->task, g->leaf_ext, float(ctx->p.gamma_k), lr, dout, counters,   \
+        skip)
+    if (bal) {
         if (tile == 64)
-            SPHX_DENSITY_LAUNCH(64, 1);
+            SPHX_DENSITY_LAUNCH(64, 1, true);
         else if (tile == 128)
-            SPHX_DENSITY_LAUNCH(128, 1);
+            SPHX_DENSITY_LAUNCH(128, 1, true);
         else
-            SPHX_DENSITY_LAUNCH(256, 1);
+            SPHX_DENSITY_LAUNCH(256, 1, true);
+    } else if (waves == 1) {
+        if (tile == 64)
+            SPHX_DENSITY_LAUNCH(64, 1, false);
+        else if (tile == 128)
+            SPHX_DENSITY_LAUNCH(128, 1, false);
+        else
+            SPHX_DENSITY_LAUNCH(256, 1, false);
     } else {
         if (tile == 64)
-            SPHX_DENSITY_LAUNCH(64, 2);
+            SPHX_DENSITY_LAUNCH(64, 2, false);
         else if (tile == 128)
-            SPHX_DENSITY_LAUNCH(128, 2);
+            SPHX_DENSITY_LAUNCH(128, 2, false);
         else
-            SPHX_DENSITY_LAUNCH(256, 2);
+            SPHX_DENSITY_LAUNCH(256, 2, false);
     }
 #undef SPHX_DENSITY_LAUNCH
     SPHX_HIP(hipGetLastError());

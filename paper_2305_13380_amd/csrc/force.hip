@@ -44,7 +44,8 @@ __global__ __launch_bounds__(64 * NW) void k_force(
     const int32_t *__restrict__ perm, const float4 *__restrict__ q0,
     const float4 *__restrict__ q1, const float2 *__restrict__ qa, const float4 *__restrict__ g0,
     const float4 *__restrict__ g1, const uint8_t *__restrict__ active,
-    const int32_t *__restrict__ toff, const Task *__restrict__ task, float gamma_k, float beta,
+    const int32_t *__restrict__ toff, const Task *__restrict__ task,
+    const float4 *__restrict__ ext, const float *__restrict__ radius, float gamma_k, float beta,
     float *__restrict__ o_ax, float *__restrict__ o_ay, float *__restrict__ o_az,
     float *__restrict__ o_du, float *__restrict__ o_vsig, int32_t *__restrict__ o_nf,
     double *__restrict__ fsum, const int32_t *__restrict__ gate)
@@ -225,6 +226,13 @@ __global__ __launch_bounds__(64 * NW) void k_force(
         const int nb = min(64, t_end - tb);
         TaskRegs tr;
         tr.load(task, tb + lane, lane < nb);
+        // whole source cells beyond max(R, the cell's search radius) of the
+        // receivers' box are skipped (the radius bounds every H_j of the cell)
+        if (lane < nb) {
+            const float rj = radius[tr.a.w];
+            if (task_box_dist2(tr.b.x, tr.b.y, tr.b.z, ext[tr.a.w], lo, hb) >= fmaxf(R2, rj * rj))
+                tr.a.y = 0;
+        }
         for (int u = 0; u < nb; u += 4) {
             int j0[4], jc[4];
             float ox[4], oy[4], oz[4];
@@ -370,7 +378,8 @@ sphx_status force_launch(const sphx_ctx *ctx, const sphx_grid *g, const sphx_tas
 #define SPHX_FORCE_LAUNCH(CAP_, NW_)                                                           \
     k_force<CAP_, NW_><<<unsigned(nbp), 64 * NW_, 0, s>>>(                                     \
         g->n_leaves, nbp, t->order, g->leaf_start, g->perm, g->q0, g->q1, g->qa, g->g0, g->g1, \
-        in->active, t->off, t->task, float(ctx->p.gamma_k), float(ctx->p.beta_v), o->ax,       \
+        in->active, t->off, t->task, g->leaf_ext, t->radius, float(ctx->p.gamma_k),            \
+        float(ctx->p.beta_v), o->ax,                                                           \
         o->ay, o->az, o->du_dt, o->v_sig, o->nforce, g->fsum, gate)
     if (waves == 1) {
         if (tile == 64)

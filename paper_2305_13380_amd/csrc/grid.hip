@@ -4,7 +4,7 @@
 #include <rocprim/device/device_radix_sort.hpp>
 #include <rocprim/device/device_scan.hpp>
 
-#include "sphx_internal.h"
+#include "pairs.h"
 
 namespace sphx {
 namespace {
@@ -251,7 +251,8 @@ __global__ __launch_bounds__(64) void k_leaf_setup(
     const float *__restrict__ m, const float *__restrict__ u, const float *__restrict__ av,
     const float *__restrict__ ac, double Lx, double Ly, double Lz, int periodic,
     double *__restrict__ org, double *__restrict__ node_lo, double *__restrict__ node_hi,
-    float4 *__restrict__ q0, float4 *__restrict__ q1, float2 *__restrict__ qa)
+    float4 *__restrict__ q0, float4 *__restrict__ q1, float2 *__restrict__ qa,
+    float4 *__restrict__ ext)
 {
     int64_t L = blockIdx.x;
     if (L >= n_leaves)
@@ -277,11 +278,17 @@ __global__ __launch_bounds__(64) void k_leaf_setup(
         node_hi[3 * L + 1] = hiy;
         node_hi[3 * L + 2] = hiz;
     }
+    const float fx = float(px - lox), fy = float(py - loy), fz = float(pz - loz);
     if (valid) {
-        q0[s] = make_float4(float(px - lox), float(py - loy), float(pz - loz), m[i]);
+        q0[s] = make_float4(fx, fy, fz, m[i]);
         q1[s] = make_float4(vx[i], vy[i], vz[i], u[i]);
         qa[s] = make_float2(av[i], ac[i]);
     }
+    // the cell's extent in its own frame, from the stored FP32 coordinates
+    const float ex = wave_maxf(valid ? fx : 0.0f), ey = wave_maxf(valid ? fy : 0.0f),
+                ez = wave_maxf(valid ? fz : 0.0f);
+    if (lane == 0)
+        ext[L] = make_float4(ex, ey, ez, 0.0f);
 }
 
 // Tree over the leaves: node c of level l+1 covers nodes [8c, 8c+8) of level l.
@@ -342,7 +349,7 @@ size_t grid_bytes(int64_t n)
     size_t per = 8 * 2 + 4 * 2 + 4 + 4 * 2 + 16 * 2 + 8 + 1 + 16 * 2 + 4 + 32;
     // per leaf (at most n leaves): start, origin, tree nodes (~8/7 of the
     // leaves: lo, hi, radius), partial sums
-    size_t per_leaf = 4 + 24 + (48 + 4) * 8 / 7 + 1 + 48;
+    size_t per_leaf = 4 + 24 + 16 + (48 + 4) * 8 / 7 + 1 + 48;
     size_t sort_tmp = size_t(n) * 16 + (1 << 20);
     return size_t(n) * (per + per_leaf) + sort_tmp + (1 << 16);
 }
@@ -355,7 +362,8 @@ void grid_free(sphx_grid *g)
                     g->need,    g->g0,       g->g1,       g->leaf_start, g->leaf_org, g->node_lo,
                     g->node_hi, g->node_r,   g->fsum,     g->sort_tmp, g->keys_in, g->idx_in,
                     g->flags,   g->d_status, g->hs,       g->d0,       g->d1,
-                    g->lrad,    g->lcnt,     g->lcap,     g->lboff,    g->lst,    g->lscan_tmp};
+                    g->lrad,    g->lcnt,     g->lcap,     g->lboff,    g->lst,    g->lscan_tmp,
+                    g->leaf_ext};
     for (void *p : ptrs)
         dfree(p, g->stream);
     delete g;
@@ -518,6 +526,7 @@ sphx_status grid_build(sphx_ctx *ctx, const sphx_particles *in, hipStream_t s, s
     g->n_levels = lev;
     g->n_nodes = off;
     SPHX_TRY(dalloc(&g->leaf_org, 3 * nl, s));
+    SPHX_TRY(dalloc(&g->leaf_ext, nl, s));
     SPHX_TRY(dalloc(&g->node_lo, 3 * off, s));
     SPHX_TRY(dalloc(&g->node_hi, 3 * off, s));
     SPHX_TRY(dalloc(&g->node_r, off, s));
@@ -527,7 +536,7 @@ sphx_status grid_build(sphx_ctx *ctx, const sphx_particles *in, hipStream_t s, s
                                              in->vx, in->vy, in->vz, in->m, in->u, in->alpha_v,
                                              in->alpha_c, P.box[0], P.box[1], P.box[2],
                                              P.periodic, g->leaf_org, g->node_lo, g->node_hi,
-                                             g->q0, g->q1, g->qa);
+                                             g->q0, g->q1, g->qa, g->leaf_ext);
     SPHX_HIP(hipGetLastError());
     for (int l = 0; l + 1 < g->n_levels; ++l) {
         int64_t up = g->level_cnt[l + 1];

@@ -26,7 +26,8 @@ __global__ __launch_bounds__(64) void k_list(
     const int32_t *__restrict__ leaf_start,
     const float4 *__restrict__ q0, const uint8_t *__restrict__ need, const float *__restrict__ hs,
     const float *__restrict__ radius, const int32_t *__restrict__ toff,
-    const Task *__restrict__ task, float list_scale, float *__restrict__ lrad,
+    const Task *__restrict__ task, const float4 *__restrict__ ext, float list_scale,
+    float *__restrict__ lrad,
     int32_t *__restrict__ lcnt, const int64_t *__restrict__ lboff, uint32_t *__restrict__ lst)
 {
     const int64_t L = leaf_of_block(blockIdx.x, nb_padded, order);
@@ -141,6 +142,8 @@ __global__ __launch_bounds__(64) void k_list(
         const int nb = min(64, tn - tb);
         TaskRegs tr;
         tr.load(task, ta + tb + lane, lane < nb);
+        if (lane < nb && task_box_dist2(tr.b.x, tr.b.y, tr.b.z, ext[tr.a.w], lo, hb) >= R2)
+            tr.a.y = 0;  // whole source cells beyond R of the receivers' box
         for (int u = 0; u < nb; u += 4) {
             int j0[4], jc[4];
             float ox[4], oy[4], oz[4];
@@ -228,9 +231,9 @@ sphx_status list_build(const sphx_ctx *ctx, sphx_grid *g, const sphx_tasks *t, h
     const int64_t nlp = pad8(nl);
     const float scale = float(ctx->p.gamma_k * (1.0 + ctx->p.skin));
     SPHX_HIP(ctx->prof->begin(3, s));
-    k_list<false><<<unsigned(nlp), 64, 0, s>>>(nl, nlp, t->order, g->leaf_start, g->q0, g->need, g->hs,
-                                               t->radius, t->off, t->task, scale, g->lrad, g->lcnt,
-                                               nullptr, nullptr);
+    k_list<false><<<unsigned(nlp), 64, 0, s>>>(nl, nlp, t->order, g->leaf_start, g->q0, g->need,
+                                               g->hs, t->radius, t->off, t->task, g->leaf_ext,
+                                               scale, g->lrad, g->lcnt, nullptr, nullptr);
     SPHX_HIP(hipGetLastError());
     k_list_cap<<<unsigned((nb + 1 + 3) / 4), 256, 0, s>>>(n, nb, g->lcnt, g->lcap);
     SPHX_HIP(hipGetLastError());
@@ -255,9 +258,9 @@ sphx_status list_build(const sphx_ctx *ctx, sphx_grid *g, const sphx_tasks *t, h
     }
     g->lst_total = total;
     SPHX_HIP(ctx->prof->begin(3, s));
-    k_list<true><<<unsigned(nlp), 64, 0, s>>>(nl, nlp, t->order, g->leaf_start, g->q0, g->need, g->hs,
-                                              t->radius, t->off, t->task, scale, g->lrad, g->lcnt,
-                                              g->lboff, g->lst);
+    k_list<true><<<unsigned(nlp), 64, 0, s>>>(nl, nlp, t->order, g->leaf_start, g->q0, g->need,
+                                              g->hs, t->radius, t->off, t->task, g->leaf_ext,
+                                              scale, g->lrad, g->lcnt, g->lboff, g->lst);
     SPHX_HIP(hipGetLastError());
     SPHX_HIP(ctx->prof->end(3, s));
     *ok = true;

@@ -42,6 +42,12 @@ __device__ __forceinline__ float wave_maxf(float v)
         v = fmaxf(v, __shfl_xor(v, o, 64));
     return v;
 }
+__device__ __forceinline__ int wave_sumi(int v)
+{
+    for (int o = 32; o > 0; o >>= 1)
+        v += __shfl_xor(v, o, 64);
+    return v;
+}
 __device__ __forceinline__ int wave_maxi(int v)
 {
     for (int o = 32; o > 0; o >>= 1)
@@ -96,6 +102,20 @@ struct TaskRegs {
 __device__ __forceinline__ float dist2(float dx, float dy, float dz)
 {
     return __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
+}
+
+// Squared distance between the box [lo, hi] and a task's source cell,
+// [o, o + e] in the receiving cell's frame (o the task's offset, e the cell's
+// FP32 extent). FP32 addition is monotone, so no particle of the cell lies
+// closer (box_dist2 of each particle is >= this): skipping a task whose
+// distance is >= R^2 drops no particle that the per-particle cull keeps.
+__device__ __forceinline__ float task_box_dist2(float ox, float oy, float oz, float4 e, float3 lo,
+                                                float3 hi)
+{
+    const float dx = fmaxf(fmaxf(lo.x - (ox + e.x), ox - hi.x), 0.0f);
+    const float dy = fmaxf(fmaxf(lo.y - (oy + e.y), oy - hi.y), 0.0f);
+    const float dz = fmaxf(fmaxf(lo.z - (oz + e.z), oz - hi.z), 0.0f);
+    return dist2(dx, dy, dz);
 }
 
 // Squared distance from p to the box [lo, hi].

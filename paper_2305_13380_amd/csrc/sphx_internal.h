@@ -128,6 +128,7 @@ struct sphx_grid {
     // per leaf
     int32_t *leaf_start;  // n_leaves + 1
     double *leaf_org;     // 3 * n_leaves, FP64 origin (minimum corner of the particles' box)
+    float4 *leaf_ext;     // n_leaves: largest FP32 cell-relative x, y, z of the leaf's particles
 
     // per tree node (all levels)
     double *node_lo;    // 3 * n_nodes

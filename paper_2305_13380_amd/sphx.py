@@ -37,7 +37,7 @@ class Params(C.Structure):
                 ("neighbour_lists", C.c_int32), ("density_tile", C.c_int32),
                 ("density_waves", C.c_int32), ("force_tile", C.c_int32),
                 ("force_waves", C.c_int32), ("graph_passes", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("density_balance", C.c_int32)]
 
 
 class Particles(C.Structure):

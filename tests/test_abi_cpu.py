@@ -51,7 +51,7 @@ def test_default_params_are_the_papers(sphx):
     assert p.eta == 1.2348 and p.leaf_max == 64 and p.max_iter == 30
     assert p.neighbour_lists == 0
     assert (p.density_tile, p.density_waves, p.force_tile, p.force_waves) == (0, 0, 0, 0)
-    assert p.graph_passes == 0
+    assert p.graph_passes == 0 and p.density_balance == 0
 
 
 @pytest.mark.parametrize("field,value", [("eta", 0.0), ("h_tol", -1.0), ("max_iter", 0),
@@ -59,7 +59,8 @@ def test_default_params_are_the_papers(sphx):
                                          ("box", (1.0, 0.0, 1.0)), ("gamma_gas", 1.0),
                                          ("density_tile", 100), ("density_waves", 3),
                                          ("force_tile", 256), ("force_tile", 32), ("force_waves", -1),
-                                         ("graph_passes", -1), ("graph_passes", 65)])
+                                         ("graph_passes", -1), ("graph_passes", 65),
+                                         ("density_balance", 2)])
 def test_ctx_create_rejects_invalid_params(sphx, field, value):
     p = sphx.default_params(**{field: value})
     h = C.c_void_p()

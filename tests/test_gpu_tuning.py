@@ -19,9 +19,9 @@ from helpers import check_density, check_force, check_ghost, gpu_fixed_h
 pytestmark = pytest.mark.gpu
 P = oracle.Params()
 
-SHAPES = [dict(density_tile=t, density_waves=w, force_tile=ft, force_waves=fw)
-          for t, w, ft, fw in [(256, 1, 128, 2), (64, 1, 64, 2), (256, 2, 128, 1),
-                               (128, 2, 64, 1)]]
+SHAPES = [dict(density_tile=t, density_waves=w, force_tile=ft, force_waves=fw, density_balance=b)
+          for t, w, ft, fw, b in [(256, 1, 128, 2, 0), (64, 1, 64, 2, 0), (256, 2, 128, 1, 0),
+                                  (128, 2, 64, 1, 0), (128, 1, 64, 1, 1), (64, 1, 128, 1, 1)]]
 
 
 def case():
