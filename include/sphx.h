@@ -256,7 +256,8 @@ sphx_status sphx_step(sphx_ctx *ctx, sphx_grid *grid, sphx_tasks **tasks, sphx_p
                       sphx_density_out *dens, sphx_ghost_out *gst, sphx_force_out *out,
                       double *d_sums6, void *stream, sphx_step_info *info);
 
-/* Autotuner: times each density-loop shape (tile x waves) on fixed-h density
+/* Autotuner: times each density-loop shape (tile x waves, unbalanced rounds;
+ * density_balance is returned as given) on fixed-h density
  * passes, and each force-loop shape on force passes, over this grid and task
  * list at the particles' current h (reps launches each, HIP events on
  * `stream`), and returns in *tuned the context's parameters with the fastest

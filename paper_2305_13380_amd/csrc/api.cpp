@@ -468,9 +468,9 @@ sphx_status sphx_autotune(sphx_ctx *ctx, sphx_grid *grid, sphx_tasks *tasks, sph
     };
     sphx_status st = SPHX_OK;
     auto run = [&]() -> sphx_status {
-        // tile, waves, balance
-        const int32_t dshape[8][3] = {{128, 1, 0}, {64, 1, 0}, {256, 1, 0}, {128, 2, 0},
-                                      {64, 2, 0},  {128, 1, 1}, {64, 1, 1}, {256, 1, 1}};
+        // tile, waves, balance (the balanced rounds keep their own parameter:
+        // never measurably faster, they are not among the tuned shapes)
+        const int32_t dshape[5][3] = {{128, 1, 0}, {64, 1, 0}, {256, 1, 0}, {128, 2, 0}, {64, 2, 0}};
         double best = 1e300;
         int32_t bt = 128, bw = 1, bb = 0;
         for (auto &sh : dshape) {
