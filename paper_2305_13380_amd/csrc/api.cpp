@@ -240,6 +240,22 @@ sphx_status sphx_iter_reset(sphx_ctx *ctx, sphx_grid *grid, const sphx_particles
     return iter_reset(grid, in, as_stream(stream));
 }
 
+// Every output array a whole step writes (sphx_step, sphx_autotune).
+static sphx_status check_step_outputs(const char *who, const sphx_particles *in,
+                                      const sphx_density_out *d, const sphx_ghost_out *g,
+                                      const sphx_force_out *o)
+{
+    if (!d || !g || !o ||
+        (in->n && (!d->rho || !d->rho_dh || !d->n || !d->n_dh || !d->div_sum || !d->curl_x ||
+                   !d->curl_y || !d->curl_z || !d->nngb || !g->f || !g->P || !g->c ||
+                   !g->balsara || !g->A || !g->div_v || !g->curl_v || !g->converged || !o->ax ||
+                   !o->ay || !o->az || !o->du_dt || !o->v_sig))) {
+        set_error(std::string(who) + ": NULL density, ghost or force output array");
+        return SPHX_E_INVALID;
+    }
+    return SPHX_OK;
+}
+
 sphx_status sphx_density(sphx_ctx *ctx, const sphx_grid *grid, const sphx_tasks *tasks,
                          const sphx_particles *in, sphx_density_out *out, int32_t *d_counters,
                          void *stream)
@@ -299,6 +315,7 @@ sphx_status sphx_step(sphx_ctx *ctx, sphx_grid *grid, sphx_tasks **tasks, sphx_p
     }
     SPHX_TRY(check_handles(ctx, grid, *tasks, in));
     SPHX_TRY(check_particles(in, true));
+    SPHX_TRY(check_step_outputs("sphx_step", in, dens, gst, out));
     hipStream_t s = as_stream(stream);
     SPHX_HIP(hipSetDevice(ctx->device));
     sphx_step_info local;
@@ -358,7 +375,7 @@ sphx_status sphx_step(sphx_ctx *ctx, sphx_grid *grid, sphx_tasks **tasks, sphx_p
             SPHX_TRY(density_list_launch(ctx, grid, *tasks, dens, s));
         const int final_pass = (pass + 1 == max_iter) ? 1 : 0;
         SPHX_TRY(ghost_launch(ctx, grid, *tasks, in, dens, gst, dc, final_pass, lists, d_units,
-                              s));
+                              s, nullptr, true));
         SPHX_HIP(hipMemcpyAsync(h_buf, dc, kStepCounterBytes, hipMemcpyDeviceToHost, s));
         SPHX_HIP(hipStreamSynchronize(s));
         memcpy(h_counters, h_buf, sizeof(h_counters));
@@ -410,7 +427,7 @@ sphx_status sphx_step(sphx_ctx *ctx, sphx_grid *grid, sphx_tasks **tasks, sphx_p
         local.pairs_cellpair = int64_t(u[0]);
         local.pairs_list = int64_t(u[1]);
     }
-    SPHX_TRY(sphx_force(ctx, grid, *tasks, in, dens, gst, out, d_sums6, stream));
+    SPHX_TRY(force_launch(ctx, grid, *tasks, in, dens, gst, out, d_sums6, s, nullptr, true));
     local.n_leaves = grid->n_leaves;
     local.n_tasks = (*tasks)->n_tasks;
     if (info)
@@ -429,10 +446,11 @@ sphx_status sphx_autotune(sphx_ctx *ctx, sphx_grid *grid, sphx_tasks *tasks, sph
 {
     SPHX_TRY(check_handles(ctx, grid, tasks, in));
     SPHX_TRY(check_particles(in, true));
-    if (!tasks || !dens || !gst || !out || !tuned || reps < 1) {
-        set_error("sphx_autotune: NULL task list, output or result, or reps < 1");
+    if (!tasks || !tuned || reps < 1) {
+        set_error("sphx_autotune: NULL task list or result, or reps < 1");
         return SPHX_E_INVALID;
     }
+    SPHX_TRY(check_step_outputs("sphx_autotune", in, dens, gst, out));
     hipStream_t s = as_stream(stream);
     SPHX_HIP(hipSetDevice(ctx->device));
     const sphx_params saved = ctx->p;

@@ -12,17 +12,22 @@ namespace {
 
 // Sorted copies of the ghost state every source needs: (h, rho, P, c) and
 // (f, B, A, 0).
+// Source state of the force pass in sorted order, gathered from the caller's
+// arrays; with skip_active, only for the inactive particles (a step's ghost
+// has written the active ones).
 __global__ void k_force_state(int64_t n, const int32_t *__restrict__ perm,
                               const float *__restrict__ h, const float *__restrict__ rho,
                               const float *__restrict__ P, const float *__restrict__ c,
                               const float *__restrict__ f, const float *__restrict__ B,
-                              const float *__restrict__ A, float4 *__restrict__ g0,
-                              float4 *__restrict__ g1)
+                              const float *__restrict__ A, const uint8_t *__restrict__ skip_active,
+                              float4 *__restrict__ g0, float4 *__restrict__ g1)
 {
     const int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (s >= n)
         return;
     const int32_t i = perm[s];
+    if (skip_active && skip_active[i])
+        return;
     g0[s] = make_float4(h[i], rho[i], P[i], c[i]);
     g1[s] = make_float4(f[i], B[i], A[i], 0.0f);
 }
@@ -360,17 +365,19 @@ __global__ __launch_bounds__(256) void k_sum_leaves(int64_t n_leaves,
 sphx_status force_launch(const sphx_ctx *ctx, const sphx_grid *g, const sphx_tasks *t,
                          const sphx_particles *in, const sphx_density_out *d,
                          const sphx_ghost_out *gs, const sphx_force_out *o, double *sums6,
-                         hipStream_t s, const int32_t *gate)
+                         hipStream_t s, const int32_t *gate, bool state_ready)
 {
     if (g->n_leaves == 0) {
         if (sums6)
             SPHX_HIP(hipMemsetAsync(sums6, 0, 6 * sizeof(double), s));
         return SPHX_OK;
     }
-    k_force_state<<<unsigned((g->n + 255) / 256), 256, 0, s>>>(g->n, g->perm, in->h, d->rho,
-                                                                gs->P, gs->c, gs->f, gs->balsara,
-                                                                gs->A, g->g0, g->g1);
-    SPHX_HIP(hipGetLastError());
+    if (!state_ready || in->active) {
+        k_force_state<<<unsigned((g->n + 255) / 256), 256, 0, s>>>(
+            g->n, g->perm, in->h, d->rho, gs->P, gs->c, gs->f, gs->balsara, gs->A,
+            state_ready ? in->active : nullptr, g->g0, g->g1);
+        SPHX_HIP(hipGetLastError());
+    }
     const int64_t nbp = pad8(g->n_leaves);
     SPHX_HIP(ctx->prof->begin(1, s));
     const int tile = ctx->p.force_tile ? ctx->p.force_tile : 64;

@@ -21,7 +21,8 @@ __global__ __launch_bounds__(kGhostThreads) void k_ghost(int64_t n, const int32_
                         const float *__restrict__ lrad,
                         const float4 *__restrict__ d0, const float4 *__restrict__ d1, float inv_eta3,
                         float h_tol, float h_max, float gamma_k, float gamma_gas, float eps_b,
-                        int final_pass, const int32_t *__restrict__ nngb,
+                        int final_pass, int step_mode, float4 *__restrict__ g0,
+                        float4 *__restrict__ g1, const int32_t *__restrict__ nngb,
                         unsigned long long *__restrict__ units, float *__restrict__ o_f,
                         float *__restrict__ o_P,
                         float *__restrict__ o_c, float *__restrict__ o_B,
@@ -64,9 +65,13 @@ __global__ __launch_bounds__(kGhostThreads) void k_ghost(int64_t n, const int32_
                 pairs_cell += c;
         }
         if (!conv && !final_pass) {
-            h[i] = hn;
             hs[s] = hn;
-            o_conv[i] = 0;
+            // Inside a step the caller's h and flag are written once, when the
+            // particle is finalised (no scattered writes in every pass).
+            if (!step_mode) {
+                h[i] = hn;
+                o_conv[i] = 0;
+            }
             n_rebuild += gamma_k * hn > radius[leaf_of[s]] ? 1 : 0;
             // with neighbour lists: the next pass cannot use this one's list
             n_beyond += (lrad && gamma_k * hn > lrad[s]) ? 1 : 0;
@@ -85,13 +90,22 @@ __global__ __launch_bounds__(kGhostThreads) void k_ghost(int64_t n, const int32_
             const float div = b.x * irho;
             const float curl = sqrtf(b.y * b.y + b.z * b.z + b.w * b.w) * irho;
             const float ad = fabsf(div);
+            const float B = ad / (ad + curl + eps_b * c / hh);
+            const float A = f * P * irho * irho;
             o_f[i] = f;
             o_P[i] = P;
             o_c[i] = c;
-            o_B[i] = ad / (ad + curl + eps_b * c / hh);
-            o_A[i] = f * P * irho * irho;
+            o_B[i] = B;
+            o_A[i] = A;
             o_div[i] = div;
             o_curl[i] = curl;
+            if (step_mode) {
+                h[i] = hh;
+                // the force pass's source state, in sorted order (the same
+                // values its gather would read from the outputs)
+                g0[s] = make_float4(hh, rho, P, c);
+                g1[s] = make_float4(f, B, A, 0.0f);
+            }
         }
     }
     if (!counters && !units)
@@ -131,7 +145,8 @@ __global__ __launch_bounds__(kGhostThreads) void k_ghost(int64_t n, const int32_
 sphx_status ghost_launch(const sphx_ctx *ctx, sphx_grid *g, const sphx_tasks *t,
                          sphx_particles *in, const sphx_density_out *d, const sphx_ghost_out *o,
                          int32_t *counters, int final_pass, bool use_lists,
-                         unsigned long long *units, hipStream_t s, const int32_t *skip)
+                         unsigned long long *units, hipStream_t s, const int32_t *skip,
+                         bool step_mode)
 {
     if (g->n == 0)
         return SPHX_OK;
@@ -144,8 +159,8 @@ sphx_status ghost_launch(const sphx_ctx *ctx, sphx_grid *g, const sphx_tasks *t,
         use_lists ? g->lrad : nullptr, g->d0, g->d1, inv_eta3,
         float(P.h_tol),
         float(ctx->h_max), float(P.gamma_k), float(P.gamma_gas), float(P.eps_balsara),
-        final_pass, d->nngb, units, o->f, o->P, o->c, o->balsara, o->A, o->div_v, o->curl_v, o->converged,
-        counters, skip);
+        final_pass, step_mode ? 1 : 0, g->g0, g->g1, d->nngb, units, o->f, o->P, o->c,
+        o->balsara, o->A, o->div_v, o->curl_v, o->converged, counters, skip);
     SPHX_HIP(hipGetLastError());
     return SPHX_OK;
 }

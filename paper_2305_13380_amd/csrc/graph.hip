@@ -84,11 +84,11 @@ static sphx_status record(sphx_ctx *ctx, StepGraph *G, sphx_grid *grid, sphx_tas
         SPHX_TRY(
             density_launch(ctx, grid, t, in, dens, ctx->d_counters, false, cs, G->d_gate + 2));
         SPHX_TRY(ghost_launch(ctx, grid, t, pin, dens, gst, ctx->d_counters, final_pass, false,
-                              units, cs, G->d_gate + 2));
+                              units, cs, G->d_gate + 2, true));
         k_log_pass<<<1, 64, 0, cs>>>(ctx->d_counters, G->d_log, p, final_pass, G->d_gate);
         SPHX_HIP(hipGetLastError());
     }
-    return force_launch(ctx, grid, t, in, dens, gst, out, sums6, cs, G->d_gate);
+    return force_launch(ctx, grid, t, in, dens, gst, out, sums6, cs, G->d_gate, true);
 }
 
 sphx_status step_graph_run(sphx_ctx *ctx, sphx_grid *grid, sphx_tasks *t, const sphx_particles *in,

@@ -219,17 +219,21 @@ sphx_status list_build(const sphx_ctx *ctx, sphx_grid *g, const sphx_tasks *t, h
 size_t lists_bytes(int64_t n);
 
 // ghost.hip
+// step_mode (sphx_step): the caller's h and converged flag are written only
+// when a particle is finalised, and the finalising pass also writes the force
+// pass's sorted source state (force_launch then runs with state_ready).
 sphx_status ghost_launch(const sphx_ctx *ctx, sphx_grid *g, const sphx_tasks *t,
                          sphx_particles *in, const sphx_density_out *d, const sphx_ghost_out *o,
                          int32_t *counters, int final_pass, bool use_lists,
                          unsigned long long *units, hipStream_t s,
-                         const int32_t *skip = nullptr);
+                         const int32_t *skip = nullptr, bool step_mode = false);
 
 // force.hip
 sphx_status force_launch(const sphx_ctx *ctx, const sphx_grid *g, const sphx_tasks *t,
                          const sphx_particles *in, const sphx_density_out *d,
                          const sphx_ghost_out *gs, const sphx_force_out *o, double *sums6,
-                         hipStream_t s, const int32_t *gate = nullptr);
+                         hipStream_t s, const int32_t *gate = nullptr,
+                         bool state_ready = false);
 
 // graph.hip
 // Captured step: the h iteration's first `passes` passes and a gated force

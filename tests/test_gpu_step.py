@@ -198,3 +198,22 @@ def test_active_subset_step():
     err = np.linalg.norm(a - b, axis=1) / np.maximum(nb, rms(nb))
     dmax = (np.abs(hg[ridx] - h2) / h2).max()
     assert err.max() <= 1e-4 + 50 * dmax, "active accel worst %.3g" % err.max()
+
+
+def test_step_rejects_null_outputs():
+    """A step with a missing output array is refused before any pass runs."""
+    import ctypes as C
+    from paper_2305_13380_amd import sphx
+    ps = inputs.lattice_box(8, 6)
+    ctx = sphx.Context()
+    dp = sphx.DeviceParticles.from_set(ps)
+    out = sphx.Outputs(ps.n)
+    grid = sphx.Grid(ctx, dp)
+    tasks = sphx.Tasks(ctx, grid, dp)
+    pv, dv, gv, fv = dp.view(), out.dens_view(), out.ghost_view(), out.force_view()
+    dv.rho = None
+    info = sphx.StepInfo()
+    st = sphx.lib.sphx_step(ctx.handle, grid.handle, C.byref(tasks.handle), C.byref(pv),
+                            C.byref(dv), C.byref(gv), C.byref(fv), None, None, C.byref(info))
+    assert st == sphx.E_INVALID and "NULL" in sphx.last_error()
+    assert np.all(np.isnan(out.d["n"].cpu().numpy()))  # nothing ran
