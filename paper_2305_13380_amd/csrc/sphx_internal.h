@@ -182,6 +182,15 @@ struct sphx_tasks {
     void *sort_tmp;
     size_t sort_tmp_bytes;
     int64_t order_cap;
+    // Rebuilds in one tree walk: the walk writes each leaf's tasks into its
+    // slot of the `soff` layout (capacity count + count/4 + 8 from the last
+    // two-pass build) while counting them, and they are compacted into `task`;
+    // a leaf over its capacity sends the rebuild back to the two-pass build.
+    sphx::Task *slack;  // slack_cap
+    int32_t *soff;      // n_leaves + 1
+    int32_t *flag;      // [0]: a leaf exceeded its capacity
+    int64_t slack_cap;
+    bool slack_ok;      // soff holds a layout for this grid
 };
 
 namespace sphx {

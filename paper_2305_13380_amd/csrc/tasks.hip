@@ -262,8 +262,10 @@ __device__ __forceinline__ int wave_prefix_small(int v, int &total)
 // nodes x 8 children tested per step by the 64 lanes; survivors keep their
 // ascending order, so the cells (and their shifts) come out in the same order
 // as in the serial walk. A frontier that would exceed kFront marks the cell
-// for the serial walk instead.
-template <bool FILL>
+// for the serial walk instead. MODE 0 counts; MODE 1 writes at off[I];
+// MODE 2 writes at off[I] (the slack layout) up to the cell's capacity
+// off[I+1] - off[I] and counts.
+template <int MODE>
 __global__ __launch_bounds__(64) void k_task_bfs(int64_t n_leaves, TreeView T,
                                                  const double *__restrict__ org,
                                                  const int32_t *__restrict__ leaf_start,
@@ -275,7 +277,8 @@ __global__ __launch_bounds__(64) void k_task_bfs(int64_t n_leaves, TreeView T,
     const int64_t I = blockIdx.x;
     if (I >= n_leaves)
         return;
-    if (FILL && overflow[I])
+    constexpr bool COUNT = MODE != 1, WRITE = MODE != 0;
+    if (!COUNT && overflow[I])
         return;
     const int lane = threadIdx.x;
     __shared__ int32_t front[2][kFront];
@@ -286,7 +289,7 @@ __global__ __launch_bounds__(64) void k_task_bfs(int64_t n_leaves, TreeView T,
     int cur = 0;
     int ncur = int(T.level_cnt[top]);
     if (ncur > kFront) {
-        if (!FILL && lane == 0) {
+        if (COUNT && lane == 0) {
             overflow[I] = 1;
             count[I] = 0;
         }
@@ -295,7 +298,8 @@ __global__ __launch_bounds__(64) void k_task_bfs(int64_t n_leaves, TreeView T,
     for (int k = lane; k < ncur; k += 64)
         front[0][k] = k;
     int emitted = 0;
-    const int32_t wbase = FILL ? off[I] : 0;
+    const int32_t wbase = WRITE ? off[I] : 0;
+    const int32_t wcap = MODE == 2 ? off[I + 1] - off[I] : 0x7fffffff;
     const double oxi = org[3 * I], oyi = org[3 * I + 1], ozi = org[3 * I + 2];
     for (int lev = top; lev >= 0; --lev) {
         __syncthreads();
@@ -314,7 +318,7 @@ __global__ __launch_bounds__(64) void k_task_bfs(int64_t n_leaves, TreeView T,
                 }
                 int tot;
                 const int pre = wave_prefix_small(nt, tot);
-                if (FILL && nt > 0) {
+                if (WRITE && nt > 0) {
                     const int32_t j0 = leaf_start[J];
                     const int32_t jc = leaf_start[J + 1] - j0;
                     emit_shifts(g, R, [&](int k, int sx, int sy, int sz) {
@@ -327,7 +331,8 @@ __global__ __launch_bounds__(64) void k_task_bfs(int64_t n_leaves, TreeView T,
                         t.oy = float(org[3 * J + 1] + double(sy) * T.L[1] - oyi);
                         t.oz = float(org[3 * J + 2] + double(sz) * T.L[2] - ozi);
                         t.j0b = j0;
-                        task[wbase + emitted + pre + k] = t;
+                        if (emitted + pre + k < wcap)
+                            task[wbase + emitted + pre + k] = t;
                     });
                 }
                 emitted += tot;
@@ -362,7 +367,7 @@ __global__ __launch_bounds__(64) void k_task_bfs(int64_t n_leaves, TreeView T,
             nnext += tot;
         }
         if (over) {
-            if (!FILL && lane == 0) {
+            if (COUNT && lane == 0) {
                 overflow[I] = 1;
                 count[I] = 0;
             }
@@ -371,8 +376,52 @@ __global__ __launch_bounds__(64) void k_task_bfs(int64_t n_leaves, TreeView T,
         cur ^= 1;
         ncur = nnext;
     }
-    if (!FILL && lane == 0)
+    if (COUNT && lane == 0)
         count[I] = emitted;
+}
+
+// Flag a walked cell (not left to the serial walk) whose tasks exceeded its
+// slot in the slack layout; one atomic per block.
+__global__ __launch_bounds__(256) void k_check_slack(int64_t n_leaves,
+                                                     const int32_t *__restrict__ soff,
+                                                     const int32_t *__restrict__ count,
+                                                     const uint8_t *__restrict__ overflow,
+                                                     int32_t *__restrict__ flag)
+{
+    const int64_t I = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const bool over =
+        I < n_leaves && !overflow[I] && count[I] > soff[I + 1] - soff[I];
+    if (__syncthreads_or(over) && threadIdx.x == 0)
+        atomicOr(flag, 1);
+}
+
+// Compaction of the one-walk rebuild: each walked cell's tasks from its
+// slack slot to its place in the list.
+__global__ __launch_bounds__(64) void k_compact_tasks(int64_t n_leaves,
+                                                      const int32_t *__restrict__ soff,
+                                                      const int32_t *__restrict__ off,
+                                                      const int32_t *__restrict__ count,
+                                                      const uint8_t *__restrict__ overflow,
+                                                      const Task *__restrict__ slack,
+                                                      Task *__restrict__ task)
+{
+    const int64_t I = blockIdx.x;
+    if (I >= n_leaves || overflow[I])
+        return;
+    const int32_t n = count[I], a = soff[I], b = off[I];
+    for (int32_t k = threadIdx.x; k < n; k += 64)
+        task[b + k] = slack[a + k];
+}
+
+// Slot sizes of the slack layout from the counts of a two-pass build.
+__global__ void k_slack_sizes(int64_t n_leaves, const int32_t *__restrict__ count,
+                              int32_t *__restrict__ sz)
+{
+    const int64_t I = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (I < n_leaves)
+        sz[I] = count[I] + count[I] / 4 + 8;
+    else if (I == n_leaves)
+        sz[I] = 0;
 }
 
 }  // namespace
@@ -392,7 +441,7 @@ void tasks_free(sphx_tasks *t)
     for (void *p : ptrs)
         dfree(p, t->stream);
     for (void *p : {(void *)t->order, (void *)t->okey, (void *)t->okey_out, (void *)t->oval,
-                    t->sort_tmp})
+                    t->sort_tmp, (void *)t->slack, (void *)t->soff, (void *)t->flag})
         dfree(p, t->stream);
     delete t;
 }
@@ -457,7 +506,9 @@ sphx_status tasks_build(sphx_ctx *ctx, sphx_grid *g, const sphx_particles *in, h
         if (dmalloc((void **)&t->off, (nl + 1) * sizeof(int32_t), s) != hipSuccess ||
             dmalloc((void **)&t->count, (nl + 1) * sizeof(int32_t), s) != hipSuccess ||
             dmalloc((void **)&t->radius, (nl + 1) * sizeof(float), s) != hipSuccess ||
-            dmalloc((void **)&t->overflow, (nl + 1) * sizeof(uint8_t), s) != hipSuccess) {
+            dmalloc((void **)&t->overflow, (nl + 1) * sizeof(uint8_t), s) != hipSuccess ||
+            dmalloc((void **)&t->soff, (nl + 1) * sizeof(int32_t), s) != hipSuccess ||
+            dmalloc((void **)&t->flag, sizeof(int32_t), s) != hipSuccess) {
             set_error("sphx_tasks_build: out of device memory");
             return fail(SPHX_E_OOM);
         }
@@ -513,37 +564,102 @@ sphx_status tasks_build(sphx_ctx *ctx, sphx_grid *g, const sphx_particles *in, h
         T.L[a] = ctx->p.box[a];
     T.periodic = ctx->p.periodic;
 
+    auto ensure_task_cap = [&](int64_t total) -> sphx_status {
+        if (total > t->cap) {
+            dfree(t->task, s);
+            t->task = nullptr;
+            t->cap = 0;
+            const int64_t cap = total + total / 4 + 64;
+            SPHX_HIP(dmalloc((void **)&t->task, size_t(cap) * sizeof(Task), s));
+            t->cap = cap;
+        }
+        return SPHX_OK;
+    };
+    size_t tmp = t->scan_tmp_bytes;
+    int32_t total = 0;
     SPHX_HIP(hipMemsetAsync(t->count + nl, 0, sizeof(int32_t), s));
     SPHX_HIP(hipMemsetAsync(t->overflow, 0, size_t(nl) * sizeof(uint8_t), s));
-    k_task_bfs<false><<<unsigned(nl), 64, 0, s>>>(nl, T, g->leaf_org, g->leaf_start, t->off,
+    if (t->slack_ok) {
+        // One walk: count every cell's tasks and write them into its slot of
+        // the slack layout; if every walked cell fitted, compact and finish.
+        SPHX_HIP(hipMemsetAsync(t->flag, 0, sizeof(int32_t), s));
+        k_task_bfs<2><<<unsigned(nl), 64, 0, s>>>(nl, T, g->leaf_org, g->leaf_start, t->soff,
+                                                  t->count, t->overflow, t->slack);
+        SPHX_HIP(hipGetLastError());
+        k_task_count<<<blocks(nl, 64), 64, 0, s>>>(nl, T, t->overflow, t->count);
+        SPHX_HIP(hipGetLastError());
+        k_check_slack<<<blocks(nl, 256), 256, 0, s>>>(nl, t->soff, t->count, t->overflow,
+                                                       t->flag);
+        SPHX_HIP(hipGetLastError());
+        SPHX_HIP(rocprim::exclusive_scan(t->scan_tmp, tmp, t->count, t->off, 0, size_t(nl + 1),
+                                         rocprim::plus<int32_t>(), s));
+        int32_t flag = 0;
+        SPHX_HIP(hipMemcpyAsync(&total, t->off + nl, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        SPHX_HIP(hipMemcpyAsync(&flag, t->flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        SPHX_HIP(hipStreamSynchronize(s));
+        if (total < 0) {
+            set_error("sphx_tasks_build: task count overflow");
+            return SPHX_E_INVALID;
+        }
+        if (flag == 0) {
+            SPHX_TRY(ensure_task_cap(total));
+            t->n_tasks = total;
+            k_compact_tasks<<<unsigned(nl), 64, 0, s>>>(nl, t->soff, t->off, t->count,
+                                                        t->overflow, t->slack, t->task);
+            SPHX_HIP(hipGetLastError());
+            k_task_fill<<<blocks(nl, 64), 64, 0, s>>>(nl, T, g->leaf_org, g->leaf_start,
+                                                      t->overflow, t->off, t->task);
+            SPHX_HIP(hipGetLastError());
+            SPHX_TRY(leaf_order(t, nl, s));
+            guard.keep = true;
+            *out = t;
+            return SPHX_OK;
+        }
+        // Some cell outgrew its slot: the counts are exact, so only the
+        // writing walk remains (below), followed by new slots.
+    } else {
+        k_task_bfs<0><<<unsigned(nl), 64, 0, s>>>(nl, T, g->leaf_org, g->leaf_start, t->off,
                                                   t->count, t->overflow, t->task);
-    SPHX_HIP(hipGetLastError());
-    k_task_count<<<blocks(nl, 64), 64, 0, s>>>(nl, T, t->overflow, t->count);
-    SPHX_HIP(hipGetLastError());
-    size_t tmp = t->scan_tmp_bytes;
-    SPHX_HIP(rocprim::exclusive_scan(t->scan_tmp, tmp, t->count, t->off, 0, size_t(nl + 1),
-                                     rocprim::plus<int32_t>(), s));
-    int32_t total = 0;
-    SPHX_HIP(hipMemcpyAsync(&total, t->off + nl, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    SPHX_HIP(hipStreamSynchronize(s));
-    if (total < 0) {
-        set_error("sphx_tasks_build: task count overflow");
-        return SPHX_E_INVALID;
+        SPHX_HIP(hipGetLastError());
+        k_task_count<<<blocks(nl, 64), 64, 0, s>>>(nl, T, t->overflow, t->count);
+        SPHX_HIP(hipGetLastError());
+        SPHX_HIP(rocprim::exclusive_scan(t->scan_tmp, tmp, t->count, t->off, 0, size_t(nl + 1),
+                                         rocprim::plus<int32_t>(), s));
+        SPHX_HIP(hipMemcpyAsync(&total, t->off + nl, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        SPHX_HIP(hipStreamSynchronize(s));
+        if (total < 0) {
+            set_error("sphx_tasks_build: task count overflow");
+            return SPHX_E_INVALID;
+        }
     }
-    if (int64_t(total) > t->cap) {
-        dfree(t->task, s);
-        t->task = nullptr;
-        int64_t cap = int64_t(total) + int64_t(total) / 4 + 64;
-        SPHX_HIP(dmalloc((void **)&t->task, size_t(cap) * sizeof(Task), s));
-        t->cap = cap;
-    }
+    SPHX_TRY(ensure_task_cap(total));
     t->n_tasks = total;
-    k_task_bfs<true><<<unsigned(nl), 64, 0, s>>>(nl, T, g->leaf_org, g->leaf_start, t->off,
-                                                 t->count, t->overflow, t->task);
+    k_task_bfs<1><<<unsigned(nl), 64, 0, s>>>(nl, T, g->leaf_org, g->leaf_start, t->off,
+                                              t->count, t->overflow, t->task);
     SPHX_HIP(hipGetLastError());
     k_task_fill<<<blocks(nl, 64), 64, 0, s>>>(nl, T, g->leaf_org, g->leaf_start, t->overflow,
                                               t->off, t->task);
     SPHX_HIP(hipGetLastError());
+    // slots of the slack layout for the next rebuild, from these counts
+    t->slack_ok = false;
+    k_slack_sizes<<<blocks(nl + 1, 256), 256, 0, s>>>(nl, t->count, t->count);
+    SPHX_HIP(hipGetLastError());
+    SPHX_HIP(rocprim::exclusive_scan(t->scan_tmp, tmp, t->count, t->soff, 0, size_t(nl + 1),
+                                     rocprim::plus<int32_t>(), s));
+    int32_t slack_total = 0;
+    SPHX_HIP(hipMemcpyAsync(&slack_total, t->soff + nl, sizeof(int32_t), hipMemcpyDeviceToHost,
+                            s));
+    SPHX_HIP(hipStreamSynchronize(s));
+    if (slack_total > 0 && int64_t(slack_total) > t->slack_cap) {
+        dfree(t->slack, s);
+        t->slack = nullptr;
+        t->slack_cap = 0;
+        if (dmalloc((void **)&t->slack, size_t(slack_total) * sizeof(Task), s) == hipSuccess)
+            t->slack_cap = slack_total;
+        else
+            (void)hipGetLastError();  // no slack: rebuilds keep two walks
+    }
+    t->slack_ok = slack_total > 0 && t->slack && t->slack_cap >= int64_t(slack_total);
     SPHX_TRY(leaf_order(t, nl, s));
     guard.keep = true;
     *out = t;

@@ -217,3 +217,29 @@ def test_step_rejects_null_outputs():
                             C.byref(dv), C.byref(gv), C.byref(fv), None, None, C.byref(info))
     assert st == sphx.E_INVALID and "NULL" in sphx.last_error()
     assert np.all(np.isnan(out.d["n"].cpu().numpy()))  # nothing ran
+
+
+@pytest.mark.parametrize("growth", [1.02, 1.6])
+def test_rebuild_in_place_matches_fresh_build(growth):
+    """Rebuilding a task list in place (one walk into the slot layout of the
+    previous build when every cell fits, else two walks) gives the same task
+    list as a fresh build: a fixed-h pass over either is bitwise the same."""
+    import torch
+    from paper_2305_13380_amd import sphx
+    ps = inputs.lognormal_box(16, 6000, 2.0, 41)
+    ctx = sphx.Context()
+    dp = sphx.DeviceParticles.from_set(ps)
+    grid = sphx.Grid(ctx, dp)
+    tasks = sphx.Tasks(ctx, grid, dp)
+    dp.t["h"].mul_(growth)
+    tasks.build(dp)  # in place
+    fresh = sphx.Tasks(ctx, grid, dp)
+    assert tasks.count == fresh.count
+    res = []
+    for t in (tasks, fresh):
+        out = sphx.Outputs(ps.n)
+        sphx.fixed_h_pass(ctx, grid, t, dp, out)
+        torch.cuda.synchronize()
+        res.append({k: v.cpu().numpy() for k, v in {**out.d, **out.g, **out.f}.items()})
+    for k in res[0]:
+        assert np.array_equal(res[0][k].view(np.uint8), res[1][k].view(np.uint8)), k
