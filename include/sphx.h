@@ -204,8 +204,10 @@ sphx_status sphx_tasks_build(sphx_ctx *ctx, sphx_grid *grid, const sphx_particle
                              void *stream, sphx_tasks **out);
 void sphx_tasks_destroy(sphx_tasks *tasks);
 
-/* Mark every active particle as needing a density pass (start of an h
- * iteration). sphx_grid_build does this too. Asynchronous. */
+/* Start an h iteration: mark every active particle as needing a density pass
+ * and clear each particle's bracket of the root (the safeguard of the
+ * Newton-Raphson step in sphx_ghost). sphx_grid_build does this too.
+ * Asynchronous. */
 sphx_status sphx_iter_reset(sphx_ctx *ctx, sphx_grid *grid, const sphx_particles *in,
                             void *stream);
 

@@ -61,7 +61,7 @@ def lib():
                                  _nullable(_ip), _nullable(_ip), _nullable(_ip)] + [_dp] * 8 + [_ip])
         L.or_density.restype = C.c_int64
         L.or_h_update.argtypes = [C.c_int64, _dp, _dp, _dp, C.c_double, C.c_double, C.c_double,
-                                  _dp, _i32p]
+                                  _dp, _dp, _dp, _i32p]
         L.or_h_update.restype = None
         L.or_ghost.argtypes = ([C.c_int64] + [_dp] * 8 + [C.c_double, C.c_double] + [_dp] * 7)
         L.or_ghost.restype = None
@@ -255,12 +255,19 @@ def density(ps, h, params: Params, recv=None, mode="auto"):
     return out
 
 
-def h_update(h, nd, nd_dh, params: Params):
+def h_update(h, nd, nd_dh, params: Params, lo=None, hi=None):
+    """One safeguarded Newton-Raphson step per particle (or_h_update). lo/hi
+    are the per-particle bracket (largest h with G < 0, smallest with G > 0),
+    updated in place; None starts without one."""
     h = _f64(h)
+    lo = np.zeros(h.shape[0]) if lo is None else lo
+    hi = np.full(h.shape[0], np.inf) if hi is None else hi
+    assert lo.dtype == np.float64 and hi.dtype == np.float64
+    assert lo.flags.c_contiguous and hi.flags.c_contiguous
     hn = np.empty_like(h)
     conv = np.empty(h.shape[0], np.int32)
     lib().or_h_update(h.shape[0], h, _f64(nd), _f64(nd_dh), float(params.eta),
-                      float(params.h_tol), float(params.hmax()), hn, conv)
+                      float(params.h_tol), float(params.hmax()), lo, hi, hn, conv)
     return hn, conv.astype(bool)
 
 
@@ -292,6 +299,8 @@ def solve_h(ps, params: Params, recv=None, mode="auto", h0=None):
     dens = None
     todo = np.arange(nr)
     iters = np.zeros(nr, np.int32)
+    lo = np.zeros(nr)          # bracket of the root, per receiver
+    hi = np.full(nr, np.inf)
     passes = 0
     while todo.size and passes < params.max_iter:
         passes += 1
@@ -303,7 +312,9 @@ def solve_h(ps, params: Params, recv=None, mode="auto", h0=None):
             if k != "total":
                 dens[k][todo] = v
         iters[todo] += 1
-        hn, c = h_update(h[todo], d["n"], d["n_dh"], params)
+        lo_t, hi_t = lo[todo], hi[todo]
+        hn, c = h_update(h[todo], d["n"], d["n_dh"], params, lo_t, hi_t)
+        lo[todo], hi[todo] = lo_t, hi_t
         conv[todo] = c
         last = passes == params.max_iter
         # A receiver still unconverged after the last allowed pass keeps the

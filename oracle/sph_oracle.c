@@ -162,15 +162,27 @@ int64_t or_density(int64_t n, const double *x, const double *y, const double *z,
  * step is a halving or doubling in the direction of -G. The particle is
  * converged when the change is below h_tol * h; its h then stays at the value
  * the sums were evaluated at.
+ *
+ * Safeguard: h_lo / h_hi carry, per particle, the largest h seen with G < 0
+ * and the smallest with G > 0 (0 and +inf before any); the root lies between.
+ * Once both are known, a Newton step that would not converge and does not
+ * land strictly inside (h_lo, h_hi) is replaced by the geometric midpoint
+ * sqrt(h_lo h_hi) (a bisection in ln h), so the iteration cannot cycle where
+ * G is nearly flat.
  */
 void or_h_update(int64_t n, const double *h, const double *nd, const double *nd_dh,
-                 double eta, double h_tol, double h_max, double *h_new, int32_t *converged)
+                 double eta, double h_tol, double h_max, double *h_lo, double *h_hi,
+                 double *h_new, int32_t *converged)
 {
     const double ln2 = log(2.0);
     for (int64_t k = 0; k < n; ++k) {
         double hk = h[k];
         double G = log(nd[k] * hk * hk * hk / (eta * eta * eta));
         double dG = 3.0 + hk * nd_dh[k] / nd[k];
+        if (G < 0.0 && hk > h_lo[k])
+            h_lo[k] = hk;
+        if (G > 0.0 && hk < h_hi[k])
+            h_hi[k] = hk;
         double step;
         if (dG > 0.0 && isfinite(G / dG))
             step = -G / dG;
@@ -183,6 +195,9 @@ void or_h_update(int64_t n, const double *h, const double *nd, const double *nd_
         double hn = hk * exp(step);
         if (hn > h_max)
             hn = h_max;
+        if (!(fabs(hn - hk) < h_tol * hk) && h_lo[k] > 0.0 && isfinite(h_hi[k]) &&
+            !(hn > h_lo[k] && hn < h_hi[k]))
+            hn = sqrt(h_lo[k] * h_hi[k]);
         if (fabs(hn - hk) < h_tol * hk) {
             converged[k] = 1;
             h_new[k] = hk;

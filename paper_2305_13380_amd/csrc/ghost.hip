@@ -17,6 +17,7 @@ constexpr int kGhostMaxBlocks = 1024;
 __global__ __launch_bounds__(kGhostThreads) void k_ghost(int64_t n, const int32_t *__restrict__ perm,
                         const int32_t *__restrict__ leaf_of, uint8_t *__restrict__ need,
                         float *__restrict__ h, float *__restrict__ hs,
+                        float *__restrict__ hlo, float *__restrict__ hhi,
                         const float4 *__restrict__ q1, const float *__restrict__ radius,
                         const float *__restrict__ lrad,
                         const float4 *__restrict__ d0, const float4 *__restrict__ d1, float inv_eta3,
@@ -48,12 +49,24 @@ __global__ __launch_bounds__(kGhostThreads) void k_ghost(int64_t n, const int32_
         // log2(h_new / h) = -log2(n h^3 / eta^3) / G'.
         const float G2 = __log2f(nd * (hh * hh * hh) * inv_eta3);
         const float dG = a.y;
+        // bracket of the root: the largest h with G < 0, the smallest with G > 0
+        float lo = hlo[s], hi = hhi[s];
+        if (G2 < 0.0f && hh > lo)
+            hlo[s] = lo = hh;
+        if (G2 > 0.0f && hh < hi)
+            hhi[s] = hi = hh;
         float e = -G2 / dG;
         if (!(dG > 0.0f) || !isfinite(e))
             e = G2 < 0.0f ? 1.0f : -1.0f;
         e = fminf(fmaxf(e, -1.0f), 1.0f);
         float hn = hh * exp2f(e);
         hn = fminf(hn, h_max);
+        // a Newton step that would not converge and leaves a known bracket is
+        // replaced by its geometric midpoint (a bisection in ln h): no cycling
+        // where G is nearly flat (a converging step may round onto an end)
+        if (!(fabsf(hn - hh) < h_tol * hh) && lo > 0.0f && hi < __builtin_inff() &&
+            !(hn > lo && hn < hi))
+            hn = sqrtf(lo * hi);
         const bool conv = fabsf(hn - hh) < h_tol * hh;
         const int32_t i = perm[s];
         n_unconv += conv ? 0 : 1;
@@ -155,7 +168,7 @@ sphx_status ghost_launch(const sphx_ctx *ctx, sphx_grid *g, const sphx_tasks *t,
     const int64_t nblk = std::min<int64_t>((g->n + kGhostThreads - 1) / kGhostThreads,
                                            kGhostMaxBlocks);
     k_ghost<<<unsigned(nblk), kGhostThreads, 0, s>>>(
-        g->n, g->perm, g->leaf_of, g->need, in->h, g->hs, g->q1, t->radius,
+        g->n, g->perm, g->leaf_of, g->need, in->h, g->hs, g->hlo, g->hhi, g->q1, t->radius,
         use_lists ? g->lrad : nullptr, g->d0, g->d1, inv_eta3,
         float(P.h_tol),
         float(ctx->h_max), float(P.gamma_k), float(P.gamma_gas), float(P.eps_balsara),

@@ -318,15 +318,19 @@ __global__ void k_tree_level(int64_t cnt_up, int64_t cnt_dn, const double *__res
 // order (with mark == nullptr only the copy).
 __global__ void k_iter_reset(int64_t n, const int32_t *__restrict__ perm,
                              const uint8_t *__restrict__ active, const float *__restrict__ h,
-                             uint8_t *__restrict__ need, float *__restrict__ hs)
+                             uint8_t *__restrict__ need, float *__restrict__ hs,
+                             float *__restrict__ hlo, float *__restrict__ hhi)
 {
     int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (s >= n)
         return;
     const int32_t i = perm[s];
     hs[s] = h[i];
-    if (need)
+    if (need) {
         need[s] = active ? (active[i] ? 1 : 0) : 1;
+        hlo[s] = 0.0f;
+        hhi[s] = __builtin_inff();
+    }
 }
 
 template <class T>
@@ -346,7 +350,7 @@ inline unsigned blocks(int64_t n, int t) { return unsigned((n + t - 1) / t); }
 size_t grid_bytes(int64_t n)
 {
     // per particle: keys x2, perm/idx, leaf_of, flags x2, q0, q1, qa, need, g0, g1
-    size_t per = 8 * 2 + 4 * 2 + 4 + 4 * 2 + 16 * 2 + 8 + 1 + 16 * 2 + 4 + 32;
+    size_t per = 8 * 2 + 4 * 2 + 4 + 4 * 2 + 16 * 2 + 8 + 1 + 16 * 2 + 4 + 32 + 8;
     // per leaf (at most n leaves): start, origin, tree nodes (~8/7 of the
     // leaves: lo, hi, radius), partial sums
     size_t per_leaf = 4 + 24 + 16 + (48 + 4) * 8 / 7 + 1 + 48;
@@ -363,7 +367,7 @@ void grid_free(sphx_grid *g)
                     g->node_hi, g->node_r,   g->fsum,     g->sort_tmp, g->keys_in, g->idx_in,
                     g->flags,   g->d_status, g->hs,       g->d0,       g->d1,
                     g->lrad,    g->lcnt,     g->lcap,     g->lboff,    g->lst,    g->lscan_tmp,
-                    g->leaf_ext};
+                    g->leaf_ext, g->hlo,    g->hhi};
     for (void *p : ptrs)
         dfree(p, g->stream);
     delete g;
@@ -374,7 +378,7 @@ sphx_status iter_reset(sphx_grid *g, const sphx_particles *in, hipStream_t s)
     if (g->n == 0)
         return SPHX_OK;
     k_iter_reset<<<blocks(g->n, 256), 256, 0, s>>>(g->n, g->perm, in->active, in->h, g->need,
-                                                    g->hs);
+                                                    g->hs, g->hlo, g->hhi);
     SPHX_HIP(hipGetLastError());
     return SPHX_OK;
 }
@@ -384,7 +388,7 @@ sphx_status refresh_h(sphx_grid *g, const sphx_particles *in, hipStream_t s)
     if (g->n == 0)
         return SPHX_OK;
     k_iter_reset<<<blocks(g->n, 256), 256, 0, s>>>(g->n, g->perm, in->active, in->h, nullptr,
-                                                    g->hs);
+                                                    g->hs, nullptr, nullptr);
     SPHX_HIP(hipGetLastError());
     return SPHX_OK;
 }
@@ -423,6 +427,8 @@ sphx_status grid_build(sphx_ctx *ctx, const sphx_particles *in, hipStream_t s, s
     SPHX_TRY(dalloc(&g->g0, n, s));
     SPHX_TRY(dalloc(&g->g1, n, s));
     SPHX_TRY(dalloc(&g->hs, n, s));
+    SPHX_TRY(dalloc(&g->hlo, n, s));
+    SPHX_TRY(dalloc(&g->hhi, n, s));
     SPHX_TRY(dalloc(&g->d0, n, s));
     SPHX_TRY(dalloc(&g->d1, n, s));
 

@@ -120,6 +120,8 @@ struct sphx_grid {
     uint8_t *need;      // 1: needs a density pass
     float *hs;          // h in sorted order (kept equal to the caller's h by iter_reset,
                         // refresh_h and the ghost)
+    float *hlo, *hhi;   // per particle, sorted: bracket of the h iteration's root
+                        // (largest h with G < 0, smallest with G > 0), reset by iter_reset
     float4 *d0;         // density results in sorted order: n, 3 + h n'/n, rho, 1 + h rho'/(3 rho)
     float4 *d1;         // div_sum, curl_x, curl_y, curl_z
     float4 *g0;         // force-pass state: h, rho, P, c

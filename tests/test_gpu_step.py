@@ -75,7 +75,8 @@ def test_step_matches_oracle_iteration(case, variant):
     if variant == "cellpair" or info.passes == 1:
         assert info.list_builds == 0
     else:
-        assert info.list_builds >= 1 and info.list_entries >= ps.n
+        # (entries of the last build, which may cover only the receivers left)
+        assert info.list_builds >= 1 and info.list_entries > 0
     dh = compare_step(g, ref, case)
     print("  passes gpu=%d oracle=%d, list builds %d, fallback %d, max |dh|/h=%.2e, "
           "median %.2e" % (info.passes, ref["passes"], info.list_builds, info.list_fallback,
@@ -196,7 +197,10 @@ def test_active_subset_step():
     b = np.stack([fo[k] for k in ("ax", "ay", "az")], 1)
     nb = np.linalg.norm(b, axis=1)
     err = np.linalg.norm(a - b, axis=1) / np.maximum(nb, rms(nb))
-    dmax = (np.abs(hg[ridx] - h2) / h2).max()
+    # first-order h effect: the receivers' h and, through H_j, f_j and A_j, the
+    # sources' h (step 1 on both sides, each converged to 1e-4 on its own)
+    dmax = max((np.abs(hg[ridx] - h2) / h2).max(),
+               (np.abs(h1.astype(np.float64) - r1["h"]) / r1["h"]).max())
     assert err.max() <= 1e-4 + 50 * dmax, "active accel worst %.3g" % err.max()
 
 

@@ -223,3 +223,85 @@ def test_h_solve_iteration_cap_and_h_max():
     h, dens, conv, _, _ = oracle.solve_h(ps, P, mode="brute")
     assert conv.all()
     np.testing.assert_allclose(h, P.hmax(), rtol=0, atol=0)
+
+
+def _synthetic_update(g, dg, h, P, lo=None, hi=None):
+    """One oracle h update for a synthetic condition G(ln h) = g(ln h): the
+    density sums are chosen so that ln(n h^3 / eta^3) = g and
+    3 + h n'/n = g'."""
+    x = np.log(h)
+    eta3 = P.eta ** 3
+    nd = eta3 * np.exp(g(x)) / h ** 3
+    nd_dh = nd * (dg(x) - 3.0) / h
+    return oracle.h_update(h, nd, nd_dh, P, lo, hi)
+
+
+def test_h_update_without_bracket_is_the_clamped_newton_step():
+    P = oracle.Params()
+    h = np.array([1.0, 0.02, 0.05])
+    g = lambda x: 0.3 * (x + 3.0)  # root at ln h = -3
+    dg = lambda x: 0.3 + 0 * x
+    hn, _ = _synthetic_update(g, dg, h, P)
+    step = np.clip(-g(np.log(h)) / dg(np.log(h)), -np.log(2), np.log(2))
+    np.testing.assert_allclose(hn, np.minimum(h * np.exp(step), P.hmax()), rtol=1e-14)
+
+
+def test_h_update_bisects_a_step_that_leaves_the_bracket():
+    """h = 0.1 with G > 0 (so the bracket's top becomes 0.1); the bottom is
+    0.05; a Newton step to below 0.05 is replaced by sqrt(0.05 * 0.1)."""
+    P = oracle.Params()
+    h = np.array([0.1])
+    lo, hi = np.array([0.05]), np.array([np.inf])
+    g = lambda x: 5.0 + 0 * x       # far above the root
+    dg = lambda x: 1.0 + 0 * x      # Newton wants a factor e^-5, clamped to 1/2
+    hn, conv = _synthetic_update(g, dg, h, P, lo, hi)
+    assert hi[0] == 0.1 and lo[0] == 0.05 and not conv[0]
+    np.testing.assert_allclose(hn, [np.sqrt(0.05 * 0.1)], rtol=1e-15)
+
+
+def test_h_update_keeps_a_converging_step_on_the_bracket_edge():
+    """A step smaller than the tolerance stands, even where it lands on an end
+    of the bracket: at h = 0.1 a small positive G makes 0.1 the bracket's top,
+    and with a steep G the Newton step rounds to zero, so the new h is that
+    top itself. The particle converges and keeps its h; it is not bisected
+    toward the bottom at 0.05."""
+    P = oracle.Params()
+    h = np.array([0.1])
+    lo, hi = np.array([0.05]), np.array([np.inf])
+    g = lambda x: 1e-13 + 0 * x
+    dg = lambda x: 1e4 + 0 * x
+    hn, conv = _synthetic_update(g, dg, h, P, lo, hi)
+    assert hi[0] == 0.1 and 0.1 * np.exp(-1e-17) == 0.1
+    assert conv[0] and hn[0] == 0.1
+    # a step of the same kind that would not converge is bisected
+    h = np.array([0.1])
+    lo, hi = np.array([0.0999]), np.array([np.inf])
+    g = lambda x: 0.3 + 0 * x
+    dg = lambda x: 3.0 + 0 * x
+    hn, conv = _synthetic_update(g, dg, h, P, lo, hi)
+    assert not conv[0]
+    np.testing.assert_allclose(hn, [np.sqrt(0.0999 * 0.1)], rtol=1e-15)
+
+
+def test_h_solve_safeguard_converges_where_newton_cycles():
+    """G(ln h) = cbrt(ln h - ln h*) (root h*, infinitely steep there): Newton
+    in ln h maps the offset x to -2x and never converges; with the bracket it
+    reaches h* within the tolerance."""
+    P = oracle.Params()
+    hstar = 0.05
+    g = lambda x: np.cbrt(x - np.log(hstar))
+    dg = lambda x: (1.0 / 3.0) * np.abs(x - np.log(hstar)) ** (-2.0 / 3.0)
+    # plain Newton (a fresh bracket every step): cycles
+    h = np.array([hstar * 1.1])
+    for _ in range(40):
+        h, conv = _synthetic_update(g, dg, h, P)
+    assert not conv[0] and abs(np.log(h[0] / hstar)) > 1e-3
+    # safeguarded: converges to h*
+    h = np.array([hstar * 1.1])
+    lo, hi = np.zeros(1), np.full(1, np.inf)
+    for it in range(60):
+        hn, conv = _synthetic_update(g, dg, h, P, lo, hi)
+        if conv[0]:
+            break
+        h = hn
+    assert conv[0] and abs(h[0] / hstar - 1.0) < 4 * P.h_tol
