@@ -259,15 +259,17 @@ sphx_status sphx_step(sphx_ctx *ctx, sphx_grid *grid, sphx_tasks **tasks, sphx_p
                       double *d_sums6, void *stream, sphx_step_info *info);
 
 /* Autotuner: times each density-loop shape (tile x waves, unbalanced rounds;
- * density_balance is returned as given) on fixed-h density
- * passes, and each force-loop shape on force passes, over this grid and task
- * list at the particles' current h (reps launches each, HIP events on
- * `stream`), and returns in *tuned the context's parameters with the fastest
- * shapes. The output arrays are overwritten (density and ghost at the
- * current h, then the force); h is not changed. Contexts created from *tuned
- * give identical results to each other, so a caller that needs the same
- * results from several contexts (a server's slots) tunes once and creates
- * all of them from *tuned. Synchronises the stream. */
+ * density_balance is returned as given) on whole steps (as sphx_step, pass by
+ * pass, from the particles' current h, iterating on a device copy of h), and
+ * each force-loop shape on force passes at the converged state; the shortest
+ * of reps timed runs (after one untimed run) counts, HIP events on `stream`.
+ * Returns in *tuned the context's parameters with the fastest shapes. The
+ * output arrays are overwritten; h is not changed; the task list is left as
+ * a build at the current h leaves it. Allocates n floats for the copy of h.
+ * Contexts created from *tuned give identical results to each other, so a
+ * caller that needs the same results from several contexts (a server's
+ * slots) tunes once and creates all of them from *tuned. Synchronises the
+ * stream. */
 sphx_status sphx_autotune(sphx_ctx *ctx, sphx_grid *grid, sphx_tasks *tasks, sphx_particles *in,
                           sphx_density_out *dens, sphx_ghost_out *gst, sphx_force_out *out,
                           int32_t reps, sphx_params *tuned, void *stream);

@@ -50,7 +50,7 @@ __global__ __launch_bounds__(64 * NW) void k_force(
     const float4 *__restrict__ q1, const float2 *__restrict__ qa, const float4 *__restrict__ g0,
     const float4 *__restrict__ g1, const uint8_t *__restrict__ active,
     const int32_t *__restrict__ toff, const Task *__restrict__ task,
-    const float4 *__restrict__ ext, const float *__restrict__ radius, float gamma_k, float beta,
+    const float4 *__restrict__ ext, const float *__restrict__ hmax, float gamma_k, float beta,
     float *__restrict__ o_ax, float *__restrict__ o_ay, float *__restrict__ o_az,
     float *__restrict__ o_du, float *__restrict__ o_vsig, int32_t *__restrict__ o_nf,
     double *__restrict__ fsum, const int32_t *__restrict__ gate)
@@ -231,10 +231,10 @@ __global__ __launch_bounds__(64 * NW) void k_force(
         const int nb = min(64, t_end - tb);
         TaskRegs tr;
         tr.load(task, tb + lane, lane < nb);
-        // whole source cells beyond max(R, the cell's search radius) of the
-        // receivers' box are skipped (the radius bounds every H_j of the cell)
+        // whole source cells beyond max(R, the cell's largest H_j) of the
+        // receivers' box are skipped
         if (lane < nb) {
-            const float rj = radius[tr.a.w];
+            const float rj = hmax[tr.a.w];
             if (task_box_dist2(tr.b.x, tr.b.y, tr.b.z, ext[tr.a.w], lo, hb) >= fmaxf(R2, rj * rj))
                 tr.a.y = 0;
         }
@@ -333,6 +333,27 @@ __global__ __launch_bounds__(64 * NW) void k_force(
     }
 }
 
+// One wave per leaf: the largest search radius gamma_k h of the leaf's
+// particles in the force-pass state (their final h), which bounds every H_j
+// of a source cell more tightly than the task list's radius.
+__global__ __launch_bounds__(64) void k_leaf_hmax(int64_t n_leaves,
+                                                  const int32_t *__restrict__ leaf_start,
+                                                  const float4 *__restrict__ g0, float gamma_k,
+                                                  float *__restrict__ hmax,
+                                                  const int32_t *__restrict__ gate)
+{
+    const int64_t L = blockIdx.x;
+    if (L >= n_leaves || (gate && *gate))
+        return;
+    const int lane = threadIdx.x;
+    const int32_t s0 = leaf_start[L], cnt = leaf_start[L + 1] - s0;
+    float v = lane < cnt ? g0[s0 + lane].x : 0.0f;
+    for (int o = 32; o > 0; o >>= 1)
+        v = fmaxf(v, __shfl_xor(v, o, 64));
+    if (lane == 0)
+        hmax[L] = gamma_k * v;
+}
+
 // Fixed-order FP64 reduction of the per-leaf partial sums (one block).
 __global__ __launch_bounds__(256) void k_sum_leaves(int64_t n_leaves,
                                                     const double *__restrict__ fsum,
@@ -378,6 +399,9 @@ sphx_status force_launch(const sphx_ctx *ctx, const sphx_grid *g, const sphx_tas
             state_ready ? in->active : nullptr, g->g0, g->g1);
         SPHX_HIP(hipGetLastError());
     }
+    k_leaf_hmax<<<unsigned(g->n_leaves), 64, 0, s>>>(g->n_leaves, g->leaf_start, g->g0,
+                                                      float(ctx->p.gamma_k), g->leaf_hmax, gate);
+    SPHX_HIP(hipGetLastError());
     const int64_t nbp = pad8(g->n_leaves);
     SPHX_HIP(ctx->prof->begin(1, s));
     const int tile = ctx->p.force_tile ? ctx->p.force_tile : 64;
@@ -385,7 +409,7 @@ sphx_status force_launch(const sphx_ctx *ctx, const sphx_grid *g, const sphx_tas
 #define SPHX_FORCE_LAUNCH(CAP_, NW_)                                                           \
     k_force<CAP_, NW_><<<unsigned(nbp), 64 * NW_, 0, s>>>(                                     \
         g->n_leaves, nbp, t->order, g->leaf_start, g->perm, g->q0, g->q1, g->qa, g->g0, g->g1, \
-        in->active, t->off, t->task, g->leaf_ext, t->radius, float(ctx->p.gamma_k),            \
+        in->active, t->off, t->task, g->leaf_ext, g->leaf_hmax, float(ctx->p.gamma_k),         \
         float(ctx->p.beta_v), o->ax,                                                           \
         o->ay, o->az, o->du_dt, o->v_sig, o->nforce, g->fsum, gate)
     if (waves == 1) {

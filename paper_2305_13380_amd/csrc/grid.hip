@@ -353,7 +353,7 @@ size_t grid_bytes(int64_t n)
     size_t per = 8 * 2 + 4 * 2 + 4 + 4 * 2 + 16 * 2 + 8 + 1 + 16 * 2 + 4 + 32 + 8;
     // per leaf (at most n leaves): start, origin, tree nodes (~8/7 of the
     // leaves: lo, hi, radius), partial sums
-    size_t per_leaf = 4 + 24 + 16 + (48 + 4) * 8 / 7 + 1 + 48;
+    size_t per_leaf = 4 + 24 + 16 + 4 + (48 + 4) * 8 / 7 + 1 + 48;
     size_t sort_tmp = size_t(n) * 16 + (1 << 20);
     return size_t(n) * (per + per_leaf) + sort_tmp + (1 << 16);
 }
@@ -367,7 +367,7 @@ void grid_free(sphx_grid *g)
                     g->node_hi, g->node_r,   g->fsum,     g->sort_tmp, g->keys_in, g->idx_in,
                     g->flags,   g->d_status, g->hs,       g->d0,       g->d1,
                     g->lrad,    g->lcnt,     g->lcap,     g->lboff,    g->lst,    g->lscan_tmp,
-                    g->leaf_ext, g->hlo,    g->hhi};
+                    g->leaf_ext, g->leaf_hmax, g->hlo, g->hhi};
     for (void *p : ptrs)
         dfree(p, g->stream);
     delete g;
@@ -533,6 +533,7 @@ sphx_status grid_build(sphx_ctx *ctx, const sphx_particles *in, hipStream_t s, s
     g->n_nodes = off;
     SPHX_TRY(dalloc(&g->leaf_org, 3 * nl, s));
     SPHX_TRY(dalloc(&g->leaf_ext, nl, s));
+    SPHX_TRY(dalloc(&g->leaf_hmax, nl, s));
     SPHX_TRY(dalloc(&g->node_lo, 3 * off, s));
     SPHX_TRY(dalloc(&g->node_hi, 3 * off, s));
     SPHX_TRY(dalloc(&g->node_r, off, s));

@@ -131,6 +131,7 @@ struct sphx_grid {
     int32_t *leaf_start;  // n_leaves + 1
     double *leaf_org;     // 3 * n_leaves, FP64 origin (minimum corner of the particles' box)
     float4 *leaf_ext;     // n_leaves: largest FP32 cell-relative x, y, z of the leaf's particles
+    float *leaf_hmax;     // n_leaves: gamma_k * largest h of the leaf at the force pass
 
     // per tree node (all levels)
     double *node_lo;    // 3 * n_nodes
@@ -186,11 +187,10 @@ struct sphx_tasks {
     int64_t order_cap;
     // Rebuilds in one tree walk: the walk writes each leaf's tasks into its
     // slot of the `soff` layout (capacity count + count/4 + 8 from the last
-    // two-pass build) while counting them, and they are compacted into `task`;
-    // a leaf over its capacity sends the rebuild back to the two-pass build.
+    // build) while counting them, and they are compacted into `task`; only
+    // the leaves over their capacity are walked a second time.
     sphx::Task *slack;  // slack_cap
     int32_t *soff;      // n_leaves + 1
-    int32_t *flag;      // [0]: a leaf exceeded its capacity
     int64_t slack_cap;
     bool slack_ok;      // soff holds a layout for this grid
 };

@@ -4,6 +4,9 @@
 // cell size matches the local search radius). The search walks a tree of
 // bounding boxes over the Morton-ordered leaves once per rebuild; the
 // neighbour loops themselves never walk it.
+#include <algorithm>
+#include <climits>
+
 #include <rocprim/device/device_radix_sort.hpp>
 #include <rocprim/device/device_scan.hpp>
 
@@ -263,13 +266,15 @@ __device__ __forceinline__ int wave_prefix_small(int v, int &total)
 // ascending order, so the cells (and their shifts) come out in the same order
 // as in the serial walk. A frontier that would exceed kFront marks the cell
 // for the serial walk instead. MODE 0 counts; MODE 1 writes at off[I];
-// MODE 2 writes at off[I] (the slack layout) up to the cell's capacity
-// off[I+1] - off[I] and counts.
+// MODE 2 writes into the cell's slot of the slack layout, at slot[I] up to
+// its size slot[I+1] - slot[I], and counts; MODE 3 writes at off[I] the cells
+// whose MODE 2 count exceeded their slot (the others return at once).
 template <int MODE>
 __global__ __launch_bounds__(64) void k_task_bfs(int64_t n_leaves, TreeView T,
                                                  const double *__restrict__ org,
                                                  const int32_t *__restrict__ leaf_start,
                                                  const int32_t *__restrict__ off,
+                                                 const int32_t *__restrict__ slot,
                                                  int32_t *__restrict__ count,
                                                  uint8_t *__restrict__ overflow,
                                                  Task *__restrict__ task)
@@ -277,8 +282,10 @@ __global__ __launch_bounds__(64) void k_task_bfs(int64_t n_leaves, TreeView T,
     const int64_t I = blockIdx.x;
     if (I >= n_leaves)
         return;
-    constexpr bool COUNT = MODE != 1, WRITE = MODE != 0;
+    constexpr bool COUNT = MODE == 0 || MODE == 2, WRITE = MODE != 0;
     if (!COUNT && overflow[I])
+        return;
+    if (MODE == 3 && count[I] <= slot[I + 1] - slot[I])
         return;
     const int lane = threadIdx.x;
     __shared__ int32_t front[2][kFront];
@@ -298,8 +305,8 @@ __global__ __launch_bounds__(64) void k_task_bfs(int64_t n_leaves, TreeView T,
     for (int k = lane; k < ncur; k += 64)
         front[0][k] = k;
     int emitted = 0;
-    const int32_t wbase = WRITE ? off[I] : 0;
-    const int32_t wcap = MODE == 2 ? off[I + 1] - off[I] : 0x7fffffff;
+    const int32_t wbase = MODE == 2 ? slot[I] : (WRITE ? off[I] : 0);
+    const int32_t wcap = MODE == 2 ? slot[I + 1] - slot[I] : 0x7fffffff;
     const double oxi = org[3 * I], oyi = org[3 * I + 1], ozi = org[3 * I + 2];
     for (int lev = top; lev >= 0; --lev) {
         __syncthreads();
@@ -380,23 +387,9 @@ __global__ __launch_bounds__(64) void k_task_bfs(int64_t n_leaves, TreeView T,
         count[I] = emitted;
 }
 
-// Flag a walked cell (not left to the serial walk) whose tasks exceeded its
-// slot in the slack layout; one atomic per block.
-__global__ __launch_bounds__(256) void k_check_slack(int64_t n_leaves,
-                                                     const int32_t *__restrict__ soff,
-                                                     const int32_t *__restrict__ count,
-                                                     const uint8_t *__restrict__ overflow,
-                                                     int32_t *__restrict__ flag)
-{
-    const int64_t I = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    const bool over =
-        I < n_leaves && !overflow[I] && count[I] > soff[I + 1] - soff[I];
-    if (__syncthreads_or(over) && threadIdx.x == 0)
-        atomicOr(flag, 1);
-}
-
-// Compaction of the one-walk rebuild: each walked cell's tasks from its
-// slack slot to its place in the list.
+// Compaction of the one-walk rebuild: the tasks of each walked cell that fit
+// its slack slot, from the slot to the cell's place in the list (the cells
+// that did not fit are walked again, straight into the list).
 __global__ __launch_bounds__(64) void k_compact_tasks(int64_t n_leaves,
                                                       const int32_t *__restrict__ soff,
                                                       const int32_t *__restrict__ off,
@@ -409,6 +402,8 @@ __global__ __launch_bounds__(64) void k_compact_tasks(int64_t n_leaves,
     if (I >= n_leaves || overflow[I])
         return;
     const int32_t n = count[I], a = soff[I], b = off[I];
+    if (n > soff[I + 1] - a)
+        return;
     for (int32_t k = threadIdx.x; k < n; k += 64)
         task[b + k] = slack[a + k];
 }
@@ -441,7 +436,7 @@ void tasks_free(sphx_tasks *t)
     for (void *p : ptrs)
         dfree(p, t->stream);
     for (void *p : {(void *)t->order, (void *)t->okey, (void *)t->okey_out, (void *)t->oval,
-                    t->sort_tmp, (void *)t->slack, (void *)t->soff, (void *)t->flag})
+                    t->sort_tmp, (void *)t->slack, (void *)t->soff})
         dfree(p, t->stream);
     delete t;
 }
@@ -507,8 +502,7 @@ sphx_status tasks_build(sphx_ctx *ctx, sphx_grid *g, const sphx_particles *in, h
             dmalloc((void **)&t->count, (nl + 1) * sizeof(int32_t), s) != hipSuccess ||
             dmalloc((void **)&t->radius, (nl + 1) * sizeof(float), s) != hipSuccess ||
             dmalloc((void **)&t->overflow, (nl + 1) * sizeof(uint8_t), s) != hipSuccess ||
-            dmalloc((void **)&t->soff, (nl + 1) * sizeof(int32_t), s) != hipSuccess ||
-            dmalloc((void **)&t->flag, sizeof(int32_t), s) != hipSuccess) {
+            dmalloc((void **)&t->soff, (nl + 1) * sizeof(int32_t), s) != hipSuccess) {
             set_error("sphx_tasks_build: out of device memory");
             return fail(SPHX_E_OOM);
         }
@@ -579,87 +573,69 @@ sphx_status tasks_build(sphx_ctx *ctx, sphx_grid *g, const sphx_particles *in, h
     int32_t total = 0;
     SPHX_HIP(hipMemsetAsync(t->count + nl, 0, sizeof(int32_t), s));
     SPHX_HIP(hipMemsetAsync(t->overflow, 0, size_t(nl) * sizeof(uint8_t), s));
-    if (t->slack_ok) {
+    const bool one_walk = t->slack_ok;
+    if (one_walk) {
         // One walk: count every cell's tasks and write them into its slot of
-        // the slack layout; if every walked cell fitted, compact and finish.
-        SPHX_HIP(hipMemsetAsync(t->flag, 0, sizeof(int32_t), s));
-        k_task_bfs<2><<<unsigned(nl), 64, 0, s>>>(nl, T, g->leaf_org, g->leaf_start, t->soff,
-                                                  t->count, t->overflow, t->slack);
-        SPHX_HIP(hipGetLastError());
-        k_task_count<<<blocks(nl, 64), 64, 0, s>>>(nl, T, t->overflow, t->count);
-        SPHX_HIP(hipGetLastError());
-        k_check_slack<<<blocks(nl, 256), 256, 0, s>>>(nl, t->soff, t->count, t->overflow,
-                                                       t->flag);
-        SPHX_HIP(hipGetLastError());
-        SPHX_HIP(rocprim::exclusive_scan(t->scan_tmp, tmp, t->count, t->off, 0, size_t(nl + 1),
-                                         rocprim::plus<int32_t>(), s));
-        int32_t flag = 0;
-        SPHX_HIP(hipMemcpyAsync(&total, t->off + nl, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-        SPHX_HIP(hipMemcpyAsync(&flag, t->flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-        SPHX_HIP(hipStreamSynchronize(s));
-        if (total < 0) {
-            set_error("sphx_tasks_build: task count overflow");
-            return SPHX_E_INVALID;
-        }
-        if (flag == 0) {
-            SPHX_TRY(ensure_task_cap(total));
-            t->n_tasks = total;
-            k_compact_tasks<<<unsigned(nl), 64, 0, s>>>(nl, t->soff, t->off, t->count,
-                                                        t->overflow, t->slack, t->task);
-            SPHX_HIP(hipGetLastError());
-            k_task_fill<<<blocks(nl, 64), 64, 0, s>>>(nl, T, g->leaf_org, g->leaf_start,
-                                                      t->overflow, t->off, t->task);
-            SPHX_HIP(hipGetLastError());
-            SPHX_TRY(leaf_order(t, nl, s));
-            guard.keep = true;
-            *out = t;
-            return SPHX_OK;
-        }
-        // Some cell outgrew its slot: the counts are exact, so only the
-        // writing walk remains (below), followed by new slots.
+        // the slack layout (slots sized from the previous build's counts).
+        k_task_bfs<2><<<unsigned(nl), 64, 0, s>>>(nl, T, g->leaf_org, g->leaf_start, t->off,
+                                                  t->soff, t->count, t->overflow, t->slack);
     } else {
         k_task_bfs<0><<<unsigned(nl), 64, 0, s>>>(nl, T, g->leaf_org, g->leaf_start, t->off,
-                                                  t->count, t->overflow, t->task);
-        SPHX_HIP(hipGetLastError());
-        k_task_count<<<blocks(nl, 64), 64, 0, s>>>(nl, T, t->overflow, t->count);
-        SPHX_HIP(hipGetLastError());
-        SPHX_HIP(rocprim::exclusive_scan(t->scan_tmp, tmp, t->count, t->off, 0, size_t(nl + 1),
-                                         rocprim::plus<int32_t>(), s));
-        SPHX_HIP(hipMemcpyAsync(&total, t->off + nl, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-        SPHX_HIP(hipStreamSynchronize(s));
-        if (total < 0) {
-            set_error("sphx_tasks_build: task count overflow");
-            return SPHX_E_INVALID;
-        }
+                                                  t->soff, t->count, t->overflow, t->task);
+    }
+    SPHX_HIP(hipGetLastError());
+    k_task_count<<<blocks(nl, 64), 64, 0, s>>>(nl, T, t->overflow, t->count);
+    SPHX_HIP(hipGetLastError());
+    SPHX_HIP(rocprim::exclusive_scan(t->scan_tmp, tmp, t->count, t->off, 0, size_t(nl + 1),
+                                     rocprim::plus<int32_t>(), s));
+    SPHX_HIP(hipMemcpyAsync(&total, t->off + nl, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    SPHX_HIP(hipStreamSynchronize(s));
+    if (total < 0) {
+        set_error("sphx_tasks_build: task count overflow");
+        return SPHX_E_INVALID;
     }
     SPHX_TRY(ensure_task_cap(total));
     t->n_tasks = total;
-    k_task_bfs<1><<<unsigned(nl), 64, 0, s>>>(nl, T, g->leaf_org, g->leaf_start, t->off,
-                                              t->count, t->overflow, t->task);
+    if (one_walk) {
+        // cells that fitted: from the slot into the list; the others (a few
+        // cells whose h grew most) are walked again, writing at their place
+        k_compact_tasks<<<unsigned(nl), 64, 0, s>>>(nl, t->soff, t->off, t->count, t->overflow,
+                                                    t->slack, t->task);
+        SPHX_HIP(hipGetLastError());
+        k_task_bfs<3><<<unsigned(nl), 64, 0, s>>>(nl, T, g->leaf_org, g->leaf_start, t->off,
+                                                  t->soff, t->count, t->overflow, t->task);
+    } else {
+        k_task_bfs<1><<<unsigned(nl), 64, 0, s>>>(nl, T, g->leaf_org, g->leaf_start, t->off,
+                                                  t->soff, t->count, t->overflow, t->task);
+    }
     SPHX_HIP(hipGetLastError());
     k_task_fill<<<blocks(nl, 64), 64, 0, s>>>(nl, T, g->leaf_org, g->leaf_start, t->overflow,
                                               t->off, t->task);
     SPHX_HIP(hipGetLastError());
-    // slots of the slack layout for the next rebuild, from these counts
+    // Slots of the slack layout for the next rebuild, from these counts
+    // (count + count/4 + 8 per cell); the buffer is sized from the host's
+    // bound on their sum, so no readback is needed.
     t->slack_ok = false;
-    k_slack_sizes<<<blocks(nl + 1, 256), 256, 0, s>>>(nl, t->count, t->count);
-    SPHX_HIP(hipGetLastError());
-    SPHX_HIP(rocprim::exclusive_scan(t->scan_tmp, tmp, t->count, t->soff, 0, size_t(nl + 1),
-                                     rocprim::plus<int32_t>(), s));
-    int32_t slack_total = 0;
-    SPHX_HIP(hipMemcpyAsync(&slack_total, t->soff + nl, sizeof(int32_t), hipMemcpyDeviceToHost,
-                            s));
-    SPHX_HIP(hipStreamSynchronize(s));
-    if (slack_total > 0 && int64_t(slack_total) > t->slack_cap) {
-        dfree(t->slack, s);
-        t->slack = nullptr;
-        t->slack_cap = 0;
-        if (dmalloc((void **)&t->slack, size_t(slack_total) * sizeof(Task), s) == hipSuccess)
-            t->slack_cap = slack_total;
-        else
-            (void)hipGetLastError();  // no slack: rebuilds keep two walks
+    const int64_t bound = int64_t(total) + int64_t(total) / 4 + 8 * nl;
+    if (bound <= int64_t(INT32_MAX)) {
+        if (bound > t->slack_cap) {
+            dfree(t->slack, s);
+            t->slack = nullptr;
+            t->slack_cap = 0;
+            const int64_t want = std::min<int64_t>(bound + bound / 8, int64_t(INT32_MAX));
+            if (dmalloc((void **)&t->slack, size_t(want) * sizeof(Task), s) == hipSuccess)
+                t->slack_cap = want;
+            else
+                (void)hipGetLastError();  // no slack: rebuilds keep two walks
+        }
+        if (t->slack && t->slack_cap >= bound) {
+            k_slack_sizes<<<blocks(nl + 1, 256), 256, 0, s>>>(nl, t->count, t->count);
+            SPHX_HIP(hipGetLastError());
+            SPHX_HIP(rocprim::exclusive_scan(t->scan_tmp, tmp, t->count, t->soff, 0,
+                                             size_t(nl + 1), rocprim::plus<int32_t>(), s));
+            t->slack_ok = true;
+        }
     }
-    t->slack_ok = slack_total > 0 && t->slack && t->slack_cap >= int64_t(slack_total);
     SPHX_TRY(leaf_order(t, nl, s));
     guard.keep = true;
     *out = t;

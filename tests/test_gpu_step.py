@@ -223,11 +223,13 @@ def test_step_rejects_null_outputs():
     assert np.all(np.isnan(out.d["n"].cpu().numpy()))  # nothing ran
 
 
-@pytest.mark.parametrize("growth", [1.02, 1.6])
-def test_rebuild_in_place_matches_fresh_build(growth):
+@pytest.mark.parametrize("growth,region", [(1.02, 1.0), (1.6, 1.0), (1.6, 0.3)])
+def test_rebuild_in_place_matches_fresh_build(growth, region):
     """Rebuilding a task list in place (one walk into the slot layout of the
-    previous build when every cell fits, else two walks) gives the same task
-    list as a fresh build: a fixed-h pass over either is bitwise the same."""
+    previous build; the cells that outgrew their slot are walked again, the
+    others compacted from it) gives the same task list as a fresh build: a
+    fixed-h pass over either is bitwise the same. h grows by `growth` for the
+    particles with x < region: every cell fits, most outgrow, or a mix."""
     import torch
     from paper_2305_13380_amd import sphx
     ps = inputs.lognormal_box(16, 6000, 2.0, 41)
@@ -235,10 +237,12 @@ def test_rebuild_in_place_matches_fresh_build(growth):
     dp = sphx.DeviceParticles.from_set(ps)
     grid = sphx.Grid(ctx, dp)
     tasks = sphx.Tasks(ctx, grid, dp)
-    dp.t["h"].mul_(growth)
+    first = tasks.count
+    sel = torch.as_tensor(ps.x < region, device=dp.t["h"].device)
+    dp.t["h"].copy_(torch.where(sel, dp.t["h"] * growth, dp.t["h"]))
     tasks.build(dp)  # in place
     fresh = sphx.Tasks(ctx, grid, dp)
-    assert tasks.count == fresh.count
+    assert tasks.count == fresh.count and (growth < 1.1 or tasks.count > first)
     res = []
     for t in (tasks, fresh):
         out = sphx.Outputs(ps.n)
