@@ -362,8 +362,16 @@ static sphx_status step_run(sphx_ctx *ctx, sphx_grid *grid, sphx_tasks **tasks,
     int stale_repeats = 0;
     while (pass < max_iter) {
         SPHX_HIP(hipMemsetAsync(dc, 0, kStepCounters * sizeof(int32_t), s));
+        // Before the first pass: an h that outgrew the task list since it was
+        // built (the caller's h, or the previous step's list) makes the pass
+        // return at once; the list is rebuilt below and the pass repeated.
+        const int32_t *skip = nullptr;
+        if (pass == 0 && !lists) {
+            SPHX_TRY(stale_count_launch(ctx, grid, *tasks, dc + 3, s));
+            skip = dc + 3;
+        }
         if (!lists || beyond > 0)
-            SPHX_TRY(density_launch(ctx, grid, *tasks, in, dens, dc, lists, s));
+            SPHX_TRY(density_launch(ctx, grid, *tasks, in, dens, dc, lists, s, skip));
         if (lists)
             SPHX_TRY(density_list_launch(ctx, grid, *tasks, dens, s));
         const int final_pass = (pass + 1 == max_iter) ? 1 : 0;

@@ -465,6 +465,33 @@ static DensOut dens_out(const sphx_grid *g, const sphx_density_out *o)
                    o->curl_y, o->curl_z, o->nngb,   g->d0,    g->d1};
 }
 
+// Receivers whose H exceeds their leaf's task radius (the density loop's own
+// staleness test), counted before the first pass of a step: a caller's h may
+// have outgrown the task list since it was built, and a pass on a stale list
+// would be thrown away. Any count > 0 makes the pass return at once.
+__global__ __launch_bounds__(256) void k_stale_count(int64_t n, const uint8_t *__restrict__ need,
+                                                     const float *__restrict__ hs,
+                                                     const int32_t *__restrict__ leaf_of,
+                                                     const float *__restrict__ radius,
+                                                     float gamma_k, int32_t *__restrict__ stale)
+{
+    const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    const bool st = i < n && need[i] && gamma_k * hs[i] > radius[leaf_of[i]];
+    if (__syncthreads_or(st) && threadIdx.x == 0)
+        atomicAdd(stale, 1);
+}
+
+sphx_status stale_count_launch(const sphx_ctx *ctx, const sphx_grid *g, const sphx_tasks *t,
+                               int32_t *stale, hipStream_t s)
+{
+    if (g->n == 0 || g->n_leaves == 0)
+        return SPHX_OK;
+    k_stale_count<<<unsigned((g->n + 255) / 256), 256, 0, s>>>(
+        g->n, g->need, g->hs, g->leaf_of, t->radius, float(ctx->p.gamma_k), stale);
+    SPHX_HIP(hipGetLastError());
+    return SPHX_OK;
+}
+
 sphx_status density_launch(const sphx_ctx *ctx, const sphx_grid *g, const sphx_tasks *t,
                            const sphx_particles *in, const sphx_density_out *o,
                            int32_t *counters, bool use_lists, hipStream_t s, const int32_t *skip)

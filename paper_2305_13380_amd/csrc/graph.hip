@@ -81,8 +81,12 @@ static sphx_status record(sphx_ctx *ctx, StepGraph *G, sphx_grid *grid, sphx_tas
         const int final_pass = (p + 1 == ctx->p.max_iter) ? 1 : 0;
         k_fill_i32<<<1, 64, 0, cs>>>(ctx->d_counters, kStepCounters, 0);
         SPHX_HIP(hipGetLastError());
-        SPHX_TRY(
-            density_launch(ctx, grid, t, in, dens, ctx->d_counters, false, cs, G->d_gate + 2));
+        // the first pass returns at once on a stale task list (the log then
+        // stops the graph and the caller rebuilds)
+        if (p == 0)
+            SPHX_TRY(stale_count_launch(ctx, grid, t, ctx->d_counters + 3, cs));
+        SPHX_TRY(density_launch(ctx, grid, t, in, dens, ctx->d_counters, false, cs,
+                                p == 0 ? ctx->d_counters + 3 : G->d_gate + 2));
         SPHX_TRY(ghost_launch(ctx, grid, t, pin, dens, gst, ctx->d_counters, final_pass, false,
                               units, cs, G->d_gate + 2, true));
         k_log_pass<<<1, 64, 0, cs>>>(ctx->d_counters, G->d_log, p, final_pass, G->d_gate);
