@@ -143,7 +143,6 @@ __global__ __launch_bounds__(64 * NW) void k_density(
     const int32_t gi = perm[s];
     const float hi = act ? hi0 : 1.0f;
     const float H = gamma_k * hi;
-    const float H2 = act ? H * H : -1.0f;
     const float invH = fast_rcp(H);
     if (w == 0 && act && H > radius[L] && counters)
         atomicAdd(counters + 3, 1);
@@ -161,7 +160,49 @@ __global__ __launch_bounds__(64 * NW) void k_density(
     const float R = wave_maxf(act ? H : 0.0f);
     const float R2 = R * R;
 
+    // Lane replication: with n_act receivers needing work, each gets nrep
+    // lanes (the largest power of two with nrep n_act <= 64). Replica j of a
+    // receiver tests and sums the candidates whose running index (over the
+    // whole loop, not the buffer) is j mod nrep, so a cell with few receivers
+    // left runs its tests and pairs nrep times wider; the replicas' partial
+    // sums are added by a butterfly over their lanes at the end (a fixed
+    // order). The running index does not depend on the buffer size, so
+    // neither do the results; nrep = 1 is the plain loop, lane = receiver.
+    const uint64_t amask = __ballot(act);
+    const int n_act = __popcll(amask);
+    int nrep = 1;
+    if (!BAL)
+        while (2 * nrep * n_act <= 64)
+            nrep *= 2;
+    __shared__ uint8_t rmap_all[NW][64];
+    int src = lane;
+    bool ract = act;
+    if (nrep > 1) {
+        if (act)
+            rmap_all[w][lanes_below(amask)] = uint8_t(lane);
+        wave_sync();
+        const int k = lane / nrep;
+        ract = k < n_act;
+        src = ract ? int(rmap_all[w][k]) : lane;
+    }
+    const int rj = lane & (nrep - 1);  // replica index
+    // this lane's receiver (the lane's own particle when nrep = 1)
+    const float4 pr = nrep > 1 ? make_float4(__shfl(pi.x, src, 64), __shfl(pi.y, src, 64),
+                                             __shfl(pi.z, src, 64), __shfl(pi.w, src, 64))
+                               : pi;
+    const float4 vr = nrep > 1 ? make_float4(__shfl(vi.x, src, 64), __shfl(vi.y, src, 64),
+                                             __shfl(vi.z, src, 64), __shfl(vi.w, src, 64))
+                               : vi;
+    const float h_src = nrep > 1 ? __shfl(hi, src, 64) : hi;  // every lane shuffles
+    const float hr = ract ? h_src : 1.0f;
+    const float Hr = gamma_k * hr;
+    const float H2r = ract ? Hr * Hr : -1.0f;
+    const float invHr = nrep > 1 ? fast_rcp(Hr) : invH;
+    const int32_t sr = s0 + src;
+    const int32_t gr = nrep > 1 ? __shfl(gi, src, 64) : gi;
+
     float S[kSums] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    int gbase = 0;  // candidates of the earlier buffers (wave-uniform)
     int nc = 0;   // buffered candidates (wave-uniform)
     int myn = 0;  // this lane's list length (its own particle is listed too)
     float4 *rp = rp_all[w];
@@ -190,7 +231,7 @@ __global__ __launch_bounds__(64 * NW) void k_density(
             }
 #pragma unroll
             for (int q = 0; q < 4; ++q)
-                dens_pair(S, pi, vi, invH, p[q], v[q], on[q]);
+                dens_pair(S, pr, vr, invHr, p[q], v[q], on[q]);
         }
         myn = 0;
     };
@@ -274,33 +315,58 @@ __global__ __launch_bounds__(64 * NW) void k_density(
     };
     // The slot is always written; it is kept (the length advanced) only
     // when the candidate lies inside H.
-    auto accept = [&](int c, const float4 &p) __attribute__((always_inline)) {
-        const float r2 = dist2(pi.x - p.x, pi.y - p.y, pi.z - p.z);
+    auto accept = [&](int c, const float4 &p, bool ok) __attribute__((always_inline)) {
+        const float r2 = dist2(pr.x - p.x, pr.y - p.y, pr.z - p.z);
         my_list[myn] = uint8_t(c);
-        myn += r2 < H2 ? 1 : 0;
+        myn += (ok && r2 < H2r) ? 1 : 0;
     };
     auto flush = [&]() __attribute__((always_inline)) {
         wave_sync();
-        int c = 0;
-        for (; c + 4 <= nc; c += 4) {
-            const float4 p0 = cp[c], p1 = cp[c + 1], p2 = cp[c + 2], p3 = cp[c + 3];
-            accept(c, p0);
-            accept(c + 1, p1);
-            accept(c + 2, p2);
-            accept(c + 3, p3);
-            if (__any(myn > kListMax - 4)) {
-                if (BAL)
-                    compute_bal();
-                else
+        if (nrep == 1) {
+            int c = 0;
+            for (; c + 4 <= nc; c += 4) {
+                const float4 p0 = cp[c], p1 = cp[c + 1], p2 = cp[c + 2], p3 = cp[c + 3];
+                accept(c, p0, true);
+                accept(c + 1, p1, true);
+                accept(c + 2, p2, true);
+                accept(c + 3, p3, true);
+                if (__any(myn > kListMax - 4)) {
+                    if (BAL)
+                        compute_bal();
+                    else
+                        compute();
+                }
+            }
+            for (; c < nc; ++c)
+                accept(c, cp[c], true);
+            if (BAL)
+                compute_bal();
+            else
+                compute();
+        } else {
+            // replica rj takes the slots c with gbase + c = rj (mod nrep)
+            const int c0 = (rj - (gbase & (nrep - 1))) & (nrep - 1);
+            const int m_end = (nc + nrep - 1) / nrep;
+            for (int m = 0; m < m_end; m += 4) {
+                int cq[4];
+                bool ok[4];
+                float4 pq[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int c = c0 + (m + q) * nrep;
+                    ok[q] = c < nc;
+                    cq[q] = ok[q] ? c : 0;
+                    pq[q] = cp[cq[q]];
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    accept(cq[q], pq[q], ok[q]);
+                if (__any(myn > kListMax - 4))
                     compute();
             }
-        }
-        for (; c < nc; ++c)
-            accept(c, cp[c]);
-        if (BAL)
-            compute_bal();
-        else
             compute();
+        }
+        gbase += nc;
         wave_sync();
         nc = 0;
     };
@@ -368,6 +434,12 @@ __global__ __launch_bounds__(64 * NW) void k_density(
     }
     if (nc > 0)
         flush();
+    // the replicas' partial sums, by a butterfly: every replica ends with
+    // the same total (each addition is commutative)
+    for (int o = 1; o < nrep; o <<= 1)
+#pragma unroll
+        for (int k = 0; k < kSums; ++k)
+            S[k] += __shfl_xor(S[k], o, 64);
 
     if (NW > 1) {
         // Add the other waves' partial sums to wave 0's, in wave order.
@@ -385,9 +457,9 @@ __global__ __launch_bounds__(64 * NW) void k_density(
             for (int k = 0; k < kSums; ++k)
                 S[k] += red[((w2 - 1) * kSums + k) * 64 + lane];
     }
-    if (!act)
+    if (!ract || rj != 0)
         return;
-    dens_finish(S, hi, invH, s, gi, o);
+    dens_finish(S, hr, invHr, sr, gr, o);
 }
 
 // List pass: lane = receiver s = 64 b + lane of 64-block b. Entries decode to
@@ -475,10 +547,12 @@ __global__ __launch_bounds__(256) void k_stale_count(int64_t n, const uint8_t *_
                                                      const float *__restrict__ radius,
                                                      float gamma_k, int32_t *__restrict__ stale)
 {
-    const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
-    const bool st = i < n && need[i] && gamma_k * hs[i] > radius[leaf_of[i]];
+    bool st = false;
+    for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n;
+         i += int64_t(gridDim.x) * 256)
+        st = st || (need[i] && gamma_k * hs[i] > radius[leaf_of[i]]);
     if (__syncthreads_or(st) && threadIdx.x == 0)
-        atomicAdd(stale, 1);
+        atomicAdd(stale, 1);  // one per block: at most 1024 on one word
 }
 
 sphx_status stale_count_launch(const sphx_ctx *ctx, const sphx_grid *g, const sphx_tasks *t,
@@ -486,7 +560,8 @@ sphx_status stale_count_launch(const sphx_ctx *ctx, const sphx_grid *g, const sp
 {
     if (g->n == 0 || g->n_leaves == 0)
         return SPHX_OK;
-    k_stale_count<<<unsigned((g->n + 255) / 256), 256, 0, s>>>(
+    const int64_t nb = (g->n + 255) / 256;
+    k_stale_count<<<unsigned(nb < 1024 ? nb : 1024), 256, 0, s>>>(
         g->n, g->need, g->hs, g->leaf_of, t->radius, float(ctx->p.gamma_k), stale);
     SPHX_HIP(hipGetLastError());
     return SPHX_OK;

@@ -354,24 +354,52 @@ __global__ __launch_bounds__(64) void k_leaf_hmax(int64_t n_leaves,
         hmax[L] = gamma_k * v;
 }
 
-// Fixed-order FP64 reduction of the per-leaf partial sums (one block).
+// Fixed-order FP64 reduction of the per-leaf partial sums in two levels:
+// block b of kSumParts sums its contiguous range of leaves (threads stride the
+// range, then a tree over the block), and one block sums the parts in order.
+constexpr int kSumParts = 128;
+
 __global__ __launch_bounds__(256) void k_sum_leaves(int64_t n_leaves,
                                                     const double *__restrict__ fsum,
-                                                    double *__restrict__ out,
+                                                    double *__restrict__ part,
                                                     const int32_t *__restrict__ gate)
 {
     if (gate && *gate)
         return;
     __shared__ double red[6][256];
     const int t = threadIdx.x;
+    const int64_t per = (n_leaves + kSumParts - 1) / kSumParts;
+    const int64_t a0 = int64_t(blockIdx.x) * per;
+    const int64_t a1 = min(n_leaves, a0 + per);
     double a[6] = {0, 0, 0, 0, 0, 0};
-    for (int64_t L = t; L < n_leaves; L += 256)
+    for (int64_t L = a0 + t; L < a1; L += 256)
         for (int k = 0; k < 6; ++k)
             a[k] += fsum[6 * L + k];
     for (int k = 0; k < 6; ++k)
         red[k][t] = a[k];
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
+        if (t < w)
+            for (int k = 0; k < 6; ++k)
+                red[k][t] += red[k][t + w];
+        __syncthreads();
+    }
+    if (t < 6)
+        part[6 * blockIdx.x + t] = red[t][0];
+}
+
+__global__ __launch_bounds__(kSumParts) void k_sum_parts(const double *__restrict__ part,
+                                                         double *__restrict__ out,
+                                                         const int32_t *__restrict__ gate)
+{
+    if (gate && *gate)
+        return;
+    __shared__ double red[6][kSumParts];
+    const int t = threadIdx.x;
+    for (int k = 0; k < 6; ++k)
+        red[k][t] = part[6 * t + k];
+    __syncthreads();
+    for (int w = kSumParts / 2; w > 0; w >>= 1) {
         if (t < w)
             for (int k = 0; k < 6; ++k)
                 red[k][t] += red[k][t + w];
@@ -427,7 +455,10 @@ sphx_status force_launch(const sphx_ctx *ctx, const sphx_grid *g, const sphx_tas
     SPHX_HIP(hipGetLastError());
     SPHX_HIP(ctx->prof->end(1, s));
     if (sums6) {
-        k_sum_leaves<<<1, 256, 0, s>>>(g->n_leaves, g->fsum, sums6, gate);
+        double *part = g->fsum + 6 * g->n_leaves;
+        k_sum_leaves<<<kSumParts, 256, 0, s>>>(g->n_leaves, g->fsum, part, gate);
+        SPHX_HIP(hipGetLastError());
+        k_sum_parts<<<1, kSumParts, 0, s>>>(part, sums6, gate);
         SPHX_HIP(hipGetLastError());
     }
     return SPHX_OK;

@@ -537,7 +537,7 @@ sphx_status grid_build(sphx_ctx *ctx, const sphx_particles *in, hipStream_t s, s
     SPHX_TRY(dalloc(&g->node_lo, 3 * off, s));
     SPHX_TRY(dalloc(&g->node_hi, 3 * off, s));
     SPHX_TRY(dalloc(&g->node_r, off, s));
-    SPHX_TRY(dalloc(&g->fsum, 6 * nl, s));
+    SPHX_TRY(dalloc(&g->fsum, 6 * (nl + 128), s));  // + the parts of the sums' reduction
 
     k_leaf_setup<<<unsigned(nl), 64, 0, s>>>(nl, g->leaf_start, g->perm, in->x, in->y, in->z,
                                              in->vx, in->vy, in->vz, in->m, in->u, in->alpha_v,

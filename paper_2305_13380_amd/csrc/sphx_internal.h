@@ -138,7 +138,8 @@ struct sphx_grid {
     double *node_hi;    // 3 * n_nodes
     float *node_r;      // search radius of the node (max over its leaves), from tasks build
 
-    double *fsum;       // 6 * n_leaves FP64 partial sums of the force pass
+    double *fsum;       // 6 * (n_leaves + 128) FP64 partial sums of the force pass, then
+                        // the 128 parts of their reduction
 
     // Per-receiver neighbour lists of the h iteration (sorted order). The
     // receivers of 64-block b (sorted indices 64b .. 64b+63) own entries
