@@ -86,36 +86,66 @@ __global__ __launch_bounds__(64 * NW) void k_force(
     uint8_t *lst = reinterpret_cast<uint8_t *>(lst_all[w]);
     uint8_t *my_list = lst + lane * kListStride;
 
-    const float4 pi = q0[s];
-    const float4 vi = q1[s];  // w = u
-    const float2 ai = qa[s];
-    const float4 gi0 = g0[s];  // h, rho, P, c
-    const float4 gi1 = g1[s];  // f, B, A
-    const float Hi = gamma_k * gi0.x;
-    const float Hi2 = act ? Hi * Hi : -1.0f;
-    const float invHi = fast_rcp(Hi);
-    const float invHi4 = (invHi * invHi) * (invHi * invHi);
-    const float rhoi = gi0.y, Pi = gi0.z, ci = gi0.w;
-    const float fi = gi1.x, Bi = gi1.y, Ai = gi1.z;
-    const float acPi = ai.y * Pi;
-
+    // the box of the receivers, and their largest radius
+    const float4 pown = q0[s];
+    const float Hown = gamma_k * g0[s].x;
     const float inf = __builtin_inff();
-    float3 lo = make_float3(act ? pi.x : inf, act ? pi.y : inf, act ? pi.z : inf);
-    float3 hb = make_float3(act ? pi.x : -inf, act ? pi.y : -inf, act ? pi.z : -inf);
+    float3 lo = make_float3(act ? pown.x : inf, act ? pown.y : inf, act ? pown.z : inf);
+    float3 hb = make_float3(act ? pown.x : -inf, act ? pown.y : -inf, act ? pown.z : -inf);
     lo.x = wave_minf(lo.x);
     lo.y = wave_minf(lo.y);
     lo.z = wave_minf(lo.z);
     hb.x = wave_maxf(hb.x);
     hb.y = wave_maxf(hb.y);
     hb.z = wave_maxf(hb.z);
-    const float R = wave_maxf(act ? Hi : 0.0f);
+    const float R = wave_maxf(act ? Hown : 0.0f);
     const float R2 = R * R;
+
+    // Lane replication, as in the density loop: with n_act receivers, each
+    // gets nrep lanes (the largest power of two with nrep n_act <= 64);
+    // replica j takes the candidates whose running index is j mod nrep, and
+    // the replicas' sums (max for v_sig) are combined by a butterfly at the
+    // end. nrep = 1 is the plain loop, lane = receiver.
+    const uint64_t amask = __ballot(act);
+    const int n_act = __popcll(amask);
+    int nrep = 1;
+    while (2 * nrep * n_act <= 64)
+        nrep *= 2;
+    __shared__ uint8_t rmap_all[NW][64];
+    int src = lane;
+    bool ract = act;
+    if (nrep > 1) {
+        if (act)
+            rmap_all[w][lanes_below(amask)] = uint8_t(lane);
+        wave_sync();
+        const int k = lane / nrep;
+        ract = k < n_act;
+        src = ract ? int(rmap_all[w][k]) : 0;
+    }
+    const int rj = lane & (nrep - 1);  // replica index
+    // this lane's receiver (its own particle when nrep = 1; idle lanes read
+    // the cell's first particle)
+    const int32_t sr = nrep > 1 ? s0 + src : s;
+    const int32_t gr = nrep > 1 ? perm[sr] : gi;
+    const float4 pi = nrep > 1 ? q0[sr] : pown;
+    const float4 vi = q1[sr];  // w = u
+    const float2 ai = qa[sr];
+    const float4 gi0 = g0[sr];  // h, rho, P, c
+    const float4 gi1 = g1[sr];  // f, B, A
+    const float Hi = gamma_k * gi0.x;
+    const float Hi2 = ract ? Hi * Hi : -1.0f;
+    const float invHi = fast_rcp(Hi);
+    const float invHi4 = (invHi * invHi) * (invHi * invHi);
+    const float rhoi = gi0.y, Pi = gi0.z, ci = gi0.w;
+    const float fi = gi1.x, Bi = gi1.y, Ai = gi1.z;
+    const float acPi = ai.y * Pi;
 
     float ax = 0.f, ay = 0.f, az = 0.f, du = 0.f;
     float vsig = 2.0f * ci;
     int32_t nf = 0;
     int nc = 0;
     int myn = 0;  // this lane's list length (its own particle is listed too)
+    int gbase = 0;  // candidates of the earlier buffers (wave-uniform)
 
     // One listed pair; with on = false (past the lane's list, or its own
     // particle) it adds nothing: every accumulation is a select, so the
@@ -175,27 +205,51 @@ __global__ __launch_bounds__(64 * NW) void k_force(
     };
     // The slot is always written; it is kept (the length advanced) only
     // when the pair lies inside max(H_i, H_j).
-    auto accept = [&](int c, const float4 &p) __attribute__((always_inline)) {
+    auto accept = [&](int c, const float4 &p, bool ok) __attribute__((always_inline)) {
         const float dx = pi.x - p.x, dy = pi.y - p.y, dz = pi.z - p.z;
         const float r2 = dx * dx + dy * dy + dz * dz;
         my_list[myn] = uint8_t(c);
-        myn += (act && r2 < fmaxf(Hi2, p.w)) ? 1 : 0;
+        myn += (ok && ract && r2 < fmaxf(Hi2, p.w)) ? 1 : 0;
     };
     auto flush = [&]() __attribute__((always_inline)) {
         wave_sync();
-        int c = 0;
-        for (; c + 4 <= nc; c += 4) {
-            const float4 p0 = cp[c], p1 = cp[c + 1], p2 = cp[c + 2], p3 = cp[c + 3];
-            accept(c, p0);
-            accept(c + 1, p1);
-            accept(c + 2, p2);
-            accept(c + 3, p3);
-            if (__any(myn > kListMax - 4))
-                compute();
+        if (nrep == 1) {
+            int c = 0;
+            for (; c + 4 <= nc; c += 4) {
+                const float4 p0 = cp[c], p1 = cp[c + 1], p2 = cp[c + 2], p3 = cp[c + 3];
+                accept(c, p0, true);
+                accept(c + 1, p1, true);
+                accept(c + 2, p2, true);
+                accept(c + 3, p3, true);
+                if (__any(myn > kListMax - 4))
+                    compute();
+            }
+            for (; c < nc; ++c)
+                accept(c, cp[c], true);
+        } else {
+            // replica rj takes the slots c with gbase + c = rj (mod nrep)
+            const int c0 = (rj - (gbase & (nrep - 1))) & (nrep - 1);
+            const int m_end = (nc + nrep - 1) / nrep;
+            for (int m = 0; m < m_end; m += 4) {
+                int cq[4];
+                bool ok[4];
+                float4 pq[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int c = c0 + (m + q) * nrep;
+                    ok[q] = c < nc;
+                    cq[q] = ok[q] ? c : 0;
+                    pq[q] = cp[cq[q]];
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    accept(cq[q], pq[q], ok[q]);
+                if (__any(myn > kListMax - 4))
+                    compute();
+            }
         }
-        for (; c < nc; ++c)
-            accept(c, cp[c]);
         compute();
+        gbase += nc;
         wave_sync();
         nc = 0;
     };
@@ -277,9 +331,19 @@ __global__ __launch_bounds__(64 * NW) void k_force(
     }
     if (nc > 0)
         flush();
+    // the replicas' partial results, by a butterfly: every replica ends with
+    // the same totals (each addition and max is commutative)
+    for (int o = 1; o < nrep; o <<= 1) {
+        ax += __shfl_xor(ax, o, 64);
+        ay += __shfl_xor(ay, o, 64);
+        az += __shfl_xor(az, o, 64);
+        du += __shfl_xor(du, o, 64);
+        vsig = fmaxf(vsig, __shfl_xor(vsig, o, 64));
+        nf += __shfl_xor(nf, o, 64);
+    }
 
     // the receiver's own particle was listed as a pair at r = 0 and counted
-    float F[kFSums] = {ax, ay, az, du, vsig, float(nf - (w == 0 && act ? 1 : 0))};
+    float F[kFSums] = {ax, ay, az, du, vsig, float(nf - (w == 0 && ract ? 1 : 0))};
     if (NW > 1) {
         __syncthreads();
         // the other waves' partial sums (own array: small tiles leave too
@@ -299,14 +363,14 @@ __global__ __launch_bounds__(64 * NW) void k_force(
         }
     }
     double m0 = 0, m1 = 0, m2 = 0, e = 0, sa_ = 0, sd = 0;
-    if (act) {
-        o_ax[gi] = F[0];
-        o_ay[gi] = F[1];
-        o_az[gi] = F[2];
-        o_du[gi] = F[3];
-        o_vsig[gi] = F[4];
+    if (ract && rj == 0) {
+        o_ax[gr] = F[0];
+        o_ay[gr] = F[1];
+        o_az[gr] = F[2];
+        o_du[gr] = F[3];
+        o_vsig[gr] = F[4];
         if (o_nf)
-            o_nf[gi] = int32_t(F[5]);
+            o_nf[gr] = int32_t(F[5]);
         const double mi = pi.w;
         const double dax = F[0], day = F[1], daz = F[2], ddu = F[3];
         m0 = mi * dax;
