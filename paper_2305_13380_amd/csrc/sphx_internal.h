@@ -212,12 +212,12 @@ void tasks_free(sphx_tasks *t);
 size_t tasks_bytes(int64_t n);
 
 // density.hip
-// Cell-pair density pass over the receivers that need one; with use_lists,
-// only over those whose H exceeds their list radius.
 // Count the receivers that outgrew their leaf's task radius into *stale
 // (added to; a density pass given skip = stale then returns at once).
 sphx_status stale_count_launch(const sphx_ctx *ctx, const sphx_grid *g, const sphx_tasks *t,
                                int32_t *stale, hipStream_t s);
+// Cell-pair density pass over the receivers that need one; with use_lists,
+// only over those whose H exceeds their list radius.
 sphx_status density_launch(const sphx_ctx *ctx, const sphx_grid *g, const sphx_tasks *t,
                            const sphx_particles *in, const sphx_density_out *out,
                            int32_t *counters, bool use_lists, hipStream_t s,
