@@ -187,8 +187,8 @@ struct sphx_tasks {
     size_t sort_tmp_bytes;
     int64_t order_cap;
     // Rebuilds in one tree walk: the walk writes each leaf's tasks into its
-    // slot of the `soff` layout (capacity count + count/4 + 8 from the last
-    // build) while counting them, and they are compacted into `task`; only
+    // slot of the `soff` layout (capacity 4 count + 8 from the last build)
+    // while counting them, and they are compacted into `task`; only
     // the leaves over their capacity are walked a second time.
     sphx::Task *slack;  // slack_cap
     int32_t *soff;      // n_leaves + 1
