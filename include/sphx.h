@@ -259,10 +259,12 @@ sphx_status sphx_step(sphx_ctx *ctx, sphx_grid *grid, sphx_tasks **tasks, sphx_p
                       double *d_sums6, void *stream, sphx_step_info *info);
 
 /* Autotuner: times each density-loop shape (tile x waves, unbalanced rounds;
- * density_balance is returned as given) on whole steps (as sphx_step, pass by
- * pass, from the particles' current h, iterating on a device copy of h), and
- * each force-loop shape on force passes at the converged state; the shortest
- * of reps timed runs (after one untimed run) counts, HIP events on `stream`.
+ * density_balance is returned as given) over whole steps (as sphx_step, pass
+ * by pass, from the particles' current h, iterating on a device copy of h;
+ * the time of the step's density launches, HIP events around each), and each
+ * force-loop shape on force passes at the converged state; the shortest of
+ * reps timed runs (after one untimed run) counts, events on `stream`. The
+ * context's kernel statistics (sphx_profile_*) are left as they were.
  * Returns in *tuned the context's parameters with the fastest shapes. The
  * output arrays are overwritten; h is not changed; the task list is left as
  * a build at the current h leaves it. Allocates n floats for the copy of h.

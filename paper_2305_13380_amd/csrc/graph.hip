@@ -4,9 +4,10 @@
 // replayed on the caller's stream for as long as the grid, task list, arrays
 // and loop shapes stay the same. Passes after every particle has converged
 // find no receiver and do nothing, so the graph can hold a fixed number of
-// them; a log kernel after each pass keeps its counters, and the force
-// kernels are gated on the log (no pass met a stale task list, and the last
-// pass left no particle unconverged). One readback of the log after the
+// them; a log kernel after each pass keeps its counters and stops the later
+// passes when the task list needs a rebuild (the graph cannot rebuild it),
+// and the force kernels are gated on the log (no pass stopped the graph, and
+// the last pass left no particle unconverged). One readback of the log after the
 // replay replaces the readback after every pass; if the iteration is not
 // finished inside the graph the caller continues it pass by pass from the
 // state the graph left. Counters and flags are cleared by kernels: the graph
@@ -26,10 +27,13 @@ __global__ void k_fill_i32(int32_t *__restrict__ p, int n, int32_t v)
         p[i] = v;
 }
 
-// Pass p's counters into the log, and the flags: gate[1] remembers a stale
-// pass; gate[0] = 0 opens the force pass (no pass was stale and pass p left no
-// particle unconverged; a final pass finalises every particle); gate[2] = 1
-// makes the remaining passes return at once (a stale pass, or nothing left).
+// Pass p's counters into the log, and the flags: gate[1] remembers a pass
+// that must not be followed inside the graph (it met a stale task list, or it
+// left an h beyond its task radius, so the next pass would: the caller
+// rebuilds the list and goes on pass by pass); gate[0] = 0 opens the force
+// pass (no such pass, and pass p left no particle unconverged; a final pass
+// finalises every particle); gate[2] = 1 makes the remaining passes return at
+// once (such a pass, or nothing left).
 __global__ void k_log_pass(const int32_t *__restrict__ c, int32_t *__restrict__ log, int p,
                            int final_pass, int32_t *__restrict__ gate)
 {
@@ -37,10 +41,11 @@ __global__ void k_log_pass(const int32_t *__restrict__ c, int32_t *__restrict__ 
     if (i < kStepCounters)
         log[p * kStepCounters + i] = c[i];
     if (i == 0) {
-        const int32_t stale = gate[1] | (c[3] > 0 ? 1 : 0);
-        gate[1] = stale;
-        gate[0] = stale | ((c[0] > 0 && !final_pass) ? 1 : 0);
-        gate[2] = stale | (c[0] == 0 ? 1 : 0);
+        const int32_t halt = gate[1] | (c[3] > 0 ? 1 : 0) |
+                             ((c[1] > 0 && c[0] > 0 && !final_pass) ? 1 : 0);
+        gate[1] = halt;
+        gate[0] = halt | ((c[0] > 0 && !final_pass) ? 1 : 0);
+        gate[2] = halt | (c[0] == 0 ? 1 : 0);
     }
 }
 
@@ -182,8 +187,10 @@ sphx_status step_graph_run(sphx_ctx *ctx, sphx_grid *grid, sphx_tasks *t, const 
             *done = true;
             break;
         }
-        if (p + 1 == passes)
-            *rebuild = c[1] > 0;
+        if (c[1] > 0) {
+            *rebuild = true;  // the later passes of the graph returned at once
+            break;
+        }
     }
     return SPHX_OK;
 }
