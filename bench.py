@@ -169,22 +169,32 @@ def measured_traffic(config, kernel):
     (profiles/traffic_<config>.json: FETCH_SIZE and WRITE_SIZE scaled by a
     plain copy of known size), or None when the summary is missing or the
     kernel's sources changed since the counters were taken."""
-    import hashlib
     path = os.path.join(ROOT, "profiles", "traffic_%s.json" % config)
     if not os.path.exists(path):
         return None
     rec = json.load(open(path)).get(kernel)
     if not rec:
         return None
+    if kernel_source_hash(kernel) != rec["source_hash"]:
+        return None
+    return rec["mean_bytes_per_launch"]
+
+
+def kernel_source_hash(kernel):
+    """Hash of the sources a neighbour-loop kernel is compiled from, with
+    comments and blank space removed (a comment cannot change the kernel)."""
+    import hashlib
+    import re
     base = os.path.join(ROOT, "paper_2305_13380_amd", "csrc")
     srcs = {"k_density": ["density.hip", "pairs.h", "sphx_internal.h"],
             "k_force": ["force.hip", "pairs.h", "sphx_internal.h"]}[kernel]
     hsh = hashlib.sha256()
     for f in srcs:
-        hsh.update(open(os.path.join(base, f), "rb").read())
-    if hsh.hexdigest()[:16] != rec["source_hash"]:
-        return None
-    return rec["mean_bytes_per_launch"]
+        text = open(os.path.join(base, f)).read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        hsh.update(" ".join(text.split()).encode())
+    return hsh.hexdigest()[:16]
 
 
 def main():

@@ -450,7 +450,9 @@ void tasks_free(sphx_tasks *t)
     delete t;
 }
 
-// Launch order of the per-leaf loops (see sphx_tasks::order).
+// Launch order of the per-leaf loops (see sphx_tasks::order). The sort keys
+// use 35 bits: the XCD range (0..7) above the 32-bit inverted work.
+constexpr unsigned kOrderKeyBits = 35;
 static sphx_status leaf_order(sphx_tasks *t, int64_t nl, hipStream_t s)
 {
     const int64_t nbp = pad8(nl);
@@ -466,7 +468,7 @@ static sphx_status leaf_order(sphx_tasks *t, int64_t nl, hipStream_t s)
         size_t tmp = 0;
         SPHX_HIP(rocprim::radix_sort_pairs(nullptr, tmp, (uint64_t *)nullptr, (uint64_t *)nullptr,
                                            (int32_t *)nullptr, (int32_t *)nullptr, size_t(nbp), 0,
-                                           64, s));
+                                           kOrderKeyBits, s));
         if (dmalloc((void **)&t->order, size_t(nbp) * sizeof(int32_t), s) != hipSuccess ||
             dmalloc((void **)&t->okey, size_t(nbp) * sizeof(uint64_t), s) != hipSuccess ||
             dmalloc((void **)&t->okey_out, size_t(nbp) * sizeof(uint64_t), s) != hipSuccess ||
@@ -482,7 +484,7 @@ static sphx_status leaf_order(sphx_tasks *t, int64_t nl, hipStream_t s)
     SPHX_HIP(hipGetLastError());
     size_t tmp = t->sort_tmp_bytes;
     SPHX_HIP(rocprim::radix_sort_pairs(t->sort_tmp, tmp, t->okey, t->okey_out, t->oval, t->order,
-                                       size_t(nbp), 0, 64, s));
+                                       size_t(nbp), 0, kOrderKeyBits, s));
     return SPHX_OK;
 }
 
