@@ -52,51 +52,57 @@ def log(*a):
 
 def cpu_baseline(ps, params_cls, n_recv, seed=0):
     """The oracle (FP64, C + OpenMP, k-d tree candidates) timed on the host
-    for a bounded random sample of receivers: one density pass over the
-    receivers and every particle in their force neighbourhoods, the ghost, and
-    one force pass over the receivers. Candidate generation is excluded, as
-    the grid and task builds are on the GPU side."""
+    over the work of a GPU step, for a bounded random sample of receivers: the
+    h iteration from the initial h (every density pass, with the oracle's
+    candidate search in each) for the receivers and every particle in their
+    force neighbourhoods at the initial h, the ghost, and the force pass over
+    the receivers. Interactions are counted as on the GPU: the density
+    interactions at the final h once, plus the force interactions. Timed on
+    all host threads, and on one thread for a sample 8 times smaller. The
+    oracle's candidate search (scipy k-d tree queries, one thread) is part of
+    every pass and takes most of the time.
+    (Neighbours outside the sampled neighbourhoods carry no ghost state: their
+    force terms are NaN, which costs the same time.)"""
+    import ctypes
+
     import numpy as np
     import oracle
     P = params_cls()
-    rng = np.random.default_rng(seed)
-    recv = np.sort(rng.choice(ps.n, size=min(n_recv, ps.n), replace=False))
-    h = np.asarray(ps.h, np.float64)
-    need = oracle.force_needed(ps, h, P, recv, mode="tree")
-    doff, didx = oracle.density_candidates(ps, h, P, need)
-    foff, fidx = oracle.force_candidates(ps, h, P, recv)
-    L = oracle.lib()
-    f64 = lambda a: np.ascontiguousarray(np.asarray(a, np.float64))
-    x, y, z = f64(ps.x), f64(ps.y), f64(ps.z)
-    vx, vy, vz, m, u = f64(ps.vx), f64(ps.vy), f64(ps.vz), f64(ps.m), f64(ps.u)
-    av, ac, box = f64(ps.alpha_v), f64(ps.alpha_c), f64(ps.box)
-    nd = len(need)
-    d = {k: np.zeros(nd) for k in ("rho", "rho_dh", "n", "n_dh", "div", "cx", "cy", "cz")}
-    nngb = np.zeros(nd, np.int64)
-    g = {k: np.zeros(nd) for k in ("f", "P", "c", "B", "A", "dv", "cv")}
-    full = {k: np.full(ps.n, np.nan) for k in ("rho", "P", "c", "f", "B")}
-    fo = {k: np.zeros(len(recv)) for k in ("ax", "ay", "az", "du", "vs")}
-    nf = np.zeros(len(recv), np.int64)
-    t0 = time.perf_counter()
-    tot_d = L.or_density(ps.n, x, y, z, vx, vy, vz, m, h, box, 1, P.gamma_k, nd,
-                         np.ascontiguousarray(need, np.int64), doff, didx, d["rho"], d["rho_dh"],
-                         d["n"], d["n_dh"], d["div"], d["cx"], d["cy"], d["cz"], nngb)
-    L.or_ghost(nd, d["rho"], d["rho_dh"], d["div"], d["cx"], d["cy"], d["cz"], u[need], h[need],
-               P.gamma_gas, P.eps_b, g["f"], g["P"], g["c"], g["B"], g["A"], g["dv"], g["cv"])
-    full["rho"][need] = d["rho"]
-    for k in ("P", "c", "f", "B"):
-        full[k][need] = g[k]
-    tot_f = L.or_force(ps.n, x, y, z, vx, vy, vz, m, u, h, full["rho"], full["P"], full["c"],
-                       full["f"], full["B"], av, ac, box, 1, P.gamma_k, P.beta_v, len(recv),
-                       np.ascontiguousarray(recv, np.int64), foff, fidx, fo["ax"], fo["ay"],
-                       fo["az"], fo["du"], fo["vs"], nf)
-    dt = time.perf_counter() - t0
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": (tot_d + tot_f) / dt, "unit": "interactions/s", "cores": cores,
-            "kind": "oracle",
-            "sample": "%d random receivers: density for them and their %d force neighbours "
-                      "(%d interactions), force for the receivers (%d interactions); %.1f s" % (
-                          len(recv), nd - len(recv), tot_d, tot_f, dt)}
+    u_all = np.asarray(ps.u, np.float64)
+    h0 = np.asarray(ps.h, np.float64)
+
+    def run(n):
+        rng = np.random.default_rng(seed)
+        recv = np.sort(rng.choice(ps.n, size=min(n, ps.n), replace=False))
+        t0 = time.perf_counter()
+        need = oracle.force_needed(ps, h0, P, recv, mode="tree")
+        h, dens, conv, iters, passes = oracle.solve_h(ps, P, recv=need, mode="tree")
+        g = oracle.ghost(dens, u_all[need], h, P)
+        h_all = h0.copy()
+        h_all[need] = h
+        full = {k: np.full(ps.n, np.nan) for k in ("P", "c", "f", "balsara")}
+        for k in full:
+            full[k][need] = g[k]
+        rho = np.full(ps.n, np.nan)
+        rho[need] = dens["rho"]
+        fo = oracle.force(ps, h_all, full, rho, P, recv=recv, mode="tree")
+        dt = time.perf_counter() - t0
+        n_int = int(dens["nngb"].sum()) + int(fo["total"])
+        return n_int / dt, ("%d random receivers and their %d force neighbours: %d h-iteration "
+                            "passes (candidate search included), ghost, force for the "
+                            "receivers; %d interactions in %.1f s" % (
+                                len(recv), len(need) - len(recv), passes, n_int, dt))
+
+    gomp = ctypes.CDLL("libgomp.so.1")  # the OpenMP runtime the oracle runs on
+    threads = int(gomp.omp_get_max_threads())
+    rate, sample = run(n_recv)
+    gomp.omp_set_num_threads(1)
+    try:
+        rate1, sample1 = run(max(1, n_recv // 8))
+    finally:
+        gomp.omp_set_num_threads(threads)
+    return {"value": rate, "unit": "interactions/s", "cores": threads, "kind": "oracle",
+            "sample": sample, "value_1core": rate1, "sample_1core": sample1}
 
 
 def serving_bench(slots, n_req, seed=4):
@@ -180,6 +186,20 @@ def measured_traffic(config, kernel):
     return rec["mean_bytes_per_launch"]
 
 
+def measured_counter_rate(config, kernel):
+    """FP32 VALU rate of `kernel` counted by the hardware (issued ADD, MUL,
+    2 x FMA and TRANS FP32 lane operations per second) from the committed
+    counter summary (profiles/valu_<config>.json), or None when it is missing
+    or the kernel's sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "valu_%s.json" % config)
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path)).get(kernel)
+    if not rec or kernel_source_hash(kernel) != rec["source_hash"]:
+        return None
+    return rec["counter_tflops"]
+
+
 def kernel_source_hash(kernel):
     """Hash of the sources a neighbour-loop kernel is compiled from, with
     comments and blank space removed (a comment cannot change the kernel)."""
@@ -203,7 +223,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", default="clustered", choices=sorted(CONFIGS))
-    ap.add_argument("--cpu-receivers", type=int, default=4096)
+    ap.add_argument("--cpu-receivers", type=int, default=2048)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--graph", type=int, default=-1, metavar="K",
                     help="captured passes per step (HIP graph); 0: pass by pass; "
@@ -419,6 +439,7 @@ def main():
                      "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS,
                      "traffic": measured_traffic(args.config, kern),
+                     "counter_tflops": measured_counter_rate(args.config, kern),
                      "flop_per_launch": per_launch},
     }
     del grid, tasks, out
