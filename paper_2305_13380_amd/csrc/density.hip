@@ -26,27 +26,34 @@ struct DensOut {
 };
 
 // Contributions of one directed pair; p and v are the source's position (in
-// the receiver's frame) and mass, and its velocity. u = r / H. With on =
-// false the pair adds nothing (its inputs must be finite): the loops evaluate
-// several list entries at once without branching.
+// the receiver's frame) and mass, and its velocity. u = r / H, clamped at 1
+// (a pair at or beyond the support adds nothing, also where rounding puts an
+// accepted edge pair there). MASK: with on = false the pair adds nothing
+// (its inputs must be finite) and on counts it; without MASK every pair is
+// evaluated and counted by the caller: list entries past a lane's length
+// point to a dummy source beyond every support (mass 0, velocity 0), which
+// adds exactly zero. Either way the loops evaluate several list entries at
+// once without branching.
+template <bool MASK>
 __device__ __forceinline__ void dens_pair(float (&S)[kSums], const float4 &pi, const float4 &vi,
                                           float invH, const float4 &p, const float4 &v, bool on)
 {
     const float dx = pi.x - p.x, dy = pi.y - p.y, dz = pi.z - p.z;
     const float r2 = dx * dx + dy * dy + dz * dz;
-    const float u = fast_sqrt(r2) * invH;
+    const float u = fminf(fast_sqrt(r2) * invH, 1.0f);
     const float t1u = 1.0f - u;
     const float t2 = t1u * t1u;
     const float t3 = t2 * t1u;
-    const float wk = on ? t2 * t2 * (1.0f + 4.0f * u) : 0.0f;
-    const float ud = on ? u * u * t3 : 0.0f;
+    const float wk = (!MASK || on) ? t2 * t2 * (1.0f + 4.0f * u) : 0.0f;
+    const float ud = (!MASK || on) ? u * u * t3 : 0.0f;
     S[0] += wk;
     S[1] += p.w * wk;
     S[2] += ud;
     S[3] += p.w * ud;
-    S[8] += on ? 1.0f : 0.0f;
+    if (MASK)
+        S[8] += on ? 1.0f : 0.0f;
     const float dvx = v.x - vi.x, dvy = v.y - vi.y, dvz = v.z - vi.z;
-    const float mt3 = on ? p.w * t3 : 0.0f;
+    const float mt3 = (!MASK || on) ? p.w * t3 : 0.0f;
     S[4] += mt3 * (dvx * dx + dvy * dy + dvz * dz);
     S[5] += mt3 * (dy * dvz - dz * dvy);
     S[6] += mt3 * (dz * dvx - dx * dvz);
@@ -102,7 +109,7 @@ __global__ __launch_bounds__(64 * NW) void k_density(
     const int32_t *__restrict__ perm, const float4 *__restrict__ q0,
     const float4 *__restrict__ q1, const uint8_t *__restrict__ need, const float *__restrict__ hs,
     const float *__restrict__ radius, const int32_t *__restrict__ toff,
-    const Task *__restrict__ task, const float4 *__restrict__ ext, float gamma_k,
+    const Task *__restrict__ task, const float4 *__restrict__ ext, float gamma_k, float far,
     const float *__restrict__ lrad, DensOut o, int32_t *__restrict__ counters,
     const int32_t *__restrict__ skip)
 {
@@ -124,8 +131,10 @@ __global__ __launch_bounds__(64 * NW) void k_density(
     if (!__any(act))
         return;  // the same for every wave of the block
 
-    __shared__ float4 cp_all[NW][CAP];  // candidate x, y, z (receiver cell frame), m
-    __shared__ float4 cv_all[NW][CAP];  // candidate vx, vy, vz
+    // candidates x, y, z (receiver cell frame), m and vx, vy, vz; slot CAP is
+    // the dummy source that list entries past a lane's length point to
+    __shared__ float4 cp_all[NW][CAP + 1];
+    __shared__ float4 cv_all[NW][CAP + 1];
     __shared__ uint32_t lst_all[NW][kListStride * 16];
     // BAL only: the receivers' positions and (velocity, 1/H), each receiver's
     // first chunk of the round, and the chunks' partial sums ([sum][slot]).
@@ -215,23 +224,26 @@ __global__ __launch_bounds__(64 * NW) void k_density(
     }
 
     // Four list entries at a time, without branches: entries past a lane's
-    // list length read slot 0 (a candidate of the current buffer, so finite
-    // data) and add nothing.
+    // list length read the dummy slot (beyond every support, mass 0: adds
+    // exactly nothing); every listed entry is a neighbour, counted at once.
+    if (lane == 0) {
+        cp[CAP] = make_float4(far, far, far, 0.0f);
+        cv[CAP] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    }
     auto compute = [&]() __attribute__((always_inline)) {
+        S[8] += float(myn);
         for (int k = 0; __any(k < myn); k += 4) {
             const uint32_t four = *reinterpret_cast<const uint32_t *>(my_list + k);
             float4 p[4], v[4];
-            bool on[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                on[q] = k + q < myn;
-                const int c = on[q] ? int((four >> (8 * q)) & 0xffu) : 0;
+                const int c = k + q < myn ? int((four >> (8 * q)) & 0xffu) : CAP;
                 p[q] = cp[c];
                 v[q] = cv[c];
             }
 #pragma unroll
             for (int q = 0; q < 4; ++q)
-                dens_pair(S, pr, vr, invHr, p[q], v[q], on[q]);
+                dens_pair<false>(S, pr, vr, invHr, p[q], v[q], true);
         }
         myn = 0;
     };
@@ -298,7 +310,7 @@ __global__ __launch_bounds__(64 * NW) void k_density(
                 }
 #pragma unroll
                 for (int q = 0; q < 4; ++q)
-                    dens_pair(Tc, P, V, V.w, p[q], v[q], on[q]);
+                    dens_pair<true>(Tc, P, V, V.w, p[q], v[q], on[q]);
             }
 #pragma unroll
             for (int k = 0; k < kSums; ++k)
@@ -521,7 +533,7 @@ __global__ __launch_bounds__(256) void k_dens_list(
             p[q].y += T[q].y;
             p[q].z += T[q].z;
             const float r2 = dist2(pi.x - p[q].x, pi.y - p[q].y, pi.z - p[q].z);
-            dens_pair(S, pi, vi, invH, p[q], v[q], k + q < len && r2 < H2);
+            dens_pair<true>(S, pi, vi, invH, p[q], v[q], k + q < len && r2 < H2);
         }
     }
     if (!act)
@@ -579,12 +591,15 @@ sphx_status density_launch(const sphx_ctx *ctx, const sphx_grid *g, const sphx_t
     const bool bal = ctx->p.density_balance == 1;
     const float *lr = use_lists ? g->lrad : nullptr;
     const DensOut dout = dens_out(g, o);
+    // the dummy source: 4 box lengths out, more than 3 box lengths from any
+    // receiver (cell-relative coordinates), while every H is below a third
+    const float far = float(4.0 * std::max(ctx->p.box[0], std::max(ctx->p.box[1], ctx->p.box[2])));
     SPHX_HIP(ctx->prof->begin(0, s));
 #define SPHX_DENSITY_LAUNCH(CAP_, NW_, BAL_)                                                   \
     k_density<CAP_, NW_, BAL_><<<unsigned(nbp), 64 * NW_, 0, s>>>(                             \
         g->n_leaves, nbp, t->order, g->leaf_start, g->perm, g->q0, g->q1, g->need, g->hs,      \
-        t->radius, t->off, t->task, g->leaf_ext, float(ctx->p.gamma_k), lr, dout, counters,   \
-        skip)
+        t->radius, t->off, t->task, g->leaf_ext, float(ctx->p.gamma_k), far, lr, dout,        \
+        counters, skip)
     if (bal) {
         if (tile == 64)
             SPHX_DENSITY_LAUNCH(64, 1, true);
