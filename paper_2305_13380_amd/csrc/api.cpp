@@ -87,6 +87,17 @@ static sphx_status check_handles(const sphx_ctx *ctx, const sphx_grid *g, const 
     return SPHX_OK;
 }
 
+hipError_t wait_stream(sphx_ctx *ctx, hipStream_t s)
+{
+    hipError_t e = hipEventRecord(ctx->ev_wait, s);
+    if (e != hipSuccess)
+        return e;
+    while ((e = hipEventQuery(ctx->ev_wait)) == hipErrorNotReady) {
+    }
+    (void)hipGetLastError();  // the runtime keeps "not ready" as the last error
+    return e;
+}
+
 }  // namespace sphx
 
 using namespace sphx;
@@ -168,8 +179,14 @@ sphx_status sphx_ctx_create(const sphx_params *p, int hip_device, sphx_ctx **out
     double auto_max = lmin / (3.0 * p->gamma_k) * (1.0 - 1e-6);
     c->h_max = p->h_max > 0.0 ? fmin(p->h_max, auto_max) : auto_max;
     if (hipMalloc(&c->d_counters, kStepCounterBytes) != hipSuccess ||
-        hipMalloc(&c->d_sums, 8 * sizeof(double)) != hipSuccess) {
+        hipMalloc(&c->d_sums, 8 * sizeof(double)) != hipSuccess ||
+        hipHostMalloc((void **)&c->h_pinned, kPinnedBytes, hipHostMallocDefault) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_wait, hipEventDisableTiming) != hipSuccess) {
         (void)hipFree(c->d_counters);
+        (void)hipFree(c->d_sums);
+        if (c->h_pinned)
+            (void)hipHostFree(c->h_pinned);
+        (void)hipGetLastError();
         delete c->prof;
         delete c;
         set_error("sphx_ctx_create: out of device memory");
@@ -186,6 +203,8 @@ void sphx_ctx_destroy(sphx_ctx *ctx)
     step_graph_free(ctx->graph);
     (void)hipFree(ctx->d_counters);
     (void)hipFree(ctx->d_sums);
+    (void)hipHostFree(ctx->h_pinned);
+    (void)hipEventDestroy(ctx->ev_wait);
     for (auto &v : ctx->prof->pool)
         for (auto &r : v) {
             (void)hipEventDestroy(r.a);
@@ -315,8 +334,8 @@ static sphx_status step_run(sphx_ctx *ctx, sphx_grid *grid, sphx_tasks **tasks,
     memset(&local, 0, sizeof(local));
     if (!*tasks)
         SPHX_TRY(tasks_build(ctx, grid, in, s, tasks));
-    alignas(8) unsigned char h_buf[kStepCounterBytes];
-    memset(h_buf, 0, sizeof(h_buf));
+    unsigned char *h_buf = ctx->h_pinned;  // kStepCounterBytes of it
+    memset(h_buf, 0, kStepCounterBytes);
     int32_t h_counters[kStepCounters] = {0, 0, 0, 0, 0, 0, 0, 0};
     int32_t *dc = ctx->d_counters;
     unsigned long long *d_units =
@@ -378,7 +397,7 @@ static sphx_status step_run(sphx_ctx *ctx, sphx_grid *grid, sphx_tasks **tasks,
         SPHX_TRY(ghost_launch(ctx, grid, *tasks, in, dens, gst, dc, final_pass, lists, d_units,
                               s, nullptr, true));
         SPHX_HIP(hipMemcpyAsync(h_buf, dc, kStepCounterBytes, hipMemcpyDeviceToHost, s));
-        SPHX_HIP(hipStreamSynchronize(s));
+        SPHX_HIP(wait_stream(ctx, s));
         memcpy(h_counters, h_buf, sizeof(h_counters));
         if (h_counters[3] > 0) {
             // The pass ran on a stale task list and the ghost skipped it.

@@ -89,6 +89,7 @@ struct Profiler {
 
 namespace sphx {
 struct StepGraph;
+constexpr size_t kPinnedBytes = 256;
 }
 struct sphx_ctx {
     sphx_params p;
@@ -98,6 +99,11 @@ struct sphx_ctx {
     int32_t *d_counters;  // scratch counters used by sphx_step
     double *d_sums;       // scratch FP64 sums used by sphx_step when the caller passes none
     sphx::StepGraph *graph = nullptr;  // captured step (graph_passes > 0)
+    // Readbacks inside a step (pass counters, task totals) land in pinned
+    // host memory and are waited for by polling an event: a blocking stream
+    // synchronisation left the device idle ~40 us per readback.
+    unsigned char *h_pinned = nullptr;  // kPinnedBytes
+    hipEvent_t ev_wait = nullptr;
 };
 
 struct sphx_grid {
@@ -197,6 +203,10 @@ struct sphx_tasks {
 };
 
 namespace sphx {
+
+// Waits, by polling an event recorded on s, until the work queued on s so far
+// (a readback into ctx->h_pinned) has finished.
+hipError_t wait_stream(sphx_ctx *ctx, hipStream_t s);
 
 // grid.hip
 sphx_status grid_build(sphx_ctx *ctx, const sphx_particles *in, hipStream_t s, sphx_grid **out);

@@ -599,8 +599,10 @@ sphx_status tasks_build(sphx_ctx *ctx, sphx_grid *g, const sphx_particles *in, h
     SPHX_HIP(hipGetLastError());
     SPHX_HIP(rocprim::exclusive_scan(t->scan_tmp, tmp, t->count, t->off, 0, size_t(nl + 1),
                                      rocprim::plus<int32_t>(), s));
-    SPHX_HIP(hipMemcpyAsync(&total, t->off + nl, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    SPHX_HIP(hipStreamSynchronize(s));
+    int32_t *h_total = reinterpret_cast<int32_t *>(ctx->h_pinned + kPinnedBytes - 64);
+    SPHX_HIP(hipMemcpyAsync(h_total, t->off + nl, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    SPHX_HIP(wait_stream(ctx, s));
+    total = *h_total;
     if (total < 0) {
         set_error("sphx_tasks_build: task count overflow");
         return SPHX_E_INVALID;
