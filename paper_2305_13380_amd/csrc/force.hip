@@ -42,6 +42,16 @@ __device__ __forceinline__ double wave_sum(double v)
 constexpr int kFSums = 6;  // ax, ay, az, du, vsig, count
 
 // CAP >= 64: a task's kept sources (up to 64) always fit after a flush.
+// Inside a step the ghost leaves its results in sorted order only, and the
+// force kernel writes them to the caller's arrays for its receivers (every
+// particle the step finalised): h, f, P, c, B, A from the force state, div,
+// curl and the converged flag from g2. h == null: nothing to write.
+struct StepOut {
+    float *h, *f, *P, *c, *B, *A, *div, *curl;
+    uint8_t *conv;
+    const float4 *g2;
+};
+
 template <int CAP, int NW>
 __global__ __launch_bounds__(64 * NW) void k_force(
     int64_t n_leaves, int64_t nb_padded, const int32_t *__restrict__ order,
@@ -53,7 +63,7 @@ __global__ __launch_bounds__(64 * NW) void k_force(
     const float4 *__restrict__ ext, const float *__restrict__ hmax, float gamma_k, float beta,
     float *__restrict__ o_ax, float *__restrict__ o_ay, float *__restrict__ o_az,
     float *__restrict__ o_du, float *__restrict__ o_vsig, int32_t *__restrict__ o_nf,
-    double *__restrict__ fsum, const int32_t *__restrict__ gate)
+    double *__restrict__ fsum, const int32_t *__restrict__ gate, StepOut so)
 {
     if (gate && *gate)
         return;  // a captured step whose iteration is not finished
@@ -371,6 +381,18 @@ __global__ __launch_bounds__(64 * NW) void k_force(
         o_vsig[gr] = F[4];
         if (o_nf)
             o_nf[gr] = int32_t(F[5]);
+        if (so.h) {
+            const float4 e = so.g2[sr];  // div, curl, converged
+            so.h[gr] = gi0.x;
+            so.f[gr] = gi1.x;
+            so.P[gr] = gi0.z;
+            so.c[gr] = gi0.w;
+            so.B[gr] = gi1.y;
+            so.A[gr] = gi1.z;
+            so.div[gr] = e.x;
+            so.curl[gr] = e.y;
+            so.conv[gr] = e.z != 0.0f ? 1 : 0;
+        }
         const double mi = pi.w;
         const double dax = F[0], day = F[1], daz = F[2], ddu = F[3];
         m0 = mi * dax;
@@ -494,6 +516,11 @@ sphx_status force_launch(const sphx_ctx *ctx, const sphx_grid *g, const sphx_tas
     k_leaf_hmax<<<unsigned(g->n_leaves), 64, 0, s>>>(g->n_leaves, g->leaf_start, g->g0,
                                                       float(ctx->p.gamma_k), g->leaf_hmax, gate);
     SPHX_HIP(hipGetLastError());
+    const StepOut so = state_ready ? StepOut{in->h,         gs->f, gs->P,      gs->c,
+                                             gs->balsara,   gs->A, gs->div_v,  gs->curl_v,
+                                             gs->converged, g->g2}
+                                   : StepOut{nullptr, nullptr, nullptr, nullptr, nullptr,
+                                             nullptr, nullptr, nullptr, nullptr, nullptr};
     const int64_t nbp = pad8(g->n_leaves);
     SPHX_HIP(ctx->prof->begin(1, s));
     const int tile = ctx->p.force_tile ? ctx->p.force_tile : 64;
@@ -503,7 +530,7 @@ sphx_status force_launch(const sphx_ctx *ctx, const sphx_grid *g, const sphx_tas
         g->n_leaves, nbp, t->order, g->leaf_start, g->perm, g->q0, g->q1, g->qa, g->g0, g->g1, \
         in->active, t->off, t->task, g->leaf_ext, g->leaf_hmax, float(ctx->p.gamma_k),         \
         float(ctx->p.beta_v), o->ax,                                                           \
-        o->ay, o->az, o->du_dt, o->v_sig, o->nforce, g->fsum, gate)
+        o->ay, o->az, o->du_dt, o->v_sig, o->nforce, g->fsum, gate, so)
     if (waves == 1) {
         if (tile == 64)
             SPHX_FORCE_LAUNCH(64, 1);

@@ -23,7 +23,7 @@ __global__ __launch_bounds__(kGhostThreads) void k_ghost(int64_t n, const int32_
                         const float4 *__restrict__ d0, const float4 *__restrict__ d1, float inv_eta3,
                         float h_tol, float h_max, float gamma_k, float gamma_gas, float eps_b,
                         int final_pass, int step_mode, float4 *__restrict__ g0,
-                        float4 *__restrict__ g1, const int32_t *__restrict__ nngb,
+                        float4 *__restrict__ g1, float4 *__restrict__ g2, const int32_t *__restrict__ nngb,
                         unsigned long long *__restrict__ units, float *__restrict__ o_f,
                         float *__restrict__ o_P,
                         float *__restrict__ o_c, float *__restrict__ o_B,
@@ -91,7 +91,6 @@ __global__ __launch_bounds__(kGhostThreads) void k_ghost(int64_t n, const int32_
         } else {
             // Converged, or out of passes: finalise at the h the sums belong to.
             need[s] = 0;
-            o_conv[i] = conv ? 1 : 0;
             n_clamped += hh >= h_max ? 1 : 0;
             const float4 b = d1[s];  // div_sum, curl_x, curl_y, curl_z
             const float rho = a.z;
@@ -105,19 +104,23 @@ __global__ __launch_bounds__(kGhostThreads) void k_ghost(int64_t n, const int32_
             const float ad = fabsf(div);
             const float B = ad / (ad + curl + eps_b * c / hh);
             const float A = f * P * irho * irho;
-            o_f[i] = f;
-            o_P[i] = P;
-            o_c[i] = c;
-            o_B[i] = B;
-            o_A[i] = A;
-            o_div[i] = div;
-            o_curl[i] = curl;
             if (step_mode) {
-                h[i] = hh;
-                // the force pass's source state, in sorted order (the same
-                // values its gather would read from the outputs)
+                // Sorted state only: the force pass's source state (the same
+                // values its gather would read from the outputs) and the
+                // rest; the force kernel, which every finalised particle of a
+                // step receives in, writes the caller's h and outputs.
                 g0[s] = make_float4(hh, rho, P, c);
                 g1[s] = make_float4(f, B, A, 0.0f);
+                g2[s] = make_float4(div, curl, conv ? 1.0f : 0.0f, 0.0f);
+            } else {
+                o_conv[i] = conv ? 1 : 0;
+                o_f[i] = f;
+                o_P[i] = P;
+                o_c[i] = c;
+                o_B[i] = B;
+                o_A[i] = A;
+                o_div[i] = div;
+                o_curl[i] = curl;
             }
         }
     }
@@ -172,7 +175,7 @@ sphx_status ghost_launch(const sphx_ctx *ctx, sphx_grid *g, const sphx_tasks *t,
         use_lists ? g->lrad : nullptr, g->d0, g->d1, inv_eta3,
         float(P.h_tol),
         float(ctx->h_max), float(P.gamma_k), float(P.gamma_gas), float(P.eps_balsara),
-        final_pass, step_mode ? 1 : 0, g->g0, g->g1, d->nngb, units, o->f, o->P, o->c,
+        final_pass, step_mode ? 1 : 0, g->g0, g->g1, g->g2, d->nngb, units, o->f, o->P, o->c,
         o->balsara, o->A, o->div_v, o->curl_v, o->converged, counters, skip);
     SPHX_HIP(hipGetLastError());
     return SPHX_OK;

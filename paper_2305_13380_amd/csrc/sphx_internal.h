@@ -132,6 +132,7 @@ struct sphx_grid {
     float4 *d1;         // div_sum, curl_x, curl_y, curl_z
     float4 *g0;         // force-pass state: h, rho, P, c
     float4 *g1;         // force-pass state: f, balsara, A, 0
+    float4 *g2;         // inside a step, the rest of the ghost's outputs: div, curl, converged
 
     // per leaf
     int32_t *leaf_start;  // n_leaves + 1
