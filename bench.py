@@ -58,7 +58,7 @@ def cpu_baseline(ps, params_cls, n_recv, seed=0):
     force neighbourhoods at the initial h, the ghost, and the force pass over
     the receivers. Interactions are counted as on the GPU: the density
     interactions at the final h once, plus the force interactions. Timed on
-    all host threads, and on one thread for a sample 8 times smaller. The
+    all host threads, and on one thread for a sample 4 times smaller. The
     oracle's candidate search (scipy k-d tree queries, one thread) is part of
     every pass and takes most of the time.
     (Neighbours outside the sampled neighbourhoods carry no ghost state: their
@@ -98,7 +98,7 @@ def cpu_baseline(ps, params_cls, n_recv, seed=0):
     rate, sample = run(n_recv)
     gomp.omp_set_num_threads(1)
     try:
-        rate1, sample1 = run(max(1, n_recv // 8))
+        rate1, sample1 = run(max(1, n_recv // 4))
     finally:
         gomp.omp_set_num_threads(threads)
     return {"value": rate, "unit": "interactions/s", "cores": threads, "kind": "oracle",
