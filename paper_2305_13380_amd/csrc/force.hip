@@ -157,20 +157,21 @@ __global__ __launch_bounds__(64 * NW) void k_force(
     int myn = 0;  // this lane's list length (its own particle is listed too)
     int gbase = 0;  // candidates of the earlier buffers (wave-uniform)
 
-    // One listed pair; with on = false (past the lane's list, or its own
-    // particle) it adds nothing: every accumulation is a select, so the
-    // entries need no branches and may hold any data.
+    // One listed pair; with on = false (past the lane's list, which reads
+    // slot 0, or its own particle) it adds exactly nothing, without branches.
     auto pair = [&](int c, bool listed) __attribute__((always_inline)) {
         const float4 p = cp[c];
         const float dx = pi.x - p.x, dy = pi.y - p.y, dz = pi.z - p.z;
         const float r2 = dx * dx + dy * dy + dz * dz;
-        nf += listed ? 1 : 0;
         const bool on = listed && r2 > 0.0f;
         const float4 v = cv[c];
         const float4 a = ca[c];
         const float4 b = cb[c];
         const float2 c2 = cc[c];
-        const float rinv = fast_rsq(r2);
+        // 1/r = 0 for entries past the list (slot 0: finite data) and the
+        // receiver's own particle: r, both gradients, G and nu are then 0 and
+        // every sum below adds exactly zero without a select
+        const float rinv = on ? fast_rsq(r2) : 0.0f;
         const float r = r2 * rinv;
         const float ui = r * invHi;
         const float ti = fmaxf(1.0f - ui, 0.0f);
@@ -188,10 +189,12 @@ __global__ __launch_bounds__(64 * NW) void k_force(
         const float alpha = 0.25f * (ai.x + b.w) * (Bi + b.z);
         const float irs = fast_rcp(rhoi + a.z);
         const float nu = -2.0f * alpha * mu * vs * irs;
-        // a kernel term outside its own support is zero, also when f is
-        // infinite (a particle alone in its support at a fixed h)
-        const float fgi = ui < 1.0f ? fi * gi : 0.0f, Agi = ui < 1.0f ? Ai * gi : 0.0f;
-        const float fgj = uj < 1.0f ? b.x * gj : 0.0f, Agj = uj < 1.0f ? b.y * gj : 0.0f;
+        // a kernel term outside its own support (or of an entry that is not
+        // a pair) is zero, also when f is infinite (a particle alone in its
+        // support at a fixed h)
+        const bool in_i = on && ui < 1.0f, in_j = on && uj < 1.0f;
+        const float fgi = in_i ? fi * gi : 0.0f, Agi = in_i ? Ai * gi : 0.0f;
+        const float fgj = in_j ? b.x * gj : 0.0f, Agj = in_j ? b.y * gj : 0.0f;
         const float G = fgi + fgj;
         const float acc = Agi + Agj + 0.5f * nu * G;
         const float m = v.w;
@@ -199,17 +202,22 @@ __global__ __launch_bounds__(64 * NW) void k_force(
         const float ac = psum > 0.0f ? (acPi + c2.x) * fast_rcp(psum) : 0.0f;
         const float vc = fabsf(vdote) + fast_sqrt(2.0f * fabsf(Pi - a.w) * irs);
         const float dui = m * (Agi + 0.25f * nu * G) * vdote + m * ac * vc * (vi.w - c2.y) * G * irs;
-        ax = on ? ax - m * acc * ex : ax;
-        ay = on ? ay - m * acc * ey : ay;
-        az = on ? az - m * acc * ez : az;
-        du = on ? du + dui : du;
+        ax -= m * acc * ex;
+        ay -= m * acc * ey;
+        az -= m * acc * ez;
+        du += dui;
     };
+    // Every listed entry is a force neighbour (the receiver's own particle
+    // too, subtracted at the end): counted at once.
     auto compute = [&]() __attribute__((always_inline)) {
+        nf += myn;
         for (int k = 0; __any(k < myn); k += 4) {
             const uint32_t four = *reinterpret_cast<const uint32_t *>(my_list + k);
 #pragma unroll
-            for (int q = 0; q < 4; ++q)
-                pair(int((four >> (8 * q)) & 0xffu), k + q < myn);
+            for (int q = 0; q < 4; ++q) {
+                const bool listed = k + q < myn;
+                pair(listed ? int((four >> (8 * q)) & 0xffu) : 0, listed);
+            }
         }
         myn = 0;
     };
