@@ -356,23 +356,23 @@ __global__ __launch_bounds__(64 * NW) void k_density(
             else
                 compute();
         } else {
-            // replica rj takes the slots c with gbase + c = rj (mod nrep)
+            // replica rj takes the slots c with gbase + c = rj (mod nrep);
+            // slots past the buffer read the dummy source, which no test
+            // accepts (no branch around the test)
             const int c0 = (rj - (gbase & (nrep - 1))) & (nrep - 1);
             const int m_end = (nc + nrep - 1) / nrep;
             for (int m = 0; m < m_end; m += 4) {
                 int cq[4];
-                bool ok[4];
                 float4 pq[4];
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     const int c = c0 + (m + q) * nrep;
-                    ok[q] = c < nc;
-                    cq[q] = ok[q] ? c : 0;
+                    cq[q] = c < nc ? c : CAP;
                     pq[q] = cp[cq[q]];
                 }
 #pragma unroll
                 for (int q = 0; q < 4; ++q)
-                    accept(cq[q], pq[q], ok[q]);
+                    accept(cq[q], pq[q], true);
                 if (__any(myn > kListMax - 4))
                     compute();
             }

@@ -61,6 +61,7 @@ __global__ __launch_bounds__(64 * NW) void k_force(
     const float4 *__restrict__ g1, const uint8_t *__restrict__ active,
     const int32_t *__restrict__ toff, const Task *__restrict__ task,
     const float4 *__restrict__ ext, const float *__restrict__ hmax, float gamma_k, float beta,
+    float far,
     float *__restrict__ o_ax, float *__restrict__ o_ay, float *__restrict__ o_az,
     float *__restrict__ o_du, float *__restrict__ o_vsig, int32_t *__restrict__ o_nf,
     double *__restrict__ fsum, const int32_t *__restrict__ gate, StepOut so)
@@ -85,13 +86,17 @@ __global__ __launch_bounds__(64 * NW) void k_force(
         return;
     }
 
-    __shared__ float4 cp_all[NW][CAP];  // x, y, z (receiver cell frame), H^2
+    // x, y, z (receiver cell frame), H^2; slot CAP is a dummy source beyond
+    // every support (H^2 = 0) that the replicated tests read past the buffer
+    __shared__ float4 cp_all[NW][CAP + 1];
     __shared__ float4 cv_all[NW][CAP];  // vx, vy, vz, m
     __shared__ float4 ca_all[NW][CAP];  // 1/H, c, rho, P
     __shared__ float4 cb_all[NW][CAP];  // f, A, B, alpha_v
     __shared__ float2 cc_all[NW][CAP];  // alpha_c P, u
     __shared__ uint32_t lst_all[NW][kListStride * 16];
     float4 *cp = cp_all[w], *cv = cv_all[w], *ca = ca_all[w], *cb = cb_all[w];
+    if (lane == 0)
+        cp[CAP] = make_float4(far, far, far, 0.0f);
     float2 *cc = cc_all[w];
     uint8_t *lst = reinterpret_cast<uint8_t *>(lst_all[w]);
     uint8_t *my_list = lst + lane * kListStride;
@@ -245,23 +250,23 @@ __global__ __launch_bounds__(64 * NW) void k_force(
             for (; c < nc; ++c)
                 accept(c, cp[c], true);
         } else {
-            // replica rj takes the slots c with gbase + c = rj (mod nrep)
+            // replica rj takes the slots c with gbase + c = rj (mod nrep);
+            // slots past the buffer read the dummy source, which no test
+            // accepts (no branch around the test)
             const int c0 = (rj - (gbase & (nrep - 1))) & (nrep - 1);
             const int m_end = (nc + nrep - 1) / nrep;
             for (int m = 0; m < m_end; m += 4) {
                 int cq[4];
-                bool ok[4];
                 float4 pq[4];
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     const int c = c0 + (m + q) * nrep;
-                    ok[q] = c < nc;
-                    cq[q] = ok[q] ? c : 0;
+                    cq[q] = c < nc ? c : CAP;
                     pq[q] = cp[cq[q]];
                 }
 #pragma unroll
                 for (int q = 0; q < 4; ++q)
-                    accept(cq[q], pq[q], ok[q]);
+                    accept(cq[q], pq[q], true);
                 if (__any(myn > kListMax - 4))
                     compute();
             }
@@ -529,6 +534,9 @@ sphx_status force_launch(const sphx_ctx *ctx, const sphx_grid *g, const sphx_tas
                                              gs->converged, g->g2}
                                    : StepOut{nullptr, nullptr, nullptr, nullptr, nullptr,
                                              nullptr, nullptr, nullptr, nullptr, nullptr};
+    // the dummy source: 4 box lengths out, more than 3 box lengths from any
+    // receiver (cell-relative coordinates), while every H is below a third
+    const float far = float(4.0 * std::max(ctx->p.box[0], std::max(ctx->p.box[1], ctx->p.box[2])));
     const int64_t nbp = pad8(g->n_leaves);
     SPHX_HIP(ctx->prof->begin(1, s));
     const int tile = ctx->p.force_tile ? ctx->p.force_tile : 64;
@@ -537,7 +545,7 @@ sphx_status force_launch(const sphx_ctx *ctx, const sphx_grid *g, const sphx_tas
     k_force<CAP_, NW_><<<unsigned(nbp), 64 * NW_, 0, s>>>(                                     \
         g->n_leaves, nbp, t->order, g->leaf_start, g->perm, g->q0, g->q1, g->qa, g->g0, g->g1, \
         in->active, t->off, t->task, g->leaf_ext, g->leaf_hmax, float(ctx->p.gamma_k),         \
-        float(ctx->p.beta_v), o->ax,                                                           \
+        float(ctx->p.beta_v), far, o->ax,                                                      \
         o->ay, o->az, o->du_dt, o->v_sig, o->nforce, g->fsum, gate, so)
     if (waves == 1) {
         if (tile == 64)
