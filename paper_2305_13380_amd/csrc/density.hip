@@ -422,11 +422,17 @@ __global__ __launch_bounds__(64 * NW) void k_density(
                 oy[q] = bcastf(tr.b.y, k);
                 oz[q] = bcastf(tr.b.z, k);
             }
-            float4 p[4];
+            // positions and velocities in one round trip (the velocities of
+            // culled sources are read for nothing: the loop is far from
+            // bandwidth-bound, and latency-bound here)
+            float4 p[4], v[4];
             bool keep[4];
 #pragma unroll
-            for (int q = 0; q < 4; ++q)
-                p[q] = lane < jc[q] ? q0[j0[q] + lane] : make_float4(0.f, 0.f, 0.f, 0.f);
+            for (int q = 0; q < 4; ++q) {
+                const bool in = lane < jc[q];
+                p[q] = in ? q0[j0[q] + lane] : make_float4(0.f, 0.f, 0.f, 0.f);
+                v[q] = in ? q1[j0[q] + lane] : make_float4(0.f, 0.f, 0.f, 0.f);
+            }
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 p[q].x += ox[q];
@@ -434,10 +440,6 @@ __global__ __launch_bounds__(64 * NW) void k_density(
                 p[q].z += oz[q];
                 keep[q] = lane < jc[q] && box_dist2(p[q].x, p[q].y, p[q].z, lo, hb) < R2;
             }
-            float4 v[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-                v[q] = keep[q] ? q1[j0[q] + lane] : make_float4(0.f, 0.f, 0.f, 0.f);
             emit(p[0], v[0], keep[0]);
             emit(p[1], v[1], keep[1]);
             emit(p[2], v[2], keep[2]);
