@@ -81,7 +81,8 @@ def _load():
     if _LIB is not None:
         return _LIB
     if not os.path.exists(LIB_PATH):
-        raise ImportError("libsphx.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+        raise ImportError("libsphx.so is not built (%s); run python paper_2305_13380_amd/build.py"
+                          % LIB_PATH)
     # torch ships its own HIP runtime under the same soname. Loading torch
     # first makes the loader bind the library to that runtime, so the streams
     # and memory torch hands over belong to the runtime the library calls;
