@@ -269,7 +269,10 @@ __device__ __forceinline__ int wave_prefix_small(int v, int &total)
 // MODE 2 writes into the cell's slot of the slack layout, at slot[I] up to
 // its size slot[I+1] - slot[I], and counts; MODE 3 writes at off[I] the cells
 // whose MODE 2 count exceeded their slot (the others return at once).
-template <int MODE>
+// FT: the frontier's index type, 16 bits when every level has at most 2^16
+// nodes (half the LDS per wave: twice the waves per CU for this
+// latency-bound walk), else 32.
+template <int MODE, typename FT>
 __global__ __launch_bounds__(64) void k_task_bfs(int64_t n_leaves, TreeView T,
                                                  const double *__restrict__ org,
                                                  const int32_t *__restrict__ leaf_start,
@@ -288,7 +291,7 @@ __global__ __launch_bounds__(64) void k_task_bfs(int64_t n_leaves, TreeView T,
     if (MODE == 3 && count[I] <= slot[I + 1] - slot[I])
         return;
     const int lane = threadIdx.x;
-    __shared__ int32_t front[2][kFront];
+    __shared__ FT front[2][kFront];
     const double alo[3] = {T.lo[3 * I], T.lo[3 * I + 1], T.lo[3 * I + 2]};
     const double ahi[3] = {T.hi[3 * I], T.hi[3 * I + 1], T.hi[3 * I + 2]};
     const float RI = T.r[I];
@@ -303,7 +306,7 @@ __global__ __launch_bounds__(64) void k_task_bfs(int64_t n_leaves, TreeView T,
         return;
     }
     for (int k = lane; k < ncur; k += 64)
-        front[0][k] = k;
+        front[0][k] = FT(k);
     int emitted = 0;
     const int32_t wbase = MODE == 2 ? slot[I] : (WRITE ? off[I] : 0);
     const int32_t wcap = MODE == 2 ? slot[I + 1] - slot[I] : 0x7fffffff;
@@ -318,7 +321,7 @@ __global__ __launch_bounds__(64) void k_task_bfs(int64_t n_leaves, TreeView T,
                 int32_t J = 0;
                 bool near = false;
                 if (idx < ncur) {
-                    J = front[cur][idx];
+                    J = int32_t(front[cur][idx]);
                     near = node_near(T, alo, ahi, RI, J, g, R);
                     if (near)
                         nt = emit_shifts(g, R, [](int, int, int, int) {});
@@ -370,7 +373,7 @@ __global__ __launch_bounds__(64) void k_task_bfs(int64_t n_leaves, TreeView T,
                 break;
             }
             if (keep)
-                front[cur ^ 1][nnext + lanes_below64(mask)] = int32_t(child);
+                front[cur ^ 1][nnext + lanes_below64(mask)] = FT(child);
             nnext += tot;
         }
         if (over) {
@@ -427,6 +430,20 @@ __global__ void k_slack_sizes(int64_t n_leaves, const int32_t *__restrict__ coun
 }
 
 }  // namespace
+
+// Launches the walk of mode MODE with the narrowest frontier index type.
+template <int MODE>
+static void walk_launch(int64_t nl, const TreeView &T, const double *org,
+                        const int32_t *leaf_start, const int32_t *off, const int32_t *slot,
+                        int32_t *count, uint8_t *overflow, Task *task, hipStream_t s)
+{
+    if (nl <= 65536)
+        k_task_bfs<MODE, uint16_t><<<unsigned(nl), 64, 0, s>>>(nl, T, org, leaf_start, off, slot,
+                                                              count, overflow, task);
+    else
+        k_task_bfs<MODE, int32_t><<<unsigned(nl), 64, 0, s>>>(nl, T, org, leaf_start, off, slot,
+                                                             count, overflow, task);
+}
 
 size_t tasks_bytes(int64_t n)
 {
@@ -588,11 +605,11 @@ sphx_status tasks_build(sphx_ctx *ctx, sphx_grid *g, const sphx_particles *in, h
     if (one_walk) {
         // One walk: count every cell's tasks and write them into its slot of
         // the slack layout (slots sized from the previous build's counts).
-        k_task_bfs<2><<<unsigned(nl), 64, 0, s>>>(nl, T, g->leaf_org, g->leaf_start, t->off,
-                                                  t->soff, t->count, t->overflow, t->slack);
+        walk_launch<2>(nl, T, g->leaf_org, g->leaf_start, t->off, t->soff, t->count,
+                       t->overflow, t->slack, s);
     } else {
-        k_task_bfs<0><<<unsigned(nl), 64, 0, s>>>(nl, T, g->leaf_org, g->leaf_start, t->off,
-                                                  t->soff, t->count, t->overflow, t->task);
+        walk_launch<0>(nl, T, g->leaf_org, g->leaf_start, t->off, t->soff, t->count,
+                       t->overflow, t->task, s);
     }
     SPHX_HIP(hipGetLastError());
     k_task_count<<<blocks(nl, 64), 64, 0, s>>>(nl, T, t->overflow, t->count);
@@ -615,11 +632,11 @@ sphx_status tasks_build(sphx_ctx *ctx, sphx_grid *g, const sphx_particles *in, h
         k_compact_tasks<<<unsigned(nl), 64, 0, s>>>(nl, t->soff, t->off, t->count, t->overflow,
                                                     t->slack, t->task);
         SPHX_HIP(hipGetLastError());
-        k_task_bfs<3><<<unsigned(nl), 64, 0, s>>>(nl, T, g->leaf_org, g->leaf_start, t->off,
-                                                  t->soff, t->count, t->overflow, t->task);
+        walk_launch<3>(nl, T, g->leaf_org, g->leaf_start, t->off, t->soff, t->count,
+                       t->overflow, t->task, s);
     } else {
-        k_task_bfs<1><<<unsigned(nl), 64, 0, s>>>(nl, T, g->leaf_org, g->leaf_start, t->off,
-                                                  t->soff, t->count, t->overflow, t->task);
+        walk_launch<1>(nl, T, g->leaf_org, g->leaf_start, t->off, t->soff, t->count,
+                       t->overflow, t->task, s);
     }
     SPHX_HIP(hipGetLastError());
     k_task_fill<<<blocks(nl, 64), 64, 0, s>>>(nl, T, g->leaf_org, g->leaf_start, t->overflow,
