@@ -5,7 +5,9 @@ of receivers against all N sources (k-d tree candidates, exact test in FP64).
 * fixed h: density, ghost and force of the sampled receivers element by
   element at the tolerances of the small cases;
 * full step: the sampled receivers' converged h against the oracle's own
-  Newton-Raphson solve, plus the FP64 conservation sums of the whole box.
+  Newton-Raphson solve, the FP64 conservation sums of the whole box, and
+  every density, ghost and force output of the step against the oracle
+  evaluated at the step's own final h.
 """
 import time
 
@@ -66,6 +68,14 @@ def step_case(ps, k, seed, where):
     v = np.sqrt(np.mean(ps.vx.astype(np.float64) ** 2 + ps.vy ** 2 + ps.vz ** 2))
     assert abs(s[3]) < 1e-5 * (s[4] * max(v, 1e-6) + s[5])
     log("%s: max |dh|/h = %.2e, median %.2e" % (where, dh.max(), np.median(dh)))
+    # Every output of the step at the step's own final h: the oracle's
+    # density, ghost and force evaluated at the GPU's h, element by element.
+    h_all = g["h"].astype(np.float64)
+    ref = oracle.fixed_h_step(ps, P, recv=recv, mode="tree", h=h_all)
+    log("%s: oracle at the step's h done (%.1f s)" % (where, time.time() - t0))
+    check_density(g, ref, ps, h_all, recv, P, where + " at its h")
+    check_ghost(g, ref, recv, where + " at its h")
+    check_force(g, ref, ps, h_all, recv, P, where + " at its h")
 
 
 def test_sedov_full_size_fixed_h():

@@ -7,14 +7,15 @@ Both sides stop when the Newton step falls below h_tol * h, so their final h
 agree within ~2 h_tol (usually far closer: both follow the same iteration).
 Quantities evaluated at h are then compared with a tolerance that adds the
 first-order effect of that h difference (d ln rho / d ln h = h rho'/rho from
-the oracle's own derivative)."""
+the oracle's own derivative). Every output of the step is then compared with
+the oracle evaluated at the step's own final h, at the fixed-h tolerances."""
 import numpy as np
 import pytest
 
 import oracle
 from paper_2305_13380_amd import inputs
 
-from helpers import RHO_TOL, gpu_step, rms
+from helpers import RHO_TOL, check_density, check_force, check_ghost, gpu_step, rms
 
 pytestmark = pytest.mark.gpu
 P = oracle.Params()
@@ -84,6 +85,15 @@ def test_step_matches_oracle_iteration(case, variant):
     s = g["sums"]
     assert np.abs(s[:3]).max() < 2e-5 * s[4]
     assert abs(s[3]) < 2e-5 * (s[4] * rms(np.stack([ps.vx, ps.vy, ps.vz])) * 3 + s[5] + 1e-300)
+    # Every output at the step's own final h, at the fixed-h tolerances: the
+    # h the sums belong to is the h the step returns.
+    h_all = g["h"].astype(np.float64)
+    ref_h = oracle.fixed_h_step(ps, P, h=h_all)
+    recv = np.arange(ps.n)
+    where = "%s/%s at its h" % (case, variant)
+    check_density(g, ref_h, ps, h_all, recv, P, where)
+    check_ghost(g, ref_h, recv, where)
+    check_force(g, ref_h, ps, h_all, recv, P, where)
 
 
 def test_step_is_bitwise_repeatable():
