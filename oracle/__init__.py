@@ -57,7 +57,10 @@ def lib():
         L = C.CDLL(path)
         L.or_wc2_array.argtypes = [C.c_int64, _dp, _dp, C.c_double, _dp, _dp, _dp]
         L.or_wc2_array.restype = None
-        L.or_density.argtypes = ([C.c_int64] + [_dp] * 8 + [_dp, C.c_int, C.c_double, C.c_int64,
+        L.or_kernel_array.argtypes = [C.c_int, C.c_int64, _dp, _dp, C.c_double, _dp, _dp, _dp]
+        L.or_kernel_array.restype = None
+        L.or_density.argtypes = ([C.c_int64] + [_dp] * 8 + [_dp, C.c_int, C.c_double, C.c_int,
+                                 C.c_int64,
                                  _nullable(_ip), _nullable(_ip), _nullable(_ip)] + [_dp] * 8 + [_ip])
         L.or_density.restype = C.c_int64
         L.or_h_update.argtypes = [C.c_int64, _dp, _dp, _dp, C.c_double, C.c_double, C.c_double,
@@ -65,7 +68,8 @@ def lib():
         L.or_h_update.restype = None
         L.or_ghost.argtypes = ([C.c_int64] + [_dp] * 8 + [C.c_double, C.c_double] + [_dp] * 7)
         L.or_ghost.restype = None
-        L.or_force.argtypes = ([C.c_int64] + [_dp] * 16 + [_dp, C.c_int, C.c_double, C.c_double,
+        L.or_force.argtypes = ([C.c_int64] + [_dp] * 16 + [_dp, C.c_int, C.c_double, C.c_int,
+                               C.c_double,
                                C.c_int64, _nullable(_ip), _nullable(_ip), _nullable(_ip)]
                                + [_dp] * 5 + [_ip])
         L.or_force.restype = C.c_int64
@@ -73,6 +77,27 @@ def lib():
         L.or_sums.restype = None
         _LIB = L
     return _LIB
+
+
+# The kernels Section 3.1 lists, by the id the C code takes, with the square
+# of gamma_k = H / h for h = twice the kernel's standard deviation (the
+# smoothing length is the same for every kernel: only the cut-off moves).
+# Exact fractions: sigma^2 = (1/3) int r^2 W dV is rational for these
+# piecewise polynomials; the tests recompute them from the kernels' shapes.
+KERNELS = {
+    "wendland_c2": (0, (15, 4)),
+    "wendland_c4": (1, (39, 8)),
+    "wendland_c6": (2, (6, 1)),
+    "cubic_spline": (3, (10, 3)),
+    "quartic_spline": (4, (375, 92)),
+    "quintic_spline": (5, (135, 28)),
+}
+
+
+def kernel_gamma(name: str) -> float:
+    """gamma_k of a kernel: H / h with h twice its standard deviation."""
+    p, q = KERNELS[name][1]
+    return math.sqrt(p / q)
 
 
 @dataclass
@@ -83,6 +108,7 @@ class Params:
     periodic: bool = True
     # H = gamma_k h; sqrt(15)/2 makes h twice the kernel's standard deviation.
     gamma_k: float = math.sqrt(15.0) / 2.0
+    kernel: str = "wendland_c2"    # a key of KERNELS (with_kernel sets gamma_k)
     eta: float = 1.2348
     gamma_gas: float = 5.0 / 3.0   # ratio of specific heats (Section 8, gas gamma 5/3)
     beta_v: float = 3.0            # signal-velocity constant (Section 3.2)
@@ -95,6 +121,14 @@ class Params:
         if self.h_max is not None:
             return float(self.h_max)
         return min(self.box) / (3.0 * self.gamma_k) * (1.0 - 1e-6)
+
+    @classmethod
+    def with_kernel(cls, name: str, **kw):
+        """Parameters for another kernel of the family, with its own gamma_k."""
+        return cls(kernel=name, gamma_k=kernel_gamma(name), **kw)
+
+    def kernel_id(self) -> int:
+        return KERNELS[self.kernel][0]
 
 
 def _f64(a):
@@ -110,6 +144,19 @@ def _recv_arr(recv, n):
         return None, n
     r = np.ascontiguousarray(np.asarray(recv, dtype=np.int64))
     return r, int(r.shape[0])
+
+
+def kernel(name, r, h, gamma_k=None):
+    """Vectorised W, dW/dr, dW/dh of a kernel of KERNELS (its own gamma_k
+    unless given)."""
+    g = kernel_gamma(name) if gamma_k is None else float(gamma_k)
+    r = _f64(np.atleast_1d(r))
+    h = _f64(np.broadcast_to(np.asarray(h, dtype=np.float64), r.shape))
+    w = np.empty_like(r)
+    d1 = np.empty_like(r)
+    d2 = np.empty_like(r)
+    lib().or_kernel_array(KERNELS[name][0], r.shape[0], r, h, g, w, d1, d2)
+    return w, d1, d2
 
 
 def wc2(r, h, gamma_k=Params.gamma_k):
@@ -247,7 +294,8 @@ def density(ps, h, params: Params, recv=None, mode="auto"):
     nngb = np.zeros(nrecv, np.int64)
     x, y, z = _pos(ps)
     total = lib().or_density(ps.n, x, y, z, _f64(ps.vx), _f64(ps.vy), _f64(ps.vz), _f64(ps.m), h,
-                             _f64(ps.box), int(params.periodic), float(params.gamma_k), nrecv, r,
+                             _f64(ps.box), int(params.periodic), float(params.gamma_k),
+                             params.kernel_id(), nrecv, r,
                              off, idx, out["rho"], out["rho_dh"], out["n"], out["n_dh"],
                              out["div_sum"], out["curl_x"], out["curl_y"], out["curl_z"], nngb)
     out["nngb"] = nngb
@@ -342,7 +390,8 @@ def force(ps, h, gst, dens_rho, params: Params, recv=None, mode="auto", cand=Non
                            _f64(ps.u), h, _f64(dens_rho), _f64(gst["P"]), _f64(gst["c"]),
                            _f64(gst["f"]), _f64(gst["balsara"]), _f64(ps.alpha_v),
                            _f64(ps.alpha_c), _f64(ps.box), int(params.periodic),
-                           float(params.gamma_k), float(params.beta_v), nrecv, r, off, idx,
+                           float(params.gamma_k), params.kernel_id(), float(params.beta_v),
+                           nrecv, r, off, idx,
                            out["ax"], out["ay"], out["az"], out["du"], out["vsig"], nf)
     out["nforce"] = nf
     out["total"] = int(total)

@@ -16,9 +16,14 @@
  * decides, so both modes give bit-identical results.
  *
  * Readings of the paper taken here (each one also listed in the design notes):
- *  - kernel: Wendland C2 in 3D, W(r,h) = 21/(2 pi H^3) (4u^5 - 15u^4 + 20u^3
- *    - 10u^2 + 1), u = r/H, H = gamma_k h (Sections 3.1 and 4.1); gamma_k is
- *    a parameter (sqrt(15)/2 for h = twice the kernel's standard deviation).
+ *  - kernel: Wendland C2 in 3D by default, W(r,h) = 21/(2 pi H^3) (4u^5 -
+ *    15u^4 + 20u^3 - 10u^2 + 1), u = r/H, H = gamma_k h (Sections 3.1 and
+ *    4.1); gamma_k is a parameter (sqrt(15)/2 for h = twice the kernel's
+ *    standard deviation). Section 3.1 also names the Wendland C4 and C6
+ *    functions and the cubic, quartic and quintic B-splines; they are
+ *    written below in their usual forms on the support [0, H), each scaled
+ *    to unit integral over 3D space (the paper asks every kernel to be
+ *    normalised), see or_kernel.
  *  - the self term is included in rho, n and their h-derivatives and excluded
  *    from the neighbour count; j is a neighbour of i iff r_ij < H_i (strict).
  *  - velocity divergence and curl use the difference form v_j - v_i in the
@@ -69,6 +74,76 @@ void or_wc2_array(int64_t n, const double *r, const double *h, double gamma_k,
         or_wc2(r[k], h[k], gamma_k, &w[k], &dwdr[k], &dwdh[k]);
 }
 
+/* (x)_+ and its powers, the building block of the B-splines. */
+static double pos(double x) { return x > 0.0 ? x : 0.0; }
+
+/* The kernels Section 3.1 lists, as W(r,h) = C H^-3 w(u), u = r/H < 1,
+ * H = gamma_k h, with the 3D normalisation C that makes the integral of W
+ * over space one. kind: 0 Wendland C2, 1 Wendland C4, 2 Wendland C6 (the
+ * Wendland functions psi_{3,k}, k = 1, 2, 3: (1-u)^(2k+2) times their
+ * polynomial), 3 cubic, 4 quartic, 5 quintic B-spline (the M4, M5, M6
+ * splines as sums of truncated powers (b - u)_+^p with knots spread evenly
+ * over the support). w' is the term-by-term derivative of the same
+ * expression. Returns W, dW/dr and dW/dh = -(3/h) W - (r/h) dW/dr; 0 for an
+ * unknown kind (the callers validate it). */
+void or_kernel(int kind, double r, double h, double gamma_k, double *w, double *dwdr,
+               double *dwdh)
+{
+    if (kind == 0) { /* (1-u)^4 (1 + 4u), in the expanded form Section 4.1 prints */
+        or_wc2(r, h, gamma_k, w, dwdr, dwdh);
+        return;
+    }
+    double H = gamma_k * h;
+    double u = r / H;
+    *w = *dwdr = *dwdh = 0.0;
+    if (!(u < 1.0))
+        return;
+    double a = 1.0 - u, C, f, df;
+    switch (kind) {
+    case 1: /* (1-u)^6 (1 + 6u + 35/3 u^2) */
+        C = 495.0 / (32.0 * OR_PI);
+        f = pow(a, 6) * (1.0 + 6.0 * u + 35.0 / 3.0 * u * u);
+        df = -6.0 * pow(a, 5) * (1.0 + 6.0 * u + 35.0 / 3.0 * u * u) +
+             pow(a, 6) * (6.0 + 70.0 / 3.0 * u);
+        break;
+    case 2: /* (1-u)^8 (1 + 8u + 25u^2 + 32u^3) */
+        C = 1365.0 / (64.0 * OR_PI);
+        f = pow(a, 8) * (1.0 + 8.0 * u + 25.0 * u * u + 32.0 * u * u * u);
+        df = -8.0 * pow(a, 7) * (1.0 + 8.0 * u + 25.0 * u * u + 32.0 * u * u * u) +
+             pow(a, 8) * (8.0 + 50.0 * u + 96.0 * u * u);
+        break;
+    case 3: /* (1-u)^3 - 4 (1/2-u)_+^3 */
+        C = 16.0 / OR_PI;
+        f = pow(a, 3) - 4.0 * pow(pos(0.5 - u), 3);
+        df = -3.0 * pow(a, 2) + 12.0 * pow(pos(0.5 - u), 2);
+        break;
+    case 4: /* (1-u)^4 - 5 (3/5-u)_+^4 + 10 (1/5-u)_+^4 */
+        C = 15625.0 / (512.0 * OR_PI);
+        f = pow(a, 4) - 5.0 * pow(pos(0.6 - u), 4) + 10.0 * pow(pos(0.2 - u), 4);
+        df = -4.0 * pow(a, 3) + 20.0 * pow(pos(0.6 - u), 3) - 40.0 * pow(pos(0.2 - u), 3);
+        break;
+    case 5: /* (1-u)^5 - 6 (2/3-u)_+^5 + 15 (1/3-u)_+^5 */
+        C = 2187.0 / (40.0 * OR_PI);
+        f = pow(a, 5) - 6.0 * pow(pos(2.0 / 3.0 - u), 5) + 15.0 * pow(pos(1.0 / 3.0 - u), 5);
+        df = -5.0 * pow(a, 4) + 30.0 * pow(pos(2.0 / 3.0 - u), 4) -
+             75.0 * pow(pos(1.0 / 3.0 - u), 4);
+        break;
+    default:
+        return;
+    }
+    double norm = C / (H * H * H);
+    *w = norm * f;
+    *dwdr = norm * df / H;
+    *dwdh = -3.0 / h * (*w) - r / h * (*dwdr);
+}
+
+void or_kernel_array(int kind, int64_t n, const double *r, const double *h, double gamma_k,
+                     double *w, double *dwdr, double *dwdh)
+{
+    for (int64_t k = 0; k < n; ++k)
+        or_kernel(kind, r[k], h[k], gamma_k, &w[k], &dwdr[k], &dwdh[k]);
+}
+
 /* Minimum-image separation along one axis of a periodic box. */
 static double min_image(double d, double L, int periodic)
 {
@@ -94,7 +169,7 @@ static double min_image(double d, double L, int periodic)
 int64_t or_density(int64_t n, const double *x, const double *y, const double *z,
                    const double *vx, const double *vy, const double *vz,
                    const double *m, const double *h, const double *box, int periodic,
-                   double gamma_k, int64_t nrecv, const int64_t *recv,
+                   double gamma_k, int kernel, int64_t nrecv, const int64_t *recv,
                    const int64_t *cand_off, const int64_t *cand_idx,
                    double *rho, double *rho_dh, double *nd, double *nd_dh,
                    double *div_sum, double *curl_x, double *curl_y, double *curl_z,
@@ -119,7 +194,7 @@ int64_t or_density(int64_t n, const double *x, const double *y, const double *z,
             if (!(r < Hi))
                 continue;
             double w, dwdr, dwdh;
-            or_wc2(r, hi, gamma_k, &w, &dwdr, &dwdh);
+            or_kernel(kernel, r, hi, gamma_k, &w, &dwdr, &dwdh);
             s_n += w;
             s_n_dh += dwdh;
             s_rho += m[j] * w;
@@ -262,7 +337,7 @@ int64_t or_force(int64_t n, const double *x, const double *y, const double *z,
                  const double *m, const double *u, const double *h,
                  const double *rho, const double *P, const double *c, const double *f,
                  const double *balsara, const double *alpha_v, const double *alpha_c,
-                 const double *box, int periodic, double gamma_k, double beta_v,
+                 const double *box, int periodic, double gamma_k, int kernel, double beta_v,
                  int64_t nrecv, const int64_t *recv,
                  const int64_t *cand_off, const int64_t *cand_idx,
                  double *ax, double *ay, double *az, double *du, double *vsig, int64_t *nforce)
@@ -294,8 +369,8 @@ int64_t or_force(int64_t n, const double *x, const double *y, const double *z,
             if (!(r > 0.0))
                 continue;
             double w, gi, gj, dwdh;
-            or_wc2(r, h[i], gamma_k, &w, &gi, &dwdh);
-            or_wc2(r, h[j], gamma_k, &w, &gj, &dwdh);
+            or_kernel(kernel, r, h[i], gamma_k, &w, &gi, &dwdh);
+            or_kernel(kernel, r, h[j], gamma_k, &w, &gj, &dwdh);
             double ex = dx / r, ey = dy / r, ez = dz / r;
             double wx = vx[i] - vx[j], wy = vy[i] - vy[j], wz = vz[i] - vz[j];
             double vdotx = wx * dx + wy * dy + wz * dz;
