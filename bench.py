@@ -29,9 +29,26 @@ sys.path.insert(0, ROOT)
 
 # FP32 FLOPs per accepted directed interaction, counted from the formulas as
 # the kernels evaluate them (FMA = 2, sqrt/rsqrt/rcp = 1; compares, min/max and
-# selects not counted).
+# selects not counted), with the Wendland C2 kernel.
 FLOP_DENSITY = 51
 FLOP_FORCE = 84
+# The kernel's own share of those counts, for each kernel as written in the
+# device code: w(u) and phi(u) in the density loop (both pieces of a spline
+# are evaluated), -w'(u) at each end of a force pair.
+KERNEL_FLOP_DENSITY = {"wendland_c2": 7, "wendland_c4": 13, "wendland_c6": 18,
+                       "cubic_spline": 13, "quartic_spline": 23, "quintic_spline": 27}
+KERNEL_FLOP_FORCE_END = {"wendland_c2": 4, "wendland_c4": 8, "wendland_c6": 11,
+                         "cubic_spline": 6, "quartic_spline": 13, "quintic_spline": 16}
+KERNEL_NAMES = {"wendland_c2": "Wendland C2", "wendland_c4": "Wendland C4",
+                "wendland_c6": "Wendland C6", "cubic_spline": "cubic spline",
+                "quartic_spline": "quartic spline", "quintic_spline": "quintic spline"}
+
+
+def flops_per_interaction(kernel):
+    """(density, force) FLOPs per interaction with the given kernel."""
+    d = FLOP_DENSITY - KERNEL_FLOP_DENSITY["wendland_c2"] + KERNEL_FLOP_DENSITY[kernel]
+    f = FLOP_FORCE + 2 * (KERNEL_FLOP_FORCE_END[kernel] - KERNEL_FLOP_FORCE_END["wendland_c2"])
+    return d, f
 PEAK_FP32_TFLOPS = 157.3  # MI355X published FP32 vector peak
 PEAK_HBM_GBS = 8000.0
 
@@ -50,7 +67,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(ps, params_cls, n_recv, seed=0):
+def cpu_baseline(ps, make_params, n_recv, seed=0):
     """The oracle (FP64, C + OpenMP, k-d tree candidates) timed on the host
     over the work of a GPU step, for a bounded random sample of receivers: the
     h iteration from the initial h (every density pass, with the oracle's
@@ -67,7 +84,7 @@ def cpu_baseline(ps, params_cls, n_recv, seed=0):
 
     import numpy as np
     import oracle
-    P = params_cls()
+    P = make_params()
     u_all = np.asarray(ps.u, np.float64)
     h0 = np.asarray(ps.h, np.float64)
 
@@ -206,8 +223,8 @@ def kernel_source_hash(kernel):
     import hashlib
     import re
     base = os.path.join(ROOT, "paper_2305_13380_amd", "csrc")
-    srcs = {"k_density": ["density.hip", "pairs.h", "sphx_internal.h"],
-            "k_force": ["force.hip", "pairs.h", "sphx_internal.h"]}[kernel]
+    srcs = {"k_density": ["density.hip", "pairs.h", "kernel_shapes.h", "sphx_internal.h"],
+            "k_force": ["force.hip", "pairs.h", "kernel_shapes.h", "sphx_internal.h"]}[kernel]
     hsh = hashlib.sha256()
     for f in srcs:
         text = open(os.path.join(base, f)).read()
@@ -232,6 +249,8 @@ def main():
                     help="relative enlargement of the task search radii")
     ap.add_argument("--leaf-max", type=int, default=64,
                     help="particles per leaf cell (8..64)")
+    ap.add_argument("--kernel", default="wendland_c2", choices=sorted(KERNEL_NAMES),
+                    help="smoothing kernel (default Wendland C2)")
     ap.add_argument("--no-tune", action="store_true",
                     help="default loop shapes instead of the autotuner's")
     ap.add_argument("--no-serving", action="store_true",
@@ -267,7 +286,7 @@ def main():
     log("bench: %s: N=%d generated in %.1f s" % (args.config, ps.n, time.perf_counter() - t0))
 
     dev = "cuda:0"
-    params = sphx.default_params(leaf_max=args.leaf_max, skin=args.skin)
+    params = sphx.default_params(leaf_max=args.leaf_max, skin=args.skin, kernel=args.kernel)
     dp = sphx.DeviceParticles.from_set(ps, dev)
     out = sphx.Outputs(ps.n, dev)
     stream = torch.cuda.current_stream()
@@ -396,9 +415,10 @@ def main():
     # computes the same) times the FLOPs per interaction, over the kernel's own
     # event-timed duration per step.
     S = args.steps
-    kern_units = {"k_density": (info.pairs_cellpair * FLOP_DENSITY, dens_ms / S, dens_n / S),
-                  "k_dens_list": (info.pairs_list * FLOP_DENSITY, dlist_ms / S, dlist_n / S),
-                  "k_force": (n_force * FLOP_FORCE, force_ms / S, force_n / S)}
+    fl_d, fl_f = flops_per_interaction(args.kernel)
+    kern_units = {"k_density": (info.pairs_cellpair * fl_d, dens_ms / S, dens_n / S),
+                  "k_dens_list": (info.pairs_list * fl_d, dlist_ms / S, dlist_n / S),
+                  "k_force": (n_force * fl_f, force_ms / S, force_n / S)}
     rates = {k: (f / (ms / 1e3) / 1e12 if ms > 0 else 0.0) for k, (f, ms, _) in kern_units.items()}
     kern = max(kern_units, key=lambda k: kern_units[k][1])
     flops_step, _, launches_step = kern_units[kern]
@@ -419,7 +439,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": desc, "n_particles": ps.n, "seed": ps.meta.get("seed"),
-                   "kernel": "Wendland C2", "eta": ps.eta, "h_tol": 1e-4,
+                   "kernel": KERNEL_NAMES[args.kernel], "eta": ps.eta, "h_tol": 1e-4,
                    "positions": "f64 (cell offsets f64, pair arithmetic f32)",
                    "n_dens": n_dens, "n_force": n_force, "density_passes": passes,
                    "task_rebuilds_per_step": infos[-1][1], "unconverged": infos[-1][2],
@@ -438,8 +458,11 @@ def main():
         "roofline": {"bound": "alu", "kernel": kern, "achieved": achieved,
                      "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS,
-                     "traffic": measured_traffic(args.config, kern),
-                     "counter_tflops": measured_counter_rate(args.config, kern),
+                     # (the committed counter records are of the default kernel)
+                     "traffic": (measured_traffic(args.config, kern)
+                                 if args.kernel == "wendland_c2" else None),
+                     "counter_tflops": (measured_counter_rate(args.config, kern)
+                                        if args.kernel == "wendland_c2" else None),
                      "flop_per_launch": per_launch},
     }
     del grid, tasks, out
@@ -451,7 +474,8 @@ def main():
     if not args.no_cpu_baseline:
         log("bench: timing the oracle on the host ...")
         import oracle
-        line["cpu_baseline"] = cpu_baseline(ps, oracle.Params, args.cpu_receivers)
+        line["cpu_baseline"] = cpu_baseline(
+            ps, lambda: oracle.Params.with_kernel(args.kernel), args.cpu_receivers)
     print(json.dumps(line), flush=True)
 
 

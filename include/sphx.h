@@ -97,7 +97,18 @@ typedef struct sphx_params {
      * wave's lanes (lists cut into chunks of one receiver each), 0 (default)
      * lets every lane walk its own list. Changes the FP32 summation order. */
     int32_t density_balance;
+    /* Smoothing kernel (Section 3.1 lists them; one smoothing length h for
+     * all, cut-off H = gamma_k h): SPHX_KERNEL_*. Default Wendland C2. Set it
+     * with sphx_params_set_kernel, which also sets the kernel's gamma_k. */
+    int32_t kernel;
 } sphx_params;
+
+#define SPHX_KERNEL_WENDLAND_C2 0
+#define SPHX_KERNEL_WENDLAND_C4 1
+#define SPHX_KERNEL_WENDLAND_C6 2
+#define SPHX_KERNEL_CUBIC_SPLINE 3
+#define SPHX_KERNEL_QUARTIC_SPLINE 4
+#define SPHX_KERNEL_QUINTIC_SPLINE 5
 
 /* Particle-carried inputs (Section 3.1): positions FP64, the rest FP32. */
 typedef struct sphx_particles {
@@ -160,14 +171,24 @@ typedef struct sphx_ctx sphx_ctx;
 typedef struct sphx_grid sphx_grid;
 typedef struct sphx_tasks sphx_tasks;
 
-/* Fill *p with the defaults: unit periodic box, gamma_k = sqrt(15)/2,
- * eta = 1.2348, h_tol = 1e-4, max_iter = 30, gamma_gas = 5/3, beta_v = 3,
- * eps_balsara = 1e-4, skin = 0.1, leaf_max = 64, h_max automatic. */
+/* Fill *p with the defaults: unit periodic box, Wendland C2 kernel with
+ * gamma_k = sqrt(15)/2, eta = 1.2348, h_tol = 1e-4, max_iter = 30,
+ * gamma_gas = 5/3, beta_v = 3, eps_balsara = 1e-4, skin = 0.1,
+ * leaf_max = 64, h_max automatic. */
 void sphx_params_default(sphx_params *p);
+
+/* Select the smoothing kernel `kernel` (SPHX_KERNEL_*, Section 3.1) and set
+ * p->gamma_k to its cut-off ratio H/h for h = twice the kernel's standard
+ * deviation (the convention that keeps h, and so eta, the same for every
+ * kernel): sqrt(15/4), sqrt(39/8), sqrt(6), sqrt(10/3), sqrt(375/92),
+ * sqrt(135/28) in the order of the constants. Other fields are left as they
+ * are (an automatic h_max follows gamma_k). E_INVALID for an unknown kernel,
+ * *p unchanged. */
+sphx_status sphx_params_set_kernel(sphx_params *p, int32_t kernel);
 
 /* Create a context on HIP device `hip_device` (makes it current for the
  * calling thread). Validates *p: E_INVALID for non-positive box, eta, h_tol,
- * max_iter, gamma_k, or leaf_max outside 8..64. *out is owned by the caller
+ * max_iter, gamma_k, leaf_max outside 8..64, or an unknown kernel. *out is owned by the caller
  * and released with sphx_ctx_destroy. */
 sphx_status sphx_ctx_create(const sphx_params *p, int hip_device, sphx_ctx **out);
 void sphx_ctx_destroy(sphx_ctx *ctx);

@@ -6,6 +6,7 @@
 
 #include <string>
 
+#include "kernel_shapes.h"
 #include "sphx_internal.h"
 
 namespace sphx {
@@ -128,6 +129,22 @@ void sphx_params_default(sphx_params *p)
     p->force_waves = 0;
     p->graph_passes = 0;
     p->density_balance = 0;
+    p->kernel = SPHX_KERNEL_WENDLAND_C2;
+}
+
+sphx_status sphx_params_set_kernel(sphx_params *p, int32_t kernel)
+{
+    // (H/h)^2 for h = twice the kernel's standard deviation: the per-axis
+    // variance of each normalised kernel with support 1 is 1/(4 (H/h)^2)
+    static const double gamma2[6] = {15.0 / 4.0, 39.0 / 8.0, 6.0,
+                                     10.0 / 3.0, 375.0 / 92.0, 135.0 / 28.0};
+    if (!p || kernel < 0 || kernel >= sphx::kKernelKinds) {
+        set_error("sphx_params_set_kernel: unknown kernel");
+        return SPHX_E_INVALID;
+    }
+    p->kernel = kernel;
+    p->gamma_k = sqrt(gamma2[kernel]);
+    return SPHX_OK;
 }
 
 const char *sphx_last_error(void) { return g_last_error.c_str(); }
@@ -157,6 +174,10 @@ sphx_status sphx_ctx_create(const sphx_params *p, int hip_device, sphx_ctx **out
         !one_of(p->force_tile, 64, 128, 64) || !one_of(p->force_waves, 1, 2, 1)) {
         set_error("sphx_ctx_create: loop shapes must be 0 or density_tile 64/128/256, "
                   "density_waves 1/2, force_tile 64/128, force_waves 1/2");
+        return SPHX_E_INVALID;
+    }
+    if (p->kernel < 0 || p->kernel >= sphx::kKernelKinds) {
+        set_error("sphx_ctx_create: unknown kernel (SPHX_KERNEL_*)");
         return SPHX_E_INVALID;
     }
     if (p->graph_passes < 0 || p->graph_passes > 64 || p->density_balance < 0 ||

@@ -34,17 +34,15 @@ struct DensOut {
 // point to a dummy source beyond every support (mass 0, velocity 0), which
 // adds exactly zero. Either way the loops evaluate several list entries at
 // once without branching.
-template <bool MASK>
+template <bool MASK, int K>
 __device__ __forceinline__ void dens_pair(float (&S)[kSums], const float4 &pi, const float4 &vi,
                                           float invH, const float4 &p, const float4 &v, bool on)
 {
     const float dx = pi.x - p.x, dy = pi.y - p.y, dz = pi.z - p.z;
     const float r2 = dx * dx + dy * dy + dz * dz;
     const float u = fminf(fast_sqrt(r2) * invH, 1.0f);
-    const float t1u = 1.0f - u;
-    const float t2 = t1u * t1u;
-    const float t3 = t2 * t1u;
-    const float wk = (!MASK || on) ? t2 * t2 * (1.0f + 4.0f * u) : 0.0f;
+    const float t3 = Kern<K>::phi(u);
+    const float wk = (!MASK || on) ? Kern<K>::w(u) : 0.0f;
     const float ud = (!MASK || on) ? u * u * t3 : 0.0f;
     S[0] += wk;
     S[1] += p.w * wk;
@@ -63,13 +61,15 @@ __device__ __forceinline__ void dens_pair(float (&S)[kSums], const float4 &pi, c
 // A receiver's results from its sums. Its own particle went through the loop
 // as a pair at r = 0: it contributes W(0) to n and rho and nothing to the
 // gradient sums; it is not a neighbour.
+template <int K>
 __device__ __forceinline__ void dens_finish(const float (&S)[kSums], float hi, float invH,
                                             int64_t s, int32_t gi, const DensOut &o)
 {
+    constexpr float kW = Kern<K>::kW, kD = Kern<K>::kD;
     const float Sw = S[0];
     const float Smw = S[1];
-    // W = kW H^-3 (1-u)^4 (1+4u); dW/dh = -(H^-3/h)(3 kW w - kD u^2 (1-u)^3);
-    // grad_i W = (dW/dr / r) x_ij with dW/dr / r = -kD H^-5 (1-u)^3.
+    // W = kW H^-3 w(u); dW/dh = -(H^-3/h)(3 kW w - kD u^2 phi(u));
+    // grad_i W = (dW/dr / r) x_ij with dW/dr / r = -kD H^-5 phi(u).
     const float invH3 = invH * invH * invH;
     const float invH5 = invH3 * invH * invH;
     const float ih = fast_rcp(hi);
@@ -102,7 +102,7 @@ __device__ __forceinline__ void dens_finish(const float (&S)[kSums], float hi, f
 // BAL: compute rounds cut the lanes' lists into chunks of one receiver each
 // and spread them over the lanes (compute_bal) instead of each lane walking
 // its own list.
-template <int CAP, int NW, bool BAL>
+template <int CAP, int NW, bool BAL, int K>
 __global__ __launch_bounds__(64 * NW) void k_density(
     int64_t n_leaves, int64_t nb_padded, const int32_t *__restrict__ order,
     const int32_t *__restrict__ leaf_start,
@@ -243,7 +243,7 @@ __global__ __launch_bounds__(64 * NW) void k_density(
             }
 #pragma unroll
             for (int q = 0; q < 4; ++q)
-                dens_pair<false>(S, pr, vr, invHr, p[q], v[q], true);
+                dens_pair<false, K>(S, pr, vr, invHr, p[q], v[q], true);
         }
         myn = 0;
     };
@@ -310,7 +310,7 @@ __global__ __launch_bounds__(64 * NW) void k_density(
                 }
 #pragma unroll
                 for (int q = 0; q < 4; ++q)
-                    dens_pair<true>(Tc, P, V, V.w, p[q], v[q], on[q]);
+                    dens_pair<true, K>(Tc, P, V, V.w, p[q], v[q], on[q]);
             }
 #pragma unroll
             for (int k = 0; k < kSums; ++k)
@@ -473,7 +473,7 @@ __global__ __launch_bounds__(64 * NW) void k_density(
     }
     if (!ract || rj != 0)
         return;
-    dens_finish(S, hr, invHr, sr, gr, o);
+    dens_finish<K>(S, hr, invHr, sr, gr, o);
 }
 
 // List pass: lane = receiver s = 64 b + lane of 64-block b. Entries decode to
@@ -481,6 +481,7 @@ __global__ __launch_bounds__(64 * NW) void k_density(
 // first sorted index and the FP32 offset into the receiver's frame. Entries
 // lie within the list radius (>= H); the r < H test is redone here, with
 // the same arithmetic as the cell-pair loop.
+template <int K>
 __global__ __launch_bounds__(256) void k_dens_list(
     int64_t n, int64_t nwg_padded, const uint8_t *__restrict__ need,
     const float *__restrict__ hs, const float *__restrict__ lrad,
@@ -535,12 +536,12 @@ __global__ __launch_bounds__(256) void k_dens_list(
             p[q].y += T[q].y;
             p[q].z += T[q].z;
             const float r2 = dist2(pi.x - p[q].x, pi.y - p[q].y, pi.z - p[q].z);
-            dens_pair<true>(S, pi, vi, invH, p[q], v[q], k + q < len && r2 < H2);
+            dens_pair<true, K>(S, pi, vi, invH, p[q], v[q], k + q < len && r2 < H2);
         }
     }
     if (!act)
         return;
-    dens_finish(S, hi, invH, s, perm[s], o);
+    dens_finish<K>(S, hi, invH, s, perm[s], o);
 }
 
 }  // namespace
@@ -581,24 +582,15 @@ sphx_status stale_count_launch(const sphx_ctx *ctx, const sphx_grid *g, const sp
     return SPHX_OK;
 }
 
-sphx_status density_launch(const sphx_ctx *ctx, const sphx_grid *g, const sphx_tasks *t,
-                           const sphx_particles *in, const sphx_density_out *o,
-                           int32_t *counters, bool use_lists, hipStream_t s, const int32_t *skip)
+// The loop shapes of one kernel kind.
+template <int K>
+static void density_shapes(int tile, int waves, bool bal, int64_t nbp, const sphx_ctx *ctx,
+                           const sphx_grid *g, const sphx_tasks *t, const float *lr,
+                           const DensOut &dout, float far, int32_t *counters,
+                           const int32_t *skip, hipStream_t s)
 {
-    if (g->n_leaves == 0)
-        return SPHX_OK;
-    const int64_t nbp = pad8(g->n_leaves);
-    const int tile = ctx->p.density_tile ? ctx->p.density_tile : 128;
-    const int waves = ctx->p.density_waves ? ctx->p.density_waves : 1;
-    const bool bal = ctx->p.density_balance == 1;
-    const float *lr = use_lists ? g->lrad : nullptr;
-    const DensOut dout = dens_out(g, o);
-    // the dummy source: 4 box lengths out, more than 3 box lengths from any
-    // receiver (cell-relative coordinates), while every H is below a third
-    const float far = float(4.0 * std::max(ctx->p.box[0], std::max(ctx->p.box[1], ctx->p.box[2])));
-    SPHX_HIP(ctx->prof->begin(0, s));
 #define SPHX_DENSITY_LAUNCH(CAP_, NW_, BAL_)                                                   \
-    k_density<CAP_, NW_, BAL_><<<unsigned(nbp), 64 * NW_, 0, s>>>(                             \
+    k_density<CAP_, NW_, BAL_, K><<<unsigned(nbp), 64 * NW_, 0, s>>>(                             \
         g->n_leaves, nbp, t->order, g->leaf_start, g->perm, g->q0, g->q1, g->need, g->hs,      \
         t->radius, t->off, t->task, g->leaf_ext, float(ctx->p.gamma_k), far, lr, dout,        \
         counters, skip)
@@ -625,6 +617,26 @@ sphx_status density_launch(const sphx_ctx *ctx, const sphx_grid *g, const sphx_t
             SPHX_DENSITY_LAUNCH(256, 2, false);
     }
 #undef SPHX_DENSITY_LAUNCH
+}
+
+sphx_status density_launch(const sphx_ctx *ctx, const sphx_grid *g, const sphx_tasks *t,
+                           const sphx_particles *in, const sphx_density_out *o,
+                           int32_t *counters, bool use_lists, hipStream_t s, const int32_t *skip)
+{
+    if (g->n_leaves == 0)
+        return SPHX_OK;
+    const int64_t nbp = pad8(g->n_leaves);
+    const int tile = ctx->p.density_tile ? ctx->p.density_tile : 128;
+    const int waves = ctx->p.density_waves ? ctx->p.density_waves : 1;
+    const bool bal = ctx->p.density_balance == 1;
+    const float *lr = use_lists ? g->lrad : nullptr;
+    const DensOut dout = dens_out(g, o);
+    // the dummy source: 4 box lengths out, more than 3 box lengths from any
+    // receiver (cell-relative coordinates), while every H is below a third
+    const float far = float(4.0 * std::max(ctx->p.box[0], std::max(ctx->p.box[1], ctx->p.box[2])));
+    SPHX_HIP(ctx->prof->begin(0, s));
+    SPHX_WITH_KERNEL(ctx->p.kernel, density_shapes<KK>(tile, waves, bal, nbp, ctx, g, t, lr, dout,
+                                                       far, counters, skip, s));
     SPHX_HIP(hipGetLastError());
     SPHX_HIP(ctx->prof->end(0, s));
     return SPHX_OK;
@@ -638,9 +650,11 @@ sphx_status density_list_launch(const sphx_ctx *ctx, const sphx_grid *g, const s
     const int64_t nwg = (g->n + 255) / 256;
     const int64_t nwgp = pad8(nwg);
     SPHX_HIP(ctx->prof->begin(2, s));
-    k_dens_list<<<unsigned(nwgp), 256, 0, s>>>(
-        g->n, nwgp, g->need, g->hs, g->lrad, g->leaf_of, g->perm, t->off, t->task, g->q0, g->q1,
-        g->lcnt, g->lboff, g->lst, float(ctx->p.gamma_k), dens_out(g, o));
+    SPHX_WITH_KERNEL(ctx->p.kernel,
+                     (k_dens_list<KK><<<unsigned(nwgp), 256, 0, s>>>(
+                         g->n, nwgp, g->need, g->hs, g->lrad, g->leaf_of, g->perm, t->off,
+                         t->task, g->q0, g->q1, g->lcnt, g->lboff, g->lst,
+                         float(ctx->p.gamma_k), dens_out(g, o))));
     SPHX_HIP(hipGetLastError());
     SPHX_HIP(ctx->prof->end(2, s));
     return SPHX_OK;

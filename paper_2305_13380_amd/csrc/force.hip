@@ -52,7 +52,7 @@ struct StepOut {
     const float4 *g2;
 };
 
-template <int CAP, int NW>
+template <int CAP, int NW, int K>
 __global__ __launch_bounds__(64 * NW) void k_force(
     int64_t n_leaves, int64_t nb_padded, const int32_t *__restrict__ order,
     const int32_t *__restrict__ leaf_start,
@@ -178,13 +178,13 @@ __global__ __launch_bounds__(64 * NW) void k_force(
         // every sum below adds exactly zero without a select
         const float rinv = on ? fast_rsq(r2) : 0.0f;
         const float r = r2 * rinv;
+        // dW/dr of either end at u clamped to the support (0 beyond it)
+        constexpr float kD = Kern<K>::kD;
         const float ui = r * invHi;
-        const float ti = fmaxf(1.0f - ui, 0.0f);
-        const float gi = -kD * invHi4 * ui * (ti * ti * ti);
+        const float gi = -kD * invHi4 * Kern<K>::mdw(fminf(ui, 1.0f));
         const float uj = r * a.x;
-        const float tj = fmaxf(1.0f - uj, 0.0f);
         const float ij2 = a.x * a.x;
-        const float gj = -kD * (ij2 * ij2) * uj * (tj * tj * tj);
+        const float gj = -kD * (ij2 * ij2) * Kern<K>::mdw(fminf(uj, 1.0f));
         const float ex = dx * rinv, ey = dy * rinv, ez = dz * rinv;
         const float dvx = vi.x - v.x, dvy = vi.y - v.y, dvz = vi.z - v.z;
         const float vdote = dvx * ex + dvy * ey + dvz * ez;
@@ -510,6 +510,33 @@ __global__ __launch_bounds__(kSumParts) void k_sum_parts(const double *__restric
 
 }  // namespace
 
+// The loop shapes of one kernel kind.
+template <int K>
+static void force_shapes(int tile, int waves, int64_t nbp, const sphx_ctx *ctx,
+                         const sphx_grid *g, const sphx_tasks *t, const sphx_particles *in,
+                         const sphx_force_out *o, float far, const int32_t *gate,
+                         const StepOut &so, hipStream_t s)
+{
+#define SPHX_FORCE_LAUNCH(CAP_, NW_)                                                           \
+    k_force<CAP_, NW_, K><<<unsigned(nbp), 64 * NW_, 0, s>>>(                                     \
+        g->n_leaves, nbp, t->order, g->leaf_start, g->perm, g->q0, g->q1, g->qa, g->g0, g->g1, \
+        in->active, t->off, t->task, g->leaf_ext, g->leaf_hmax, float(ctx->p.gamma_k),         \
+        float(ctx->p.beta_v), far, o->ax,                                                      \
+        o->ay, o->az, o->du_dt, o->v_sig, o->nforce, g->fsum, gate, so)
+    if (waves == 1) {
+        if (tile == 64)
+            SPHX_FORCE_LAUNCH(64, 1);
+        else
+            SPHX_FORCE_LAUNCH(128, 1);
+    } else {
+        if (tile == 64)
+            SPHX_FORCE_LAUNCH(64, 2);
+        else
+            SPHX_FORCE_LAUNCH(128, 2);
+    }
+#undef SPHX_FORCE_LAUNCH
+}
+
 sphx_status force_launch(const sphx_ctx *ctx, const sphx_grid *g, const sphx_tasks *t,
                          const sphx_particles *in, const sphx_density_out *d,
                          const sphx_ghost_out *gs, const sphx_force_out *o, double *sums6,
@@ -541,24 +568,8 @@ sphx_status force_launch(const sphx_ctx *ctx, const sphx_grid *g, const sphx_tas
     SPHX_HIP(ctx->prof->begin(1, s));
     const int tile = ctx->p.force_tile ? ctx->p.force_tile : 64;
     const int waves = ctx->p.force_waves ? ctx->p.force_waves : 1;
-#define SPHX_FORCE_LAUNCH(CAP_, NW_)                                                           \
-    k_force<CAP_, NW_><<<unsigned(nbp), 64 * NW_, 0, s>>>(                                     \
-        g->n_leaves, nbp, t->order, g->leaf_start, g->perm, g->q0, g->q1, g->qa, g->g0, g->g1, \
-        in->active, t->off, t->task, g->leaf_ext, g->leaf_hmax, float(ctx->p.gamma_k),         \
-        float(ctx->p.beta_v), far, o->ax,                                                      \
-        o->ay, o->az, o->du_dt, o->v_sig, o->nforce, g->fsum, gate, so)
-    if (waves == 1) {
-        if (tile == 64)
-            SPHX_FORCE_LAUNCH(64, 1);
-        else
-            SPHX_FORCE_LAUNCH(128, 1);
-    } else {
-        if (tile == 64)
-            SPHX_FORCE_LAUNCH(64, 2);
-        else
-            SPHX_FORCE_LAUNCH(128, 2);
-    }
-#undef SPHX_FORCE_LAUNCH
+    SPHX_WITH_KERNEL(ctx->p.kernel, force_shapes<KK>(tile, waves, nbp, ctx, g, t, in, o, far,
+                                                     gate, so, s));
     SPHX_HIP(hipGetLastError());
     SPHX_HIP(ctx->prof->end(1, s));
     if (sums6) {

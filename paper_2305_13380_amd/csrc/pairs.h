@@ -14,6 +14,7 @@
 // source order), so results do not depend on scheduling.
 #pragma once
 
+#include "kernel_shapes.h"
 #include "sphx_internal.h"
 
 namespace sphx {

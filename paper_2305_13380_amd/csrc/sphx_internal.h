@@ -39,11 +39,6 @@ constexpr int kTreeFan = 8;     // tree over leaves: groups of 8 consecutive nod
 constexpr int kMaxLevels = 24;
 constexpr int kMortonBits = 21; // bits per axis of the 63-bit Morton key
 
-// Kernel constants of the Wendland C2 kernel: W = kW H^-3 (1-u)^4 (1+4u),
-// dW/dr = -kD H^-4 u (1-u)^3.
-constexpr float kW = 3.3422538049298023f;  // 21 / (2 pi)
-constexpr float kD = 66.845076098596050f;  // 210 / pi
-
 // Task record: the source cell (its first sorted index and count), whether it
 // is the receiving cell itself without a periodic shift, and the FP32 offset
 // origin_j + shift - origin_i (formed in FP64). The second half repeats j0, so

@@ -37,7 +37,12 @@ class Params(C.Structure):
                 ("neighbour_lists", C.c_int32), ("density_tile", C.c_int32),
                 ("density_waves", C.c_int32), ("force_tile", C.c_int32),
                 ("force_waves", C.c_int32), ("graph_passes", C.c_int32),
-                ("density_balance", C.c_int32)]
+                ("density_balance", C.c_int32), ("kernel", C.c_int32)]
+
+
+# Smoothing kernels (SPHX_KERNEL_* of sphx.h), by name.
+KERNELS = {"wendland_c2": 0, "wendland_c4": 1, "wendland_c6": 2, "cubic_spline": 3,
+           "quartic_spline": 4, "quintic_spline": 5}
 
 
 class Particles(C.Structure):
@@ -71,7 +76,7 @@ SYMBOLS = ("sphx_params_default", "sphx_ctx_create", "sphx_ctx_destroy", "sphx_w
            "sphx_grid_build", "sphx_grid_destroy", "sphx_tasks_build", "sphx_tasks_destroy",
            "sphx_iter_reset", "sphx_density", "sphx_ghost", "sphx_force", "sphx_step",
            "sphx_grid_leaves", "sphx_tasks_count", "sphx_last_error", "sphx_profile_enable",
-           "sphx_profile_read", "sphx_autotune")
+           "sphx_profile_read", "sphx_autotune", "sphx_params_set_kernel")
 
 _LIB = None
 
@@ -92,6 +97,8 @@ def _load():
     vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
     P = C.POINTER
     L.sphx_params_default.argtypes = [P(Params)]
+    L.sphx_params_set_kernel.argtypes = [P(Params), i32]
+    L.sphx_params_set_kernel.restype = i32
     L.sphx_params_default.restype = None
     L.sphx_ctx_create.argtypes = [P(Params), C.c_int, P(vp)]
     L.sphx_ctx_destroy.argtypes = [vp]
@@ -145,9 +152,17 @@ def _check(status):
 
 
 def default_params(**kw) -> Params:
+    """The library's defaults with fields overridden by keyword; kernel= takes
+    a name of KERNELS (or its number) and sets the kernel's gamma_k too."""
     p = Params()
     lib.sphx_params_default(C.byref(p))
+    if "kernel" in kw:
+        k = kw["kernel"]
+        k = KERNELS[k] if isinstance(k, str) else int(k)
+        _check(lib.sphx_params_set_kernel(C.byref(p), k))
     for k, v in kw.items():
+        if k == "kernel":
+            continue
         if k == "box":
             p.box = (C.c_double * 3)(*v)
         else:

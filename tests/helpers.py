@@ -85,7 +85,7 @@ def edge_counts(ps, h, recv, params, force=False):
     pos = np.stack([ps.x, ps.y, ps.z], 1)
     H = params.gamma_k * np.asarray(h, np.float64)
     if force:
-        off, idx = oracle.force_candidates(ps, h, params, recv)
+        off, idx = oracle.force_candidates(ps, h * (1 + 2 * EDGE), params, recv)
     else:
         off, idx = oracle.density_candidates(ps, h * (1 + 2 * EDGE), params, recv)
     k = np.repeat(np.arange(len(recv)), np.diff(off))

@@ -99,3 +99,25 @@ def test_one_hip_runtime_in_the_process(sphx):
     import ast
     paths = ast.literal_eval(out)
     assert len(paths) == 1, paths
+
+
+def test_kernel_setter_gives_each_kernels_gamma(sphx):
+    import oracle
+    assert sphx.default_params().kernel == 0
+    for name, (kid, _) in oracle.KERNELS.items():
+        p = sphx.default_params(kernel=name)
+        assert p.kernel == kid == sphx.KERNELS[name]
+        assert abs(p.gamma_k - oracle.kernel_gamma(name)) < 1e-15
+    p = sphx.default_params()
+    assert sphx.lib.sphx_params_set_kernel(C.byref(p), 6) == sphx.E_INVALID
+    assert sphx.lib.sphx_params_set_kernel(C.byref(p), -1) == sphx.E_INVALID
+    assert p.kernel == 0 and abs(p.gamma_k - math.sqrt(15.0) / 2.0) < 1e-15
+
+
+@pytest.mark.parametrize("kernel", [-1, 6])
+def test_ctx_create_rejects_unknown_kernel(sphx, kernel):
+    p = sphx.default_params()
+    p.kernel = kernel
+    h = C.c_void_p()
+    assert sphx.lib.sphx_ctx_create(C.byref(p), 0, C.byref(h)) == sphx.E_INVALID
+    assert "kernel" in sphx.last_error() and not h.value
