@@ -75,6 +75,9 @@ def lib():
         L.or_force.restype = C.c_int64
         L.or_sums.argtypes = [C.c_int64] + [_dp] * 8 + [_dp]
         L.or_sums.restype = None
+        L.or_fof.argtypes = ([C.c_int64] + [_dp] * 4 + [C.c_int, C.c_double, _nullable(_ip),
+                             _nullable(_ip), _ip])
+        L.or_fof.restype = C.c_int64
         _LIB = L
     return _LIB
 
@@ -467,3 +470,38 @@ def nr_step(ps, params: Params, mode="auto"):
     res["n_dens_total"] = int(dens["nngb"].sum())
     res["n_force_total"] = fo["total"]
     return res
+
+
+# ---------------------------------------------------------------------------
+# Friends-of-friends groups (Section 9.1).
+# ---------------------------------------------------------------------------
+
+def fof_link_length(ps, frac=0.2):
+    """frac times the mean inter-particle separation (V / N)^(1/3)."""
+    vol = float(np.prod(np.asarray(ps.box, dtype=np.float64)))
+    return frac * (vol / ps.n) ** (1.0 / 3.0)
+
+
+def fof(ps, b, periodic=True, mode="auto"):
+    """Friends-of-friends groups at linking length b (or_fof): returns
+    (group, links) with group[i] the smallest index of i's group and links the
+    number of linked pairs. Tree mode takes candidates from a k-d tree within
+    b (padded); the C code applies the exact test, so both modes agree."""
+    mode = _resolve_mode(mode, ps.n)
+    off = idx = None
+    if mode == "tree":
+        p = _wrapped_positions(ps, periodic)
+        tree = _tree(p, ps, periodic)
+        ks, js = [], []
+        chunk = 65536
+        for s in range(0, ps.n, chunk):
+            lists = tree.query_ball_point(p[s:s + chunk], b * _PAD, return_sorted=True)
+            k, j = _pairs(lists, s)
+            ks.append(k)
+            js.append(j)
+        off, idx = _csr(np.concatenate(ks), np.concatenate(js), ps.n, ps.n)
+    group = np.empty(ps.n, np.int64)
+    x, y, z = _pos(ps)
+    links = lib().or_fof(ps.n, x, y, z, _f64(ps.box), int(periodic), float(b) * float(b),
+                         off, idx, group)
+    return group, int(links)

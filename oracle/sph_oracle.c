@@ -427,3 +427,54 @@ void or_sums(int64_t n, const double *m, const double *vx, const double *vy, con
     for (int q = 0; q < 6; ++q)
         out[q] = s[q];
 }
+
+/*
+ * Friends-of-friends groups (Section 9.1): particles i and j are linked when
+ * they lie closer than the linking length b, read here as
+ * |x_i - x_j|^2 < b^2 for the minimum-image separation, the squared distance
+ * formed in FP64 as ((dx dx + dy dy) + dz dz) and compared with b2 = b^2.
+ * Groups are the connected components of the links. Plain sequential
+ * union-find over the candidate pairs (every pair, or an ascending candidate
+ * list per particle), each union hanging the larger root under the smaller,
+ * so the root of every set is its smallest index; on return group[i] is the
+ * smallest index of i's group. Returns the number of links (pairs i < j).
+ */
+static int64_t or_find(int64_t *parent, int64_t i)
+{
+    while (parent[i] != i)
+        i = parent[i];
+    return i;
+}
+
+int64_t or_fof(int64_t n, const double *x, const double *y, const double *z, const double *box,
+               int periodic, double b2, const int64_t *cand_off, const int64_t *cand_idx,
+               int64_t *group)
+{
+    for (int64_t i = 0; i < n; ++i)
+        group[i] = i;
+    int64_t links = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t jb = cand_off ? cand_off[i] : 0;
+        int64_t je = cand_off ? cand_off[i + 1] : n;
+        for (int64_t q = jb; q < je; ++q) {
+            int64_t j = cand_off ? cand_idx[q] : q;
+            if (j <= i)
+                continue;
+            double dx = min_image(x[i] - x[j], box[0], periodic);
+            double dy = min_image(y[i] - y[j], box[1], periodic);
+            double dz = min_image(z[i] - z[j], box[2], periodic);
+            double r2 = dx * dx + dy * dy + dz * dz;
+            if (!(r2 < b2))
+                continue;
+            links += 1;
+            int64_t ri = or_find(group, i), rj = or_find(group, j);
+            if (ri < rj)
+                group[rj] = ri;
+            else if (rj < ri)
+                group[ri] = rj;
+        }
+    }
+    for (int64_t i = 0; i < n; ++i)
+        group[i] = or_find(group, i);
+    return links;
+}
