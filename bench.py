@@ -187,6 +187,37 @@ def serving_bench(slots, n_req, seed=4):
     return out
 
 
+def fof_bench(params, dp, reps):
+    """Friends-of-friends groups of the workload at 0.2 of the mean particle
+    separation (sphx_fof: cell and task build at that radius, the link loop,
+    labels), inputs resident in HBM; one warm-up call, then the shortest of
+    `reps` timed calls (host clock around a call and a device sync)."""
+    import numpy as np
+    import torch
+    from paper_2305_13380_amd import sphx
+    ctx = sphx.Context(params, 0)
+    vol = float(np.prod(np.asarray(params.box)))
+    b = 0.2 * (vol / dp.n) ** (1.0 / 3.0)
+    group, gsize, counts = sphx.fof(ctx, dp, b)
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(max(1, reps)):
+        t0 = time.perf_counter()
+        group, gsize, counts = sphx.fof(ctx, dp, b)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    c = counts.cpu().numpy()
+    biggest = int(torch.bincount(group.to(torch.int64)).max()) if dp.n else 0
+    ctx.close()
+    t = min(times)
+    rec = {"link_length": b, "link_length_of_mean_separation": 0.2, "ms": t * 1e3,
+           "particles_per_s": dp.n / t, "groups": int(c[0]), "links": int(c[1]),
+           "largest_group": biggest, "reps": len(times),
+           "timed": "whole sphx_fof call: cell and task build at radius b, link loop, labels"}
+    log("bench: fof: %s" % json.dumps(rec))
+    return rec
+
+
 def measured_traffic(config, kernel):
     """HBM bytes per launch of `kernel` from the committed counter summary
     (profiles/traffic_<config>.json: FETCH_SIZE and WRITE_SIZE scaled by a
@@ -255,6 +286,9 @@ def main():
                     help="default loop shapes instead of the autotuner's")
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the serving-stream latency measurement")
+    ap.add_argument("--no-fof", action="store_true",
+                    help="skip the friends-of-friends timing on the workload")
+    ap.add_argument("--fof-reps", type=int, default=5)
     ap.add_argument("--serving-requests", type=int, default=512)
     ap.add_argument("--serving-slots", type=int, default=8)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -466,6 +500,8 @@ def main():
                      "flop_per_launch": per_launch},
     }
     del grid, tasks, out
+    if not args.no_fof:
+        line["fof"] = fof_bench(params, dp, args.fof_reps)
     if not args.no_serving:
         sv = serving_bench(args.serving_slots, args.serving_requests)
         line["serving"] = sv

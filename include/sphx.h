@@ -297,6 +297,28 @@ sphx_status sphx_autotune(sphx_ctx *ctx, sphx_grid *grid, sphx_tasks *tasks, sph
                           sphx_density_out *dens, sphx_ghost_out *gst, sphx_force_out *out,
                           int32_t reps, sphx_params *tuned, void *stream);
 
+/* Friends-of-friends groups (Section 9.1): particles i and j are linked when
+ * they lie closer than the linking length b, decided in FP64 on the caller's
+ * positions as |x_i - x_j|^2 < b^2 (minimum image in a periodic box; the
+ * squared distance formed as (dx dx + dy dy) + dz dz, each operation rounded
+ * on its own); groups are the connected components of the links, found by
+ * union-find over the self and pair tasks of a cell structure built with b
+ * as its search radius (ctx's leaf_max and skin apply).
+ *   in         every particle takes part (in->active and in->h are ignored,
+ *              h may be NULL); the other per-particle arrays are read by the
+ *              cell build but do not change the groups.
+ *   b          0 < b <= min(box)/3 (1 - 1e-5), else E_INVALID.
+ *   group      device, n int32, caller order: the smallest caller index of
+ *              the particle's group (so group[i] == i marks one particle of
+ *              each group). Required when n > 0.
+ *   group_size device, n int32, or NULL: the number of particles in i's group.
+ *   d_counts   device, 2 int64, or NULL: [0] number of groups, [1] number of
+ *              linked pairs.
+ * Results do not depend on scheduling. Allocates its workspace on `stream`
+ * and synchronises once (the task build reads back its size). */
+sphx_status sphx_fof(sphx_ctx *ctx, const sphx_particles *in, double b, int32_t *group,
+                     int32_t *group_size, int64_t *d_counts, void *stream);
+
 /* Kernel timing for measurement tools. sphx_profile_enable(ctx, 1) clears the
  * statistics and starts recording a pair of HIP events around every launch of
  * the cell-pair density kernel (kernel 0), the force kernel (kernel 1), the

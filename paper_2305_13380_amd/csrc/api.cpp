@@ -272,6 +272,31 @@ sphx_status sphx_tasks_build(sphx_ctx *ctx, sphx_grid *grid, const sphx_particle
 
 void sphx_tasks_destroy(sphx_tasks *tasks) { tasks_free(tasks); }
 
+sphx_status sphx_fof(sphx_ctx *ctx, const sphx_particles *in, double b, int32_t *group,
+                     int32_t *group_size, int64_t *d_counts, void *stream)
+{
+    if (!ctx || !in) {
+        set_error("sphx_fof: NULL argument");
+        return SPHX_E_INVALID;
+    }
+    // h is not used (the search radius is b): check the rest with a stand-in
+    sphx_particles chk = *in;
+    if (!chk.h)
+        chk.h = reinterpret_cast<float *>(group);
+    SPHX_TRY(check_particles(&chk, false));
+    const double lmin = std::min(ctx->p.box[0], std::min(ctx->p.box[1], ctx->p.box[2]));
+    if (!(b > 0.0) || !(b <= lmin / 3.0 * (1.0 - 1e-5))) {
+        set_error("sphx_fof: the linking length must be in (0, min(box)/3 (1 - 1e-5)]");
+        return SPHX_E_INVALID;
+    }
+    if (in->n > 0 && !group) {
+        set_error("sphx_fof: group is NULL");
+        return SPHX_E_INVALID;
+    }
+    SPHX_HIP(hipSetDevice(ctx->device));
+    return fof_run(ctx, in, b, group, group_size, d_counts, as_stream(stream));
+}
+
 sphx_status sphx_iter_reset(sphx_ctx *ctx, sphx_grid *grid, const sphx_particles *in,
                             void *stream)
 {

@@ -14,7 +14,10 @@
 // [0, 1] (callers clamp u at 1, where every function vanishes). The spline
 // pieces are the splines' truncated-power sums multiplied out on each
 // interval between knots: no cancellation near u = 0 and no division there;
-// phi divides by u only on intervals that stay away from 0.
+// phi divides by u only on intervals that stay away from 0. Both pieces are
+// evaluated and one is picked by a bit mask: with a plain conditional the
+// compiler forms predicated blocks in the unrolled pair loops, and the
+// spline loops then need about 180 instead of about 128 registers.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -30,6 +33,14 @@ enum KernelKind : int {
     kQuinticSpline = 5,
     kKernelKinds = 6
 };
+
+// a where pick, else b, by bit masks: both operands are computed first, and
+// no branch or predicated block is left for the compiler to form
+__device__ __forceinline__ float pick(bool pick_a, float a, float b)
+{
+    const int m = -int(pick_a);
+    return __int_as_float((__float_as_int(a) & m) | (__float_as_int(b) & ~m));
+}
 
 template <int K>
 struct Kern;
@@ -103,13 +114,14 @@ struct Kern<kCubicSpline> {
     __device__ static __forceinline__ float phi(float u)
     {
         const float t = 1.0f - u;
-        return u < 0.5f ? 6.0f - 9.0f * u
-                        : 3.0f * (t * t) * __builtin_amdgcn_rcpf(fmaxf(u, 0.5f));
+        const float in = 6.0f - 9.0f * u;
+        const float out = 3.0f * (t * t) * __builtin_amdgcn_rcpf(fmaxf(u, 0.5f));
+        return pick(u < 0.5f, in, out);
     }
     __device__ static __forceinline__ float mdw(float u)
     {
         const float t = 1.0f - u;
-        return u < 0.5f ? u * (6.0f - 9.0f * u) : 3.0f * (t * t);
+        return pick(u < 0.5f, u * (6.0f - 9.0f * u), 3.0f * (t * t));
     }
 };
 
@@ -132,12 +144,13 @@ struct Kern<kQuarticSpline> {
     }
     __device__ static __forceinline__ float phi(float u)
     {
-        return u < 0.2f ? 4.8f - 24.0f * (u * u)
-                        : outer(u) * __builtin_amdgcn_rcpf(fmaxf(u, 0.2f));
+        const float in = 4.8f - 24.0f * (u * u);
+        const float out = outer(u) * __builtin_amdgcn_rcpf(fmaxf(u, 0.2f));
+        return pick(u < 0.2f, in, out);
     }
     __device__ static __forceinline__ float mdw(float u)
     {
-        return u < 0.2f ? u * (4.8f - 24.0f * (u * u)) : outer(u);
+        return pick(u < 0.2f, u * (4.8f - 24.0f * (u * u)), outer(u));
     }
 };
 
@@ -162,17 +175,17 @@ struct Kern<kQuinticSpline> {
     }
     __device__ static __forceinline__ float inner(float u)
     {
-        const float u2 = u * u;
-        return (40.0f / 9.0f) - 40.0f * u2 + 50.0f * (u2 * u);
+        return (40.0f / 9.0f) + (u * u) * (50.0f * u - 40.0f);
     }
     __device__ static __forceinline__ float phi(float u)
     {
-        return u < (1.0f / 3.0f) ? inner(u)
-                                 : outer(u) * __builtin_amdgcn_rcpf(fmaxf(u, 1.0f / 3.0f));
+        const float in = inner(u);
+        const float out = outer(u) * __builtin_amdgcn_rcpf(fmaxf(u, 1.0f / 3.0f));
+        return pick(u < (1.0f / 3.0f), in, out);
     }
     __device__ static __forceinline__ float mdw(float u)
     {
-        return u < (1.0f / 3.0f) ? u * inner(u) : outer(u);
+        return pick(u < (1.0f / 3.0f), u * inner(u), outer(u));
     }
 };
 

@@ -215,6 +215,9 @@ size_t grid_bytes(int64_t n);
 sphx_status tasks_build(sphx_ctx *ctx, sphx_grid *g, const sphx_particles *in, hipStream_t s,
                         sphx_tasks **out);
 void tasks_free(sphx_tasks *t);
+// Friends-of-friends groups over a grid and tasks built at search radius b.
+sphx_status fof_run(sphx_ctx *ctx, const sphx_particles *in, double b, int32_t *group,
+                    int32_t *group_size, int64_t *d_counts, hipStream_t s);
 size_t tasks_bytes(int64_t n);
 
 // density.hip

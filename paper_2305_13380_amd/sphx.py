@@ -76,7 +76,7 @@ SYMBOLS = ("sphx_params_default", "sphx_ctx_create", "sphx_ctx_destroy", "sphx_w
            "sphx_grid_build", "sphx_grid_destroy", "sphx_tasks_build", "sphx_tasks_destroy",
            "sphx_iter_reset", "sphx_density", "sphx_ghost", "sphx_force", "sphx_step",
            "sphx_grid_leaves", "sphx_tasks_count", "sphx_last_error", "sphx_profile_enable",
-           "sphx_profile_read", "sphx_autotune", "sphx_params_set_kernel")
+           "sphx_profile_read", "sphx_autotune", "sphx_params_set_kernel", "sphx_fof")
 
 _LIB = None
 
@@ -99,6 +99,8 @@ def _load():
     L.sphx_params_default.argtypes = [P(Params)]
     L.sphx_params_set_kernel.argtypes = [P(Params), i32]
     L.sphx_params_set_kernel.restype = i32
+    L.sphx_fof.argtypes = [vp, P(Particles), C.c_double, vp, vp, vp, vp]
+    L.sphx_fof.restype = i32
     L.sphx_params_default.restype = None
     L.sphx_ctx_create.argtypes = [P(Params), C.c_int, P(vp)]
     L.sphx_ctx_destroy.argtypes = [vp]
@@ -370,6 +372,21 @@ def fixed_h_pass(ctx, grid, tasks, parts, out: Outputs, stream=None):
     density(ctx, grid, tasks, parts, out, stream=stream)
     ghost(ctx, grid, tasks, parts, out, final_pass=True, stream=stream)
     force(ctx, grid, tasks, parts, out, stream=stream)
+
+
+def fof(ctx, parts, b, sizes=True, stream=None):
+    """Friends-of-friends groups at linking length b (sphx_fof): returns
+    (group, group_size or None, counts) as device tensors: group[i] is the
+    smallest index of i's group, counts = [groups, linked pairs] (int64)."""
+    import torch
+    dev = parts.t["x"].device
+    group = torch.empty(parts.n, dtype=torch.int32, device=dev)
+    gsize = torch.empty(parts.n, dtype=torch.int32, device=dev) if sizes else None
+    counts = torch.empty(2, dtype=torch.int64, device=dev)
+    pv = parts.view()
+    _check(lib.sphx_fof(ctx.handle, C.byref(pv), float(b), _ptr(group), _ptr(gsize),
+                        _ptr(counts), _stream(stream)))
+    return group, gsize, counts
 
 
 def autotune(ctx, grid, tasks, parts, out: Outputs, reps=3, stream=None) -> Params:

@@ -145,3 +145,26 @@ def test_large_active_full_size_fixed_h():
     check_density(gs, ref, sub, h, recv, P, where)
     check_ghost(gs, ref, recv, where)
     check_force(gs, ref, sub, h, recv, P, where)
+
+
+def test_clustered_full_size_fof():
+    """Friends-of-friends groups of the whole 2,097,152-particle clustered box
+    at 0.2 of the mean separation, bit for bit against the oracle (k-d tree
+    candidates, exact FP64 link test)."""
+    import torch
+    from paper_2305_13380_amd import sphx
+    where = "clustered 128^3 fof"
+    t0 = time.time()
+    ps = inputs.config_clustered(3)
+    b = oracle.fof_link_length(ps)
+    ctx = sphx.Context()
+    dp = sphx.DeviceParticles.from_set(ps)
+    group, gsize, counts = sphx.fof(ctx, dp, b)
+    torch.cuda.synchronize()
+    g, gs, cnt = group.cpu().numpy(), gsize.cpu().numpy(), counts.cpu().numpy()
+    log("%s: GPU done, %d groups, %d links (%.1f s)" % (where, cnt[0], cnt[1], time.time() - t0))
+    ref, links = oracle.fof(ps, b, mode="tree")
+    log("%s: oracle done (%.1f s)" % (where, time.time() - t0))
+    assert cnt[1] == links and cnt[0] == len(np.unique(ref))
+    assert np.array_equal(g, ref), "%d particles in another group" % int((g != ref).sum())
+    np.testing.assert_array_equal(gs, np.bincount(ref, minlength=ps.n)[ref])
