@@ -192,6 +192,16 @@ sphx_status sphx_ctx_create(const sphx_params *p, int hip_device, sphx_ctx **out
         return SPHX_E_INVALID;
     }
     SPHX_HIP(hipSetDevice(hip_device));
+    // Grids, task lists and their scratch come stream-ordered from the
+    // device's default pool and go back to it when a request is done; by
+    // default the pool hands freed memory back to the device at every
+    // synchronisation, and the next build maps it again. Keep it cached.
+    hipMemPool_t pool = nullptr;
+    if (hipDeviceGetDefaultMemPool(&pool, hip_device) == hipSuccess && pool) {
+        uint64_t keep = UINT64_MAX;
+        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+    }
+    (void)hipGetLastError();
     sphx_ctx *c = new sphx_ctx();
     c->prof = new Profiler();
     c->p = *p;
