@@ -78,6 +78,12 @@ def lib():
         L.or_fof.argtypes = ([C.c_int64] + [_dp] * 4 + [C.c_int, C.c_double, _nullable(_ip),
                              _nullable(_ip), _ip])
         L.or_fof.restype = C.c_int64
+        L.or_grav_pair_array.argtypes = [C.c_int64, _dp, C.c_double, C.c_double, _dp, _dp]
+        L.or_grav_pair_array.restype = None
+        L.or_gravity.argtypes = ([C.c_int64] + [_dp] * 5 + [C.c_int] + [C.c_double] * 4
+                                 + [C.c_int64, _nullable(_ip), _nullable(_ip), _nullable(_ip)]
+                                 + [_dp] * 5)
+        L.or_gravity.restype = C.c_int64
         _LIB = L
     return _LIB
 
@@ -505,3 +511,44 @@ def fof(ps, b, periodic=True, mode="auto"):
     links = lib().or_fof(ps.n, x, y, z, _f64(ps.box), int(periodic), float(b) * float(b),
                          off, idx, group)
     return group, int(links)
+
+
+# ---------------------------------------------------------------------------
+# Short-range softened gravity by direct summation (Sections 4.1 and 4.4).
+# ---------------------------------------------------------------------------
+
+def grav_pair(r, H, rs=0.0):
+    """(phi_s, k/r) of or_grav_pair for an array of separations."""
+    r = _f64(np.atleast_1d(r))
+    phi = np.empty_like(r)
+    kr = np.empty_like(r)
+    lib().or_grav_pair_array(r.shape[0], r, float(H), float(rs), phi, kr)
+    return phi, kr
+
+
+def gravity(ps, G, H, rs, rp2p, periodic=True, recv=None, mode="auto"):
+    """Accelerations, potential and term scale of or_gravity for the
+    receivers (all particles when recv is None), over j != i with
+    r_ij < rp2p."""
+    mode = _resolve_mode(mode, ps.n)
+    r, nrecv = _recv_arr(recv, ps.n)
+    off = idx = None
+    if mode == "tree":
+        p = _wrapped_positions(ps, periodic)
+        tree = _tree(p, ps, periodic)
+        ri = np.arange(ps.n) if recv is None else np.asarray(recv)
+        ks, js = [], []
+        chunk = 65536
+        for s in range(0, len(ri), chunk):
+            lists = tree.query_ball_point(p[ri[s:s + chunk]], rp2p * _PAD, return_sorted=True)
+            k, j = _pairs(lists, s)
+            ks.append(k)
+            js.append(j)
+        off, idx = _csr(np.concatenate(ks), np.concatenate(js), len(ri), ps.n)
+    out = {k: np.zeros(nrecv) for k in ("ax", "ay", "az", "pot", "scale")}
+    x, y, z = _pos(ps)
+    total = lib().or_gravity(ps.n, x, y, z, _f64(ps.m), _f64(ps.box), int(periodic), float(G),
+                             float(H), float(rs), float(rp2p), nrecv, r, off, idx, out["ax"],
+                             out["ay"], out["az"], out["pot"], out["scale"])
+    out["pairs"] = int(total)
+    return out

@@ -478,3 +478,100 @@ int64_t or_fof(int64_t n, const double *x, const double *y, const double *z, con
         group[i] = or_find(group, i);
     return links;
 }
+
+/*
+ * Short-range softened gravity by direct summation (Section 4.1: the C2
+ * softened potential; Section 4.4: the short-range truncation of the mesh
+ * split). For a pair at separation r:
+ *   phi(r)   = f(r/H) / H for r < H, 1/r beyond, with the printed
+ *              f(u) = -3u^7 + 15u^6 - 28u^5 + 21u^4 - 7u^2 + 3;
+ *   phi'(r)/r = g(r/H) / H^3 for r < H, -1/r^3 beyond, with the printed
+ *              g(u) = f'(u)/u = -21u^5 + 90u^4 - 140u^3 + 84u^2 - 14
+ *              (the printed outer branch, r^-3, is the magnitude: the
+ *              gradient of 1/r is -r/r^3);
+ *   chi(r)   = erfc(r / (2 r_s)) (chi = 1 when r_s <= 0: no truncation),
+ *   the short-range potential phi_s = phi chi, and the acceleration is its
+ *   exact gradient:
+ *   a_i      = G sum_j m_j x_ij [phi'(r) chi(r) + phi(r) chi'(r)] / r,
+ *   pot_i    = -G sum_j m_j phi(r) chi(r),
+ * over j != i with r_ij < r_p2p (the pairs a tree code sums directly), x_ij
+ * = x_i - x_j minimum image, chi'(r) = -exp(-r^2 / (4 r_s^2)) / (sqrt(pi)
+ * r_s). A coincident pair (r = 0) adds to the potential, not to the force.
+ * scale_i = G sum_j m_j |[...] / r| r, the size of the summed terms (the
+ * natural scale of the rounding error of the sum). Returns the pair count.
+ */
+static void or_grav_f_g(double u, double *f, double *g)
+{
+    double u2 = u * u, u3 = u2 * u, u4 = u3 * u, u5 = u4 * u, u6 = u5 * u, u7 = u6 * u;
+    *f = -3.0 * u7 + 15.0 * u6 - 28.0 * u5 + 21.0 * u4 - 7.0 * u2 + 3.0;
+    *g = -21.0 * u5 + 90.0 * u4 - 140.0 * u3 + 84.0 * u2 - 14.0;
+}
+
+void or_grav_pair(double r, double H, double rs, double *phi_s, double *k_over_r)
+{
+    double phi, dphi_r; /* phi and phi'(r)/r */
+    if (r < H) {
+        double f, g;
+        or_grav_f_g(r / H, &f, &g);
+        phi = f / H;
+        dphi_r = g / (H * H * H);
+    } else {
+        phi = 1.0 / r;
+        dphi_r = -1.0 / (r * r * r);
+    }
+    double chi = 1.0, dchi_r = 0.0; /* chi and chi'(r)/r */
+    if (rs > 0.0) {
+        chi = erfc(r / (2.0 * rs));
+        dchi_r = r > 0.0 ? -exp(-r * r / (4.0 * rs * rs)) / (sqrt(OR_PI) * rs) / r : 0.0;
+    }
+    *phi_s = phi * chi;
+    *k_over_r = r > 0.0 ? dphi_r * chi + phi * dchi_r : 0.0;
+}
+
+void or_grav_pair_array(int64_t n, const double *r, double H, double rs, double *phi_s,
+                        double *k_over_r)
+{
+    for (int64_t k = 0; k < n; ++k)
+        or_grav_pair(r[k], H, rs, &phi_s[k], &k_over_r[k]);
+}
+
+int64_t or_gravity(int64_t n, const double *x, const double *y, const double *z, const double *m,
+                   const double *box, int periodic, double G, double H, double rs, double rp2p,
+                   int64_t nrecv, const int64_t *recv, const int64_t *cand_off,
+                   const int64_t *cand_idx, double *ax, double *ay, double *az, double *pot,
+                   double *scale)
+{
+    int64_t total = 0;
+#pragma omp parallel for schedule(dynamic, 16) reduction(+ : total)
+    for (int64_t k = 0; k < nrecv; ++k) {
+        int64_t i = recv ? recv[k] : k;
+        double sx = 0, sy = 0, sz = 0, sp = 0, sa = 0;
+        int64_t jb = cand_off ? cand_off[k] : 0;
+        int64_t je = cand_off ? cand_off[k + 1] : n;
+        for (int64_t q = jb; q < je; ++q) {
+            int64_t j = cand_off ? cand_idx[q] : q;
+            if (j == i)
+                continue;
+            double dx = min_image(x[i] - x[j], box[0], periodic);
+            double dy = min_image(y[i] - y[j], box[1], periodic);
+            double dz = min_image(z[i] - z[j], box[2], periodic);
+            double r = sqrt(dx * dx + dy * dy + dz * dz);
+            if (!(r < rp2p))
+                continue;
+            total += 1;
+            double phi_s, kr;
+            or_grav_pair(r, H, rs, &phi_s, &kr);
+            sp += m[j] * phi_s;
+            sx += m[j] * kr * dx;
+            sy += m[j] * kr * dy;
+            sz += m[j] * kr * dz;
+            sa += m[j] * fabs(kr) * r;
+        }
+        ax[k] = G * sx;
+        ay[k] = G * sy;
+        az[k] = G * sz;
+        pot[k] = -G * sp;
+        scale[k] = G * sa;
+    }
+    return total;
+}
