@@ -39,6 +39,11 @@ KERNEL_FLOP_DENSITY = {"wendland_c2": 7, "wendland_c4": 13, "wendland_c6": 18,
                        "cubic_spline": 13, "quartic_spline": 23, "quintic_spline": 27}
 KERNEL_FLOP_FORCE_END = {"wendland_c2": 4, "wendland_c4": 8, "wendland_c6": 11,
                          "cubic_spline": 6, "quartic_spline": 13, "quintic_spline": 16}
+# FP32 FLOPs per summed pair of the truncated gravity loop, as evaluated:
+# separation and r^2 8, rsqrt and r 2, u and u^2 2, f and g by Horner 18, the
+# two branches 4, erfc and exp 2 (one each), their arguments and chi'/r 5,
+# the combination 3, the three accelerations 7, the potential 3.
+FLOP_GRAVITY = 54
 KERNEL_NAMES = {"wendland_c2": "Wendland C2", "wendland_c4": "Wendland C4",
                 "wendland_c6": "Wendland C6", "cubic_spline": "cubic spline",
                 "quartic_spline": "quartic spline", "quintic_spline": "quintic spline"}
@@ -218,6 +223,44 @@ def fof_bench(params, dp, reps):
     return rec
 
 
+def gravity_bench(params, dp, reps):
+    """Short-range softened gravity of the workload by direct summation
+    (sphx_gravity) at G = 1, softening support H = 0.12, truncation scale
+    r_s = 1.25 and summation radius r_p2p = 1.25 mean particle separations:
+    one warm-up call, then the shortest of `reps` timed calls (host clock
+    around a call and a device sync), and the gravity kernel's own time from
+    the library's event profiler."""
+    import numpy as np
+    import torch
+    from paper_2305_13380_amd import sphx
+    ctx = sphx.Context(params, 0)
+    d = (float(np.prod(np.asarray(params.box))) / dp.n) ** (1.0 / 3.0)
+    H, rs, rp = 0.12 * d, 1.25 * d, 1.25 * d
+    pairs = torch.zeros(1, dtype=torch.int64, device="cuda:0")
+    sphx.gravity(ctx, dp, 1.0, H, rs, rp, pairs=pairs)
+    torch.cuda.synchronize()
+    times = []
+    ctx.profile(True)
+    for _ in range(max(1, reps)):
+        t0 = time.perf_counter()
+        sphx.gravity(ctx, dp, 1.0, H, rs, rp, pairs=pairs)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    k_ms, k_n = ctx.profile_read(4)
+    ctx.close()
+    npairs = int(pairs.item())
+    kern_s = k_ms / 1e3 / max(k_n, 1)
+    rec = {"G": 1.0, "H": H, "r_s": rs, "r_p2p": rp, "of_mean_separation": [0.12, 1.25, 1.25],
+           "pairs": npairs, "ms": min(times) * 1e3, "kernel_ms": kern_s * 1e3,
+           "pairs_per_s": npairs / kern_s if kern_s > 0 else None,
+           "kernel_tflops_algorithmic": npairs * FLOP_GRAVITY / kern_s / 1e12 if kern_s > 0 else None,
+           "flop_per_pair": FLOP_GRAVITY, "reps": len(times),
+           "timed": "ms: whole sphx_gravity call (cell and task build at r_p2p, the loop); "
+                    "kernel_ms: the loop alone"}
+    log("bench: gravity: %s" % json.dumps(rec))
+    return rec
+
+
 def measured_traffic(config, kernel):
     """HBM bytes per launch of `kernel` from the committed counter summary
     (profiles/traffic_<config>.json: FETCH_SIZE and WRITE_SIZE scaled by a
@@ -288,7 +331,10 @@ def main():
                     help="skip the serving-stream latency measurement")
     ap.add_argument("--no-fof", action="store_true",
                     help="skip the friends-of-friends timing on the workload")
-    ap.add_argument("--fof-reps", type=int, default=5)
+    ap.add_argument("--fof-reps", type=int, default=5,
+                    help="timed calls of the friends-of-friends and gravity legs")
+    ap.add_argument("--no-gravity", action="store_true",
+                    help="skip the direct-summation gravity timing on the workload")
     ap.add_argument("--serving-requests", type=int, default=512)
     ap.add_argument("--serving-slots", type=int, default=8)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -502,6 +548,8 @@ def main():
     del grid, tasks, out
     if not args.no_fof:
         line["fof"] = fof_bench(params, dp, args.fof_reps)
+    if not args.no_gravity:
+        line["gravity"] = gravity_bench(params, dp, args.fof_reps)
     if not args.no_serving:
         sv = serving_bench(args.serving_slots, args.serving_requests)
         line["serving"] = sv

@@ -319,11 +319,37 @@ sphx_status sphx_autotune(sphx_ctx *ctx, sphx_grid *grid, sphx_tasks *tasks, sph
 sphx_status sphx_fof(sphx_ctx *ctx, const sphx_particles *in, double b, int32_t *group,
                      int32_t *group_size, int64_t *d_counts, void *stream);
 
+/* Short-range softened gravity by direct summation (Section 4.1: the C2
+ * softened potential and force; Section 4.4: the short-range truncation of
+ * the mesh split). For a pair at separation r (minimum image):
+ *   phi(r) = f(r/H)/H for r < H, else 1/r, with the printed
+ *            f(u) = -3u^7 + 15u^6 - 28u^5 + 21u^4 - 7u^2 + 3;
+ *   phi'(r)/r = g(r/H)/H^3 for r < H, else -1/r^3, g(u) = f'(u)/u;
+ *   chi(r) = erfc(r / (2 r_s)) (1 when r_s = 0: no truncation);
+ *   a_i = G sum_j m_j x_ij [phi'(r) chi(r) + phi(r) chi'(r)] / r (the exact
+ *   gradient of the truncated potential), pot_i = -G sum_j m_j phi(r) chi(r),
+ *   over j != i with r_ij < r_p2p: the pairs a tree code sums directly (the
+ *   multipole and mesh parts of the force are not computed here).
+ *   G > 0; H > 0 is the softening kernel's support (3 eps_Plummer); r_s >= 0;
+ *   0 < r_p2p <= min(box)/3 (1 - 1e-5); else E_INVALID.
+ *   ax, ay, az (device, n FP32 each, caller order) required when n > 0;
+ *   pot (device, n FP32) or NULL; d_pairs (device, 1 int64) or NULL: the
+ *   number of directed pairs summed.
+ * Every particle receives (in->active and in->h are ignored, h may be NULL;
+ * the other per-particle arrays are read by the cell build). Pair arithmetic
+ * in FP32 on cell-relative coordinates; the r < r_p2p test is taken in FP32
+ * too. Allocates its workspace on `stream` and synchronises once (the task
+ * build reads back its size). */
+sphx_status sphx_gravity(sphx_ctx *ctx, const sphx_particles *in, double G, double H,
+                         double r_s, double r_p2p, float *ax, float *ay, float *az, float *pot,
+                         int64_t *d_pairs, void *stream);
+
 /* Kernel timing for measurement tools. sphx_profile_enable(ctx, 1) clears the
  * statistics and starts recording a pair of HIP events around every launch of
  * the cell-pair density kernel (kernel 0), the force kernel (kernel 1), the
- * list density kernel (kernel 2) and the neighbour-list build (kernel 3: its
- * counting pass with the offset scan, and its filling pass), on the stream
+ * list density kernel (kernel 2), the neighbour-list build (kernel 3: its
+ * counting pass with the offset scan, and its filling pass) and the gravity
+ * loop of sphx_gravity (kernel 4), on the stream
  * the kernel is launched on; 0 stops recording. sphx_profile_read
  * waits for the recorded events and returns the summed kernel time in
  * milliseconds and the number of launches since the last enable. */

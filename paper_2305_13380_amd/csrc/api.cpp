@@ -1,4 +1,5 @@
 #include <algorithm>
+#include <cmath>
 // C-ABI entry points of the sphx library: argument validation, ownership of
 // the opaque handles, and the host side of the h iteration.
 #include <math.h>
@@ -281,6 +282,34 @@ sphx_status sphx_tasks_build(sphx_ctx *ctx, sphx_grid *grid, const sphx_particle
 }
 
 void sphx_tasks_destroy(sphx_tasks *tasks) { tasks_free(tasks); }
+
+sphx_status sphx_gravity(sphx_ctx *ctx, const sphx_particles *in, double G, double H,
+                         double r_s, double r_p2p, float *ax, float *ay, float *az, float *pot,
+                         int64_t *d_pairs, void *stream)
+{
+    if (!ctx || !in) {
+        set_error("sphx_gravity: NULL argument");
+        return SPHX_E_INVALID;
+    }
+    sphx_particles chk = *in;
+    if (!chk.h)
+        chk.h = ax;  // h is not used: the search radius is r_p2p
+    SPHX_TRY(check_particles(&chk, false));
+    const double lmin = std::min(ctx->p.box[0], std::min(ctx->p.box[1], ctx->p.box[2]));
+    if (!(G > 0.0) || !(H > 0.0) || !(r_s >= 0.0) || !(r_p2p > 0.0) ||
+        !(r_p2p <= lmin / 3.0 * (1.0 - 1e-5)) || !std::isfinite(G) || !std::isfinite(H) ||
+        !std::isfinite(r_s)) {
+        set_error("sphx_gravity: need G > 0, H > 0, r_s >= 0 and 0 < r_p2p <= min(box)/3 "
+                  "(1 - 1e-5)");
+        return SPHX_E_INVALID;
+    }
+    if (in->n > 0 && (!ax || !ay || !az)) {
+        set_error("sphx_gravity: NULL acceleration array");
+        return SPHX_E_INVALID;
+    }
+    SPHX_HIP(hipSetDevice(ctx->device));
+    return gravity_run(ctx, in, G, H, r_s, r_p2p, ax, ay, az, pot, d_pairs, as_stream(stream));
+}
 
 sphx_status sphx_fof(sphx_ctx *ctx, const sphx_particles *in, double b, int32_t *group,
                      int32_t *group_size, int64_t *d_counts, void *stream)

@@ -72,13 +72,19 @@ __device__ void unite(int32_t *parent, int32_t a, int32_t b)
     }
 }
 
-__global__ void k_fof_fill(int64_t n, float hv, float *__restrict__ h, int32_t *__restrict__ parent,
-                           int32_t *__restrict__ minc, int32_t *__restrict__ size)
+__global__ void k_fill_h(int64_t n, float hv, float *__restrict__ h)
+{
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n)
+        h[i] = hv;
+}
+
+__global__ void k_fof_fill(int64_t n, int32_t *__restrict__ parent, int32_t *__restrict__ minc,
+                           int32_t *__restrict__ size)
 {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= n)
         return;
-    h[i] = hv;
     parent[i] = int32_t(i);
     minc[i] = INT_MAX;
     size[i] = 0;
@@ -195,6 +201,39 @@ __global__ void k_fof_out(int64_t n, const int32_t *__restrict__ perm,
 
 }  // namespace
 
+SearchCells::~SearchCells()
+{
+    if (t)
+        tasks_free(t);
+    if (g)
+        grid_free(g);
+    dfree(h, s);
+}
+
+sphx_status search_cells_build(sphx_ctx *ctx, const sphx_particles *in, double radius,
+                               hipStream_t s, SearchCells &sc)
+{
+    const int64_t n = in->n;
+    sc.s = s;
+    // h such that the search radius gamma_k h covers `radius` (a relative
+    // margin of 2^-20 absorbs the FP32 rounding of h)
+    const float hv = float(radius / ctx->p.gamma_k * (1.0 + 1.0 / 1048576.0));
+    if (dmalloc((void **)&sc.h, size_t(n) * sizeof(float), s) != hipSuccess) {
+        (void)hipGetLastError();
+        sc.h = nullptr;
+        set_error("device allocation failed");
+        return SPHX_E_OOM;
+    }
+    k_fill_h<<<unsigned((n + kFofThreads - 1) / kFofThreads), kFofThreads, 0, s>>>(n, hv, sc.h);
+    SPHX_HIP(hipGetLastError());
+    sphx_particles tmp = *in;
+    tmp.h = sc.h;
+    tmp.active = nullptr;  // every particle takes part
+    SPHX_TRY(grid_build(ctx, &tmp, s, &sc.g));
+    SPHX_TRY(refresh_h(sc.g, &tmp, s));
+    return tasks_build(ctx, sc.g, &tmp, s, &sc.t);
+}
+
 sphx_status fof_run(sphx_ctx *ctx, const sphx_particles *in, double b, int32_t *group,
                     int32_t *group_size, int64_t *d_counts, hipStream_t s)
 {
@@ -205,50 +244,25 @@ sphx_status fof_run(sphx_ctx *ctx, const sphx_particles *in, double b, int32_t *
     }
     if (n == 0)
         return SPHX_OK;
-    // h such that the search radius gamma_k h covers b (a relative margin
-    // of 2^-20 absorbs the FP32 rounding of h)
-    const float hv = float(b / ctx->p.gamma_k * (1.0 + 1.0 / 1048576.0));
-    float *h_tmp = nullptr;
     int32_t *ws = nullptr;
-    SPHX_HIP(dmalloc((void **)&h_tmp, size_t(n) * sizeof(float), s));
     if (dmalloc((void **)&ws, size_t(n) * 3 * sizeof(int32_t), s) != hipSuccess) {
         (void)hipGetLastError();
-        dfree(h_tmp, s);
         set_error("sphx_fof: device allocation failed");
         return SPHX_E_OOM;
     }
     int32_t *parent = ws, *minc = ws + n, *size = ws + 2 * n;
     struct Scratch {
-        void *a, *b;
+        void *a;
         hipStream_t s;
-        ~Scratch()
-        {
-            dfree(a, s);
-            dfree(b, s);
-        }
-    } scratch{h_tmp, ws, s};
+        ~Scratch() { dfree(a, s); }
+    } scratch{ws, s};
     const unsigned nb = unsigned((n + kFofThreads - 1) / kFofThreads);
-    k_fof_fill<<<nb, kFofThreads, 0, s>>>(n, hv, h_tmp, parent, minc, size);
+    k_fof_fill<<<nb, kFofThreads, 0, s>>>(n, parent, minc, size);
     SPHX_HIP(hipGetLastError());
-
-    sphx_particles tmp = *in;
-    tmp.h = h_tmp;
-    tmp.active = nullptr;  // every particle links
-    sphx_grid *g = nullptr;
-    sphx_tasks *t = nullptr;
-    SPHX_TRY(grid_build(ctx, &tmp, s, &g));
-    struct Handles {
-        sphx_grid *g;
-        sphx_tasks **t;
-        ~Handles()
-        {
-            if (*t)
-                tasks_free(*t);
-            grid_free(g);
-        }
-    } handles{g, &t};
-    SPHX_TRY(refresh_h(g, &tmp, s));
-    SPHX_TRY(tasks_build(ctx, g, &tmp, s, &t));
+    SearchCells sc;
+    SPHX_TRY(search_cells_build(ctx, in, b, s, sc));
+    const sphx_grid *g = sc.g;
+    const sphx_tasks *t = sc.t;
 
     // group and link counts: into the caller's array, else a private one
     unsigned long long *cnt = reinterpret_cast<unsigned long long *>(d_counts);

@@ -74,9 +74,10 @@ struct Profiler {
     struct Rec {
         hipEvent_t a, b;
     };
-    static constexpr int kKinds = 4;  // density cell-pair, force, density list, list build
+    // density cell-pair, force, density list, list build, gravity
+    static constexpr int kKinds = 5;
     std::vector<Rec> pool[kKinds];
-    size_t used[kKinds] = {0, 0, 0, 0};
+    size_t used[kKinds] = {0, 0, 0, 0, 0};
     hipError_t begin(int k, hipStream_t s);
     hipError_t end(int k, hipStream_t s);
 };
@@ -215,6 +216,25 @@ size_t grid_bytes(int64_t n);
 sphx_status tasks_build(sphx_ctx *ctx, sphx_grid *g, const sphx_particles *in, hipStream_t s,
                         sphx_tasks **out);
 void tasks_free(sphx_tasks *t);
+// A grid and task list over every particle of `in` with a uniform search
+// radius (h = radius / gamma_k on a private array): the pair structure of
+// friends-of-friends and direct-summation gravity. Released with the struct.
+struct SearchCells {
+    sphx_grid *g = nullptr;
+    sphx_tasks *t = nullptr;
+    float *h = nullptr;
+    hipStream_t s = nullptr;
+    SearchCells() = default;
+    SearchCells(const SearchCells &) = delete;
+    SearchCells &operator=(const SearchCells &) = delete;
+    ~SearchCells();
+};
+sphx_status search_cells_build(sphx_ctx *ctx, const sphx_particles *in, double radius,
+                               hipStream_t s, SearchCells &sc);
+// Short-range softened gravity over a grid and tasks built at radius rp2p.
+sphx_status gravity_run(sphx_ctx *ctx, const sphx_particles *in, double G, double H, double rs,
+                        double rp2p, float *ax, float *ay, float *az, float *pot,
+                        int64_t *d_pairs, hipStream_t s);
 // Friends-of-friends groups over a grid and tasks built at search radius b.
 sphx_status fof_run(sphx_ctx *ctx, const sphx_particles *in, double b, int32_t *group,
                     int32_t *group_size, int64_t *d_counts, hipStream_t s);

@@ -76,7 +76,8 @@ SYMBOLS = ("sphx_params_default", "sphx_ctx_create", "sphx_ctx_destroy", "sphx_w
            "sphx_grid_build", "sphx_grid_destroy", "sphx_tasks_build", "sphx_tasks_destroy",
            "sphx_iter_reset", "sphx_density", "sphx_ghost", "sphx_force", "sphx_step",
            "sphx_grid_leaves", "sphx_tasks_count", "sphx_last_error", "sphx_profile_enable",
-           "sphx_profile_read", "sphx_autotune", "sphx_params_set_kernel", "sphx_fof")
+           "sphx_profile_read", "sphx_autotune", "sphx_params_set_kernel", "sphx_fof",
+           "sphx_gravity")
 
 _LIB = None
 
@@ -101,6 +102,8 @@ def _load():
     L.sphx_params_set_kernel.restype = i32
     L.sphx_fof.argtypes = [vp, P(Particles), C.c_double, vp, vp, vp, vp]
     L.sphx_fof.restype = i32
+    L.sphx_gravity.argtypes = [vp, P(Particles)] + [C.c_double] * 4 + [vp] * 6
+    L.sphx_gravity.restype = i32
     L.sphx_params_default.restype = None
     L.sphx_ctx_create.argtypes = [P(Params), C.c_int, P(vp)]
     L.sphx_ctx_destroy.argtypes = [vp]
@@ -387,6 +390,21 @@ def fof(ctx, parts, b, sizes=True, stream=None):
     _check(lib.sphx_fof(ctx.handle, C.byref(pv), float(b), _ptr(group), _ptr(gsize),
                         _ptr(counts), _stream(stream)))
     return group, gsize, counts
+
+
+def gravity(ctx, parts, G, H, r_s, r_p2p, potential=True, pairs=None, stream=None):
+    """Short-range softened gravity by direct summation (sphx_gravity):
+    returns device tensors (ax, ay, az, pot or None); `pairs`, a device int64
+    tensor of one element, receives the number of pairs summed."""
+    import torch
+    dev = parts.t["x"].device
+    a = [torch.empty(parts.n, dtype=torch.float32, device=dev) for _ in range(3)]
+    pot = torch.empty(parts.n, dtype=torch.float32, device=dev) if potential else None
+    pv = parts.view()
+    _check(lib.sphx_gravity(ctx.handle, C.byref(pv), float(G), float(H), float(r_s),
+                            float(r_p2p), _ptr(a[0]), _ptr(a[1]), _ptr(a[2]), _ptr(pot),
+                            _ptr(pairs), _stream(stream)))
+    return a[0], a[1], a[2], pot
 
 
 def autotune(ctx, grid, tasks, parts, out: Outputs, reps=3, stream=None) -> Params:

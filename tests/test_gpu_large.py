@@ -168,3 +168,27 @@ def test_clustered_full_size_fof():
     assert cnt[1] == links and cnt[0] == len(np.unique(ref))
     assert np.array_equal(g, ref), "%d particles in another group" % int((g != ref).sum())
     np.testing.assert_array_equal(gs, np.bincount(ref, minlength=ps.n)[ref])
+
+
+def test_clustered_full_size_gravity():
+    """Short-range softened gravity of the 2,097,152-particle clustered box
+    (H = 0.12, r_s = 1.25, r_p2p = 1.25 mean separations), a random sample of
+    receivers against the oracle at the tolerances of the small cases."""
+    import torch
+    from paper_2305_13380_amd import sphx
+    from test_gpu_gravity import check
+    where = "clustered 128^3 gravity"
+    t0 = time.time()
+    ps = inputs.config_clustered(3)
+    d = (1.0 / ps.n) ** (1.0 / 3.0)
+    H, rs, rp = 0.12 * d, 1.25 * d, 1.25 * d
+    ctx = sphx.Context()
+    dp = sphx.DeviceParticles.from_set(ps)
+    ax, ay, az, pot = sphx.gravity(ctx, dp, 1.0, H, rs, rp)
+    torch.cuda.synchronize()
+    a = np.stack([ax.cpu().numpy(), ay.cpu().numpy(), az.cpu().numpy()], 1)
+    p = pot.cpu().numpy()
+    log("%s: GPU done (%.1f s)" % (where, time.time() - t0))
+    recv = np.sort(sample(ps.n, 2048, 17))
+    check(ps, a, p, 1.0, H, rs, rp, where, recv=recv)
+    log("%s: oracle on %d receivers done (%.1f s)" % (where, len(recv), time.time() - t0))
