@@ -311,41 +311,55 @@ __global__ __launch_bounds__(64) void k_task_bfs(int64_t n_leaves, TreeView T,
     const int32_t wbase = MODE == 2 ? slot[I] : (WRITE ? off[I] : 0);
     const int32_t wcap = MODE == 2 ? slot[I + 1] - slot[I] : 0x7fffffff;
     const double oxi = org[3 * I], oyi = org[3 * I + 1], ozi = org[3 * I + 2];
+    // One wave-wide round of up to 64 candidate leaves, one per lane, in lane
+    // order: tasks counted, prefix-summed over the lanes and written.
+    auto emit_round = [&](bool cand, int32_t J) __attribute__((always_inline)) {
+        int nt = 0;
+        double g[3][3], R = 0.0;
+        if (cand && node_near(T, alo, ahi, RI, J, g, R))
+            nt = emit_shifts(g, R, [](int, int, int, int) {});
+        int tot;
+        const int pre = wave_prefix_small(nt, tot);
+        if (WRITE && nt > 0) {
+            const int32_t j0 = leaf_start[J];
+            const int32_t jc = leaf_start[J + 1] - j0;
+            emit_shifts(g, R, [&](int k, int sx, int sy, int sz) {
+                Task t;
+                t.j = J;
+                t.j0 = j0;
+                t.jc = jc;
+                t.self = (J == I && sx == 0 && sy == 0 && sz == 0) ? 1 : 0;
+                t.ox = float(org[3 * J] + double(sx) * T.L[0] - oxi);
+                t.oy = float(org[3 * J + 1] + double(sy) * T.L[1] - oyi);
+                t.oz = float(org[3 * J + 2] + double(sz) * T.L[2] - ozi);
+                t.j0b = j0;
+                if (emitted + pre + k < wcap)
+                    task[wbase + emitted + pre + k] = t;
+            });
+        }
+        emitted += tot;
+    };
     for (int lev = top; lev >= 0; --lev) {
         __syncthreads();
         if (lev == 0) {
+            // a tree of one level: the frontier holds the leaves themselves
             for (int base = 0; base < ncur; base += 64) {
                 const int idx = base + lane;
-                int nt = 0;
-                double g[3][3], R = 0.0;
-                int32_t J = 0;
-                bool near = false;
-                if (idx < ncur) {
-                    J = int32_t(front[cur][idx]);
-                    near = node_near(T, alo, ahi, RI, J, g, R);
-                    if (near)
-                        nt = emit_shifts(g, R, [](int, int, int, int) {});
-                }
-                int tot;
-                const int pre = wave_prefix_small(nt, tot);
-                if (WRITE && nt > 0) {
-                    const int32_t j0 = leaf_start[J];
-                    const int32_t jc = leaf_start[J + 1] - j0;
-                    emit_shifts(g, R, [&](int k, int sx, int sy, int sz) {
-                        Task t;
-                        t.j = J;
-                        t.j0 = j0;
-                        t.jc = jc;
-                        t.self = (J == I && sx == 0 && sy == 0 && sz == 0) ? 1 : 0;
-                        t.ox = float(org[3 * J] + double(sx) * T.L[0] - oxi);
-                        t.oy = float(org[3 * J + 1] + double(sy) * T.L[1] - oyi);
-                        t.oz = float(org[3 * J + 2] + double(sz) * T.L[2] - ozi);
-                        t.j0b = j0;
-                        if (emitted + pre + k < wcap)
-                            task[wbase + emitted + pre + k] = t;
-                    });
-                }
-                emitted += tot;
+                emit_round(idx < ncur, idx < ncur ? int32_t(front[cur][idx]) : 0);
+            }
+            break;
+        }
+        if (lev == 1) {
+            // the children are the leaves (level 0 holds them at their own
+            // index): emit them straight from this expansion, in the order
+            // a leaf frontier would hold them, so the frontier never has to
+            // hold the finest level
+            const int64_t n0 = T.level_cnt[0];
+            for (int base = 0; base < ncur; base += 8) {
+                const int k = base + (lane >> 3);
+                const int64_t child =
+                    k < ncur ? int64_t(front[cur][k]) * kTreeFan + (lane & 7) : n0;
+                emit_round(child < n0, child < n0 ? int32_t(child) : 0);
             }
             break;
         }
