@@ -71,3 +71,26 @@ def test_kernels_give_different_densities():
     for a in range(len(NAMES)):
         for b in range(a):
             assert np.abs(rho[a] - rho[b]).max() > 1e-3 * np.abs(rho[b]).max()
+
+
+@pytest.mark.parametrize("variant", ["lists", "graph"])
+@pytest.mark.parametrize("name", ["quartic_spline", "wendland_c6"])
+def test_step_paths_with_other_kernels(name, variant):
+    # the neighbour-list density loop and the captured step run the same
+    # kernel templates: a whole step through each, at the step's own h
+    ps = inputs.lognormal_box(16, 6000, 2.0, 11)
+    P = oracle.Params.with_kernel(name)
+    kw = {"kernel": name}
+    kw.update({"neighbour_lists": 1} if variant == "lists" else {"graph_passes": 4})
+    print("kernel step path:", name, variant, flush=True)
+    g = gpu_step(ps, params=kw)
+    assert g["status"] >= 0 and g["info"].unconverged == 0
+    h = g["h"].astype(np.float64)
+    ref = oracle.nr_step(ps, P, mode="auto")
+    assert np.all(np.abs(h - ref["h"]) <= 2 * P.h_tol * ref["h"])
+    at = oracle.fixed_h_step(ps, P, mode="auto", h=h)
+    recv = np.arange(ps.n)
+    where = "%s %s step at its h" % (name, variant)
+    check_density(g, at, ps, h, recv, P, where)
+    check_ghost(g, at, recv, where)
+    check_force(g, at, ps, h, recv, P, where)
