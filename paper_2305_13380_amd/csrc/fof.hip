@@ -244,18 +244,22 @@ sphx_status fof_run(sphx_ctx *ctx, const sphx_particles *in, double b, int32_t *
     }
     if (n == 0)
         return SPHX_OK;
-    int32_t *ws = nullptr;
-    if (dmalloc((void **)&ws, size_t(n) * 3 * sizeof(int32_t), s) != hipSuccess) {
+    // one workspace: two count words (used when the caller gives none), then
+    // parent, smallest caller index and size per particle
+    unsigned char *ws = nullptr;
+    if (dmalloc((void **)&ws, 16 + size_t(n) * 3 * sizeof(int32_t), s) != hipSuccess) {
         (void)hipGetLastError();
         set_error("sphx_fof: device allocation failed");
         return SPHX_E_OOM;
     }
-    int32_t *parent = ws, *minc = ws + n, *size = ws + 2 * n;
     struct Scratch {
         void *a;
         hipStream_t s;
         ~Scratch() { dfree(a, s); }
     } scratch{ws, s};
+    unsigned long long *own = reinterpret_cast<unsigned long long *>(ws);
+    int32_t *parent = reinterpret_cast<int32_t *>(ws + 16), *minc = parent + n,
+            *size = parent + 2 * n;
     const unsigned nb = unsigned((n + kFofThreads - 1) / kFofThreads);
     k_fof_fill<<<nb, kFofThreads, 0, s>>>(n, parent, minc, size);
     SPHX_HIP(hipGetLastError());
@@ -264,18 +268,14 @@ sphx_status fof_run(sphx_ctx *ctx, const sphx_particles *in, double b, int32_t *
     const sphx_grid *g = sc.g;
     const sphx_tasks *t = sc.t;
 
-    // group and link counts: into the caller's array, else a private one
+    // group and link counts: into the caller's array, else the private words
     unsigned long long *cnt = reinterpret_cast<unsigned long long *>(d_counts);
-    unsigned long long *links = cnt ? cnt + 1 : nullptr;
-    unsigned long long *groups = cnt ? cnt : nullptr;
-    unsigned long long *own = nullptr;
     if (!cnt) {
-        SPHX_HIP(dmalloc((void **)&own, 2 * sizeof(unsigned long long), s));
         k_fof_zero<<<1, 64, 0, s>>>(reinterpret_cast<int64_t *>(own));
         SPHX_HIP(hipGetLastError());
-        links = own + 1;
-        groups = own;
+        cnt = own;
     }
+    unsigned long long *groups = cnt, *links = cnt + 1;
     k_fof_link<<<unsigned(g->n_leaves), 64, 0, s>>>(
         g->n_leaves, g->leaf_start, g->leaf_org, g->perm, in->x, in->y, in->z, ctx->p.box[0],
         ctx->p.box[1], ctx->p.box[2], ctx->p.periodic, b * b, t->off, t->task, parent, links);
@@ -284,7 +284,6 @@ sphx_status fof_run(sphx_ctx *ctx, const sphx_particles *in, double b, int32_t *
     SPHX_HIP(hipGetLastError());
     k_fof_out<<<nb, kFofThreads, 0, s>>>(n, g->perm, parent, minc, size, group, group_size);
     SPHX_HIP(hipGetLastError());
-    dfree(own, s);
     return SPHX_OK;
 }
 

@@ -108,3 +108,23 @@ def test_fof_small_leaves_and_repeat():
     for a, c in zip(g1, g2):
         np.testing.assert_array_equal(a, c)
     np.testing.assert_array_equal(g1[0], ref)
+
+
+def test_fof_without_sizes_or_counts():
+    # group_size and d_counts may be NULL: the library counts into its own
+    # workspace and writes the groups alone
+    import ctypes as C
+    import torch
+    from paper_2305_13380_amd import sphx
+    ps = inputs.lognormal_box(16, 6000, 2.0, 11)
+    b = 0.5 * sep(ps)
+    ctx = sphx.Context(sphx.default_params(), 0)
+    dp = sphx.DeviceParticles.from_set(ps, "cuda:0")
+    group = torch.full((ps.n,), -1, dtype=torch.int32, device="cuda:0")
+    pv = dp.view()
+    st = sphx.lib.sphx_fof(ctx.handle, C.byref(pv), b, C.c_void_p(group.data_ptr()), None, None,
+                           C.c_void_p(torch.cuda.current_stream().cuda_stream))
+    torch.cuda.synchronize()
+    assert st == 0
+    ref, _ = oracle.fof(ps, b, mode="auto")
+    np.testing.assert_array_equal(group.cpu().numpy(), ref)
