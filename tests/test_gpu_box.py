@@ -62,3 +62,32 @@ def test_box_fof_and_gravity():
     torch.cuda.synchronize()
     a = np.stack([ax.cpu().numpy(), ay.cpu().numpy(), az.cpu().numpy()], 1)
     check(ps, a, pot.cpu().numpy(), 1.0, 0.5 * sep, 1.25 * sep, 1.5 * sep, "box gravity")
+
+
+def test_fof_and_gravity_ignore_h_and_active():
+    # h may be NULL and the active mask does not matter: every particle links
+    # and receives
+    import ctypes as C
+    import torch
+    from paper_2305_13380_amd import sphx
+    ps = inputs.lognormal_box(16, 5000, 2.0, 8)
+    sep = (1.0 / ps.n) ** (1.0 / 3.0)
+    ctx = sphx.Context(sphx.default_params(), 0)
+    dp = sphx.DeviceParticles.from_set(ps, "cuda:0")
+    g0, _, c0 = sphx.fof(ctx, dp, 0.5 * sep)
+    a0 = sphx.gravity(ctx, dp, 1.0, 0.5 * sep, 1.25 * sep, 1.5 * sep)
+    dp.t["active"] = torch.from_numpy((np.arange(ps.n) % 7 == 0).astype(np.uint8)).cuda()
+    pv = dp.view()
+    pv.h = None
+    stream = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    g1 = torch.empty(ps.n, dtype=torch.int32, device="cuda:0")
+    c1 = torch.empty(2, dtype=torch.int64, device="cuda:0")
+    assert sphx.lib.sphx_fof(ctx.handle, C.byref(pv), 0.5 * sep, C.c_void_p(g1.data_ptr()), None,
+                             C.c_void_p(c1.data_ptr()), stream) == 0
+    a1 = [torch.empty(ps.n, dtype=torch.float32, device="cuda:0") for _ in range(4)]
+    assert sphx.lib.sphx_gravity(ctx.handle, C.byref(pv), 1.0, 0.5 * sep, 1.25 * sep, 1.5 * sep,
+                                 *[C.c_void_p(t.data_ptr()) for t in a1], None, stream) == 0
+    torch.cuda.synchronize()
+    assert torch.equal(g0, g1) and torch.equal(c0, c1)
+    for x, y in zip(a0, a1):
+        assert torch.equal(x, y)
