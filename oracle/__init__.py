@@ -84,6 +84,8 @@ def lib():
                                  + [C.c_int64, _nullable(_ip), _nullable(_ip), _nullable(_ip)]
                                  + [_dp] * 5)
         L.or_gravity.restype = C.c_int64
+        L.or_alpha_v_update.argtypes = ([C.c_int64] + [_dp] * 5 + [C.c_double] * 4 + [_dp])
+        L.or_alpha_v_update.restype = None
         _LIB = L
     return _LIB
 
@@ -552,3 +554,21 @@ def gravity(ps, G, H, rs, rp2p, periodic=True, recv=None, mode="auto"):
                              out["ay"], out["az"], out["pot"], out["scale"])
     out["pairs"] = int(total)
     return out
+
+
+# ---------------------------------------------------------------------------
+# SPHENIX viscosity switch (Section 3.3).
+# ---------------------------------------------------------------------------
+
+SPHENIX_ALPHA_V_MAX = 2.0   # Section 3.3: maximal viscosity parameter
+SPHENIX_ELL = 0.05          # Section 3.3: viscosity decay length
+
+
+def alpha_v_update(alpha, div_old, div_new, c, h, vsig, dt, params: Params,
+                   alpha_max=SPHENIX_ALPHA_V_MAX, ell=SPHENIX_ELL):
+    """New alpha_V of every particle after a step dt (or_alpha_v_update)."""
+    a = _f64(alpha).copy()
+    n = a.shape[0]
+    lib().or_alpha_v_update(n, _f64(div_old), _f64(div_new), _f64(c), _f64(h), _f64(vsig),
+                            float(dt), float(params.gamma_k), float(alpha_max), float(ell), a)
+    return a

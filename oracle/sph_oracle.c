@@ -575,3 +575,32 @@ int64_t or_gravity(int64_t n, const double *x, const double *y, const double *z,
     }
     return total;
 }
+
+/*
+ * SPHENIX viscosity switch (Section 3.3): the time derivative of the
+ * velocity divergence from the values at the start and end of the step,
+ *   Ddiv = (div_new - div_old) / dt,
+ * the shock indicator S = H^2 max(0, -Ddiv) with H = gamma_k h, the local
+ * target alpha_loc = alpha_max S / (v_sig^2 + S) (0 where S = 0), then
+ *   alpha_new = alpha_loc                                   if alpha_loc > alpha,
+ *   alpha_new = alpha_loc + (alpha - alpha_loc) exp(-ell c dt / H)   otherwise:
+ * an immediate rise at a shock and an exponential decay towards alpha_loc
+ * on the time scale H / (ell c) (the reading of the printed update, which
+ * as typeset would lower alpha the more the larger alpha_loc is).
+ * alpha is updated in place.
+ */
+void or_alpha_v_update(int64_t n, const double *div_old, const double *div_new, const double *c,
+                       const double *h, const double *vsig, double dt, double gamma_k,
+                       double alpha_max, double ell, double *alpha)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        double H = gamma_k * h[i];
+        double ddiv = (div_new[i] - div_old[i]) / dt;
+        double S = H * H * (ddiv < 0.0 ? -ddiv : 0.0);
+        double loc = S > 0.0 ? alpha_max * S / (vsig[i] * vsig[i] + S) : 0.0;
+        if (loc > alpha[i])
+            alpha[i] = loc;
+        else
+            alpha[i] = loc + (alpha[i] - loc) * exp(-ell * c[i] * dt / H);
+    }
+}
