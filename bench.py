@@ -261,6 +261,32 @@ def gravity_bench(params, dp, reps):
     return rec
 
 
+def switch_bench(params, n, reps=200):
+    """The SPHENIX viscosity switch over n particles (sphx_alpha_v_update),
+    inputs resident in HBM: reps launches timed with events on the stream they
+    run on; 28 bytes per particle (six FP32 words read, one written)."""
+    import torch
+    from paper_2305_13380_amd import sphx
+    ctx = sphx.Context(params, 0)
+    g = torch.Generator(device="cuda:0").manual_seed(7)
+    t = [torch.rand(n, device="cuda:0", generator=g) for _ in range(6)]
+    sphx.alpha_v_update(ctx, t[0], t[1], t[2], t[3], t[4], t[5], 1e-3)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        sphx.alpha_v_update(ctx, t[0], t[1], t[2], t[3], t[4], t[5], 1e-3)
+    b.record()
+    torch.cuda.synchronize()
+    per = a.elapsed_time(b) / reps / 1e3
+    ctx.close()
+    rec = {"particles": n, "us_per_launch": per * 1e6, "bytes_per_particle": 28,
+           "GB_per_s": 28.0 * n / per / 1e9, "of_hbm_peak": 28.0 * n / per / 1e9 / PEAK_HBM_GBS,
+           "reps": reps, "timed": "back-to-back launches, events on the launch stream"}
+    log("bench: viscosity switch: %s" % json.dumps(rec))
+    return rec
+
+
 def measured_traffic(config, kernel):
     """HBM bytes per launch of `kernel` from the committed counter summary
     (profiles/traffic_<config>.json: FETCH_SIZE and WRITE_SIZE scaled by a
@@ -550,6 +576,7 @@ def main():
         line["fof"] = fof_bench(params, dp, args.fof_reps)
     if not args.no_gravity:
         line["gravity"] = gravity_bench(params, dp, args.fof_reps)
+        line["viscosity_switch"] = switch_bench(params, dp.n)
     if not args.no_serving:
         sv = serving_bench(args.serving_slots, args.serving_requests)
         line["serving"] = sv

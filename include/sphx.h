@@ -344,6 +344,21 @@ sphx_status sphx_gravity(sphx_ctx *ctx, const sphx_particles *in, double G, doub
                          double r_s, double r_p2p, float *ax, float *ay, float *az, float *pot,
                          int64_t *d_pairs, void *stream);
 
+/* SPHENIX viscosity switch (Section 3.3), per particle i < n (caller order,
+ * device FP32 arrays of n): from the velocity divergence at the start and at
+ * the end of a step of length dt (div_old, div_new, e.g. sphx_ghost_out.div_v
+ * of two steps), the shock indicator S = H^2 max(0, -(div_new - div_old)/dt)
+ * with H = gamma_k h, and the target alpha_loc = 2 S / (v_sig^2 + S) (0 where
+ * S = 0; alpha_max = 2), alpha_v becomes alpha_loc if that is larger, else
+ * alpha_loc + (alpha_v - alpha_loc) exp(-0.05 c dt / H) (decay length 0.05;
+ * the printed update is read as this decay towards the target). alpha_v is
+ * read and written in place; c is the sound speed (sphx_ghost_out.c), h the
+ * smoothing length, v_sig the signal velocity (sphx_force_out.v_sig).
+ * dt > 0 and finite, n >= 0, else E_INVALID. Asynchronous on `stream`. */
+sphx_status sphx_alpha_v_update(sphx_ctx *ctx, int64_t n, const float *div_old,
+                                const float *div_new, const float *c, const float *h,
+                                const float *v_sig, double dt, float *alpha_v, void *stream);
+
 /* Kernel timing for measurement tools. sphx_profile_enable(ctx, 1) clears the
  * statistics and starts recording a pair of HIP events around every launch of
  * the cell-pair density kernel (kernel 0), the force kernel (kernel 1), the

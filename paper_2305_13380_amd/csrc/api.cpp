@@ -283,6 +283,22 @@ sphx_status sphx_tasks_build(sphx_ctx *ctx, sphx_grid *grid, const sphx_particle
 
 void sphx_tasks_destroy(sphx_tasks *tasks) { tasks_free(tasks); }
 
+sphx_status sphx_alpha_v_update(sphx_ctx *ctx, int64_t n, const float *div_old,
+                                const float *div_new, const float *c, const float *h,
+                                const float *v_sig, double dt, float *alpha_v, void *stream)
+{
+    if (!ctx || n < 0 || !(dt > 0.0) || !std::isfinite(dt)) {
+        set_error("sphx_alpha_v_update: need a context, n >= 0 and a finite dt > 0");
+        return SPHX_E_INVALID;
+    }
+    if (n > 0 && (!div_old || !div_new || !c || !h || !v_sig || !alpha_v)) {
+        set_error("sphx_alpha_v_update: NULL array");
+        return SPHX_E_INVALID;
+    }
+    SPHX_HIP(hipSetDevice(ctx->device));
+    return alpha_v_launch(ctx, n, div_old, div_new, c, h, v_sig, dt, alpha_v, as_stream(stream));
+}
+
 sphx_status sphx_gravity(sphx_ctx *ctx, const sphx_particles *in, double G, double H,
                          double r_s, double r_p2p, float *ax, float *ay, float *az, float *pot,
                          int64_t *d_pairs, void *stream)

@@ -1,0 +1,46 @@
+// SPHENIX viscosity switch (Section 3.3), one particle per thread: the
+// change of the velocity divergence over the step gives the shock indicator
+// S = H^2 max(0, -d(div v)/dt), H = gamma_k h, and the target
+// alpha_loc = alpha_max S / (v_sig^2 + S); alpha rises to the target at once
+// and otherwise decays towards it as exp(-ell c dt / H). Streams seven FP32
+// words per particle (six read, one written): bound by HBM bandwidth.
+#include "sphx_internal.h"
+
+namespace sphx {
+namespace {
+
+constexpr int kSwitchThreads = 256;
+
+__global__ __launch_bounds__(kSwitchThreads) void k_alpha_v(
+    int64_t n, const float *__restrict__ div_old, const float *__restrict__ div_new,
+    const float *__restrict__ c, const float *__restrict__ h, const float *__restrict__ vsig,
+    float dt, float gamma_k, float alpha_max, float ell, float *__restrict__ alpha)
+{
+    const int64_t i = int64_t(blockIdx.x) * kSwitchThreads + threadIdx.x;
+    if (i >= n)
+        return;
+    const float H = gamma_k * h[i];
+    const float ddiv = (div_new[i] - div_old[i]) / dt;
+    const float S = H * H * fmaxf(-ddiv, 0.0f);
+    const float vs = vsig[i];
+    const float loc = S > 0.0f ? alpha_max * S / (vs * vs + S) : 0.0f;
+    const float a = alpha[i];
+    alpha[i] = loc > a ? loc : loc + (a - loc) * expf(-ell * c[i] * dt / H);
+}
+
+}  // namespace
+
+sphx_status alpha_v_launch(const sphx_ctx *ctx, int64_t n, const float *div_old,
+                           const float *div_new, const float *c, const float *h,
+                           const float *vsig, double dt, float *alpha, hipStream_t s)
+{
+    if (n == 0)
+        return SPHX_OK;
+    const unsigned nb = unsigned((n + kSwitchThreads - 1) / kSwitchThreads);
+    k_alpha_v<<<nb, kSwitchThreads, 0, s>>>(n, div_old, div_new, c, h, vsig, float(dt),
+                                            float(ctx->p.gamma_k), 2.0f, 0.05f, alpha);
+    SPHX_HIP(hipGetLastError());
+    return SPHX_OK;
+}
+
+}  // namespace sphx

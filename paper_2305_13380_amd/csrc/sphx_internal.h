@@ -231,6 +231,10 @@ struct SearchCells {
 };
 sphx_status search_cells_build(sphx_ctx *ctx, const sphx_particles *in, double radius,
                                hipStream_t s, SearchCells &sc);
+// SPHENIX viscosity switch update, elementwise (alpha_max 2, ell 0.05).
+sphx_status alpha_v_launch(const sphx_ctx *ctx, int64_t n, const float *div_old,
+                           const float *div_new, const float *c, const float *h,
+                           const float *vsig, double dt, float *alpha, hipStream_t s);
 // Short-range softened gravity over a grid and tasks built at radius rp2p.
 sphx_status gravity_run(sphx_ctx *ctx, const sphx_particles *in, double G, double H, double rs,
                         double rp2p, float *ax, float *ay, float *az, float *pot,

@@ -77,7 +77,7 @@ SYMBOLS = ("sphx_params_default", "sphx_ctx_create", "sphx_ctx_destroy", "sphx_w
            "sphx_iter_reset", "sphx_density", "sphx_ghost", "sphx_force", "sphx_step",
            "sphx_grid_leaves", "sphx_tasks_count", "sphx_last_error", "sphx_profile_enable",
            "sphx_profile_read", "sphx_autotune", "sphx_params_set_kernel", "sphx_fof",
-           "sphx_gravity")
+           "sphx_gravity", "sphx_alpha_v_update")
 
 _LIB = None
 
@@ -104,6 +104,8 @@ def _load():
     L.sphx_fof.restype = i32
     L.sphx_gravity.argtypes = [vp, P(Particles)] + [C.c_double] * 4 + [vp] * 6
     L.sphx_gravity.restype = i32
+    L.sphx_alpha_v_update.argtypes = [vp, i64] + [vp] * 5 + [C.c_double, vp, vp]
+    L.sphx_alpha_v_update.restype = i32
     L.sphx_params_default.restype = None
     L.sphx_ctx_create.argtypes = [P(Params), C.c_int, P(vp)]
     L.sphx_ctx_destroy.argtypes = [vp]
@@ -405,6 +407,15 @@ def gravity(ctx, parts, G, H, r_s, r_p2p, potential=True, pairs=None, stream=Non
                             float(r_p2p), _ptr(a[0]), _ptr(a[1]), _ptr(a[2]), _ptr(pot),
                             _ptr(pairs), _stream(stream)))
     return a[0], a[1], a[2], pot
+
+
+def alpha_v_update(ctx, alpha_v, div_old, div_new, c, h, v_sig, dt, stream=None):
+    """SPHENIX viscosity switch (sphx_alpha_v_update): updates the FP32
+    device tensor alpha_v in place."""
+    _check(lib.sphx_alpha_v_update(ctx.handle, int(alpha_v.numel()), _ptr(div_old),
+                                   _ptr(div_new), _ptr(c), _ptr(h), _ptr(v_sig), float(dt),
+                                   _ptr(alpha_v), _stream(stream)))
+    return alpha_v
 
 
 def autotune(ctx, grid, tasks, parts, out: Outputs, reps=3, stream=None) -> Params:
