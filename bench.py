@@ -41,9 +41,10 @@ KERNEL_FLOP_FORCE_END = {"wendland_c2": 4, "wendland_c4": 8, "wendland_c6": 11,
                          "cubic_spline": 6, "quartic_spline": 13, "quintic_spline": 16}
 # FP32 FLOPs per summed pair of the truncated gravity loop, as evaluated:
 # separation and r^2 8, rsqrt and r 2, u and u^2 2, f and g by Horner 18, the
-# two branches 4, erfc and exp 2 (one each), their arguments and chi'/r 5,
-# the combination 3, the three accelerations 7, the potential 3.
-FLOP_GRAVITY = 54
+# two branches 4, x, x^2 and exp 3, t = 1/(1 + p x) 3, the erfc polynomial 9,
+# chi 1, chi'/r 2, the combination 3, the three accelerations 7, the
+# potential 3.
+FLOP_GRAVITY = 65
 KERNEL_NAMES = {"wendland_c2": "Wendland C2", "wendland_c4": "Wendland C4",
                 "wendland_c6": "Wendland C6", "cubic_spline": "cubic spline",
                 "quartic_spline": "quartic spline", "quintic_spline": "quintic spline"}

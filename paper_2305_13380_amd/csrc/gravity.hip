@@ -6,7 +6,8 @@
 //               f(u) = -3u^7 + 15u^6 - 28u^5 + 21u^4 - 7u^2 + 3;
 //   phi'(r)/r = g(r/H) / H^3 inside, -1/r^3 beyond,
 //               g(u) = f'(u)/u = -21u^5 + 90u^4 - 140u^3 + 84u^2 - 14;
-//   chi(r)    = erfc(r / (2 r_s)), chi'(r) = -exp(-r^2/(4 r_s^2)) / (sqrt(pi) r_s);
+//   chi(r)    = erfc(r / (2 r_s)), chi'(r) = -exp(-r^2/(4 r_s^2)) / (sqrt(pi) r_s)
+//               (erfc by the rational approximation the paper names);
 //   a_i      += G m_j x_ij [phi' chi + phi chi'] / r,  pot_i -= G m_j phi chi,
 // over j != i with r_ij < r_p2p. One wave per receiving leaf, one receiver
 // per lane; each task's sources are staged in LDS in the receiver cell's
@@ -90,8 +91,19 @@ __global__ __launch_bounds__(64) void k_gravity(int64_t n_leaves,
             const float dphir = in ? g * invH3 : -(rinv * rinv * rinv);
             float chi = 1.0f, k_r = dphir;
             if (TRUNC) {
-                chi = erfcf(r * inv2rs);
-                const float dchir = -cdchi * expf(-(r2 * inv2rs * inv2rs)) * rinv;
+                // erfc(x), x = r / (2 r_s), by the rational approximation
+                // 7.1.26 of Abramowitz & Stegun (absolute error below
+                // 1.5e-7), the one the paper's solver uses: a polynomial in
+                // t = 1 / (1 + p x) times exp(-x^2), the factor chi' needs too
+                const float x = r * inv2rs;
+                const float e = expf(-(x * x));
+                const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, x, 1.0f));
+                const float poly =
+                    t * (0.254829592f +
+                         t * (-0.284496736f +
+                              t * (1.421413741f + t * (-1.453152027f + t * 1.061405429f))));
+                chi = poly * e;
+                const float dchir = -cdchi * e * rinv;
                 k_r = dphir * chi + phi * dchir;
             }
             const float mk = on ? p.w * k_r : 0.0f;
