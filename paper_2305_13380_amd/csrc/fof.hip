@@ -51,8 +51,8 @@ __device__ int32_t find_root(int32_t *parent, int32_t i)
 
 // Merge the sets of a and b: the larger root is hung under the smaller by a
 // compare-and-swap that succeeds only while it is still a root. A failed swap
-// means that root was hung under a smaller index meanwhile; the next round
-// starts from there, so the roots only decrease and the loop ends.
+// means that root was hung under a smaller index meanwhile; the loop goes
+// on from there, so the roots only decrease and the loop ends.
 __device__ void unite(int32_t *parent, int32_t a, int32_t b)
 {
     for (;;) {
