@@ -288,6 +288,44 @@ def switch_bench(params, n, reps=200):
     return rec
 
 
+def oracle_beside(ps, fof_rec, grav_rec, sw_rec, n_recv=2048, seed=0):
+    """The oracle timed on the host for the rows beyond the step, on the same
+    workload: friends-of-friends of the whole box (k-d tree candidates,
+    sequential union-find), short-range gravity for a random sample of
+    receivers (all their pairs, FP64), and the viscosity switch of every
+    particle. Threads as the oracle uses them (OpenMP in the gravity sum)."""
+    import numpy as np
+    import oracle
+    out = {}
+    if fof_rec is not None:
+        t0 = time.perf_counter()
+        _, links = oracle.fof(ps, fof_rec["link_length"], mode="tree")
+        t = time.perf_counter() - t0
+        out["fof"] = {"particles_per_s": ps.n / t, "s": t, "links": links, "kind": "oracle",
+                      "sample": "the whole box"}
+    if grav_rec is not None:
+        recv = np.sort(np.random.default_rng(seed).choice(ps.n, size=min(n_recv, ps.n),
+                                                          replace=False))
+        oracle.gravity(ps, 1.0, grav_rec["H"], grav_rec["r_s"], grav_rec["r_p2p"],
+                       recv=recv[:16], mode="tree")  # the k-d tree, built once
+        t0 = time.perf_counter()
+        o = oracle.gravity(ps, 1.0, grav_rec["H"], grav_rec["r_s"], grav_rec["r_p2p"],
+                           recv=recv, mode="tree")
+        t = time.perf_counter() - t0
+        out["gravity"] = {"pairs_per_s": o["pairs"] / t, "s": t, "pairs": o["pairs"],
+                          "kind": "oracle", "sample": "%d random receivers" % len(recv)}
+    if sw_rec is not None:
+        rng = np.random.default_rng(seed)
+        a = [rng.random(ps.n) for _ in range(6)]
+        t0 = time.perf_counter()
+        oracle.alpha_v_update(a[0], a[1], a[2], a[3], a[4], a[5], 1e-3, oracle.Params())
+        t = time.perf_counter() - t0
+        out["viscosity_switch"] = {"particles_per_s": ps.n / t, "s": t, "kind": "oracle",
+                                   "sample": "every particle"}
+    log("bench: oracle beside the other rows: %s" % json.dumps(out))
+    return out
+
+
 def measured_traffic(config, kernel):
     """HBM bytes per launch of `kernel` from the committed counter summary
     (profiles/traffic_<config>.json: FETCH_SIZE and WRITE_SIZE scaled by a
@@ -588,6 +626,8 @@ def main():
         import oracle
         line["cpu_baseline"] = cpu_baseline(
             ps, lambda: oracle.Params.with_kernel(args.kernel), args.cpu_receivers)
+        line["cpu_oracle_other_rows"] = oracle_beside(
+            ps, line.get("fof"), line.get("gravity"), line.get("viscosity_switch"))
     print(json.dumps(line), flush=True)
 
 
