@@ -184,6 +184,11 @@ __global__ void k_fof_label(int64_t n, const int32_t *__restrict__ perm,
         atomicAdd(groups, 1ull);
 }
 
+// Walks to the root again rather than trusting a pointer written in the
+// label pass: the path halving of another thread's walk there may read a
+// particle's old parent before the particle points at its root and write an
+// older ancestor over it afterwards (tried; one particle of 20,000 lost its
+// group).
 __global__ void k_fof_out(int64_t n, const int32_t *__restrict__ perm,
                           int32_t *__restrict__ parent, const int32_t *__restrict__ minc,
                           const int32_t *__restrict__ size, int32_t *__restrict__ group,
