@@ -38,6 +38,17 @@
  *    conserve momentum and energy exactly.
  *  - conduction: scalar radial gradient G_ij, v_c uses rho_i + rho_j.
  *  - force neighbours: j != i with r_ij < max(H_i, H_j).
+ *  - friends-of-friends (Section 9.1): linked iff the minimum-image squared
+ *    distance, formed in FP64 as (dx dx + dy dy) + dz dz, is below b^2; a
+ *    group is named by its smallest index.
+ *  - short-range gravity (Sections 4.1 and 4.4): the truncated potential is
+ *    the product of the softened potential and erfc(r / 2 r_s), the force
+ *    its exact gradient; the printed outer force branch r^-3 is read as the
+ *    magnitude of -x/r^3.
+ *  - SPHENIX viscosity switch (Section 3.3): the printed update is garbled;
+ *    it is read as a rise to the target and an exponential decay towards
+ *    it. The pins fix this reading's own properties; its agreement with the
+ *    printed equation is parity unpinned.
  */
 #include <math.h>
 #include <stddef.h>
