@@ -148,6 +148,80 @@ def test_large_active_full_size_fixed_h():
     check_force(gs, ref, sub, h, recv, P, where)
 
 
+def _region(ps, h, cube_half, centre=0.5):
+    """Particles that the fixed-h results of receivers inside the central cube
+    depend on. With d_k the L-infinity distance of particle k from the cube
+    (a lower bound of its distance from any receiver): a force neighbour j
+    of a receiver has d_j < max(H_cube, H_j), and the state of such a j
+    depends on particles within H_j of it, so at L-infinity distance below
+    d_j + H_j. Returns that set (ascending) and the mask of the cube."""
+    H = P.gamma_k * np.asarray(h, np.float64)
+    dist = np.max(np.abs(ps.positions() - centre), axis=1) - cube_half
+    inner = dist < 0
+    Hc = float(H[inner].max())
+    near = dist < np.maximum(Hc, H)
+    M = float((np.maximum(dist[near], 0.0) + H[near]).max()) * (1 + 1e-6)
+    assert cube_half + M < 0.45, "region wraps the box"
+    return np.nonzero(dist < M)[0], inner
+
+
+def test_large_active_full_size_step():
+    """The 16.8M-particle box with ~10% active, as bench.py times it: an
+    all-active step gives every particle its state, the active particles
+    restart from the generator's h, and the active-only step iterates them
+    (task rebuilds included). Sampled active receivers: h against the
+    oracle's own solve from the same start, and every density, ghost and
+    force output against the oracle evaluated at the step's own h (inactive
+    sources at the h the first step left them)."""
+    import torch
+    from paper_2305_13380_amd import sphx
+    where = "large 256^3 active step"
+    t0 = time.time()
+    ps = inputs.config_large(5)
+    log("%s: generated N=%d, active %d (%.1f s)" % (where, ps.n, int(ps.active.sum()),
+                                                   time.time() - t0))
+    ctx = sphx.Context()
+    all_on = ps.copy()
+    all_on.active = None
+    dp = sphx.DeviceParticles.from_set(all_on)
+    out = sphx.Outputs(ps.n)
+    grid = sphx.Grid(ctx, dp)
+    tasks = sphx.Tasks(ctx, grid, dp)
+    st, info = sphx.step(ctx, grid, tasks, dp, out)
+    assert st >= 0 and info.unconverged == 0
+    act_t = torch.from_numpy(ps.active).cuda()
+    dp.t["active"] = act_t
+    h_guess = torch.from_numpy(ps.h).cuda()
+    dp.t["h"].copy_(torch.where(act_t.bool(), h_guess, dp.t["h"]))
+    st, info = sphx.step(ctx, grid, tasks, dp, out)
+    torch.cuda.synchronize()
+    log("%s: GPU steps done, active step passes=%d rebuilds=%d (%.1f s)" % (
+        where, info.passes, info.task_rebuilds, time.time() - t0))
+    assert st >= 0 and info.unconverged == 0
+    g = {k: v.cpu().numpy() for k, v in {**out.d, **out.g, **out.f}.items()}
+    h_all = dp.t["h"].cpu().numpy().astype(np.float64)
+    region, inner = _region(ps, h_all, 0.03)
+    cand = np.nonzero(inner & (ps.active == 1))[0]
+    recv_full = np.sort(np.random.default_rng(16).choice(cand, size=min(512, cand.size),
+                                                          replace=False))
+    sub = ps.subset(region)
+    recv = np.searchsorted(region, recv_full)
+    hs = h_all[region]
+    log("%s: %d receivers, %d particles in region" % (where, len(recv), len(region)))
+    # h: the oracle's own solve from the generator's h (its receivers' sums
+    # depend only on particles within their H, all inside the region)
+    hr, dens, conv, _, _ = oracle.solve_h(sub, P, recv=recv, mode="tree")
+    assert conv.all()
+    dh = np.abs(hs[recv] - hr) / hr
+    assert np.all(dh <= 2 * P.h_tol), "%s h: worst %.3g" % (where, dh.max())
+    ref = oracle.fixed_h_step(sub, P, recv=recv, mode="tree", h=hs)
+    log("%s: oracle done, max |dh|/h = %.2e (%.1f s)" % (where, dh.max(), time.time() - t0))
+    gs = {k: v[region] for k, v in g.items()}
+    check_density(gs, ref, sub, hs, recv, P, where + " at its h")
+    check_ghost(gs, ref, recv, where + " at its h")
+    check_force(gs, ref, sub, hs, recv, P, where + " at its h")
+
+
 def test_clustered_full_size_fof():
     """Friends-of-friends groups of the whole 2,097,152-particle clustered box
     at 0.2 of the mean separation, bit for bit against the oracle (k-d tree

@@ -144,3 +144,13 @@ def test_conservation_sums_fp64():
     np.testing.assert_allclose(s[3], e, rtol=1e-9, atol=1e-12 * (s[4] + s[5]))
     # pairwise-antisymmetric forces: net momentum at FP32 round-off of the terms
     assert np.abs(s[:3]).max() < 1e-5 * s[4]
+    # the oracle's own FP64 sums of the same outputs
+    s_ref = oracle.sums(ps.m, ps.vx, ps.vy, ps.vz, g["ax"], g["ay"], g["az"], g["du_dt"])
+    np.testing.assert_allclose(s, s_ref, rtol=1e-12, atol=1e-12 * (s_ref[4] + s_ref[5]))
+    # and the sums of the oracle's forces: each at the force tolerance of its
+    # scale (the net momentum and energy are ~0 on both sides)
+    ref = oracle.fixed_h_step(ps, P)
+    s_or = oracle.sums(ps.m, ps.vx, ps.vy, ps.vz, ref["ax"], ref["ay"], ref["az"], ref["du"])
+    assert np.abs(s[:3] - s_or[:3]).max() <= 1e-4 * s_or[4]
+    assert abs(s[3] - s_or[3]) <= 1e-4 * (s_or[4] + s_or[5])
+    np.testing.assert_allclose(s[4:], s_or[4:], rtol=1e-4)

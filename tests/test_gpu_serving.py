@@ -5,8 +5,9 @@ overlap on the device, each on its own stream and grid.
 * a tiny HBM budget makes requests wait (never an out-of-memory failure), and
   a request larger than the budget is rejected with a message;
 * latencies are completion minus arrival, and the percentiles are ordered;
-* the smallest lattice and the smallest lognormal request agree with the
-  oracle's own smoothing-length solve.
+* the two smallest lattice and lognormal requests agree with the oracle's
+  own smoothing-length solve, and every output and the FP64 sums with the
+  oracle at the request's own final h.
 """
 import numpy as np
 import pytest
@@ -83,13 +84,17 @@ def test_latency_accounting(served):
     assert 0 < q["p50_s"] <= q["p99_s"] <= q["max_s"]
 
 
+@pytest.mark.parametrize("rank", [0, 1])
 @pytest.mark.parametrize("geometry", ["lattice", "lognormal"])
-def test_smallest_request_matches_oracle(served, geometry):
-    """The smallest request of each geometry against the oracle's h solve."""
-    from helpers import RHO_TOL
+def test_small_requests_match_oracle(served, geometry, rank):
+    """The smallest and second-smallest request of each geometry: h against
+    the oracle's own solve, then every density, ghost and force output of
+    the served step against the oracle evaluated at the step's own h."""
+    from helpers import RHO_TOL, check_density, check_force, check_ghost
     reqs = served["reqs"]
-    ks = [k for k, r in enumerate(reqs) if r.name.endswith(geometry)]
-    k = min(ks, key=lambda k: reqs[k].n)
+    ks = sorted((k for k, r in enumerate(reqs) if r.name.endswith(geometry)),
+                key=lambda k: reqs[k].n)
+    k = ks[rank]
     ps, g = reqs[k], served["mix"][k].outputs
     log("serving: oracle check of request %d (%s, N=%d)" % (k, geometry, ps.n))
     hr, dens, conv, _, _ = oracle.solve_h(ps, P)
@@ -100,6 +105,14 @@ def test_smallest_request_matches_oracle(served, geometry):
     sens = np.abs(hr * dens["rho_dh"] / dens["rho"])
     rho = g["rho"].astype(np.float64)
     assert np.all(np.abs(rho - dens["rho"]) <= (RHO_TOL + 1.5 * sens * dh) * dens["rho"])
+    ref = oracle.fixed_h_step(ps, P, h=hg)
+    recv = np.arange(ps.n)
+    where = "served request %d at its h" % k
+    check_density(g, ref, ps, hg, recv, P, where)
+    check_ghost(g, ref, recv, where)
+    check_force(g, ref, ps, hg, recv, P, where)
+    s_ref = oracle.sums(ps.m, ps.vx, ps.vy, ps.vz, g["ax"], g["ay"], g["az"], g["du_dt"])
+    np.testing.assert_allclose(g["sums"], s_ref, rtol=1e-12, atol=1e-12 * (s_ref[4] + s_ref[5]))
 
 
 def test_tiny_budget_queues_and_rejects():

@@ -159,7 +159,11 @@ def test_h_max_clamp_is_reported():
 
 def test_active_subset_step():
     """Only active particles receive; inactive ones act as sources with the
-    state of a previous all-active step (time-step bins)."""
+    state of a previous all-active step (time-step bins). The active
+    receivers' h is checked against the oracle's own solve, and every output
+    of the active step against the oracle evaluated at the step's own h, at
+    the fixed-h tolerances: the receivers at their final h with the new u,
+    the inactive sources at their step-1 h with the step-1 u."""
     import torch
     from paper_2305_13380_amd import sphx
     ps = inputs.lognormal_box(16, 5000, 2.0, 21, time_bins=(0.1, 0.2, 0.3, 0.4))
@@ -171,8 +175,10 @@ def test_active_subset_step():
     out = sphx.Outputs(ps.n)
     grid = sphx.Grid(ctx, dp)
     tasks = sphx.Tasks(ctx, grid, dp)
-    sphx.step(ctx, grid, tasks, dp, out)
+    st1, _ = sphx.step(ctx, grid, tasks, dp, out)
+    assert st1 >= 0
     h1 = dp.t["h"].cpu().numpy()
+    step1 = {k: v.cpu().numpy() for k, v in {**out.d, **out.g, **out.f}.items()}
     # second step with the activity mask, same device arrays (h carried over)
     dp.t["active"] = torch.from_numpy(ps.active).cuda()
     q = ps.copy()
@@ -183,35 +189,35 @@ def test_active_subset_step():
     tasks2 = sphx.Tasks(ctx, grid2, dp)
     st, info = sphx.step(ctx, grid2, tasks2, dp, out)
     torch.cuda.synchronize()
+    assert st >= 0 and info.unconverged == 0
     g = {k: v.cpu().numpy() for k, v in {**out.d, **out.g, **out.f}.items()}
-    # oracle: step 1 on everything, then the active receivers with the
-    # inactive sources' step-1 state
-    r1 = oracle.nr_step(all_on, P, mode="tree")
+    hg = dp.t["h"].cpu().numpy().astype(np.float64)
     ridx = np.nonzero(act)[0]
-    q.h = r1["h"].copy()
-    h2, d2, conv, _, _ = oracle.solve_h(q, P, recv=ridx, mode="tree", h0=r1["h"])
-    hfull = r1["h"].copy()
-    hfull[ridx] = h2
-    gst2 = oracle.ghost(d2, q.u[ridx], h2, P)
-    state = {k: r1[k].copy() for k in ("P", "c", "f", "balsara")}
-    rho = r1["rho"].copy()
+    assert np.array_equal(hg[~act], h1[~act])  # inactive h untouched
+    for k in g:  # and so are the inactive particles' outputs
+        assert np.array_equal(g[k][~act], step1[k][~act]), k
+    # the receivers' h against the oracle's own solve from the same start
+    h2, _, conv, _, _ = oracle.solve_h(q, P, recv=ridx, mode="tree", h0=h1)
+    assert conv.all()
+    assert np.all(np.abs(hg[ridx] - h2) <= 2 * P.h_tol * h2)
+    # the oracle at the step's own h: inactive sources' state at h1 with the
+    # step-1 u (they kept it), the receivers' at their final h with the new u
+    s1 = oracle.fixed_h_step(ps, P, h=h1.astype(np.float64), mode="tree")
+    d2 = oracle.density(q, hg, P, recv=ridx, mode="tree")
+    g2 = oracle.ghost(d2, q.u[ridx], hg[ridx], P)
+    state = {k: s1[k].copy() for k in ("P", "c", "f", "balsara")}
+    rho = s1["rho"].copy()
     rho[ridx] = d2["rho"]
     for k in state:
-        state[k][ridx] = gst2[k]
-    # inactive sources carry their step-1 pressure, built from step-1 u
-    fo = oracle.force(q, hfull, state, rho, P, recv=ridx, mode="tree")
-    hg = dp.t["h"].cpu().numpy().astype(np.float64)
-    assert np.all(np.abs(hg[ridx] - h2) <= 2 * P.h_tol * h2)
-    assert np.array_equal(hg[~act], h1[~act])  # inactive h untouched
-    a = np.stack([g[k][ridx] for k in ("ax", "ay", "az")], 1).astype(np.float64)
-    b = np.stack([fo[k] for k in ("ax", "ay", "az")], 1)
-    nb = np.linalg.norm(b, axis=1)
-    err = np.linalg.norm(a - b, axis=1) / np.maximum(nb, rms(nb))
-    # first-order h effect: the receivers' h and, through H_j, f_j and A_j, the
-    # sources' h (step 1 on both sides, each converged to 1e-4 on its own)
-    dmax = max((np.abs(hg[ridx] - h2) / h2).max(),
-               (np.abs(h1.astype(np.float64) - r1["h"]) / r1["h"]).max())
-    assert err.max() <= 1e-4 + 50 * dmax, "active accel worst %.3g" % err.max()
+        state[k][ridx] = g2[k]
+    # conduction reads every particle's u from the grid (the new u)
+    fo = oracle.force(q, hg, state, rho, P, recv=ridx, mode="tree")
+    ref = {**{k: v for k, v in d2.items() if k != "total"}, **g2,
+           **{k: v for k, v in fo.items() if k != "total"}}
+    where = "active step at its h"
+    check_density(g, ref, q, hg, ridx, P, where)
+    check_ghost(g, ref, ridx, where)
+    check_force(g, ref, q, hg, ridx, P, where)
 
 
 def test_step_rejects_null_outputs():
