@@ -268,6 +268,26 @@ sphx_status sphx_force(sphx_ctx *ctx, const sphx_grid *grid, const sphx_tasks *t
                        const sphx_ghost_out *gst, sphx_force_out *out, double *d_sums6,
                        void *stream);
 
+/* sphx_force with no allocation of any kind, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the same kernels, arguments, outputs and
+ * bits as sphx_force, but the FP64 partial sums of the conservation sums
+ * (6 per leaf cell plus 128 parts of their reduction) live in a fixed
+ * device array of the library (25.2 MB per device, set aside by the HIP
+ * runtime when the library's code is loaded on the device, at the first
+ * sphx_ctx_create there, and held until the process ends) instead of the grid's
+ * workspace, no kernel timing events are created, and an empty set clears
+ * d_sums6 with a kernel (no memset). Limit: grids of at most 524,288 leaf
+ * cells (about 20 M particles at the default leaf size); a larger grid is
+ * refused with E_INVALID before anything is enqueued. Every call on one
+ * device shares that array, so calls that overlap on one device (other
+ * streams, other host threads, other contexts) race: serialise them.
+ * Asynchronous. */
+sphx_status sphx_force_noalloc(sphx_ctx *ctx, const sphx_grid *grid, const sphx_tasks *tasks,
+                               const sphx_particles *in, const sphx_density_out *dens,
+                               const sphx_ghost_out *gst, sphx_force_out *out, double *d_sums6,
+                               void *stream);
+
 /* One step on an existing grid: the h iteration (density + ghost passes
  * until every active particle has converged or max_iter passes ran; the task
  * list is rebuilt in place whenever an h outgrows its task radius, and a

@@ -224,6 +224,15 @@ sphx_status sphx_ctx_create(const sphx_params *p, int hip_device, sphx_ctx **out
         set_error("sphx_ctx_create: out of device memory");
         return SPHX_E_OOM;
     }
+    // The fixed workspace of sphx_force_noalloc on this device: its address
+    // is looked up here, at set-up, once per device.
+    const sphx_status ws = noalloc_scratch(hip_device, &c->noalloc_sums);
+    if (ws < 0) {
+        const std::string msg = sphx_last_error();
+        sphx_ctx_destroy(c);
+        set_error("sphx_ctx_create: " + msg);
+        return ws;
+    }
     *out = c;
     return SPHX_OK;
 }
@@ -423,6 +432,33 @@ sphx_status sphx_force(sphx_ctx *ctx, const sphx_grid *grid, const sphx_tasks *t
         return SPHX_E_INVALID;
     }
     return force_launch(ctx, grid, tasks, in, dens, gst, out, d_sums6, as_stream(stream));
+}
+
+sphx_status sphx_force_noalloc(sphx_ctx *ctx, const sphx_grid *grid, const sphx_tasks *tasks,
+                               const sphx_particles *in, const sphx_density_out *dens,
+                               const sphx_ghost_out *gst, sphx_force_out *out, double *d_sums6,
+                               void *stream)
+{
+    SPHX_TRY(check_handles(ctx, grid, tasks, in));
+    SPHX_TRY(check_particles(in, false));
+    if (!tasks || !dens || !gst || !out ||
+        (in->n && (!out->ax || !out->ay || !out->az || !out->du_dt || !out->v_sig || !dens->rho ||
+                   !gst->P || !gst->c || !gst->f || !gst->balsara || !gst->A))) {
+        set_error("sphx_force_noalloc: NULL task list, state or output array");
+        return SPHX_E_INVALID;
+    }
+    if (grid->n_leaves > kNoallocLeaves) {
+        set_error("sphx_force_noalloc: the grid has " + std::to_string(grid->n_leaves) +
+                  " leaf cells, more than the " + std::to_string(kNoallocLeaves) +
+                  " its fixed workspace holds (use sphx_force)");
+        return SPHX_E_INVALID;
+    }
+    if (!ctx->noalloc_sums) {
+        set_error("sphx_force_noalloc: no fixed workspace on this device");
+        return SPHX_E_STATE;
+    }
+    return force_launch(ctx, grid, tasks, in, dens, gst, out, d_sums6, as_stream(stream), nullptr,
+                        false, ctx->noalloc_sums);
 }
 
 // The step after validation (sphx_step; the autotuner's timed steps).

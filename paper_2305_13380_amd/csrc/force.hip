@@ -4,6 +4,8 @@
 //
 // The loop structure (cull, candidate buffer, per-lane lists) is described in
 // pairs.h; the force set of receiver i is every j != i with r_ij < max(H_i, H_j).
+#include <mutex>
+
 #include "pairs.h"
 
 namespace sphx {
@@ -508,21 +510,63 @@ __global__ __launch_bounds__(kSumParts) void k_sum_parts(const double *__restric
         out[t] = red[t][0];
 }
 
+// Clears the six FP64 sums of an empty particle set (a kernel, not a memset
+// node, so that the call can be recorded in a graph).
+__global__ void k_zero_sums(double *__restrict__ out)
+{
+    if (threadIdx.x < 6)
+        out[threadIdx.x] = 0.0;
+}
+
 }  // namespace
+
+// Fixed workspace of sphx_force_noalloc: the per-leaf FP64 partial sums of
+// the force kernel (6 per leaf) followed by the kSumParts parts of their
+// reduction, for at most kNoallocLeaves leaves (25.2 MB). Every device the
+// library runs on holds its own copy until the process ends. Every entry
+// is written before it is read in each call (each leaf writes its six, the
+// reduction its parts), so nothing needs clearing between calls; calls that
+// overlap on one device share it and race.
+static __device__ __align__(256) double scratch[6 * (kNoallocLeaves + kSumParts)];
+
+sphx_status noalloc_scratch(int device, double **out)
+{
+    static std::mutex mu;
+    static double *ptr[kNoallocMaxDevices] = {};
+    if (device < 0 || device >= kNoallocMaxDevices) {
+        set_error("fixed workspace: device index out of range");
+        return SPHX_E_INVALID;
+    }
+    std::lock_guard<std::mutex> lock(mu);
+    if (!ptr[device]) {
+        // `device` is current: the array's address on it (each device holds
+        // its own copy at its own address)
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            set_error(std::string("fixed workspace: hipGetSymbolAddress: ") +
+                      hipGetErrorString(e));
+            return SPHX_E_HIP;
+        }
+        ptr[device] = static_cast<double *>(p);
+    }
+    *out = ptr[device];
+    return SPHX_OK;
+}
 
 // The loop shapes of one kernel kind.
 template <int K>
 static void force_shapes(int tile, int waves, int64_t nbp, const sphx_ctx *ctx,
                          const sphx_grid *g, const sphx_tasks *t, const sphx_particles *in,
                          const sphx_force_out *o, float far, const int32_t *gate,
-                         const StepOut &so, hipStream_t s)
+                         const StepOut &so, double *fsum, hipStream_t s)
 {
 #define SPHX_FORCE_LAUNCH(CAP_, NW_)                                                           \
     k_force<CAP_, NW_, K><<<unsigned(nbp), 64 * NW_, 0, s>>>(                                     \
         g->n_leaves, nbp, t->order, g->leaf_start, g->perm, g->q0, g->q1, g->qa, g->g0, g->g1, \
         in->active, t->off, t->task, g->leaf_ext, g->leaf_hmax, float(ctx->p.gamma_k),         \
         float(ctx->p.beta_v), far, o->ax,                                                      \
-        o->ay, o->az, o->du_dt, o->v_sig, o->nforce, g->fsum, gate, so)
+        o->ay, o->az, o->du_dt, o->v_sig, o->nforce, fsum, gate, so)
     if (waves == 1) {
         if (tile == 64)
             SPHX_FORCE_LAUNCH(64, 1);
@@ -540,13 +584,21 @@ static void force_shapes(int tile, int waves, int64_t nbp, const sphx_ctx *ctx,
 sphx_status force_launch(const sphx_ctx *ctx, const sphx_grid *g, const sphx_tasks *t,
                          const sphx_particles *in, const sphx_density_out *d,
                          const sphx_ghost_out *gs, const sphx_force_out *o, double *sums6,
-                         hipStream_t s, const int32_t *gate, bool state_ready)
+                         hipStream_t s, const int32_t *gate, bool state_ready,
+                         double *fsum_fixed)
 {
     if (g->n_leaves == 0) {
-        if (sums6)
-            SPHX_HIP(hipMemsetAsync(sums6, 0, 6 * sizeof(double), s));
+        if (sums6) {
+            k_zero_sums<<<1, 64, 0, s>>>(sums6);
+            SPHX_HIP(hipGetLastError());
+        }
         return SPHX_OK;
     }
+    // the partial sums: the grid's workspace, or the fixed one
+    double *fsum = fsum_fixed ? fsum_fixed : g->fsum;
+    // (no kernel timing in the fixed-workspace call: creating timing events
+    // would allocate)
+    Profiler *prof = fsum_fixed ? nullptr : ctx->prof;
     if (!state_ready || in->active) {
         k_force_state<<<unsigned((g->n + 255) / 256), 256, 0, s>>>(
             g->n, g->perm, in->h, d->rho, gs->P, gs->c, gs->f, gs->balsara, gs->A,
@@ -565,16 +617,18 @@ sphx_status force_launch(const sphx_ctx *ctx, const sphx_grid *g, const sphx_tas
     // receiver (cell-relative coordinates), while every H is below a third
     const float far = float(4.0 * std::max(ctx->p.box[0], std::max(ctx->p.box[1], ctx->p.box[2])));
     const int64_t nbp = pad8(g->n_leaves);
-    SPHX_HIP(ctx->prof->begin(1, s));
+    if (prof)
+        SPHX_HIP(prof->begin(1, s));
     const int tile = ctx->p.force_tile ? ctx->p.force_tile : 64;
     const int waves = ctx->p.force_waves ? ctx->p.force_waves : 1;
     SPHX_WITH_KERNEL(ctx->p.kernel, force_shapes<KK>(tile, waves, nbp, ctx, g, t, in, o, far,
-                                                     gate, so, s));
+                                                     gate, so, fsum, s));
     SPHX_HIP(hipGetLastError());
-    SPHX_HIP(ctx->prof->end(1, s));
+    if (prof)
+        SPHX_HIP(prof->end(1, s));
     if (sums6) {
-        double *part = g->fsum + 6 * g->n_leaves;
-        k_sum_leaves<<<kSumParts, 256, 0, s>>>(g->n_leaves, g->fsum, part, gate);
+        double *part = fsum + 6 * g->n_leaves;
+        k_sum_leaves<<<kSumParts, 256, 0, s>>>(g->n_leaves, fsum, part, gate);
         SPHX_HIP(hipGetLastError());
         k_sum_parts<<<1, kSumParts, 0, s>>>(part, sums6, gate);
         SPHX_HIP(hipGetLastError());

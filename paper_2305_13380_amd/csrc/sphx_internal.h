@@ -100,6 +100,7 @@ struct sphx_ctx {
     // synchronisation left the device idle ~40 us per readback.
     unsigned char *h_pinned = nullptr;  // kPinnedBytes
     hipEvent_t ev_wait = nullptr;
+    double *noalloc_sums = nullptr;  // this device's fixed workspace (sphx_force_noalloc)
 };
 
 struct sphx_grid {
@@ -278,11 +279,19 @@ sphx_status ghost_launch(const sphx_ctx *ctx, sphx_grid *g, const sphx_tasks *t,
                          const int32_t *skip = nullptr, bool step_mode = false);
 
 // force.hip
+// fsum_fixed: the FP64 partial sums go to this fixed workspace (6 per leaf,
+// then the parts of their reduction) instead of the grid's; the launch then
+// creates nothing (no timing events).
 sphx_status force_launch(const sphx_ctx *ctx, const sphx_grid *g, const sphx_tasks *t,
                          const sphx_particles *in, const sphx_density_out *d,
                          const sphx_ghost_out *gs, const sphx_force_out *o, double *sums6,
                          hipStream_t s, const int32_t *gate = nullptr,
-                         bool state_ready = false);
+                         bool state_ready = false, double *fsum_fixed = nullptr);
+// The fixed workspace of sphx_force_noalloc on `device` (which must be
+// current): its address is looked up once per device and kept.
+constexpr int64_t kNoallocLeaves = int64_t(1) << 19;
+constexpr int kNoallocMaxDevices = 64;
+sphx_status noalloc_scratch(int device, double **out);
 
 // graph.hip
 // Captured step: the h iteration's first `passes` passes and a gated force

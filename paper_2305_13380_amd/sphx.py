@@ -77,7 +77,7 @@ SYMBOLS = ("sphx_params_default", "sphx_ctx_create", "sphx_ctx_destroy", "sphx_w
            "sphx_iter_reset", "sphx_density", "sphx_ghost", "sphx_force", "sphx_step",
            "sphx_grid_leaves", "sphx_tasks_count", "sphx_last_error", "sphx_profile_enable",
            "sphx_profile_read", "sphx_autotune", "sphx_params_set_kernel", "sphx_fof",
-           "sphx_gravity", "sphx_alpha_v_update")
+           "sphx_gravity", "sphx_alpha_v_update", "sphx_force_noalloc")
 
 _LIB = None
 
@@ -123,6 +123,7 @@ def _load():
     L.sphx_ghost.argtypes = [vp, vp, vp, P(Particles), P(DensityOut), P(GhostOut), vp, i32, vp]
     L.sphx_force.argtypes = [vp, vp, vp, P(Particles), P(DensityOut), P(GhostOut), P(ForceOut),
                              vp, vp]
+    L.sphx_force_noalloc.argtypes = L.sphx_force.argtypes
     L.sphx_step.argtypes = [vp, vp, P(vp), P(Particles), P(DensityOut), P(GhostOut),
                             P(ForceOut), vp, vp, P(StepInfo)]
     L.sphx_autotune.argtypes = [vp, vp, vp, P(Particles), P(DensityOut), P(GhostOut),
@@ -139,7 +140,7 @@ def _load():
     L.sphx_last_error.argtypes = []
     L.sphx_last_error.restype = C.c_char_p
     for name in ("sphx_ctx_create", "sphx_grid_build", "sphx_tasks_build", "sphx_iter_reset",
-                 "sphx_density", "sphx_ghost", "sphx_force", "sphx_step"):
+                 "sphx_density", "sphx_ghost", "sphx_force", "sphx_step", "sphx_force_noalloc"):
         getattr(L, name).restype = i32
     _LIB = L
     return L
@@ -357,6 +358,16 @@ def force(ctx, grid, tasks, parts, out: Outputs, sums=True, stream=None):
     return _check(lib.sphx_force(ctx.handle, grid.handle, tasks.handle, C.byref(pv), C.byref(dv),
                                  C.byref(gv), C.byref(fv), _ptr(out.sums) if sums else None,
                                  _stream(stream)))
+
+
+def force_noalloc(ctx, grid, tasks, parts, out: Outputs, sums=True, stream=None):
+    """sphx_force_noalloc: the force pass with its partial sums in the
+    library's fixed device workspace (no allocation)."""
+    pv = parts.view()
+    dv, gv, fv = out.dens_view(), out.ghost_view(), out.force_view()
+    return _check(lib.sphx_force_noalloc(ctx.handle, grid.handle, tasks.handle, C.byref(pv),
+                                         C.byref(dv), C.byref(gv), C.byref(fv),
+                                         _ptr(out.sums) if sums else None, _stream(stream)))
 
 
 def step(ctx, grid, tasks: Tasks, parts, out: Outputs, stream=None):
