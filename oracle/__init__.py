@@ -86,6 +86,22 @@ def lib():
         L.or_gravity.restype = C.c_int64
         L.or_alpha_v_update.argtypes = ([C.c_int64] + [_dp] * 5 + [C.c_double] * 4 + [_dp])
         L.or_alpha_v_update.restype = None
+        L.or_gradient.argtypes = ([C.c_int64] + [_dp] * 12 + [_dp, C.c_int, C.c_double, C.c_int,
+                                  C.c_int64, _nullable(_ip), _nullable(_ip), _nullable(_ip)]
+                                  + [_dp] * 3)
+        L.or_gradient.restype = C.c_int64
+        L.or_alpha_c_update.argtypes = ([C.c_int64] + [_dp] * 5 + [C.c_double] * 6 + [_dp])
+        L.or_alpha_c_update.restype = None
+        L.or_dt_cfl.argtypes = [C.c_int64, _dp, _dp, C.c_double, C.c_double, _dp]
+        L.or_dt_cfl.restype = None
+        L.or_dt_limit.argtypes = ([C.c_int64] + [_dp] * 5 + [_dp, C.c_int, C.c_double,
+                                  C.c_double, C.c_int64, _nullable(_ip), _nullable(_ip),
+                                  _nullable(_ip), _dp])
+        L.or_dt_limit.restype = C.c_int64
+        L.or_kick.argtypes = [C.c_int64] + [_dp] * 8 + [C.c_double]
+        L.or_kick.restype = None
+        L.or_drift.argtypes = [C.c_int64] + [_dp] * 6 + [C.c_double, _dp, C.c_int]
+        L.or_drift.restype = None
         _LIB = L
     return _LIB
 
@@ -572,3 +588,141 @@ def alpha_v_update(alpha, div_old, div_new, c, h, vsig, dt, params: Params,
     lib().or_alpha_v_update(n, _f64(div_old), _f64(div_new), _f64(c), _f64(h), _f64(vsig),
                             float(dt), float(params.gamma_k), float(alpha_max), float(ell), a)
     return a
+
+
+# ---------------------------------------------------------------------------
+# The rest of SPHENIX (Section 3.3) and the time integration (Sections 2.4,
+# 3.4).
+# ---------------------------------------------------------------------------
+
+SPHENIX_BETA_C = 1.0        # Section 3.3: conduction source strength
+SPHENIX_ALPHA_C_MIN = 0.0   # Section 3.3: smallest conduction parameter
+SPHENIX_ALPHA_C_MAX = 1.0   # Section 3.3: constant of the shock limiter
+DT_LIMIT_DELTA = 4.0        # Section 3.4: largest step ratio between neighbours
+
+
+def gradient(ps, h, rho, P, params: Params, recv=None, mode="auto"):
+    """SPHENIX gradient loop (or_gradient): Laplacian of u, conduction speed
+    and the largest neighbouring alpha_V for the receivers. rho and P hold
+    every particle's values (only neighbours' entries are read)."""
+    mode = _resolve_mode(mode, ps.n)
+    h = _f64(h)
+    r, nrecv = _recv_arr(recv, ps.n)
+    off = idx = None
+    if mode == "tree":
+        off, idx = density_candidates(ps, h, params, r)
+    out = {k: np.zeros(nrecv) for k in ("lap_u", "vc", "avmax")}
+    x, y, z = _pos(ps)
+    total = lib().or_gradient(ps.n, x, y, z, _f64(ps.vx), _f64(ps.vy), _f64(ps.vz), _f64(ps.m),
+                              _f64(ps.u), h, _f64(rho), _f64(P), _f64(ps.alpha_v), _f64(ps.box),
+                              int(params.periodic), float(params.gamma_k), params.kernel_id(),
+                              nrecv, r, off, idx, out["lap_u"], out["vc"], out["avmax"])
+    out["total"] = int(total)
+    return out
+
+
+def alpha_c_update(alpha, lap_u, u, h, vc, avmax, dt, params: Params,
+                   beta_c=SPHENIX_BETA_C, a_min=SPHENIX_ALPHA_C_MIN, a_max=SPHENIX_ALPHA_C_MAX,
+                   av_max=SPHENIX_ALPHA_V_MAX):
+    """New alpha_c of every particle after a step dt (or_alpha_c_update)."""
+    a = _f64(alpha).copy()
+    lib().or_alpha_c_update(a.shape[0], _f64(lap_u), _f64(u), _f64(h), _f64(vc), _f64(avmax),
+                            float(dt), float(params.gamma_k), float(beta_c), float(a_min),
+                            float(a_max), float(av_max), a)
+    return a
+
+
+def dt_cfl(h, vsig, params: Params, c_cfl):
+    h = _f64(h)
+    dt = np.empty_like(h)
+    lib().or_dt_cfl(h.shape[0], h, _f64(vsig), float(params.gamma_k), float(c_cfl), dt)
+    return dt
+
+
+def dt_limit(ps, h, dt, params: Params, delta=DT_LIMIT_DELTA, recv=None, mode="auto"):
+    """Each receiver's step capped at delta times the smallest step of its
+    force-loop neighbours (or_dt_limit)."""
+    mode = _resolve_mode(mode, ps.n)
+    h = _f64(h)
+    r, nrecv = _recv_arr(recv, ps.n)
+    off = idx = None
+    if mode == "tree":
+        off, idx = force_candidates(ps, h, params, r)
+    out = np.zeros(nrecv)
+    x, y, z = _pos(ps)
+    lib().or_dt_limit(ps.n, x, y, z, h, _f64(dt), _f64(ps.box), int(params.periodic),
+                      float(params.gamma_k), float(delta), nrecv, r, off, idx, out)
+    return out
+
+
+def kick(v, u, a, du, dt_half):
+    """Half kick in place: v (3 x n) += a dt/2, u += du/dt dt/2."""
+    lib().or_kick(u.shape[0], v[0], v[1], v[2], u, _f64(a[0]), _f64(a[1]), _f64(a[2]), _f64(du),
+                  float(dt_half))
+
+
+def drift(pos, v, dt, box, periodic=True):
+    """Drift in place: pos (3 x n) += v dt, wrapped into the box."""
+    lib().or_drift(pos.shape[1], pos[0], pos[1], pos[2], _f64(v[0]), _f64(v[1]), _f64(v[2]),
+                   float(dt), _f64(box), int(periodic))
+
+
+def sphenix_run(ps, params: Params, n_steps, c_cfl=0.2, delta=DT_LIMIT_DELTA, mode="auto",
+                dt_max=None, callback=None):
+    """Kick-drift-kick integration with one global step (the smallest
+    limited CFL step; every particle active). Per step: half kick, drift
+    (with v and u predicted to the end of the drift by the previous
+    derivatives), h iteration, ghost and force with the viscosity and
+    conduction parameters of the step before, then the viscosity switch, the
+    gradient loop and the conduction parameter, the second half kick and the
+    next step size. Returns the final state and the list of (t, dt)."""
+    n = ps.n
+    pos = np.stack([_f64(ps.x), _f64(ps.y), _f64(ps.z)]).copy()
+    v = np.stack([_f64(ps.vx), _f64(ps.vy), _f64(ps.vz)]).copy()
+    u = _f64(ps.u).copy()
+    q = ps.copy()
+
+    def evaluate(h0, vp=None, up=None):
+        for k, a in zip(("x", "y", "z"), pos):
+            setattr(q, k, np.ascontiguousarray(a))
+        q.vx, q.vy, q.vz = (np.ascontiguousarray(a) for a in (v if vp is None else vp))
+        q.u = (u if up is None else up).copy()
+        h, _, conv, _, _ = solve_h(q, params, mode=mode, h0=h0)
+        r = fixed_h_step(q, params, mode=mode, h=h)
+        return h, r
+
+    h, r = evaluate(_f64(ps.h))
+    alpha_v = _f64(ps.alpha_v).copy()
+    alpha_c = _f64(ps.alpha_c).copy()
+    dt = float(dt_limit(q, h, dt_cfl(h, r["vsig"], params, c_cfl), params, delta, mode=mode).min())
+    if dt_max is not None:
+        dt = min(dt, dt_max)
+    t = 0.0
+    hist = []
+    for step in range(n_steps):
+        a = (r["ax"], r["ay"], r["az"])
+        kick(v, u, a, r["du"], 0.5 * dt)
+        drift(pos, v, dt, ps.box, params.periodic)
+        div_old = r["div_v"]
+        q.alpha_v, q.alpha_c = alpha_v.copy(), alpha_c.copy()
+        # the forces at the end of the drift see v and u predicted to that
+        # time with the derivatives of the step before (the half-step values
+        # would make the energy equation first order in dt)
+        vp = v + 0.5 * dt * np.stack(a)
+        up = u + 0.5 * dt * r["du"]
+        h, r = evaluate(h, vp, up)
+        alpha_v = alpha_v_update(alpha_v, div_old, r["div_v"], r["c"], h, r["vsig"], dt, params)
+        q.alpha_v = alpha_v.copy()
+        g = gradient(q, h, r["rho"], r["P"], params, mode=mode)
+        alpha_c = alpha_c_update(alpha_c, g["lap_u"], up, h, g["vc"], g["avmax"], dt, params)
+        kick(v, u, (r["ax"], r["ay"], r["az"]), r["du"], 0.5 * dt)
+        t += dt
+        hist.append((t, dt))
+        if callback is not None:
+            callback(step, t, pos, v, u, h, r)
+        dt = float(dt_limit(q, h, dt_cfl(h, r["vsig"], params, c_cfl), params, delta,
+                            mode=mode).min())
+        if dt_max is not None:
+            dt = min(dt, dt_max)
+    return dict(pos=pos, v=v, u=u, h=h, alpha_v=alpha_v, alpha_c=alpha_c, t=t, hist=hist,
+                last=r)

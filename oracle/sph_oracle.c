@@ -49,6 +49,16 @@
  *    it is read as a rise to the target and an exponential decay towards
  *    it. The pins fix this reading's own properties; its agreement with the
  *    printed equation is parity unpinned.
+ *  - SPHENIX conduction (Section 3.3): the Laplacian of u, which the paper
+ *    names but does not print, is Brookshaw's second-derivative estimator
+ *    2 sum (m_j/rho_j)(u_i - u_j) W'/r over r < H_i; the particle's
+ *    conduction speed is the largest pair speed v_c,ij over the same
+ *    neighbours and alpha_V,max,i the largest alpha_V among them and i; the
+ *    conduction parameter's equation, linear with constant coefficients over
+ *    a step, is integrated exactly, then capped by the shock limiter.
+ *  - time step (Section 3.4): the CFL condition, named but not printed, is
+ *    read as dt = c_cfl H / v_sig; the first limiter caps a step at Delta
+ *    times the smallest step among the force-loop neighbours.
  */
 #include <math.h>
 #include <stddef.h>
@@ -613,5 +623,186 @@ void or_alpha_v_update(int64_t n, const double *div_old, const double *div_new, 
             alpha[i] = loc;
         else
             alpha[i] = loc + (alpha[i] - loc) * exp(-ell * c[i] * dt / H);
+    }
+}
+
+/*
+ * SPHENIX gradient loop (Section 3.3: the conduction parameter is driven by
+ * the Laplacian of the internal energy and decays on the conduction speed;
+ * the conduction limiter reads the largest viscosity parameter nearby). For
+ * receiver k (particle i) over every j != i with 0 < r_ij < H_i:
+ *   lap_u_i  = 2 sum_j (m_j / rho_j) (u_i - u_j) dW/dr(r_ij, h_i) / r_ij
+ *              (the paper does not print the estimator; this is the
+ *              second-derivative form of Brookshaw, which returns 2 for
+ *              u = x^2 in the continuum limit)
+ *   vc_i     = max_j [ |v_ij . x_ij| / r_ij + sqrt(2 |P_i - P_j| / (rho_i + rho_j)) ]
+ *              (the pair conduction speed of Section 3.3; 0 without neighbours)
+ *   avmax_i  = max(alpha_V,i, max_j alpha_V,j)
+ * Coincident pairs (r = 0) have no direction and are skipped. Returns the
+ * number of pairs used.
+ */
+int64_t or_gradient(int64_t n, const double *x, const double *y, const double *z,
+                    const double *vx, const double *vy, const double *vz, const double *m,
+                    const double *u, const double *h, const double *rho, const double *P,
+                    const double *alpha_v, const double *box, int periodic, double gamma_k,
+                    int kernel, int64_t nrecv, const int64_t *recv, const int64_t *cand_off,
+                    const int64_t *cand_idx, double *lap_u, double *vc, double *avmax)
+{
+    int64_t total = 0;
+#pragma omp parallel for schedule(dynamic, 16) reduction(+ : total)
+    for (int64_t k = 0; k < nrecv; ++k) {
+        int64_t i = recv ? recv[k] : k;
+        double hi = h[i], Hi = gamma_k * hi;
+        double s_lap = 0.0, s_vc = 0.0, s_av = alpha_v[i];
+        int64_t cnt = 0;
+        int64_t jb = cand_off ? cand_off[k] : 0;
+        int64_t je = cand_off ? cand_off[k + 1] : n;
+        for (int64_t q = jb; q < je; ++q) {
+            int64_t j = cand_off ? cand_idx[q] : q;
+            if (j == i)
+                continue;
+            double dx = min_image(x[i] - x[j], box[0], periodic);
+            double dy = min_image(y[i] - y[j], box[1], periodic);
+            double dz = min_image(z[i] - z[j], box[2], periodic);
+            double r = sqrt(dx * dx + dy * dy + dz * dz);
+            if (!(r < Hi) || !(r > 0.0))
+                continue;
+            double w, dwdr, dwdh;
+            or_kernel(kernel, r, hi, gamma_k, &w, &dwdr, &dwdh);
+            s_lap += m[j] / rho[j] * (u[i] - u[j]) * dwdr / r;
+            double vdotx = (vx[i] - vx[j]) * dx + (vy[i] - vy[j]) * dy + (vz[i] - vz[j]) * dz;
+            double v_c = fabs(vdotx) / r + sqrt(2.0 * fabs(P[i] - P[j]) / (rho[i] + rho[j]));
+            if (v_c > s_vc)
+                s_vc = v_c;
+            if (alpha_v[j] > s_av)
+                s_av = alpha_v[j];
+            cnt += 1;
+        }
+        lap_u[k] = 2.0 * s_lap;
+        vc[k] = s_vc;
+        avmax[k] = s_av;
+        total += cnt;
+    }
+    return total;
+}
+
+/*
+ * SPHENIX conduction parameter over a step dt (Section 3.3): the evolution
+ * equation
+ *   d alpha_c / dt = beta_c H lap_u / sqrt(u) - (alpha_c - alpha_c,min) vc / H
+ * has constant coefficients over the step, so it is integrated exactly: with
+ * S = beta_c H lap_u / sqrt(u) and lam = vc / H,
+ *   alpha = a_inf + (alpha - a_inf) exp(-lam dt),  a_inf = alpha_c,min + S / lam,
+ * and alpha + S dt where lam = 0 (its limit). Then the shock limiter caps
+ * it at alpha_c,max (1 - avmax / alpha_V,max) and it is kept >= alpha_c,min
+ * (beta_c = 1, alpha_c,min = 0, alpha_c,max = 1, alpha_V,max = 2 as
+ * printed). alpha is updated in place.
+ */
+void or_alpha_c_update(int64_t n, const double *lap_u, const double *u, const double *h,
+                       const double *vc, const double *avmax, double dt, double gamma_k,
+                       double beta_c, double a_min, double a_max, double av_max, double *alpha)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        double H = gamma_k * h[i];
+        double S = u[i] > 0.0 ? beta_c * H * lap_u[i] / sqrt(u[i]) : 0.0;
+        double lam = vc[i] / H;
+        double a = alpha[i];
+        if (lam > 0.0) {
+            double a_inf = a_min + S / lam;
+            a = a_inf + (a - a_inf) * exp(-lam * dt);
+        } else {
+            a = a + S * dt;
+        }
+        double cap = a_max * (1.0 - avmax[i] / av_max);
+        if (cap < a_min)
+            cap = a_min;
+        if (a > cap)
+            a = cap;
+        if (a < a_min)
+            a = a_min;
+        alpha[i] = a;
+    }
+}
+
+/*
+ * Time-step size (Section 3.4: the CFL condition, then the first limiter).
+ * The paper names the condition without printing it; here the Courant form
+ * on the kernel support, dt_i = c_cfl H_i / v_sig,i. The limiter: no
+ * particle's step exceeds delta times the smallest step among the particles
+ * it interacts with in the force loop (j != i, r_ij < max(H_i, H_j)):
+ *   dt_out_i = min(dt_i, delta min_j dt_j).
+ * or_dt_cfl fills dt from h and v_sig; or_dt_limit applies the limiter for
+ * the receivers (cand lists as in the force pass) and returns the pair count.
+ */
+void or_dt_cfl(int64_t n, const double *h, const double *vsig, double gamma_k, double c_cfl,
+               double *dt)
+{
+    for (int64_t i = 0; i < n; ++i)
+        dt[i] = c_cfl * gamma_k * h[i] / vsig[i];
+}
+
+int64_t or_dt_limit(int64_t n, const double *x, const double *y, const double *z,
+                    const double *h, const double *dt, const double *box, int periodic,
+                    double gamma_k, double delta, int64_t nrecv, const int64_t *recv,
+                    const int64_t *cand_off, const int64_t *cand_idx, double *dt_out)
+{
+    int64_t total = 0;
+#pragma omp parallel for schedule(dynamic, 16) reduction(+ : total)
+    for (int64_t k = 0; k < nrecv; ++k) {
+        int64_t i = recv ? recv[k] : k;
+        double Hi = gamma_k * h[i];
+        double lim = dt[i];
+        int64_t jb = cand_off ? cand_off[k] : 0;
+        int64_t je = cand_off ? cand_off[k + 1] : n;
+        for (int64_t q = jb; q < je; ++q) {
+            int64_t j = cand_off ? cand_idx[q] : q;
+            if (j == i)
+                continue;
+            double dx = min_image(x[i] - x[j], box[0], periodic);
+            double dy = min_image(y[i] - y[j], box[1], periodic);
+            double dz = min_image(z[i] - z[j], box[2], periodic);
+            double r = sqrt(dx * dx + dy * dy + dz * dz);
+            double Hj = gamma_k * h[j];
+            if (!(r < (Hi > Hj ? Hi : Hj)))
+                continue;
+            total += 1;
+            if (delta * dt[j] < lim)
+                lim = delta * dt[j];
+        }
+        dt_out[k] = lim;
+    }
+    return total;
+}
+
+/*
+ * Leapfrog operators (Section 2.4: kick-drift-kick). A half kick adds
+ * a dt/2 to v and du/dt dt/2 to u; a drift moves x by v dt, wrapped into
+ * [0, L) in a periodic box.
+ */
+void or_kick(int64_t n, double *vx, double *vy, double *vz, double *u, const double *ax,
+             const double *ay, const double *az, const double *du, double dt_half)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        vx[i] += ax[i] * dt_half;
+        vy[i] += ay[i] * dt_half;
+        vz[i] += az[i] * dt_half;
+        u[i] += du[i] * dt_half;
+    }
+}
+
+void or_drift(int64_t n, double *x, double *y, double *z, const double *vx, const double *vy,
+              const double *vz, double dt, const double *box, int periodic)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        double p[3] = {x[i] + vx[i] * dt, y[i] + vy[i] * dt, z[i] + vz[i] * dt};
+        for (int a = 0; a < 3; ++a)
+            if (periodic) {
+                p[a] -= box[a] * floor(p[a] / box[a]);
+                if (p[a] >= box[a])  /* a tiny negative p rounds up to L */
+                    p[a] -= box[a];
+            }
+        x[i] = p[0];
+        y[i] = p[1];
+        z[i] = p[2];
     }
 }
