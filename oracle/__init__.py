@@ -66,12 +66,13 @@ def lib():
         L.or_h_update.argtypes = [C.c_int64, _dp, _dp, _dp, C.c_double, C.c_double, C.c_double,
                                   _dp, _dp, _dp, _i32p]
         L.or_h_update.restype = None
-        L.or_ghost.argtypes = ([C.c_int64] + [_dp] * 8 + [C.c_double, C.c_double] + [_dp] * 7)
+        L.or_ghost.argtypes = ([C.c_int64] + [_dp] * 8 + [C.c_double, C.c_double] + [_dp] * 7
+                               + [C.c_int])
         L.or_ghost.restype = None
         L.or_force.argtypes = ([C.c_int64] + [_dp] * 16 + [_dp, C.c_int, C.c_double, C.c_int,
                                C.c_double,
                                C.c_int64, _nullable(_ip), _nullable(_ip), _nullable(_ip)]
-                               + [_dp] * 5 + [_ip])
+                               + [_dp] * 5 + [_ip, C.c_int, C.c_double, _nullable(_dp)])
         L.or_force.restype = C.c_int64
         L.or_sums.argtypes = [C.c_int64] + [_dp] * 8 + [_dp]
         L.or_sums.restype = None
@@ -143,6 +144,10 @@ class Params:
     h_tol: float = 1e-4            # relative Newton-Raphson tolerance (Section 3.1)
     max_iter: int = 30
     h_max: Optional[float] = None  # default: min(box) / (3 gamma_k) * (1 - 1e-6)
+    # "energy": density-energy (u is the internal energy, with conduction);
+    # "entropy": density-entropy, the Gadget2 flavour of Section 3.2 (the u
+    # array holds the adiabat A, no conduction, du/dt becomes dA/dt)
+    flavour: str = "energy"
 
     def hmax(self) -> float:
         if self.h_max is not None:
@@ -353,7 +358,8 @@ def ghost(dens, u, h, params: Params):
     lib().or_ghost(n, _f64(dens["rho"]), _f64(dens["rho_dh"]), _f64(dens["div_sum"]),
                    _f64(dens["curl_x"]), _f64(dens["curl_y"]), _f64(dens["curl_z"]), _f64(u),
                    _f64(h), float(params.gamma_gas), float(params.eps_b), out["f"], out["P"],
-                   out["c"], out["balsara"], out["A"], out["div_v"], out["curl_v"])
+                   out["c"], out["balsara"], out["A"], out["div_v"], out["curl_v"],
+                   int(params.flavour == "entropy"))
     return out
 
 
@@ -410,7 +416,7 @@ def force(ps, h, gst, dens_rho, params: Params, recv=None, mode="auto", cand=Non
     off = idx = None
     if mode == "tree":
         off, idx = cand if cand is not None else force_candidates(ps, h, params, r)
-    out = {k: np.zeros(nrecv) for k in ("ax", "ay", "az", "du", "vsig")}
+    out = {k: np.zeros(nrecv) for k in ("ax", "ay", "az", "du", "vsig", "du_energy")}
     nf = np.zeros(nrecv, np.int64)
     x, y, z = _pos(ps)
     total = lib().or_force(ps.n, x, y, z, _f64(ps.vx), _f64(ps.vy), _f64(ps.vz), _f64(ps.m),
@@ -419,7 +425,9 @@ def force(ps, h, gst, dens_rho, params: Params, recv=None, mode="auto", cand=Non
                            _f64(ps.alpha_c), _f64(ps.box), int(params.periodic),
                            float(params.gamma_k), params.kernel_id(), float(params.beta_v),
                            nrecv, r, off, idx,
-                           out["ax"], out["ay"], out["az"], out["du"], out["vsig"], nf)
+                           out["ax"], out["ay"], out["az"], out["du"], out["vsig"], nf,
+                           int(params.flavour == "entropy"), float(params.gamma_gas),
+                           out["du_energy"])
     out["nforce"] = nf
     out["total"] = int(total)
     return out

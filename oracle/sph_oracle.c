@@ -312,16 +312,21 @@ void or_h_update(int64_t n, const double *h, const double *nd, const double *nd_
  *   div v = div_sum / rho,  |curl v| = |curl_sum| / rho,
  *   B = |div v| / (|div v| + |curl v| + eps c / h),
  *   A = f P / rho^2.
+ * With entropy != 0 (density-entropy, Section 3.2) the input u is the
+ * adiabat A_i and P = A_i rho^gamma; the rest is unchanged.
  */
 void or_ghost(int64_t n, const double *rho, const double *rho_dh, const double *div_sum,
               const double *curl_x, const double *curl_y, const double *curl_z,
               const double *u, const double *h, double gamma_gas, double eps_b,
               double *f, double *P, double *c, double *balsara, double *A,
-              double *div_v, double *curl_v)
+              double *div_v, double *curl_v, int entropy)
 {
     for (int64_t k = 0; k < n; ++k) {
         double r = rho[k];
-        P[k] = (gamma_gas - 1.0) * u[k] * r;
+        /* density-energy: u is the internal energy; density-entropy (the
+         * Gadget2 flavour of Section 3.2): u holds the adiabat A, and the
+         * equation of state is its other printed form A rho^gamma */
+        P[k] = entropy ? u[k] * pow(r, gamma_gas) : (gamma_gas - 1.0) * u[k] * r;
         c[k] = sqrt(gamma_gas * P[k] / r);
         f[k] = 1.0 / (1.0 + h[k] / (3.0 * r) * rho_dh[k]);
         div_v[k] = div_sum[k] / r;
@@ -352,6 +357,11 @@ void or_ghost(int64_t n, const double *rho, const double *rho_dh, const double *
  *   vsig_i = max(2 c_i, max_j vsig_ij)
  * Coincident pairs (r = 0) are counted but add nothing (every term carries
  * a kernel gradient, which vanishes at r = 0). Returns the total count.
+ * With entropy != 0 (density-entropy, the Gadget2 flavour of Section 3.2:
+ * the input u holds the adiabat A, dA/dt = 0 but for the viscous heating)
+ * there is no conduction, du receives dA/dt = (gamma - 1) rho_i^(1 - gamma)
+ * sum_j m_j (nu G / 4) (v_ij . e), and du_energy (if not NULL) the
+ * internal-energy rate sum_j m_j [A_i g_i + nu G / 4] (v_ij . e).
  */
 int64_t or_force(int64_t n, const double *x, const double *y, const double *z,
                  const double *vx, const double *vy, const double *vz,
@@ -361,7 +371,8 @@ int64_t or_force(int64_t n, const double *x, const double *y, const double *z,
                  const double *box, int periodic, double gamma_k, int kernel, double beta_v,
                  int64_t nrecv, const int64_t *recv,
                  const int64_t *cand_off, const int64_t *cand_idx,
-                 double *ax, double *ay, double *az, double *du, double *vsig, int64_t *nforce)
+                 double *ax, double *ay, double *az, double *du, double *vsig, int64_t *nforce,
+                 int entropy, double gamma_gas, double *du_energy)
 {
     int64_t total = 0;
 #pragma omp parallel for schedule(dynamic, 16) reduction(+ : total)
@@ -369,7 +380,7 @@ int64_t or_force(int64_t n, const double *x, const double *y, const double *z,
         int64_t i = recv ? recv[k] : k;
         double Hi = gamma_k * h[i];
         double Ai = f[i] * P[i] / (rho[i] * rho[i]);
-        double s_ax = 0, s_ay = 0, s_az = 0, s_du = 0;
+        double s_ax = 0, s_ay = 0, s_az = 0, s_du = 0, s_visc = 0;
         double s_vsig = 2.0 * c[i];
         int64_t cnt = 0;
         int64_t jb = cand_off ? cand_off[k] : 0;
@@ -411,17 +422,26 @@ int64_t or_force(int64_t n, const double *x, const double *y, const double *z,
             s_ay -= m[j] * acc * ey;
             s_az -= m[j] * acc * ez;
             s_du += m[j] * (Agi + 0.25 * nu * G) * vdote;
-            double psum = P[i] + P[j];
-            double alpha_c_ij = psum > 0.0 ? (P[i] * alpha_c[i] + P[j] * alpha_c[j]) / psum : 0.0;
-            double v_c = fabs(vdote) + sqrt(2.0 * fabs(P[i] - P[j]) / (rho[i] + rho[j]));
-            s_du += m[j] * alpha_c_ij * v_c * (u[i] - u[j]) * G / (rho[i] + rho[j]);
+            s_visc += m[j] * 0.25 * nu * G * vdote;
+            if (!entropy) {
+                double psum = P[i] + P[j];
+                double alpha_c_ij =
+                    psum > 0.0 ? (P[i] * alpha_c[i] + P[j] * alpha_c[j]) / psum : 0.0;
+                double v_c = fabs(vdote) + sqrt(2.0 * fabs(P[i] - P[j]) / (rho[i] + rho[j]));
+                s_du += m[j] * alpha_c_ij * v_c * (u[i] - u[j]) * G / (rho[i] + rho[j]);
+            }
             if (vsig_ij > s_vsig)
                 s_vsig = vsig_ij;
         }
         ax[k] = s_ax;
         ay[k] = s_ay;
         az[k] = s_az;
-        du[k] = s_du;
+        /* density-entropy: the adiabat changes only by the viscous heating,
+         * dA/dt = (gamma - 1) rho^(1 - gamma) du/dt|visc; du_energy keeps the
+         * internal-energy rate the forces imply (for the energy balance) */
+        du[k] = entropy ? (gamma_gas - 1.0) * pow(rho[i], 1.0 - gamma_gas) * s_visc : s_du;
+        if (du_energy)
+            du_energy[k] = s_du;
         vsig[k] = s_vsig;
         nforce[k] = cnt;
         total += cnt;
