@@ -118,6 +118,17 @@ def cpu_baseline(ps, make_params, n_recv, seed=0):
 
     gomp = ctypes.CDLL("libgomp.so.1")  # the OpenMP runtime the oracle runs on
     threads = int(gomp.omp_get_max_threads())
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")),
+                         "")
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
     rate, sample = run(n_recv)
     gomp.omp_set_num_threads(1)
     try:
@@ -125,7 +136,11 @@ def cpu_baseline(ps, make_params, n_recv, seed=0):
     finally:
         gomp.omp_set_num_threads(threads)
     return {"value": rate, "unit": "interactions/s", "cores": threads, "kind": "oracle",
-            "sample": sample, "value_1core": rate1, "sample_1core": sample1}
+            "sample": sample, "value_1core": rate1, "sample_1core": sample1,
+            "cores_are": "OpenMP threads of the oracle's loops (its k-d tree candidate search "
+                         "runs on one thread)",
+            "host_cpu_model": model, "host_logical_cpus": os.cpu_count(),
+            "host_cpus_usable": usable}
 
 
 def serving_bench(slots, n_req, seed=4):
@@ -255,6 +270,9 @@ def gravity_bench(params, dp, reps):
            "pairs": npairs, "ms": min(times) * 1e3, "kernel_ms": kern_s * 1e3,
            "pairs_per_s": npairs / kern_s if kern_s > 0 else None,
            "kernel_tflops_algorithmic": npairs * FLOP_GRAVITY / kern_s / 1e12 if kern_s > 0 else None,
+           "roofline": {"bound": "alu", "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                        "frac": (npairs * FLOP_GRAVITY / kern_s / 1e12 / PEAK_FP32_TFLOPS
+                                 if kern_s > 0 else None)},
            "flop_per_pair": FLOP_GRAVITY, "reps": len(times),
            "timed": "ms: whole sphx_gravity call (cell and task build at r_p2p, the loop); "
                     "kernel_ms: the loop alone"}
@@ -262,28 +280,154 @@ def gravity_bench(params, dp, reps):
     return rec
 
 
-def switch_bench(params, n, reps=200):
+def step_leg(name, params, steps=5, warmup=1, flavour=None):
+    """One more workload of the step, timed like the headline one (HIP events
+    on the stream around `steps` whole steps from the generator's h, inputs
+    resident): the Sedov box and the large box with its active subset (after
+    an untimed all-active step that gives the inactive particles their
+    state), or the headline box with another SPH flavour."""
+    import numpy as np
+    import torch
+    from paper_2305_13380_amd import inputs, sphx
+    desc, make = CONFIGS[name]
+    t0 = time.perf_counter()
+    ps = make(inputs)
+    if flavour == "entropy":
+        # the same particles carrying the adiabat A = (gamma - 1) u / rho^(gamma - 1),
+        # rho from one density pass at the generator's h (on the GPU)
+        c0 = sphx.Context(params, 0)
+        d0 = sphx.DeviceParticles.from_set(ps, "cuda:0")
+        o0 = sphx.Outputs(ps.n, "cuda:0")
+        g0 = sphx.Grid(c0, d0)
+        k0 = sphx.Tasks(c0, g0, d0)
+        sphx.fixed_h_pass(c0, g0, k0, d0, o0)
+        rho = o0.d["rho"].cpu().numpy().astype(np.float64)
+        k0.close()
+        g0.close()
+        c0.close()
+        gam = 5.0 / 3.0
+        ps.u = np.ascontiguousarray(((gam - 1.0) * ps.u.astype(np.float64)
+                                     / rho ** (gam - 1.0)).astype(np.float32))
+        params = type(params).from_buffer_copy(params)
+        params.flavour = sphx.FLAVOURS["entropy"]
+    dp = sphx.DeviceParticles.from_set(ps, "cuda:0")
+    out = sphx.Outputs(ps.n, "cuda:0")
+    ctx = sphx.Context(params, 0)
+    if dp.t["active"] is not None:
+        act = dp.t["active"]
+        h_guess = dp.t["h"].clone()
+        dp.t["active"] = None
+        g1 = sphx.Grid(ctx, dp)
+        k1 = sphx.Tasks(ctx, g1, dp)
+        sphx.step(ctx, g1, k1, dp, out)
+        k1.close()
+        g1.close()
+        dp.t["active"] = act
+        dp.t["h"].copy_(torch.where(act.bool(), h_guess, dp.t["h"]))
+    h0 = dp.t["h"].clone()
+    grid = sphx.Grid(ctx, dp)
+    tasks = sphx.Tasks(ctx, grid, dp)
+    for _ in range(warmup):
+        dp.t["h"].copy_(h0)
+        sphx.step(ctx, grid, tasks, dp, out)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    infos = []
+    a.record(stream)
+    for _ in range(steps):
+        dp.t["h"].copy_(h0)
+        infos.append(sphx.step(ctx, grid, tasks, dp, out)[1])
+    b.record(stream)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / steps
+    recv = dp.t["active"].bool() if dp.t["active"] is not None else slice(None)
+    n_dens = int(out.d["nngb"].to(torch.int64)[recv].sum())
+    n_force = int(out.f["nforce"].to(torch.int64)[recv].sum())
+    sums = out.sums.cpu().numpy()
+    rec = {"workload": desc, "n_particles": ps.n,
+           "active": int(dp.t["active"].sum()) if dp.t["active"] is not None else ps.n,
+           "flavour": flavour or "energy", "ms_per_step": ms,
+           "interactions_per_s": (n_dens + n_force) / (ms / 1e3), "n_dens": n_dens,
+           "n_force": n_force, "density_passes": infos[-1].passes,
+           "task_rebuilds_per_step": infos[-1].task_rebuilds, "steps": steps,
+           "momentum_err_rel": float(np.abs(sums[:3]).max() / max(sums[4], 1e-300)),
+           "timed": "HIP events on the stream around whole steps from the generator's h "
+                    "(h iteration with task rebuilds, ghost, force, FP64 sums); inputs "
+                    "resident; %.1f s with the set-up" % (time.perf_counter() - t0)}
+    tasks.close()
+    grid.close()
+    ctx.close()
+    log("bench: step leg %s%s: %s" % (name, " " + flavour if flavour else "", json.dumps(rec)))
+    return rec
+
+
+def sphenix_leg(params, n_steps=20):
+    """The SPHENIX row as a run: the Sedov box (64^3 jittered lattice, one unit
+    of energy in the central 32 particles) integrated over n_steps leapfrog
+    steps with one global step size (paper_2305_13380_amd.sphenix): each step
+    drifts, builds a new grid and task list, iterates h, runs the ghost and
+    force pass, the viscosity switch, the gradient loop, the conduction
+    parameter and the step-size limiter. Timed on the host clock (the step
+    size is read back every step), after one untimed step."""
+    import torch
+    from paper_2305_13380_amd import inputs
+    from paper_2305_13380_amd.sphenix import SphenixRun
+    ps = inputs.config_sedov(2)
+    ps.alpha_v[:] = 0.1
+    ps.alpha_c[:] = 0.0
+    run = SphenixRun(ps, params, c_cfl=0.1)
+    run.step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    n_int = 0
+    for _ in range(n_steps):
+        run.step()
+        n_int += int(run.out.d["nngb"].to(torch.int64).sum() +
+                     run.out.f["nforce"].to(torch.int64).sum())
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    rec = {"workload": CONFIGS["sedov"][0] + ", multi-step SPHENIX", "steps": n_steps,
+           "ms_per_step": wall / n_steps * 1e3, "interactions_per_s": n_int / wall,
+           "t_end": run.state.t,
+           "timed": "host clock over whole leapfrog steps (kick, drift, grid and task build, "
+                    "h iteration, ghost, force, viscosity switch, gradient loop, conduction "
+                    "parameter, step size with its read-back)"}
+    run.close()
+    log("bench: sphenix run: %s" % json.dumps(rec))
+    return rec
+
+
+def switch_bench(params, n, reps=200, sets=6):
     """The SPHENIX viscosity switch over n particles (sphx_alpha_v_update),
     inputs resident in HBM: reps launches timed with events on the stream they
-    run on; 28 bytes per particle (six FP32 words read, one written)."""
+    run on; 28 bytes per particle (six FP32 words read, one written). The
+    launches rotate over `sets` independent input sets whose total exceeds
+    the device's 256 MB last-level cache, so each launch streams from HBM."""
     import torch
     from paper_2305_13380_amd import sphx
     ctx = sphx.Context(params, 0)
     g = torch.Generator(device="cuda:0").manual_seed(7)
-    t = [torch.rand(n, device="cuda:0", generator=g) for _ in range(6)]
-    sphx.alpha_v_update(ctx, t[0], t[1], t[2], t[3], t[4], t[5], 1e-3)
+    t = [[torch.rand(n, device="cuda:0", generator=g) for _ in range(6)] for _ in range(sets)]
+    for x in t:
+        sphx.alpha_v_update(ctx, x[0], x[1], x[2], x[3], x[4], x[5], 1e-3)
     torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    a.record()
-    for _ in range(reps):
-        sphx.alpha_v_update(ctx, t[0], t[1], t[2], t[3], t[4], t[5], 1e-3)
-    b.record()
+    a.record(stream)
+    for k in range(reps):
+        x = t[k % sets]
+        sphx.alpha_v_update(ctx, x[0], x[1], x[2], x[3], x[4], x[5], 1e-3)
+    b.record(stream)
     torch.cuda.synchronize()
     per = a.elapsed_time(b) / reps / 1e3
     ctx.close()
     rec = {"particles": n, "us_per_launch": per * 1e6, "bytes_per_particle": 28,
            "GB_per_s": 28.0 * n / per / 1e9, "of_hbm_peak": 28.0 * n / per / 1e9 / PEAK_HBM_GBS,
-           "reps": reps, "timed": "back-to-back launches, events on the launch stream"}
+           "reps": reps, "input_sets": sets,
+           "working_set_MB": 28.0 * n * sets / 1e6,
+           "timed": "back-to-back launches rotating over the input sets (more than the "
+                    "256 MB last-level cache), events on the launch stream"}
     log("bench: viscosity switch: %s" % json.dumps(rec))
     return rec
 
@@ -392,6 +536,10 @@ def main():
                     help="smoothing kernel (default Wendland C2)")
     ap.add_argument("--no-tune", action="store_true",
                     help="default loop shapes instead of the autotuner's")
+    ap.add_argument("--shape", default="", metavar="DT,DW,FT,FW[,DB]",
+                    help="fixed loop shapes (density tile, density waves, force tile, force "
+                         "waves, density rounds: 0 per lane, 2 grouped) instead of the "
+                         "autotuner's")
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the serving-stream latency measurement")
     ap.add_argument("--no-fof", action="store_true",
@@ -400,6 +548,9 @@ def main():
                     help="timed calls of the friends-of-friends and gravity legs")
     ap.add_argument("--no-gravity", action="store_true",
                     help="skip the direct-summation gravity timing on the workload")
+    ap.add_argument("--no-legs", action="store_true",
+                    help="skip the other workloads of the step (Sedov box, large box, "
+                         "density-entropy flavour) and the multi-step SPHENIX run")
     ap.add_argument("--serving-requests", type=int, default=512)
     ap.add_argument("--serving-slots", type=int, default=8)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -459,7 +610,15 @@ def main():
     h0 = dp.t["h"].clone()
     torch.cuda.synchronize()
     shapes = "default"
-    if not args.no_tune:
+    if args.shape:
+        sh = [int(x) for x in args.shape.split(",")]
+        dt, dw, ft, fw = sh[:4]
+        db = sh[4] if len(sh) > 4 else 0
+        params.density_tile, params.density_waves, params.density_balance = dt, dw, db
+        params.force_tile, params.force_waves = ft, fw
+        shapes = {"density_tile": dt, "density_waves": dw, "density_balance": db,
+                  "force_tile": ft, "force_waves": fw}
+    elif not args.no_tune:
         # Loop shapes by the library's autotuner, on this workload at its
         # initial h (outside the timed region).
         t0 = time.perf_counter()
@@ -611,6 +770,13 @@ def main():
                      "flop_per_launch": per_launch},
     }
     del grid, tasks, out
+    if not args.no_legs and args.config == "clustered":
+        line["other_workloads"] = {
+            "sedov": step_leg("sedov", params, steps=10),
+            "large": step_leg("large", params, steps=3),
+            "clustered_entropy": step_leg("clustered", params, steps=5, flavour="entropy"),
+        }
+        line["sphenix_run"] = sphenix_leg(params)
     if not args.no_fof:
         line["fof"] = fof_bench(params, dp, args.fof_reps)
     if not args.no_gravity:

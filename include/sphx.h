@@ -95,13 +95,28 @@ typedef struct sphx_params {
     int32_t graph_passes;
     /* Density loop: 1 spreads each compute round's pair work evenly over the
      * wave's lanes (lists cut into chunks of one receiver each), 0 (default)
-     * lets every lane walk its own list. Changes the FP32 summation order. */
+     * lets every lane walk its own list; 2 takes the cell's receivers in
+     * groups of up to 16 at each flush of the candidate buffer, each group
+     * testing only the candidates near its own bounding box with several
+     * lanes per receiver (one wave per cell; the tile then changes the FP32
+     * summation order too). Changes the FP32 summation order. */
     int32_t density_balance;
     /* Smoothing kernel (Section 3.1 lists them; one smoothing length h for
      * all, cut-off H = gamma_k h): SPHX_KERNEL_*. Default Wendland C2. Set it
      * with sphx_params_set_kernel, which also sets the kernel's gamma_k. */
     int32_t kernel;
+    /* SPH flavour (Section 3.2): SPHX_FLAVOUR_DENSITY_ENERGY (default: the
+     * particles carry the internal energy u; Balsara-switched viscosity and
+     * artificial conduction) or SPHX_FLAVOUR_DENSITY_ENTROPY (the Gadget2
+     * solver: the u array holds the adiabat A, P = A rho^gamma, no
+     * conduction, and sphx_force_out.du_dt receives dA/dt = (gamma - 1)
+     * rho^(1 - gamma) times the viscous heating rate; the FP64 energy sum
+     * keeps the internal-energy rate the forces imply). */
+    int32_t flavour;
 } sphx_params;
+
+#define SPHX_FLAVOUR_DENSITY_ENERGY 0
+#define SPHX_FLAVOUR_DENSITY_ENTROPY 1
 
 #define SPHX_KERNEL_WENDLAND_C2 0
 #define SPHX_KERNEL_WENDLAND_C4 1
@@ -299,8 +314,9 @@ sphx_status sphx_step(sphx_ctx *ctx, sphx_grid *grid, sphx_tasks **tasks, sphx_p
                       sphx_density_out *dens, sphx_ghost_out *gst, sphx_force_out *out,
                       double *d_sums6, void *stream, sphx_step_info *info);
 
-/* Autotuner: times each density-loop shape (tile x waves, unbalanced rounds;
- * density_balance is returned as given) over whole steps (as sphx_step, pass
+/* Autotuner: times each density-loop shape (tile x waves with per-lane
+ * rounds, and tiles with grouped rounds; the balanced rounds are not among
+ * them) over whole steps (as sphx_step, pass
  * by pass, from the particles' current h, iterating on a device copy of h;
  * the time of the step's density launches, HIP events around each), and each
  * force-loop shape on force passes at the converged state; the shortest of
@@ -378,6 +394,76 @@ sphx_status sphx_gravity(sphx_ctx *ctx, const sphx_particles *in, double G, doub
 sphx_status sphx_alpha_v_update(sphx_ctx *ctx, int64_t n, const float *div_old,
                                 const float *div_new, const float *c, const float *h,
                                 const float *v_sig, double dt, float *alpha_v, void *stream);
+
+/* SPHENIX gradient loop (Section 3.3), after a step on this grid and task
+ * list (the tasks must cover every active particle's H, as sphx_step leaves
+ * them). For every active particle i, over the particles j != i with
+ * 0 < r_ij < H_i (FP32 arithmetic in the cell frame, like the density pass):
+ *   lap_u[i]       = 2 sum_j (m_j / rho_j) (u_i - u_j) (dW/dr)(r_ij, h_i) / r_ij,
+ *                    the Laplacian of u that drives the conduction parameter
+ *                    (Brookshaw's second-derivative estimator; the paper names
+ *                    the Laplacian without printing an estimator);
+ *   v_c[i]         = max_j |v_ij . x_ij| / r_ij + sqrt(2 |P_i - P_j| / (rho_i + rho_j)),
+ *                    the largest pair conduction speed (0 without neighbours);
+ *   alpha_v_max[i] = the largest alpha_V among i and those j (the shock
+ *                    limiter's input).
+ * Reads positions, velocities, masses and u of the grid (as copied at its
+ * build), and h, alpha_v (in), rho, P (device, caller order, n FP32 each:
+ * e.g. sphx_density_out.rho and sphx_ghost_out.P) of every particle. Outputs:
+ * device FP32 arrays of n in caller order, written for active particles only.
+ * Uses the grid's scratch (not safe concurrently with another call on the
+ * same grid). Asynchronous. */
+sphx_status sphx_gradient(sphx_ctx *ctx, sphx_grid *grid, const sphx_tasks *tasks,
+                          const sphx_particles *in, const float *rho, const float *P,
+                          float *lap_u, float *v_c, float *alpha_v_max, void *stream);
+
+/* SPHENIX conduction parameter over a step dt (Section 3.3), per active
+ * particle i < n (active NULL: all): the evolution equation
+ *   d alpha_c / dt = beta_c H lap_u / sqrt(u) - (alpha_c - alpha_c,min) v_c / H
+ * (H = gamma_k h; beta_c = 1, alpha_c,min = 0 as printed) has constant
+ * coefficients over the step and is integrated exactly (alpha_inf + (alpha -
+ * alpha_inf) exp(-v_c dt / H), alpha_inf = alpha_c,min + S H / v_c with
+ * S = beta_c H lap_u / sqrt(u); alpha + S dt where v_c = 0), then capped by
+ * the shock limiter at alpha_c,max (1 - alpha_v_max / alpha_V,max) (1 and 2
+ * as printed) and kept >= 0. Inputs from sphx_gradient (lap_u, v_c,
+ * alpha_v_max) and the particles (u, h); alpha_c is updated in place.
+ * Device FP32 arrays of n, caller order. dt > 0 and finite, n >= 0, else
+ * E_INVALID. Asynchronous. */
+sphx_status sphx_alpha_c_update(sphx_ctx *ctx, int64_t n, const float *lap_u, const float *u,
+                                const float *h, const float *v_c, const float *alpha_v_max,
+                                const uint8_t *active, double dt, float *alpha_c, void *stream);
+
+/* Time-step sizes (Section 3.4): every particle's CFL step
+ * dt_cfl = c_cfl H / v_sig (H = gamma_k h, v_sig the force pass's signal
+ * velocity; the paper names the condition without printing it), then for
+ * every active particle the first limiter: dt[i] = min(dt_cfl,i, delta
+ * min_j dt_cfl,j) over the particles j != i with r_ij < max(H_i, H_j) (the
+ * force-loop neighbours; delta = 4 in the paper). dt (device FP32, n, caller
+ * order) is written for active particles; d_dt_min (device, 1 FP32, or NULL)
+ * receives the smallest of them (+inf when none is active), the step of a
+ * run with one global step. 0 < c_cfl, 1 <= delta, both finite, else
+ * E_INVALID. Uses the grid's scratch. Asynchronous. */
+sphx_status sphx_timestep(sphx_ctx *ctx, sphx_grid *grid, const sphx_tasks *tasks,
+                          const sphx_particles *in, const float *v_sig, double c_cfl,
+                          double delta, float *dt, float *d_dt_min, void *stream);
+
+/* Leapfrog half kick (Section 2.4, kick-drift-kick): for every active
+ * particle i < n (active NULL: all), v_out = v + a dt_half, u_out = u +
+ * du_dt dt_half (device FP32 arrays of n, caller order; the outputs may be
+ * the inputs, for an update in place, or other arrays, for the prediction of
+ * v and u at the end of a drift). Asynchronous. */
+sphx_status sphx_kick(sphx_ctx *ctx, int64_t n, const float *vx, const float *vy,
+                      const float *vz, const float *u, const float *ax, const float *ay,
+                      const float *az, const float *du_dt, const uint8_t *active, double dt_half,
+                      float *vx_out, float *vy_out, float *vz_out, float *u_out, void *stream);
+
+/* Leapfrog drift (Section 2.4): x += v dt for every particle, in FP64 on the
+ * caller's position arrays (updated in place), wrapped into [0, box) in a
+ * periodic box. A grid built before the drift no longer matches: build a
+ * new one. Asynchronous. */
+sphx_status sphx_drift(sphx_ctx *ctx, int64_t n, double *x, double *y, double *z,
+                       const float *vx, const float *vy, const float *vz, double dt,
+                       void *stream);
 
 /* Kernel timing for measurement tools. sphx_profile_enable(ctx, 1) clears the
  * statistics and starts recording a pair of HIP events around every launch of

@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsphx.so")
 SOURCES = ["grid.hip", "tasks.hip", "density.hip", "lists.hip", "ghost.hip", "force.hip",
-           "graph.hip", "fof.hip", "gravity.hip", "sphenix.hip", "api.cpp"]
+           "graph.hip", "fof.hip", "gravity.hip", "sphenix.hip", "integrate.hip", "api.cpp"]
 ARCH = os.environ.get("SPHX_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

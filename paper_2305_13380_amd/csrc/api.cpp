@@ -131,6 +131,7 @@ void sphx_params_default(sphx_params *p)
     p->graph_passes = 0;
     p->density_balance = 0;
     p->kernel = SPHX_KERNEL_WENDLAND_C2;
+    p->flavour = SPHX_FLAVOUR_DENSITY_ENERGY;
 }
 
 sphx_status sphx_params_set_kernel(sphx_params *p, int32_t kernel)
@@ -181,9 +182,13 @@ sphx_status sphx_ctx_create(const sphx_params *p, int hip_device, sphx_ctx **out
         set_error("sphx_ctx_create: unknown kernel (SPHX_KERNEL_*)");
         return SPHX_E_INVALID;
     }
+    if (p->flavour != SPHX_FLAVOUR_DENSITY_ENERGY && p->flavour != SPHX_FLAVOUR_DENSITY_ENTROPY) {
+        set_error("sphx_ctx_create: unknown flavour (SPHX_FLAVOUR_*)");
+        return SPHX_E_INVALID;
+    }
     if (p->graph_passes < 0 || p->graph_passes > 64 || p->density_balance < 0 ||
-        p->density_balance > 1) {
-        set_error("sphx_ctx_create: graph_passes must be 0..64 and density_balance 0 or 1");
+        p->density_balance > 2) {
+        set_error("sphx_ctx_create: graph_passes must be 0..64 and density_balance 0, 1 or 2");
         return SPHX_E_INVALID;
     }
     int ndev = 0;
@@ -306,6 +311,92 @@ sphx_status sphx_alpha_v_update(sphx_ctx *ctx, int64_t n, const float *div_old,
     }
     SPHX_HIP(hipSetDevice(ctx->device));
     return alpha_v_launch(ctx, n, div_old, div_new, c, h, v_sig, dt, alpha_v, as_stream(stream));
+}
+
+sphx_status sphx_gradient(sphx_ctx *ctx, sphx_grid *grid, const sphx_tasks *tasks,
+                          const sphx_particles *in, const float *rho, const float *P,
+                          float *lap_u, float *v_c, float *alpha_v_max, void *stream)
+{
+    SPHX_TRY(check_handles(ctx, grid, tasks, in));
+    SPHX_TRY(check_particles(in, false));
+    if (!tasks || (in->n && (!rho || !P || !lap_u || !v_c || !alpha_v_max))) {
+        set_error("sphx_gradient: NULL task list, state or output array");
+        return SPHX_E_INVALID;
+    }
+    SPHX_HIP(hipSetDevice(ctx->device));
+    return gradient_launch(ctx, grid, tasks, in, rho, P, lap_u, v_c, alpha_v_max,
+                           as_stream(stream));
+}
+
+sphx_status sphx_alpha_c_update(sphx_ctx *ctx, int64_t n, const float *lap_u, const float *u,
+                                const float *h, const float *v_c, const float *alpha_v_max,
+                                const uint8_t *active, double dt, float *alpha_c, void *stream)
+{
+    if (!ctx || n < 0 || !(dt > 0.0) || !std::isfinite(dt)) {
+        set_error("sphx_alpha_c_update: need a context, n >= 0 and a finite dt > 0");
+        return SPHX_E_INVALID;
+    }
+    if (n > 0 && (!lap_u || !u || !h || !v_c || !alpha_v_max || !alpha_c)) {
+        set_error("sphx_alpha_c_update: NULL array");
+        return SPHX_E_INVALID;
+    }
+    SPHX_HIP(hipSetDevice(ctx->device));
+    return alpha_c_launch(ctx, n, lap_u, u, h, v_c, alpha_v_max, active, dt, alpha_c,
+                          as_stream(stream));
+}
+
+sphx_status sphx_timestep(sphx_ctx *ctx, sphx_grid *grid, const sphx_tasks *tasks,
+                          const sphx_particles *in, const float *v_sig, double c_cfl,
+                          double delta, float *dt, float *d_dt_min, void *stream)
+{
+    SPHX_TRY(check_handles(ctx, grid, tasks, in));
+    SPHX_TRY(check_particles(in, false));
+    if (!(c_cfl > 0.0) || !std::isfinite(c_cfl) || !(delta >= 1.0) || !std::isfinite(delta)) {
+        set_error("sphx_timestep: need 0 < c_cfl < inf and 1 <= delta < inf");
+        return SPHX_E_INVALID;
+    }
+    if (!tasks || (in->n && (!v_sig || !dt))) {
+        set_error("sphx_timestep: NULL task list, v_sig or dt");
+        return SPHX_E_INVALID;
+    }
+    SPHX_HIP(hipSetDevice(ctx->device));
+    return timestep_launch(ctx, grid, tasks, in, v_sig, c_cfl, delta, dt, d_dt_min,
+                           as_stream(stream));
+}
+
+sphx_status sphx_kick(sphx_ctx *ctx, int64_t n, const float *vx, const float *vy,
+                      const float *vz, const float *u, const float *ax, const float *ay,
+                      const float *az, const float *du_dt, const uint8_t *active, double dt_half,
+                      float *vx_out, float *vy_out, float *vz_out, float *u_out, void *stream)
+{
+    if (!ctx || n < 0 || !std::isfinite(dt_half)) {
+        set_error("sphx_kick: need a context, n >= 0 and a finite dt_half");
+        return SPHX_E_INVALID;
+    }
+    if (n > 0 && (!vx || !vy || !vz || !u || !ax || !ay || !az || !du_dt || !vx_out ||
+                  !vy_out || !vz_out || !u_out)) {
+        set_error("sphx_kick: NULL array");
+        return SPHX_E_INVALID;
+    }
+    SPHX_HIP(hipSetDevice(ctx->device));
+    return kick_launch(n, vx, vy, vz, u, ax, ay, az, du_dt, active, dt_half, vx_out, vy_out,
+                       vz_out, u_out, as_stream(stream));
+}
+
+sphx_status sphx_drift(sphx_ctx *ctx, int64_t n, double *x, double *y, double *z,
+                       const float *vx, const float *vy, const float *vz, double dt,
+                       void *stream)
+{
+    if (!ctx || n < 0 || !std::isfinite(dt)) {
+        set_error("sphx_drift: need a context, n >= 0 and a finite dt");
+        return SPHX_E_INVALID;
+    }
+    if (n > 0 && (!x || !y || !z || !vx || !vy || !vz)) {
+        set_error("sphx_drift: NULL array");
+        return SPHX_E_INVALID;
+    }
+    SPHX_HIP(hipSetDevice(ctx->device));
+    return drift_launch(ctx, n, x, y, z, vx, vy, vz, dt, as_stream(stream));
 }
 
 sphx_status sphx_gravity(sphx_ctx *ctx, const sphx_particles *in, double G, double H,
@@ -706,9 +797,10 @@ sphx_status sphx_autotune(sphx_ctx *ctx, sphx_grid *grid, sphx_tasks *tasks, sph
         // Density shapes (tile, waves, balance) on whole steps from the
         // caller's h: the passes after the first run on ever fewer receivers,
         // and the best shape for the full first pass is not always the best
-        // for the step. (The balanced rounds keep their own parameter: never
-        // measurably faster, they are not among the tuned shapes.)
-        const int32_t dshape[5][3] = {{128, 1, 0}, {64, 1, 0}, {256, 1, 0}, {128, 2, 0}, {64, 2, 0}};
+        // for the step. (The balanced rounds, never measurably faster, are
+        // not among the tuned shapes; the grouped rounds are.)
+        const int32_t dshape[7][3] = {{128, 1, 0}, {64, 1, 0}, {256, 1, 0}, {128, 2, 0},
+                                      {64, 2, 0},  {128, 1, 2}, {256, 1, 2}};
         double best = 1e300;
         int32_t bt = 128, bw = 1, bb = 0;
         for (auto &sh : dshape) {

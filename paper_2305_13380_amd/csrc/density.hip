@@ -476,6 +476,283 @@ __global__ __launch_bounds__(64 * NW) void k_density(
     dens_finish<K>(S, hr, invHr, sr, gr, o);
 }
 
+// Grouped rounds (density_balance = 2). The cell's sources are loaded, culled
+// against the box of all the receivers that need work and buffered as in
+// k_density; at each flush the receivers are taken in groups of up to 16
+// consecutive sorted indices (Morton order: each group is spatially compact)
+// with precomputed bounding boxes and radii. For each group in turn the
+// wave compacts the buffered candidates that lie within the group's radius
+// of its box, and tests and sums only those, with nrep = 64 / (group size)
+// lanes per receiver (rounded down to a power of two): replica q takes every
+// nrep-th candidate of the group's list from q. So a candidate is tested by
+// the receivers near it rather than by every receiver of the cell, and each
+// receiver's pair work is spread evenly over its replicas. After each
+// group's flush the replicas' partial sums are added by a butterfly and
+// accumulated per receiver in LDS, in flush order: results are reproducible
+// (they depend on the buffer size, which is fixed per instantiation).
+constexpr int kGroupMax = 16;  // receivers per group
+
+template <int CAP, int K>
+__global__ __launch_bounds__(64) void k_density_grp(
+    int64_t n_leaves, int64_t nb_padded, const int32_t *__restrict__ order,
+    const int32_t *__restrict__ leaf_start, const int32_t *__restrict__ perm,
+    const float4 *__restrict__ q0, const float4 *__restrict__ q1,
+    const uint8_t *__restrict__ need, const float *__restrict__ hs,
+    const float *__restrict__ radius, const int32_t *__restrict__ toff,
+    const Task *__restrict__ task, const float4 *__restrict__ ext, float gamma_k, float far,
+    DensOut o, int32_t *__restrict__ counters, const int32_t *__restrict__ skip)
+{
+    if (skip && *skip)
+        return;  // a captured pass with nothing left to do
+    static_assert(CAP >= 64 && CAP <= 256, "candidate slots: one task's sources, 8-bit slots");
+    const int64_t L = leaf_of_block(blockIdx.x, nb_padded, order);
+    if (L >= n_leaves)
+        return;
+    const int lane = threadIdx.x;
+    const int32_t s0 = leaf_start[L];
+    const int32_t cnt = leaf_start[L + 1] - s0;
+    const bool valid = lane < cnt;
+    const int32_t s = s0 + (valid ? lane : 0);
+    const float hi0 = hs[s];
+    const bool act = valid && need[s];
+    const uint64_t amask = __ballot(act);
+    if (amask == 0)
+        return;
+    const int n_act = __popcll(amask);
+
+    __shared__ float4 cp[CAP + 1];  // candidates: x, y, z (cell frame), m; slot CAP: dummy
+    __shared__ float4 cv[CAP + 1];  // vx, vy, vz
+    // per-lane lists: a replica sees at most CAP / 4 of a flush's candidates
+    // (groups of up to 16 receivers have 4 or more lanes each)
+    constexpr int LMAX = CAP / 4 < 32 ? 32 : CAP / 4;
+    constexpr int LSTRIDE = LMAX + 4;  // an odd number of dwords
+    __shared__ uint32_t lst_w[LSTRIDE * 16];
+    __shared__ float4 rtp[64];           // active receivers by rank: position, m
+    __shared__ float4 rtv[64];           // velocity, h
+    __shared__ uint8_t rts[64];          // rank -> index in the cell
+    __shared__ float acc[kSums][64];     // the receivers' sums by rank
+    __shared__ float4 gbox[64 / kGroupMax][2];  // group boxes: lo (w = R^2), hi
+    __shared__ uint8_t gidx[CAP];        // the current group's candidate slots
+    uint8_t *lst = reinterpret_cast<uint8_t *>(lst_w);
+    uint8_t *my_list = lst + lane * LSTRIDE;
+
+    const float4 pi = q0[s];
+    const float H = gamma_k * (act ? hi0 : 1.0f);
+    if (act) {
+        const int k = lanes_below(amask);
+        const float4 vi = q1[s];
+        rtp[k] = pi;
+        rtv[k] = make_float4(vi.x, vi.y, vi.z, hi0);
+        rts[k] = uint8_t(lane);
+        if (H > radius[L] && counters)
+            atomicAdd(counters + 3, 1);
+    }
+#pragma unroll
+    for (int k = 0; k < kSums; ++k)
+        acc[k][lane] = 0.0f;
+    if (lane == 0) {
+        cp[CAP] = make_float4(far, far, far, 0.0f);
+        cv[CAP] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    }
+    // the box of all the active receivers and their largest radius
+    const float inf = __builtin_inff();
+    float3 lo = make_float3(act ? pi.x : inf, act ? pi.y : inf, act ? pi.z : inf);
+    float3 hb = make_float3(act ? pi.x : -inf, act ? pi.y : -inf, act ? pi.z : -inf);
+    lo.x = wave_minf(lo.x);
+    lo.y = wave_minf(lo.y);
+    lo.z = wave_minf(lo.z);
+    hb.x = wave_maxf(hb.x);
+    hb.y = wave_maxf(hb.y);
+    hb.z = wave_maxf(hb.z);
+    const float R = wave_maxf(act ? H : 0.0f);
+    const float R2 = R * R;
+    const int NG = (n_act + kGroupMax - 1) / kGroupMax;
+    wave_sync();  // the receiver table
+    // each group's box and radius
+    for (int g = 0; g < NG; ++g) {
+        const int r0 = g * kGroupMax;
+        const int kg = min(kGroupMax, n_act - r0);
+        const bool mine = lane < kg;
+        const float4 p = rtp[r0 + (mine ? lane : 0)];
+        const float Hg = mine ? gamma_k * rtv[r0 + (mine ? lane : 0)].w : 0.0f;
+        float3 glo = make_float3(mine ? p.x : inf, mine ? p.y : inf, mine ? p.z : inf);
+        float3 ghi = make_float3(mine ? p.x : -inf, mine ? p.y : -inf, mine ? p.z : -inf);
+        glo.x = wave_minf(glo.x);
+        glo.y = wave_minf(glo.y);
+        glo.z = wave_minf(glo.z);
+        ghi.x = wave_maxf(ghi.x);
+        ghi.y = wave_maxf(ghi.y);
+        ghi.z = wave_maxf(ghi.z);
+        const float Rg = wave_maxf(Hg);
+        if (lane == 0) {
+            gbox[g][0] = make_float4(glo.x, glo.y, glo.z, Rg * Rg);
+            gbox[g][1] = make_float4(ghi.x, ghi.y, ghi.z, 0.0f);
+        }
+    }
+    wave_sync();
+
+    int nc = 0;  // buffered candidates (wave-uniform)
+    auto flush = [&]() __attribute__((always_inline)) {
+        wave_sync();
+        for (int g = 0; g < NG; ++g) {
+            const int r0 = g * kGroupMax;
+            const int kg = min(kGroupMax, n_act - r0);
+            int nrep = 1;
+            while (2 * nrep * kg <= 64)
+                nrep *= 2;
+            const int r = lane / nrep;
+            const int q = lane & (nrep - 1);
+            const bool ract = r < kg;
+            const int rank = r0 + (ract ? r : 0);
+            const float4 pr = rtp[rank];
+            const float4 vr = rtv[rank];
+            const float Hr = gamma_k * vr.w;
+            const float H2r = ract ? Hr * Hr : -1.0f;
+            const float invHr = fast_rcp(Hr);
+            const float4 b0 = gbox[g][0], b1 = gbox[g][1];
+            const float3 glo = make_float3(b0.x, b0.y, b0.z);
+            const float3 ghi = make_float3(b1.x, b1.y, b1.z);
+            // the group's candidates, buffer order kept
+            int len = 0;
+            for (int c0 = 0; c0 < nc; c0 += 64) {
+                const int slot = c0 + lane;
+                bool in = false;
+                if (slot < nc) {
+                    const float4 p = cp[slot];
+                    in = box_dist2(p.x, p.y, p.z, glo, ghi) < b0.w;
+                }
+                const uint64_t m = __ballot(in);
+                if (in)
+                    gidx[len + lanes_below(m)] = uint8_t(slot);
+                len += __popcll(m);
+            }
+            wave_sync();
+            float S[kSums] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+            int myn = 0;
+            auto compute = [&]() __attribute__((always_inline)) {
+                S[8] += float(myn);
+                for (int k = 0; __any(k < myn); k += 4) {
+                    const uint32_t four = *reinterpret_cast<const uint32_t *>(my_list + k);
+                    float4 p[4], v[4];
+#pragma unroll
+                    for (int qq = 0; qq < 4; ++qq) {
+                        const int c = k + qq < myn ? int((four >> (8 * qq)) & 0xffu) : CAP;
+                        p[qq] = cp[c];
+                        v[qq] = cv[c];
+                    }
+#pragma unroll
+                    for (int qq = 0; qq < 4; ++qq)
+                        dens_pair<false, K>(S, pr, vr, invHr, p[qq], v[qq], true);
+                }
+                myn = 0;
+            };
+            // replica q takes the group's candidates q, q + nrep, ...; entries
+            // past the list read the dummy source, which no test accepts
+            const int m_end = (len + nrep - 1) / nrep;
+            for (int m = 0; m < m_end; m += 4) {
+                int cq[4];
+                float4 pq[4];
+#pragma unroll
+                for (int qq = 0; qq < 4; ++qq) {
+                    const int k = q + (m + qq) * nrep;
+                    cq[qq] = k < len ? int(gidx[k]) : CAP;
+                    pq[qq] = cp[cq[qq]];
+                }
+#pragma unroll
+                for (int qq = 0; qq < 4; ++qq) {
+                    const float r2 = dist2(pr.x - pq[qq].x, pr.y - pq[qq].y, pr.z - pq[qq].z);
+                    my_list[myn] = uint8_t(cq[qq]);
+                    myn += r2 < H2r ? 1 : 0;
+                }
+                if (__any(myn > LMAX - 4))
+                    compute();
+            }
+            compute();
+            // the replicas' sums (butterfly), added to the receiver's
+            for (int x = 1; x < nrep; x <<= 1)
+#pragma unroll
+                for (int k = 0; k < kSums; ++k)
+                    S[k] += __shfl_xor(S[k], x, 64);
+            if (ract && q == 0)
+#pragma unroll
+                for (int k = 0; k < kSums; ++k)
+                    acc[k][rank] += S[k];
+            wave_sync();  // the group list is rewritten by the next group
+        }
+        nc = 0;
+    };
+
+    // Append the kept sources of one task to the candidate buffer.
+    auto emit = [&](const float4 &p, const float4 &v, bool keep) __attribute__((always_inline)) {
+        const uint64_t mask = __ballot(keep);
+        if (mask == 0)
+            return;
+        const int tot = __popcll(mask);
+        if (nc + tot > CAP)
+            flush();
+        const int pos = nc + lanes_below(mask);
+        if (keep) {
+            cp[pos] = p;
+            cv[pos] = v;
+        }
+        nc += tot;
+    };
+
+    const int32_t ta = toff[L], tn = toff[L + 1] - ta;
+    for (int32_t tb = ta; tb < ta + tn; tb += 64) {
+        const int nb = min(64, ta + tn - tb);
+        TaskRegs tr;
+        tr.load(task, tb + lane, lane < nb);
+        // whole source cells beyond R of the receivers' box are skipped
+        if (lane < nb && task_box_dist2(tr.b.x, tr.b.y, tr.b.z, ext[tr.a.w], lo, hb) >= R2)
+            tr.a.y = 0;
+        for (int u = 0; u < nb; u += 4) {
+            int j0[4], jc[4];
+            float ox[4], oy[4], oz[4];
+#pragma unroll
+            for (int qq = 0; qq < 4; ++qq) {
+                const int k = min(u + qq, nb - 1);
+                j0[qq] = bcast(tr.a.x, k);
+                jc[qq] = (u + qq < nb) ? bcast(tr.a.y, k) : 0;
+                ox[qq] = bcastf(tr.b.x, k);
+                oy[qq] = bcastf(tr.b.y, k);
+                oz[qq] = bcastf(tr.b.z, k);
+            }
+            float4 p[4], v[4];
+#pragma unroll
+            for (int qq = 0; qq < 4; ++qq) {
+                const bool in = lane < jc[qq];
+                p[qq] = in ? q0[j0[qq] + lane] : make_float4(0.f, 0.f, 0.f, 0.f);
+                v[qq] = in ? q1[j0[qq] + lane] : make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+            bool keep[4];
+#pragma unroll
+            for (int qq = 0; qq < 4; ++qq) {
+                p[qq].x += ox[qq];
+                p[qq].y += oy[qq];
+                p[qq].z += oz[qq];
+                keep[qq] = lane < jc[qq] && box_dist2(p[qq].x, p[qq].y, p[qq].z, lo, hb) < R2;
+            }
+            emit(p[0], v[0], keep[0]);
+            emit(p[1], v[1], keep[1]);
+            emit(p[2], v[2], keep[2]);
+            emit(p[3], v[3], keep[3]);
+        }
+    }
+    if (nc > 0)
+        flush();
+    wave_sync();
+    if (lane < n_act) {
+        float T[kSums];
+#pragma unroll
+        for (int k = 0; k < kSums; ++k)
+            T[k] = acc[k][lane];
+        const float hr = rtv[lane].w;
+        const int32_t sr = s0 + int32_t(rts[lane]);
+        dens_finish<K>(T, hr, fast_rcp(gamma_k * hr), sr, perm[sr], o);
+    }
+}
+
 // List pass: lane = receiver s = 64 b + lane of 64-block b. Entries decode to
 // (task, source index in its leaf); the task's offset half gives the source's
 // first sorted index and the FP32 offset into the receiver's frame. Entries
@@ -584,11 +861,27 @@ sphx_status stale_count_launch(const sphx_ctx *ctx, const sphx_grid *g, const sp
 
 // The loop shapes of one kernel kind.
 template <int K>
-static void density_shapes(int tile, int waves, bool bal, int64_t nbp, const sphx_ctx *ctx,
+static void density_shapes(int tile, int waves, bool bal, bool grouped, int64_t nbp,
+                           const sphx_ctx *ctx,
                            const sphx_grid *g, const sphx_tasks *t, const float *lr,
                            const DensOut &dout, float far, int32_t *counters,
                            const int32_t *skip, hipStream_t s)
 {
+    if (grouped && !lr) {
+#define SPHX_DENSITY_GRP(CAP_)                                                                 \
+    k_density_grp<CAP_, K><<<unsigned(nbp), 64, 0, s>>>(                                      \
+        g->n_leaves, nbp, t->order, g->leaf_start, g->perm, g->q0, g->q1, g->need, g->hs,      \
+        t->radius, t->off, t->task, g->leaf_ext, float(ctx->p.gamma_k), far, dout, counters,   \
+        skip)
+        if (tile == 64)
+            SPHX_DENSITY_GRP(64);
+        else if (tile == 128)
+            SPHX_DENSITY_GRP(128);
+        else
+            SPHX_DENSITY_GRP(256);
+#undef SPHX_DENSITY_GRP
+        return;
+    }
 #define SPHX_DENSITY_LAUNCH(CAP_, NW_, BAL_)                                                   \
     k_density<CAP_, NW_, BAL_, K><<<unsigned(nbp), 64 * NW_, 0, s>>>(                             \
         g->n_leaves, nbp, t->order, g->leaf_start, g->perm, g->q0, g->q1, g->need, g->hs,      \
@@ -629,13 +922,15 @@ sphx_status density_launch(const sphx_ctx *ctx, const sphx_grid *g, const sphx_t
     const int tile = ctx->p.density_tile ? ctx->p.density_tile : 128;
     const int waves = ctx->p.density_waves ? ctx->p.density_waves : 1;
     const bool bal = ctx->p.density_balance == 1;
+    const bool grouped = ctx->p.density_balance == 2;
     const float *lr = use_lists ? g->lrad : nullptr;
     const DensOut dout = dens_out(g, o);
     // the dummy source: 4 box lengths out, more than 3 box lengths from any
     // receiver (cell-relative coordinates), while every H is below a third
     const float far = float(4.0 * std::max(ctx->p.box[0], std::max(ctx->p.box[1], ctx->p.box[2])));
     SPHX_HIP(ctx->prof->begin(0, s));
-    SPHX_WITH_KERNEL(ctx->p.kernel, density_shapes<KK>(tile, waves, bal, nbp, ctx, g, t, lr, dout,
+    SPHX_WITH_KERNEL(ctx->p.kernel, density_shapes<KK>(tile, waves, bal, grouped, nbp, ctx, g, t,
+                                                       lr, dout,
                                                        far, counters, skip, s));
     SPHX_HIP(hipGetLastError());
     SPHX_HIP(ctx->prof->end(0, s));

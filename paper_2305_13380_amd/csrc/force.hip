@@ -41,7 +41,7 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
-constexpr int kFSums = 6;  // ax, ay, az, du, vsig, count
+constexpr int kFSums = 7;  // ax, ay, az, du, vsig, count, viscous part of du
 
 // CAP >= 64: a task's kept sources (up to 64) always fit after a flush.
 // Inside a step the ghost leaves its results in sorted order only, and the
@@ -54,7 +54,11 @@ struct StepOut {
     const float4 *g2;
 };
 
-template <int CAP, int NW, int K>
+// ENT: the density-entropy flavour (Section 3.2): the particles' u is the
+// adiabat A (their P came from A rho^gamma in the ghost), no conduction, and
+// the output rate is dA/dt = (gamma - 1) rho^(1 - gamma) du/dt|visc; the
+// FP64 energy sum keeps the internal-energy rate.
+template <int CAP, int NW, int K, bool ENT>
 __global__ __launch_bounds__(64 * NW) void k_force(
     int64_t n_leaves, int64_t nb_padded, const int32_t *__restrict__ order,
     const int32_t *__restrict__ leaf_start,
@@ -66,7 +70,7 @@ __global__ __launch_bounds__(64 * NW) void k_force(
     float far,
     float *__restrict__ o_ax, float *__restrict__ o_ay, float *__restrict__ o_az,
     float *__restrict__ o_du, float *__restrict__ o_vsig, int32_t *__restrict__ o_nf,
-    double *__restrict__ fsum, const int32_t *__restrict__ gate, StepOut so)
+    double *__restrict__ fsum, const int32_t *__restrict__ gate, StepOut so, float gamma_gas)
 {
     if (gate && *gate)
         return;  // a captured step whose iteration is not finished
@@ -157,7 +161,7 @@ __global__ __launch_bounds__(64 * NW) void k_force(
     const float fi = gi1.x, Bi = gi1.y, Ai = gi1.z;
     const float acPi = ai.y * Pi;
 
-    float ax = 0.f, ay = 0.f, az = 0.f, du = 0.f;
+    float ax = 0.f, ay = 0.f, az = 0.f, du = 0.f, duv = 0.f;
     float vsig = 2.0f * ci;
     int32_t nf = 0;
     int nc = 0;
@@ -208,7 +212,12 @@ __global__ __launch_bounds__(64 * NW) void k_force(
         const float psum = Pi + a.w;
         const float ac = psum > 0.0f ? (acPi + c2.x) * fast_rcp(psum) : 0.0f;
         const float vc = fabsf(vdote) + fast_sqrt(2.0f * fabsf(Pi - a.w) * irs);
-        const float dui = m * (Agi + 0.25f * nu * G) * vdote + m * ac * vc * (vi.w - c2.y) * G * irs;
+        const float dvi = m * (0.25f * nu * G) * vdote;
+        const float dui = ENT ? m * Agi * vdote + dvi
+                              : m * (Agi + 0.25f * nu * G) * vdote +
+                                    m * ac * vc * (vi.w - c2.y) * G * irs;
+        if (ENT)
+            duv += dvi;
         ax -= m * acc * ex;
         ay -= m * acc * ey;
         az -= m * acc * ez;
@@ -363,12 +372,14 @@ __global__ __launch_bounds__(64 * NW) void k_force(
         ay += __shfl_xor(ay, o, 64);
         az += __shfl_xor(az, o, 64);
         du += __shfl_xor(du, o, 64);
+        if (ENT)
+            duv += __shfl_xor(duv, o, 64);
         vsig = fmaxf(vsig, __shfl_xor(vsig, o, 64));
         nf += __shfl_xor(nf, o, 64);
     }
 
     // the receiver's own particle was listed as a pair at r = 0 and counted
-    float F[kFSums] = {ax, ay, az, du, vsig, float(nf - (w == 0 && ract ? 1 : 0))};
+    float F[kFSums] = {ax, ay, az, du, vsig, float(nf - (w == 0 && ract ? 1 : 0)), duv};
     if (NW > 1) {
         __syncthreads();
         // the other waves' partial sums (own array: small tiles leave too
@@ -385,6 +396,7 @@ __global__ __launch_bounds__(64 * NW) void k_force(
                 F[k] += red[((w2 - 1) * kFSums + k) * 64 + lane];
             F[4] = fmaxf(F[4], red[((w2 - 1) * kFSums + 4) * 64 + lane]);
             F[5] += red[((w2 - 1) * kFSums + 5) * 64 + lane];
+            F[6] += red[((w2 - 1) * kFSums + 6) * 64 + lane];
         }
     }
     double m0 = 0, m1 = 0, m2 = 0, e = 0, sa_ = 0, sd = 0;
@@ -392,7 +404,7 @@ __global__ __launch_bounds__(64 * NW) void k_force(
         o_ax[gr] = F[0];
         o_ay[gr] = F[1];
         o_az[gr] = F[2];
-        o_du[gr] = F[3];
+        o_du[gr] = ENT ? (gamma_gas - 1.0f) * powf(rhoi, 1.0f - gamma_gas) * F[6] : F[3];
         o_vsig[gr] = F[4];
         if (o_nf)
             o_nf[gr] = int32_t(F[5]);
@@ -555,18 +567,18 @@ sphx_status noalloc_scratch(int device, double **out)
 }
 
 // The loop shapes of one kernel kind.
-template <int K>
+template <int K, bool ENT>
 static void force_shapes(int tile, int waves, int64_t nbp, const sphx_ctx *ctx,
                          const sphx_grid *g, const sphx_tasks *t, const sphx_particles *in,
                          const sphx_force_out *o, float far, const int32_t *gate,
                          const StepOut &so, double *fsum, hipStream_t s)
 {
 #define SPHX_FORCE_LAUNCH(CAP_, NW_)                                                           \
-    k_force<CAP_, NW_, K><<<unsigned(nbp), 64 * NW_, 0, s>>>(                                     \
+    k_force<CAP_, NW_, K, ENT><<<unsigned(nbp), 64 * NW_, 0, s>>>(                                \
         g->n_leaves, nbp, t->order, g->leaf_start, g->perm, g->q0, g->q1, g->qa, g->g0, g->g1, \
         in->active, t->off, t->task, g->leaf_ext, g->leaf_hmax, float(ctx->p.gamma_k),         \
         float(ctx->p.beta_v), far, o->ax,                                                      \
-        o->ay, o->az, o->du_dt, o->v_sig, o->nforce, fsum, gate, so)
+        o->ay, o->az, o->du_dt, o->v_sig, o->nforce, fsum, gate, so, float(ctx->p.gamma_gas))
     if (waves == 1) {
         if (tile == 64)
             SPHX_FORCE_LAUNCH(64, 1);
@@ -621,8 +633,13 @@ sphx_status force_launch(const sphx_ctx *ctx, const sphx_grid *g, const sphx_tas
         SPHX_HIP(prof->begin(1, s));
     const int tile = ctx->p.force_tile ? ctx->p.force_tile : 64;
     const int waves = ctx->p.force_waves ? ctx->p.force_waves : 1;
-    SPHX_WITH_KERNEL(ctx->p.kernel, force_shapes<KK>(tile, waves, nbp, ctx, g, t, in, o, far,
-                                                     gate, so, fsum, s));
+    if (ctx->p.flavour == SPHX_FLAVOUR_DENSITY_ENTROPY) {
+        SPHX_WITH_KERNEL(ctx->p.kernel, (force_shapes<KK, true>(tile, waves, nbp, ctx, g, t, in,
+                                                                 o, far, gate, so, fsum, s)));
+    } else {
+        SPHX_WITH_KERNEL(ctx->p.kernel, (force_shapes<KK, false>(tile, waves, nbp, ctx, g, t, in,
+                                                                  o, far, gate, so, fsum, s)));
+    }
     SPHX_HIP(hipGetLastError());
     if (prof)
         SPHX_HIP(prof->end(1, s));

@@ -22,7 +22,7 @@ __global__ __launch_bounds__(kGhostThreads) void k_ghost(int64_t n, const int32_
                         const float *__restrict__ lrad,
                         const float4 *__restrict__ d0, const float4 *__restrict__ d1, float inv_eta3,
                         float h_tol, float h_max, float gamma_k, float gamma_gas, float eps_b,
-                        int final_pass, int step_mode, float4 *__restrict__ g0,
+                        int final_pass, int step_mode, int entropy, float4 *__restrict__ g0,
                         float4 *__restrict__ g1, float4 *__restrict__ g2, const int32_t *__restrict__ nngb,
                         unsigned long long *__restrict__ units, float *__restrict__ o_f,
                         float *__restrict__ o_P,
@@ -95,8 +95,11 @@ __global__ __launch_bounds__(kGhostThreads) void k_ghost(int64_t n, const int32_
             const float4 b = d1[s];  // div_sum, curl_x, curl_y, curl_z
             const float rho = a.z;
             const float u = q1[s].w;
-            const float P = (gamma_gas - 1.0f) * u * rho;
-            const float c = sqrtf(gamma_gas * (gamma_gas - 1.0f) * u);
+            // density-energy: u is the internal energy; density-entropy: the
+            // particle carries the adiabat A, and P = A rho^gamma
+            const float P = entropy ? u * powf(rho, gamma_gas) : (gamma_gas - 1.0f) * u * rho;
+            const float c = entropy ? sqrtf(gamma_gas * P / rho)
+                                    : sqrtf(gamma_gas * (gamma_gas - 1.0f) * u);
             const float f = 1.0f / a.w;
             const float irho = 1.0f / rho;
             const float div = b.x * irho;
@@ -175,7 +178,8 @@ sphx_status ghost_launch(const sphx_ctx *ctx, sphx_grid *g, const sphx_tasks *t,
         use_lists ? g->lrad : nullptr, g->d0, g->d1, inv_eta3,
         float(P.h_tol),
         float(ctx->h_max), float(P.gamma_k), float(P.gamma_gas), float(P.eps_balsara),
-        final_pass, step_mode ? 1 : 0, g->g0, g->g1, g->g2, d->nngb, units, o->f, o->P, o->c,
+        final_pass, step_mode ? 1 : 0, P.flavour == SPHX_FLAVOUR_DENSITY_ENTROPY ? 1 : 0, g->g0,
+        g->g1, g->g2, d->nngb, units, o->f, o->P, o->c,
         o->balsara, o->A, o->div_v, o->curl_v, o->converged, counters, skip);
     SPHX_HIP(hipGetLastError());
     return SPHX_OK;

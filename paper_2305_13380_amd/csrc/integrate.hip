@@ -1,0 +1,401 @@
+// The rest of SPHENIX (Section 3.3) and the time integration (Sections 2.4
+// and 3.4) on the cell structure of a step:
+//
+// * gradient loop: for every active receiver i over j != i with
+//   0 < r_ij < H_i, the Laplacian of u (Brookshaw's second-derivative form)
+//   lap_u_i = 2 sum_j (m_j/rho_j)(u_i - u_j) (dW/dr)/r, the conduction speed
+//   vc_i = max_j (|v_ij . x_ij|/r_ij + sqrt(2|P_i - P_j|/(rho_i + rho_j))) and
+//   the largest alpha_V among i and its neighbours;
+// * the conduction parameter over a step: its linear evolution equation
+//   with constant coefficients integrated exactly, then the shock limiter;
+// * the step size: the CFL step c_cfl H_i / v_sig,i, capped at Delta times
+//   the smallest CFL step among the force-loop neighbours (r < max(H_i, H_j)),
+//   and the smallest limited step over the active particles;
+// * the leapfrog operators: a (half) kick of v and u, a drift of x.
+//
+// The two neighbour loops run one wave per receiving cell, one receiver per
+// lane; each task's sources are staged in LDS in the receiver cell's FP32
+// frame, and a source that no lane uses is skipped by a wave-uniform branch.
+// Both are run once per step (the h iteration runs its density loop several
+// times), so they keep this plain shape.
+#include "kernel_shapes.h"
+#include "pairs.h"
+
+namespace sphx {
+namespace {
+
+constexpr int kElemThreads = 256;
+
+// Sorted source state of the gradient loop: (h, rho, P, alpha_V).
+__global__ __launch_bounds__(kElemThreads) void k_grad_state(
+    int64_t n, const int32_t *__restrict__ perm, const float *__restrict__ h,
+    const float *__restrict__ rho, const float *__restrict__ P, const float *__restrict__ av,
+    float4 *__restrict__ st)
+{
+    const int64_t s = int64_t(blockIdx.x) * kElemThreads + threadIdx.x;
+    if (s >= n)
+        return;
+    const int32_t i = perm[s];
+    st[s] = make_float4(h[i], rho[i], P[i], av[i]);
+}
+
+template <int K>
+__global__ __launch_bounds__(64) void k_gradient(
+    int64_t n_leaves, const int32_t *__restrict__ leaf_start, const int32_t *__restrict__ perm,
+    const float4 *__restrict__ q0, const float4 *__restrict__ q1,
+    const float4 *__restrict__ st, const uint8_t *__restrict__ active,
+    const int32_t *__restrict__ toff, const Task *__restrict__ task,
+    const float4 *__restrict__ ext, float gamma_k, float *__restrict__ lap_u,
+    float *__restrict__ vc, float *__restrict__ avmax)
+{
+    const int64_t L = blockIdx.x;
+    if (L >= n_leaves)
+        return;
+    const int lane = threadIdx.x;
+    const int32_t s0 = leaf_start[L], cnt = leaf_start[L + 1] - s0;
+    const bool valid = lane < cnt;
+    const int32_t s = s0 + (valid ? lane : 0);
+    const int32_t gi = perm[s];
+    const bool act = valid && (!active || active[gi] != 0);
+    if (!__any(act))
+        return;
+    const float4 pi = q0[s];  // x, y, z (cell frame), m
+    const float4 vi = q1[s];  // vx, vy, vz, u
+    const float4 si = st[s];  // h, rho, P, alpha_V
+    const float Hi = gamma_k * si.x;
+    const float H2 = act ? Hi * Hi : -1.0f;
+    const float invH = fast_rcp(Hi);
+    const float invH5 = (invH * invH) * (invH * invH) * invH;
+    constexpr float kD = Kern<K>::kD;
+    const float inf = __builtin_inff();
+    float3 lo = make_float3(act ? pi.x : inf, act ? pi.y : inf, act ? pi.z : inf);
+    float3 hb = make_float3(act ? pi.x : -inf, act ? pi.y : -inf, act ? pi.z : -inf);
+    lo.x = wave_minf(lo.x);
+    lo.y = wave_minf(lo.y);
+    lo.z = wave_minf(lo.z);
+    hb.x = wave_maxf(hb.x);
+    hb.y = wave_maxf(hb.y);
+    hb.z = wave_maxf(hb.z);
+    const float R = wave_maxf(act ? Hi : 0.0f);
+    const float R2 = R * R;
+
+    __shared__ float4 sp[kLeafMax], sv[kLeafMax], ss[kLeafMax];
+    float lap = 0.0f, vcm = 0.0f, avm = si.w;
+    const int32_t ta = toff[L], tb = toff[L + 1];
+    for (int32_t t = ta; t < tb; ++t) {
+        const Task tk = task[t];
+        if (task_box_dist2(tk.ox, tk.oy, tk.oz, ext[tk.j], lo, hb) >= R2)
+            continue;
+        __syncthreads();  // (one wave per block) the previous task's sources are read
+        if (lane < tk.jc) {
+            float4 p = q0[tk.j0 + lane];
+            p.x += tk.ox;
+            p.y += tk.oy;
+            p.z += tk.oz;
+            sp[lane] = p;
+            sv[lane] = q1[tk.j0 + lane];
+            ss[lane] = st[tk.j0 + lane];
+        }
+        __syncthreads();
+        for (int k = 0; k < tk.jc; ++k) {
+            const float4 p = sp[k];
+            const float dx = pi.x - p.x, dy = pi.y - p.y, dz = pi.z - p.z;
+            const float r2 = dist2(dx, dy, dz);
+            // j != i, 0 < r < H_i (the receiver itself is at r = 0)
+            const bool on = r2 < H2 && r2 > 0.0f;
+            if (!__any(on))
+                continue;
+            const float4 v = sv[k];
+            const float4 sj = ss[k];
+            const float rinv = on ? fast_rsq(r2) : 0.0f;
+            const float r = r2 * rinv;
+            const float u = fminf(r * invH, 1.0f);
+            // dW/dr / r = -kD H^-5 phi(u)
+            const float wr = -kD * invH5 * Kern<K>::phi(u);
+            const float dl = p.w / sj.y * (vi.w - v.w) * wr;
+            const float vdx = (vi.x - v.x) * dx + (vi.y - v.y) * dy + (vi.z - v.z) * dz;
+            const float vcij =
+                fabsf(vdx) * rinv + fast_sqrt(2.0f * fabsf(si.z - sj.z) / (si.y + sj.y));
+            lap += on ? dl : 0.0f;
+            vcm = on ? fmaxf(vcm, vcij) : vcm;
+            avm = on ? fmaxf(avm, sj.w) : avm;
+        }
+    }
+    if (act) {
+        lap_u[gi] = 2.0f * lap;
+        vc[gi] = vcm;
+        avmax[gi] = avm;
+    }
+}
+
+// The conduction parameter over a step dt (constants printed in Section 3.3:
+// beta_c = 1, alpha_c,min = 0, alpha_c,max = 1, alpha_V,max = 2).
+__global__ __launch_bounds__(kElemThreads) void k_alpha_c(
+    int64_t n, const float *__restrict__ lap_u, const float *__restrict__ u,
+    const float *__restrict__ h, const float *__restrict__ vc, const float *__restrict__ avmax,
+    const uint8_t *__restrict__ active, float dt, float gamma_k, float *__restrict__ alpha)
+{
+    const int64_t i = int64_t(blockIdx.x) * kElemThreads + threadIdx.x;
+    if (i >= n || (active && !active[i]))
+        return;
+    constexpr float beta_c = 1.0f, a_min = 0.0f, a_max = 1.0f, av_max = 2.0f;
+    const float H = gamma_k * h[i];
+    const float ui = u[i];
+    const float S = ui > 0.0f ? beta_c * H * lap_u[i] / sqrtf(ui) : 0.0f;
+    const float lam = vc[i] / H;
+    float a = alpha[i];
+    if (lam > 0.0f) {
+        // a_inf + (a - a_inf) e^(-lam dt), written as a + (a_inf - a)(1 - e^(-lam dt))
+        // with expm1: no cancellation between a_inf and a when lam dt is small
+        const float a_inf = a_min + S / lam;
+        a = a + (a_inf - a) * (-expm1f(-lam * dt));
+    } else {
+        a = a + S * dt;
+    }
+    const float cap = fmaxf(a_max * (1.0f - avmax[i] / av_max), a_min);
+    alpha[i] = fmaxf(fminf(a, cap), a_min);
+}
+
+// Sorted (h, CFL step) of every particle, from the caller's h and v_sig.
+__global__ __launch_bounds__(kElemThreads) void k_dt_state(
+    int64_t n, const int32_t *__restrict__ perm, const float *__restrict__ h,
+    const float *__restrict__ vsig, float gamma_k, float c_cfl, float4 *__restrict__ st)
+{
+    const int64_t s = int64_t(blockIdx.x) * kElemThreads + threadIdx.x;
+    if (s >= n)
+        return;
+    const int32_t i = perm[s];
+    const float hh = h[i];
+    st[s] = make_float4(hh, c_cfl * gamma_k * hh / vsig[i], 0.0f, 0.0f);
+}
+
+// Limited step of every active receiver: its CFL step, capped at delta times
+// the smallest CFL step of the particles j != i with r_ij < max(H_i, H_j);
+// the smallest limited step over the block goes to *dt_min (FP32 bits of a
+// positive value order as integers).
+__global__ __launch_bounds__(64) void k_dt_limit(
+    int64_t n_leaves, const int32_t *__restrict__ leaf_start, const int32_t *__restrict__ perm,
+    const float4 *__restrict__ q0, const float4 *__restrict__ st,
+    const uint8_t *__restrict__ active, const int32_t *__restrict__ toff,
+    const Task *__restrict__ task, const float4 *__restrict__ ext, const float *__restrict__ hmax,
+    float gamma_k, float delta, float *__restrict__ dt_out, int32_t *__restrict__ dt_min)
+{
+    const int64_t L = blockIdx.x;
+    if (L >= n_leaves)
+        return;
+    const int lane = threadIdx.x;
+    const int32_t s0 = leaf_start[L], cnt = leaf_start[L + 1] - s0;
+    const bool valid = lane < cnt;
+    const int32_t s = s0 + (valid ? lane : 0);
+    const int32_t gi = perm[s];
+    const bool act = valid && (!active || active[gi] != 0);
+    if (!__any(act))
+        return;
+    const float4 pi = q0[s];
+    const float4 si = st[s];
+    const float Hi = gamma_k * si.x;
+    const float H2 = act ? Hi * Hi : -1.0f;
+    const float inf = __builtin_inff();
+    float3 lo = make_float3(act ? pi.x : inf, act ? pi.y : inf, act ? pi.z : inf);
+    float3 hb = make_float3(act ? pi.x : -inf, act ? pi.y : -inf, act ? pi.z : -inf);
+    lo.x = wave_minf(lo.x);
+    lo.y = wave_minf(lo.y);
+    lo.z = wave_minf(lo.z);
+    hb.x = wave_maxf(hb.x);
+    hb.y = wave_maxf(hb.y);
+    hb.z = wave_maxf(hb.z);
+    const float R = wave_maxf(act ? Hi : 0.0f);
+    const float R2 = R * R;
+    __shared__ float4 sp[kLeafMax];
+    __shared__ float2 ss[kLeafMax];
+    float lim = si.y;
+    const int32_t ta = toff[L], tb = toff[L + 1];
+    for (int32_t t = ta; t < tb; ++t) {
+        const Task tk = task[t];
+        // a source cell reaches the receivers within max(R, its largest H)
+        const float rj = hmax[tk.j];
+        if (task_box_dist2(tk.ox, tk.oy, tk.oz, ext[tk.j], lo, hb) >= fmaxf(R2, rj * rj))
+            continue;
+        __syncthreads();
+        if (lane < tk.jc) {
+            float4 p = q0[tk.j0 + lane];
+            p.x += tk.ox;
+            p.y += tk.oy;
+            p.z += tk.oz;
+            sp[lane] = p;
+            const float4 sj = st[tk.j0 + lane];
+            ss[lane] = make_float2(gamma_k * sj.x, sj.y);
+        }
+        __syncthreads();
+        // the receiver itself: in the unshifted self task, at its own slot
+        const int own = (tk.self && valid) ? s - tk.j0 : -1;
+        for (int k = 0; k < tk.jc; ++k) {
+            const float4 p = sp[k];
+            const float2 sj = ss[k];
+            const float r2 = dist2(pi.x - p.x, pi.y - p.y, pi.z - p.z);
+            const bool on = k != own && r2 < fmaxf(H2, act ? sj.x * sj.x : -1.0f);
+            lim = on ? fminf(lim, delta * sj.y) : lim;
+        }
+    }
+    if (act)
+        dt_out[gi] = lim;
+    float m = act ? lim : inf;
+    m = wave_minf(m);
+    if (lane == 0 && m < inf)
+        atomicMin(dt_min, __float_as_int(m));
+}
+
+__global__ void k_fill_inf(int32_t *p)
+{
+    if (threadIdx.x == 0)
+        *p = __float_as_int(__builtin_inff());
+}
+
+// One wave per leaf: the largest gamma_k h of the leaf's particles (from a
+// sorted (h, ...) state), for the limiter's source-cell cull.
+__global__ __launch_bounds__(64) void k_leaf_hmax_st(int64_t n_leaves,
+                                                     const int32_t *__restrict__ leaf_start,
+                                                     const float4 *__restrict__ st, float gamma_k,
+                                                     float *__restrict__ hmax)
+{
+    const int64_t L = blockIdx.x;
+    if (L >= n_leaves)
+        return;
+    const int lane = threadIdx.x;
+    const int32_t s0 = leaf_start[L], cnt = leaf_start[L + 1] - s0;
+    float v = lane < cnt ? st[s0 + lane].x : 0.0f;
+    v = wave_maxf(v);
+    if (lane == 0)
+        hmax[L] = gamma_k * v;
+}
+
+// Half kick (or prediction): out = in + d * dt_half for v (3) and u.
+__global__ __launch_bounds__(kElemThreads) void k_kick(
+    int64_t n, const float *__restrict__ vx, const float *__restrict__ vy,
+    const float *__restrict__ vz, const float *__restrict__ u, const float *__restrict__ ax,
+    const float *__restrict__ ay, const float *__restrict__ az, const float *__restrict__ du,
+    const uint8_t *__restrict__ active, float dt_half, float *vx_o, float *vy_o, float *vz_o,
+    float *u_o)
+{
+    const int64_t i = int64_t(blockIdx.x) * kElemThreads + threadIdx.x;
+    if (i >= n || (active && !active[i]))
+        return;
+    vx_o[i] = vx[i] + ax[i] * dt_half;
+    vy_o[i] = vy[i] + ay[i] * dt_half;
+    vz_o[i] = vz[i] + az[i] * dt_half;
+    u_o[i] = u[i] + du[i] * dt_half;
+}
+
+// Drift in FP64: x += v dt, wrapped into [0, L) in a periodic box.
+__global__ __launch_bounds__(kElemThreads) void k_drift(
+    int64_t n, double *__restrict__ x, double *__restrict__ y, double *__restrict__ z,
+    const float *__restrict__ vx, const float *__restrict__ vy, const float *__restrict__ vz,
+    double dt, double Lx, double Ly, double Lz, int periodic)
+{
+    // each operation rounded on its own (no fused multiply-add), so that the
+    // positions follow the plain FP64 arithmetic of a drift exactly
+#pragma clang fp contract(off)
+    const int64_t i = int64_t(blockIdx.x) * kElemThreads + threadIdx.x;
+    if (i >= n)
+        return;
+    double p[3] = {x[i] + double(vx[i]) * dt, y[i] + double(vy[i]) * dt,
+                   z[i] + double(vz[i]) * dt};
+    const double B[3] = {Lx, Ly, Lz};
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+        if (periodic) {
+            p[a] -= B[a] * floor(p[a] / B[a]);
+            if (p[a] >= B[a])  // a tiny negative coordinate rounds up to L
+                p[a] -= B[a];
+        }
+    x[i] = p[0];
+    y[i] = p[1];
+    z[i] = p[2];
+}
+
+inline unsigned elem_blocks(int64_t n) { return unsigned((n + kElemThreads - 1) / kElemThreads); }
+
+}  // namespace
+
+sphx_status gradient_launch(const sphx_ctx *ctx, sphx_grid *g, const sphx_tasks *t,
+                            const sphx_particles *in, const float *rho, const float *P,
+                            float *lap_u, float *vc, float *avmax, hipStream_t s)
+{
+    if (g->n == 0 || g->n_leaves == 0)
+        return SPHX_OK;
+    k_grad_state<<<elem_blocks(g->n), kElemThreads, 0, s>>>(g->n, g->perm, in->h, rho, P,
+                                                           in->alpha_v, g->g2);
+    SPHX_HIP(hipGetLastError());
+    SPHX_WITH_KERNEL(ctx->p.kernel,
+                     (k_gradient<KK><<<unsigned(g->n_leaves), 64, 0, s>>>(
+                         g->n_leaves, g->leaf_start, g->perm, g->q0, g->q1, g->g2, in->active,
+                         t->off, t->task, g->leaf_ext, float(ctx->p.gamma_k), lap_u, vc,
+                         avmax)));
+    SPHX_HIP(hipGetLastError());
+    return SPHX_OK;
+}
+
+sphx_status alpha_c_launch(const sphx_ctx *ctx, int64_t n, const float *lap_u, const float *u,
+                           const float *h, const float *vc, const float *avmax,
+                           const uint8_t *active, double dt, float *alpha, hipStream_t s)
+{
+    if (n == 0)
+        return SPHX_OK;
+    k_alpha_c<<<elem_blocks(n), kElemThreads, 0, s>>>(n, lap_u, u, h, vc, avmax, active,
+                                                      float(dt), float(ctx->p.gamma_k), alpha);
+    SPHX_HIP(hipGetLastError());
+    return SPHX_OK;
+}
+
+sphx_status timestep_launch(const sphx_ctx *ctx, sphx_grid *g, const sphx_tasks *t,
+                            const sphx_particles *in, const float *vsig, double c_cfl,
+                            double delta, float *dt_out, float *dt_min, hipStream_t s)
+{
+    int32_t *mn = reinterpret_cast<int32_t *>(dt_min);
+    if (mn) {
+        k_fill_inf<<<1, 64, 0, s>>>(mn);
+        SPHX_HIP(hipGetLastError());
+    }
+    if (g->n == 0 || g->n_leaves == 0)
+        return SPHX_OK;
+    const float gk = float(ctx->p.gamma_k);
+    k_dt_state<<<elem_blocks(g->n), kElemThreads, 0, s>>>(g->n, g->perm, in->h, vsig, gk,
+                                                          float(c_cfl), g->g2);
+    SPHX_HIP(hipGetLastError());
+    k_leaf_hmax_st<<<unsigned(g->n_leaves), 64, 0, s>>>(g->n_leaves, g->leaf_start, g->g2, gk,
+                                                        g->leaf_hmax);
+    SPHX_HIP(hipGetLastError());
+    k_dt_limit<<<unsigned(g->n_leaves), 64, 0, s>>>(
+        g->n_leaves, g->leaf_start, g->perm, g->q0, g->g2, in->active, t->off, t->task,
+        g->leaf_ext, g->leaf_hmax, gk, float(delta), dt_out, mn);
+    SPHX_HIP(hipGetLastError());
+    return SPHX_OK;
+}
+
+sphx_status kick_launch(int64_t n, const float *vx, const float *vy, const float *vz,
+                        const float *u, const float *ax, const float *ay, const float *az,
+                        const float *du, const uint8_t *active, double dt_half, float *vx_o,
+                        float *vy_o, float *vz_o, float *u_o, hipStream_t s)
+{
+    if (n == 0)
+        return SPHX_OK;
+    k_kick<<<elem_blocks(n), kElemThreads, 0, s>>>(n, vx, vy, vz, u, ax, ay, az, du, active,
+                                                   float(dt_half), vx_o, vy_o, vz_o, u_o);
+    SPHX_HIP(hipGetLastError());
+    return SPHX_OK;
+}
+
+sphx_status drift_launch(const sphx_ctx *ctx, int64_t n, double *x, double *y, double *z,
+                         const float *vx, const float *vy, const float *vz, double dt,
+                         hipStream_t s)
+{
+    if (n == 0)
+        return SPHX_OK;
+    k_drift<<<elem_blocks(n), kElemThreads, 0, s>>>(n, x, y, z, vx, vy, vz, dt, ctx->p.box[0],
+                                                    ctx->p.box[1], ctx->p.box[2],
+                                                    ctx->p.periodic);
+    SPHX_HIP(hipGetLastError());
+    return SPHX_OK;
+}
+
+}  // namespace sphx

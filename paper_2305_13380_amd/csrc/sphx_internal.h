@@ -293,6 +293,25 @@ constexpr int64_t kNoallocLeaves = int64_t(1) << 19;
 constexpr int kNoallocMaxDevices = 64;
 sphx_status noalloc_scratch(int device, double **out);
 
+// integrate.hip: the gradient loop, the conduction parameter, the step size
+// and the leapfrog operators (their scratch is the grid's g2 and leaf_hmax).
+sphx_status gradient_launch(const sphx_ctx *ctx, sphx_grid *g, const sphx_tasks *t,
+                            const sphx_particles *in, const float *rho, const float *P,
+                            float *lap_u, float *vc, float *avmax, hipStream_t s);
+sphx_status alpha_c_launch(const sphx_ctx *ctx, int64_t n, const float *lap_u, const float *u,
+                           const float *h, const float *vc, const float *avmax,
+                           const uint8_t *active, double dt, float *alpha, hipStream_t s);
+sphx_status timestep_launch(const sphx_ctx *ctx, sphx_grid *g, const sphx_tasks *t,
+                            const sphx_particles *in, const float *vsig, double c_cfl,
+                            double delta, float *dt_out, float *dt_min, hipStream_t s);
+sphx_status kick_launch(int64_t n, const float *vx, const float *vy, const float *vz,
+                        const float *u, const float *ax, const float *ay, const float *az,
+                        const float *du, const uint8_t *active, double dt_half, float *vx_o,
+                        float *vy_o, float *vz_o, float *u_o, hipStream_t s);
+sphx_status drift_launch(const sphx_ctx *ctx, int64_t n, double *x, double *y, double *z,
+                         const float *vx, const float *vy, const float *vz, double dt,
+                         hipStream_t s);
+
 // graph.hip
 // Captured step: the h iteration's first `passes` passes and a gated force
 // pass as one HIP graph, replayed while the handles and arrays stay the same.

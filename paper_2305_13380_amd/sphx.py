@@ -37,7 +37,7 @@ class Params(C.Structure):
                 ("neighbour_lists", C.c_int32), ("density_tile", C.c_int32),
                 ("density_waves", C.c_int32), ("force_tile", C.c_int32),
                 ("force_waves", C.c_int32), ("graph_passes", C.c_int32),
-                ("density_balance", C.c_int32), ("kernel", C.c_int32)]
+                ("density_balance", C.c_int32), ("kernel", C.c_int32), ("flavour", C.c_int32)]
 
 
 # Smoothing kernels (SPHX_KERNEL_* of sphx.h), by name.
@@ -77,7 +77,8 @@ SYMBOLS = ("sphx_params_default", "sphx_ctx_create", "sphx_ctx_destroy", "sphx_w
            "sphx_iter_reset", "sphx_density", "sphx_ghost", "sphx_force", "sphx_step",
            "sphx_grid_leaves", "sphx_tasks_count", "sphx_last_error", "sphx_profile_enable",
            "sphx_profile_read", "sphx_autotune", "sphx_params_set_kernel", "sphx_fof",
-           "sphx_gravity", "sphx_alpha_v_update", "sphx_force_noalloc")
+           "sphx_gravity", "sphx_alpha_v_update", "sphx_force_noalloc", "sphx_gradient",
+           "sphx_alpha_c_update", "sphx_timestep", "sphx_kick", "sphx_drift")
 
 _LIB = None
 
@@ -124,6 +125,12 @@ def _load():
     L.sphx_force.argtypes = [vp, vp, vp, P(Particles), P(DensityOut), P(GhostOut), P(ForceOut),
                              vp, vp]
     L.sphx_force_noalloc.argtypes = L.sphx_force.argtypes
+    L.sphx_gradient.argtypes = [vp, vp, vp, P(Particles), vp, vp, vp, vp, vp, vp]
+    L.sphx_alpha_c_update.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, C.c_double, vp, vp]
+    L.sphx_timestep.argtypes = [vp, vp, vp, P(Particles), vp, C.c_double, C.c_double, vp, vp,
+                                vp]
+    L.sphx_kick.argtypes = [vp, i64] + [vp] * 9 + [C.c_double] + [vp] * 5
+    L.sphx_drift.argtypes = [vp, i64] + [vp] * 6 + [C.c_double, vp]
     L.sphx_step.argtypes = [vp, vp, P(vp), P(Particles), P(DensityOut), P(GhostOut),
                             P(ForceOut), vp, vp, P(StepInfo)]
     L.sphx_autotune.argtypes = [vp, vp, vp, P(Particles), P(DensityOut), P(GhostOut),
@@ -140,7 +147,9 @@ def _load():
     L.sphx_last_error.argtypes = []
     L.sphx_last_error.restype = C.c_char_p
     for name in ("sphx_ctx_create", "sphx_grid_build", "sphx_tasks_build", "sphx_iter_reset",
-                 "sphx_density", "sphx_ghost", "sphx_force", "sphx_step", "sphx_force_noalloc"):
+                 "sphx_density", "sphx_ghost", "sphx_force", "sphx_step", "sphx_force_noalloc",
+                 "sphx_gradient", "sphx_alpha_c_update", "sphx_timestep", "sphx_kick",
+                 "sphx_drift"):
         getattr(L, name).restype = i32
     _LIB = L
     return L
@@ -159,11 +168,17 @@ def _check(status):
     return status
 
 
+FLAVOURS = {"energy": 0, "entropy": 1}  # SPHX_FLAVOUR_DENSITY_ENERGY / _ENTROPY
+
+
 def default_params(**kw) -> Params:
     """The library's defaults with fields overridden by keyword; kernel= takes
-    a name of KERNELS (or its number) and sets the kernel's gamma_k too."""
+    a name of KERNELS (or its number) and sets the kernel's gamma_k too;
+    flavour= takes "energy" or "entropy" (or the number)."""
     p = Params()
     lib.sphx_params_default(C.byref(p))
+    if isinstance(kw.get("flavour"), str):
+        kw = dict(kw, flavour=FLAVOURS[kw["flavour"]])
     if "kernel" in kw:
         k = kw["kernel"]
         k = KERNELS[k] if isinstance(k, str) else int(k)
@@ -427,6 +442,63 @@ def alpha_v_update(ctx, alpha_v, div_old, div_new, c, h, v_sig, dt, stream=None)
                                    _ptr(div_new), _ptr(c), _ptr(h), _ptr(v_sig), float(dt),
                                    _ptr(alpha_v), _stream(stream)))
     return alpha_v
+
+
+def gradient(ctx, grid, tasks, parts, out: Outputs, stream=None):
+    """SPHENIX gradient loop (sphx_gradient) after a step: returns device
+    tensors (lap_u, v_c, alpha_v_max); entries of inactive particles are
+    left as allocated (NaN)."""
+    import torch
+    dev = parts.t["x"].device
+    res = [torch.full((parts.n,), float("nan"), dtype=torch.float32, device=dev)
+           for _ in range(3)]
+    pv = parts.view()
+    _check(lib.sphx_gradient(ctx.handle, grid.handle, tasks.handle, C.byref(pv),
+                             _ptr(out.d["rho"]), _ptr(out.g["P"]), _ptr(res[0]), _ptr(res[1]),
+                             _ptr(res[2]), _stream(stream)))
+    return tuple(res)
+
+
+def alpha_c_update(ctx, alpha_c, lap_u, u, h, v_c, alpha_v_max, dt, active=None, stream=None):
+    """SPHENIX conduction parameter over a step dt (sphx_alpha_c_update):
+    updates the FP32 device tensor alpha_c in place."""
+    _check(lib.sphx_alpha_c_update(ctx.handle, int(alpha_c.numel()), _ptr(lap_u), _ptr(u),
+                                   _ptr(h), _ptr(v_c), _ptr(alpha_v_max), _ptr(active),
+                                   float(dt), _ptr(alpha_c), _stream(stream)))
+    return alpha_c
+
+
+def timestep(ctx, grid, tasks, parts, v_sig, c_cfl, delta=4.0, stream=None):
+    """Step sizes (sphx_timestep): returns device tensors (dt of every active
+    particle, the smallest of them as one FP32 element)."""
+    import torch
+    dev = parts.t["x"].device
+    dt = torch.full((parts.n,), float("nan"), dtype=torch.float32, device=dev)
+    mn = torch.empty(1, dtype=torch.float32, device=dev)
+    pv = parts.view()
+    _check(lib.sphx_timestep(ctx.handle, grid.handle, tasks.handle, C.byref(pv), _ptr(v_sig),
+                             float(c_cfl), float(delta), _ptr(dt), _ptr(mn), _stream(stream)))
+    return dt, mn
+
+
+def kick(ctx, v, u, a, du, dt_half, v_out=None, u_out=None, active=None, stream=None):
+    """Half kick (sphx_kick): v, a are sequences of three FP32 device
+    tensors; in place unless v_out/u_out are given."""
+    v_out = v if v_out is None else v_out
+    u_out = u if u_out is None else u_out
+    _check(lib.sphx_kick(ctx.handle, int(u.numel()), _ptr(v[0]), _ptr(v[1]), _ptr(v[2]), _ptr(u),
+                         _ptr(a[0]), _ptr(a[1]), _ptr(a[2]), _ptr(du), _ptr(active),
+                         float(dt_half), _ptr(v_out[0]), _ptr(v_out[1]), _ptr(v_out[2]),
+                         _ptr(u_out), _stream(stream)))
+    return v_out, u_out
+
+
+def drift(ctx, parts, dt, stream=None):
+    """Drift (sphx_drift) of the particles' FP64 positions, in place."""
+    t = parts.t
+    _check(lib.sphx_drift(ctx.handle, parts.n, _ptr(t["x"]), _ptr(t["y"]), _ptr(t["z"]),
+                          _ptr(t["vx"]), _ptr(t["vy"]), _ptr(t["vz"]), float(dt),
+                          _stream(stream)))
 
 
 def autotune(ctx, grid, tasks, parts, out: Outputs, reps=3, stream=None) -> Params:

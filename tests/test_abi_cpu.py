@@ -60,7 +60,7 @@ def test_default_params_are_the_papers(sphx):
                                          ("density_tile", 100), ("density_waves", 3),
                                          ("force_tile", 256), ("force_tile", 32), ("force_waves", -1),
                                          ("graph_passes", -1), ("graph_passes", 65),
-                                         ("density_balance", 2)])
+                                         ("density_balance", 3)])
 def test_ctx_create_rejects_invalid_params(sphx, field, value):
     p = sphx.default_params(**{field: value})
     h = C.c_void_p()

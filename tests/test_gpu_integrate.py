@@ -1,0 +1,267 @@
+"""GPU rest of SPHENIX and time integration against the oracle:
+
+* the gradient loop (sphx_gradient) after a step, element by element at the
+  step's own h, with the oracle given the GPU's own rho and P (the loop's
+  parity; its inputs are checked by the step tests): the Laplacian of u
+  within 2e-4 of the scale of its terms (sum of their magnitudes), the conduction speed and the
+  largest neighbouring alpha_V within the bounds a pair at the support edge
+  (1e-6 relative) may move them;
+* the conduction parameter (sphx_alpha_c_update) on seeded inputs that cover
+  growth, decay, the limiter and the floor;
+* the step sizes (sphx_timestep): CFL steps and the neighbour limiter, the
+  smallest limited step;
+* the leapfrog operators (sphx_kick, sphx_drift);
+* multi-step runs: the first steps of a Sedov blast against the oracle's own
+  run, and the 32^3 blast (sizes of the workload's Sedov box halved per
+  side) against the self-similar radius and energy conservation.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2305_13380_amd import inputs
+
+pytestmark = pytest.mark.gpu
+P = oracle.Params()
+
+
+def log(*a):
+    print(*a, flush=True)
+
+
+def stepped(ps):
+    import torch
+    from paper_2305_13380_amd import sphx
+    ctx = sphx.Context()
+    dp = sphx.DeviceParticles.from_set(ps)
+    out = sphx.Outputs(ps.n)
+    grid = sphx.Grid(ctx, dp)
+    tasks = sphx.Tasks(ctx, grid, dp)
+    st, info = sphx.step(ctx, grid, tasks, dp, out)
+    assert st >= 0
+    torch.cuda.synchronize()
+    return ctx, dp, out, grid, tasks
+
+
+def host(t):
+    return t.cpu().numpy().astype(np.float64)
+
+
+def lap_scale(ps, h, rho, recv=None):
+    """Per receiver, 2 sum_j |m_j/rho_j (u_i - u_j) W'/r|: the scale of the
+    Laplacian's terms (from the oracle's candidate lists and kernel)."""
+    recv = np.arange(ps.n) if recv is None else np.asarray(recv)
+    off, idx = oracle.density_candidates(ps, h, P, recv)
+    k = np.repeat(np.arange(len(recv)), np.diff(off))
+    i = recv[k]
+    pos = ps.positions()
+    d = pos[i] - pos[idx]
+    d -= np.round(d)
+    r = np.sqrt((d * d).sum(1))
+    on = (r > 0) & (r < P.gamma_k * h[i])
+    _, dwdr, _ = oracle.wc2(r[on], h[i][on])
+    u = ps.u.astype(np.float64)
+    term = np.abs(ps.m[idx][on] / rho[idx][on] * (u[i][on] - u[idx][on]) * dwdr / r[on])
+    return 2.0 * np.bincount(k[on], weights=term, minlength=len(recv)) + 1e-30
+
+
+@pytest.mark.parametrize("case", ["lognormal", "lattice_logu", "sedov"])
+def test_gradient_loop_matches_oracle(case):
+    import torch
+    from paper_2305_13380_amd import sphx
+    if case == "lognormal":
+        ps = inputs.lognormal_box(16, 6000, 2.0, 51, sigma_v=0.3)
+    elif case == "lattice_logu":
+        ps = inputs.lattice_box(16, 52, u="logu", sigma_v=0.2)
+    else:
+        ps = inputs.sedov_box(16, 2, n_hot=8)
+        ps.vx[:] = np.random.default_rng(3).normal(0, 0.5, ps.n)
+    log("gradient loop: %s N=%d" % (case, ps.n))
+    ctx, dp, out, grid, tasks = stepped(ps)
+    lap, vc, avm = sphx.gradient(ctx, grid, tasks, dp, out)
+    torch.cuda.synchronize()
+    h = host(dp.t["h"])
+    rho, Pg = host(out.d["rho"]), host(out.g["P"])
+    q = ps.copy()
+    ref = oracle.gradient(q, h, rho, Pg, P)
+    scale = lap_scale(q, h, rho)
+    lap_g = host(lap)
+    err = np.abs(lap_g - ref["lap_u"])
+    # FP32 (1 - u)^3 near the support edge (u -> 1) carries a relative error
+    # of about 1e-7 / (1 - u) per term: a few 1e-5 of the term scale
+    assert np.all(err <= 2e-4 * scale), "lap_u worst %.3g of its scale" % (err / scale).max()
+    # maxima: between the oracle's values with the support 1e-6 smaller and larger
+    lo = oracle.gradient(q, h * (1 - 1e-6), rho, Pg, P)
+    hi = oracle.gradient(q, h * (1 + 1e-6), rho, Pg, P)
+    for k, g in (("vc", host(vc)), ("avmax", host(avm))):
+        a = np.minimum(lo[k], hi[k]) * (1 - 5e-6)
+        b = np.maximum(lo[k], hi[k]) * (1 + 5e-6)
+        assert np.all((g >= a - 1e-30) & (g <= b + 1e-30)), "%s: %d outside" % (
+            k, int(((g < a) | (g > b)).sum()))
+
+
+def test_gradient_loop_active_subset():
+    import torch
+    from paper_2305_13380_amd import sphx
+    ps = inputs.lognormal_box(16, 5000, 2.0, 53, time_bins=(0.3, 0.7))
+    # an all-active step gives the inactive particles their state, then the
+    # active-only step
+    all_on = ps.copy()
+    all_on.active = None
+    ctx, dp, out, grid, tasks = stepped(all_on)
+    dp.t["active"] = torch.from_numpy(ps.active).cuda()
+    st, _ = sphx.step(ctx, grid, tasks, dp, out)
+    assert st >= 0
+    lap, vc, avm = sphx.gradient(ctx, grid, tasks, dp, out)
+    torch.cuda.synchronize()
+    act = ps.active.astype(bool)
+    g = host(lap)
+    assert np.all(np.isnan(g[~act])) and np.all(np.isfinite(g[act]))
+    h = host(dp.t["h"])
+    ref = oracle.gradient(ps, h, host(out.d["rho"]), host(out.g["P"]), P,
+                          recv=np.flatnonzero(act))
+    err = np.abs(g[act] - ref["lap_u"])
+    scale = lap_scale(ps, h, host(out.d["rho"]), np.flatnonzero(act))
+    assert np.all(err <= 2e-4 * scale), "lap_u worst %.3g of its scale" % (err / scale).max()
+
+
+def alpha_c_inputs(n, seed):
+    rng = np.random.default_rng(seed)
+    f = lambda a: np.asarray(a, np.float32)
+    lap = f(rng.normal(0, 50, n))
+    u = f(10.0 ** rng.uniform(-1, 1, n))
+    h = f(10.0 ** rng.uniform(-3, -1, n))
+    vc = f(10.0 ** rng.uniform(-2, 1, n) * (rng.random(n) > 0.05))
+    avm = f(rng.uniform(0, 2.0, n))
+    a = f(rng.uniform(0, 1.0, n))
+    return a, lap, u, h, vc, avm
+
+
+@pytest.mark.parametrize("n,dt", [(100003, 1e-3), (777, 0.05)])
+def test_alpha_c_update_matches_oracle(n, dt):
+    import torch
+    from paper_2305_13380_amd import sphx
+    a, lap, u, h, vc, avm = alpha_c_inputs(n, n)
+    ctx = sphx.Context()
+    t = [torch.from_numpy(x).cuda() for x in (a, lap, u, h, vc, avm)]
+    sphx.alpha_c_update(ctx, t[0], t[1], t[2], t[3], t[4], t[5], dt)
+    torch.cuda.synchronize()
+    got = host(t[0])
+    ref = oracle.alpha_c_update(a, lap, u, h, vc, avm, dt, P)
+    err = np.abs(got - ref)
+    assert np.all(err <= 2e-5 * np.abs(ref) + 2e-6), "worst %.3g" % err.max()
+    # the limiter and the floor were exercised
+    cap = 1.0 - avm.astype(np.float64) / 2.0
+    assert np.any(np.abs(ref - cap) < 1e-12) and np.any(ref == 0.0)
+
+
+def test_timestep_matches_oracle():
+    import torch
+    from paper_2305_13380_amd import sphx
+    ps = inputs.lognormal_box(16, 6000, 2.0, 54, sigma_v=0.3)
+    ctx, dp, out, grid, tasks = stepped(ps)
+    vs = out.f["v_sig"].clone()
+    vs[123] *= 1e3  # one particle with a tiny step: its neighbours are capped
+    dt, mn = sphx.timestep(ctx, grid, tasks, dp, vs, 0.2, 4.0)
+    torch.cuda.synchronize()
+    h = host(dp.t["h"])
+    cfl = oracle.dt_cfl(h, host(vs), P, 0.2)
+    ref = oracle.dt_limit(ps, h, cfl, P)
+    lo = oracle.dt_limit(ps, h * (1 + 1e-6), cfl, P)  # a larger support: more neighbours
+    hi = oracle.dt_limit(ps, h * (1 - 1e-6), cfl, P)
+    g = host(dt)
+    assert np.all((g >= lo * (1 - 2e-6)) & (g <= hi * (1 + 2e-6)))
+    assert np.sum(g < 0.99 * cfl) > 10
+    assert abs(float(mn.item()) - g.min()) == 0.0
+    np.testing.assert_allclose(g.min(), ref.min(), rtol=2e-6)
+
+
+def test_kick_and_drift_match_oracle():
+    import torch
+    from paper_2305_13380_amd import sphx
+    ps = inputs.uniform_random_box(5003, 55, sigma_v=0.5)
+    ctx = sphx.Context()
+    dp = sphx.DeviceParticles.from_set(ps)
+    rng = np.random.default_rng(1)
+    acc = [torch.from_numpy(rng.normal(0, 3, ps.n).astype(np.float32)).cuda() for _ in range(4)]
+    t = dp.t
+    v0 = [t[k].clone() for k in ("vx", "vy", "vz")]
+    u0 = t["u"].clone()
+    vo = [torch.empty_like(x) for x in v0]
+    uo = torch.empty_like(u0)
+    sphx.kick(ctx, v0, u0, acc[:3], acc[3], 0.0125, v_out=vo, u_out=uo)
+    sphx.drift(ctx, dp, 0.75)
+    torch.cuda.synchronize()
+    for a, b, c in zip(vo, v0, acc[:3]):
+        np.testing.assert_allclose(host(a), host(b) + host(c) * 0.0125, rtol=1e-6, atol=1e-7)
+    np.testing.assert_allclose(host(uo), host(u0) + host(acc[3]) * 0.0125, rtol=1e-6, atol=1e-7)
+    pos = np.stack([ps.x, ps.y, ps.z]).astype(np.float64)
+    v = np.stack([ps.vx, ps.vy, ps.vz]).astype(np.float64)
+    oracle.drift(pos, v, 0.75, ps.box)
+    for k, ax in zip(("x", "y", "z"), pos):
+        assert np.array_equal(t[k].cpu().numpy(), ax), k
+
+
+def test_sedov_first_steps_match_the_oracle_run():
+    """Three steps of a 16^3 blast from the same state on both sides: the
+    GPU's FP32 state stays within a few 1e-5 of the oracle's FP64 run."""
+    from paper_2305_13380_amd.sphenix import SphenixRun
+    ps = inputs.sedov_box(16, 2, n_hot=8)
+    ps.alpha_v[:] = 0.1
+    ps.alpha_c[:] = 0.0
+    run = SphenixRun(ps, c_cfl=0.1)
+    gs = run.run(3)
+    r3 = oracle.sphenix_run(ps, P, 3, c_cfl=0.1, mode="brute")
+    t = run.dp.t
+    tg = gs.t
+    log("sedov 16^3: GPU t=%.6g oracle t=%.6g" % (tg, r3["t"]))
+    assert abs(tg - r3["t"]) <= 1e-4 * r3["t"]
+    pos = np.stack([host(t["x"]), host(t["y"]), host(t["z"])])
+    d = pos - r3["pos"]
+    d -= np.round(d)
+    spacing = 1.0 / 16
+    assert np.abs(d).max() < 1e-4 * spacing
+    v = np.stack([host(t["vx"]), host(t["vy"]), host(t["vz"])])
+    vmax = np.abs(r3["v"]).max()
+    assert np.abs(v - r3["v"]).max() < 1e-3 * vmax
+    np.testing.assert_allclose(host(t["u"]), r3["u"], rtol=1e-3, atol=1e-4 * r3["u"].max())
+    np.testing.assert_allclose(host(t["alpha_v"]), r3["alpha_v"], atol=1e-2)
+    np.testing.assert_allclose(host(t["alpha_c"]), r3["alpha_c"], atol=5e-3)
+    run.close()
+
+
+def test_sedov_blast_32_self_similar():
+    """A 32^3 blast over 60 steps: the shell radius follows the self-similar
+    R = 1.15 (E t^2 / rho)^(1/5) and the total energy is conserved."""
+    import torch
+    from paper_2305_13380_amd.sphenix import SphenixRun
+    ps = inputs.sedov_box(32, 2, n_hot=32)
+    ps.alpha_v[:] = 0.1
+    ps.alpha_c[:] = 0.0
+    run = SphenixRun(ps, c_cfl=0.1)
+    m = ps.m.astype(np.float64)
+    E0 = float((m * ps.u.astype(np.float64)).sum())
+    rec = []
+
+    def cb(k, r):
+        t = r.dp.t
+        pos = torch.stack([t["x"], t["y"], t["z"]]).cpu().numpy()
+        v = torch.stack([t["vx"], t["vy"], t["vz"]]).cpu().numpy().astype(np.float64)
+        u = host(t["u"])
+        rho = host(r.out.d["rho"])
+        d = pos - 0.5
+        rr = np.sqrt((d * d).sum(0))
+        sel = rho > 1.3 * rho.mean()
+        R = (rho[sel] * rr[sel]).sum() / rho[sel].sum() if sel.any() else np.nan
+        E = 0.5 * (m * (v * v).sum(0)).sum() + (m * u).sum()
+        rec.append((r.state.t, R, E / E0))
+
+    run.run(60, cb)
+    t, R, E = (np.array(x) for x in zip(*rec))
+    log("sedov 32^3: t=%.4g R=%.4f xi=%.3f max |dE|/E=%.2e" % (
+        t[-1], R[-1], R[-1] / t[-1] ** 0.4, np.abs(E - 1).max()))
+    assert np.abs(E - 1).max() < 5e-3
+    late = t > 0.5 * t[-1]
+    xi = R[late] / t[late] ** 0.4
+    assert np.all(np.abs(xi / 1.15 - 1) < 0.12), xi
+    run.close()

@@ -62,7 +62,8 @@ def oracle_step(case):
 # lists after the first pass, and lists without skin (every growth of h
 # sends the receiver back to the cell-pair loop or forces a list rebuild).
 VARIANTS = {"lists": {"neighbour_lists": 1}, "cellpair": {"neighbour_lists": 0},
-            "skin0": {"neighbour_lists": 1, "skin": 0.0}}
+            "skin0": {"neighbour_lists": 1, "skin": 0.0},
+            "grouped": {"neighbour_lists": 0, "density_balance": 2}}
 
 
 @pytest.mark.parametrize("variant", sorted(VARIANTS))
@@ -73,7 +74,7 @@ def test_step_matches_oracle_iteration(case, variant):
     g = gpu_step(ps, params=VARIANTS[variant])
     info = g["info"]
     assert g["status"] >= 0 and info.unconverged == 0
-    if variant == "cellpair" or info.passes == 1:
+    if variant in ("cellpair", "grouped") or info.passes == 1:
         assert info.list_builds == 0
     else:
         # (entries of the last build, which may cover only the receivers left)

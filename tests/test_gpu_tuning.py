@@ -21,7 +21,8 @@ P = oracle.Params()
 
 SHAPES = [dict(density_tile=t, density_waves=w, force_tile=ft, force_waves=fw, density_balance=b)
           for t, w, ft, fw, b in [(256, 1, 128, 2, 0), (64, 1, 64, 2, 0), (256, 2, 128, 1, 0),
-                                  (128, 2, 64, 1, 0), (128, 1, 64, 1, 1), (64, 1, 128, 1, 1)]]
+                                  (128, 2, 64, 1, 0), (128, 1, 64, 1, 1), (64, 1, 128, 1, 1),
+                                  (128, 1, 64, 1, 2), (256, 1, 128, 1, 2)]]
 
 
 def case():
@@ -49,6 +50,11 @@ def test_tile_size_is_bitwise_neutral(runs):
     d = out[tuple(sorted(SHAPES[3].items()))]  # other tiles, same waves for both loops
     for k in ("rho", "nngb", "ax", "ay", "az", "du_dt", "v_sig", "nforce"):
         assert np.array_equal(c[k].view(np.uint8), d[k].view(np.uint8)), k
+    # the grouped density rounds add their partial sums at every flush: the
+    # buffer size changes their FP32 summation order, not the neighbour sets
+    e = out[tuple(sorted(SHAPES[6].items()))]
+    f = out[tuple(sorted(SHAPES[7].items()))]
+    assert np.array_equal(e["nngb"], f["nngb"])
 
 
 def test_every_shape_matches_the_oracle(runs):
@@ -75,6 +81,7 @@ def test_autotune_returns_a_shape_and_keeps_h():
     tuned = sphx.autotune(ctx, grid, tasks, dp, out, reps=2)
     torch.cuda.synchronize()
     assert tuned.density_tile in (64, 128, 256) and tuned.density_waves in (1, 2)
+    assert tuned.density_balance in (0, 1, 2)
     assert tuned.force_tile in (64, 128) and tuned.force_waves in (1, 2)
     assert tuned.eta == ctx.params.eta and tuned.max_iter == ctx.params.max_iter
     np.testing.assert_array_equal(dp.t["h"].cpu().numpy(), ps.h)
@@ -108,3 +115,6 @@ def test_sparse_receivers_tile_neutral_and_match_oracle(frac):
         assert np.array_equal(a[k][recv].view(np.uint8), b[k][recv].view(np.uint8)), k
     ref = oracle.density(ps, ps.h.astype(np.float64), P, recv=recv)
     check_density(a, ref, ps, ps.h, recv, P, "active fraction %.2f" % frac)
+    # the grouped loop: few receivers per cell, small groups, many replicas
+    c = gpu_fixed_h(ps, params=dict(density_balance=2))
+    check_density(c, ref, ps, ps.h, recv, P, "grouped, active fraction %.2f" % frac)
