@@ -655,10 +655,13 @@ def main():
     if graph_k < 0:
         graph_k = info.passes if info.task_rebuilds == 0 else 0
     torch.cuda.synchronize()
+    sphx.probe_read(ctxp, clear=True)
     ctxp.profile(True)
     run_steps(ctxp, gridp, tasksp, args.steps)
     torch.cuda.synchronize()
     ctxp.profile(False)
+    # neighbour-test counters of a measurement build (SPHX_PROBE=1)
+    probe_on, probe = sphx.probe_read(ctxp, clear=True)
     dens_ms, dens_n = ctxp.profile_read(0)
     force_ms, force_n = ctxp.profile_read(1)
     dlist_ms, dlist_n = ctxp.profile_read(2)
@@ -769,6 +772,14 @@ def main():
                                         if args.kernel == "wendland_c2" else None),
                      "flop_per_launch": per_launch},
     }
+    if probe_on and probe[2] > 0:
+        line["probe"] = {
+            "lane_slots_per_accepted_pair": probe[0] / probe[2],
+            "receiver_lane_tests_per_accepted_pair": probe[1] / probe[2],
+            "accepted_pairs": probe[2], "steps": args.steps,
+            "what": "cell-pair density loop of a measurement build (SPHX_PROBE=1): lane slots "
+                    "of its candidate tests, the tests of lanes holding a receiver, accepted "
+                    "pairs (own particle included)"}
     del grid, tasks, out
     if not args.no_legs and args.config == "clustered":
         line["other_workloads"] = {

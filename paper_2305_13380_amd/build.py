@@ -20,6 +20,9 @@ SOURCES = ["grid.hip", "tasks.hip", "density.hip", "lists.hip", "ghost.hip", "fo
 ARCH = os.environ.get("SPHX_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+# SPHX_PROBE=1: a measurement build whose density loop counts its neighbour
+# tests (sphx_probe_read); product builds leave it out.
+PROBE = os.environ.get("SPHX_PROBE", "0") == "1"
 FLAGS = ["-x", "hip", "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
          "-I" + os.path.join(ROOT, "include"), "-I" + CSRC,
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -28,7 +31,8 @@ FLAGS = ["-x", "hip", "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
 
 def _compile(src, verbose):
     out = os.path.join(OBJ, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC] + FLAGS + ["-c", os.path.join(CSRC, src), "-o", out]
+    cmd = [HIPCC] + FLAGS + (["-DSPHX_PROBE=1"] if PROBE else []) + [
+        "-c", os.path.join(CSRC, src), "-o", out]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)

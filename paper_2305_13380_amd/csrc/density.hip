@@ -12,7 +12,18 @@
 //   receivers per wave, each lane walking its own list in its fixed order.
 #include "pairs.h"
 
+// Measurement builds (SPHX_PROBE=1) count the cell-pair loop's neighbour
+// tests: the lane slots the tests occupy, the tests made by lanes that hold a
+// receiver, and the accepted pairs, into probe_counts (read and cleared by
+// sphx_probe_read). Product builds count nothing.
+#ifndef SPHX_PROBE
+#define SPHX_PROBE 0
+#endif
+
 namespace sphx {
+
+__device__ unsigned long long probe_counts[3];
+
 namespace {
 
 constexpr int kSums = 9;  // Sw, Smw, Sud, Smud, Sdiv, Scx, Scy, Scz, count
@@ -327,10 +338,17 @@ __global__ __launch_bounds__(64 * NW) void k_density(
     };
     // The slot is always written; it is kept (the length advanced) only
     // when the candidate lies inside H.
+    unsigned probe_tests = 0, probe_hits = 0, probe_slots = 0;
     auto accept = [&](int c, const float4 &p, bool ok) __attribute__((always_inline)) {
         const float r2 = dist2(pr.x - p.x, pr.y - p.y, pr.z - p.z);
         my_list[myn] = uint8_t(c);
-        myn += (ok && r2 < H2r) ? 1 : 0;
+        const int hit = (ok && r2 < H2r) ? 1 : 0;
+        myn += hit;
+        if (SPHX_PROBE) {
+            probe_slots += 1;
+            probe_tests += (ract && c < CAP) ? 1 : 0;
+            probe_hits += hit;
+        }
     };
     auto flush = [&]() __attribute__((always_inline)) {
         wave_sync();
@@ -454,6 +472,15 @@ __global__ __launch_bounds__(64 * NW) void k_density(
 #pragma unroll
         for (int k = 0; k < kSums; ++k)
             S[k] += __shfl_xor(S[k], o, 64);
+    if (SPHX_PROBE) {
+        unsigned long long v[3] = {probe_slots, probe_tests, probe_hits};
+        for (int k = 0; k < 3; ++k) {
+            for (int o = 32; o > 0; o >>= 1)
+                v[k] += __shfl_xor(v[k], o, 64);
+            if (lane == 0)
+                atomicAdd(probe_counts + k, v[k]);
+        }
+    }
 
     if (NW > 1) {
         // Add the other waves' partial sums to wave 0's, in wave order.
@@ -845,6 +872,16 @@ __global__ __launch_bounds__(256) void k_stale_count(int64_t n, const uint8_t *_
         st = st || (need[i] && gamma_k * hs[i] > radius[leaf_of[i]]);
     if (__syncthreads_or(st) && threadIdx.x == 0)
         atomicAdd(stale, 1);  // one per block: at most 1024 on one word
+}
+
+sphx_status probe_read(unsigned long long out[3], bool clear)
+{
+    SPHX_HIP(hipMemcpyFromSymbol(out, HIP_SYMBOL(probe_counts), 3 * sizeof(unsigned long long)));
+    if (clear) {
+        const unsigned long long zero[3] = {0, 0, 0};
+        SPHX_HIP(hipMemcpyToSymbol(HIP_SYMBOL(probe_counts), zero, sizeof(zero)));
+    }
+    return SPHX_PROBE ? SPHX_OK : 1;
 }
 
 sphx_status stale_count_launch(const sphx_ctx *ctx, const sphx_grid *g, const sphx_tasks *t,

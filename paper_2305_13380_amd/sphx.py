@@ -78,7 +78,8 @@ SYMBOLS = ("sphx_params_default", "sphx_ctx_create", "sphx_ctx_destroy", "sphx_w
            "sphx_grid_leaves", "sphx_tasks_count", "sphx_last_error", "sphx_profile_enable",
            "sphx_profile_read", "sphx_autotune", "sphx_params_set_kernel", "sphx_fof",
            "sphx_gravity", "sphx_alpha_v_update", "sphx_force_noalloc", "sphx_gradient",
-           "sphx_alpha_c_update", "sphx_timestep", "sphx_kick", "sphx_drift")
+           "sphx_alpha_c_update", "sphx_timestep", "sphx_kick", "sphx_drift",
+           "sphx_probe_read")
 
 _LIB = None
 
@@ -126,6 +127,8 @@ def _load():
                              vp, vp]
     L.sphx_force_noalloc.argtypes = L.sphx_force.argtypes
     L.sphx_gradient.argtypes = [vp, vp, vp, P(Particles), vp, vp, vp, vp, vp, vp]
+    L.sphx_probe_read.argtypes = [vp, P(C.c_uint64), i32]
+    L.sphx_probe_read.restype = i32
     L.sphx_alpha_c_update.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, C.c_double, vp, vp]
     L.sphx_timestep.argtypes = [vp, vp, vp, P(Particles), vp, C.c_double, C.c_double, vp, vp,
                                 vp]
@@ -442,6 +445,14 @@ def alpha_v_update(ctx, alpha_v, div_old, div_new, c, h, v_sig, dt, stream=None)
                                    _ptr(div_new), _ptr(c), _ptr(h), _ptr(v_sig), float(dt),
                                    _ptr(alpha_v), _stream(stream)))
     return alpha_v
+
+
+def probe_read(ctx, clear=True):
+    """Neighbour-test counters of a measurement build (sphx_probe_read):
+    (probe build?, [lane slots, receiver-lane tests, accepted pairs])."""
+    v = (C.c_uint64 * 3)()
+    st = _check(lib.sphx_probe_read(ctx.handle, v, 1 if clear else 0))
+    return st == 0, [int(x) for x in v]
 
 
 def gradient(ctx, grid, tasks, parts, out: Outputs, stream=None):
