@@ -146,8 +146,14 @@ class Params:
     h_max: Optional[float] = None  # default: min(box) / (3 gamma_k) * (1 - 1e-6)
     # "energy": density-energy (u is the internal energy, with conduction);
     # "entropy": density-entropy, the Gadget2 flavour of Section 3.2 (the u
-    # array holds the adiabat A, no conduction, du/dt becomes dA/dt)
+    # array holds the adiabat A, no conduction, du/dt becomes dA/dt);
+    # "phantom": the Phantom-like flavour of Appendix A (density-energy, fixed
+    # alpha_c = 1, conduction speed without the velocity term; its viscosity
+    # switch decays with ell = 0.25)
     flavour: str = "energy"
+
+    def flavour_id(self) -> int:
+        return {"energy": 0, "entropy": 1, "phantom": 2}[self.flavour]
 
     def hmax(self) -> float:
         if self.h_max is not None:
@@ -426,7 +432,7 @@ def force(ps, h, gst, dens_rho, params: Params, recv=None, mode="auto", cand=Non
                            float(params.gamma_k), params.kernel_id(), float(params.beta_v),
                            nrecv, r, off, idx,
                            out["ax"], out["ay"], out["az"], out["du"], out["vsig"], nf,
-                           int(params.flavour == "entropy"), float(params.gamma_gas),
+                           params.flavour_id(), float(params.gamma_gas),
                            out["du_energy"])
     out["nforce"] = nf
     out["total"] = int(total)
@@ -586,6 +592,7 @@ def gravity(ps, G, H, rs, rp2p, periodic=True, recv=None, mode="auto"):
 
 SPHENIX_ALPHA_V_MAX = 2.0   # Section 3.3: maximal viscosity parameter
 SPHENIX_ELL = 0.05          # Section 3.3: viscosity decay length
+PHANTOM_ELL = 0.25          # Appendix A: the Phantom-like flavour's decay length
 
 
 def alpha_v_update(alpha, div_old, div_new, c, h, vsig, dt, params: Params,

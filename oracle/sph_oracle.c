@@ -357,11 +357,14 @@ void or_ghost(int64_t n, const double *rho, const double *rho_dh, const double *
  *   vsig_i = max(2 c_i, max_j vsig_ij)
  * Coincident pairs (r = 0) are counted but add nothing (every term carries
  * a kernel gradient, which vanishes at r = 0). Returns the total count.
- * With entropy != 0 (density-entropy, the Gadget2 flavour of Section 3.2:
- * the input u holds the adiabat A, dA/dt = 0 but for the viscous heating)
- * there is no conduction, du receives dA/dt = (gamma - 1) rho_i^(1 - gamma)
+ * flavour 1 (density-entropy, the Gadget2 flavour of Section 3.2: the input
+ * u holds the adiabat A, dA/dt = 0 but for the viscous heating): there is no
+ * conduction, du receives dA/dt = (gamma - 1) rho_i^(1 - gamma)
  * sum_j m_j (nu G / 4) (v_ij . e), and du_energy (if not NULL) the
  * internal-energy rate sum_j m_j [A_i g_i + nu G / 4] (v_ij . e).
+ * flavour 2 (the Phantom-like flavour of Appendix A): conduction with
+ * alpha_c = 1 for every particle and v_c,ij = sqrt(2 |P_i - P_j| / (rho_i +
+ * rho_j)); the rest as flavour 0 (density-energy).
  */
 int64_t or_force(int64_t n, const double *x, const double *y, const double *z,
                  const double *vx, const double *vy, const double *vz,
@@ -372,8 +375,9 @@ int64_t or_force(int64_t n, const double *x, const double *y, const double *z,
                  int64_t nrecv, const int64_t *recv,
                  const int64_t *cand_off, const int64_t *cand_idx,
                  double *ax, double *ay, double *az, double *du, double *vsig, int64_t *nforce,
-                 int entropy, double gamma_gas, double *du_energy)
+                 int flavour, double gamma_gas, double *du_energy)
 {
+    const int entropy = flavour == 1, phantom = flavour == 2;
     int64_t total = 0;
 #pragma omp parallel for schedule(dynamic, 16) reduction(+ : total)
     for (int64_t k = 0; k < nrecv; ++k) {
@@ -423,7 +427,12 @@ int64_t or_force(int64_t n, const double *x, const double *y, const double *z,
             s_az -= m[j] * acc * ez;
             s_du += m[j] * (Agi + 0.25 * nu * G) * vdote;
             s_visc += m[j] * 0.25 * nu * G * vdote;
-            if (!entropy) {
+            if (phantom) {
+                /* Phantom-like (Appendix A): alpha_c = 1 for every particle and
+                 * the conduction speed without the velocity term */
+                double v_c = sqrt(2.0 * fabs(P[i] - P[j]) / (rho[i] + rho[j]));
+                s_du += m[j] * v_c * (u[i] - u[j]) * G / (rho[i] + rho[j]);
+            } else if (!entropy) {
                 double psum = P[i] + P[j];
                 double alpha_c_ij =
                     psum > 0.0 ? (P[i] * alpha_c[i] + P[j] * alpha_c[j]) / psum : 0.0;
