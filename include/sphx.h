@@ -111,12 +111,17 @@ typedef struct sphx_params {
      * solver: the u array holds the adiabat A, P = A rho^gamma, no
      * conduction, and sphx_force_out.du_dt receives dA/dt = (gamma - 1)
      * rho^(1 - gamma) times the viscous heating rate; the FP64 energy sum
-     * keeps the internal-energy rate the forces imply). */
+     * keeps the internal-energy rate the forces imply) or SPHX_FLAVOUR_PHANTOM
+     * (the Phantom-like flavour of Appendix A: density-energy with alpha_c = 1
+     * for every particle, conduction speed sqrt(2 |P_i - P_j| / (rho_i +
+     * rho_j)), and the viscosity switch of sphx_alpha_v_update decaying with
+     * length 0.25 instead of 0.05). */
     int32_t flavour;
 } sphx_params;
 
 #define SPHX_FLAVOUR_DENSITY_ENERGY 0
 #define SPHX_FLAVOUR_DENSITY_ENTROPY 1
+#define SPHX_FLAVOUR_PHANTOM 2
 
 #define SPHX_KERNEL_WENDLAND_C2 0
 #define SPHX_KERNEL_WENDLAND_C4 1
@@ -386,8 +391,9 @@ sphx_status sphx_gravity(sphx_ctx *ctx, const sphx_particles *in, double G, doub
  * of two steps), the shock indicator S = H^2 max(0, -(div_new - div_old)/dt)
  * with H = gamma_k h, and the target alpha_loc = 2 S / (v_sig^2 + S) (0 where
  * S = 0; alpha_max = 2), alpha_v becomes alpha_loc if that is larger, else
- * alpha_loc + (alpha_v - alpha_loc) exp(-0.05 c dt / H) (decay length 0.05;
- * the printed update is read as this decay towards the target). alpha_v is
+ * alpha_loc + (alpha_v - alpha_loc) exp(-ell c dt / H) (decay length ell =
+ * 0.05, or 0.25 with the Phantom-like flavour; the printed update is read as
+ * this decay towards the target). alpha_v is
  * read and written in place; c is the sound speed (sphx_ghost_out.c), h the
  * smoothing length, v_sig the signal velocity (sphx_force_out.v_sig).
  * dt > 0 and finite, n >= 0, else E_INVALID. Asynchronous on `stream`. */

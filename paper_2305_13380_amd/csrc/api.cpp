@@ -182,7 +182,8 @@ sphx_status sphx_ctx_create(const sphx_params *p, int hip_device, sphx_ctx **out
         set_error("sphx_ctx_create: unknown kernel (SPHX_KERNEL_*)");
         return SPHX_E_INVALID;
     }
-    if (p->flavour != SPHX_FLAVOUR_DENSITY_ENERGY && p->flavour != SPHX_FLAVOUR_DENSITY_ENTROPY) {
+    if (p->flavour != SPHX_FLAVOUR_DENSITY_ENERGY && p->flavour != SPHX_FLAVOUR_DENSITY_ENTROPY &&
+        p->flavour != SPHX_FLAVOUR_PHANTOM) {
         set_error("sphx_ctx_create: unknown flavour (SPHX_FLAVOUR_*)");
         return SPHX_E_INVALID;
     }

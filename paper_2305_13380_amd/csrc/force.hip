@@ -54,11 +54,13 @@ struct StepOut {
     const float4 *g2;
 };
 
-// ENT: the density-entropy flavour (Section 3.2): the particles' u is the
-// adiabat A (their P came from A rho^gamma in the ghost), no conduction, and
-// the output rate is dA/dt = (gamma - 1) rho^(1 - gamma) du/dt|visc; the
-// FP64 energy sum keeps the internal-energy rate.
-template <int CAP, int NW, int K, bool ENT>
+// FLAV: SPHX_FLAVOUR_* (0 density-energy; 1 density-entropy, Section 3.2:
+// the particles' u is the adiabat A (their P came from A rho^gamma in the
+// ghost), no conduction, and the output rate is dA/dt = (gamma - 1)
+// rho^(1 - gamma) du/dt|visc, the FP64 energy sum keeping the internal-energy
+// rate; 2 the Phantom-like flavour of Appendix A: conduction with alpha_c = 1
+// and the speed sqrt(2 |P_i - P_j| / (rho_i + rho_j))).
+template <int CAP, int NW, int K, int FLAV>
 __global__ __launch_bounds__(64 * NW) void k_force(
     int64_t n_leaves, int64_t nb_padded, const int32_t *__restrict__ order,
     const int32_t *__restrict__ leaf_start,
@@ -210,13 +212,15 @@ __global__ __launch_bounds__(64 * NW) void k_force(
         const float acc = Agi + Agj + 0.5f * nu * G;
         const float m = v.w;
         const float psum = Pi + a.w;
-        const float ac = psum > 0.0f ? (acPi + c2.x) * fast_rcp(psum) : 0.0f;
-        const float vc = fabsf(vdote) + fast_sqrt(2.0f * fabsf(Pi - a.w) * irs);
+        const float ac =
+            FLAV == 2 ? 1.0f : (psum > 0.0f ? (acPi + c2.x) * fast_rcp(psum) : 0.0f);
+        const float vc =
+            (FLAV == 2 ? 0.0f : fabsf(vdote)) + fast_sqrt(2.0f * fabsf(Pi - a.w) * irs);
         const float dvi = m * (0.25f * nu * G) * vdote;
-        const float dui = ENT ? m * Agi * vdote + dvi
-                              : m * (Agi + 0.25f * nu * G) * vdote +
-                                    m * ac * vc * (vi.w - c2.y) * G * irs;
-        if (ENT)
+        const float dui = FLAV == 1 ? m * Agi * vdote + dvi
+                                    : m * (Agi + 0.25f * nu * G) * vdote +
+                                          m * ac * vc * (vi.w - c2.y) * G * irs;
+        if (FLAV == 1)
             duv += dvi;
         ax -= m * acc * ex;
         ay -= m * acc * ey;
@@ -372,7 +376,7 @@ __global__ __launch_bounds__(64 * NW) void k_force(
         ay += __shfl_xor(ay, o, 64);
         az += __shfl_xor(az, o, 64);
         du += __shfl_xor(du, o, 64);
-        if (ENT)
+        if (FLAV == 1)
             duv += __shfl_xor(duv, o, 64);
         vsig = fmaxf(vsig, __shfl_xor(vsig, o, 64));
         nf += __shfl_xor(nf, o, 64);
@@ -404,7 +408,7 @@ __global__ __launch_bounds__(64 * NW) void k_force(
         o_ax[gr] = F[0];
         o_ay[gr] = F[1];
         o_az[gr] = F[2];
-        o_du[gr] = ENT ? (gamma_gas - 1.0f) * powf(rhoi, 1.0f - gamma_gas) * F[6] : F[3];
+        o_du[gr] = FLAV == 1 ? (gamma_gas - 1.0f) * powf(rhoi, 1.0f - gamma_gas) * F[6] : F[3];
         o_vsig[gr] = F[4];
         if (o_nf)
             o_nf[gr] = int32_t(F[5]);
@@ -567,14 +571,14 @@ sphx_status noalloc_scratch(int device, double **out)
 }
 
 // The loop shapes of one kernel kind.
-template <int K, bool ENT>
+template <int K, int FLAV>
 static void force_shapes(int tile, int waves, int64_t nbp, const sphx_ctx *ctx,
                          const sphx_grid *g, const sphx_tasks *t, const sphx_particles *in,
                          const sphx_force_out *o, float far, const int32_t *gate,
                          const StepOut &so, double *fsum, hipStream_t s)
 {
 #define SPHX_FORCE_LAUNCH(CAP_, NW_)                                                           \
-    k_force<CAP_, NW_, K, ENT><<<unsigned(nbp), 64 * NW_, 0, s>>>(                                \
+    k_force<CAP_, NW_, K, FLAV><<<unsigned(nbp), 64 * NW_, 0, s>>>(                               \
         g->n_leaves, nbp, t->order, g->leaf_start, g->perm, g->q0, g->q1, g->qa, g->g0, g->g1, \
         in->active, t->off, t->task, g->leaf_ext, g->leaf_hmax, float(ctx->p.gamma_k),         \
         float(ctx->p.beta_v), far, o->ax,                                                      \
@@ -634,11 +638,14 @@ sphx_status force_launch(const sphx_ctx *ctx, const sphx_grid *g, const sphx_tas
     const int tile = ctx->p.force_tile ? ctx->p.force_tile : 64;
     const int waves = ctx->p.force_waves ? ctx->p.force_waves : 1;
     if (ctx->p.flavour == SPHX_FLAVOUR_DENSITY_ENTROPY) {
-        SPHX_WITH_KERNEL(ctx->p.kernel, (force_shapes<KK, true>(tile, waves, nbp, ctx, g, t, in,
-                                                                 o, far, gate, so, fsum, s)));
+        SPHX_WITH_KERNEL(ctx->p.kernel, (force_shapes<KK, 1>(tile, waves, nbp, ctx, g, t, in, o,
+                                                              far, gate, so, fsum, s)));
+    } else if (ctx->p.flavour == SPHX_FLAVOUR_PHANTOM) {
+        SPHX_WITH_KERNEL(ctx->p.kernel, (force_shapes<KK, 2>(tile, waves, nbp, ctx, g, t, in, o,
+                                                              far, gate, so, fsum, s)));
     } else {
-        SPHX_WITH_KERNEL(ctx->p.kernel, (force_shapes<KK, false>(tile, waves, nbp, ctx, g, t, in,
-                                                                  o, far, gate, so, fsum, s)));
+        SPHX_WITH_KERNEL(ctx->p.kernel, (force_shapes<KK, 0>(tile, waves, nbp, ctx, g, t, in, o,
+                                                              far, gate, so, fsum, s)));
     }
     SPHX_HIP(hipGetLastError());
     if (prof)

@@ -171,13 +171,13 @@ def _check(status):
     return status
 
 
-FLAVOURS = {"energy": 0, "entropy": 1}  # SPHX_FLAVOUR_DENSITY_ENERGY / _ENTROPY
+FLAVOURS = {"energy": 0, "entropy": 1, "phantom": 2}  # SPHX_FLAVOUR_*
 
 
 def default_params(**kw) -> Params:
     """The library's defaults with fields overridden by keyword; kernel= takes
     a name of KERNELS (or its number) and sets the kernel's gamma_k too;
-    flavour= takes "energy" or "entropy" (or the number)."""
+    flavour= takes "energy", "entropy" or "phantom" (or the number)."""
     p = Params()
     lib.sphx_params_default(C.byref(p))
     if isinstance(kw.get("flavour"), str):

@@ -1,9 +1,13 @@
-"""GPU density-entropy flavour (the Gadget2 solver of Section 3.2) against
-the oracle: a whole step (h iteration, ghost with P = A rho^gamma, force
-pass without conduction, dA/dt from the viscous heating) compared output by
-output with the oracle evaluated at the step's own h, at the fixed-h
-tolerances, and the FP64 sums with the internal-energy rate the forces
-imply."""
+"""GPU SPH flavours against the oracle, output by output at the step's own
+h and the fixed-h tolerances:
+
+* density-entropy (the Gadget2 solver of Section 3.2): a whole step (h
+  iteration, ghost with P = A rho^gamma, force pass without conduction,
+  dA/dt from the viscous heating), and the FP64 sums with the
+  internal-energy rate the forces imply;
+* Phantom-like (Appendix A): a whole step with alpha_c = 1 and the pressure
+  conduction speed, and its viscosity switch with decay length 0.25.
+"""
 import numpy as np
 import pytest
 
@@ -15,6 +19,7 @@ from helpers import check_density, check_force, check_ghost, gpu_step
 pytestmark = pytest.mark.gpu
 PE = oracle.Params()
 PS = oracle.Params(flavour="entropy")
+PP = oracle.Params(flavour="phantom")
 
 
 def as_entropy(ps):
@@ -57,3 +62,37 @@ def test_entropy_step_matches_oracle(case):
     assert np.abs(s[:3]).max() < 2e-5 * s[4]
     np.testing.assert_allclose(s[4:], s_ref[4:], rtol=1e-4)
     assert abs(s[3] - s_ref[3]) <= 1e-4 * (s_ref[4] * 1.0 + s_ref[5])
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_phantom_step_matches_oracle(case):
+    ps = CASES[case]()
+    if case == "sedov16":
+        ps.vx[:] = np.random.default_rng(5).normal(0, 0.5, ps.n).astype(np.float32)
+    print("phantom flavour step:", case, "N=%d" % ps.n, flush=True)
+    g = gpu_step(ps, params={"flavour": "phantom"})
+    assert g["status"] >= 0 and g["info"].unconverged == 0
+    h = g["h"].astype(np.float64)
+    ref = oracle.fixed_h_step(ps, PP, h=h)
+    recv = np.arange(ps.n)
+    where = "phantom %s at its h" % case
+    check_density(g, ref, ps, h, recv, PP, where)
+    check_ghost(g, ref, recv, where)
+    check_force(g, ref, ps, h, recv, PP, where)
+
+
+def test_phantom_viscosity_switch_decay_length():
+    import torch
+    from paper_2305_13380_amd import sphx
+    from test_gpu_sphenix import inputs_set
+    alpha, dold, dnew, c, h, vs = inputs_set(20011, 7)
+    ctx = sphx.Context(sphx.default_params(flavour="phantom"), 0)
+    t = [torch.from_numpy(a).cuda() for a in (alpha, dold, dnew, c, h, vs)]
+    sphx.alpha_v_update(ctx, t[0], t[1], t[2], t[3], t[4], t[5], 1e-2)
+    torch.cuda.synchronize()
+    got = t[0].cpu().numpy().astype(np.float64)
+    ref = oracle.alpha_v_update(alpha, dold, dnew, c, h, vs, 1e-2, PE, ell=oracle.PHANTOM_ELL)
+    err = np.abs(got - ref)
+    assert np.all(err <= 2e-6 * np.maximum(np.abs(got), np.abs(ref)) + 1e-12)
+    other = oracle.alpha_v_update(alpha, dold, dnew, c, h, vs, 1e-2, PE)  # ell = 0.05
+    assert np.abs(other - ref).max() > 1e-3
