@@ -67,13 +67,18 @@ def lib():
                                   _dp, _dp, _dp, _i32p]
         L.or_h_update.restype = None
         L.or_ghost.argtypes = ([C.c_int64] + [_dp] * 8 + [C.c_double, C.c_double] + [_dp] * 7
-                               + [C.c_int])
+                               + [C.c_int] + [_nullable(_dp)] * 4)
         L.or_ghost.restype = None
         L.or_force.argtypes = ([C.c_int64] + [_dp] * 16 + [_dp, C.c_int, C.c_double, C.c_int,
                                C.c_double,
                                C.c_int64, _nullable(_ip), _nullable(_ip), _nullable(_ip)]
-                               + [_dp] * 5 + [_ip, C.c_int, C.c_double, _nullable(_dp)])
+                               + [_dp] * 5 + [_ip, C.c_int, C.c_double, _nullable(_dp),
+                                              _nullable(_dp)])
         L.or_force.restype = C.c_int64
+        L.or_pressure.argtypes = ([C.c_int64] + [_dp] * 7 + [C.c_int, C.c_double, C.c_int,
+                                  C.c_double, C.c_int64, _nullable(_ip), _nullable(_ip),
+                                  _nullable(_ip), _dp, _dp])
+        L.or_pressure.restype = None
         L.or_sums.argtypes = [C.c_int64] + [_dp] * 8 + [_dp]
         L.or_sums.restype = None
         L.or_fof.argtypes = ([C.c_int64] + [_dp] * 4 + [C.c_int, C.c_double, _nullable(_ip),
@@ -149,11 +154,14 @@ class Params:
     # array holds the adiabat A, no conduction, du/dt becomes dA/dt);
     # "phantom": the Phantom-like flavour of Appendix A (density-energy, fixed
     # alpha_c = 1, conduction speed without the velocity term; its viscosity
-    # switch decays with ell = 0.25)
+    # switch decays with ell = 0.25);
+    # "pressure_energy": pressure-smoothed SPH of Appendix A (the smoothed
+    # pressure P_hat from u, factors f_ij, density-flavour viscosity, no
+    # conduction; u > 0 everywhere)
     flavour: str = "energy"
 
     def flavour_id(self) -> int:
-        return {"energy": 0, "entropy": 1, "phantom": 2}[self.flavour]
+        return {"energy": 0, "entropy": 1, "phantom": 2, "pressure_energy": 3}[self.flavour]
 
     def hmax(self) -> float:
         if self.h_max is not None:
@@ -338,7 +346,30 @@ def density(ps, h, params: Params, recv=None, mode="auto"):
                              out["div_sum"], out["curl_x"], out["curl_y"], out["curl_z"], nngb)
     out["nngb"] = nngb
     out["total"] = int(total)
+    if params.flavour == "pressure_energy":
+        out["P_hat"], out["P_hat_dh"] = np.zeros(nrecv), np.zeros(nrecv)
+        lib().or_pressure(ps.n, x, y, z, _f64(ps.m), _f64(ps.u), h, _f64(ps.box),
+                          int(params.periodic), float(params.gamma_k), params.kernel_id(),
+                          float(params.gamma_gas), nrecv, r, off, idx, out["P_hat"],
+                          out["P_hat_dh"])
     return out
+
+
+def pressure(ps, h, params: Params, recv=None, mode="auto"):
+    """Smoothed pressure and its h-derivative at the given h (or_pressure,
+    Appendix A)."""
+    mode = _resolve_mode(mode, ps.n)
+    h = _f64(h)
+    r, nrecv = _recv_arr(recv, ps.n)
+    off = idx = None
+    if mode == "tree":
+        off, idx = density_candidates(ps, h, params, r)
+    P, P_dh = np.zeros(nrecv), np.zeros(nrecv)
+    x, y, z = _pos(ps)
+    lib().or_pressure(ps.n, x, y, z, _f64(ps.m), _f64(ps.u), h, _f64(ps.box),
+                      int(params.periodic), float(params.gamma_k), params.kernel_id(),
+                      float(params.gamma_gas), nrecv, r, off, idx, P, P_dh)
+    return P, P_dh
 
 
 def h_update(h, nd, nd_dh, params: Params, lo=None, hi=None):
@@ -358,14 +389,18 @@ def h_update(h, nd, nd_dh, params: Params, lo=None, hi=None):
 
 
 def ghost(dens, u, h, params: Params):
-    """Pressure, sound speed, f-factor, Balsara switch and A = f P / rho^2."""
+    """Pressure, sound speed, f-factor, Balsara switch and A = f P / rho^2
+    (pressure-energy: P = P_hat and A the grad-h term F of its f_ij)."""
     n = dens["rho"].shape[0]
     out = {k: np.zeros(n) for k in ("f", "P", "c", "balsara", "A", "div_v", "curl_v")}
+    pe = params.flavour == "pressure_energy"
+    extra = ([_f64(dens[k]) for k in ("n", "n_dh", "P_hat", "P_hat_dh")] if pe
+             else [None] * 4)
     lib().or_ghost(n, _f64(dens["rho"]), _f64(dens["rho_dh"]), _f64(dens["div_sum"]),
                    _f64(dens["curl_x"]), _f64(dens["curl_y"]), _f64(dens["curl_z"]), _f64(u),
                    _f64(h), float(params.gamma_gas), float(params.eps_b), out["f"], out["P"],
                    out["c"], out["balsara"], out["A"], out["div_v"], out["curl_v"],
-                   int(params.flavour == "entropy"))
+                   params.flavour_id(), *extra)
     return out
 
 
@@ -433,7 +468,8 @@ def force(ps, h, gst, dens_rho, params: Params, recv=None, mode="auto", cand=Non
                            nrecv, r, off, idx,
                            out["ax"], out["ay"], out["az"], out["du"], out["vsig"], nf,
                            params.flavour_id(), float(params.gamma_gas),
-                           out["du_energy"])
+                           out["du_energy"],
+                           _f64(gst["A"]) if params.flavour == "pressure_energy" else None)
     out["nforce"] = nf
     out["total"] = int(total)
     return out
@@ -472,7 +508,7 @@ def fixed_h_step(ps, params: Params, recv=None, mode="auto", h=None):
     need = force_needed(ps, h, params, recv, mode, cand=cand)
     d = density(ps, h, params, recv=need, mode=mode)
     g = ghost(d, _f64(ps.u)[need], h[need], params)
-    full = {k: np.full(ps.n, np.nan) for k in ("P", "c", "f", "balsara")}
+    full = {k: np.full(ps.n, np.nan) for k in ("P", "c", "f", "balsara", "A")}
     rho = np.full(ps.n, np.nan)
     for k in full:
         full[k][need] = g[k]

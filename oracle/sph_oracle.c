@@ -59,6 +59,12 @@
  *  - time step (Section 3.4): the CFL condition, named but not printed, is
  *    read as dt = c_cfl H / v_sig; the first limiter caps a step at Delta
  *    times the smallest step among the force-loop neighbours.
+ *  - pressure-energy (Appendix A): the factors f_ij take the form printed
+ *    for this flavour, with the number density n = sum_j W_ij in both
+ *    brackets (the generic form of Section 3.2 prints the smoothed b there);
+ *    du/dt is the energy-conserving partner of the printed acceleration;
+ *    the sound speed is sqrt(gamma P_hat / rho); the viscosity is that of
+ *    the density flavours and there is no conduction.
  */
 #include <math.h>
 #include <stddef.h>
@@ -248,6 +254,44 @@ int64_t or_density(int64_t n, const double *x, const double *y, const double *z,
 }
 
 /*
+ * Smoothed pressure of the pressure-energy flavour (Appendix A, pressure-
+ * smoothed SPH) at the receiver's h, over the density neighbours r_ij < H_i
+ * with the receiver's own particle included (as for rho):
+ *   P_hat_i    = (gamma - 1) sum_j m_j u_j W(r_ij, h_i),
+ *   P_hat_dh_i = (gamma - 1) sum_j m_j u_j dW/dh(r_ij, h_i).
+ */
+void or_pressure(int64_t n, const double *x, const double *y, const double *z,
+                 const double *m, const double *u, const double *h, const double *box,
+                 int periodic, double gamma_k, int kernel, double gamma_gas, int64_t nrecv,
+                 const int64_t *recv, const int64_t *cand_off, const int64_t *cand_idx,
+                 double *P_hat, double *P_hat_dh)
+{
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t k = 0; k < nrecv; ++k) {
+        int64_t i = recv ? recv[k] : k;
+        double hi = h[i], Hi = gamma_k * hi;
+        double s_p = 0, s_p_dh = 0;
+        int64_t jb = cand_off ? cand_off[k] : 0;
+        int64_t je = cand_off ? cand_off[k + 1] : n;
+        for (int64_t q = jb; q < je; ++q) {
+            int64_t j = cand_off ? cand_idx[q] : q;
+            double dx = min_image(x[i] - x[j], box[0], periodic);
+            double dy = min_image(y[i] - y[j], box[1], periodic);
+            double dz = min_image(z[i] - z[j], box[2], periodic);
+            double r = sqrt(dx * dx + dy * dy + dz * dz);
+            if (!(r < Hi))
+                continue;
+            double w, dwdr, dwdh;
+            or_kernel(kernel, r, hi, gamma_k, &w, &dwdr, &dwdh);
+            s_p += m[j] * u[j] * w;
+            s_p_dh += m[j] * u[j] * dwdh;
+        }
+        P_hat[k] = (gamma_gas - 1.0) * s_p;
+        P_hat_dh[k] = (gamma_gas - 1.0) * s_p_dh;
+    }
+}
+
+/*
  * One Newton-Raphson update of h on the partition-of-unity condition
  * (Section 3.1), n(h) (h/eta)^3 = 1, taken in the variable ln h:
  *   G(ln h) = ln(n h^3 / eta^3) = 0,   dG/d ln h = 3 + (h/n) dn/dh,
@@ -312,28 +356,44 @@ void or_h_update(int64_t n, const double *h, const double *nd, const double *nd_
  *   div v = div_sum / rho,  |curl v| = |curl_sum| / rho,
  *   B = |div v| / (|div v| + |curl v| + eps c / h),
  *   A = f P / rho^2.
- * With entropy != 0 (density-entropy, Section 3.2) the input u is the
+ * With flavour 1 (density-entropy, Section 3.2) the input u is the
  * adiabat A_i and P = A_i rho^gamma; the rest is unchanged.
+ * With flavour 3 (pressure-energy, Appendix A) the pressure is the smoothed
+ * one, P = P_hat (or_pressure), c = sqrt(gamma P_hat / rho), and A returns
+ * the grad-h term of its factors f_ij = 1 - A_i / (m_j u_j),
+ *   A_i = [h_i dP_hat_i/dh / ((gamma - 1) 3 n_i)] / [1 + h_i/(3 n_i) dn_i/dh],
+ * with n the number density; f, div, curl and B as for the other flavours
+ * (B with this sound speed). nd, nd_dh, P_hat and P_hat_dh are read only
+ * for flavour 3 (NULL otherwise).
  */
 void or_ghost(int64_t n, const double *rho, const double *rho_dh, const double *div_sum,
               const double *curl_x, const double *curl_y, const double *curl_z,
               const double *u, const double *h, double gamma_gas, double eps_b,
               double *f, double *P, double *c, double *balsara, double *A,
-              double *div_v, double *curl_v, int entropy)
+              double *div_v, double *curl_v, int flavour, const double *nd,
+              const double *nd_dh, const double *P_hat, const double *P_hat_dh)
 {
+    const int entropy = flavour == 1, pe = flavour == 3;
     for (int64_t k = 0; k < n; ++k) {
         double r = rho[k];
         /* density-energy: u is the internal energy; density-entropy (the
          * Gadget2 flavour of Section 3.2): u holds the adiabat A, and the
          * equation of state is its other printed form A rho^gamma */
-        P[k] = entropy ? u[k] * pow(r, gamma_gas) : (gamma_gas - 1.0) * u[k] * r;
+        if (pe)
+            P[k] = P_hat[k];
+        else
+            P[k] = entropy ? u[k] * pow(r, gamma_gas) : (gamma_gas - 1.0) * u[k] * r;
         c[k] = sqrt(gamma_gas * P[k] / r);
         f[k] = 1.0 / (1.0 + h[k] / (3.0 * r) * rho_dh[k]);
         div_v[k] = div_sum[k] / r;
         curl_v[k] = sqrt(curl_x[k] * curl_x[k] + curl_y[k] * curl_y[k] + curl_z[k] * curl_z[k]) / r;
         double ad = fabs(div_v[k]);
         balsara[k] = ad / (ad + curl_v[k] + eps_b * c[k] / h[k]);
-        A[k] = f[k] * P[k] / (r * r);
+        if (pe)
+            A[k] = (h[k] * P_hat_dh[k] / ((gamma_gas - 1.0) * 3.0 * nd[k])) /
+                   (1.0 + h[k] / (3.0 * nd[k]) * nd_dh[k]);
+        else
+            A[k] = f[k] * P[k] / (r * r);
     }
 }
 
@@ -365,6 +425,14 @@ void or_ghost(int64_t n, const double *rho, const double *rho_dh, const double *
  * flavour 2 (the Phantom-like flavour of Appendix A): conduction with
  * alpha_c = 1 for every particle and v_c,ij = sqrt(2 |P_i - P_j| / (rho_i +
  * rho_j)); the rest as flavour 0 (density-energy).
+ * flavour 3 (pressure-energy, Appendix A): P holds the smoothed pressure
+ * P_hat and F the ghost's grad-h terms; with f_ij = 1 - F_i / (m_j u_j),
+ * f_ji = 1 - F_j / (m_i u_i) and K_ij = (gamma - 1)^2 u_i u_j,
+ *   a_i  -= m_j [K_ij (f_ij g_i / P_i + f_ji g_j / P_j) + nu G / 2] e
+ *   du_i += m_j [K_ij f_ij g_i / P_i + nu G / 4] (v_ij . e)
+ * (the internal-energy equation is the one that conserves the total energy
+ * with this acceleration), the same viscosity as the density flavours (f,
+ * rho and c of the ghost) and no conduction. F is read only for flavour 3.
  */
 int64_t or_force(int64_t n, const double *x, const double *y, const double *z,
                  const double *vx, const double *vy, const double *vz,
@@ -375,15 +443,16 @@ int64_t or_force(int64_t n, const double *x, const double *y, const double *z,
                  int64_t nrecv, const int64_t *recv,
                  const int64_t *cand_off, const int64_t *cand_idx,
                  double *ax, double *ay, double *az, double *du, double *vsig, int64_t *nforce,
-                 int flavour, double gamma_gas, double *du_energy)
+                 int flavour, double gamma_gas, double *du_energy, const double *F)
 {
-    const int entropy = flavour == 1, phantom = flavour == 2;
+    const int entropy = flavour == 1, phantom = flavour == 2, pe = flavour == 3;
+    const double gm1sq = (gamma_gas - 1.0) * (gamma_gas - 1.0);
     int64_t total = 0;
 #pragma omp parallel for schedule(dynamic, 16) reduction(+ : total)
     for (int64_t k = 0; k < nrecv; ++k) {
         int64_t i = recv ? recv[k] : k;
         double Hi = gamma_k * h[i];
-        double Ai = f[i] * P[i] / (rho[i] * rho[i]);
+        double Ai = pe ? 0.0 : f[i] * P[i] / (rho[i] * rho[i]);
         double s_ax = 0, s_ay = 0, s_az = 0, s_du = 0, s_visc = 0;
         double s_vsig = 2.0 * c[i];
         int64_t cnt = 0;
@@ -415,11 +484,20 @@ int64_t or_force(int64_t n, const double *x, const double *y, const double *z,
             double vsig_ij = c[i] + c[j] - beta_v * mu;
             double alpha_ij = 0.5 * (alpha_v[i] + alpha_v[j]) * 0.5 * (balsara[i] + balsara[j]);
             double nu = -alpha_ij * mu * vsig_ij / (0.5 * (rho[i] + rho[j]));
-            double Aj = f[j] * P[j] / (rho[j] * rho[j]);
+            double Aj = pe ? 0.0 : f[j] * P[j] / (rho[j] * rho[j]);
             /* a kernel term outside its own support is zero (W' = 0 there),
              * also when the particle's f is infinite (alone in its support) */
             double fgi = r < Hi ? f[i] * gi : 0.0, Agi = r < Hi ? Ai * gi : 0.0;
             double fgj = r < Hj ? f[j] * gj : 0.0, Agj = r < Hj ? Aj * gj : 0.0;
+            if (pe) {
+                /* pressure-energy: the pressure terms with the smoothed
+                 * pressure and the factors f_ij, f_ji */
+                double K = gm1sq * u[i] * u[j];
+                double fij = 1.0 - F[i] / (m[j] * u[j]);
+                double fji = 1.0 - F[j] / (m[i] * u[i]);
+                Agi = r < Hi ? K * fij * gi / P[i] : 0.0;
+                Agj = r < Hj ? K * fji * gj / P[j] : 0.0;
+            }
             double G = fgi + fgj;
             double acc = Agi + Agj + 0.5 * nu * G;
             s_ax -= m[j] * acc * ex;
@@ -432,7 +510,7 @@ int64_t or_force(int64_t n, const double *x, const double *y, const double *z,
                  * the conduction speed without the velocity term */
                 double v_c = sqrt(2.0 * fabs(P[i] - P[j]) / (rho[i] + rho[j]));
                 s_du += m[j] * v_c * (u[i] - u[j]) * G / (rho[i] + rho[j]);
-            } else if (!entropy) {
+            } else if (!entropy && !pe) {
                 double psum = P[i] + P[j];
                 double alpha_c_ij =
                     psum > 0.0 ? (P[i] * alpha_c[i] + P[j] * alpha_c[j]) / psum : 0.0;
