@@ -115,13 +115,22 @@ typedef struct sphx_params {
      * (the Phantom-like flavour of Appendix A: density-energy with alpha_c = 1
      * for every particle, conduction speed sqrt(2 |P_i - P_j| / (rho_i +
      * rho_j)), and the viscosity switch of sphx_alpha_v_update decaying with
-     * length 0.25 instead of 0.05). */
+     * length 0.25 instead of 0.05) or SPHX_FLAVOUR_PRESSURE_ENERGY
+     * (pressure-smoothed SPH of Appendix A: the density loop also forms the
+     * smoothed pressure P_hat = (gamma - 1) sum_j m_j u_j W_ij; the ghost
+     * returns P = P_hat, c = sqrt(gamma P_hat / rho) and, in
+     * sphx_ghost_out.A, the grad-h term F_i of the factors f_ij = 1 - F_i /
+     * (m_j u_j); the force pass uses the pressure-energy equation of motion
+     * with the density flavours' viscosity and no conduction. Every u must be
+     * positive. Runs the plain cell-pair density loop only: sphx_ctx_create
+     * refuses it with density_balance != 0 or neighbour_lists != 0). */
     int32_t flavour;
 } sphx_params;
 
 #define SPHX_FLAVOUR_DENSITY_ENERGY 0
 #define SPHX_FLAVOUR_DENSITY_ENTROPY 1
 #define SPHX_FLAVOUR_PHANTOM 2
+#define SPHX_FLAVOUR_PRESSURE_ENERGY 3
 
 #define SPHX_KERNEL_WENDLAND_C2 0
 #define SPHX_KERNEL_WENDLAND_C4 1
@@ -145,11 +154,15 @@ typedef struct sphx_particles {
 
 /* Density-pass outputs (caller order, FP32 unless noted). Sums include the
  * self term; nngb excludes it. div_sum/curl_* are the raw sums
- * sum_j m_j (v_j - v_i).grad_i W_ij and sum_j m_j grad_i W_ij x (v_j - v_i). */
+ * sum_j m_j (v_j - v_i).grad_i W_ij and sum_j m_j grad_i W_ij x (v_j - v_i).
+ * P_hat, P_hat_dh: with SPHX_FLAVOUR_PRESSURE_ENERGY, the smoothed pressure
+ * (gamma - 1) sum_j m_j u_j W_ij and its h-derivative (Appendix A); NULL:
+ * not written (always ignored by the other flavours). */
 typedef struct sphx_density_out {
     float *rho, *rho_dh, *n, *n_dh;
     float *div_sum, *curl_x, *curl_y, *curl_z;
     int32_t *nngb;
+    float *P_hat, *P_hat_dh;
 } sphx_density_out;
 
 /* Ghost outputs (caller order). converged: 1 once h has converged. */
@@ -280,7 +293,9 @@ sphx_status sphx_ghost(sphx_ctx *ctx, sphx_grid *grid, const sphx_tasks *tasks,
 
 /* Force pass (Sections 3.2-3.3) for every active particle, over all j != i
  * with r_ij < max(H_i, H_j). Reads the ghost state (rho from *dens; f, P, c,
- * balsara from *gst) of every particle, including inactive ones. If
+ * balsara from *gst, and A with SPHX_FLAVOUR_PRESSURE_ENERGY, where P is the
+ * smoothed pressure and A the grad-h term F) of every particle, including
+ * inactive ones. If
  * d_sums6 != NULL it receives, in FP64, sum m a (3), sum m (v.a + du/dt),
  * sum m |a|, sum m |du/dt| over the active particles. Asynchronous. */
 sphx_status sphx_force(sphx_ctx *ctx, const sphx_grid *grid, const sphx_tasks *tasks,

@@ -27,6 +27,9 @@ __device__ unsigned long long probe_counts[3];
 namespace {
 
 constexpr int kSums = 9;  // Sw, Smw, Sud, Smud, Sdiv, Scx, Scy, Scz, count
+// The pressure-energy flavour (Appendix A) adds Smuw = sum m u w and Smuud =
+// sum m u u^2 phi for its smoothed pressure and that pressure's h-derivative.
+constexpr int kSumsPE = kSums + 2;
 
 // Where a receiver's results go: the caller's arrays (caller order) and the
 // sorted-order state the ghost reads.
@@ -34,6 +37,11 @@ struct DensOut {
     float *rho, *rho_dh, *n, *n_dh, *div, *cx, *cy, *cz;
     int32_t *nngb;
     float4 *d0, *d1;
+    // pressure-energy only: the smoothed pressure and its h-derivative (caller
+    // order, may be null), the sorted pair the ghost reads, and gamma - 1
+    float *p_hat, *p_hat_dh;
+    float2 *d2;
+    float gm1;
 };
 
 // Contributions of one directed pair; p and v are the source's position (in
@@ -45,8 +53,8 @@ struct DensOut {
 // point to a dummy source beyond every support (mass 0, velocity 0), which
 // adds exactly zero. Either way the loops evaluate several list entries at
 // once without branching.
-template <bool MASK, int K>
-__device__ __forceinline__ void dens_pair(float (&S)[kSums], const float4 &pi, const float4 &vi,
+template <bool MASK, int K, int NS>
+__device__ __forceinline__ void dens_pair(float (&S)[NS], const float4 &pi, const float4 &vi,
                                           float invH, const float4 &p, const float4 &v, bool on)
 {
     const float dx = pi.x - p.x, dy = pi.y - p.y, dz = pi.z - p.z;
@@ -67,13 +75,18 @@ __device__ __forceinline__ void dens_pair(float (&S)[kSums], const float4 &pi, c
     S[5] += mt3 * (dy * dvz - dz * dvy);
     S[6] += mt3 * (dz * dvx - dx * dvz);
     S[7] += mt3 * (dx * dvy - dy * dvx);
+    if constexpr (NS == kSumsPE) {
+        const float mu = p.w * v.w;  // m_j u_j (the dummy source has m = 0)
+        S[9] += mu * wk;
+        S[10] += mu * ud;
+    }
 }
 
 // A receiver's results from its sums. Its own particle went through the loop
 // as a pair at r = 0: it contributes W(0) to n and rho and nothing to the
 // gradient sums; it is not a neighbour.
-template <int K>
-__device__ __forceinline__ void dens_finish(const float (&S)[kSums], float hi, float invH,
+template <int K, int NS>
+__device__ __forceinline__ void dens_finish(const float (&S)[NS], float hi, float invH,
                                             int64_t s, int32_t gi, const DensOut &o)
 {
     constexpr float kW = Kern<K>::kW, kD = Kern<K>::kD;
@@ -108,12 +121,23 @@ __device__ __forceinline__ void dens_finish(const float (&S)[kSums], float hi, f
     o.cy[gi] = cy;
     o.cz[gi] = cz;
     o.nngb[gi] = int32_t(S[8]) - 1;
+    if constexpr (NS == kSumsPE) {
+        // sum m u W, and the numerator of the grad-h term F of the factors
+        // f_ij = 1 - F_i / (m_j u_j): F = h P_hat' / ((gamma - 1) 3 n) /
+        // (1 + h n'/(3 n)) = (kD Smuud - 3 kW Smuw) / (kW Sw) / G'
+        const float Smuw = S[9], Smuud = S[10];
+        o.d2[s] = make_float2(kW * invH3 * Smuw, (kD * Smuud - 3.0f * kW * Smuw) / (kW * Sw));
+        if (o.p_hat) {
+            o.p_hat[gi] = o.gm1 * kW * invH3 * Smuw;
+            o.p_hat_dh[gi] = -o.gm1 * invH3 * ih * (3.0f * kW * Smuw - kD * Smuud);
+        }
+    }
 }
 
 // BAL: compute rounds cut the lanes' lists into chunks of one receiver each
 // and spread them over the lanes (compute_bal) instead of each lane walking
 // its own list.
-template <int CAP, int NW, bool BAL, int K>
+template <int CAP, int NW, bool BAL, int K, bool PE>
 __global__ __launch_bounds__(64 * NW) void k_density(
     int64_t n_leaves, int64_t nb_padded, const int32_t *__restrict__ order,
     const int32_t *__restrict__ leaf_start,
@@ -127,6 +151,7 @@ __global__ __launch_bounds__(64 * NW) void k_density(
     if (skip && *skip)
         return;  // a captured pass with nothing left to do
     static_assert(CAP >= 64 && CAP <= 256, "candidate slots: one task's sources, 8-bit slots");
+    constexpr int NS = PE ? kSumsPE : kSums;
     const int64_t L = leaf_of_block(blockIdx.x, nb_padded, order);
     if (L >= n_leaves)
         return;
@@ -152,7 +177,7 @@ __global__ __launch_bounds__(64 * NW) void k_density(
     __shared__ float4 rp_all[NW][BAL ? 64 : 1];
     __shared__ float4 rv_all[NW][BAL ? 64 : 1];
     __shared__ int32_t cb_all[NW][BAL ? 68 : 1];
-    __shared__ float pt_all[NW][BAL ? kSums * 64 : 1];
+    __shared__ float pt_all[NW][BAL ? NS * 64 : 1];
     float4 *cp = cp_all[w];
     float4 *cv = cv_all[w];
     uint8_t *lst = reinterpret_cast<uint8_t *>(lst_all[w]);
@@ -221,7 +246,7 @@ __global__ __launch_bounds__(64 * NW) void k_density(
     const int32_t sr = s0 + src;
     const int32_t gr = nrep > 1 ? __shfl(gi, src, 64) : gi;
 
-    float S[kSums] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    float S[NS] = {};
     int gbase = 0;  // candidates of the earlier buffers (wave-uniform)
     int nc = 0;   // buffered candidates (wave-uniform)
     int myn = 0;  // this lane's list length (its own particle is listed too)
@@ -307,7 +332,7 @@ __global__ __launch_bounds__(64 * NW) void k_density(
             const int len = id < T ? min(C, mr - k0) : 0;
             const float4 P = rp[r], V = rv[r];
             const uint8_t *rl = lst + r * kListStride + (id < T ? k0 : 0);
-            float Tc[kSums] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+            float Tc[NS] = {};
             for (int k = 0; __any(k < len); k += 4) {
                 const uint32_t four = k < len ? *reinterpret_cast<const uint32_t *>(rl + k) : 0u;
                 float4 p[4], v[4];
@@ -324,13 +349,13 @@ __global__ __launch_bounds__(64 * NW) void k_density(
                     dens_pair<true, K>(Tc, P, V, V.w, p[q], v[q], on[q]);
             }
 #pragma unroll
-            for (int k = 0; k < kSums; ++k)
+            for (int k = 0; k < NS; ++k)
                 pt[k * 64 + lane] = Tc[k];
             wave_sync();
             const int c0 = max(incl - nch, j0), c1 = min(incl, j0 + 64);
             for (int c = c0; c < c1; ++c)
 #pragma unroll
-                for (int k = 0; k < kSums; ++k)
+                for (int k = 0; k < NS; ++k)
                     S[k] += pt[k * 64 + (c - j0)];
             wave_sync();
         }
@@ -470,7 +495,7 @@ __global__ __launch_bounds__(64 * NW) void k_density(
     // the same total (each addition is commutative)
     for (int o = 1; o < nrep; o <<= 1)
 #pragma unroll
-        for (int k = 0; k < kSums; ++k)
+        for (int k = 0; k < NS; ++k)
             S[k] += __shfl_xor(S[k], o, 64);
     if (SPHX_PROBE) {
         unsigned long long v[3] = {probe_slots, probe_tests, probe_hits};
@@ -487,16 +512,16 @@ __global__ __launch_bounds__(64 * NW) void k_density(
         __syncthreads();
         // the other waves' partial sums (own array: small tiles leave too
         // little room in the candidate buffers)
-        __shared__ float red[NW > 1 ? (NW - 1) * kSums * 64 : 1];
+        __shared__ float red[NW > 1 ? (NW - 1) * NS * 64 : 1];
         if (w > 0)
-            for (int k = 0; k < kSums; ++k)
-                red[((w - 1) * kSums + k) * 64 + lane] = S[k];
+            for (int k = 0; k < NS; ++k)
+                red[((w - 1) * NS + k) * 64 + lane] = S[k];
         __syncthreads();
         if (w > 0)
             return;
         for (int w2 = 1; w2 < NW; ++w2)
-            for (int k = 0; k < kSums; ++k)
-                S[k] += red[((w2 - 1) * kSums + k) * 64 + lane];
+            for (int k = 0; k < NS; ++k)
+                S[k] += red[((w2 - 1) * NS + k) * 64 + lane];
     }
     if (!ract || rj != 0)
         return;
@@ -850,10 +875,11 @@ __global__ __launch_bounds__(256) void k_dens_list(
 
 }  // namespace
 
-static DensOut dens_out(const sphx_grid *g, const sphx_density_out *o)
+static DensOut dens_out(const sphx_ctx *ctx, const sphx_grid *g, const sphx_density_out *o)
 {
-    return DensOut{o->rho,    o->rho_dh, o->n,      o->n_dh,  o->div_sum, o->curl_x,
-                   o->curl_y, o->curl_z, o->nngb,   g->d0,    g->d1};
+    return DensOut{o->rho,    o->rho_dh, o->n,      o->n_dh,     o->div_sum, o->curl_x,
+                   o->curl_y, o->curl_z, o->nngb,   g->d0,       g->d1,      o->P_hat,
+                   o->P_hat_dh, g->d2,   float(ctx->p.gamma_gas - 1.0)};
 }
 
 // Receivers whose H exceeds their leaf's task radius (the density loop's own
@@ -896,14 +922,40 @@ sphx_status stale_count_launch(const sphx_ctx *ctx, const sphx_grid *g, const sp
     return SPHX_OK;
 }
 
-// The loop shapes of one kernel kind.
-template <int K>
+// The loop shapes of one kernel kind. PE (the pressure-energy flavour's two
+// extra sums) is built for the plain cell-pair loop only: the balanced,
+// grouped and list loops are refused for that flavour when the context is
+// made.
+template <int K, bool PE>
 static void density_shapes(int tile, int waves, bool bal, bool grouped, int64_t nbp,
                            const sphx_ctx *ctx,
                            const sphx_grid *g, const sphx_tasks *t, const float *lr,
                            const DensOut &dout, float far, int32_t *counters,
                            const int32_t *skip, hipStream_t s)
 {
+#define SPHX_DENSITY_LAUNCH(CAP_, NW_, BAL_)                                                   \
+    k_density<CAP_, NW_, BAL_, K, PE><<<unsigned(nbp), 64 * NW_, 0, s>>>(                         \
+        g->n_leaves, nbp, t->order, g->leaf_start, g->perm, g->q0, g->q1, g->need, g->hs,      \
+        t->radius, t->off, t->task, g->leaf_ext, float(ctx->p.gamma_k), far, lr, dout,        \
+        counters, skip)
+    if constexpr (PE) {
+        if (waves == 1) {
+            if (tile == 64)
+                SPHX_DENSITY_LAUNCH(64, 1, false);
+            else if (tile == 128)
+                SPHX_DENSITY_LAUNCH(128, 1, false);
+            else
+                SPHX_DENSITY_LAUNCH(256, 1, false);
+        } else {
+            if (tile == 64)
+                SPHX_DENSITY_LAUNCH(64, 2, false);
+            else if (tile == 128)
+                SPHX_DENSITY_LAUNCH(128, 2, false);
+            else
+                SPHX_DENSITY_LAUNCH(256, 2, false);
+        }
+        return;
+    }
     if (grouped && !lr) {
 #define SPHX_DENSITY_GRP(CAP_)                                                                 \
     k_density_grp<CAP_, K><<<unsigned(nbp), 64, 0, s>>>(                                      \
@@ -919,11 +971,6 @@ static void density_shapes(int tile, int waves, bool bal, bool grouped, int64_t 
 #undef SPHX_DENSITY_GRP
         return;
     }
-#define SPHX_DENSITY_LAUNCH(CAP_, NW_, BAL_)                                                   \
-    k_density<CAP_, NW_, BAL_, K><<<unsigned(nbp), 64 * NW_, 0, s>>>(                             \
-        g->n_leaves, nbp, t->order, g->leaf_start, g->perm, g->q0, g->q1, g->need, g->hs,      \
-        t->radius, t->off, t->task, g->leaf_ext, float(ctx->p.gamma_k), far, lr, dout,        \
-        counters, skip)
     if (bal) {
         if (tile == 64)
             SPHX_DENSITY_LAUNCH(64, 1, true);
@@ -961,14 +1008,20 @@ sphx_status density_launch(const sphx_ctx *ctx, const sphx_grid *g, const sphx_t
     const bool bal = ctx->p.density_balance == 1;
     const bool grouped = ctx->p.density_balance == 2;
     const float *lr = use_lists ? g->lrad : nullptr;
-    const DensOut dout = dens_out(g, o);
+    const DensOut dout = dens_out(ctx, g, o);
     // the dummy source: 4 box lengths out, more than 3 box lengths from any
     // receiver (cell-relative coordinates), while every H is below a third
     const float far = float(4.0 * std::max(ctx->p.box[0], std::max(ctx->p.box[1], ctx->p.box[2])));
     SPHX_HIP(ctx->prof->begin(0, s));
-    SPHX_WITH_KERNEL(ctx->p.kernel, density_shapes<KK>(tile, waves, bal, grouped, nbp, ctx, g, t,
-                                                       lr, dout,
-                                                       far, counters, skip, s));
+    if (ctx->p.flavour == SPHX_FLAVOUR_PRESSURE_ENERGY) {
+        SPHX_WITH_KERNEL(ctx->p.kernel, (density_shapes<KK, true>(tile, waves, bal, grouped, nbp,
+                                                                  ctx, g, t, lr, dout, far,
+                                                                  counters, skip, s)));
+    } else {
+        SPHX_WITH_KERNEL(ctx->p.kernel, (density_shapes<KK, false>(tile, waves, bal, grouped, nbp,
+                                                                   ctx, g, t, lr, dout, far,
+                                                                   counters, skip, s)));
+    }
     SPHX_HIP(hipGetLastError());
     SPHX_HIP(ctx->prof->end(0, s));
     return SPHX_OK;
@@ -986,7 +1039,7 @@ sphx_status density_list_launch(const sphx_ctx *ctx, const sphx_grid *g, const s
                      (k_dens_list<KK><<<unsigned(nwgp), 256, 0, s>>>(
                          g->n, nwgp, g->need, g->hs, g->lrad, g->leaf_of, g->perm, t->off,
                          t->task, g->q0, g->q1, g->lcnt, g->lboff, g->lst,
-                         float(ctx->p.gamma_k), dens_out(g, o))));
+                         float(ctx->p.gamma_k), dens_out(ctx, g, o))));
     SPHX_HIP(hipGetLastError());
     SPHX_HIP(ctx->prof->end(2, s));
     return SPHX_OK;

@@ -12,16 +12,17 @@ namespace sphx {
 namespace {
 
 
-// Sorted copies of the ghost state every source needs: (h, rho, P, c) and
-// (f, B, A, 0).
 // Source state of the force pass in sorted order, gathered from the caller's
-// arrays; with skip_active, only for the inactive particles (a step's ghost
-// has written the active ones).
+// arrays: (h, rho, P, c) and (f, B, A, 0), with the pressure-energy flavour
+// (gm1sq = (gamma - 1)^2 > 0) (f, B, F, (gamma - 1)^2 u / P_hat); with
+// skip_active, only for the inactive particles (a step's ghost has written
+// the active ones).
 __global__ void k_force_state(int64_t n, const int32_t *__restrict__ perm,
                               const float *__restrict__ h, const float *__restrict__ rho,
                               const float *__restrict__ P, const float *__restrict__ c,
                               const float *__restrict__ f, const float *__restrict__ B,
-                              const float *__restrict__ A, const uint8_t *__restrict__ skip_active,
+                              const float *__restrict__ A, const float *__restrict__ u,
+                              float gm1sq, const uint8_t *__restrict__ skip_active,
                               float4 *__restrict__ g0, float4 *__restrict__ g1)
 {
     const int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -31,7 +32,7 @@ __global__ void k_force_state(int64_t n, const int32_t *__restrict__ perm,
     if (skip_active && skip_active[i])
         return;
     g0[s] = make_float4(h[i], rho[i], P[i], c[i]);
-    g1[s] = make_float4(f[i], B[i], A[i], 0.0f);
+    g1[s] = make_float4(f[i], B[i], A[i], gm1sq > 0.0f ? gm1sq * u[i] / P[i] : 0.0f);
 }
 
 __device__ __forceinline__ double wave_sum(double v)
@@ -59,7 +60,12 @@ struct StepOut {
 // ghost), no conduction, and the output rate is dA/dt = (gamma - 1)
 // rho^(1 - gamma) du/dt|visc, the FP64 energy sum keeping the internal-energy
 // rate; 2 the Phantom-like flavour of Appendix A: conduction with alpha_c = 1
-// and the speed sqrt(2 |P_i - P_j| / (rho_i + rho_j))).
+// and the speed sqrt(2 |P_i - P_j| / (rho_i + rho_j)); 3 pressure-energy,
+// Appendix A: P is the smoothed pressure and the pressure terms are
+// m_j (gamma - 1)^2 u_i u_j (f_ij g_i / P_i + f_ji g_j / P_j) with f_ij = 1 -
+// F_i / (m_j u_j), no conduction; per particle the state holds F and Q =
+// (gamma - 1)^2 u / P, so that with R = Q F the pair needs only
+// g_i (Q_i m_j u_j - R_i) + g_j (Q_j m_j u_i - R_j m_j / m_i)).
 template <int CAP, int NW, int K, int FLAV>
 __global__ __launch_bounds__(64 * NW) void k_force(
     int64_t n_leaves, int64_t nb_padded, const int32_t *__restrict__ order,
@@ -161,6 +167,9 @@ __global__ __launch_bounds__(64 * NW) void k_force(
     const float invHi4 = (invHi * invHi) * (invHi * invHi);
     const float rhoi = gi0.y, Pi = gi0.z, ci = gi0.w;
     const float fi = gi1.x, Bi = gi1.y, Ai = gi1.z;
+    // pressure-energy: the receiver's Q, R = Q F, u and 1/m (else unused)
+    const float Qi = gi1.w, Ri = gi1.w * gi1.z, ui_ = vi.w;
+    const float inv_mi = FLAV == 3 ? fast_rcp(pi.w) : 0.0f;
     const float acPi = ai.y * Pi;
 
     float ax = 0.f, ay = 0.f, az = 0.f, du = 0.f, duv = 0.f;
@@ -206,25 +215,30 @@ __global__ __launch_bounds__(64 * NW) void k_force(
         // a pair) is zero, also when f is infinite (a particle alone in its
         // support at a fixed h)
         const bool in_i = on && ui < 1.0f, in_j = on && uj < 1.0f;
-        const float fgi = in_i ? fi * gi : 0.0f, Agi = in_i ? Ai * gi : 0.0f;
-        const float fgj = in_j ? b.x * gj : 0.0f, Agj = in_j ? b.y * gj : 0.0f;
+        const float fgi = in_i ? fi * gi : 0.0f, fgj = in_j ? b.x * gj : 0.0f;
         const float G = fgi + fgj;
-        const float acc = Agi + Agj + 0.5f * nu * G;
         const float m = v.w;
+        // the pressure terms of i and j (pressure-energy: already times m_j,
+        // with the source's b.y = m_j Q_j, c2.x = m_j R_j, c2.y = m_j u_j)
+        const float Agi = in_i ? (FLAV == 3 ? gi * (Qi * c2.y - Ri) : Ai * gi) : 0.0f;
+        const float Agj = in_j ? (FLAV == 3 ? gj * (b.y * ui_ - c2.x * inv_mi) : b.y * gj) : 0.0f;
+        const float macc =
+            FLAV == 3 ? Agi + Agj + m * (0.5f * nu * G) : m * (Agi + Agj + 0.5f * nu * G);
         const float psum = Pi + a.w;
         const float ac =
             FLAV == 2 ? 1.0f : (psum > 0.0f ? (acPi + c2.x) * fast_rcp(psum) : 0.0f);
         const float vc =
             (FLAV == 2 ? 0.0f : fabsf(vdote)) + fast_sqrt(2.0f * fabsf(Pi - a.w) * irs);
         const float dvi = m * (0.25f * nu * G) * vdote;
-        const float dui = FLAV == 1 ? m * Agi * vdote + dvi
-                                    : m * (Agi + 0.25f * nu * G) * vdote +
-                                          m * ac * vc * (vi.w - c2.y) * G * irs;
+        const float dui = FLAV == 3   ? Agi * vdote + dvi
+                          : FLAV == 1 ? m * Agi * vdote + dvi
+                                      : m * (Agi + 0.25f * nu * G) * vdote +
+                                            m * ac * vc * (vi.w - c2.y) * G * irs;
         if (FLAV == 1)
             duv += dvi;
-        ax -= m * acc * ex;
-        ay -= m * acc * ey;
-        az -= m * acc * ez;
+        ax -= macc * ex;
+        ay -= macc * ey;
+        az -= macc * ez;
         du += dui;
     };
     // Every listed entry is a force neighbour (the receiver's own particle
@@ -310,8 +324,14 @@ __global__ __launch_bounds__(64 * NW) void k_force(
             cp[pos] = make_float4(p.x, p.y, p.z, Hj * Hj);
             cv[pos] = make_float4(v.x, v.y, v.z, p.w);
             ca[pos] = make_float4(fast_rcp(Hj), h0.w, h0.y, h0.z);
-            cb[pos] = make_float4(h1.x, h1.z, h1.y, a.x);
-            cc[pos] = make_float2(a.y * h0.z, v.w);
+            if (FLAV == 3) {
+                // m_j Q_j, m_j R_j = m_j Q_j F_j, m_j u_j
+                cb[pos] = make_float4(h1.x, p.w * h1.w, h1.y, a.x);
+                cc[pos] = make_float2(p.w * h1.w * h1.z, p.w * v.w);
+            } else {
+                cb[pos] = make_float4(h1.x, h1.z, h1.y, a.x);
+                cc[pos] = make_float2(a.y * h0.z, v.w);
+            }
         }
         nc += tot;
     };
@@ -617,7 +637,10 @@ sphx_status force_launch(const sphx_ctx *ctx, const sphx_grid *g, const sphx_tas
     Profiler *prof = fsum_fixed ? nullptr : ctx->prof;
     if (!state_ready || in->active) {
         k_force_state<<<unsigned((g->n + 255) / 256), 256, 0, s>>>(
-            g->n, g->perm, in->h, d->rho, gs->P, gs->c, gs->f, gs->balsara, gs->A,
+            g->n, g->perm, in->h, d->rho, gs->P, gs->c, gs->f, gs->balsara, gs->A, in->u,
+            ctx->p.flavour == SPHX_FLAVOUR_PRESSURE_ENERGY
+                ? float((ctx->p.gamma_gas - 1.0) * (ctx->p.gamma_gas - 1.0))
+                : 0.0f,
             state_ready ? in->active : nullptr, g->g0, g->g1);
         SPHX_HIP(hipGetLastError());
     }
@@ -642,6 +665,9 @@ sphx_status force_launch(const sphx_ctx *ctx, const sphx_grid *g, const sphx_tas
                                                               far, gate, so, fsum, s)));
     } else if (ctx->p.flavour == SPHX_FLAVOUR_PHANTOM) {
         SPHX_WITH_KERNEL(ctx->p.kernel, (force_shapes<KK, 2>(tile, waves, nbp, ctx, g, t, in, o,
+                                                              far, gate, so, fsum, s)));
+    } else if (ctx->p.flavour == SPHX_FLAVOUR_PRESSURE_ENERGY) {
+        SPHX_WITH_KERNEL(ctx->p.kernel, (force_shapes<KK, 3>(tile, waves, nbp, ctx, g, t, in, o,
                                                               far, gate, so, fsum, s)));
     } else {
         SPHX_WITH_KERNEL(ctx->p.kernel, (force_shapes<KK, 0>(tile, waves, nbp, ctx, g, t, in, o,

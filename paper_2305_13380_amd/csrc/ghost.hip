@@ -1,7 +1,8 @@
 // Ghost (Section 3.1 Newton-Raphson on the partition condition, equation of
-// state; Section 3.2 f-factor and Balsara switch). Particles needing a pass,
-// in sorted order (the density kernel leaves its sums in sorted order too),
-// over a grid-stride loop; everything in FP32. The iteration's counters are
+// state; Section 3.2 f-factor and Balsara switch; Appendix A smoothed
+// pressure and grad-h term of the pressure-energy flavour). Particles needing
+// a pass, in sorted order (the density kernel leaves its sums in sorted order
+// too), over a grid-stride loop; everything in FP32. The iteration's counters are
 // reduced per block and added with one atomic per block and counter (atomics
 // from every wave on the same few words serialise in L2).
 #include <algorithm>
@@ -22,7 +23,8 @@ __global__ __launch_bounds__(kGhostThreads) void k_ghost(int64_t n, const int32_
                         const float *__restrict__ lrad,
                         const float4 *__restrict__ d0, const float4 *__restrict__ d1, float inv_eta3,
                         float h_tol, float h_max, float gamma_k, float gamma_gas, float eps_b,
-                        int final_pass, int step_mode, int entropy, float4 *__restrict__ g0,
+                        int final_pass, int step_mode, int flavour,
+                        const float2 *__restrict__ d2, float4 *__restrict__ g0,
                         float4 *__restrict__ g1, float4 *__restrict__ g2, const int32_t *__restrict__ nngb,
                         unsigned long long *__restrict__ units, float *__restrict__ o_f,
                         float *__restrict__ o_P,
@@ -96,24 +98,33 @@ __global__ __launch_bounds__(kGhostThreads) void k_ghost(int64_t n, const int32_
             const float rho = a.z;
             const float u = q1[s].w;
             // density-energy: u is the internal energy; density-entropy: the
-            // particle carries the adiabat A, and P = A rho^gamma
-            const float P = entropy ? u * powf(rho, gamma_gas) : (gamma_gas - 1.0f) * u * rho;
-            const float c = entropy ? sqrtf(gamma_gas * P / rho)
-                                    : sqrtf(gamma_gas * (gamma_gas - 1.0f) * u);
+            // particle carries the adiabat A, and P = A rho^gamma;
+            // pressure-energy: the smoothed pressure (gamma - 1) sum m u W
+            const bool entropy = flavour == SPHX_FLAVOUR_DENSITY_ENTROPY;
+            const bool pe = flavour == SPHX_FLAVOUR_PRESSURE_ENERGY;
+            const float2 sp = pe ? d2[s] : make_float2(0.0f, 0.0f);  // sum m u W, F G'
+            const float P = pe ? (gamma_gas - 1.0f) * sp.x
+                               : (entropy ? u * powf(rho, gamma_gas)
+                                          : (gamma_gas - 1.0f) * u * rho);
+            const float c = (entropy || pe) ? sqrtf(gamma_gas * P / rho)
+                                            : sqrtf(gamma_gas * (gamma_gas - 1.0f) * u);
             const float f = 1.0f / a.w;
             const float irho = 1.0f / rho;
             const float div = b.x * irho;
             const float curl = sqrtf(b.y * b.y + b.z * b.z + b.w * b.w) * irho;
             const float ad = fabsf(div);
             const float B = ad / (ad + curl + eps_b * c / hh);
-            const float A = f * P * irho * irho;
+            // pressure-energy: A is the grad-h term F of f_ij = 1 - F_i / (m_j
+            // u_j), and the force state's fourth slot (gamma - 1)^2 u / P_hat
+            const float A = pe ? sp.y / a.y : f * P * irho * irho;
+            const float Q = pe ? (gamma_gas - 1.0f) * (gamma_gas - 1.0f) * u / P : 0.0f;
             if (step_mode) {
                 // Sorted state only: the force pass's source state (the same
                 // values its gather would read from the outputs) and the
                 // rest; the force kernel, which every finalised particle of a
                 // step receives in, writes the caller's h and outputs.
                 g0[s] = make_float4(hh, rho, P, c);
-                g1[s] = make_float4(f, B, A, 0.0f);
+                g1[s] = make_float4(f, B, A, Q);
                 g2[s] = make_float4(div, curl, conv ? 1.0f : 0.0f, 0.0f);
             } else {
                 o_conv[i] = conv ? 1 : 0;
@@ -178,7 +189,7 @@ sphx_status ghost_launch(const sphx_ctx *ctx, sphx_grid *g, const sphx_tasks *t,
         use_lists ? g->lrad : nullptr, g->d0, g->d1, inv_eta3,
         float(P.h_tol),
         float(ctx->h_max), float(P.gamma_k), float(P.gamma_gas), float(P.eps_balsara),
-        final_pass, step_mode ? 1 : 0, P.flavour == SPHX_FLAVOUR_DENSITY_ENTROPY ? 1 : 0, g->g0,
+        final_pass, step_mode ? 1 : 0, P.flavour, g->d2, g->g0,
         g->g1, g->g2, d->nngb, units, o->f, o->P, o->c,
         o->balsara, o->A, o->div_v, o->curl_v, o->converged, counters, skip);
     SPHX_HIP(hipGetLastError());

@@ -349,8 +349,9 @@ inline unsigned blocks(int64_t n, int t) { return unsigned((n + t - 1) / t); }
 
 size_t grid_bytes(int64_t n)
 {
-    // per particle: keys x2, perm/idx, leaf_of, flags x2, q0, q1, qa, need, g0, g1, g2
-    size_t per = 8 * 2 + 4 * 2 + 4 + 4 * 2 + 16 * 2 + 8 + 1 + 16 * 3 + 4 + 32 + 8;
+    // per particle: keys x2, perm/idx, leaf_of, flags x2, q0, q1, qa, need, g0, g1, g2,
+    // hs, d0 + d1, hlo + hhi, d2 (pressure-energy)
+    size_t per = 8 * 2 + 4 * 2 + 4 + 4 * 2 + 16 * 2 + 8 + 1 + 16 * 3 + 4 + 32 + 8 + 8;
     // per leaf (at most n leaves): start, origin, tree nodes (~8/7 of the
     // leaves: lo, hi, radius), partial sums
     size_t per_leaf = 4 + 24 + 16 + 4 + (48 + 4) * 8 / 7 + 1 + 48;
@@ -366,7 +367,7 @@ void grid_free(sphx_grid *g)
                     g->need,    g->g0,       g->g1,       g->g2,       g->leaf_start, g->leaf_org,
                     g->node_lo,
                     g->node_hi, g->node_r,   g->fsum,     g->sort_tmp, g->keys_in, g->idx_in,
-                    g->flags,   g->d_status, g->hs,       g->d0,       g->d1,
+                    g->flags,   g->d_status, g->hs,       g->d0,       g->d1,     g->d2,
                     g->lrad,    g->lcnt,     g->lcap,     g->lboff,    g->lst,    g->lscan_tmp,
                     g->leaf_ext, g->leaf_hmax, g->hlo, g->hhi};
     for (void *p : ptrs)
@@ -433,6 +434,8 @@ sphx_status grid_build(sphx_ctx *ctx, const sphx_particles *in, hipStream_t s, s
     SPHX_TRY(dalloc(&g->hhi, n, s));
     SPHX_TRY(dalloc(&g->d0, n, s));
     SPHX_TRY(dalloc(&g->d1, n, s));
+    if (P.flavour == SPHX_FLAVOUR_PRESSURE_ENERGY)
+        SPHX_TRY(dalloc(&g->d2, n, s));
 
     if (n == 0) {
         g->n_leaves = 0;

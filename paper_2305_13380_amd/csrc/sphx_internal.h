@@ -127,8 +127,11 @@ struct sphx_grid {
                         // (largest h with G < 0, smallest with G > 0), reset by iter_reset
     float4 *d0;         // density results in sorted order: n, 3 + h n'/n, rho, 1 + h rho'/(3 rho)
     float4 *d1;         // div_sum, curl_x, curl_y, curl_z
+    float2 *d2;         // pressure-energy flavour only (else null): sum m u W and
+                        // the grad-h term times 3 + h n'/n
     float4 *g0;         // force-pass state: h, rho, P, c
-    float4 *g1;         // force-pass state: f, balsara, A, 0
+    float4 *g1;         // force-pass state: f, balsara, A, 0 (pressure-energy:
+                        // f, balsara, F, (gamma - 1)^2 u / P_hat)
     float4 *g2;         // inside a step, the rest of the ghost's outputs: div, curl, converged
 
     // per leaf

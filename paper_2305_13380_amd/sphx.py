@@ -52,7 +52,8 @@ class Particles(C.Structure):
 
 class DensityOut(C.Structure):
     _fields_ = [(k, C.c_void_p) for k in (
-        "rho", "rho_dh", "n", "n_dh", "div_sum", "curl_x", "curl_y", "curl_z", "nngb")]
+        "rho", "rho_dh", "n", "n_dh", "div_sum", "curl_x", "curl_y", "curl_z", "nngb",
+        "P_hat", "P_hat_dh")]
 
 
 class GhostOut(C.Structure):
@@ -171,13 +172,14 @@ def _check(status):
     return status
 
 
-FLAVOURS = {"energy": 0, "entropy": 1, "phantom": 2}  # SPHX_FLAVOUR_*
+FLAVOURS = {"energy": 0, "entropy": 1, "phantom": 2,  # SPHX_FLAVOUR_*
+            "pressure_energy": 3}
 
 
 def default_params(**kw) -> Params:
     """The library's defaults with fields overridden by keyword; kernel= takes
     a name of KERNELS (or its number) and sets the kernel's gamma_k too;
-    flavour= takes "energy", "entropy" or "phantom" (or the number)."""
+    flavour= takes a name of FLAVOURS (or the number)."""
     p = Params()
     lib.sphx_params_default(C.byref(p))
     if isinstance(kw.get("flavour"), str):
@@ -263,17 +265,19 @@ class DeviceParticles:
 
 
 DENS_F32 = ("rho", "rho_dh", "n", "n_dh", "div_sum", "curl_x", "curl_y", "curl_z")
+DENS_PE = ("P_hat", "P_hat_dh")  # the pressure-energy flavour's extra outputs
 GHOST_F32 = ("f", "P", "c", "balsara", "A", "div_v", "curl_v")
 FORCE_F32 = ("ax", "ay", "az", "du_dt", "v_sig")
 
 
 class Outputs:
-    """Caller-owned output arrays for the density, ghost and force passes."""
+    """Caller-owned output arrays for the density, ghost and force passes
+    (pressure=True: also the smoothed pressure and its h-derivative)."""
 
-    def __init__(self, n, device="cuda"):
+    def __init__(self, n, device="cuda", pressure=False):
         import torch
         f = lambda: torch.full((n,), float("nan"), dtype=torch.float32, device=device)
-        self.d = {k: f() for k in DENS_F32}
+        self.d = {k: f() for k in DENS_F32 + (DENS_PE if pressure else ())}
         self.d["nngb"] = torch.full((n,), -1, dtype=torch.int32, device=device)
         self.g = {k: f() for k in GHOST_F32}
         self.g["converged"] = torch.zeros((n,), dtype=torch.uint8, device=device)
@@ -284,8 +288,8 @@ class Outputs:
 
     def dens_view(self):
         o = DensityOut()
-        for k in DENS_F32 + ("nngb",):
-            setattr(o, k, _ptr(self.d[k]))
+        for k in DENS_F32 + ("nngb",) + DENS_PE:
+            setattr(o, k, _ptr(self.d.get(k)))
         return o
 
     def ghost_view(self):

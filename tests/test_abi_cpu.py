@@ -70,6 +70,17 @@ def test_ctx_create_rejects_invalid_params(sphx, field, value):
     assert not h.value
 
 
+@pytest.mark.parametrize("extra", [{"density_balance": 1}, {"density_balance": 2},
+                                   {"neighbour_lists": 1}, {"flavour": 4}])
+def test_ctx_create_rejects_loops_the_pressure_flavour_lacks(sphx, extra):
+    kw = {"flavour": "pressure_energy"}
+    kw.update(extra)
+    p = sphx.default_params(**kw)
+    h = C.c_void_p()
+    assert sphx.lib.sphx_ctx_create(C.byref(p), 0, C.byref(h)) == sphx.E_INVALID
+    assert sphx.last_error() and not h.value
+
+
 def test_workspace_bytes_grows_with_n(sphx):
     p = sphx.default_params()
     a = sphx.lib.sphx_workspace_bytes(C.byref(p), 1000)
