@@ -94,7 +94,7 @@ def lib():
         L.or_alpha_v_update.restype = None
         L.or_gradient.argtypes = ([C.c_int64] + [_dp] * 12 + [_dp, C.c_int, C.c_double, C.c_int,
                                   C.c_int64, _nullable(_ip), _nullable(_ip), _nullable(_ip)]
-                                  + [_dp] * 3)
+                                  + [_dp] * 3 + [_nullable(_dp)])
         L.or_gradient.restype = C.c_int64
         L.or_alpha_c_update.argtypes = ([C.c_int64] + [_dp] * 5 + [C.c_double] * 6 + [_dp])
         L.or_alpha_c_update.restype = None
@@ -157,11 +157,19 @@ class Params:
     # switch decays with ell = 0.25);
     # "pressure_energy": pressure-smoothed SPH of Appendix A (the smoothed
     # pressure P_hat from u, factors f_ij, density-flavour viscosity, no
-    # conduction; u > 0 everywhere)
+    # conduction; u > 0 everywhere);
+    # "anarchy_pu": Anarchy-PU of Appendix A (pressure-energy plus conduction
+    # with the mean alpha_c and speed c_i + c_j + mu; its conduction parameter
+    # evolves with beta_c = 0.01 and no shock limiter, its viscosity switch
+    # with ell = 0.25)
     flavour: str = "energy"
 
     def flavour_id(self) -> int:
-        return {"energy": 0, "entropy": 1, "phantom": 2, "pressure_energy": 3}[self.flavour]
+        return {"energy": 0, "entropy": 1, "phantom": 2, "pressure_energy": 3,
+                "anarchy_pu": 4}[self.flavour]
+
+    def smoothed_pressure(self) -> bool:
+        return self.flavour in ("pressure_energy", "anarchy_pu")
 
     def hmax(self) -> float:
         if self.h_max is not None:
@@ -346,7 +354,7 @@ def density(ps, h, params: Params, recv=None, mode="auto"):
                              out["div_sum"], out["curl_x"], out["curl_y"], out["curl_z"], nngb)
     out["nngb"] = nngb
     out["total"] = int(total)
-    if params.flavour == "pressure_energy":
+    if params.smoothed_pressure():
         out["P_hat"], out["P_hat_dh"] = np.zeros(nrecv), np.zeros(nrecv)
         lib().or_pressure(ps.n, x, y, z, _f64(ps.m), _f64(ps.u), h, _f64(ps.box),
                           int(params.periodic), float(params.gamma_k), params.kernel_id(),
@@ -393,9 +401,8 @@ def ghost(dens, u, h, params: Params):
     (pressure-energy: P = P_hat and A the grad-h term F of its f_ij)."""
     n = dens["rho"].shape[0]
     out = {k: np.zeros(n) for k in ("f", "P", "c", "balsara", "A", "div_v", "curl_v")}
-    pe = params.flavour == "pressure_energy"
-    extra = ([_f64(dens[k]) for k in ("n", "n_dh", "P_hat", "P_hat_dh")] if pe
-             else [None] * 4)
+    extra = ([_f64(dens[k]) for k in ("n", "n_dh", "P_hat", "P_hat_dh")]
+             if params.smoothed_pressure() else [None] * 4)
     lib().or_ghost(n, _f64(dens["rho"]), _f64(dens["rho_dh"]), _f64(dens["div_sum"]),
                    _f64(dens["curl_x"]), _f64(dens["curl_y"]), _f64(dens["curl_z"]), _f64(u),
                    _f64(h), float(params.gamma_gas), float(params.eps_b), out["f"], out["P"],
@@ -469,7 +476,7 @@ def force(ps, h, gst, dens_rho, params: Params, recv=None, mode="auto", cand=Non
                            out["ax"], out["ay"], out["az"], out["du"], out["vsig"], nf,
                            params.flavour_id(), float(params.gamma_gas),
                            out["du_energy"],
-                           _f64(gst["A"]) if params.flavour == "pressure_energy" else None)
+                           _f64(gst["A"]) if params.smoothed_pressure() else None)
     out["nforce"] = nf
     out["total"] = int(total)
     return out
@@ -647,15 +654,33 @@ def alpha_v_update(alpha, div_old, div_new, c, h, vsig, dt, params: Params,
 # ---------------------------------------------------------------------------
 
 SPHENIX_BETA_C = 1.0        # Section 3.3: conduction source strength
+ANARCHY_BETA_C = 0.01       # Appendix A: Anarchy-PU's conduction source strength
+ANARCHY_ELL = 0.25          # Appendix A: Anarchy-PU's viscosity decay length
+
+
+def switch_constants(params: Params):
+    """(ell, beta_c, alpha_V,max of the shock limiter) of a flavour's
+    viscosity switch and conduction parameter; alpha_V,max = inf leaves only
+    the plain cap alpha_c <= alpha_c,max (Anarchy-PU has no shock limiter)."""
+    if params.flavour == "anarchy_pu":
+        return ANARCHY_ELL, ANARCHY_BETA_C, math.inf
+    if params.flavour == "phantom":
+        return PHANTOM_ELL, SPHENIX_BETA_C, SPHENIX_ALPHA_V_MAX
+    return SPHENIX_ELL, SPHENIX_BETA_C, SPHENIX_ALPHA_V_MAX
 SPHENIX_ALPHA_C_MIN = 0.0   # Section 3.3: smallest conduction parameter
 SPHENIX_ALPHA_C_MAX = 1.0   # Section 3.3: constant of the shock limiter
 DT_LIMIT_DELTA = 4.0        # Section 3.4: largest step ratio between neighbours
 
 
-def gradient(ps, h, rho, P, params: Params, recv=None, mode="auto"):
+def gradient(ps, h, rho, P, params: Params, recv=None, mode="auto", c=None):
     """SPHENIX gradient loop (or_gradient): Laplacian of u, conduction speed
     and the largest neighbouring alpha_V for the receivers. rho and P hold
-    every particle's values (only neighbours' entries are read)."""
+    every particle's values (only neighbours' entries are read); c, every
+    particle's sound speed, is required by (and only read for) Anarchy-PU."""
+    if params.flavour == "anarchy_pu":
+        assert c is not None, "Anarchy-PU's conduction speed needs the sound speeds"
+    else:
+        c = None
     mode = _resolve_mode(mode, ps.n)
     h = _f64(h)
     r, nrecv = _recv_arr(recv, ps.n)
@@ -667,7 +692,8 @@ def gradient(ps, h, rho, P, params: Params, recv=None, mode="auto"):
     total = lib().or_gradient(ps.n, x, y, z, _f64(ps.vx), _f64(ps.vy), _f64(ps.vz), _f64(ps.m),
                               _f64(ps.u), h, _f64(rho), _f64(P), _f64(ps.alpha_v), _f64(ps.box),
                               int(params.periodic), float(params.gamma_k), params.kernel_id(),
-                              nrecv, r, off, idx, out["lap_u"], out["vc"], out["avmax"])
+                              nrecv, r, off, idx, out["lap_u"], out["vc"], out["avmax"],
+                              None if c is None else _f64(c))
     out["total"] = int(total)
     return out
 
@@ -762,10 +788,13 @@ def sphenix_run(ps, params: Params, n_steps, c_cfl=0.2, delta=DT_LIMIT_DELTA, mo
         vp = v + 0.5 * dt * np.stack(a)
         up = u + 0.5 * dt * r["du"]
         h, r = evaluate(h, vp, up)
-        alpha_v = alpha_v_update(alpha_v, div_old, r["div_v"], r["c"], h, r["vsig"], dt, params)
+        ell, beta_c, av_lim = switch_constants(params)
+        alpha_v = alpha_v_update(alpha_v, div_old, r["div_v"], r["c"], h, r["vsig"], dt, params,
+                                 ell=ell)
         q.alpha_v = alpha_v.copy()
-        g = gradient(q, h, r["rho"], r["P"], params, mode=mode)
-        alpha_c = alpha_c_update(alpha_c, g["lap_u"], up, h, g["vc"], g["avmax"], dt, params)
+        g = gradient(q, h, r["rho"], r["P"], params, mode=mode, c=r["c"])
+        alpha_c = alpha_c_update(alpha_c, g["lap_u"], up, h, g["vc"], g["avmax"], dt, params,
+                                 beta_c=beta_c, av_max=av_lim)
         kick(v, u, (r["ax"], r["ay"], r["az"]), r["du"], 0.5 * dt)
         t += dt
         hist.append((t, dt))

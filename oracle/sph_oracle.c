@@ -59,6 +59,11 @@
  *  - time step (Section 3.4): the CFL condition, named but not printed, is
  *    read as dt = c_cfl H / v_sig; the first limiter caps a step at Delta
  *    times the smallest step among the force-loop neighbours.
+ *  - Anarchy-PU (Appendix A): the printed conduction speed c_s,i + v_c,j +
+ *    mu_ij is read as c_i + c_j + mu_ij (the signal velocity with the sign
+ *    of mu reversed, as the text says); the conduction parameter evolves
+ *    with beta_c = 0.01 and only the plain cap alpha_c <= 1 (no shock
+ *    limiter); the viscosity switch decays with ell = 0.25.
  *  - pressure-energy (Appendix A): the factors f_ij take the form printed
  *    for this flavour, with the number density n = sum_j W_ij in both
  *    brackets (the generic form of Section 3.2 prints the smoothed b there);
@@ -358,13 +363,14 @@ void or_h_update(int64_t n, const double *h, const double *nd, const double *nd_
  *   A = f P / rho^2.
  * With flavour 1 (density-entropy, Section 3.2) the input u is the
  * adiabat A_i and P = A_i rho^gamma; the rest is unchanged.
- * With flavour 3 (pressure-energy, Appendix A) the pressure is the smoothed
+ * With flavour 3 (pressure-energy, Appendix A; also flavour 4, Anarchy-PU,
+ * which is built on it) the pressure is the smoothed
  * one, P = P_hat (or_pressure), c = sqrt(gamma P_hat / rho), and A returns
  * the grad-h term of its factors f_ij = 1 - A_i / (m_j u_j),
  *   A_i = [h_i dP_hat_i/dh / ((gamma - 1) 3 n_i)] / [1 + h_i/(3 n_i) dn_i/dh],
  * with n the number density; f, div, curl and B as for the other flavours
  * (B with this sound speed). nd, nd_dh, P_hat and P_hat_dh are read only
- * for flavour 3 (NULL otherwise).
+ * for flavours 3 and 4 (NULL otherwise).
  */
 void or_ghost(int64_t n, const double *rho, const double *rho_dh, const double *div_sum,
               const double *curl_x, const double *curl_y, const double *curl_z,
@@ -373,7 +379,7 @@ void or_ghost(int64_t n, const double *rho, const double *rho_dh, const double *
               double *div_v, double *curl_v, int flavour, const double *nd,
               const double *nd_dh, const double *P_hat, const double *P_hat_dh)
 {
-    const int entropy = flavour == 1, pe = flavour == 3;
+    const int entropy = flavour == 1, pe = flavour == 3 || flavour == 4;
     for (int64_t k = 0; k < n; ++k) {
         double r = rho[k];
         /* density-energy: u is the internal energy; density-entropy (the
@@ -432,7 +438,12 @@ void or_ghost(int64_t n, const double *rho, const double *rho_dh, const double *
  *   du_i += m_j [K_ij f_ij g_i / P_i + nu G / 4] (v_ij . e)
  * (the internal-energy equation is the one that conserves the total energy
  * with this acceleration), the same viscosity as the density flavours (f,
- * rho and c of the ghost) and no conduction. F is read only for flavour 3.
+ * rho and c of the ghost) and no conduction. F is read only for flavours 3
+ * and 4.
+ * flavour 4 (Anarchy-PU, Appendix A): flavour 3 plus conduction with the
+ * arithmetic mean alpha_c,ij = (alpha_c,i + alpha_c,j) / 2 and the speed
+ * v_c,ij = c_i + c_j + mu (mu <= 0 as in the viscosity):
+ *   du_i += m_j alpha_c,ij v_c,ij (u_i - u_j) G / (rho_i + rho_j).
  */
 int64_t or_force(int64_t n, const double *x, const double *y, const double *z,
                  const double *vx, const double *vy, const double *vz,
@@ -445,7 +456,8 @@ int64_t or_force(int64_t n, const double *x, const double *y, const double *z,
                  double *ax, double *ay, double *az, double *du, double *vsig, int64_t *nforce,
                  int flavour, double gamma_gas, double *du_energy, const double *F)
 {
-    const int entropy = flavour == 1, phantom = flavour == 2, pe = flavour == 3;
+    const int entropy = flavour == 1, phantom = flavour == 2;
+    const int pe = flavour == 3 || flavour == 4, anarchy = flavour == 4;
     const double gm1sq = (gamma_gas - 1.0) * (gamma_gas - 1.0);
     int64_t total = 0;
 #pragma omp parallel for schedule(dynamic, 16) reduction(+ : total)
@@ -505,7 +517,13 @@ int64_t or_force(int64_t n, const double *x, const double *y, const double *z,
             s_az -= m[j] * acc * ez;
             s_du += m[j] * (Agi + 0.25 * nu * G) * vdote;
             s_visc += m[j] * 0.25 * nu * G * vdote;
-            if (phantom) {
+            if (anarchy) {
+                /* Anarchy-PU (Appendix A): mean alpha_c and the signal speed
+                 * with the sign of mu reversed (and no beta) */
+                double v_c = c[i] + c[j] + mu;
+                double alpha_c_ij = 0.5 * (alpha_c[i] + alpha_c[j]);
+                s_du += m[j] * alpha_c_ij * v_c * (u[i] - u[j]) * G / (rho[i] + rho[j]);
+            } else if (phantom) {
                 /* Phantom-like (Appendix A): alpha_c = 1 for every particle and
                  * the conduction speed without the velocity term */
                 double v_c = sqrt(2.0 * fabs(P[i] - P[j]) / (rho[i] + rho[j]));
@@ -743,7 +761,9 @@ void or_alpha_v_update(int64_t n, const double *div_old, const double *div_new, 
  *              second-derivative form of Brookshaw, which returns 2 for
  *              u = x^2 in the continuum limit)
  *   vc_i     = max_j [ |v_ij . x_ij| / r_ij + sqrt(2 |P_i - P_j| / (rho_i + rho_j)) ]
- *              (the pair conduction speed of Section 3.3; 0 without neighbours)
+ *              (the pair conduction speed of Section 3.3; 0 without neighbours;
+ *              with c != NULL, Anarchy-PU of Appendix A, the pair speed is
+ *              c_i + c_j + min(0, v_ij . x_ij) / r_ij)
  *   avmax_i  = max(alpha_V,i, max_j alpha_V,j)
  * Coincident pairs (r = 0) have no direction and are skipped. Returns the
  * number of pairs used.
@@ -753,7 +773,8 @@ int64_t or_gradient(int64_t n, const double *x, const double *y, const double *z
                     const double *u, const double *h, const double *rho, const double *P,
                     const double *alpha_v, const double *box, int periodic, double gamma_k,
                     int kernel, int64_t nrecv, const int64_t *recv, const int64_t *cand_off,
-                    const int64_t *cand_idx, double *lap_u, double *vc, double *avmax)
+                    const int64_t *cand_idx, double *lap_u, double *vc, double *avmax,
+                    const double *c)
 {
     int64_t total = 0;
 #pragma omp parallel for schedule(dynamic, 16) reduction(+ : total)
@@ -778,7 +799,8 @@ int64_t or_gradient(int64_t n, const double *x, const double *y, const double *z
             or_kernel(kernel, r, hi, gamma_k, &w, &dwdr, &dwdh);
             s_lap += m[j] / rho[j] * (u[i] - u[j]) * dwdr / r;
             double vdotx = (vx[i] - vx[j]) * dx + (vy[i] - vy[j]) * dy + (vz[i] - vz[j]) * dz;
-            double v_c = fabs(vdotx) / r + sqrt(2.0 * fabs(P[i] - P[j]) / (rho[i] + rho[j]));
+            double v_c = c ? c[i] + c[j] + (vdotx < 0.0 ? vdotx / r : 0.0)
+                           : fabs(vdotx) / r + sqrt(2.0 * fabs(P[i] - P[j]) / (rho[i] + rho[j]));
             if (v_c > s_vc)
                 s_vc = v_c;
             if (alpha_v[j] > s_av)
