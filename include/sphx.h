@@ -123,7 +123,12 @@ typedef struct sphx_params {
      * (m_j u_j); the force pass uses the pressure-energy equation of motion
      * with the density flavours' viscosity and no conduction. Every u must be
      * positive. Runs the plain cell-pair density loop only: sphx_ctx_create
-     * refuses it with density_balance != 0 or neighbour_lists != 0). */
+     * refuses it with density_balance != 0 or neighbour_lists != 0) or
+     * SPHX_FLAVOUR_ANARCHY_PU (Anarchy-PU of Appendix A: the pressure-energy
+     * flavour, with its restrictions, plus conduction with the mean
+     * (alpha_c,i + alpha_c,j)/2 and the speed c_i + c_j + mu_ij; in
+     * sphx_gradient the same pair speed, in sphx_alpha_c_update beta_c =
+     * 0.01 and no shock limiter, in sphx_alpha_v_update the length 0.25). */
     int32_t flavour;
 } sphx_params;
 
@@ -131,6 +136,7 @@ typedef struct sphx_params {
 #define SPHX_FLAVOUR_DENSITY_ENTROPY 1
 #define SPHX_FLAVOUR_PHANTOM 2
 #define SPHX_FLAVOUR_PRESSURE_ENERGY 3
+#define SPHX_FLAVOUR_ANARCHY_PU 4
 
 #define SPHX_KERNEL_WENDLAND_C2 0
 #define SPHX_KERNEL_WENDLAND_C4 1
@@ -407,9 +413,9 @@ sphx_status sphx_gravity(sphx_ctx *ctx, const sphx_particles *in, double G, doub
  * with H = gamma_k h, and the target alpha_loc = 2 S / (v_sig^2 + S) (0 where
  * S = 0; alpha_max = 2), alpha_v becomes alpha_loc if that is larger, else
  * alpha_loc + (alpha_v - alpha_loc) exp(-ell c dt / H) (decay length ell =
- * 0.05, or 0.25 with the Phantom-like flavour; the printed update is read as
- * this decay towards the target). alpha_v is
- * read and written in place; c is the sound speed (sphx_ghost_out.c), h the
+ * 0.05, or 0.25 with the Phantom-like and Anarchy-PU flavours; the printed
+ * update is read as this decay towards the target). alpha_v is read and
+ * written in place; c is the sound speed (sphx_ghost_out.c), h the
  * smoothing length, v_sig the signal velocity (sphx_force_out.v_sig).
  * dt > 0 and finite, n >= 0, else E_INVALID. Asynchronous on `stream`. */
 sphx_status sphx_alpha_v_update(sphx_ctx *ctx, int64_t n, const float *div_old,
@@ -425,7 +431,9 @@ sphx_status sphx_alpha_v_update(sphx_ctx *ctx, int64_t n, const float *div_old,
  *                    (Brookshaw's second-derivative estimator; the paper names
  *                    the Laplacian without printing an estimator);
  *   v_c[i]         = max_j |v_ij . x_ij| / r_ij + sqrt(2 |P_i - P_j| / (rho_i + rho_j)),
- *                    the largest pair conduction speed (0 without neighbours);
+ *                    the largest pair conduction speed (0 without neighbours;
+ *                    SPHX_FLAVOUR_ANARCHY_PU: max_j c_i + c_j + min(0, v_ij .
+ *                    x_ij) / r_ij with c = sqrt(gamma P / rho));
  *   alpha_v_max[i] = the largest alpha_V among i and those j (the shock
  *                    limiter's input).
  * Reads positions, velocities, masses and u of the grid (as copied at its
@@ -446,7 +454,8 @@ sphx_status sphx_gradient(sphx_ctx *ctx, sphx_grid *grid, const sphx_tasks *task
  * alpha_inf) exp(-v_c dt / H), alpha_inf = alpha_c,min + S H / v_c with
  * S = beta_c H lap_u / sqrt(u); alpha + S dt where v_c = 0), then capped by
  * the shock limiter at alpha_c,max (1 - alpha_v_max / alpha_V,max) (1 and 2
- * as printed) and kept >= 0. Inputs from sphx_gradient (lap_u, v_c,
+ * as printed) and kept >= 0 (SPHX_FLAVOUR_ANARCHY_PU, Appendix A: beta_c =
+ * 0.01 and the plain cap alpha_c <= 1). Inputs from sphx_gradient (lap_u, v_c,
  * alpha_v_max) and the particles (u, h); alpha_c is updated in place.
  * Device FP32 arrays of n, caller order. dt > 0 and finite, n >= 0, else
  * E_INVALID. Asynchronous. */

@@ -183,14 +183,15 @@ sphx_status sphx_ctx_create(const sphx_params *p, int hip_device, sphx_ctx **out
         return SPHX_E_INVALID;
     }
     if (p->flavour != SPHX_FLAVOUR_DENSITY_ENERGY && p->flavour != SPHX_FLAVOUR_DENSITY_ENTROPY &&
-        p->flavour != SPHX_FLAVOUR_PHANTOM && p->flavour != SPHX_FLAVOUR_PRESSURE_ENERGY) {
+        p->flavour != SPHX_FLAVOUR_PHANTOM && p->flavour != SPHX_FLAVOUR_PRESSURE_ENERGY &&
+        p->flavour != SPHX_FLAVOUR_ANARCHY_PU) {
         set_error("sphx_ctx_create: unknown flavour (SPHX_FLAVOUR_*)");
         return SPHX_E_INVALID;
     }
-    if (p->flavour == SPHX_FLAVOUR_PRESSURE_ENERGY &&
+    if (sphx::smoothed_pressure(p->flavour) &&
         (p->density_balance != 0 || p->neighbour_lists != 0)) {
-        set_error("sphx_ctx_create: the pressure-energy flavour runs the plain cell-pair "
-                  "density loop only (density_balance 0, neighbour_lists 0)");
+        set_error("sphx_ctx_create: the pressure-energy and Anarchy-PU flavours run the plain "
+                  "cell-pair density loop only (density_balance 0, neighbour_lists 0)");
         return SPHX_E_INVALID;
     }
     if (p->graph_passes < 0 || p->graph_passes > 64 || p->density_balance < 0 ||
@@ -811,7 +812,7 @@ sphx_status sphx_autotune(sphx_ctx *ctx, sphx_grid *grid, sphx_tasks *tasks, sph
         double best = 1e300;
         int32_t bt = 128, bw = 1, bb = 0;
         for (auto &sh : dshape) {
-            if (sh[2] != 0 && ctx->p.flavour == SPHX_FLAVOUR_PRESSURE_ENERGY)
+            if (sh[2] != 0 && sphx::smoothed_pressure(ctx->p.flavour))
                 continue;  // built for the plain loop only
             ctx->p.density_tile = sh[0];
             ctx->p.density_waves = sh[1];

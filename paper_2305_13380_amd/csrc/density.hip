@@ -1013,7 +1013,7 @@ sphx_status density_launch(const sphx_ctx *ctx, const sphx_grid *g, const sphx_t
     // receiver (cell-relative coordinates), while every H is below a third
     const float far = float(4.0 * std::max(ctx->p.box[0], std::max(ctx->p.box[1], ctx->p.box[2])));
     SPHX_HIP(ctx->prof->begin(0, s));
-    if (ctx->p.flavour == SPHX_FLAVOUR_PRESSURE_ENERGY) {
+    if (smoothed_pressure(ctx->p.flavour)) {
         SPHX_WITH_KERNEL(ctx->p.kernel, (density_shapes<KK, true>(tile, waves, bal, grouped, nbp,
                                                                   ctx, g, t, lr, dout, far,
                                                                   counters, skip, s)));

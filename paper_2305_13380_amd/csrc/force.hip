@@ -65,7 +65,9 @@ struct StepOut {
 // m_j (gamma - 1)^2 u_i u_j (f_ij g_i / P_i + f_ji g_j / P_j) with f_ij = 1 -
 // F_i / (m_j u_j), no conduction; per particle the state holds F and Q =
 // (gamma - 1)^2 u / P, so that with R = Q F the pair needs only
-// g_i (Q_i m_j u_j - R_i) + g_j (Q_j m_j u_i - R_j m_j / m_i)).
+// g_i (Q_i m_j u_j - R_i) + g_j (Q_j m_j u_i - R_j m_j / m_i); 4 Anarchy-PU,
+// Appendix A: 3 plus conduction with the mean alpha_c and the speed c_i +
+// c_j + mu, its source alpha_c staged where the other flavours keep P_j).
 template <int CAP, int NW, int K, int FLAV>
 __global__ __launch_bounds__(64 * NW) void k_force(
     int64_t n_leaves, int64_t nb_padded, const int32_t *__restrict__ order,
@@ -169,7 +171,7 @@ __global__ __launch_bounds__(64 * NW) void k_force(
     const float fi = gi1.x, Bi = gi1.y, Ai = gi1.z;
     // pressure-energy: the receiver's Q, R = Q F, u and 1/m (else unused)
     const float Qi = gi1.w, Ri = gi1.w * gi1.z, ui_ = vi.w;
-    const float inv_mi = FLAV == 3 ? fast_rcp(pi.w) : 0.0f;
+    const float inv_mi = FLAV >= 3 ? fast_rcp(pi.w) : 0.0f;
     const float acPi = ai.y * Pi;
 
     float ax = 0.f, ay = 0.f, az = 0.f, du = 0.f, duv = 0.f;
@@ -220,17 +222,22 @@ __global__ __launch_bounds__(64 * NW) void k_force(
         const float m = v.w;
         // the pressure terms of i and j (pressure-energy: already times m_j,
         // with the source's b.y = m_j Q_j, c2.x = m_j R_j, c2.y = m_j u_j)
-        const float Agi = in_i ? (FLAV == 3 ? gi * (Qi * c2.y - Ri) : Ai * gi) : 0.0f;
-        const float Agj = in_j ? (FLAV == 3 ? gj * (b.y * ui_ - c2.x * inv_mi) : b.y * gj) : 0.0f;
+        const float Agi = in_i ? (FLAV >= 3 ? gi * (Qi * c2.y - Ri) : Ai * gi) : 0.0f;
+        const float Agj = in_j ? (FLAV >= 3 ? gj * (b.y * ui_ - c2.x * inv_mi) : b.y * gj) : 0.0f;
         const float macc =
-            FLAV == 3 ? Agi + Agj + m * (0.5f * nu * G) : m * (Agi + Agj + 0.5f * nu * G);
+            FLAV >= 3 ? Agi + Agj + m * (0.5f * nu * G) : m * (Agi + Agj + 0.5f * nu * G);
         const float psum = Pi + a.w;
         const float ac =
             FLAV == 2 ? 1.0f : (psum > 0.0f ? (acPi + c2.x) * fast_rcp(psum) : 0.0f);
         const float vc =
             (FLAV == 2 ? 0.0f : fabsf(vdote)) + fast_sqrt(2.0f * fabsf(Pi - a.w) * irs);
         const float dvi = m * (0.25f * nu * G) * vdote;
-        const float dui = FLAV == 3   ? Agi * vdote + dvi
+        // Anarchy-PU: the mean alpha_c (the source's in a.w) and the speed
+        // c_i + c_j + mu, with m_j (u_i - u_j) = m_j u_i - c2.y
+        const float cond4 =
+            FLAV == 4 ? 0.5f * (ai.y + a.w) * (ci + a.y + mu) * (m * ui_ - c2.y) * G * irs : 0.0f;
+        const float dui = FLAV == 4   ? Agi * vdote + dvi + cond4
+                          : FLAV == 3 ? Agi * vdote + dvi
                           : FLAV == 1 ? m * Agi * vdote + dvi
                                       : m * (Agi + 0.25f * nu * G) * vdote +
                                             m * ac * vc * (vi.w - c2.y) * G * irs;
@@ -323,8 +330,10 @@ __global__ __launch_bounds__(64 * NW) void k_force(
             const float4 h1 = g1[sj];
             cp[pos] = make_float4(p.x, p.y, p.z, Hj * Hj);
             cv[pos] = make_float4(v.x, v.y, v.z, p.w);
-            ca[pos] = make_float4(fast_rcp(Hj), h0.w, h0.y, h0.z);
-            if (FLAV == 3) {
+            // (Anarchy-PU keeps alpha_c,j in place of P_j, which its pair
+            // terms do not read)
+            ca[pos] = make_float4(fast_rcp(Hj), h0.w, h0.y, FLAV == 4 ? a.y : h0.z);
+            if (FLAV >= 3) {
                 // m_j Q_j, m_j R_j = m_j Q_j F_j, m_j u_j
                 cb[pos] = make_float4(h1.x, p.w * h1.w, h1.y, a.x);
                 cc[pos] = make_float2(p.w * h1.w * h1.z, p.w * v.w);
@@ -638,7 +647,7 @@ sphx_status force_launch(const sphx_ctx *ctx, const sphx_grid *g, const sphx_tas
     if (!state_ready || in->active) {
         k_force_state<<<unsigned((g->n + 255) / 256), 256, 0, s>>>(
             g->n, g->perm, in->h, d->rho, gs->P, gs->c, gs->f, gs->balsara, gs->A, in->u,
-            ctx->p.flavour == SPHX_FLAVOUR_PRESSURE_ENERGY
+            smoothed_pressure(ctx->p.flavour)
                 ? float((ctx->p.gamma_gas - 1.0) * (ctx->p.gamma_gas - 1.0))
                 : 0.0f,
             state_ready ? in->active : nullptr, g->g0, g->g1);
@@ -668,6 +677,9 @@ sphx_status force_launch(const sphx_ctx *ctx, const sphx_grid *g, const sphx_tas
                                                               far, gate, so, fsum, s)));
     } else if (ctx->p.flavour == SPHX_FLAVOUR_PRESSURE_ENERGY) {
         SPHX_WITH_KERNEL(ctx->p.kernel, (force_shapes<KK, 3>(tile, waves, nbp, ctx, g, t, in, o,
+                                                              far, gate, so, fsum, s)));
+    } else if (ctx->p.flavour == SPHX_FLAVOUR_ANARCHY_PU) {
+        SPHX_WITH_KERNEL(ctx->p.kernel, (force_shapes<KK, 4>(tile, waves, nbp, ctx, g, t, in, o,
                                                               far, gate, so, fsum, s)));
     } else {
         SPHX_WITH_KERNEL(ctx->p.kernel, (force_shapes<KK, 0>(tile, waves, nbp, ctx, g, t, in, o,

@@ -101,7 +101,7 @@ __global__ __launch_bounds__(kGhostThreads) void k_ghost(int64_t n, const int32_
             // particle carries the adiabat A, and P = A rho^gamma;
             // pressure-energy: the smoothed pressure (gamma - 1) sum m u W
             const bool entropy = flavour == SPHX_FLAVOUR_DENSITY_ENTROPY;
-            const bool pe = flavour == SPHX_FLAVOUR_PRESSURE_ENERGY;
+            const bool pe = smoothed_pressure(flavour);
             const float2 sp = pe ? d2[s] : make_float2(0.0f, 0.0f);  // sum m u W, F G'
             const float P = pe ? (gamma_gas - 1.0f) * sp.x
                                : (entropy ? u * powf(rho, gamma_gas)

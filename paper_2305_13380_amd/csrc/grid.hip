@@ -434,7 +434,7 @@ sphx_status grid_build(sphx_ctx *ctx, const sphx_particles *in, hipStream_t s, s
     SPHX_TRY(dalloc(&g->hhi, n, s));
     SPHX_TRY(dalloc(&g->d0, n, s));
     SPHX_TRY(dalloc(&g->d1, n, s));
-    if (P.flavour == SPHX_FLAVOUR_PRESSURE_ENERGY)
+    if (smoothed_pressure(P.flavour))
         SPHX_TRY(dalloc(&g->d2, n, s));
 
     if (n == 0) {

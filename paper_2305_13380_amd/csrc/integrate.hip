@@ -4,10 +4,13 @@
 // * gradient loop: for every active receiver i over j != i with
 //   0 < r_ij < H_i, the Laplacian of u (Brookshaw's second-derivative form)
 //   lap_u_i = 2 sum_j (m_j/rho_j)(u_i - u_j) (dW/dr)/r, the conduction speed
-//   vc_i = max_j (|v_ij . x_ij|/r_ij + sqrt(2|P_i - P_j|/(rho_i + rho_j))) and
-//   the largest alpha_V among i and its neighbours;
+//   vc_i = max_j (|v_ij . x_ij|/r_ij + sqrt(2|P_i - P_j|/(rho_i + rho_j))) (for
+//   Anarchy-PU, Appendix A: max_j (c_i + c_j + min(0, v_ij . x_ij)/r_ij) with
+//   the flavour's sound speed c = sqrt(gamma P / rho)) and the largest
+//   alpha_V among i and its neighbours;
 // * the conduction parameter over a step: its linear evolution equation
-//   with constant coefficients integrated exactly, then the shock limiter;
+//   with constant coefficients integrated exactly, then the shock limiter
+//   (Anarchy-PU: beta_c = 0.01 and only the plain cap);
 // * the step size: the CFL step c_cfl H_i / v_sig,i, capped at Delta times
 //   the smallest CFL step among the force-loop neighbours (r < max(H_i, H_j)),
 //   and the smallest limited step over the active particles;
@@ -46,7 +49,7 @@ __global__ __launch_bounds__(64) void k_gradient(
     const float4 *__restrict__ st, const uint8_t *__restrict__ active,
     const int32_t *__restrict__ toff, const Task *__restrict__ task,
     const float4 *__restrict__ ext, float gamma_k, float *__restrict__ lap_u,
-    float *__restrict__ vc, float *__restrict__ avmax)
+    float *__restrict__ vc, float *__restrict__ avmax, float anarchy_gamma)
 {
     const int64_t L = blockIdx.x;
     if (L >= n_leaves)
@@ -62,6 +65,8 @@ __global__ __launch_bounds__(64) void k_gradient(
     const float4 pi = q0[s];  // x, y, z (cell frame), m
     const float4 vi = q1[s];  // vx, vy, vz, u
     const float4 si = st[s];  // h, rho, P, alpha_V
+    // Anarchy-PU (anarchy_gamma = the gas gamma, else 0): the sound speed
+    const float ci = anarchy_gamma > 0.0f ? sqrtf(anarchy_gamma * si.z / si.y) : 0.0f;
     const float Hi = gamma_k * si.x;
     const float H2 = act ? Hi * Hi : -1.0f;
     const float invH = fast_rcp(Hi);
@@ -115,7 +120,9 @@ __global__ __launch_bounds__(64) void k_gradient(
             const float dl = p.w / sj.y * (vi.w - v.w) * wr;
             const float vdx = (vi.x - v.x) * dx + (vi.y - v.y) * dy + (vi.z - v.z) * dz;
             const float vcij =
-                fabsf(vdx) * rinv + fast_sqrt(2.0f * fabsf(si.z - sj.z) / (si.y + sj.y));
+                anarchy_gamma > 0.0f
+                    ? ci + sqrtf(anarchy_gamma * sj.z / sj.y) + fminf(vdx, 0.0f) * rinv
+                    : fabsf(vdx) * rinv + fast_sqrt(2.0f * fabsf(si.z - sj.z) / (si.y + sj.y));
             lap += on ? dl : 0.0f;
             vcm = on ? fmaxf(vcm, vcij) : vcm;
             avm = on ? fmaxf(avm, sj.w) : avm;
@@ -129,16 +136,18 @@ __global__ __launch_bounds__(64) void k_gradient(
 }
 
 // The conduction parameter over a step dt (constants printed in Section 3.3:
-// beta_c = 1, alpha_c,min = 0, alpha_c,max = 1, alpha_V,max = 2).
+// beta_c = 1, alpha_c,min = 0, alpha_c,max = 1, alpha_V,max = 2; Anarchy-PU,
+// Appendix A: beta_c = 0.01 and no shock limiter, av_max = +inf).
 __global__ __launch_bounds__(kElemThreads) void k_alpha_c(
     int64_t n, const float *__restrict__ lap_u, const float *__restrict__ u,
     const float *__restrict__ h, const float *__restrict__ vc, const float *__restrict__ avmax,
-    const uint8_t *__restrict__ active, float dt, float gamma_k, float *__restrict__ alpha)
+    const uint8_t *__restrict__ active, float dt, float gamma_k, float beta_c, float av_max,
+    float *__restrict__ alpha)
 {
     const int64_t i = int64_t(blockIdx.x) * kElemThreads + threadIdx.x;
     if (i >= n || (active && !active[i]))
         return;
-    constexpr float beta_c = 1.0f, a_min = 0.0f, a_max = 1.0f, av_max = 2.0f;
+    constexpr float a_min = 0.0f, a_max = 1.0f;
     const float H = gamma_k * h[i];
     const float ui = u[i];
     const float S = ui > 0.0f ? beta_c * H * lap_u[i] / sqrtf(ui) : 0.0f;
@@ -330,7 +339,9 @@ sphx_status gradient_launch(const sphx_ctx *ctx, sphx_grid *g, const sphx_tasks 
                      (k_gradient<KK><<<unsigned(g->n_leaves), 64, 0, s>>>(
                          g->n_leaves, g->leaf_start, g->perm, g->q0, g->q1, g->g2, in->active,
                          t->off, t->task, g->leaf_ext, float(ctx->p.gamma_k), lap_u, vc,
-                         avmax)));
+                         avmax,
+                         ctx->p.flavour == SPHX_FLAVOUR_ANARCHY_PU ? float(ctx->p.gamma_gas)
+                                                                   : 0.0f)));
     SPHX_HIP(hipGetLastError());
     return SPHX_OK;
 }
@@ -341,8 +352,10 @@ sphx_status alpha_c_launch(const sphx_ctx *ctx, int64_t n, const float *lap_u, c
 {
     if (n == 0)
         return SPHX_OK;
-    k_alpha_c<<<elem_blocks(n), kElemThreads, 0, s>>>(n, lap_u, u, h, vc, avmax, active,
-                                                      float(dt), float(ctx->p.gamma_k), alpha);
+    const bool anarchy = ctx->p.flavour == SPHX_FLAVOUR_ANARCHY_PU;
+    k_alpha_c<<<elem_blocks(n), kElemThreads, 0, s>>>(
+        n, lap_u, u, h, vc, avmax, active, float(dt), float(ctx->p.gamma_k),
+        anarchy ? 0.01f : 1.0f, anarchy ? __builtin_inff() : 2.0f, alpha);
     SPHX_HIP(hipGetLastError());
     return SPHX_OK;
 }

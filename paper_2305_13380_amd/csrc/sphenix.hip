@@ -37,9 +37,12 @@ sphx_status alpha_v_launch(const sphx_ctx *ctx, int64_t n, const float *div_old,
     if (n == 0)
         return SPHX_OK;
     const unsigned nb = unsigned((n + kSwitchThreads - 1) / kSwitchThreads);
-    // decay length: 0.05 (SPHENIX, Section 3.3), 0.25 (the Phantom-like
-    // flavour, Appendix A)
-    const float ell = ctx->p.flavour == SPHX_FLAVOUR_PHANTOM ? 0.25f : 0.05f;
+    // decay length: 0.05 (SPHENIX, Section 3.3), 0.25 (the Phantom-like and
+    // Anarchy-PU flavours, Appendix A)
+    const float ell = (ctx->p.flavour == SPHX_FLAVOUR_PHANTOM ||
+                       ctx->p.flavour == SPHX_FLAVOUR_ANARCHY_PU)
+                          ? 0.25f
+                          : 0.05f;
     k_alpha_v<<<nb, kSwitchThreads, 0, s>>>(n, div_old, div_new, c, h, vsig, float(dt),
                                             float(ctx->p.gamma_k), 2.0f, ell, alpha);
     SPHX_HIP(hipGetLastError());

@@ -35,6 +35,11 @@ void set_error(const std::string &msg);
 // One wave64 processes one leaf cell of at most kLeafMax particles.
 constexpr int kWave = 64;
 constexpr int kLeafMax = 64;
+// Flavours whose density loop also forms the smoothed pressure (Appendix A).
+__host__ __device__ inline bool smoothed_pressure(int flavour)
+{
+    return flavour == SPHX_FLAVOUR_PRESSURE_ENERGY || flavour == SPHX_FLAVOUR_ANARCHY_PU;
+}
 constexpr int kTreeFan = 8;     // tree over leaves: groups of 8 consecutive nodes
 constexpr int kMaxLevels = 24;
 constexpr int kMortonBits = 21; // bits per axis of the 63-bit Morton key

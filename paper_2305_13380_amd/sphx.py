@@ -173,7 +173,7 @@ def _check(status):
 
 
 FLAVOURS = {"energy": 0, "entropy": 1, "phantom": 2,  # SPHX_FLAVOUR_*
-            "pressure_energy": 3}
+            "pressure_energy": 3, "anarchy_pu": 4}
 
 
 def default_params(**kw) -> Params:

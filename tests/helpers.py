@@ -20,8 +20,8 @@ EDGE = 1e-6
 
 
 def _pressure(kw):
-    """The pressure-energy flavour's runs also return the smoothed pressure."""
-    return kw.get("flavour") in ("pressure_energy", 3)
+    """The smoothed-pressure flavours' runs also return the smoothed pressure."""
+    return kw.get("flavour") in ("pressure_energy", 3, "anarchy_pu", 4)
 
 
 def gpu_fixed_h(ps, params=None, device="cuda:0", leaf_max=None):

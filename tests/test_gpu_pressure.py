@@ -109,6 +109,8 @@ def check_pressure(g, ref, recv, h, where, ps, params=PPE):
 
 
 def run_and_check(ps, params, where, fixed=False):
+    """One step (or the fixed-h passes) of a smoothed-pressure flavour
+    (params["flavour"]) against the oracle at the step's own h."""
     if fixed:
         g = gpu_fixed_h(ps, params=params)
         h = ps.h.astype(np.float64)
@@ -116,7 +118,7 @@ def run_and_check(ps, params, where, fixed=False):
         g = gpu_step(ps, params=params)
         assert g["status"] >= 0 and g["info"].unconverged == 0
         h = g["h"].astype(np.float64)
-    pk = oracle.Params.with_kernel(params.get("kernel", PPE.kernel), flavour="pressure_energy")
+    pk = oracle.Params.with_kernel(params.get("kernel", PPE.kernel), flavour=params["flavour"])
     ref = oracle.fixed_h_step(ps, pk, h=h)
     recv = np.arange(ps.n)
     check_density(g, ref, ps, h, recv, pk, where)
