@@ -285,7 +285,8 @@ def step_leg(name, params, steps=5, warmup=1, flavour=None):
     on the stream around `steps` whole steps from the generator's h, inputs
     resident): the Sedov box and the large box with its active subset (after
     an untimed all-active step that gives the inactive particles their
-    state), or the headline box with another SPH flavour."""
+    state), or the headline box with another SPH flavour (the density-entropy
+    one with A set from u, the smoothed-pressure ones on the same u)."""
     import numpy as np
     import torch
     from paper_2305_13380_amd import inputs, sphx
@@ -310,6 +311,13 @@ def step_leg(name, params, steps=5, warmup=1, flavour=None):
                                      / rho ** (gam - 1.0)).astype(np.float32))
         params = type(params).from_buffer_copy(params)
         params.flavour = sphx.FLAVOURS["entropy"]
+    elif flavour in ("pressure_energy", "anarchy_pu"):
+        # the smoothed-pressure flavours run the plain cell-pair density loop
+        # (the tuned tile and wave count are kept)
+        params = type(params).from_buffer_copy(params)
+        params.flavour = sphx.FLAVOURS[flavour]
+        params.density_balance = 0
+        params.neighbour_lists = 0
     dp = sphx.DeviceParticles.from_set(ps, "cuda:0")
     out = sphx.Outputs(ps.n, "cuda:0")
     ctx = sphx.Context(params, 0)
@@ -550,7 +558,8 @@ def main():
                     help="skip the direct-summation gravity timing on the workload")
     ap.add_argument("--no-legs", action="store_true",
                     help="skip the other workloads of the step (Sedov box, large box, "
-                         "density-entropy flavour) and the multi-step SPHENIX run")
+                         "the density-entropy, pressure-energy and Anarchy-PU flavours) "
+                         "and the multi-step SPHENIX run")
     ap.add_argument("--serving-requests", type=int, default=512)
     ap.add_argument("--serving-slots", type=int, default=8)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -786,6 +795,9 @@ def main():
             "sedov": step_leg("sedov", params, steps=10),
             "large": step_leg("large", params, steps=3),
             "clustered_entropy": step_leg("clustered", params, steps=5, flavour="entropy"),
+            "clustered_pressure_energy": step_leg("clustered", params, steps=5,
+                                                  flavour="pressure_energy"),
+            "clustered_anarchy_pu": step_leg("clustered", params, steps=5, flavour="anarchy_pu"),
         }
         line["sphenix_run"] = sphenix_leg(params)
     if not args.no_fof:
