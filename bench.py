@@ -785,10 +785,12 @@ def main():
         line["probe"] = {
             "lane_slots_per_accepted_pair": probe[0] / probe[2],
             "receiver_lane_tests_per_accepted_pair": probe[1] / probe[2],
+            "compute_lane_slot_fill": probe[4] / max(probe[3], 1),
             "accepted_pairs": probe[2], "steps": args.steps,
             "what": "cell-pair density loop of a measurement build (SPHX_PROBE=1): lane slots "
                     "of its candidate tests, the tests of lanes holding a receiver, accepted "
-                    "pairs (own particle included)"}
+                    "pairs (own particle included); the share of its per-lane compute "
+                    "loops' lane slots that evaluate a list entry"}
     del grid, tasks, out
     if not args.no_legs and args.config == "clustered":
         line["other_workloads"] = {

@@ -507,13 +507,15 @@ sphx_status sphx_drift(sphx_ctx *ctx, int64_t n, double *x, double *y, double *z
 sphx_status sphx_profile_enable(sphx_ctx *ctx, int32_t enable);
 sphx_status sphx_profile_read(sphx_ctx *ctx, int32_t kernel, double *total_ms, int64_t *launches);
 
-/* Neighbour-test counters of a measurement build of the library (built with
+/* Neighbour-loop counters of a measurement build of the library (built with
  * SPHX_PROBE=1; product builds count nothing and return 1 with zeros): since
- * the last clear, counts3[0] = lane slots taken by the candidate tests of the
+ * the last clear, counts5[0] = lane slots taken by the candidate tests of the
  * cell-pair density loop (per-lane rounds), [1] = those tests made by lanes
  * holding a receiver, [2] = accepted pairs (each receiver's own particle
- * included). clear != 0 zeroes them after reading. Synchronous. */
-sphx_status sphx_probe_read(sphx_ctx *ctx, uint64_t *counts3, int32_t clear);
+ * included), [3] = lane slots of its per-lane compute loops (64 lanes x 4
+ * entries per round), [4] = list entries those loops evaluated. clear != 0
+ * zeroes them after reading. Synchronous. */
+sphx_status sphx_probe_read(sphx_ctx *ctx, uint64_t *counts5, int32_t clear);
 
 /* Leaf and task counts of a grid / task list (host values). */
 int64_t sphx_grid_leaves(const sphx_grid *grid);

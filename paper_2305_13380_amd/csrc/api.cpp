@@ -904,17 +904,17 @@ sphx_status sphx_profile_read(sphx_ctx *ctx, int32_t kernel, double *total_ms, i
     return SPHX_OK;
 }
 
-sphx_status sphx_probe_read(sphx_ctx *ctx, uint64_t *counts3, int32_t clear)
+sphx_status sphx_probe_read(sphx_ctx *ctx, uint64_t *counts5, int32_t clear)
 {
-    if (!ctx || !counts3) {
+    if (!ctx || !counts5) {
         set_error("sphx_probe_read: NULL argument");
         return SPHX_E_INVALID;
     }
     SPHX_HIP(hipSetDevice(ctx->device));
-    unsigned long long v[3] = {0, 0, 0};
+    unsigned long long v[5] = {0, 0, 0, 0, 0};
     const sphx_status st = probe_read(v, clear != 0);
-    for (int k = 0; k < 3; ++k)
-        counts3[k] = v[k];
+    for (int k = 0; k < 5; ++k)
+        counts5[k] = v[k];
     return st;
 }
 

@@ -14,15 +14,16 @@
 
 // Measurement builds (SPHX_PROBE=1) count the cell-pair loop's neighbour
 // tests: the lane slots the tests occupy, the tests made by lanes that hold a
-// receiver, and the accepted pairs, into probe_counts (read and cleared by
-// sphx_probe_read). Product builds count nothing.
+// receiver, and the accepted pairs; and its per-lane compute loops: the lane
+// slots of their rounds and the list entries evaluated; into probe_counts
+// (read and cleared by sphx_probe_read). Product builds count nothing.
 #ifndef SPHX_PROBE
 #define SPHX_PROBE 0
 #endif
 
 namespace sphx {
 
-__device__ unsigned long long probe_counts[3];
+__device__ unsigned long long probe_counts[5];
 
 namespace {
 
@@ -250,6 +251,7 @@ __global__ __launch_bounds__(64 * NW) void k_density(
     int gbase = 0;  // candidates of the earlier buffers (wave-uniform)
     int nc = 0;   // buffered candidates (wave-uniform)
     int myn = 0;  // this lane's list length (its own particle is listed too)
+    unsigned probe_cslots = 0, probe_cfill = 0;  // compute-loop lane slots, entries
     float4 *rp = rp_all[w];
     float4 *rv = rv_all[w];
     int32_t *cb = cb_all[w];
@@ -268,7 +270,11 @@ __global__ __launch_bounds__(64 * NW) void k_density(
     }
     auto compute = [&]() __attribute__((always_inline)) {
         S[8] += float(myn);
+        if (SPHX_PROBE)
+            probe_cfill += myn;
         for (int k = 0; __any(k < myn); k += 4) {
+            if (SPHX_PROBE)
+                probe_cslots += 4;
             const uint32_t four = *reinterpret_cast<const uint32_t *>(my_list + k);
             float4 p[4], v[4];
 #pragma unroll
@@ -498,8 +504,9 @@ __global__ __launch_bounds__(64 * NW) void k_density(
         for (int k = 0; k < NS; ++k)
             S[k] += __shfl_xor(S[k], o, 64);
     if (SPHX_PROBE) {
-        unsigned long long v[3] = {probe_slots, probe_tests, probe_hits};
-        for (int k = 0; k < 3; ++k) {
+        unsigned long long v[5] = {probe_slots, probe_tests, probe_hits, probe_cslots,
+                                   probe_cfill};
+        for (int k = 0; k < 5; ++k) {
             for (int o = 32; o > 0; o >>= 1)
                 v[k] += __shfl_xor(v[k], o, 64);
             if (lane == 0)
@@ -900,11 +907,11 @@ __global__ __launch_bounds__(256) void k_stale_count(int64_t n, const uint8_t *_
         atomicAdd(stale, 1);  // one per block: at most 1024 on one word
 }
 
-sphx_status probe_read(unsigned long long out[3], bool clear)
+sphx_status probe_read(unsigned long long out[5], bool clear)
 {
-    SPHX_HIP(hipMemcpyFromSymbol(out, HIP_SYMBOL(probe_counts), 3 * sizeof(unsigned long long)));
+    SPHX_HIP(hipMemcpyFromSymbol(out, HIP_SYMBOL(probe_counts), 5 * sizeof(unsigned long long)));
     if (clear) {
-        const unsigned long long zero[3] = {0, 0, 0};
+        const unsigned long long zero[5] = {0, 0, 0, 0, 0};
         SPHX_HIP(hipMemcpyToSymbol(HIP_SYMBOL(probe_counts), zero, sizeof(zero)));
     }
     return SPHX_PROBE ? SPHX_OK : 1;
@@ -927,8 +934,7 @@ sphx_status stale_count_launch(const sphx_ctx *ctx, const sphx_grid *g, const sp
 // grouped and list loops are refused for that flavour when the context is
 // made.
 template <int K, bool PE>
-static void density_shapes(int tile, int waves, bool bal, bool grouped, int64_t nbp,
-                           const sphx_ctx *ctx,
+static void density_shapes(int tile, int waves, int mode, int64_t nbp, const sphx_ctx *ctx,
                            const sphx_grid *g, const sphx_tasks *t, const float *lr,
                            const DensOut &dout, float far, int32_t *counters,
                            const int32_t *skip, hipStream_t s)
@@ -938,61 +944,45 @@ static void density_shapes(int tile, int waves, bool bal, bool grouped, int64_t 
         g->n_leaves, nbp, t->order, g->leaf_start, g->perm, g->q0, g->q1, g->need, g->hs,      \
         t->radius, t->off, t->task, g->leaf_ext, float(ctx->p.gamma_k), far, lr, dout,        \
         counters, skip)
+#define SPHX_DENSITY_TILES(NW_, BAL_)                                                          \
+    do {                                                                                       \
+        if (tile == 64)                                                                        \
+            SPHX_DENSITY_LAUNCH(64, NW_, BAL_);                                                \
+        else if (tile == 128)                                                                  \
+            SPHX_DENSITY_LAUNCH(128, NW_, BAL_);                                               \
+        else                                                                                   \
+            SPHX_DENSITY_LAUNCH(256, NW_, BAL_);                                               \
+    } while (0)
     if constexpr (PE) {
-        if (waves == 1) {
-            if (tile == 64)
-                SPHX_DENSITY_LAUNCH(64, 1, false);
-            else if (tile == 128)
-                SPHX_DENSITY_LAUNCH(128, 1, false);
-            else
-                SPHX_DENSITY_LAUNCH(256, 1, false);
-        } else {
-            if (tile == 64)
-                SPHX_DENSITY_LAUNCH(64, 2, false);
-            else if (tile == 128)
-                SPHX_DENSITY_LAUNCH(128, 2, false);
-            else
-                SPHX_DENSITY_LAUNCH(256, 2, false);
-        }
+        if (waves == 1)
+            SPHX_DENSITY_TILES(1, false);
+        else
+            SPHX_DENSITY_TILES(2, false);
         return;
-    }
-    if (grouped && !lr) {
+    } else {
+        if (mode == 2 && !lr) {
 #define SPHX_DENSITY_GRP(CAP_)                                                                 \
     k_density_grp<CAP_, K><<<unsigned(nbp), 64, 0, s>>>(                                      \
         g->n_leaves, nbp, t->order, g->leaf_start, g->perm, g->q0, g->q1, g->need, g->hs,      \
         t->radius, t->off, t->task, g->leaf_ext, float(ctx->p.gamma_k), far, dout, counters,   \
         skip)
-        if (tile == 64)
-            SPHX_DENSITY_GRP(64);
-        else if (tile == 128)
-            SPHX_DENSITY_GRP(128);
-        else
-            SPHX_DENSITY_GRP(256);
+            if (tile == 64)
+                SPHX_DENSITY_GRP(64);
+            else if (tile == 128)
+                SPHX_DENSITY_GRP(128);
+            else
+                SPHX_DENSITY_GRP(256);
 #undef SPHX_DENSITY_GRP
-        return;
+            return;
+        }
+        if (mode == 1)
+            SPHX_DENSITY_TILES(1, true);
+        else if (waves == 1)
+            SPHX_DENSITY_TILES(1, false);
+        else
+            SPHX_DENSITY_TILES(2, false);
     }
-    if (bal) {
-        if (tile == 64)
-            SPHX_DENSITY_LAUNCH(64, 1, true);
-        else if (tile == 128)
-            SPHX_DENSITY_LAUNCH(128, 1, true);
-        else
-            SPHX_DENSITY_LAUNCH(256, 1, true);
-    } else if (waves == 1) {
-        if (tile == 64)
-            SPHX_DENSITY_LAUNCH(64, 1, false);
-        else if (tile == 128)
-            SPHX_DENSITY_LAUNCH(128, 1, false);
-        else
-            SPHX_DENSITY_LAUNCH(256, 1, false);
-    } else {
-        if (tile == 64)
-            SPHX_DENSITY_LAUNCH(64, 2, false);
-        else if (tile == 128)
-            SPHX_DENSITY_LAUNCH(128, 2, false);
-        else
-            SPHX_DENSITY_LAUNCH(256, 2, false);
-    }
+#undef SPHX_DENSITY_TILES
 #undef SPHX_DENSITY_LAUNCH
 }
 
@@ -1005,8 +995,7 @@ sphx_status density_launch(const sphx_ctx *ctx, const sphx_grid *g, const sphx_t
     const int64_t nbp = pad8(g->n_leaves);
     const int tile = ctx->p.density_tile ? ctx->p.density_tile : 128;
     const int waves = ctx->p.density_waves ? ctx->p.density_waves : 1;
-    const bool bal = ctx->p.density_balance == 1;
-    const bool grouped = ctx->p.density_balance == 2;
+    const int mode = ctx->p.density_balance;
     const float *lr = use_lists ? g->lrad : nullptr;
     const DensOut dout = dens_out(ctx, g, o);
     // the dummy source: 4 box lengths out, more than 3 box lengths from any
@@ -1014,13 +1003,13 @@ sphx_status density_launch(const sphx_ctx *ctx, const sphx_grid *g, const sphx_t
     const float far = float(4.0 * std::max(ctx->p.box[0], std::max(ctx->p.box[1], ctx->p.box[2])));
     SPHX_HIP(ctx->prof->begin(0, s));
     if (smoothed_pressure(ctx->p.flavour)) {
-        SPHX_WITH_KERNEL(ctx->p.kernel, (density_shapes<KK, true>(tile, waves, bal, grouped, nbp,
-                                                                  ctx, g, t, lr, dout, far,
-                                                                  counters, skip, s)));
+        SPHX_WITH_KERNEL(ctx->p.kernel, (density_shapes<KK, true>(tile, waves, mode, nbp, ctx, g,
+                                                                  t, lr, dout, far, counters,
+                                                                  skip, s)));
     } else {
-        SPHX_WITH_KERNEL(ctx->p.kernel, (density_shapes<KK, false>(tile, waves, bal, grouped, nbp,
-                                                                   ctx, g, t, lr, dout, far,
-                                                                   counters, skip, s)));
+        SPHX_WITH_KERNEL(ctx->p.kernel, (density_shapes<KK, false>(tile, waves, mode, nbp, ctx,
+                                                                   g, t, lr, dout, far, counters,
+                                                                   skip, s)));
     }
     SPHX_HIP(hipGetLastError());
     SPHX_HIP(ctx->prof->end(0, s));

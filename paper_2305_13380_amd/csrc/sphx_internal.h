@@ -256,8 +256,9 @@ size_t tasks_bytes(int64_t n);
 // density.hip
 // The probe counters of a measurement build (SPHX_PROBE=1): lane slots of the
 // cell-pair loop's neighbour tests, tests by lanes holding a receiver,
-// accepted pairs; returns 1 (and zeros) in a product build. Synchronous.
-sphx_status probe_read(unsigned long long out[3], bool clear);
+// accepted pairs, compute-loop lane slots and the entries they evaluated;
+// returns 1 (and zeros) in a product build. Synchronous.
+sphx_status probe_read(unsigned long long out[5], bool clear);
 // Count the receivers that outgrew their leaf's task radius into *stale
 // (added to; a density pass given skip = stale then returns at once).
 sphx_status stale_count_launch(const sphx_ctx *ctx, const sphx_grid *g, const sphx_tasks *t,

@@ -452,9 +452,10 @@ def alpha_v_update(ctx, alpha_v, div_old, div_new, c, h, v_sig, dt, stream=None)
 
 
 def probe_read(ctx, clear=True):
-    """Neighbour-test counters of a measurement build (sphx_probe_read):
-    (probe build?, [lane slots, receiver-lane tests, accepted pairs])."""
-    v = (C.c_uint64 * 3)()
+    """Neighbour-loop counters of a measurement build (sphx_probe_read):
+    (probe build?, [lane slots, receiver-lane tests, accepted pairs,
+    compute-loop lane slots, entries they evaluated])."""
+    v = (C.c_uint64 * 5)()
     st = _check(lib.sphx_probe_read(ctx.handle, v, 1 if clear else 0))
     return st == 0, [int(x) for x in v]
 
