@@ -600,7 +600,7 @@ static sphx_status step_run(sphx_ctx *ctx, sphx_grid *grid, sphx_tasks **tasks,
         }
         // The iteration goes on pass by pass from the state the graph left.
         if (stale || rebuild) {
-            SPHX_TRY(tasks_build(ctx, grid, in, s, tasks));
+            SPHX_TRY(tasks_grow(ctx, grid, in, s, tasks));
             local.task_rebuilds++;
         }
         unsigned long long u[2] = {(unsigned long long)local.pairs_cellpair,
@@ -641,7 +641,7 @@ static sphx_status step_run(sphx_ctx *ctx, sphx_grid *grid, sphx_tasks **tasks,
                 set_error("sphx_step: task list keeps going stale");
                 return SPHX_E_STATE;
             }
-            SPHX_TRY(tasks_build(ctx, grid, in, s, tasks));
+            SPHX_TRY(tasks_grow(ctx, grid, in, s, tasks));
             local.task_rebuilds++;
             lists = false;
             continue;
@@ -655,7 +655,7 @@ static sphx_status step_run(sphx_ctx *ctx, sphx_grid *grid, sphx_tasks **tasks,
             break;
         }
         if (h_counters[1] > 0) {
-            SPHX_TRY(tasks_build(ctx, grid, in, s, tasks));
+            SPHX_TRY(tasks_grow(ctx, grid, in, s, tasks));
             local.task_rebuilds++;
             lists = false;  // list entries name tasks of the old list
         }
@@ -682,6 +682,12 @@ static sphx_status step_run(sphx_ctx *ctx, sphx_grid *grid, sphx_tasks **tasks,
         memcpy(u, h_buf + kStepUnitsOffset, sizeof(u));
         local.pairs_cellpair = int64_t(u[0]);
         local.pairs_list = int64_t(u[1]);
+    }
+    if (!(*tasks)->symmetric) {
+        // the growth rebuilds served the density passes; the force pass needs
+        // every pair that either side's radius reaches
+        SPHX_TRY(tasks_build(ctx, grid, in, s, tasks));
+        local.task_rebuilds++;
     }
     SPHX_TRY(force_launch(ctx, grid, *tasks, in, dens, gst, out, d_sums6, s, nullptr, true));
     local.n_leaves = grid->n_leaves;

@@ -448,16 +448,18 @@ __global__ __launch_bounds__(64 * NW) void k_density(
         nc += tot;
     };
 
-    // This wave's share of the cell's tasks.
-    const int32_t ta = toff[L], tn = toff[L + 1] - ta;
-    const int32_t t_begin = ta + int32_t((int64_t(tn) * w) / NW);
-    const int32_t t_end = ta + int32_t((int64_t(tn) * (w + 1)) / NW);
-    for (int32_t tb = t_begin; tb < t_end; tb += 64) {
+    // This wave's share of the cell's tasks: those of the source cells J with
+    // J mod NW = w. A split by position would move with the list's length,
+    // and a list that also holds cells beyond every receiver's reach (one
+    // kept through growth rebuilds) would then give other partial sums.
+    const int32_t ta = toff[L], t_end = toff[L + 1];
+    for (int32_t tb = ta; tb < t_end; tb += 64) {
         const int nb = min(64, t_end - tb);
         TaskRegs tr;
         tr.load(task, tb + lane, lane < nb);
         // whole source cells beyond R of the receivers' box are skipped
-        if (lane < nb && task_box_dist2(tr.b.x, tr.b.y, tr.b.z, ext[tr.a.w], lo, hb) >= R2)
+        if (lane < nb && ((NW > 1 && tr.a.w % NW != w) ||
+                          task_box_dist2(tr.b.x, tr.b.y, tr.b.z, ext[tr.a.w], lo, hb) >= R2))
             tr.a.y = 0;
         for (int u = 0; u < nb; u += 4) {
             int j0[4], jc[4];

@@ -345,10 +345,10 @@ __global__ __launch_bounds__(64 * NW) void k_force(
         nc += tot;
     };
 
-    const int32_t ta = toff[L], tn = toff[L + 1] - ta;
-    const int32_t t_begin = ta + int32_t((int64_t(tn) * w) / NW);
-    const int32_t t_end = ta + int32_t((int64_t(tn) * (w + 1)) / NW);
-    for (int32_t tb = t_begin; tb < t_end; tb += 64) {
+    // This wave's share: the tasks of the source cells J with J mod NW = w
+    // (a split that the list's length does not move).
+    const int32_t ta = toff[L], t_end = toff[L + 1];
+    for (int32_t tb = ta; tb < t_end; tb += 64) {
         const int nb = min(64, t_end - tb);
         TaskRegs tr;
         tr.load(task, tb + lane, lane < nb);
@@ -356,7 +356,8 @@ __global__ __launch_bounds__(64 * NW) void k_force(
         // receivers' box are skipped
         if (lane < nb) {
             const float rj = hmax[tr.a.w];
-            if (task_box_dist2(tr.b.x, tr.b.y, tr.b.z, ext[tr.a.w], lo, hb) >= fmaxf(R2, rj * rj))
+            if ((NW > 1 && tr.a.w % NW != w) ||
+                task_box_dist2(tr.b.x, tr.b.y, tr.b.z, ext[tr.a.w], lo, hb) >= fmaxf(R2, rj * rj))
                 tr.a.y = 0;
         }
         for (int u = 0; u < nb; u += 4) {

@@ -206,6 +206,17 @@ struct sphx_tasks {
     int32_t *soff;      // n_leaves + 1
     int64_t slack_cap;
     bool slack_ok;      // soff holds a layout for this grid
+    // Growth rebuilds (tasks_grow): only the leaves whose radius grew are
+    // walked again; the others keep their lists, copied into the second
+    // array, which then becomes the list. Such lists serve the density loop
+    // (each leaf's list covers its own radius) but can miss a pair that a
+    // grown neighbour's radius alone reaches: `symmetric` is false until the
+    // next full build, which the force pass requires.
+    sphx::Task *task_alt;  // cap_alt
+    int64_t cap_alt;
+    int32_t *off_alt;      // n_leaves + 1
+    uint8_t *dirty;        // n_leaves: walked again by the last growth rebuild
+    bool symmetric;        // every pair within max(R_I, R_J) of the radii is listed
 };
 
 namespace sphx {
@@ -224,6 +235,14 @@ size_t grid_bytes(int64_t n);
 // tasks.hip
 sphx_status tasks_build(sphx_ctx *ctx, sphx_grid *g, const sphx_particles *in, hipStream_t s,
                         sphx_tasks **out);
+// Growth rebuild of an existing list for the h iteration's density passes:
+// the leaves whose (1 + skin) gamma_k max h grew beyond their list's radius
+// (and those the serial walk built) are walked again at the current radii,
+// the others keep their lists; leaves' radii never shrink here. Leaves the
+// list not symmetric (see sphx_tasks). Falls back to tasks_build when the
+// list has no slot layout to walk into.
+sphx_status tasks_grow(sphx_ctx *ctx, sphx_grid *g, const sphx_particles *in, hipStream_t s,
+                       sphx_tasks **out);
 void tasks_free(sphx_tasks *t);
 // A grid and task list over every particle of `in` with a uniform search
 // radius (h = radius / gamma_k on a private array): the pair structure of

@@ -54,6 +54,76 @@ __global__ __launch_bounds__(64) void k_leaf_radius(int64_t n_leaves,
     }
 }
 
+// Growth rebuild: a leaf is walked again when (1 + skin) gamma_k max h grew
+// beyond its list's radius (the radius then grows; it never shrinks here) or
+// when the serial walk built its list; the tree holds the lists' radii.
+__global__ __launch_bounds__(64) void k_leaf_radius_grow(int64_t n_leaves,
+                                                         const int32_t *__restrict__ leaf_start,
+                                                         const float *__restrict__ hs,
+                                                         float scale, float *__restrict__ node_r,
+                                                         float *__restrict__ radius,
+                                                         uint8_t *__restrict__ overflow,
+                                                         uint8_t *__restrict__ dirty)
+{
+    int64_t L = blockIdx.x;
+    if (L >= n_leaves)
+        return;
+    int lane = threadIdx.x;
+    int32_t s0 = leaf_start[L], cnt = leaf_start[L + 1] - s0;
+    float v = lane < cnt ? hs[s0 + lane] : 0.0f;
+    v = wave_maxf(v) * scale;
+    if (lane == 0) {
+        const bool grow = v > radius[L];
+        const bool d = grow || overflow[L] != 0;
+        const float r = grow ? v : radius[L];
+        radius[L] = r;
+        node_r[L] = r;
+        dirty[L] = d ? 1 : 0;
+        if (d)
+            overflow[L] = 0;  // the walk decides again
+    }
+}
+
+// Growth rebuild: the leaves kept as they are count their current lists.
+__global__ void k_keep_counts(int64_t n_leaves, const uint8_t *__restrict__ dirty,
+                              const int32_t *__restrict__ off, int32_t *__restrict__ count)
+{
+    const int64_t I = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (I < n_leaves && !dirty[I])
+        count[I] = off[I + 1] - off[I];
+    else if (I == n_leaves)
+        count[I] = 0;
+}
+
+// Growth rebuild: the new list from the old one (leaves kept) and from the
+// slots of the walked leaves that fitted (the others are written by the
+// second walk or the serial fill).
+__global__ __launch_bounds__(64) void k_copy_grown(int64_t n_leaves,
+                                                   const uint8_t *__restrict__ dirty,
+                                                   const uint8_t *__restrict__ overflow,
+                                                   const int32_t *__restrict__ off_old,
+                                                   const int32_t *__restrict__ off_new,
+                                                   const int32_t *__restrict__ soff,
+                                                   const int32_t *__restrict__ count,
+                                                   const Task *__restrict__ task_old,
+                                                   const Task *__restrict__ slack,
+                                                   Task *__restrict__ task_new)
+{
+    const int64_t I = blockIdx.x;
+    if (I >= n_leaves)
+        return;
+    const int32_t n = count[I], b = off_new[I];
+    const Task *src;
+    if (!dirty[I])
+        src = task_old + off_old[I];
+    else if (!overflow[I] && n <= soff[I + 1] - soff[I])
+        src = slack + soff[I];
+    else
+        return;
+    for (int32_t k = threadIdx.x; k < n; k += 64)
+        task_new[b + k] = src[k];
+}
+
 __global__ void k_tree_radius(int64_t cnt_up, int64_t cnt_dn, const float *__restrict__ r_dn,
                               float *__restrict__ r_up)
 {
@@ -280,11 +350,12 @@ __global__ __launch_bounds__(64) void k_task_bfs(int64_t n_leaves, TreeView T,
                                                  const int32_t *__restrict__ slot,
                                                  int32_t *__restrict__ count,
                                                  uint8_t *__restrict__ overflow,
-                                                 Task *__restrict__ task)
+                                                 Task *__restrict__ task,
+                                                 const uint8_t *__restrict__ only)
 {
     const int64_t I = blockIdx.x;
-    if (I >= n_leaves)
-        return;
+    if (I >= n_leaves || (only && !only[I]))
+        return;  // (only: the growth rebuild walks the marked leaves alone)
     constexpr bool COUNT = MODE == 0 || MODE == 2, WRITE = MODE != 0;
     if (!COUNT && overflow[I])
         return;
@@ -449,14 +520,15 @@ __global__ void k_slack_sizes(int64_t n_leaves, const int32_t *__restrict__ coun
 template <int MODE>
 static void walk_launch(int64_t nl, const TreeView &T, const double *org,
                         const int32_t *leaf_start, const int32_t *off, const int32_t *slot,
-                        int32_t *count, uint8_t *overflow, Task *task, hipStream_t s)
+                        int32_t *count, uint8_t *overflow, Task *task, hipStream_t s,
+                        const uint8_t *only = nullptr)
 {
     if (nl <= 65536)
         k_task_bfs<MODE, uint16_t><<<unsigned(nl), 64, 0, s>>>(nl, T, org, leaf_start, off, slot,
-                                                              count, overflow, task);
+                                                              count, overflow, task, only);
     else
         k_task_bfs<MODE, int32_t><<<unsigned(nl), 64, 0, s>>>(nl, T, org, leaf_start, off, slot,
-                                                             count, overflow, task);
+                                                             count, overflow, task, only);
 }
 
 size_t tasks_bytes(int64_t n)
@@ -472,7 +544,8 @@ void tasks_free(sphx_tasks *t)
 {
     if (!t)
         return;
-    void *ptrs[] = {t->off, t->task, t->count, t->radius, t->scan_tmp, t->overflow};
+    void *ptrs[] = {t->off, t->task, t->count, t->radius, t->scan_tmp, t->overflow,
+                    t->task_alt, t->off_alt, t->dirty};
     for (void *p : ptrs)
         dfree(p, t->stream);
     for (void *p : {(void *)t->order, (void *)t->okey, (void *)t->okey_out, (void *)t->oval,
@@ -681,8 +754,103 @@ sphx_status tasks_build(sphx_ctx *ctx, sphx_grid *g, const sphx_particles *in, h
         }
     }
     SPHX_TRY(leaf_order(t, nl, s));
+    t->symmetric = true;
     guard.keep = true;
     *out = t;
+    return SPHX_OK;
+}
+
+// The tree view of a grid with the periodic box of the context.
+static TreeView tree_view(const sphx_ctx *ctx, const sphx_grid *g)
+{
+    TreeView T;
+    T.lo = g->node_lo;
+    T.hi = g->node_hi;
+    T.r = g->node_r;
+    for (int l = 0; l < kMaxLevels; ++l) {
+        T.level_off[l] = l < g->n_levels ? g->level_off[l] : 0;
+        T.level_cnt[l] = l < g->n_levels ? g->level_cnt[l] : 0;
+    }
+    T.n_levels = g->n_levels;
+    for (int a = 0; a < 3; ++a)
+        T.L[a] = ctx->p.box[a];
+    T.periodic = ctx->p.periodic;
+    return T;
+}
+
+sphx_status tasks_grow(sphx_ctx *ctx, sphx_grid *g, const sphx_particles *in, hipStream_t s,
+                       sphx_tasks **out)
+{
+    sphx_tasks *t = *out;
+    const int64_t nl = g->n_leaves;
+    if (!t || t->grid != g || !t->slack_ok || nl == 0)
+        return tasks_build(ctx, g, in, s, out);
+    t->stream = s;
+    if (!t->off_alt) {
+        if (dmalloc((void **)&t->off_alt, (nl + 1) * sizeof(int32_t), s) != hipSuccess ||
+            dmalloc((void **)&t->dirty, (nl + 1) * sizeof(uint8_t), s) != hipSuccess) {
+            set_error("sphx_tasks_build: out of device memory (growth rebuild)");
+            return SPHX_E_OOM;
+        }
+    }
+    const float scale = float(ctx->p.gamma_k * (1.0 + ctx->p.skin));
+    k_leaf_radius_grow<<<unsigned(nl), 64, 0, s>>>(nl, g->leaf_start, g->hs, scale, g->node_r,
+                                                   t->radius, t->overflow, t->dirty);
+    SPHX_HIP(hipGetLastError());
+    for (int l = 0; l + 1 < g->n_levels; ++l) {
+        int64_t up = g->level_cnt[l + 1];
+        k_tree_radius<<<blocks(up, 128), 128, 0, s>>>(up, g->level_cnt[l],
+                                                        g->node_r + g->level_off[l],
+                                                        g->node_r + g->level_off[l + 1]);
+        SPHX_HIP(hipGetLastError());
+    }
+    const TreeView T = tree_view(ctx, g);
+    // the marked leaves: one walk into their slots, counting; the serial
+    // count for those whose frontier overflowed; the others keep theirs
+    walk_launch<2>(nl, T, g->leaf_org, g->leaf_start, t->off, t->soff, t->count, t->overflow,
+                   t->slack, s, t->dirty);
+    SPHX_HIP(hipGetLastError());
+    k_task_count<<<blocks(nl, 64), 64, 0, s>>>(nl, T, t->overflow, t->count);
+    SPHX_HIP(hipGetLastError());
+    k_keep_counts<<<blocks(nl + 1, 256), 256, 0, s>>>(nl, t->dirty, t->off, t->count);
+    SPHX_HIP(hipGetLastError());
+    size_t tmp = t->scan_tmp_bytes;
+    SPHX_HIP(rocprim::exclusive_scan(t->scan_tmp, tmp, t->count, t->off_alt, 0, size_t(nl + 1),
+                                     rocprim::plus<int32_t>(), s));
+    int32_t *h_total = reinterpret_cast<int32_t *>(ctx->h_pinned + kPinnedBytes - 64);
+    SPHX_HIP(hipMemcpyAsync(h_total, t->off_alt + nl, sizeof(int32_t), hipMemcpyDeviceToHost,
+                            s));
+    SPHX_HIP(wait_stream(ctx, s));
+    const int32_t total = *h_total;
+    if (total < 0) {
+        set_error("sphx_tasks_build: task count overflow");
+        return SPHX_E_INVALID;
+    }
+    if (total > t->cap_alt) {
+        dfree(t->task_alt, s);
+        t->task_alt = nullptr;
+        t->cap_alt = 0;
+        const int64_t cap = int64_t(total) + total / 4 + 64;
+        SPHX_HIP(dmalloc((void **)&t->task_alt, size_t(cap) * sizeof(Task), s));
+        t->cap_alt = cap;
+    }
+    k_copy_grown<<<unsigned(nl), 64, 0, s>>>(nl, t->dirty, t->overflow, t->off, t->off_alt,
+                                             t->soff, t->count, t->task, t->slack, t->task_alt);
+    SPHX_HIP(hipGetLastError());
+    // marked leaves over their slot: walked again straight into the list;
+    // those with an overflowed frontier: the serial fill
+    walk_launch<3>(nl, T, g->leaf_org, g->leaf_start, t->off_alt, t->soff, t->count,
+                   t->overflow, t->task_alt, s, t->dirty);
+    SPHX_HIP(hipGetLastError());
+    k_task_fill<<<blocks(nl, 64), 64, 0, s>>>(nl, T, g->leaf_org, g->leaf_start, t->overflow,
+                                              t->off_alt, t->task_alt);
+    SPHX_HIP(hipGetLastError());
+    std::swap(t->task, t->task_alt);
+    std::swap(t->cap, t->cap_alt);
+    std::swap(t->off, t->off_alt);
+    t->n_tasks = total;
+    SPHX_TRY(leaf_order(t, nl, s));
+    t->symmetric = false;
     return SPHX_OK;
 }
 

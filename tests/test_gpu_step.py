@@ -105,6 +105,36 @@ def test_step_is_bitwise_repeatable():
     assert np.array_equal(a["sums"], b["sums"])
 
 
+@pytest.mark.parametrize("shape", [{}, {"density_waves": 2, "force_waves": 2},
+                                   {"density_balance": 2}])
+def test_step_does_not_depend_on_the_task_list_it_starts_from(shape):
+    """A task list built for larger h (a superset: cells beyond every
+    receiver's reach) and one built for the step's own h give the same bits:
+    the growth rebuilds keep the lists of the leaves that did not grow, and
+    the loops' sums must not move with a list's length."""
+    import torch
+    from paper_2305_13380_amd import sphx
+    ps = inputs.lognormal_box(16, 6000, 2.0, 15)
+    res = []
+    for grow in (1.0, 1.4):
+        ctx = sphx.Context(sphx.default_params(**shape), 0)
+        dp = sphx.DeviceParticles.from_set(ps)
+        dp.t["h"].mul_(grow)
+        grid = sphx.Grid(ctx, dp)
+        tasks = sphx.Tasks(ctx, grid, dp)
+        dp.t["h"].copy_(torch.from_numpy(ps.h).cuda())
+        out = sphx.Outputs(ps.n)
+        st, info = sphx.step(ctx, grid, tasks, dp, out)
+        torch.cuda.synchronize()
+        assert st >= 0 and info.unconverged == 0
+        r = {k: v.cpu().numpy() for k, v in {**out.d, **out.g, **out.f}.items()}
+        r["h"] = dp.t["h"].cpu().numpy()
+        r["sums"] = out.sums.cpu().numpy()
+        res.append(r)
+    for k in res[0]:
+        assert np.array_equal(res[0][k], res[1][k], equal_nan=True), k
+
+
 def test_step_rebuilds_tasks_when_h_grows():
     ps = inputs.lattice_box(14, 3, u="logu")
     ps.h *= np.float32(0.45)  # the iteration must more than double h
