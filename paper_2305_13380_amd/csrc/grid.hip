@@ -316,6 +316,14 @@ __global__ void k_tree_level(int64_t cnt_up, int64_t cnt_dn, const double *__res
 
 // Start of an h iteration: mark the active particles and copy h into sorted
 // order (with mark == nullptr only the copy).
+// The inverse of the sort's permutation: caller index -> sorted index.
+__global__ void k_invert(int64_t n, const int32_t *__restrict__ perm, int32_t *__restrict__ inv)
+{
+    const int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (s < n)
+        inv[perm[s]] = int32_t(s);
+}
+
 __global__ void k_iter_reset(int64_t n, const int32_t *__restrict__ perm,
                              const uint8_t *__restrict__ active, const float *__restrict__ h,
                              uint8_t *__restrict__ need, float *__restrict__ hs,
@@ -464,6 +472,10 @@ sphx_status grid_build(sphx_ctx *ctx, const sphx_particles *in, hipStream_t s, s
     SPHX_HIP(dmalloc(&g->sort_tmp, g->sort_tmp_bytes, s));
     SPHX_HIP(rocprim::radix_sort_pairs(g->sort_tmp, tmp, g->keys_in, g->keys, g->idx_in, g->perm,
                                        size_t(n), 0, 63, s));
+    // the sort's input indices are not needed again: the inverse goes there
+    g->inv = g->idx_in;
+    k_invert<<<blocks(n, 256), 256, 0, s>>>(n, g->perm, g->inv);
+    SPHX_HIP(hipGetLastError());
 
     const int cap = P.leaf_max;
     k_leaf_flags<<<blocks(n, 256), 256, 0, s>>>(n, g->keys, cap, g->flags);

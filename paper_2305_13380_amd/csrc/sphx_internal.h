@@ -121,6 +121,7 @@ struct sphx_grid {
     // per sorted particle
     uint64_t *keys;     // sorted Morton keys
     int32_t *perm;      // sorted index -> caller index
+    int32_t *inv;       // caller index -> sorted index (the sort's input array, reused)
     int32_t *leaf_of;   // sorted index -> leaf
     float4 *q0;         // x, y, z relative to the leaf origin; m
     float4 *q1;         // vx, vy, vz, u

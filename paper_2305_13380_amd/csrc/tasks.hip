@@ -849,7 +849,8 @@ sphx_status tasks_grow(sphx_ctx *ctx, sphx_grid *g, const sphx_particles *in, hi
     std::swap(t->cap, t->cap_alt);
     std::swap(t->off, t->off_alt);
     t->n_tasks = total;
-    SPHX_TRY(leaf_order(t, nl, s));
+    // (the launch order of the last full build stays: it orders by work,
+    // which the few walked leaves hardly move)
     t->symmetric = false;
     return SPHX_OK;
 }
