@@ -232,8 +232,11 @@ sphx_status sphx_params_set_kernel(sphx_params *p, int32_t kernel);
 sphx_status sphx_ctx_create(const sphx_params *p, int hip_device, sphx_ctx **out);
 void sphx_ctx_destroy(sphx_ctx *ctx);
 
-/* Upper bound of the device bytes a grid plus its tasks take for n particles
- * (used to admit requests against an HBM budget). Host only, no device call. */
+/* Estimate of the device bytes a grid plus its tasks take for n particles
+ * (used to admit requests against an HBM budget): one leaf per leaf_max / 4
+ * particles with 96 tasks each, the task lists, the second list of the
+ * growth rebuilds and their slack layout included. Boxes clustered into far
+ * more tasks per particle take more. Host only, no device call. */
 size_t sphx_workspace_bytes(const sphx_params *p, int64_t n);
 
 /* Grid build (Section 2.2 cells, Section 9.1 binning): validates the inputs

@@ -272,7 +272,9 @@ size_t sphx_workspace_bytes(const sphx_params *p, int64_t n)
 {
     if (n < 0)
         return 0;
-    return grid_bytes(n) + tasks_bytes(n) + ((p && p->neighbour_lists == 0) ? 0 : lists_bytes(n));
+    const int leaf_max = (p && p->leaf_max > 0) ? p->leaf_max : 64;
+    return grid_bytes(n) + tasks_bytes(n, leaf_max) +
+           ((p && p->neighbour_lists == 0) ? 0 : lists_bytes(n));
 }
 
 sphx_status sphx_grid_build(sphx_ctx *ctx, const sphx_particles *in, void *stream,

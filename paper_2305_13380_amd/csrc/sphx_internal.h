@@ -271,7 +271,7 @@ sphx_status gravity_run(sphx_ctx *ctx, const sphx_particles *in, double G, doubl
 // Friends-of-friends groups over a grid and tasks built at search radius b.
 sphx_status fof_run(sphx_ctx *ctx, const sphx_particles *in, double b, int32_t *group,
                     int32_t *group_size, int64_t *d_counts, hipStream_t s);
-size_t tasks_bytes(int64_t n);
+size_t tasks_bytes(int64_t n, int leaf_max);
 
 // density.hip
 // The probe counters of a measurement build (SPHX_PROBE=1): lane slots of the

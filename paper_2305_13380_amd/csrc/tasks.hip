@@ -531,13 +531,18 @@ static void walk_launch(int64_t nl, const TreeView &T, const double *org,
                                                              count, overflow, task, only);
 }
 
-size_t tasks_bytes(int64_t n)
+size_t tasks_bytes(int64_t n, int leaf_max)
 {
-    // Budget ~40 tasks per leaf and one leaf per 16 particles, for the list
-    // and for the slack layout of the rebuilds, plus per-leaf arrays.
-    int64_t leaves = n / 16 + 1;
-    return size_t(leaves) * ((1 + kSlackFactor) * 40 * sizeof(Task) + 8 * sizeof(Task) + 4 * 4) +
-           (1 << 20);
+    // An estimate (the task count depends on the clustering): one leaf per
+    // leaf_max / 4 particles (at least 4) with 96 tasks each, held as the
+    // list (allocated with a quarter of headroom), the second list of the
+    // growth rebuilds (the same) and the slack layout (kSlackFactor tasks per
+    // task + 8 per leaf), plus the per-leaf arrays (offsets twice, counts,
+    // radius, order and its sort keys, flags).
+    const int64_t leaves = n / std::max(4, leaf_max / 4) + 1;
+    const int64_t per_leaf_tasks = 96;
+    const int64_t task_slots = 2 * (per_leaf_tasks * 5 / 4) + kSlackFactor * per_leaf_tasks + 8;
+    return size_t(leaves) * (size_t(task_slots) * sizeof(Task) + 48) + (1 << 20);
 }
 
 void tasks_free(sphx_tasks *t)
