@@ -280,7 +280,55 @@ def gravity_bench(params, dp, reps):
     return rec
 
 
-def step_leg(name, params, steps=5, warmup=1, flavour=None):
+def graph_slots(info, params):
+    """Captured pass slots for steps like the one `info` describes: its passes,
+    one more when it rebuilt its task list (the first pass of a step can meet
+    the previous step's list stale and is repeated), at most max_iter - 1."""
+    k = info.passes + (1 if info.task_rebuilds > 0 else 0)
+    return max(0, min(k, params.max_iter - 1, 64))
+
+
+def time_steps(params, dp, out, h0, k, n=3):
+    """Average HIP-event time of n whole steps with graph_passes = k (after one
+    untimed step on fresh grid and tasks, which also captures the graph)."""
+    import torch
+    from paper_2305_13380_amd import sphx
+    p = type(params).from_buffer_copy(params)
+    p.graph_passes = k
+    ctx = sphx.Context(p, 0)
+    grid = sphx.Grid(ctx, dp)
+    tasks = sphx.Tasks(ctx, grid, dp)
+    dp.t["h"].copy_(h0)
+    sphx.step(ctx, grid, tasks, dp, out)
+    stream = torch.cuda.current_stream()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(n):
+        dp.t["h"].copy_(h0)
+        sphx.step(ctx, grid, tasks, dp, out)
+    b.record(stream)
+    torch.cuda.synchronize()
+    tasks.close()
+    grid.close()
+    ctx.close()
+    return a.elapsed_time(b) / n
+
+
+def choose_graph(params, dp, out, h0, info):
+    """Captured pass slots for the timed steps (graph_slots of a warm-up
+    step's info), kept only if the captured step is faster than pass by pass
+    on a few steps (on a box whose step needs no rebuild the gated rebuild
+    kernels of every slot can cost more than the per-pass readbacks they
+    save). Returns (slots, {"captured_ms", "pass_by_pass_ms"})."""
+    k = graph_slots(info, params)
+    if k == 0:
+        return 0, None
+    t_g = time_steps(params, dp, out, h0, k)
+    t_0 = time_steps(params, dp, out, h0, 0)
+    return (k if t_g < t_0 else 0), {"slots": k, "captured_ms": t_g, "pass_by_pass_ms": t_0}
+
+
+def step_leg(name, params, steps=5, warmup=1, flavour=None, graph=-1):
     """One more workload of the step, timed like the headline one (HIP events
     on the stream around `steps` whole steps from the generator's h, inputs
     resident): the Sedov box and the large box with its active subset (after
@@ -320,24 +368,43 @@ def step_leg(name, params, steps=5, warmup=1, flavour=None):
         params.neighbour_lists = 0
     dp = sphx.DeviceParticles.from_set(ps, "cuda:0")
     out = sphx.Outputs(ps.n, "cuda:0")
-    ctx = sphx.Context(params, 0)
     if dp.t["active"] is not None:
         act = dp.t["active"]
         h_guess = dp.t["h"].clone()
         dp.t["active"] = None
-        g1 = sphx.Grid(ctx, dp)
-        k1 = sphx.Tasks(ctx, g1, dp)
-        sphx.step(ctx, g1, k1, dp, out)
+        c1 = sphx.Context(params, 0)
+        g1 = sphx.Grid(c1, dp)
+        k1 = sphx.Tasks(c1, g1, dp)
+        sphx.step(c1, g1, k1, dp, out)
         k1.close()
         g1.close()
+        c1.close()
         dp.t["active"] = act
         dp.t["h"].copy_(torch.where(act.bool(), h_guess, dp.t["h"]))
     h0 = dp.t["h"].clone()
+    # the warm-up pass by pass, then the timed steps captured (graph_slots)
+    p0 = type(params).from_buffer_copy(params)
+    p0.graph_passes = 0
+    ctx0 = sphx.Context(p0, 0)
+    grid = sphx.Grid(ctx0, dp)
+    tasks = sphx.Tasks(ctx0, grid, dp)
+    for _ in range(max(warmup, 1)):
+        dp.t["h"].copy_(h0)
+        info = sphx.step(ctx0, grid, tasks, dp, out)[1]
+    tasks.close()
+    grid.close()
+    ctx0.close()
+    params = type(params).from_buffer_copy(params)
+    choice = None
+    if graph < 0:
+        params.graph_passes, choice = choose_graph(params, dp, out, h0, info)
+    else:
+        params.graph_passes = graph
+    ctx = sphx.Context(params, 0)
     grid = sphx.Grid(ctx, dp)
     tasks = sphx.Tasks(ctx, grid, dp)
-    for _ in range(warmup):
-        dp.t["h"].copy_(h0)
-        sphx.step(ctx, grid, tasks, dp, out)
+    dp.t["h"].copy_(h0)
+    sphx.step(ctx, grid, tasks, dp, out)  # (captures the graph)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -358,7 +425,8 @@ def step_leg(name, params, steps=5, warmup=1, flavour=None):
            "flavour": flavour or "energy", "ms_per_step": ms,
            "interactions_per_s": (n_dens + n_force) / (ms / 1e3), "n_dens": n_dens,
            "n_force": n_force, "density_passes": infos[-1].passes,
-           "task_rebuilds_per_step": infos[-1].task_rebuilds, "steps": steps,
+           "task_rebuilds_per_step": infos[-1].task_rebuilds,
+           "graph_passes": int(params.graph_passes), "graph_choice": choice, "steps": steps,
            "momentum_err_rel": float(np.abs(sums[:3]).max() / max(sums[4], 1e-300)),
            "timed": "HIP events on the stream around whole steps from the generator's h "
                     "(h iteration with task rebuilds, ghost, force, FP64 sums); inputs "
@@ -534,8 +602,9 @@ def main():
     ap.add_argument("--cpu-receivers", type=int, default=2048)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--graph", type=int, default=-1, metavar="K",
-                    help="captured passes per step (HIP graph); 0: pass by pass; "
-                         "-1 (default): the passes of a warm-up step if it needed no task rebuild")
+                    help="captured pass slots per step (HIP graph, task rebuilds inside); "
+                         "0: pass by pass; -1 (default): the passes of a warm-up step, one "
+                         "more if it rebuilt its task list (also for the step legs)")
     ap.add_argument("--skin", type=float, default=0.1,
                     help="relative enlargement of the task search radii")
     ap.add_argument("--leaf-max", type=int, default=64,
@@ -658,11 +727,14 @@ def main():
     tasksp = sphx.Tasks(ctxp, gridp, dp)
     for w, info in enumerate(run_steps(ctxp, gridp, tasksp, max(args.warmup, 1))):
         log("bench: warmup %d: passes=%d rebuilds=%d" % (w, info.passes, info.task_rebuilds))
-    # Captured passes: as many as the step needs when it needs no task rebuild
-    # (a rebuild ends the captured part early), else pass by pass.
+    # Captured passes: as many slots as the warm-up step's passes, plus one for
+    # a first pass that meets the previous step's task list stale (task
+    # rebuilds run inside the graph; a step that needs more goes on pass by
+    # pass), kept if a few captured steps beat a few pass-by-pass ones.
     graph_k = args.graph
+    graph_choice = None
     if graph_k < 0:
-        graph_k = info.passes if info.task_rebuilds == 0 else 0
+        graph_k, graph_choice = choose_graph(params, dp, out, h0, info)
     torch.cuda.synchronize()
     sphx.probe_read(ctxp, clear=True)
     ctxp.profile(True)
@@ -769,7 +841,8 @@ def main():
                    "list_builds_per_step": info.list_builds,
                    "list_fallback_receiver_passes": info.list_fallback,
                    "list_entries": info.list_entries, "loop_shapes": shapes,
-                   "graph_passes": graph_k, "leaf_max": args.leaf_max, "skin": args.skin,
+                   "graph_passes": graph_k, "graph_choice": graph_choice,
+                   "leaf_max": args.leaf_max, "skin": args.skin,
                    "momentum_err_rel": mom, "energy_err_rel": en},
         "roofline": {"bound": "alu", "kernel": kern, "achieved": achieved,
                      "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
@@ -794,12 +867,14 @@ def main():
     del grid, tasks, out
     if not args.no_legs and args.config == "clustered":
         line["other_workloads"] = {
-            "sedov": step_leg("sedov", params, steps=10),
-            "large": step_leg("large", params, steps=3),
-            "clustered_entropy": step_leg("clustered", params, steps=5, flavour="entropy"),
+            "sedov": step_leg("sedov", params, steps=10, graph=args.graph),
+            "large": step_leg("large", params, steps=3, graph=args.graph),
+            "clustered_entropy": step_leg("clustered", params, steps=5, flavour="entropy",
+                                          graph=args.graph),
             "clustered_pressure_energy": step_leg("clustered", params, steps=5,
-                                                  flavour="pressure_energy"),
-            "clustered_anarchy_pu": step_leg("clustered", params, steps=5, flavour="anarchy_pu"),
+                                                  flavour="pressure_energy", graph=args.graph),
+            "clustered_anarchy_pu": step_leg("clustered", params, steps=5, flavour="anarchy_pu",
+                                             graph=args.graph),
         }
         line["sphenix_run"] = sphenix_leg(params)
     if not args.no_fof:

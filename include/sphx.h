@@ -86,12 +86,15 @@ typedef struct sphx_params {
     int32_t density_waves;
     int32_t force_tile;
     int32_t force_waves;
-    /* sphx_step: > 0 captures the first graph_passes passes of the h iteration
-     * and the force pass as one HIP graph (replayed while the handles and
-     * arrays stay the same; one readback instead of one per pass); the step
-     * continues pass by pass when the iteration needs more passes or a task
-     * rebuild. Results are identical to graph_passes = 0 (default 0; not
-     * combined with neighbour_lists). */
+    /* sphx_step: > 0 captures up to graph_passes passes of the h iteration
+     * (at most max_iter - 1: the final pass runs uncaptured), the task
+     * rebuilds between them (in place, decided on the device), the full
+     * rebuild before the force pass and the force pass as one HIP graph
+     * (replayed while the handles and arrays stay the same; one readback
+     * instead of one per pass). The step continues pass by pass when the
+     * iteration needs more passes, or after a rebuild that outgrew the task
+     * list's layout. Results are identical to graph_passes = 0 (default 0;
+     * not combined with neighbour_lists). */
     int32_t graph_passes;
     /* Density loop: 1 spreads each compute round's pair work evenly over the
      * wave's lanes (lists cut into chunks of one receiver each), 0 (default)
@@ -204,6 +207,10 @@ typedef struct sphx_step_info {
     int64_t pairs_cellpair;    /* density interactions (self excluded) computed by the
                                   cell-pair loop over all passes */
     int64_t pairs_list;        /* ... and by the neighbour-list loop */
+    int32_t captured_passes;   /* passes (of `passes`) run inside the captured graph
+                                  (graph_passes > 0); the rest ran pass by pass */
+    int32_t task_relayouts;    /* rebuilds (of task_rebuilds) that laid the task
+                                  slots out anew: a leaf outgrew its slot */
 } sphx_step_info;
 
 typedef struct sphx_ctx sphx_ctx;
@@ -234,9 +241,9 @@ void sphx_ctx_destroy(sphx_ctx *ctx);
 
 /* Estimate of the device bytes a grid plus its tasks take for n particles
  * (used to admit requests against an HBM budget): one leaf per leaf_max / 4
- * particles with 96 tasks each, the task lists, the second list of the
- * growth rebuilds and their slack layout included. Boxes clustered into far
- * more tasks per particle take more. Host only, no device call. */
+ * particles with 96 tasks each, held in their slots (four times the count +
+ * 8 per leaf). Boxes clustered into far more tasks per particle take more.
+ * Host only, no device call. */
 size_t sphx_workspace_bytes(const sphx_params *p, int64_t n);
 
 /* Grid build (Section 2.2 cells, Section 9.1 binning): validates the inputs
@@ -260,9 +267,12 @@ void sphx_grid_destroy(sphx_grid *grid);
  * leaves (with periodic shift) whose bounding box lies within
  * max(H_i-leaf, H_j-leaf) * (1 + skin) of its own, H taken from the current
  * h. Each task carries the FP32 offset between the two leaf origins, formed
- * in FP64. Synchronises the stream (reads back the task count). *out is
- * released with sphx_tasks_destroy (on the stream of its last build, which must
- * still exist). Calling it again with an existing *out rebuilds in place. */
+ * in FP64. Each leaf's tasks sit in a slot of its own, sized four times its
+ * task count at the last layout + 8; a rebuild walks every leaf into its slot
+ * and lays the slots out anew only when a leaf outgrew its own. Synchronises
+ * the stream (reads back the task count). *out is released with
+ * sphx_tasks_destroy (on the stream of its last build, which must still
+ * exist). Calling it again with an existing *out rebuilds in place. */
 sphx_status sphx_tasks_build(sphx_ctx *ctx, sphx_grid *grid, const sphx_particles *in,
                              void *stream, sphx_tasks **out);
 void sphx_tasks_destroy(sphx_tasks *tasks);
@@ -337,8 +347,10 @@ sphx_status sphx_force_noalloc(sphx_ctx *ctx, const sphx_grid *grid, const sphx_
  * list is rebuilt in place whenever an h outgrows its task radius, and a
  * density pass that ran on a stale list is repeated), then the force pass and
  * the FP64 sums. *tasks is built first if NULL (release it with
- * sphx_tasks_destroy). Synchronises the stream once per density pass. *info
- * may be NULL. Warnings: W_NOT_CONVERGED, W_H_CLAMPED. */
+ * sphx_tasks_destroy). Synchronises the stream once per density pass run
+ * pass by pass and once per task rebuild there, and once for the captured
+ * part (graph_passes). *info may be NULL. Warnings: W_NOT_CONVERGED,
+ * W_H_CLAMPED. */
 sphx_status sphx_step(sphx_ctx *ctx, sphx_grid *grid, sphx_tasks **tasks, sphx_particles *in,
                       sphx_density_out *dens, sphx_ghost_out *gst, sphx_force_out *out,
                       double *d_sums6, void *stream, sphx_step_info *info);

@@ -572,6 +572,7 @@ static sphx_status step_run(sphx_ctx *ctx, sphx_grid *grid, sphx_tasks **tasks,
     memset(&local, 0, sizeof(local));
     if (!*tasks)
         SPHX_TRY(tasks_build(ctx, grid, in, s, tasks));
+    const int64_t relayouts0 = (*tasks)->relayouts;
     unsigned char *h_buf = ctx->h_pinned;  // kStepCounterBytes of it
     memset(h_buf, 0, kStepCounterBytes);
     int32_t h_counters[kStepCounters] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -582,15 +583,26 @@ static sphx_status step_run(sphx_ctx *ctx, sphx_grid *grid, sphx_tasks **tasks,
     const int max_iter = ctx->p.max_iter;
     bool want_lists = ctx->p.neighbour_lists != 0;
     int pass = 0;
-    const int graph_passes = std::min(ctx->p.graph_passes, max_iter);
+    // (no captured pass is the final one of max_iter: that one runs here)
+    const int graph_passes = std::min(ctx->p.graph_passes, max_iter - 1);
     if (graph_passes > 0 && !want_lists && grid->n_leaves > 0) {
-        bool done = false, stale = false, rebuild = false;
+        bool done = false, relayout = false, force_pending = false;
         SPHX_TRY(step_graph_run(ctx, grid, *tasks, in, dens, gst, out, d_sums6, graph_passes, s,
-                                &local, &pass, &done, &stale, &rebuild));
-        if (done) {
+                                &local, &pass, &done, &relayout, &force_pending));
+        local.captured_passes = pass;
+        if (relayout) {
+            // a leaf outgrew its slot inside the graph: a new layout
+            SPHX_TRY(tasks_build(ctx, grid, in, s, tasks));
+            local.task_rebuilds++;
+        }
+        if (force_pending)
+            SPHX_TRY(force_launch(ctx, grid, *tasks, in, dens, gst, out, d_sums6, s, nullptr,
+                                  true));
+        if (done || force_pending) {
             local.passes = pass;
             local.n_leaves = grid->n_leaves;
             local.n_tasks = (*tasks)->n_tasks;
+            local.task_relayouts = int32_t((*tasks)->relayouts - relayouts0);
             if (info)
                 *info = local;
             sphx_status w = SPHX_OK;
@@ -600,11 +612,8 @@ static sphx_status step_run(sphx_ctx *ctx, sphx_grid *grid, sphx_tasks **tasks,
                 w |= SPHX_W_H_CLAMPED;
             return w;
         }
-        // The iteration goes on pass by pass from the state the graph left.
-        if (stale || rebuild) {
-            SPHX_TRY(tasks_grow(ctx, grid, in, s, tasks));
-            local.task_rebuilds++;
-        }
+        // The iteration goes on pass by pass from the state the graph left
+        // (its last slot rebuilt the list if that pass asked for it).
         unsigned long long u[2] = {(unsigned long long)local.pairs_cellpair,
                                    (unsigned long long)local.pairs_list};
         memcpy(h_buf + kStepUnitsOffset, u, sizeof(u));
@@ -694,6 +703,7 @@ static sphx_status step_run(sphx_ctx *ctx, sphx_grid *grid, sphx_tasks **tasks,
     SPHX_TRY(force_launch(ctx, grid, *tasks, in, dens, gst, out, d_sums6, s, nullptr, true));
     local.n_leaves = grid->n_leaves;
     local.n_tasks = (*tasks)->n_tasks;
+    local.task_relayouts = int32_t((*tasks)->relayouts - relayouts0);
     if (info)
         *info = local;
     sphx_status w = SPHX_OK;

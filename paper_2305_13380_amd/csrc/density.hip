@@ -144,7 +144,8 @@ __global__ __launch_bounds__(64 * NW) void k_density(
     const int32_t *__restrict__ leaf_start,
     const int32_t *__restrict__ perm, const float4 *__restrict__ q0,
     const float4 *__restrict__ q1, const uint8_t *__restrict__ need, const float *__restrict__ hs,
-    const float *__restrict__ radius, const int32_t *__restrict__ toff,
+    const float *__restrict__ radius, const int32_t *__restrict__ tbeg,
+    const int32_t *__restrict__ tend,
     const Task *__restrict__ task, const float4 *__restrict__ ext, float gamma_k, float far,
     const float *__restrict__ lrad, DensOut o, int32_t *__restrict__ counters,
     const int32_t *__restrict__ skip)
@@ -452,7 +453,7 @@ __global__ __launch_bounds__(64 * NW) void k_density(
     // J mod NW = w. A split by position would move with the list's length,
     // and a list that also holds cells beyond every receiver's reach (one
     // kept through growth rebuilds) would then give other partial sums.
-    const int32_t ta = toff[L], t_end = toff[L + 1];
+    const int32_t ta = tbeg[L], t_end = tend[L];
     for (int32_t tb = ta; tb < t_end; tb += 64) {
         const int nb = min(64, t_end - tb);
         TaskRegs tr;
@@ -559,7 +560,8 @@ __global__ __launch_bounds__(64) void k_density_grp(
     const int32_t *__restrict__ leaf_start, const int32_t *__restrict__ perm,
     const float4 *__restrict__ q0, const float4 *__restrict__ q1,
     const uint8_t *__restrict__ need, const float *__restrict__ hs,
-    const float *__restrict__ radius, const int32_t *__restrict__ toff,
+    const float *__restrict__ radius, const int32_t *__restrict__ tbeg,
+    const int32_t *__restrict__ tend,
     const Task *__restrict__ task, const float4 *__restrict__ ext, float gamma_k, float far,
     DensOut o, int32_t *__restrict__ counters, const int32_t *__restrict__ skip)
 {
@@ -759,7 +761,7 @@ __global__ __launch_bounds__(64) void k_density_grp(
         nc += tot;
     };
 
-    const int32_t ta = toff[L], tn = toff[L + 1] - ta;
+    const int32_t ta = tbeg[L], tn = tend[L] - ta;
     for (int32_t tb = ta; tb < ta + tn; tb += 64) {
         const int nb = min(64, ta + tn - tb);
         TaskRegs tr;
@@ -824,7 +826,8 @@ __global__ __launch_bounds__(256) void k_dens_list(
     int64_t n, int64_t nwg_padded, const uint8_t *__restrict__ need,
     const float *__restrict__ hs, const float *__restrict__ lrad,
     const int32_t *__restrict__ leaf_of, const int32_t *__restrict__ perm,
-    const int32_t *__restrict__ toff, const Task *__restrict__ task,
+    const int32_t *__restrict__ tbeg,
+    const int32_t *__restrict__ tend, const Task *__restrict__ task,
     const float4 *__restrict__ q0, const float4 *__restrict__ q1,
     const int32_t *__restrict__ lcnt, const int64_t *__restrict__ lboff,
     const uint32_t *__restrict__ lst, float gamma_k, DensOut o)
@@ -846,7 +849,7 @@ __global__ __launch_bounds__(256) void k_dens_list(
     const float H = gamma_k * hi;
     const float H2 = act ? H * H : -1.0f;
     const float invH = fast_rcp(H);
-    const int32_t ta = act ? toff[leaf_of[s]] : 0;  // task 0 exists whenever n > 0
+    const int32_t ta = act ? tbeg[leaf_of[s]] : 0;  // task 0 exists whenever n > 0
     const uint32_t *my = lst + lboff[b] + lane;
     const float4 *thalf = reinterpret_cast<const float4 *>(task) + 1;  // stride 2
 
@@ -944,8 +947,8 @@ static void density_shapes(int tile, int waves, int mode, int64_t nbp, const sph
 #define SPHX_DENSITY_LAUNCH(CAP_, NW_, BAL_)                                                   \
     k_density<CAP_, NW_, BAL_, K, PE><<<unsigned(nbp), 64 * NW_, 0, s>>>(                         \
         g->n_leaves, nbp, t->order, g->leaf_start, g->perm, g->q0, g->q1, g->need, g->hs,      \
-        t->radius, t->off, t->task, g->leaf_ext, float(ctx->p.gamma_k), far, lr, dout,        \
-        counters, skip)
+        t->radius, t->slot, t->end, t->task, g->leaf_ext, float(ctx->p.gamma_k), far, lr,      \
+        dout, counters, skip)
 #define SPHX_DENSITY_TILES(NW_, BAL_)                                                          \
     do {                                                                                       \
         if (tile == 64)                                                                        \
@@ -966,8 +969,8 @@ static void density_shapes(int tile, int waves, int mode, int64_t nbp, const sph
 #define SPHX_DENSITY_GRP(CAP_)                                                                 \
     k_density_grp<CAP_, K><<<unsigned(nbp), 64, 0, s>>>(                                      \
         g->n_leaves, nbp, t->order, g->leaf_start, g->perm, g->q0, g->q1, g->need, g->hs,      \
-        t->radius, t->off, t->task, g->leaf_ext, float(ctx->p.gamma_k), far, dout, counters,   \
-        skip)
+        t->radius, t->slot, t->end, t->task, g->leaf_ext, float(ctx->p.gamma_k), far, dout,    \
+        counters, skip)
             if (tile == 64)
                 SPHX_DENSITY_GRP(64);
             else if (tile == 128)
@@ -1028,7 +1031,7 @@ sphx_status density_list_launch(const sphx_ctx *ctx, const sphx_grid *g, const s
     SPHX_HIP(ctx->prof->begin(2, s));
     SPHX_WITH_KERNEL(ctx->p.kernel,
                      (k_dens_list<KK><<<unsigned(nwgp), 256, 0, s>>>(
-                         g->n, nwgp, g->need, g->hs, g->lrad, g->leaf_of, g->perm, t->off,
+                         g->n, nwgp, g->need, g->hs, g->lrad, g->leaf_of, g->perm, t->slot, t->end,
                          t->task, g->q0, g->q1, g->lcnt, g->lboff, g->lst,
                          float(ctx->p.gamma_k), dens_out(ctx, g, o))));
     SPHX_HIP(hipGetLastError());

@@ -107,7 +107,8 @@ __global__ __launch_bounds__(64) void k_fof_link(int64_t n_leaves,
                                                 const double *__restrict__ y,
                                                 const double *__restrict__ z, double Lx,
                                                 double Ly, double Lz, int periodic, double b2,
-                                                const int32_t *__restrict__ toff,
+                                                const int32_t *__restrict__ tbeg,
+    const int32_t *__restrict__ tend,
                                                 const Task *__restrict__ task,
                                                 int32_t *__restrict__ parent,
                                                 unsigned long long *__restrict__ links)
@@ -124,7 +125,7 @@ __global__ __launch_bounds__(64) void k_fof_link(int64_t n_leaves,
     const double oix = org[3 * L], oiy = org[3 * L + 1], oiz = org[3 * L + 2];
     __shared__ double sx[kLeafMax], sy[kLeafMax], sz[kLeafMax];
     unsigned long long nl = 0;
-    const int32_t ta = toff[L], tb = toff[L + 1];
+    const int32_t ta = tbeg[L], tb = tend[L];
     for (int32_t t = ta; t < tb; ++t) {
         const Task tk = task[t];
         // no source after every receiver of this leaf: nothing to test
@@ -283,7 +284,8 @@ sphx_status fof_run(sphx_ctx *ctx, const sphx_particles *in, double b, int32_t *
     unsigned long long *groups = cnt, *links = cnt + 1;
     k_fof_link<<<unsigned(g->n_leaves), 64, 0, s>>>(
         g->n_leaves, g->leaf_start, g->leaf_org, g->perm, in->x, in->y, in->z, ctx->p.box[0],
-        ctx->p.box[1], ctx->p.box[2], ctx->p.periodic, b * b, t->off, t->task, parent, links);
+        ctx->p.box[1], ctx->p.box[2], ctx->p.periodic, b * b, t->slot, t->end, t->task, parent,
+        links);
     SPHX_HIP(hipGetLastError());
     k_fof_label<<<nb, kFofThreads, 0, s>>>(n, g->perm, parent, minc, size, groups);
     SPHX_HIP(hipGetLastError());

@@ -77,7 +77,8 @@ __global__ __launch_bounds__(64 * NW) void k_force(
     const int32_t *__restrict__ perm, const float4 *__restrict__ q0,
     const float4 *__restrict__ q1, const float2 *__restrict__ qa, const float4 *__restrict__ g0,
     const float4 *__restrict__ g1, const uint8_t *__restrict__ active,
-    const int32_t *__restrict__ toff, const Task *__restrict__ task,
+    const int32_t *__restrict__ tbeg,
+    const int32_t *__restrict__ tend, const Task *__restrict__ task,
     const float4 *__restrict__ ext, const float *__restrict__ hmax, float gamma_k, float beta,
     float far,
     float *__restrict__ o_ax, float *__restrict__ o_ay, float *__restrict__ o_az,
@@ -349,7 +350,7 @@ __global__ __launch_bounds__(64 * NW) void k_force(
 
     // This wave's share: the tasks of the source cells J with J mod NW = w
     // (a split that the list's length does not move).
-    const int32_t ta = toff[L], t_end = toff[L + 1];
+    const int32_t ta = tbeg[L], t_end = tend[L];
     for (int32_t tb = ta; tb < t_end; tb += 64) {
         const int nb = min(64, t_end - tb);
         TaskRegs tr;
@@ -612,8 +613,8 @@ static void force_shapes(int tile, int waves, int64_t nbp, const sphx_ctx *ctx,
 #define SPHX_FORCE_LAUNCH(CAP_, NW_)                                                           \
     k_force<CAP_, NW_, K, FLAV><<<unsigned(nbp), 64 * NW_, 0, s>>>(                               \
         g->n_leaves, nbp, t->order, g->leaf_start, g->perm, g->q0, g->q1, g->qa, g->g0, g->g1, \
-        in->active, t->off, t->task, g->leaf_ext, g->leaf_hmax, float(ctx->p.gamma_k),         \
-        float(ctx->p.beta_v), far, o->ax,                                                      \
+        in->active, t->slot, t->end, t->task, g->leaf_ext, g->leaf_hmax,                       \
+        float(ctx->p.gamma_k), float(ctx->p.beta_v), far, o->ax,                               \
         o->ay, o->az, o->du_dt, o->v_sig, o->nforce, fsum, gate, so, float(ctx->p.gamma_gas))
     if (waves == 1) {
         if (tile == 64)

@@ -25,7 +25,8 @@ __global__ __launch_bounds__(64) void k_gravity(int64_t n_leaves,
                                                const int32_t *__restrict__ leaf_start,
                                                const int32_t *__restrict__ perm,
                                                const float4 *__restrict__ q0,
-                                               const int32_t *__restrict__ toff,
+                                               const int32_t *__restrict__ tbeg,
+    const int32_t *__restrict__ tend,
                                                const Task *__restrict__ task,
                                                const float4 *__restrict__ ext, float H, float rp2,
                                                float inv2rs, float cdchi, float G,
@@ -57,7 +58,7 @@ __global__ __launch_bounds__(64) void k_gravity(int64_t n_leaves,
     hb.x = wave_maxf(hb.x);
     hb.y = wave_maxf(hb.y);
     hb.z = wave_maxf(hb.z);
-    const int32_t ta = toff[L], tb = toff[L + 1];
+    const int32_t ta = tbeg[L], tb = tend[L];
     for (int32_t t = ta; t < tb; ++t) {
         const Task tk = task[t];
         if (task_box_dist2(tk.ox, tk.oy, tk.oz, ext[tk.j], lo, hb) >= rp2)
@@ -159,13 +160,13 @@ sphx_status gravity_run(sphx_ctx *ctx, const sphx_particles *in, double G, doubl
     SPHX_HIP(ctx->prof->begin(4, s));
     if (rs > 0.0)
         k_gravity<true><<<unsigned(g->n_leaves), 64, 0, s>>>(
-            g->n_leaves, g->leaf_start, g->perm, g->q0, t->off, t->task, g->leaf_ext, float(H),
-            rp2, inv2rs, cdchi, float(G), ax, ay, az, pot,
+            g->n_leaves, g->leaf_start, g->perm, g->q0, t->slot, t->end, t->task, g->leaf_ext,
+            float(H), rp2, inv2rs, cdchi, float(G), ax, ay, az, pot,
             reinterpret_cast<unsigned long long *>(d_pairs));
     else
         k_gravity<false><<<unsigned(g->n_leaves), 64, 0, s>>>(
-            g->n_leaves, g->leaf_start, g->perm, g->q0, t->off, t->task, g->leaf_ext, float(H),
-            rp2, inv2rs, cdchi, float(G), ax, ay, az, pot,
+            g->n_leaves, g->leaf_start, g->perm, g->q0, t->slot, t->end, t->task, g->leaf_ext,
+            float(H), rp2, inv2rs, cdchi, float(G), ax, ay, az, pot,
             reinterpret_cast<unsigned long long *>(d_pairs));
     SPHX_HIP(hipGetLastError());
     SPHX_HIP(ctx->prof->end(4, s));

@@ -47,7 +47,8 @@ __global__ __launch_bounds__(64) void k_gradient(
     int64_t n_leaves, const int32_t *__restrict__ leaf_start, const int32_t *__restrict__ perm,
     const float4 *__restrict__ q0, const float4 *__restrict__ q1,
     const float4 *__restrict__ st, const uint8_t *__restrict__ active,
-    const int32_t *__restrict__ toff, const Task *__restrict__ task,
+    const int32_t *__restrict__ tbeg,
+    const int32_t *__restrict__ tend, const Task *__restrict__ task,
     const float4 *__restrict__ ext, float gamma_k, float *__restrict__ lap_u,
     float *__restrict__ vc, float *__restrict__ avmax, float anarchy_gamma)
 {
@@ -86,7 +87,7 @@ __global__ __launch_bounds__(64) void k_gradient(
 
     __shared__ float4 sp[kLeafMax], sv[kLeafMax], ss[kLeafMax];
     float lap = 0.0f, vcm = 0.0f, avm = si.w;
-    const int32_t ta = toff[L], tb = toff[L + 1];
+    const int32_t ta = tbeg[L], tb = tend[L];
     for (int32_t t = ta; t < tb; ++t) {
         const Task tk = task[t];
         if (task_box_dist2(tk.ox, tk.oy, tk.oz, ext[tk.j], lo, hb) >= R2)
@@ -185,7 +186,8 @@ __global__ __launch_bounds__(kElemThreads) void k_dt_state(
 __global__ __launch_bounds__(64) void k_dt_limit(
     int64_t n_leaves, const int32_t *__restrict__ leaf_start, const int32_t *__restrict__ perm,
     const float4 *__restrict__ q0, const float4 *__restrict__ st,
-    const uint8_t *__restrict__ active, const int32_t *__restrict__ toff,
+    const uint8_t *__restrict__ active, const int32_t *__restrict__ tbeg,
+    const int32_t *__restrict__ tend,
     const Task *__restrict__ task, const float4 *__restrict__ ext, const float *__restrict__ hmax,
     float gamma_k, float delta, float *__restrict__ dt_out, int32_t *__restrict__ dt_min)
 {
@@ -218,7 +220,7 @@ __global__ __launch_bounds__(64) void k_dt_limit(
     __shared__ float4 sp[kLeafMax];
     __shared__ float2 ss[kLeafMax];
     float lim = si.y;
-    const int32_t ta = toff[L], tb = toff[L + 1];
+    const int32_t ta = tbeg[L], tb = tend[L];
     for (int32_t t = ta; t < tb; ++t) {
         const Task tk = task[t];
         // a source cell reaches the receivers within max(R, its largest H)
@@ -338,7 +340,7 @@ sphx_status gradient_launch(const sphx_ctx *ctx, sphx_grid *g, const sphx_tasks 
     SPHX_WITH_KERNEL(ctx->p.kernel,
                      (k_gradient<KK><<<unsigned(g->n_leaves), 64, 0, s>>>(
                          g->n_leaves, g->leaf_start, g->perm, g->q0, g->q1, g->g2, in->active,
-                         t->off, t->task, g->leaf_ext, float(ctx->p.gamma_k), lap_u, vc,
+                         t->slot, t->end, t->task, g->leaf_ext, float(ctx->p.gamma_k), lap_u, vc,
                          avmax,
                          ctx->p.flavour == SPHX_FLAVOUR_ANARCHY_PU ? float(ctx->p.gamma_gas)
                                                                    : 0.0f)));
@@ -379,7 +381,7 @@ sphx_status timestep_launch(const sphx_ctx *ctx, sphx_grid *g, const sphx_tasks 
                                                         g->leaf_hmax);
     SPHX_HIP(hipGetLastError());
     k_dt_limit<<<unsigned(g->n_leaves), 64, 0, s>>>(
-        g->n_leaves, g->leaf_start, g->perm, g->q0, g->g2, in->active, t->off, t->task,
+        g->n_leaves, g->leaf_start, g->perm, g->q0, g->g2, in->active, t->slot, t->end, t->task,
         g->leaf_ext, g->leaf_hmax, gk, float(delta), dt_out, mn);
     SPHX_HIP(hipGetLastError());
     return SPHX_OK;

@@ -25,7 +25,8 @@ __global__ __launch_bounds__(64) void k_list(
     int64_t n_leaves, int64_t nb_padded, const int32_t *__restrict__ order,
     const int32_t *__restrict__ leaf_start,
     const float4 *__restrict__ q0, const uint8_t *__restrict__ need, const float *__restrict__ hs,
-    const float *__restrict__ radius, const int32_t *__restrict__ toff,
+    const float *__restrict__ radius, const int32_t *__restrict__ tbeg,
+    const int32_t *__restrict__ tend,
     const Task *__restrict__ task, const float4 *__restrict__ ext, float list_scale,
     float *__restrict__ lrad,
     int32_t *__restrict__ lcnt, const int64_t *__restrict__ lboff, uint32_t *__restrict__ lst)
@@ -137,7 +138,7 @@ __global__ __launch_bounds__(64) void k_list(
         nc += tot;
     };
 
-    const int32_t ta = toff[L], tn = toff[L + 1] - ta;
+    const int32_t ta = tbeg[L], tn = tend[L] - ta;
     for (int32_t tb = 0; tb < tn; tb += 64) {
         const int nb = min(64, tn - tb);
         TaskRegs tr;
@@ -232,8 +233,8 @@ sphx_status list_build(const sphx_ctx *ctx, sphx_grid *g, const sphx_tasks *t, h
     const float scale = float(ctx->p.gamma_k * (1.0 + ctx->p.skin));
     SPHX_HIP(ctx->prof->begin(3, s));
     k_list<false><<<unsigned(nlp), 64, 0, s>>>(nl, nlp, t->order, g->leaf_start, g->q0, g->need,
-                                               g->hs, t->radius, t->off, t->task, g->leaf_ext,
-                                               scale, g->lrad, g->lcnt, nullptr, nullptr);
+                                               g->hs, t->radius, t->slot, t->end, t->task,
+                                               g->leaf_ext, scale, g->lrad, g->lcnt, nullptr, nullptr);
     SPHX_HIP(hipGetLastError());
     k_list_cap<<<unsigned((nb + 1 + 3) / 4), 256, 0, s>>>(n, nb, g->lcnt, g->lcap);
     SPHX_HIP(hipGetLastError());
@@ -259,8 +260,8 @@ sphx_status list_build(const sphx_ctx *ctx, sphx_grid *g, const sphx_tasks *t, h
     g->lst_total = total;
     SPHX_HIP(ctx->prof->begin(3, s));
     k_list<true><<<unsigned(nlp), 64, 0, s>>>(nl, nlp, t->order, g->leaf_start, g->q0, g->need,
-                                              g->hs, t->radius, t->off, t->task, g->leaf_ext,
-                                              scale, g->lrad, g->lcnt, g->lboff, g->lst);
+                                              g->hs, t->radius, t->slot, t->end, t->task,
+                                              g->leaf_ext, scale, g->lrad, g->lcnt, g->lboff, g->lst);
     SPHX_HIP(hipGetLastError());
     SPHX_HIP(ctx->prof->end(3, s));
     *ok = true;

@@ -70,6 +70,15 @@ constexpr int kStepCounters = 8;
 constexpr size_t kStepUnitsOffset = kStepCounters * sizeof(int32_t);
 constexpr size_t kStepCounterBytes = kStepUnitsOffset + 2 * sizeof(unsigned long long);
 
+// Device words of a task list: a walked leaf outgrew its slot (a new layout
+// is needed), the tasks held, the list is not symmetric (a growth rebuild
+// since the last full build), and the slot total of a new layout.
+constexpr int kTaskOutgrown = 0;
+constexpr int kTaskTotal = 1;
+constexpr int kTaskAsym = 2;
+constexpr int kTaskSlots = 3;
+constexpr int kTaskStateWords = 4;
+
 }  // namespace sphx
 
 namespace sphx {
@@ -179,13 +188,20 @@ struct sphx_grid {
 struct sphx_tasks {
     sphx_grid *grid;
     hipStream_t stream;  // the stream of the last build (its memory is freed there)
-    int64_t n_tasks;
-    int64_t cap;
-    int32_t *off;       // n_leaves + 1
-    sphx::Task *task;   // n_tasks
-    int32_t *count;     // n_leaves (scratch)
+    int64_t n_tasks;     // tasks held (host copy, as of the last build or captured step)
+    int64_t cap;         // task records allocated
+    int64_t relayouts;   // new slot layouts so far (the first build's included)
+    // Slot layout: leaf I's tasks are task[slot[I], end[I]), inside its slot
+    // [slot[I], slot[I + 1]) of kSlotFactor times its count at the last
+    // layout + 8 records. Rebuilds walk leaves straight into their slots.
+    int32_t *slot;      // n_leaves + 1
+    int32_t *end;       // n_leaves (+ 1: scratch of a new layout)
+    sphx::Task *task;   // cap
+    int32_t *count;     // n_leaves: tasks found by each leaf's last walk
     float *radius;      // per leaf: (1 + skin) * max H at build time
     uint8_t *overflow;  // per leaf: 1 when the serial walk built its list
+    uint8_t *dirty;     // per leaf: walked by the current rebuild
+    int64_t *state;     // kTaskStateWords device words (kTaskOutgrown, ...)
     void *scan_tmp;
     size_t scan_tmp_bytes;
     // Launch order of the per-leaf loops: the leaves are split into 8
@@ -199,25 +215,13 @@ struct sphx_tasks {
     void *sort_tmp;
     size_t sort_tmp_bytes;
     int64_t order_cap;
-    // Rebuilds in one tree walk: the walk writes each leaf's tasks into its
-    // slot of the `soff` layout (capacity 4 count + 8 from the last build)
-    // while counting them, and they are compacted into `task`; only
-    // the leaves over their capacity are walked a second time.
-    sphx::Task *slack;  // slack_cap
-    int32_t *soff;      // n_leaves + 1
-    int64_t slack_cap;
-    bool slack_ok;      // soff holds a layout for this grid
-    // Growth rebuilds (tasks_grow): only the leaves whose radius grew are
-    // walked again; the others keep their lists, copied into the second
-    // array, which then becomes the list. Such lists serve the density loop
-    // (each leaf's list covers its own radius) but can miss a pair that a
-    // grown neighbour's radius alone reaches: `symmetric` is false until the
-    // next full build, which the force pass requires.
-    sphx::Task *task_alt;  // cap_alt
-    int64_t cap_alt;
-    int32_t *off_alt;      // n_leaves + 1
-    uint8_t *dirty;        // n_leaves: walked again by the last growth rebuild
-    bool symmetric;        // every pair within max(R_I, R_J) of the radii is listed
+    // Growth rebuilds (tasks_grow) walk only the leaves whose radius grew;
+    // the others keep their lists. Such lists serve the density loop (each
+    // leaf's list covers its own radius) but can miss a pair that a grown
+    // neighbour's radius alone reaches: `symmetric` is false (device copy:
+    // state[kTaskAsym] = 1) until the next full build, which the force pass
+    // requires.
+    bool symmetric;
 };
 
 namespace sphx {
@@ -238,12 +242,23 @@ sphx_status tasks_build(sphx_ctx *ctx, sphx_grid *g, const sphx_particles *in, h
                         sphx_tasks **out);
 // Growth rebuild of an existing list for the h iteration's density passes:
 // the leaves whose (1 + skin) gamma_k max h grew beyond their list's radius
-// (and those the serial walk built) are walked again at the current radii,
-// the others keep their lists; leaves' radii never shrink here. Leaves the
-// list not symmetric (see sphx_tasks). Falls back to tasks_build when the
-// list has no slot layout to walk into.
+// are walked again at the current radii, in place, the others keep their
+// lists; leaves' radii never shrink here. Leaves the list not symmetric (see
+// sphx_tasks). Falls back to tasks_build when there is no layout to walk
+// into or a leaf outgrew its slot.
 sphx_status tasks_grow(sphx_ctx *ctx, sphx_grid *g, const sphx_particles *in, hipStream_t s,
                        sphx_tasks **out);
+// The in-place walks of a growth rebuild and of a full build, for a captured
+// step: no readback, no allocation; every kernel returns at once while *run
+// is zero. A leaf that outgrows its slot sets state[kTaskOutgrown] (its list
+// is then cut short: the caller must not run a loop on it before a
+// tasks_build). The list must have a layout (a tasks_build before).
+sphx_status tasks_grow_async(const sphx_ctx *ctx, sphx_grid *g, sphx_tasks *t,
+                             const int32_t *run, hipStream_t s);
+sphx_status tasks_full_async(const sphx_ctx *ctx, sphx_grid *g, sphx_tasks *t,
+                             const int32_t *run, hipStream_t s);
+// state[kTaskTotal] = the tasks the slots hold (capturable).
+sphx_status tasks_total_async(const sphx_grid *g, sphx_tasks *t, hipStream_t s);
 void tasks_free(sphx_tasks *t);
 // A grid and task list over every particle of `in` with a uniform search
 // radius (h = radius / gamma_k on a private array): the pair structure of
@@ -346,20 +361,22 @@ sphx_status drift_launch(const sphx_ctx *ctx, int64_t n, double *x, double *y, d
                          hipStream_t s);
 
 // graph.hip
-// Captured step: the h iteration's first `passes` passes and a gated force
-// pass as one HIP graph, replayed while the handles and arrays stay the same.
-// On return *done = true when the step is complete (converged, or finalised
-// by the last allowed pass) with force and sums computed; otherwise *pass
-// is the number of passes applied, *stale whether a pass met a stale task
-// list, *rebuild whether the last applied pass asked for a task rebuild, and
-// the caller continues the iteration from there.
+// Captured step: the h iteration's first `passes` passes (none of them the
+// final pass of max_iter), the task rebuilds between them, the full rebuild
+// before the force pass and a gated force pass as one HIP graph, replayed
+// while the handles and arrays stay the same. On return *done = true when
+// the step is complete (converged) with force and sums computed; otherwise
+// *pass is the number of passes applied, *relayout whether a leaf outgrew its
+// slot (the caller must tasks_build before the next loop), *force_pending
+// whether the iteration is complete and only the force pass is left (after
+// that tasks_build), and the caller continues the iteration from there.
 struct StepGraph;
 void step_graph_free(StepGraph *g);
 sphx_status step_graph_run(sphx_ctx *ctx, sphx_grid *grid, sphx_tasks *t, const sphx_particles *in,
                            const sphx_density_out *dens, const sphx_ghost_out *gst,
                            const sphx_force_out *out, double *sums6, int passes, hipStream_t s,
-                           sphx_step_info *info, int *pass, bool *done, bool *stale,
-                           bool *rebuild);
+                           sphx_step_info *info, int *pass, bool *done, bool *relayout,
+                           bool *force_pending);
 
 // Blocks are dealt round-robin to the 8 XCDs of the MI355X; remap so that each
 // XCD works on a contiguous range of leaves (which share neighbour data in

@@ -4,6 +4,17 @@
 // cell size matches the local search radius). The search walks a tree of
 // bounding boxes over the Morton-ordered leaves once per rebuild; the
 // neighbour loops themselves never walk it.
+//
+// Slot layout. Each leaf owns a fixed slot of the task array, sized
+// kSlotFactor times its task count at the last layout plus 8; its tasks are
+// task[slot[I], end[I]). A rebuild walks the leaves straight into their
+// slots, so it moves nothing, copies nothing and needs no readback to size
+// anything: only a leaf that outgrows its slot forces a new layout (counts,
+// a scan of the new slot sizes, one readback, a walk into the new slots).
+// The in-place walks are also what a captured step replays: the _async
+// entry points below launch the same kernels, each of which returns at once
+// when its device gate reads zero, and report an outgrown slot in a device
+// flag instead of handling it.
 #include <algorithm>
 #include <climits>
 
@@ -12,14 +23,30 @@
 
 #include "sphx_internal.h"
 
-// The count and fill kernels below must reach identical decisions: keep the
-// compiler from contracting the box-distance arithmetic differently in each.
+// The walks below must reach identical decisions in every mode and in the
+// serial form: keep the compiler from contracting the box-distance
+// arithmetic differently in each.
 #pragma clang fp contract(off)
 
 namespace sphx {
 namespace {
 
 inline unsigned blocks(int64_t n, int t) { return unsigned((n + t - 1) / t); }
+
+// Per-leaf kernels loop over the leaves with a stride of their grid: one
+// block per leaf on the host path (the dispatcher balances uneven walks), at
+// most kGatedGrid blocks where a captured step launches them behind a gate
+// (a gate that reads zero then costs a small launch, not one block per leaf).
+constexpr int64_t kGatedGrid = 8192;
+inline unsigned leaf_grid(int64_t nl, const int32_t *run)
+{
+    return unsigned(run ? std::min<int64_t>(nl, kGatedGrid) : nl);
+}
+
+// Slot size of a leaf: kSlotFactor times its task count + 8. Roomy slots let
+// the growth rebuilds of the h iteration (radii up to twice larger per pass
+// in voids) stay in place.
+constexpr int kSlotFactor = 4;
 
 __device__ __forceinline__ int lanes_below64(uint64_t mask)
 {
@@ -34,109 +61,112 @@ __device__ __forceinline__ float wave_maxf(float v)
     return v;
 }
 
-// One wave per leaf: radius = (1 + skin) * gamma_k * max h over the leaf.
+// Levels of the tree over the leaves, for kernels that update its radii.
+struct TreeLevels {
+    int64_t off[kMaxLevels];
+    int n;
+};
+
+// Raise the radii of leaf L's ancestors to at least v: an atomic maximum on
+// the non-negative floats' bit patterns (which order like the values), up to
+// the first ancestor that already holds as much (it and every node above it
+// then hold at least v, or will once the thread that raised it gets there).
+__device__ __forceinline__ void raise_ancestors(float *__restrict__ node_r, const TreeLevels &lv,
+                                                int64_t L, float v)
+{
+    int64_t c = L;
+    for (int l = 1; l < lv.n; ++l) {
+        c /= kTreeFan;
+        float *a = node_r + lv.off[l] + c;
+        if (__hip_atomic_load(a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= v)
+            break;
+        atomicMax(reinterpret_cast<int *>(a), __float_as_int(v));
+    }
+}
+
+// Full build, first: the radii of the tree's nodes above the leaves cleared.
+__global__ void k_tree_clear(float *__restrict__ r, int64_t n, const int32_t *__restrict__ run)
+{
+    if (run && !*run)
+        return;
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+         i += int64_t(gridDim.x) * blockDim.x)
+        r[i] = 0.0f;
+}
+
+// Full build: radius = (1 + skin) * gamma_k * max h over the leaf, for every
+// leaf, raised into the tree above it, and every leaf marked for the walk.
+// Clears the outgrown-slot flag and the asymmetry flag (a full build lists
+// every pair within max(R_I, R_J)).
 __global__ __launch_bounds__(64) void k_leaf_radius(int64_t n_leaves,
                                                     const int32_t *__restrict__ leaf_start,
                                                     const float *__restrict__ hs, float scale,
                                                     float *__restrict__ node_r,
-                                                    float *__restrict__ radius)
+                                                    float *__restrict__ radius,
+                                                    uint8_t *__restrict__ overflow,
+                                                    uint8_t *__restrict__ dirty,
+                                                    int64_t *__restrict__ state, TreeLevels lv,
+                                                    const int32_t *__restrict__ run)
 {
-    int64_t L = blockIdx.x;
-    if (L >= n_leaves)
+    if (run && !*run)
         return;
-    int lane = threadIdx.x;
-    int32_t s0 = leaf_start[L], cnt = leaf_start[L + 1] - s0;
-    float v = lane < cnt ? hs[s0 + lane] : 0.0f;
-    v = wave_maxf(v) * scale;
-    if (lane == 0) {
-        node_r[L] = v;
-        radius[L] = v;
+    const int lane = threadIdx.x;
+    if (blockIdx.x == 0 && lane == 0) {
+        state[kTaskOutgrown] = 0;
+        state[kTaskAsym] = 0;
+    }
+    for (int64_t L = blockIdx.x; L < n_leaves; L += gridDim.x) {
+        const int32_t s0 = leaf_start[L], cnt = leaf_start[L + 1] - s0;
+        float v = lane < cnt ? hs[s0 + lane] : 0.0f;
+        v = wave_maxf(v) * scale;
+        if (lane == 0) {
+            node_r[L] = v;
+            radius[L] = v;
+            dirty[L] = 1;
+            overflow[L] = 0;
+            raise_ancestors(node_r, lv, L, v);
+        }
     }
 }
 
 // Growth rebuild: a leaf is walked again when (1 + skin) gamma_k max h grew
-// beyond its list's radius (the radius then grows; it never shrinks here) or
-// when the serial walk built its list; the tree holds the lists' radii.
+// beyond its list's radius (the radius then grows; it never shrinks here).
+// The tree holds the lists' radii: a grown leaf raises its ancestors' radii
+// itself, so no per-level pass is needed. Sets the asymmetry flag: a leaf kept
+// as it is may miss a pair that only a grown neighbour's radius reaches.
 __global__ __launch_bounds__(64) void k_leaf_radius_grow(int64_t n_leaves,
                                                          const int32_t *__restrict__ leaf_start,
                                                          const float *__restrict__ hs,
                                                          float scale, float *__restrict__ node_r,
                                                          float *__restrict__ radius,
                                                          uint8_t *__restrict__ overflow,
-                                                         uint8_t *__restrict__ dirty)
+                                                         uint8_t *__restrict__ dirty,
+                                                         int64_t *__restrict__ state,
+                                                         TreeLevels lv,
+                                                         const int32_t *__restrict__ run)
 {
-    int64_t L = blockIdx.x;
-    if (L >= n_leaves)
+    if (run && !*run)
         return;
-    int lane = threadIdx.x;
-    int32_t s0 = leaf_start[L], cnt = leaf_start[L + 1] - s0;
-    float v = lane < cnt ? hs[s0 + lane] : 0.0f;
-    v = wave_maxf(v) * scale;
-    if (lane == 0) {
-        const bool grow = v > radius[L];
-        const bool d = grow || overflow[L] != 0;
-        const float r = grow ? v : radius[L];
-        radius[L] = r;
-        node_r[L] = r;
-        dirty[L] = d ? 1 : 0;
-        if (d)
-            overflow[L] = 0;  // the walk decides again
+    const int lane = threadIdx.x;
+    if (blockIdx.x == 0 && lane == 0) {
+        state[kTaskOutgrown] = 0;
+        state[kTaskAsym] = 1;
     }
-}
-
-// Growth rebuild: the leaves kept as they are count their current lists.
-__global__ void k_keep_counts(int64_t n_leaves, const uint8_t *__restrict__ dirty,
-                              const int32_t *__restrict__ off, int32_t *__restrict__ count)
-{
-    const int64_t I = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (I < n_leaves && !dirty[I])
-        count[I] = off[I + 1] - off[I];
-    else if (I == n_leaves)
-        count[I] = 0;
-}
-
-// Growth rebuild: the new list from the old one (leaves kept) and from the
-// slots of the walked leaves that fitted (the others are written by the
-// second walk or the serial fill).
-__global__ __launch_bounds__(64) void k_copy_grown(int64_t n_leaves,
-                                                   const uint8_t *__restrict__ dirty,
-                                                   const uint8_t *__restrict__ overflow,
-                                                   const int32_t *__restrict__ off_old,
-                                                   const int32_t *__restrict__ off_new,
-                                                   const int32_t *__restrict__ soff,
-                                                   const int32_t *__restrict__ count,
-                                                   const Task *__restrict__ task_old,
-                                                   const Task *__restrict__ slack,
-                                                   Task *__restrict__ task_new)
-{
-    const int64_t I = blockIdx.x;
-    if (I >= n_leaves)
-        return;
-    const int32_t n = count[I], b = off_new[I];
-    const Task *src;
-    if (!dirty[I])
-        src = task_old + off_old[I];
-    else if (!overflow[I] && n <= soff[I + 1] - soff[I])
-        src = slack + soff[I];
-    else
-        return;
-    for (int32_t k = threadIdx.x; k < n; k += 64)
-        task_new[b + k] = src[k];
-}
-
-__global__ void k_tree_radius(int64_t cnt_up, int64_t cnt_dn, const float *__restrict__ r_dn,
-                              float *__restrict__ r_up)
-{
-    int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (c >= cnt_up)
-        return;
-    int64_t e = (c + 1) * kTreeFan;
-    if (e > cnt_dn)
-        e = cnt_dn;
-    float r = 0.0f;
-    for (int64_t k = c * kTreeFan; k < e; ++k)
-        r = fmaxf(r, r_dn[k]);
-    r_up[c] = r;
+    for (int64_t L = blockIdx.x; L < n_leaves; L += gridDim.x) {
+        const int32_t s0 = leaf_start[L], cnt = leaf_start[L + 1] - s0;
+        float v = lane < cnt ? hs[s0 + lane] : 0.0f;
+        v = wave_maxf(v) * scale;
+        if (lane == 0) {
+            const bool grow = v > radius[L];
+            dirty[L] = grow ? 1 : 0;
+            if (grow) {
+                radius[L] = v;
+                node_r[L] = v;
+                overflow[L] = 0;  // the walk decides again
+                raise_ancestors(node_r, lv, L, v);
+            }
+        }
+    }
 }
 
 struct TreeView {
@@ -209,6 +239,37 @@ __device__ __forceinline__ int emit_shifts(const double g[3][3], double R, Emit 
     return n;
 }
 
+// The task record of leaf I's pair with leaf J at shift (sx, sy, sz): the
+// offset origin_J + shift - origin_I formed in FP64, stored in FP32.
+__device__ __forceinline__ Task make_task(const TreeView &T, const double *__restrict__ org,
+                                          const int32_t *__restrict__ leaf_start, int64_t I,
+                                          int64_t J, int sx, int sy, int sz)
+{
+    Task t;
+    t.j = int32_t(J);
+    t.j0 = leaf_start[J];
+    t.jc = leaf_start[J + 1] - t.j0;
+    t.self = (J == I && sx == 0 && sy == 0 && sz == 0) ? 1 : 0;
+    t.j0b = t.j0;
+    t.ox = float(org[3 * J] + double(sx) * T.L[0] - org[3 * I]);
+    t.oy = float(org[3 * J + 1] + double(sy) * T.L[1] - org[3 * I + 1]);
+    t.oz = float(org[3 * J + 2] + double(sz) * T.L[2] - org[3 * I + 2]);
+    return t;
+}
+
+// Leaf I's walk found n tasks: its slot keeps min(n, size) of them (the ones
+// written), and a leaf over its slot raises the flag.
+__device__ __forceinline__ void slot_done(int64_t I, int32_t n, const int32_t *__restrict__ slot,
+                                          int32_t *__restrict__ end, int32_t *__restrict__ count,
+                                          int64_t *__restrict__ state)
+{
+    const int32_t size = slot[I + 1] - slot[I];
+    count[I] = n;
+    end[I] = slot[I] + (n < size ? n : size);
+    if (n > size)
+        state[kTaskOutgrown] = 1;
+}
+
 // Walk the tree for leaf `I`; for every leaf J (ascending) and shift whose box
 // gap is below max(R_I, R_J), call emit(J, sx, sy, sz).
 template <class Emit>
@@ -244,51 +305,43 @@ __device__ void walk(const TreeView &T, int64_t I, Emit &&emit)
     }
 }
 
-// Serial walks (one thread per cell), used for the cells whose breadth-first
-// frontier did not fit in LDS.
-__global__ void k_task_count(int64_t n_leaves, TreeView T, const uint8_t *__restrict__ overflow,
-                             int32_t *__restrict__ count)
+// Serial walks (one thread per leaf) of the leaves whose breadth-first
+// frontier did not fit in LDS. WRITE = false: count them (for a new layout);
+// WRITE: write them into their slots, for the leaves marked in `only`.
+template <bool WRITE>
+__global__ void k_task_serial(int64_t n_leaves, TreeView T, const double *__restrict__ org,
+                              const int32_t *__restrict__ leaf_start,
+                              const int32_t *__restrict__ slot, int32_t *__restrict__ end,
+                              int32_t *__restrict__ count, const uint8_t *__restrict__ overflow,
+                              const uint8_t *__restrict__ only, Task *__restrict__ task,
+                              int64_t *__restrict__ state, const int32_t *__restrict__ run)
 {
-    int64_t I = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (I >= n_leaves || !overflow[I])
+    if (run && !*run)
         return;
-    int32_t c = 0;
-    walk(T, I, [&](int64_t, int, int, int) { ++c; });
-    count[I] = c;
-}
-
-__global__ void k_task_fill(int64_t n_leaves, TreeView T, const double *__restrict__ org,
-                            const int32_t *__restrict__ leaf_start,
-                            const uint8_t *__restrict__ overflow,
-                            const int32_t *__restrict__ off, Task *__restrict__ task)
-{
-    int64_t I = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (I >= n_leaves || !overflow[I])
+    const int64_t I = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (I >= n_leaves || !overflow[I] || (only && !only[I]))
         return;
-    int32_t w = off[I];
-    const int32_t w_end = off[I + 1];
-    const double ox = org[3 * I], oy = org[3 * I + 1], oz = org[3 * I + 2];
+    int32_t n = 0;
+    if (!WRITE) {
+        walk(T, I, [&](int64_t, int, int, int) { ++n; });
+        count[I] = n;
+        return;
+    }
+    const int32_t w0 = slot[I], size = slot[I + 1] - w0;
     walk(T, I, [&](int64_t J, int sx, int sy, int sz) {
-        Task t;
-        t.j = int32_t(J);
-        t.j0 = leaf_start[J];
-        t.jc = leaf_start[J + 1] - t.j0;
-        t.self = (J == I && sx == 0 && sy == 0 && sz == 0) ? 1 : 0;
-        t.j0b = t.j0;
-        // origin_j + shift - origin_i, formed in FP64, stored in FP32
-        t.ox = float(org[3 * J] + double(sx) * T.L[0] - ox);
-        t.oy = float(org[3 * J + 1] + double(sy) * T.L[1] - oy);
-        t.oz = float(org[3 * J + 2] + double(sz) * T.L[2] - oz);
-        if (w < w_end)
-            task[w++] = t;
+        if (n < size)
+            task[w0 + n] = make_task(T, org, leaf_start, I, J, sx, sy, sz);
+        ++n;
     });
+    slot_done(I, n, slot, end, count, state);
 }
 
 // Sort keys of the launch order: slot i of the padded leaf range belongs to
 // XCD range x = i / per; key = (x, ~work), work = sources of all the leaf's
 // tasks (padding slots sort last in their range).
 __global__ __launch_bounds__(64) void k_leaf_order_keys(int64_t n_leaves, int64_t nbp,
-                                                        const int32_t *__restrict__ off,
+                                                        const int32_t *__restrict__ tbeg,
+                                                        const int32_t *__restrict__ tend,
                                                         const Task *__restrict__ task,
                                                         uint64_t *__restrict__ key,
                                                         int32_t *__restrict__ val)
@@ -300,7 +353,7 @@ __global__ __launch_bounds__(64) void k_leaf_order_keys(int64_t n_leaves, int64_
     const int64_t per = nbp >> 3;
     uint32_t work = 0;
     if (i < n_leaves) {
-        const int32_t a = off[i], b = off[i + 1];
+        const int32_t a = tbeg[i], b = tend[i];
         uint32_t w = 0;
         for (int32_t t = a + lane; t < b; t += 64)
             w += uint32_t(task[t].jc);
@@ -335,34 +388,21 @@ __device__ __forceinline__ int wave_prefix_small(int v, int &total)
 // nodes x 8 children tested per step by the 64 lanes; survivors keep their
 // ascending order, so the cells (and their shifts) come out in the same order
 // as in the serial walk. A frontier that would exceed kFront marks the cell
-// for the serial walk instead. MODE 0 counts; MODE 1 writes at off[I];
-// MODE 2 writes into the cell's slot of the slack layout, at slot[I] up to
-// its size slot[I+1] - slot[I], and counts; MODE 3 writes at off[I] the cells
-// whose MODE 2 count exceeded their slot (the others return at once).
-// FT: the frontier's index type, 16 bits when every level has at most 2^16
-// nodes (half the LDS per wave: twice the waves per CU for this
-// latency-bound walk), else 32.
-template <int MODE, typename FT>
-__global__ __launch_bounds__(64) void k_task_bfs(int64_t n_leaves, TreeView T,
-                                                 const double *__restrict__ org,
-                                                 const int32_t *__restrict__ leaf_start,
-                                                 const int32_t *__restrict__ off,
-                                                 const int32_t *__restrict__ slot,
-                                                 int32_t *__restrict__ count,
-                                                 uint8_t *__restrict__ overflow,
-                                                 Task *__restrict__ task,
-                                                 const uint8_t *__restrict__ only)
+// for the serial walk instead. WRITE = false counts (count[I]); WRITE writes
+// the tasks into the cell's slot, as many as fit, and records them
+// (slot_done).
+template <bool WRITE, typename FT>
+__device__ __forceinline__ void bfs_leaf(int64_t I, const TreeView &T,
+                                         const double *__restrict__ org,
+                                         const int32_t *__restrict__ leaf_start,
+                                         const int32_t *__restrict__ slot,
+                                         int32_t *__restrict__ end, int32_t *__restrict__ count,
+                                         uint8_t *__restrict__ overflow,
+                                         Task *__restrict__ task, int64_t *__restrict__ state,
+                                         FT (*front)[kFront])
 {
-    const int64_t I = blockIdx.x;
-    if (I >= n_leaves || (only && !only[I]))
-        return;  // (only: the growth rebuild walks the marked leaves alone)
-    constexpr bool COUNT = MODE == 0 || MODE == 2, WRITE = MODE != 0;
-    if (!COUNT && overflow[I])
-        return;
-    if (MODE == 3 && count[I] <= slot[I + 1] - slot[I])
-        return;
     const int lane = threadIdx.x;
-    __shared__ FT front[2][kFront];
+    __syncthreads();  // the previous leaf's frontier reads are done
     const double alo[3] = {T.lo[3 * I], T.lo[3 * I + 1], T.lo[3 * I + 2]};
     const double ahi[3] = {T.hi[3 * I], T.hi[3 * I + 1], T.hi[3 * I + 2]};
     const float RI = T.r[I];
@@ -370,18 +410,18 @@ __global__ __launch_bounds__(64) void k_task_bfs(int64_t n_leaves, TreeView T,
     int cur = 0;
     int ncur = int(T.level_cnt[top]);
     if (ncur > kFront) {
-        if (COUNT && lane == 0) {
+        if (lane == 0) {
             overflow[I] = 1;
-            count[I] = 0;
+            if (!WRITE)
+                count[I] = 0;
         }
         return;
     }
     for (int k = lane; k < ncur; k += 64)
         front[0][k] = FT(k);
     int emitted = 0;
-    const int32_t wbase = MODE == 2 ? slot[I] : (WRITE ? off[I] : 0);
-    const int32_t wcap = MODE == 2 ? slot[I + 1] - slot[I] : 0x7fffffff;
-    const double oxi = org[3 * I], oyi = org[3 * I + 1], ozi = org[3 * I + 2];
+    const int32_t wbase = WRITE ? slot[I] : 0;
+    const int32_t wcap = WRITE ? slot[I + 1] - slot[I] : 0;
     // One wave-wide round of up to 64 candidate leaves, one per lane, in lane
     // order: tasks counted, prefix-summed over the lanes and written.
     auto emit_round = [&](bool cand, int32_t J) __attribute__((always_inline)) {
@@ -392,20 +432,10 @@ __global__ __launch_bounds__(64) void k_task_bfs(int64_t n_leaves, TreeView T,
         int tot;
         const int pre = wave_prefix_small(nt, tot);
         if (WRITE && nt > 0) {
-            const int32_t j0 = leaf_start[J];
-            const int32_t jc = leaf_start[J + 1] - j0;
             emit_shifts(g, R, [&](int k, int sx, int sy, int sz) {
-                Task t;
-                t.j = J;
-                t.j0 = j0;
-                t.jc = jc;
-                t.self = (J == I && sx == 0 && sy == 0 && sz == 0) ? 1 : 0;
-                t.ox = float(org[3 * J] + double(sx) * T.L[0] - oxi);
-                t.oy = float(org[3 * J + 1] + double(sy) * T.L[1] - oyi);
-                t.oz = float(org[3 * J + 2] + double(sz) * T.L[2] - ozi);
-                t.j0b = j0;
                 if (emitted + pre + k < wcap)
-                    task[wbase + emitted + pre + k] = t;
+                    task[wbase + emitted + pre + k] =
+                        make_task(T, org, leaf_start, I, J, sx, sy, sz);
             });
         }
         emitted += tot;
@@ -462,99 +492,244 @@ __global__ __launch_bounds__(64) void k_task_bfs(int64_t n_leaves, TreeView T,
             nnext += tot;
         }
         if (over) {
-            if (COUNT && lane == 0) {
+            if (lane == 0) {
                 overflow[I] = 1;
-                count[I] = 0;
+                if (!WRITE)
+                    count[I] = 0;
             }
             return;
         }
         cur ^= 1;
         ncur = nnext;
     }
-    if (COUNT && lane == 0)
-        count[I] = emitted;
+    if (lane == 0) {
+        if (WRITE)
+            slot_done(I, emitted, slot, end, count, state);
+        else
+            count[I] = emitted;
+    }
 }
 
-// Compaction of the one-walk rebuild: the tasks of each walked cell that fit
-// its slack slot, from the slot to the cell's place in the list (the cells
-// that did not fit are walked again, straight into the list).
-__global__ __launch_bounds__(64) void k_compact_tasks(int64_t n_leaves,
-                                                      const int32_t *__restrict__ soff,
-                                                      const int32_t *__restrict__ off,
-                                                      const int32_t *__restrict__ count,
-                                                      const uint8_t *__restrict__ overflow,
-                                                      const Task *__restrict__ slack,
-                                                      Task *__restrict__ task)
+// The breadth-first walk over the leaves marked in `only` (every leaf when
+// null), with a stride of the grid. FT: the frontier's index type, 16 bits
+// when every level has at most 2^16 nodes (half the LDS per wave: twice the
+// waves per CU for this latency-bound walk), else 32.
+template <bool WRITE, typename FT>
+__global__ __launch_bounds__(64) void k_task_bfs(int64_t n_leaves, TreeView T,
+                                                 const double *__restrict__ org,
+                                                 const int32_t *__restrict__ leaf_start,
+                                                 const int32_t *__restrict__ slot,
+                                                 int32_t *__restrict__ end,
+                                                 int32_t *__restrict__ count,
+                                                 uint8_t *__restrict__ overflow,
+                                                 Task *__restrict__ task,
+                                                 const uint8_t *__restrict__ only,
+                                                 int64_t *__restrict__ state,
+                                                 const int32_t *__restrict__ run)
 {
-    const int64_t I = blockIdx.x;
-    if (I >= n_leaves || overflow[I])
+    if (run && !*run)
         return;
-    const int32_t n = count[I], a = soff[I], b = off[I];
-    if (n > soff[I + 1] - a)
-        return;
-    for (int32_t k = threadIdx.x; k < n; k += 64)
-        task[b + k] = slack[a + k];
+    __shared__ FT front[2][kFront];
+    for (int64_t I = blockIdx.x; I < n_leaves; I += gridDim.x) {
+        if (only && !only[I])
+            continue;
+        bfs_leaf<WRITE, FT>(I, T, org, leaf_start, slot, end, count, overflow, task, state,
+                            front);
+    }
 }
 
-// Slot size of a cell in the slack layout: kSlackFactor times its task count
-// at the last build, + 8. Roomy slots let the rebuilds inside a step (whose
-// radii grow, up to twofold per pass in voids) fit in one walk; measured on
-// the clustered box, 4 beats count + 25 % by 2 % per step, for ~6 task records
-// per particle of device memory.
-constexpr int kSlackFactor = 4;
+// Slot sizes of a new layout from the counts of every leaf, never below the
+// leaf's slot in the previous layout (prev, if any: slots only grow, so a
+// step whose radii rise and fall in a repeating pattern settles on a layout
+// that holds all of it); their 64-bit sum goes to state[kTaskSlots] (the
+// 32-bit scan of the sizes must not wrap).
+__global__ void k_slot_sizes(int64_t n_leaves, const int32_t *__restrict__ count,
+                             const int32_t *__restrict__ prev, int32_t *__restrict__ sz,
+                             int64_t *__restrict__ state)
+{
+    const int64_t I = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    int64_t v = 0;
+    if (I < n_leaves) {
+        v = int64_t(kSlotFactor) * count[I] + 8;
+        const int64_t was = prev ? int64_t(prev[I + 1]) - prev[I] : 0;
+        v = v > was ? v : was;
+        sz[I] = int32_t(v < int64_t(INT_MAX) ? v : int64_t(INT_MAX));
+    } else if (I == n_leaves) {
+        sz[I] = 0;
+    }
+    for (int o = 32; o > 0; o >>= 1)
+        v += __shfl_xor(v, o, 64);
+    if ((threadIdx.x & 63) == 0 && v)
+        atomicAdd(reinterpret_cast<unsigned long long *>(state + kTaskSlots),
+                  (unsigned long long)v);
+}
 
-// Slot sizes of the slack layout from the counts of the last build.
-__global__ void k_slack_sizes(int64_t n_leaves, const int32_t *__restrict__ count,
-                              int32_t *__restrict__ sz)
+// Empty slots of a new layout (end = slot start) and cleared counts.
+__global__ void k_slots_empty(int64_t n_leaves, const int32_t *__restrict__ slot,
+                              int32_t *__restrict__ end, int64_t *__restrict__ state)
 {
     const int64_t I = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (I < n_leaves)
-        sz[I] = kSlackFactor * count[I] + 8;
-    else if (I == n_leaves)
-        sz[I] = 0;
+        end[I] = slot[I];
+    if (I == 0) {
+        state[kTaskOutgrown] = 0;
+        state[kTaskTotal] = 0;
+    }
+}
+
+__global__ void k_state_clear(int64_t *__restrict__ state)
+{
+    if (threadIdx.x < kTaskStateWords)
+        state[threadIdx.x] = 0;
+}
+
+// state[kTaskTotal] = the tasks held, summed over the leaves' slots (one
+// block of kTotalThreads; no atomics on one word from every leaf).
+constexpr int kTotalThreads = 1024;
+__global__ __launch_bounds__(kTotalThreads) void k_task_total(int64_t n_leaves,
+                                                              const int32_t *__restrict__ slot,
+                                                              const int32_t *__restrict__ end,
+                                                              int64_t *__restrict__ state)
+{
+    __shared__ int64_t part[kTotalThreads / 64];
+    int64_t v = 0;
+    for (int64_t I = threadIdx.x; I < n_leaves; I += kTotalThreads)
+        v += end[I] - slot[I];
+    for (int o = 32; o > 0; o >>= 1)
+        v += __shfl_xor(v, o, 64);
+    if ((threadIdx.x & 63) == 0)
+        part[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t t = 0;
+        for (int k = 0; k < kTotalThreads / 64; ++k)
+            t += part[k];
+        state[kTaskTotal] = t;
+    }
 }
 
 }  // namespace
 
-// Launches the walk of mode MODE with the narrowest frontier index type.
-template <int MODE>
-static void walk_launch(int64_t nl, const TreeView &T, const double *org,
-                        const int32_t *leaf_start, const int32_t *off, const int32_t *slot,
-                        int32_t *count, uint8_t *overflow, Task *task, hipStream_t s,
-                        const uint8_t *only = nullptr)
+// The tree view of a grid with the periodic box of the context.
+static TreeView tree_view(const sphx_ctx *ctx, const sphx_grid *g)
 {
+    TreeView T;
+    T.lo = g->node_lo;
+    T.hi = g->node_hi;
+    T.r = g->node_r;
+    for (int l = 0; l < kMaxLevels; ++l) {
+        T.level_off[l] = l < g->n_levels ? g->level_off[l] : 0;
+        T.level_cnt[l] = l < g->n_levels ? g->level_cnt[l] : 0;
+    }
+    T.n_levels = g->n_levels;
+    for (int a = 0; a < 3; ++a)
+        T.L[a] = ctx->p.box[a];
+    T.periodic = ctx->p.periodic;
+    return T;
+}
+
+// Launches the breadth-first walk with the narrowest frontier index type.
+template <bool WRITE>
+static void bfs_launch(const sphx_ctx *ctx, const sphx_grid *g, sphx_tasks *t,
+                       const uint8_t *only, const int32_t *run, hipStream_t s)
+{
+    const int64_t nl = g->n_leaves;
+    const TreeView T = tree_view(ctx, g);
+    const unsigned grid = leaf_grid(nl, run);
     if (nl <= 65536)
-        k_task_bfs<MODE, uint16_t><<<unsigned(nl), 64, 0, s>>>(nl, T, org, leaf_start, off, slot,
-                                                              count, overflow, task, only);
+        k_task_bfs<WRITE, uint16_t><<<grid, 64, 0, s>>>(nl, T, g->leaf_org, g->leaf_start,
+                                                       t->slot, t->end, t->count, t->overflow,
+                                                       t->task, only, t->state, run);
     else
-        k_task_bfs<MODE, int32_t><<<unsigned(nl), 64, 0, s>>>(nl, T, org, leaf_start, off, slot,
-                                                             count, overflow, task, only);
+        k_task_bfs<WRITE, int32_t><<<grid, 64, 0, s>>>(nl, T, g->leaf_org, g->leaf_start,
+                                                      t->slot, t->end, t->count, t->overflow,
+                                                      t->task, only, t->state, run);
+}
+
+// Leaf radii (a full build: every leaf, marked; a growth rebuild: the grown
+// leaves, marked) and the tree's radii above them.
+static sphx_status radii_launch(const sphx_ctx *ctx, sphx_grid *g, sphx_tasks *t, bool grow,
+                                const int32_t *run, hipStream_t s)
+{
+    const int64_t nl = g->n_leaves;
+    const float scale = float(ctx->p.gamma_k * (1.0 + ctx->p.skin));
+    TreeLevels lv;
+    for (int l = 0; l < kMaxLevels; ++l)
+        lv.off[l] = l < g->n_levels ? g->level_off[l] : 0;
+    lv.n = g->n_levels;
+    if (grow) {
+        k_leaf_radius_grow<<<leaf_grid(nl, run), 64, 0, s>>>(
+            nl, g->leaf_start, g->hs, scale, g->node_r, t->radius, t->overflow, t->dirty,
+            t->state, lv, run);
+    } else {
+        const int64_t inner = g->n_nodes - nl;
+        k_tree_clear<<<unsigned(std::min<int64_t>((inner + 255) / 256 + 1, 1024)), 256, 0, s>>>(
+            g->node_r + nl, inner, run);
+        SPHX_HIP(hipGetLastError());
+        k_leaf_radius<<<leaf_grid(nl, run), 64, 0, s>>>(nl, g->leaf_start, g->hs, scale,
+                                                         g->node_r, t->radius, t->overflow,
+                                                         t->dirty, t->state, lv, run);
+    }
+    SPHX_HIP(hipGetLastError());
+    return SPHX_OK;
+}
+
+// The marked leaves walked into their slots: the breadth-first walk, then the
+// serial walk of those whose frontier overflowed.
+static sphx_status walk_slots_launch(const sphx_ctx *ctx, const sphx_grid *g, sphx_tasks *t,
+                                     const int32_t *run, hipStream_t s)
+{
+    const int64_t nl = g->n_leaves;
+    bfs_launch<true>(ctx, g, t, t->dirty, run, s);
+    SPHX_HIP(hipGetLastError());
+    k_task_serial<true><<<blocks(nl, 64), 64, 0, s>>>(nl, tree_view(ctx, g), g->leaf_org,
+                                                      g->leaf_start, t->slot, t->end, t->count,
+                                                      t->overflow, t->dirty, t->task, t->state,
+                                                      run);
+    SPHX_HIP(hipGetLastError());
+    return SPHX_OK;
+}
+
+// The task list's device state, its total summed first, read back
+// (synchronises the stream).
+static sphx_status read_state(sphx_ctx *ctx, sphx_tasks *t, hipStream_t s,
+                              int64_t st[kTaskStateWords])
+{
+    k_task_total<<<1, kTotalThreads, 0, s>>>(t->grid->n_leaves, t->slot, t->end, t->state);
+    SPHX_HIP(hipGetLastError());
+    int64_t *h = reinterpret_cast<int64_t *>(ctx->h_pinned + kPinnedBytes - 64);
+    SPHX_HIP(hipMemcpyAsync(h, t->state, kTaskStateWords * sizeof(int64_t),
+                            hipMemcpyDeviceToHost, s));
+    SPHX_HIP(wait_stream(ctx, s));
+    for (int k = 0; k < kTaskStateWords; ++k)
+        st[k] = h[k];
+    return SPHX_OK;
 }
 
 size_t tasks_bytes(int64_t n, int leaf_max)
 {
     // An estimate (the task count depends on the clustering): one leaf per
-    // leaf_max / 4 particles (at least 4) with 96 tasks each, held as the
-    // list (allocated with a quarter of headroom), the second list of the
-    // growth rebuilds (the same) and the slack layout (kSlackFactor tasks per
-    // task + 8 per leaf), plus the per-leaf arrays (offsets twice, counts,
-    // radius, order and its sort keys, flags).
+    // leaf_max / 4 particles (at least 4) with 96 tasks each, held in slots
+    // of kSlotFactor tasks per task + 8 (allocated with an eighth of
+    // headroom), plus the per-leaf arrays (slot starts and ends, counts,
+    // radius, flags, launch order and its sort keys).
     const int64_t leaves = n / std::max(4, leaf_max / 4) + 1;
     const int64_t per_leaf_tasks = 96;
-    const int64_t task_slots = 2 * (per_leaf_tasks * 5 / 4) + kSlackFactor * per_leaf_tasks + 8;
-    return size_t(leaves) * (size_t(task_slots) * sizeof(Task) + 48) + (1 << 20);
+    const int64_t task_slots = kSlotFactor * per_leaf_tasks + 8;
+    return size_t(leaves) * (size_t(task_slots + task_slots / 8) * sizeof(Task) + 48) +
+           (1 << 20);
 }
 
 void tasks_free(sphx_tasks *t)
 {
     if (!t)
         return;
-    void *ptrs[] = {t->off, t->task, t->count, t->radius, t->scan_tmp, t->overflow,
-                    t->task_alt, t->off_alt, t->dirty};
+    void *ptrs[] = {t->slot, t->end, t->task, t->count, t->radius, t->scan_tmp, t->overflow,
+                    t->dirty, t->state};
     for (void *p : ptrs)
         dfree(p, t->stream);
     for (void *p : {(void *)t->order, (void *)t->okey, (void *)t->okey_out, (void *)t->oval,
-                    t->sort_tmp, (void *)t->slack, (void *)t->soff})
+                    t->sort_tmp})
         dfree(p, t->stream);
     delete t;
 }
@@ -589,11 +764,62 @@ static sphx_status leaf_order(sphx_tasks *t, int64_t nl, hipStream_t s)
         t->sort_tmp_bytes = tmp;
         t->order_cap = nbp;
     }
-    k_leaf_order_keys<<<unsigned(nbp), 64, 0, s>>>(nl, nbp, t->off, t->task, t->okey, t->oval);
+    k_leaf_order_keys<<<unsigned(nbp), 64, 0, s>>>(nl, nbp, t->slot, t->end, t->task, t->okey,
+                                                   t->oval);
     SPHX_HIP(hipGetLastError());
     size_t tmp = t->sort_tmp_bytes;
     SPHX_HIP(rocprim::radix_sort_pairs(t->sort_tmp, tmp, t->okey, t->okey_out, t->oval, t->order,
                                        size_t(nbp), 0, kOrderKeyBits, s));
+    return SPHX_OK;
+}
+
+// A new slot layout at the current radii (every leaf marked): each leaf's
+// tasks counted, slots of kSlotFactor count + 8 (or the leaf's previous
+// slot, if larger), the task array grown if needed (the old contents are not
+// kept), every leaf walked into its slot.
+static sphx_status relayout(sphx_ctx *ctx, sphx_grid *g, sphx_tasks *t, hipStream_t s)
+{
+    const int64_t nl = g->n_leaves;
+    bfs_launch<false>(ctx, g, t, nullptr, nullptr, s);
+    SPHX_HIP(hipGetLastError());
+    k_task_serial<false><<<blocks(nl, 64), 64, 0, s>>>(nl, tree_view(ctx, g), g->leaf_org,
+                                                       g->leaf_start, t->slot, t->end, t->count,
+                                                       t->overflow, nullptr, t->task, t->state,
+                                                       nullptr);
+    SPHX_HIP(hipGetLastError());
+    k_state_clear<<<1, 64, 0, s>>>(t->state);
+    SPHX_HIP(hipGetLastError());
+    // the sizes go to `end` (free until the walk below), their scan to `slot`
+    k_slot_sizes<<<blocks(nl + 1, 256), 256, 0, s>>>(nl, t->count, t->task ? t->slot : nullptr,
+                                                      t->end, t->state);
+    SPHX_HIP(hipGetLastError());
+    size_t tmp = t->scan_tmp_bytes;
+    SPHX_HIP(rocprim::exclusive_scan(t->scan_tmp, tmp, t->end, t->slot, 0, size_t(nl + 1),
+                                     rocprim::plus<int32_t>(), s));
+    int64_t st[kTaskStateWords];
+    SPHX_TRY(read_state(ctx, t, s, st));
+    if (st[kTaskSlots] > int64_t(INT_MAX)) {
+        set_error("sphx_tasks_build: more than 2^31 task slots");
+        return SPHX_E_INVALID;
+    }
+    const int64_t slots = st[kTaskSlots];
+    if (slots > t->cap) {
+        dfree(t->task, s);
+        t->task = nullptr;
+        t->cap = 0;
+        const int64_t cap = std::min<int64_t>(slots + slots / 8 + 64, int64_t(INT_MAX));
+        SPHX_HIP(dmalloc((void **)&t->task, size_t(cap) * sizeof(Task), s));
+        t->cap = cap;
+    }
+    k_slots_empty<<<blocks(nl, 256), 256, 0, s>>>(nl, t->slot, t->end, t->state);
+    SPHX_HIP(hipGetLastError());
+    t->relayouts++;
+    SPHX_TRY(walk_slots_launch(ctx, g, t, nullptr, s));
+    SPHX_TRY(read_state(ctx, t, s, st));
+    if (st[kTaskOutgrown]) {
+        set_error("sphx_tasks_build: a leaf outgrew the slot sized from its own count");
+        return SPHX_E_STATE;
+    }
     return SPHX_OK;
 }
 
@@ -602,6 +828,7 @@ sphx_status tasks_build(sphx_ctx *ctx, sphx_grid *g, const sphx_particles *in, h
 {
     sphx_tasks *t = *out;
     const int64_t nl = g->n_leaves;
+    (void)in;
     if (t && t->grid != g) {
         set_error("sphx_tasks_build: task list belongs to another grid");
         return SPHX_E_STATE;
@@ -618,22 +845,29 @@ sphx_status tasks_build(sphx_ctx *ctx, sphx_grid *g, const sphx_particles *in, h
             tasks_free(t);
             return st;
         };
-        if (dmalloc((void **)&t->off, (nl + 1) * sizeof(int32_t), s) != hipSuccess ||
+        if (dmalloc((void **)&t->slot, (nl + 1) * sizeof(int32_t), s) != hipSuccess ||
+            dmalloc((void **)&t->end, (nl + 1) * sizeof(int32_t), s) != hipSuccess ||
             dmalloc((void **)&t->count, (nl + 1) * sizeof(int32_t), s) != hipSuccess ||
             dmalloc((void **)&t->radius, (nl + 1) * sizeof(float), s) != hipSuccess ||
             dmalloc((void **)&t->overflow, (nl + 1) * sizeof(uint8_t), s) != hipSuccess ||
-            dmalloc((void **)&t->soff, (nl + 1) * sizeof(int32_t), s) != hipSuccess) {
+            dmalloc((void **)&t->dirty, (nl + 1) * sizeof(uint8_t), s) != hipSuccess ||
+            dmalloc((void **)&t->state, kTaskStateWords * sizeof(int64_t), s) != hipSuccess) {
             set_error("sphx_tasks_build: out of device memory");
             return fail(SPHX_E_OOM);
         }
         size_t tmp = 0;
-        if (rocprim::exclusive_scan(nullptr, tmp, t->count, t->off, 0, size_t(nl + 1),
+        if (rocprim::exclusive_scan(nullptr, tmp, t->count, t->slot, 0, size_t(nl + 1),
                                     rocprim::plus<int32_t>(), s) != hipSuccess ||
             dmalloc(&t->scan_tmp, tmp + 16, s) != hipSuccess) {
             set_error("sphx_tasks_build: scan workspace");
             return fail(SPHX_E_OOM);
         }
         t->scan_tmp_bytes = tmp;
+        k_state_clear<<<1, 64, 0, s>>>(t->state);
+        if (hipGetLastError() != hipSuccess) {
+            set_error("sphx_tasks_build: launch failed");
+            return fail(SPHX_E_HIP);
+        }
     }
     struct Guard {
         sphx_tasks *t;
@@ -648,116 +882,25 @@ sphx_status tasks_build(sphx_ctx *ctx, sphx_grid *g, const sphx_particles *in, h
 
     if (nl == 0) {
         t->n_tasks = 0;
-        SPHX_HIP(hipMemsetAsync(t->off, 0, sizeof(int32_t), s));
+        t->symmetric = true;
         guard.keep = true;
         *out = t;
         return SPHX_OK;
     }
-    const float scale = float(ctx->p.gamma_k * (1.0 + ctx->p.skin));
-    (void)in;
-    k_leaf_radius<<<unsigned(nl), 64, 0, s>>>(nl, g->leaf_start, g->hs, scale, g->node_r,
-                                              t->radius);
-    SPHX_HIP(hipGetLastError());
-    for (int l = 0; l + 1 < g->n_levels; ++l) {
-        int64_t up = g->level_cnt[l + 1];
-        k_tree_radius<<<blocks(up, 128), 128, 0, s>>>(up, g->level_cnt[l],
-                                                        g->node_r + g->level_off[l],
-                                                        g->node_r + g->level_off[l + 1]);
-        SPHX_HIP(hipGetLastError());
+    SPHX_TRY(radii_launch(ctx, g, t, false, nullptr, s));
+    bool fits = false;
+    int64_t st[kTaskStateWords];
+    if (t->task) {
+        // in place: every leaf into its slot of the current layout
+        SPHX_TRY(walk_slots_launch(ctx, g, t, nullptr, s));
+        SPHX_TRY(read_state(ctx, t, s, st));
+        fits = st[kTaskOutgrown] == 0;
     }
-    TreeView T;
-    T.lo = g->node_lo;
-    T.hi = g->node_hi;
-    T.r = g->node_r;
-    for (int l = 0; l < kMaxLevels; ++l) {
-        T.level_off[l] = l < g->n_levels ? g->level_off[l] : 0;
-        T.level_cnt[l] = l < g->n_levels ? g->level_cnt[l] : 0;
+    if (!fits) {
+        SPHX_TRY(relayout(ctx, g, t, s));
+        SPHX_TRY(read_state(ctx, t, s, st));
     }
-    T.n_levels = g->n_levels;
-    for (int a = 0; a < 3; ++a)
-        T.L[a] = ctx->p.box[a];
-    T.periodic = ctx->p.periodic;
-
-    auto ensure_task_cap = [&](int64_t total) -> sphx_status {
-        if (total > t->cap) {
-            dfree(t->task, s);
-            t->task = nullptr;
-            t->cap = 0;
-            const int64_t cap = total + total / 4 + 64;
-            SPHX_HIP(dmalloc((void **)&t->task, size_t(cap) * sizeof(Task), s));
-            t->cap = cap;
-        }
-        return SPHX_OK;
-    };
-    size_t tmp = t->scan_tmp_bytes;
-    int32_t total = 0;
-    SPHX_HIP(hipMemsetAsync(t->count + nl, 0, sizeof(int32_t), s));
-    SPHX_HIP(hipMemsetAsync(t->overflow, 0, size_t(nl) * sizeof(uint8_t), s));
-    const bool one_walk = t->slack_ok;
-    if (one_walk) {
-        // One walk: count every cell's tasks and write them into its slot of
-        // the slack layout (slots sized from the previous build's counts).
-        walk_launch<2>(nl, T, g->leaf_org, g->leaf_start, t->off, t->soff, t->count,
-                       t->overflow, t->slack, s);
-    } else {
-        walk_launch<0>(nl, T, g->leaf_org, g->leaf_start, t->off, t->soff, t->count,
-                       t->overflow, t->task, s);
-    }
-    SPHX_HIP(hipGetLastError());
-    k_task_count<<<blocks(nl, 64), 64, 0, s>>>(nl, T, t->overflow, t->count);
-    SPHX_HIP(hipGetLastError());
-    SPHX_HIP(rocprim::exclusive_scan(t->scan_tmp, tmp, t->count, t->off, 0, size_t(nl + 1),
-                                     rocprim::plus<int32_t>(), s));
-    int32_t *h_total = reinterpret_cast<int32_t *>(ctx->h_pinned + kPinnedBytes - 64);
-    SPHX_HIP(hipMemcpyAsync(h_total, t->off + nl, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    SPHX_HIP(wait_stream(ctx, s));
-    total = *h_total;
-    if (total < 0) {
-        set_error("sphx_tasks_build: task count overflow");
-        return SPHX_E_INVALID;
-    }
-    SPHX_TRY(ensure_task_cap(total));
-    t->n_tasks = total;
-    if (one_walk) {
-        // cells that fitted: from the slot into the list; the others (a few
-        // cells whose h grew most) are walked again, writing at their place
-        k_compact_tasks<<<unsigned(nl), 64, 0, s>>>(nl, t->soff, t->off, t->count, t->overflow,
-                                                    t->slack, t->task);
-        SPHX_HIP(hipGetLastError());
-        walk_launch<3>(nl, T, g->leaf_org, g->leaf_start, t->off, t->soff, t->count,
-                       t->overflow, t->task, s);
-    } else {
-        walk_launch<1>(nl, T, g->leaf_org, g->leaf_start, t->off, t->soff, t->count,
-                       t->overflow, t->task, s);
-    }
-    SPHX_HIP(hipGetLastError());
-    k_task_fill<<<blocks(nl, 64), 64, 0, s>>>(nl, T, g->leaf_org, g->leaf_start, t->overflow,
-                                              t->off, t->task);
-    SPHX_HIP(hipGetLastError());
-    // Slots of the slack layout for the next rebuild, from these counts
-    // (kSlackFactor count + 8 per cell); the buffer is sized from the host's
-    // bound on their sum, so no readback is needed.
-    t->slack_ok = false;
-    const int64_t bound = kSlackFactor * int64_t(total) + 8 * nl;
-    if (bound <= int64_t(INT32_MAX)) {
-        if (bound > t->slack_cap) {
-            dfree(t->slack, s);
-            t->slack = nullptr;
-            t->slack_cap = 0;
-            const int64_t want = std::min<int64_t>(bound + bound / 8, int64_t(INT32_MAX));
-            if (dmalloc((void **)&t->slack, size_t(want) * sizeof(Task), s) == hipSuccess)
-                t->slack_cap = want;
-            else
-                (void)hipGetLastError();  // no slack: rebuilds keep two walks
-        }
-        if (t->slack && t->slack_cap >= bound) {
-            k_slack_sizes<<<blocks(nl + 1, 256), 256, 0, s>>>(nl, t->count, t->count);
-            SPHX_HIP(hipGetLastError());
-            SPHX_HIP(rocprim::exclusive_scan(t->scan_tmp, tmp, t->count, t->soff, 0,
-                                             size_t(nl + 1), rocprim::plus<int32_t>(), s));
-            t->slack_ok = true;
-        }
-    }
+    t->n_tasks = st[kTaskTotal];
     SPHX_TRY(leaf_order(t, nl, s));
     t->symmetric = true;
     guard.keep = true;
@@ -765,98 +908,49 @@ sphx_status tasks_build(sphx_ctx *ctx, sphx_grid *g, const sphx_particles *in, h
     return SPHX_OK;
 }
 
-// The tree view of a grid with the periodic box of the context.
-static TreeView tree_view(const sphx_ctx *ctx, const sphx_grid *g)
-{
-    TreeView T;
-    T.lo = g->node_lo;
-    T.hi = g->node_hi;
-    T.r = g->node_r;
-    for (int l = 0; l < kMaxLevels; ++l) {
-        T.level_off[l] = l < g->n_levels ? g->level_off[l] : 0;
-        T.level_cnt[l] = l < g->n_levels ? g->level_cnt[l] : 0;
-    }
-    T.n_levels = g->n_levels;
-    for (int a = 0; a < 3; ++a)
-        T.L[a] = ctx->p.box[a];
-    T.periodic = ctx->p.periodic;
-    return T;
-}
-
 sphx_status tasks_grow(sphx_ctx *ctx, sphx_grid *g, const sphx_particles *in, hipStream_t s,
                        sphx_tasks **out)
 {
     sphx_tasks *t = *out;
     const int64_t nl = g->n_leaves;
-    if (!t || t->grid != g || !t->slack_ok || nl == 0)
+    if (!t || t->grid != g || !t->task || nl == 0)
         return tasks_build(ctx, g, in, s, out);
     t->stream = s;
-    if (!t->off_alt) {
-        if (dmalloc((void **)&t->off_alt, (nl + 1) * sizeof(int32_t), s) != hipSuccess ||
-            dmalloc((void **)&t->dirty, (nl + 1) * sizeof(uint8_t), s) != hipSuccess) {
-            set_error("sphx_tasks_build: out of device memory (growth rebuild)");
-            return SPHX_E_OOM;
-        }
-    }
-    const float scale = float(ctx->p.gamma_k * (1.0 + ctx->p.skin));
-    k_leaf_radius_grow<<<unsigned(nl), 64, 0, s>>>(nl, g->leaf_start, g->hs, scale, g->node_r,
-                                                   t->radius, t->overflow, t->dirty);
-    SPHX_HIP(hipGetLastError());
-    for (int l = 0; l + 1 < g->n_levels; ++l) {
-        int64_t up = g->level_cnt[l + 1];
-        k_tree_radius<<<blocks(up, 128), 128, 0, s>>>(up, g->level_cnt[l],
-                                                        g->node_r + g->level_off[l],
-                                                        g->node_r + g->level_off[l + 1]);
-        SPHX_HIP(hipGetLastError());
-    }
-    const TreeView T = tree_view(ctx, g);
-    // the marked leaves: one walk into their slots, counting; the serial
-    // count for those whose frontier overflowed; the others keep theirs
-    walk_launch<2>(nl, T, g->leaf_org, g->leaf_start, t->off, t->soff, t->count, t->overflow,
-                   t->slack, s, t->dirty);
-    SPHX_HIP(hipGetLastError());
-    k_task_count<<<blocks(nl, 64), 64, 0, s>>>(nl, T, t->overflow, t->count);
-    SPHX_HIP(hipGetLastError());
-    k_keep_counts<<<blocks(nl + 1, 256), 256, 0, s>>>(nl, t->dirty, t->off, t->count);
-    SPHX_HIP(hipGetLastError());
-    size_t tmp = t->scan_tmp_bytes;
-    SPHX_HIP(rocprim::exclusive_scan(t->scan_tmp, tmp, t->count, t->off_alt, 0, size_t(nl + 1),
-                                     rocprim::plus<int32_t>(), s));
-    int32_t *h_total = reinterpret_cast<int32_t *>(ctx->h_pinned + kPinnedBytes - 64);
-    SPHX_HIP(hipMemcpyAsync(h_total, t->off_alt + nl, sizeof(int32_t), hipMemcpyDeviceToHost,
-                            s));
-    SPHX_HIP(wait_stream(ctx, s));
-    const int32_t total = *h_total;
-    if (total < 0) {
-        set_error("sphx_tasks_build: task count overflow");
-        return SPHX_E_INVALID;
-    }
-    if (total > t->cap_alt) {
-        dfree(t->task_alt, s);
-        t->task_alt = nullptr;
-        t->cap_alt = 0;
-        const int64_t cap = int64_t(total) + total / 4 + 64;
-        SPHX_HIP(dmalloc((void **)&t->task_alt, size_t(cap) * sizeof(Task), s));
-        t->cap_alt = cap;
-    }
-    k_copy_grown<<<unsigned(nl), 64, 0, s>>>(nl, t->dirty, t->overflow, t->off, t->off_alt,
-                                             t->soff, t->count, t->task, t->slack, t->task_alt);
-    SPHX_HIP(hipGetLastError());
-    // marked leaves over their slot: walked again straight into the list;
-    // those with an overflowed frontier: the serial fill
-    walk_launch<3>(nl, T, g->leaf_org, g->leaf_start, t->off_alt, t->soff, t->count,
-                   t->overflow, t->task_alt, s, t->dirty);
-    SPHX_HIP(hipGetLastError());
-    k_task_fill<<<blocks(nl, 64), 64, 0, s>>>(nl, T, g->leaf_org, g->leaf_start, t->overflow,
-                                              t->off_alt, t->task_alt);
-    SPHX_HIP(hipGetLastError());
-    std::swap(t->task, t->task_alt);
-    std::swap(t->cap, t->cap_alt);
-    std::swap(t->off, t->off_alt);
-    t->n_tasks = total;
+    SPHX_TRY(radii_launch(ctx, g, t, true, nullptr, s));
+    SPHX_TRY(walk_slots_launch(ctx, g, t, nullptr, s));
+    int64_t st[kTaskStateWords];
+    SPHX_TRY(read_state(ctx, t, s, st));
+    if (st[kTaskOutgrown])
+        return tasks_build(ctx, g, in, s, out);  // a full build, in a new layout if need be
+    t->n_tasks = st[kTaskTotal];
     // (the launch order of the last full build stays: it orders by work,
     // which the few walked leaves hardly move)
     t->symmetric = false;
+    return SPHX_OK;
+}
+
+sphx_status tasks_grow_async(const sphx_ctx *ctx, sphx_grid *g, sphx_tasks *t,
+                             const int32_t *run, hipStream_t s)
+{
+    if (g->n_leaves == 0)
+        return SPHX_OK;
+    SPHX_TRY(radii_launch(ctx, g, t, true, run, s));
+    return walk_slots_launch(ctx, g, t, run, s);
+}
+
+sphx_status tasks_full_async(const sphx_ctx *ctx, sphx_grid *g, sphx_tasks *t,
+                             const int32_t *run, hipStream_t s)
+{
+    if (g->n_leaves == 0)
+        return SPHX_OK;
+    SPHX_TRY(radii_launch(ctx, g, t, false, run, s));
+    return walk_slots_launch(ctx, g, t, run, s);
+}
+
+sphx_status tasks_total_async(const sphx_grid *g, sphx_tasks *t, hipStream_t s)
+{
+    k_task_total<<<1, kTotalThreads, 0, s>>>(g->n_leaves, t->slot, t->end, t->state);
+    SPHX_HIP(hipGetLastError());
     return SPHX_OK;
 }
 

@@ -70,7 +70,8 @@ class StepInfo(C.Structure):
                 ("clamped", C.c_int32), ("n_leaves", C.c_int64), ("n_tasks", C.c_int64),
                 ("list_builds", C.c_int32), ("list_fallback", C.c_int32),
                 ("list_entries", C.c_int64), ("pairs_cellpair", C.c_int64),
-                ("pairs_list", C.c_int64)]
+                ("pairs_list", C.c_int64), ("captured_passes", C.c_int32),
+                ("task_relayouts", C.c_int32)]
 
 
 SYMBOLS = ("sphx_params_default", "sphx_ctx_create", "sphx_ctx_destroy", "sphx_workspace_bytes",

@@ -96,3 +96,32 @@ def test_graph_step_active_subset():
     host = gpu_step(ps)
     g = gpu_step(ps, params={"graph_passes": 8})
     same(host, g, "active")
+
+
+def test_graph_rebuilds_inside():
+    """A clustered set iterated from its generator's h rebuilds its task list
+    during the step. With enough slots every pass runs inside the graph (the
+    rebuilds are walked in place, decided on the device), on every replay,
+    bitwise as pass by pass."""
+    ps = inputs.lognormal_box(16, 6000, 2.0, 11)
+    host = gpu_step(ps)
+    assert host["info"].task_rebuilds >= 1
+    reps = gpu_step(ps, params={"graph_passes": host["info"].passes + 1}, repeat=3)
+    for r, g in enumerate(reps):
+        same(host, g, "replay %d" % r)
+        assert g["info"].captured_passes == g["info"].passes, "replay %d" % r
+        assert g["info"].task_rebuilds >= 1
+
+
+def test_graph_step_outgrowing_the_layout():
+    """h five times too small with leaves of 8: the first rebuild inside the
+    graph outgrows the slots sized at the first build; the graph stops there,
+    the list is laid out anew and the step goes on pass by pass, bitwise as
+    without a graph."""
+    ps = inputs.lattice_box(14, 3, u="logu")
+    ps.h *= np.float32(0.2)
+    kw = {"leaf_max": 8}
+    host = gpu_step(ps, params=kw)
+    g = gpu_step(ps, params=dict(kw, graph_passes=12))
+    same(host, g, "outgrown")
+    assert 0 < g["info"].passes and g["info"].captured_passes < g["info"].passes
