@@ -1,10 +1,10 @@
-#include <algorithm>
-#include <cmath>
 // C-ABI entry points of the sphx library: argument validation, ownership of
 // the opaque handles, and the host side of the h iteration.
 #include <math.h>
 #include <string.h>
 
+#include <algorithm>
+#include <cmath>
 #include <string>
 
 #include "kernel_shapes.h"

@@ -71,6 +71,10 @@ def _run_one(sphx, ctx, req, stream, keep, res: Result):
             st, info = sphx.step(ctx, grid, tasks, dp, out, stream)
             res.status = st
             res.passes = info.passes
+            # wait for the step's last kernels without the interpreter lock
+            # (a tensor read would wait for them holding it, and stall the
+            # other slots' launches meanwhile)
+            stream.synchronize()
             res.interactions = int(out.d["nngb"].to(torch.int64).sum()
                                    + out.f["nforce"].to(torch.int64).sum())
             if keep:
