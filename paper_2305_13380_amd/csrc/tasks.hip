@@ -84,18 +84,28 @@ __device__ __forceinline__ void raise_ancestors(float *__restrict__ node_r, cons
     }
 }
 
-// Full build, first: the radii of the tree's nodes above the leaves cleared.
-__global__ void k_tree_clear(float *__restrict__ r, int64_t n, const int32_t *__restrict__ run)
+// Full build: one level of the tree's radii from the level below.
+__global__ void k_tree_radius(int64_t cnt_up, int64_t cnt_dn, const float *__restrict__ r_dn,
+                              float *__restrict__ r_up, const int32_t *__restrict__ run)
 {
     if (run && !*run)
         return;
-    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
-         i += int64_t(gridDim.x) * blockDim.x)
-        r[i] = 0.0f;
+    int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (c >= cnt_up)
+        return;
+    int64_t e = (c + 1) * kTreeFan;
+    if (e > cnt_dn)
+        e = cnt_dn;
+    float r = 0.0f;
+    for (int64_t k = c * kTreeFan; k < e; ++k)
+        r = fmaxf(r, r_dn[k]);
+    r_up[c] = r;
 }
 
 // Full build: radius = (1 + skin) * gamma_k * max h over the leaf, for every
-// leaf, raised into the tree above it, and every leaf marked for the walk.
+// leaf, and every leaf marked for the walk (the tree above: k_tree_radius,
+// level by level: every leaf raising its ancestors itself would pile
+// thousands of atomics onto the few nodes at the top).
 // Clears the outgrown-slot flag and the asymmetry flag (a full build lists
 // every pair within max(R_I, R_J)).
 __global__ __launch_bounds__(64) void k_leaf_radius(int64_t n_leaves,
@@ -105,7 +115,7 @@ __global__ __launch_bounds__(64) void k_leaf_radius(int64_t n_leaves,
                                                     float *__restrict__ radius,
                                                     uint8_t *__restrict__ overflow,
                                                     uint8_t *__restrict__ dirty,
-                                                    int64_t *__restrict__ state, TreeLevels lv,
+                                                    int64_t *__restrict__ state,
                                                     const int32_t *__restrict__ run)
 {
     if (run && !*run)
@@ -124,7 +134,6 @@ __global__ __launch_bounds__(64) void k_leaf_radius(int64_t n_leaves,
             radius[L] = v;
             dirty[L] = 1;
             overflow[L] = 0;
-            raise_ancestors(node_r, lv, L, v);
         }
     }
 }
@@ -653,24 +662,29 @@ static sphx_status radii_launch(const sphx_ctx *ctx, sphx_grid *g, sphx_tasks *t
 {
     const int64_t nl = g->n_leaves;
     const float scale = float(ctx->p.gamma_k * (1.0 + ctx->p.skin));
-    TreeLevels lv;
-    for (int l = 0; l < kMaxLevels; ++l)
-        lv.off[l] = l < g->n_levels ? g->level_off[l] : 0;
-    lv.n = g->n_levels;
     if (grow) {
+        // (the grown leaves raise their ancestors themselves)
+        TreeLevels lv;
+        for (int l = 0; l < kMaxLevels; ++l)
+            lv.off[l] = l < g->n_levels ? g->level_off[l] : 0;
+        lv.n = g->n_levels;
         k_leaf_radius_grow<<<leaf_grid(nl, run), 64, 0, s>>>(
             nl, g->leaf_start, g->hs, scale, g->node_r, t->radius, t->overflow, t->dirty,
             t->state, lv, run);
-    } else {
-        const int64_t inner = g->n_nodes - nl;
-        k_tree_clear<<<unsigned(std::min<int64_t>((inner + 255) / 256 + 1, 1024)), 256, 0, s>>>(
-            g->node_r + nl, inner, run);
         SPHX_HIP(hipGetLastError());
-        k_leaf_radius<<<leaf_grid(nl, run), 64, 0, s>>>(nl, g->leaf_start, g->hs, scale,
-                                                         g->node_r, t->radius, t->overflow,
-                                                         t->dirty, t->state, lv, run);
+        return SPHX_OK;
     }
+    k_leaf_radius<<<leaf_grid(nl, run), 64, 0, s>>>(nl, g->leaf_start, g->hs, scale, g->node_r,
+                                                     t->radius, t->overflow, t->dirty, t->state,
+                                                     run);
     SPHX_HIP(hipGetLastError());
+    for (int l = 0; l + 1 < g->n_levels; ++l) {
+        const int64_t up = g->level_cnt[l + 1];
+        k_tree_radius<<<blocks(up, 128), 128, 0, s>>>(up, g->level_cnt[l],
+                                                        g->node_r + g->level_off[l],
+                                                        g->node_r + g->level_off[l + 1], run);
+        SPHX_HIP(hipGetLastError());
+    }
     return SPHX_OK;
 }
 
