@@ -551,39 +551,44 @@ __global__ __launch_bounds__(64) void k_task_bfs(int64_t n_leaves, TreeView T,
 // leaf's slot in the previous layout (prev, if any: slots only grow, so a
 // step whose radii rise and fall in a repeating pattern settles on a layout
 // that holds all of it); their 64-bit sum goes to state[kTaskSlots] (the
-// 32-bit scan of the sizes must not wrap).
+// 32-bit scan of the sizes must not wrap), the counts' sum (the tasks the
+// walk into the new slots will write) to state[kTaskTotal].
 __global__ void k_slot_sizes(int64_t n_leaves, const int32_t *__restrict__ count,
                              const int32_t *__restrict__ prev, int32_t *__restrict__ sz,
                              int64_t *__restrict__ state)
 {
     const int64_t I = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    int64_t v = 0;
+    int64_t v = 0, c = 0;
     if (I < n_leaves) {
-        v = int64_t(kSlotFactor) * count[I] + 8;
+        c = count[I];
+        v = int64_t(kSlotFactor) * c + 8;
         const int64_t was = prev ? int64_t(prev[I + 1]) - prev[I] : 0;
         v = v > was ? v : was;
         sz[I] = int32_t(v < int64_t(INT_MAX) ? v : int64_t(INT_MAX));
     } else if (I == n_leaves) {
         sz[I] = 0;
     }
-    for (int o = 32; o > 0; o >>= 1)
+    for (int o = 32; o > 0; o >>= 1) {
         v += __shfl_xor(v, o, 64);
-    if ((threadIdx.x & 63) == 0 && v)
+        c += __shfl_xor(c, o, 64);
+    }
+    if ((threadIdx.x & 63) == 0 && v) {
         atomicAdd(reinterpret_cast<unsigned long long *>(state + kTaskSlots),
                   (unsigned long long)v);
+        atomicAdd(reinterpret_cast<unsigned long long *>(state + kTaskTotal),
+                  (unsigned long long)c);
+    }
 }
 
-// Empty slots of a new layout (end = slot start) and cleared counts.
+// Empty slots of a new layout (end = slot start) and a cleared flag.
 __global__ void k_slots_empty(int64_t n_leaves, const int32_t *__restrict__ slot,
                               int32_t *__restrict__ end, int64_t *__restrict__ state)
 {
     const int64_t I = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (I < n_leaves)
         end[I] = slot[I];
-    if (I == 0) {
+    if (I == 0)
         state[kTaskOutgrown] = 0;
-        state[kTaskTotal] = 0;
-    }
 }
 
 __global__ void k_state_clear(int64_t *__restrict__ state)
@@ -704,13 +709,15 @@ static sphx_status walk_slots_launch(const sphx_ctx *ctx, const sphx_grid *g, sp
     return SPHX_OK;
 }
 
-// The task list's device state, its total summed first, read back
-// (synchronises the stream).
+// The task list's device state, read back (synchronises the stream); with
+// total, state[kTaskTotal] is summed over the slots first.
 static sphx_status read_state(sphx_ctx *ctx, sphx_tasks *t, hipStream_t s,
-                              int64_t st[kTaskStateWords])
+                              int64_t st[kTaskStateWords], bool total = true)
 {
-    k_task_total<<<1, kTotalThreads, 0, s>>>(t->grid->n_leaves, t->slot, t->end, t->state);
-    SPHX_HIP(hipGetLastError());
+    if (total) {
+        k_task_total<<<1, kTotalThreads, 0, s>>>(t->grid->n_leaves, t->slot, t->end, t->state);
+        SPHX_HIP(hipGetLastError());
+    }
     int64_t *h = reinterpret_cast<int64_t *>(ctx->h_pinned + kPinnedBytes - 64);
     SPHX_HIP(hipMemcpyAsync(h, t->state, kTaskStateWords * sizeof(int64_t),
                             hipMemcpyDeviceToHost, s));
@@ -811,7 +818,7 @@ static sphx_status relayout(sphx_ctx *ctx, sphx_grid *g, sphx_tasks *t, hipStrea
     SPHX_HIP(rocprim::exclusive_scan(t->scan_tmp, tmp, t->end, t->slot, 0, size_t(nl + 1),
                                      rocprim::plus<int32_t>(), s));
     int64_t st[kTaskStateWords];
-    SPHX_TRY(read_state(ctx, t, s, st));
+    SPHX_TRY(read_state(ctx, t, s, st, false));
     if (st[kTaskSlots] > int64_t(INT_MAX)) {
         set_error("sphx_tasks_build: more than 2^31 task slots");
         return SPHX_E_INVALID;
@@ -828,12 +835,10 @@ static sphx_status relayout(sphx_ctx *ctx, sphx_grid *g, sphx_tasks *t, hipStrea
     k_slots_empty<<<blocks(nl, 256), 256, 0, s>>>(nl, t->slot, t->end, t->state);
     SPHX_HIP(hipGetLastError());
     t->relayouts++;
+    // every slot holds its leaf's count (the walk below finds the same tasks
+    // as the count above), so nothing is read back after it
     SPHX_TRY(walk_slots_launch(ctx, g, t, nullptr, s));
-    SPHX_TRY(read_state(ctx, t, s, st));
-    if (st[kTaskOutgrown]) {
-        set_error("sphx_tasks_build: a leaf outgrew the slot sized from its own count");
-        return SPHX_E_STATE;
-    }
+    t->n_tasks = st[kTaskTotal];
     return SPHX_OK;
 }
 
@@ -910,11 +915,10 @@ sphx_status tasks_build(sphx_ctx *ctx, sphx_grid *g, const sphx_particles *in, h
         SPHX_TRY(read_state(ctx, t, s, st));
         fits = st[kTaskOutgrown] == 0;
     }
-    if (!fits) {
+    if (fits)
+        t->n_tasks = st[kTaskTotal];
+    else
         SPHX_TRY(relayout(ctx, g, t, s));
-        SPHX_TRY(read_state(ctx, t, s, st));
-    }
-    t->n_tasks = st[kTaskTotal];
     SPHX_TRY(leaf_order(t, nl, s));
     t->symmetric = true;
     guard.keep = true;
