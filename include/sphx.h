@@ -261,6 +261,22 @@ size_t sphx_workspace_bytes(const sphx_params *p, int64_t n);
  * *out is released with sphx_grid_destroy. */
 sphx_status sphx_grid_build(sphx_ctx *ctx, const sphx_particles *in, void *stream,
                             sphx_grid **out);
+
+/* Grid build over several independent particle sets at once, for batching
+ * small requests into one step (the serving loop's batches): set b is the
+ * particles [set_start[b], set_start[b + 1]) of *in, each set a box of the
+ * context's size and periodicity of its own. Each set is sorted and split
+ * into leaves on its own (no leaf holds two sets), and tasks built on this
+ * grid pair leaves of one set only, so every density, ghost and force output
+ * of a set is bitwise the one a grid of that set alone gives. A step's or
+ * force pass's d_sums6 then receives 6 sums per set (set b's at
+ * d_sums6[6 b]). set_start: host array of n_sets + 1 offsets from 0 to
+ * in->n, non-decreasing (empty sets allowed); n_sets 1..65536; read before
+ * the call returns. Otherwise as sphx_grid_build; E_INVALID on bad offsets.
+ * sphx_force_noalloc refuses such grids with more than one set. */
+sphx_status sphx_grid_build_sets(sphx_ctx *ctx, const sphx_particles *in,
+                                 const int64_t *set_start, int32_t n_sets, void *stream,
+                                 sphx_grid **out);
 void sphx_grid_destroy(sphx_grid *grid);
 
 /* Tasks build (Section 2.2 self and pair tasks): for every leaf, the list of
@@ -316,7 +332,8 @@ sphx_status sphx_ghost(sphx_ctx *ctx, sphx_grid *grid, const sphx_tasks *tasks,
  * smoothed pressure and A the grad-h term F) of every particle, including
  * inactive ones. If
  * d_sums6 != NULL it receives, in FP64, sum m a (3), sum m (v.a + du/dt),
- * sum m |a|, sum m |du/dt| over the active particles. Asynchronous. */
+ * sum m |a|, sum m |du/dt| over the active particles (per set, 6 each, on a
+ * grid of several sets). Asynchronous. */
 sphx_status sphx_force(sphx_ctx *ctx, const sphx_grid *grid, const sphx_tasks *tasks,
                        const sphx_particles *in, const sphx_density_out *dens,
                        const sphx_ghost_out *gst, sphx_force_out *out, double *d_sums6,

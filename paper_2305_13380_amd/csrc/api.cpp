@@ -289,6 +289,32 @@ sphx_status sphx_grid_build(sphx_ctx *ctx, const sphx_particles *in, void *strea
     return grid_build(ctx, in, as_stream(stream), out);
 }
 
+sphx_status sphx_grid_build_sets(sphx_ctx *ctx, const sphx_particles *in,
+                                 const int64_t *set_start, int32_t n_sets, void *stream,
+                                 sphx_grid **out)
+{
+    if (!ctx || !out || !set_start) {
+        set_error("sphx_grid_build_sets: NULL argument");
+        return SPHX_E_INVALID;
+    }
+    SPHX_TRY(check_particles(in, false));
+    if (n_sets < 1 || n_sets > kMaxSets) {
+        set_error("sphx_grid_build_sets: n_sets must be 1.." + std::to_string(kMaxSets));
+        return SPHX_E_INVALID;
+    }
+    if (set_start[0] != 0 || set_start[n_sets] != in->n) {
+        set_error("sphx_grid_build_sets: set_start must run from 0 to n");
+        return SPHX_E_INVALID;
+    }
+    for (int32_t b = 0; b < n_sets; ++b)
+        if (set_start[b + 1] < set_start[b]) {
+            set_error("sphx_grid_build_sets: set_start must not decrease");
+            return SPHX_E_INVALID;
+        }
+    SPHX_HIP(hipSetDevice(ctx->device));
+    return grid_build(ctx, in, as_stream(stream), out, set_start, n_sets);
+}
+
 void sphx_grid_destroy(sphx_grid *grid) { grid_free(grid); }
 
 sphx_status sphx_tasks_build(sphx_ctx *ctx, sphx_grid *grid, const sphx_particles *in,
@@ -552,6 +578,11 @@ sphx_status sphx_force_noalloc(sphx_ctx *ctx, const sphx_grid *grid, const sphx_
         set_error("sphx_force_noalloc: the grid has " + std::to_string(grid->n_leaves) +
                   " leaf cells, more than the " + std::to_string(kNoallocLeaves) +
                   " its fixed workspace holds (use sphx_force)");
+        return SPHX_E_INVALID;
+    }
+    if (grid->n_sets > 1) {
+        set_error("sphx_force_noalloc: the grid holds several particle sets (its fixed "
+                  "workspace holds the reduction of one; use sphx_force)");
         return SPHX_E_INVALID;
     }
     if (!ctx->noalloc_sums) {

@@ -504,12 +504,15 @@ __global__ __launch_bounds__(64) void k_leaf_hmax(int64_t n_leaves,
         hmax[L] = gamma_k * v;
 }
 
-// Fixed-order FP64 reduction of the per-leaf partial sums in two levels:
-// block b of kSumParts sums its contiguous range of leaves (threads stride the
-// range, then a tree over the block), and one block sums the parts in order.
+// Fixed-order FP64 reduction of the per-leaf partial sums in two levels, per
+// particle set: block b of kSumParts sums its contiguous range of the set's
+// leaves (threads stride the range, then a tree over the block), and one
+// block per set sums its parts in order. A set's sums so do not depend on the
+// other sets in the grid.
 constexpr int kSumParts = 128;
 
 __global__ __launch_bounds__(256) void k_sum_leaves(int64_t n_leaves,
+                                                    const int32_t *__restrict__ set_leaf,
                                                     const double *__restrict__ fsum,
                                                     double *__restrict__ part,
                                                     const int32_t *__restrict__ gate)
@@ -518,9 +521,12 @@ __global__ __launch_bounds__(256) void k_sum_leaves(int64_t n_leaves,
         return;
     __shared__ double red[6][256];
     const int t = threadIdx.x;
-    const int64_t per = (n_leaves + kSumParts - 1) / kSumParts;
-    const int64_t a0 = int64_t(blockIdx.x) * per;
-    const int64_t a1 = min(n_leaves, a0 + per);
+    // set blockIdx.y's leaves (all of them with one set)
+    const int64_t lo = set_leaf ? set_leaf[blockIdx.y] : 0;
+    const int64_t hi = set_leaf ? set_leaf[blockIdx.y + 1] : n_leaves;
+    const int64_t per = (hi - lo + kSumParts - 1) / kSumParts;
+    const int64_t a0 = lo + int64_t(blockIdx.x) * per;
+    const int64_t a1 = min(hi, a0 + per);
     double a[6] = {0, 0, 0, 0, 0, 0};
     for (int64_t L = a0 + t; L < a1; L += 256)
         for (int k = 0; k < 6; ++k)
@@ -535,9 +541,10 @@ __global__ __launch_bounds__(256) void k_sum_leaves(int64_t n_leaves,
         __syncthreads();
     }
     if (t < 6)
-        part[6 * blockIdx.x + t] = red[t][0];
+        part[6 * (int64_t(blockIdx.y) * kSumParts + blockIdx.x) + t] = red[t][0];
 }
 
+// One block per set: the set's parts summed in order.
 __global__ __launch_bounds__(kSumParts) void k_sum_parts(const double *__restrict__ part,
                                                          double *__restrict__ out,
                                                          const int32_t *__restrict__ gate)
@@ -546,8 +553,9 @@ __global__ __launch_bounds__(kSumParts) void k_sum_parts(const double *__restric
         return;
     __shared__ double red[6][kSumParts];
     const int t = threadIdx.x;
+    const double *p = part + 6 * int64_t(blockIdx.x) * kSumParts;
     for (int k = 0; k < 6; ++k)
-        red[k][t] = part[6 * t + k];
+        red[k][t] = p[6 * t + k];
     __syncthreads();
     for (int w = kSumParts / 2; w > 0; w >>= 1) {
         if (t < w)
@@ -556,15 +564,15 @@ __global__ __launch_bounds__(kSumParts) void k_sum_parts(const double *__restric
         __syncthreads();
     }
     if (t < 6)
-        out[t] = red[t][0];
+        out[6 * blockIdx.x + t] = red[t][0];
 }
 
-// Clears the six FP64 sums of an empty particle set (a kernel, not a memset
-// node, so that the call can be recorded in a graph).
-__global__ void k_zero_sums(double *__restrict__ out)
+// Clears the six FP64 sums of every set of an empty grid (a kernel, not a
+// memset node, so that the call can be recorded in a graph).
+__global__ void k_zero_sums(double *__restrict__ out, int64_t n)
 {
-    if (threadIdx.x < 6)
-        out[threadIdx.x] = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x)
+        out[i] = 0.0;
 }
 
 }  // namespace
@@ -638,7 +646,7 @@ sphx_status force_launch(const sphx_ctx *ctx, const sphx_grid *g, const sphx_tas
 {
     if (g->n_leaves == 0) {
         if (sums6) {
-            k_zero_sums<<<1, 64, 0, s>>>(sums6);
+            k_zero_sums<<<1, 64, 0, s>>>(sums6, 6 * int64_t(g->n_sets));
             SPHX_HIP(hipGetLastError());
         }
         return SPHX_OK;
@@ -693,10 +701,12 @@ sphx_status force_launch(const sphx_ctx *ctx, const sphx_grid *g, const sphx_tas
     if (prof)
         SPHX_HIP(prof->end(1, s));
     if (sums6) {
+        // the six sums of every set (one set: of the whole grid)
         double *part = fsum + 6 * g->n_leaves;
-        k_sum_leaves<<<kSumParts, 256, 0, s>>>(g->n_leaves, fsum, part, gate);
+        k_sum_leaves<<<dim3(kSumParts, unsigned(g->n_sets)), 256, 0, s>>>(
+            g->n_leaves, g->set_leaf, fsum, part, gate);
         SPHX_HIP(hipGetLastError());
-        k_sum_parts<<<1, kSumParts, 0, s>>>(part, sums6, gate);
+        k_sum_parts<<<unsigned(g->n_sets), kSumParts, 0, s>>>(part, sums6, gate);
         SPHX_HIP(hipGetLastError());
     }
     return SPHX_OK;

@@ -1,8 +1,12 @@
 // Grid build: Morton sort and leaf cells (Section 2.2 nested grids; Section
 // 9.1 depth-first binning, here as a radix sort on a 63-bit Morton key, whose
 // order is a depth-first order of the octree).
+#include <algorithm>
+#include <vector>
+
 #include <rocprim/device/device_radix_sort.hpp>
 #include <rocprim/device/device_scan.hpp>
+#include <rocprim/device/device_segmented_radix_sort.hpp>
 
 #include "pairs.h"
 
@@ -96,25 +100,34 @@ __device__ __forceinline__ int64_t lower_prefix(const uint64_t *k, int64_t lo, i
 // octree block holds <= cap particles; that block's population is measured
 // inside a window of 2 cap + 2 sorted keys around s (a population above cap
 // always shows as more than cap keys inside the window).
+// With several particle sets (set_of non-null) each set is split on its own:
+// its first particle starts a leaf and the windows stay inside the set.
 __global__ void k_leaf_flags(int64_t n, const uint64_t *__restrict__ k, int cap,
-                             uint32_t *__restrict__ flag)
+                             uint32_t *__restrict__ flag, const int32_t *__restrict__ set_of,
+                             const int32_t *__restrict__ set_start)
 {
     int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (s >= n)
         return;
-    if (s == 0) {
-        flag[0] = 1;
+    int64_t lo_b = 0, hi_b = n;
+    if (set_of) {
+        const int32_t b = set_of[s];
+        lo_b = set_start[b];
+        hi_b = set_start[b + 1];
+    }
+    if (s == lo_b) {
+        flag[s] = 1;
         return;
     }
     const uint64_t b = k[s];
     const int shift = 3 * (kMortonBits - common_levels(k[s - 1], b));
     const uint64_t p = b >> shift;
     int64_t wlo = s - 1 - cap;
-    if (wlo < 0)
-        wlo = 0;
+    if (wlo < lo_b)
+        wlo = lo_b;
     int64_t whi = s + cap + 1;
-    if (whi > n)
-        whi = n;
+    if (whi > hi_b)
+        whi = hi_b;
     int64_t lo = lower_prefix(k, wlo, s, p, shift);
     int64_t hi = lower_prefix(k, s, whi, p + 1, shift);
     flag[s] = (hi - lo > cap) ? 1u : 0u;
@@ -160,16 +173,23 @@ __global__ void k_oct_index(int64_t n, const uint32_t *__restrict__ flag,
 __global__ void k_oct_parent(int64_t n, const uint64_t *__restrict__ k,
                              const int32_t *__restrict__ oct_start,
                              const int32_t *__restrict__ n_oct, int32_t *__restrict__ par_lvl,
-                             uint64_t *__restrict__ par_pfx)
+                             uint64_t *__restrict__ par_pfx, const int32_t *__restrict__ set_of,
+                             const int32_t *__restrict__ set_start)
 {
     int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (q >= *n_oct)
         return;
     int64_t a = oct_start[q], b = oct_start[q + 1];
+    int64_t lo_b = 0, hi_b = n;  // the leaf's set (a set's ends are like the array's)
+    if (set_of) {
+        const int32_t st = set_of[a];
+        lo_b = set_start[st];
+        hi_b = set_start[st + 1];
+    }
     int lv = -1;
-    if (a > 0)
+    if (a > lo_b)
         lv = common_levels(k[a - 1], k[a]);
-    if (b < n) {
+    if (b < hi_b) {
         int l2 = common_levels(k[b - 1], k[b]);
         lv = l2 > lv ? l2 : lv;
     }
@@ -187,18 +207,21 @@ __global__ void k_pack_cells(int64_t n, const uint64_t *__restrict__ k,
                              const int32_t *__restrict__ par_lvl,
                              const uint64_t *__restrict__ par_pfx,
                              const uint32_t *__restrict__ oct_incl, int cap,
-                             uint32_t *__restrict__ cell_flag)
+                             uint32_t *__restrict__ cell_flag,
+                             const int32_t *__restrict__ set_of,
+                             const int32_t *__restrict__ set_start)
 {
     int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (q >= *n_oct)
         return;
     const int lv = par_lvl[q];
     const uint64_t pf = par_pfx[q];
+    const int32_t my_set = set_of ? set_of[oct_start[q]] : 0;
     bool start;
     if (lv == kMortonBits) {
         // identical keys: leaves are single particles
         int64_t a = oct_start[q];
-        int64_t lo = 0, hi = a;
+        int64_t lo = set_of ? set_start[my_set] : 0, hi = a;
         while (lo < hi) {
             int64_t mid = (lo + hi) >> 1;
             if (k[mid] < k[a])
@@ -210,7 +233,8 @@ __global__ void k_pack_cells(int64_t n, const uint64_t *__restrict__ k,
         start = ((q - run_first_leaf) % cap) == 0;
     } else {
         int64_t r = q;
-        while (r > 0 && q - r < 8 && par_lvl[r - 1] == lv && par_pfx[r - 1] == pf && lv >= 0)
+        while (r > 0 && q - r < 8 && par_lvl[r - 1] == lv && par_pfx[r - 1] == pf && lv >= 0 &&
+               (!set_of || set_of[oct_start[r - 1]] == my_set))
             --r;
         int acc = 0;
         start = true;
@@ -317,6 +341,42 @@ __global__ void k_tree_level(int64_t cnt_up, int64_t cnt_dn, const double *__res
 // Start of an h iteration: mark the active particles and copy h into sorted
 // order (with mark == nullptr only the copy).
 // The inverse of the sort's permutation: caller index -> sorted index.
+// Set of every sorted particle (sets keep their ranges through the sort):
+// the last b with set_start[b] <= s.
+__global__ void k_set_of(int64_t n, const int32_t *__restrict__ set_start, int32_t n_sets,
+                         int32_t *__restrict__ set_of)
+{
+    const int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (s >= n)
+        return;
+    int32_t lo = 0, hi = n_sets;  // set_start[lo] <= s < set_start[hi]
+    while (hi - lo > 1) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (set_start[mid] <= s)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    set_of[s] = lo;
+}
+
+// First leaf of every set (an empty set: the next set's first leaf) and the
+// set of every leaf.
+__global__ void k_set_leaves(int64_t n, int32_t n_sets, const int32_t *__restrict__ set_start,
+                             const int32_t *__restrict__ leaf_of,
+                             const int32_t *__restrict__ leaf_start,
+                             const int32_t *__restrict__ set_of,
+                             const int32_t *__restrict__ n_leaves,
+                             int32_t *__restrict__ set_leaf, int32_t *__restrict__ leaf_set)
+{
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int32_t nl = *n_leaves;
+    if (i <= n_sets)
+        set_leaf[i] = set_start[i] < n ? leaf_of[set_start[i]] : nl;
+    if (i < nl)
+        leaf_set[i] = set_of[leaf_start[i]];
+}
+
 __global__ void k_invert(int64_t n, const int32_t *__restrict__ perm, int32_t *__restrict__ inv)
 {
     const int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -377,7 +437,8 @@ void grid_free(sphx_grid *g)
                     g->node_hi, g->node_r,   g->fsum,     g->sort_tmp, g->keys_in, g->idx_in,
                     g->flags,   g->d_status, g->hs,       g->d0,       g->d1,     g->d2,
                     g->lrad,    g->lcnt,     g->lcap,     g->lboff,    g->lst,    g->lscan_tmp,
-                    g->leaf_ext, g->leaf_hmax, g->hlo, g->hhi};
+                    g->leaf_ext, g->leaf_hmax, g->hlo, g->hhi, g->set_start, g->set_of,
+                    g->set_leaf, g->leaf_set};
     for (void *p : ptrs)
         dfree(p, g->stream);
     delete g;
@@ -403,7 +464,8 @@ sphx_status refresh_h(sphx_grid *g, const sphx_particles *in, hipStream_t s)
     return SPHX_OK;
 }
 
-sphx_status grid_build(sphx_ctx *ctx, const sphx_particles *in, hipStream_t s, sphx_grid **out)
+sphx_status grid_build(sphx_ctx *ctx, const sphx_particles *in, hipStream_t s, sphx_grid **out,
+                       const int64_t *sets, int32_t n_sets)
 {
     const sphx_params &P = ctx->p;
     const int64_t n = in->n;
@@ -412,6 +474,7 @@ sphx_status grid_build(sphx_ctx *ctx, const sphx_particles *in, hipStream_t s, s
     g->ctx = ctx;
     g->stream = s;
     g->n = n;
+    g->n_sets = sets ? n_sets : 1;
     struct Guard {
         sphx_grid *g;
         bool keep = false;
@@ -444,12 +507,26 @@ sphx_status grid_build(sphx_ctx *ctx, const sphx_particles *in, hipStream_t s, s
     SPHX_TRY(dalloc(&g->d1, n, s));
     if (smoothed_pressure(P.flavour))
         SPHX_TRY(dalloc(&g->d2, n, s));
+    if (sets) {
+        std::vector<int32_t> h_sets(size_t(n_sets) + 1);
+        for (int32_t b = 0; b <= n_sets; ++b)
+            h_sets[b] = int32_t(sets[b]);
+        SPHX_TRY(dalloc(&g->set_start, n_sets + 1, s));
+        SPHX_TRY(dalloc(&g->set_leaf, n_sets + 1, s));
+        SPHX_HIP(hipMemcpyAsync(g->set_start, h_sets.data(), h_sets.size() * sizeof(int32_t),
+                                hipMemcpyHostToDevice, s));
+        // (the copy reads the host array before this call returns)
+        SPHX_HIP(hipStreamSynchronize(s));
+    }
 
     if (n == 0) {
         g->n_leaves = 0;
         g->n_levels = 0;
         SPHX_TRY(dalloc(&g->leaf_start, 1, s));
         SPHX_HIP(hipMemsetAsync(g->leaf_start, 0, sizeof(int32_t), s));
+        if (sets)
+            SPHX_HIP(hipMemsetAsync(g->set_leaf, 0, (size_t(n_sets) + 1) * sizeof(int32_t), s));
+        SPHX_TRY(dalloc(&g->fsum, 6 * 128 * int64_t(g->n_sets), s));
         guard.keep = true;
         *out = g;
         return SPHX_OK;
@@ -461,24 +538,40 @@ sphx_status grid_build(sphx_ctx *ctx, const sphx_particles *in, hipStream_t s, s
                                            g->d_status);
     SPHX_HIP(hipGetLastError());
 
-    // Stable LSD radix sort of (key, caller index) on the 63 key bits.
+    // Stable LSD radix sort of (key, caller index) on the 63 key bits (each
+    // set within its own range).
     size_t tmp = 0;
-    SPHX_HIP(rocprim::radix_sort_pairs(nullptr, tmp, g->keys_in, g->keys, g->idx_in, g->perm,
-                                       size_t(n), 0, 63, s));
+    if (sets)
+        SPHX_HIP(rocprim::segmented_radix_sort_pairs(
+            nullptr, tmp, g->keys_in, g->keys, g->idx_in, g->perm, unsigned(n), unsigned(n_sets),
+            g->set_start, g->set_start + 1, 0, 63, s));
+    else
+        SPHX_HIP(rocprim::radix_sort_pairs(nullptr, tmp, g->keys_in, g->keys, g->idx_in,
+                                           g->perm, size_t(n), 0, 63, s));
     size_t tmp2 = 0;
     SPHX_HIP(rocprim::inclusive_scan(nullptr, tmp2, g->flags, g->flags + n, size_t(n),
                                      rocprim::plus<uint32_t>(), s));
     g->sort_tmp_bytes = tmp > tmp2 ? tmp : tmp2;
     SPHX_HIP(dmalloc(&g->sort_tmp, g->sort_tmp_bytes, s));
-    SPHX_HIP(rocprim::radix_sort_pairs(g->sort_tmp, tmp, g->keys_in, g->keys, g->idx_in, g->perm,
-                                       size_t(n), 0, 63, s));
+    if (sets) {
+        SPHX_HIP(rocprim::segmented_radix_sort_pairs(
+            g->sort_tmp, tmp, g->keys_in, g->keys, g->idx_in, g->perm, unsigned(n),
+            unsigned(n_sets), g->set_start, g->set_start + 1, 0, 63, s));
+        SPHX_TRY(dalloc(&g->set_of, n, s));
+        k_set_of<<<blocks(n, 256), 256, 0, s>>>(n, g->set_start, n_sets, g->set_of);
+        SPHX_HIP(hipGetLastError());
+    } else {
+        SPHX_HIP(rocprim::radix_sort_pairs(g->sort_tmp, tmp, g->keys_in, g->keys, g->idx_in,
+                                           g->perm, size_t(n), 0, 63, s));
+    }
     // the sort's input indices are not needed again: the inverse goes there
     g->inv = g->idx_in;
     k_invert<<<blocks(n, 256), 256, 0, s>>>(n, g->perm, g->inv);
     SPHX_HIP(hipGetLastError());
 
     const int cap = P.leaf_max;
-    k_leaf_flags<<<blocks(n, 256), 256, 0, s>>>(n, g->keys, cap, g->flags);
+    k_leaf_flags<<<blocks(n, 256), 256, 0, s>>>(n, g->keys, cap, g->flags, g->set_of,
+                                                g->set_start);
     SPHX_HIP(hipGetLastError());
     SPHX_HIP(rocprim::inclusive_scan(g->sort_tmp, tmp2, g->flags, g->flags + n, size_t(n),
                                      rocprim::plus<uint32_t>(), s));
@@ -507,7 +600,7 @@ sphx_status grid_build(sphx_ctx *ctx, const sphx_particles *in, hipStream_t s, s
                                                g->d_status + 2);
     SPHX_HIP(hipGetLastError());
     k_oct_parent<<<blocks(n, 256), 256, 0, s>>>(n, g->keys, g->leaf_start, g->d_status + 2,
-                                                par_lvl, par_pfx);
+                                                par_lvl, par_pfx, g->set_of, g->set_start);
     SPHX_HIP(hipGetLastError());
     // keep the leaf scan for the identical-key case: copy it out of the way
     SPHX_HIP(hipMemcpyAsync(g->keys_in, g->flags + n, size_t(n) * sizeof(uint32_t),
@@ -516,7 +609,7 @@ sphx_status grid_build(sphx_ctx *ctx, const sphx_particles *in, hipStream_t s, s
     k_pack_cells<<<blocks(n, 256), 256, 0, s>>>(n, g->keys, g->leaf_start, g->d_status + 2,
                                                 par_lvl, par_pfx,
                                                 reinterpret_cast<uint32_t *>(g->keys_in), cap,
-                                                g->flags);
+                                                g->flags, g->set_of, g->set_start);
     SPHX_HIP(hipGetLastError());
     SPHX_HIP(rocprim::inclusive_scan(g->sort_tmp, tmp2, g->flags, g->flags + n, size_t(n),
                                      rocprim::plus<uint32_t>(), s));
@@ -554,7 +647,15 @@ sphx_status grid_build(sphx_ctx *ctx, const sphx_particles *in, hipStream_t s, s
     SPHX_TRY(dalloc(&g->node_lo, 3 * off, s));
     SPHX_TRY(dalloc(&g->node_hi, 3 * off, s));
     SPHX_TRY(dalloc(&g->node_r, off, s));
-    SPHX_TRY(dalloc(&g->fsum, 6 * (nl + 128), s));  // + the parts of the sums' reduction
+    // + the parts of each set's reduction of the sums
+    SPHX_TRY(dalloc(&g->fsum, 6 * (nl + 128 * int64_t(g->n_sets)), s));
+    if (sets) {
+        SPHX_TRY(dalloc(&g->leaf_set, nl > 0 ? nl : 1, s));
+        k_set_leaves<<<blocks(std::max<int64_t>(nl, int64_t(n_sets) + 1), 256), 256, 0, s>>>(
+            n, n_sets, g->set_start, g->leaf_of, g->leaf_start, g->set_of, g->d_status + 1,
+            g->set_leaf, g->leaf_set);
+        SPHX_HIP(hipGetLastError());
+    }
 
     k_leaf_setup<<<unsigned(nl), 64, 0, s>>>(nl, g->leaf_start, g->perm, in->x, in->y, in->z,
                                              in->vx, in->vy, in->vz, in->m, in->u, in->alpha_v,

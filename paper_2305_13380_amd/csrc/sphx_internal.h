@@ -78,6 +78,8 @@ constexpr int kTaskTotal = 1;
 constexpr int kTaskAsym = 2;
 constexpr int kTaskSlots = 3;
 constexpr int kTaskStateWords = 4;
+// Most particle sets one grid holds (sphx_grid_build_sets).
+constexpr int32_t kMaxSets = 1 << 16;
 
 }  // namespace sphx
 
@@ -160,8 +162,18 @@ struct sphx_grid {
     double *node_hi;    // 3 * n_nodes
     float *node_r;      // search radius of the node (max over its leaves), from tasks build
 
-    double *fsum;       // 6 * (n_leaves + 128) FP64 partial sums of the force pass, then
-                        // the 128 parts of their reduction
+    double *fsum;       // 6 * (n_leaves + 128 n_sets) FP64 partial sums of the force
+                        // pass, then the 128 parts of each set's reduction
+
+    // Independent particle sets in one grid (sphx_grid_build_sets): set b is
+    // the caller's particles [set_start[b], set_start[b + 1]), sorted within
+    // itself; no leaf holds particles of two sets and no task pairs two sets.
+    // One set: n_sets = 1 and the arrays below are null.
+    int32_t n_sets;
+    int32_t *set_start;  // n_sets + 1, device (the caller's offsets)
+    int32_t *set_of;     // n: set of each sorted particle
+    int32_t *set_leaf;   // n_sets + 1: first leaf of each set
+    int32_t *leaf_set;   // n_leaves: set of each leaf
 
     // Per-receiver neighbour lists of the h iteration (sorted order). The
     // receivers of 64-block b (sorted indices 64b .. 64b+63) own entries
@@ -231,7 +243,9 @@ namespace sphx {
 hipError_t wait_stream(sphx_ctx *ctx, hipStream_t s);
 
 // grid.hip
-sphx_status grid_build(sphx_ctx *ctx, const sphx_particles *in, hipStream_t s, sphx_grid **out);
+// sets: null (one set), else n_sets + 1 host offsets (validated by the caller).
+sphx_status grid_build(sphx_ctx *ctx, const sphx_particles *in, hipStream_t s, sphx_grid **out,
+                       const int64_t *sets = nullptr, int32_t n_sets = 1);
 void grid_free(sphx_grid *g);
 sphx_status iter_reset(sphx_grid *g, const sphx_particles *in, hipStream_t s);
 sphx_status refresh_h(sphx_grid *g, const sphx_particles *in, hipStream_t s);

@@ -186,7 +186,30 @@ struct TreeView {
     int n_levels;
     double L[3];
     int periodic;
+    // several particle sets: the first leaf of each set and the set of each
+    // leaf (null with one set); a walk stays inside its leaf's set
+    const int32_t *set_leaf, *leaf_set;
 };
+
+// The leaves [la, lb) a walk from leaf I may pair it with: its own set's.
+__device__ __forceinline__ void set_range(const TreeView &T, int64_t I, int64_t &la, int64_t &lb)
+{
+    la = 0;
+    lb = T.level_cnt[0];
+    if (T.leaf_set) {
+        const int32_t b = T.leaf_set[I];
+        la = T.set_leaf[b];
+        lb = T.set_leaf[b + 1];
+    }
+}
+
+// Whether node c of level lev (the leaves [c 8^lev, (c + 1) 8^lev)) holds a
+// leaf of [la, lb).
+__device__ __forceinline__ bool node_in_range(int lev, int64_t c, int64_t la, int64_t lb)
+{
+    const int64_t first = c << (3 * lev), end = (c + 1) << (3 * lev);
+    return first < lb && end > la;
+}
 
 // Gap between [alo, ahi] and [blo, bhi] + s*L along one axis, for the shifts
 // s in {-1, 0, 1} (periodic) or {0}.
@@ -287,6 +310,8 @@ __device__ void walk(const TreeView &T, int64_t I, Emit &&emit)
     const double *ilo = T.lo + 3 * I, *ihi = T.hi + 3 * I;
     const double alo[3] = {ilo[0], ilo[1], ilo[2]}, ahi[3] = {ihi[0], ihi[1], ihi[2]};
     const float RI = T.r[I];
+    int64_t la, lb;
+    set_range(T, I, la, lb);
     // stack of (level, node) packed as level * 2^40 + node
     int64_t stack[kTreeFan * kMaxLevels + 8];
     int sp = 0;
@@ -300,7 +325,7 @@ __device__ void walk(const TreeView &T, int64_t I, Emit &&emit)
         int64_t node = T.level_off[lev] + c;
         double R;
         double g[3][3];
-        if (!node_near(T, alo, ahi, RI, node, g, R))
+        if (!node_in_range(lev, c, la, lb) || !node_near(T, alo, ahi, RI, node, g, R))
             continue;
         if (lev == 0) {
             emit_shifts(g, R, [&](int, int sx, int sy, int sz) { emit(c, sx, sy, sz); });
@@ -415,6 +440,8 @@ __device__ __forceinline__ void bfs_leaf(int64_t I, const TreeView &T,
     const double alo[3] = {T.lo[3 * I], T.lo[3 * I + 1], T.lo[3 * I + 2]};
     const double ahi[3] = {T.hi[3 * I], T.hi[3 * I + 1], T.hi[3 * I + 2]};
     const float RI = T.r[I];
+    int64_t la, lb;
+    set_range(T, I, la, lb);
     const int top = T.n_levels - 1;
     int cur = 0;
     int ncur = int(T.level_cnt[top]);
@@ -455,7 +482,8 @@ __device__ __forceinline__ void bfs_leaf(int64_t I, const TreeView &T,
             // a tree of one level: the frontier holds the leaves themselves
             for (int base = 0; base < ncur; base += 64) {
                 const int idx = base + lane;
-                emit_round(idx < ncur, idx < ncur ? int32_t(front[cur][idx]) : 0);
+                const int32_t J = idx < ncur ? int32_t(front[cur][idx]) : 0;
+                emit_round(idx < ncur && J >= la && J < lb, J);
             }
             break;
         }
@@ -469,7 +497,8 @@ __device__ __forceinline__ void bfs_leaf(int64_t I, const TreeView &T,
                 const int k = base + (lane >> 3);
                 const int64_t child =
                     k < ncur ? int64_t(front[cur][k]) * kTreeFan + (lane & 7) : n0;
-                emit_round(child < n0, child < n0 ? int32_t(child) : 0);
+                const bool in = child < n0 && child >= la && child < lb;
+                emit_round(in, in ? int32_t(child) : 0);
             }
             break;
         }
@@ -485,7 +514,7 @@ __device__ __forceinline__ void bfs_leaf(int64_t I, const TreeView &T,
             int64_t child = 0;
             if (k < ncur) {
                 child = int64_t(front[cur][k]) * kTreeFan + c;
-                if (child < cnt_dn) {
+                if (child < cnt_dn && node_in_range(lev - 1, child, la, lb)) {
                     double g[3][3], R;
                     keep = node_near(T, alo, ahi, RI, off_dn + child, g, R);
                 }
@@ -639,6 +668,8 @@ static TreeView tree_view(const sphx_ctx *ctx, const sphx_grid *g)
     for (int a = 0; a < 3; ++a)
         T.L[a] = ctx->p.box[a];
     T.periodic = ctx->p.periodic;
+    T.set_leaf = g->set_leaf;
+    T.leaf_set = g->leaf_set;
     return T;
 }
 

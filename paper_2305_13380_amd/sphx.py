@@ -81,7 +81,7 @@ SYMBOLS = ("sphx_params_default", "sphx_ctx_create", "sphx_ctx_destroy", "sphx_w
            "sphx_profile_read", "sphx_autotune", "sphx_params_set_kernel", "sphx_fof",
            "sphx_gravity", "sphx_alpha_v_update", "sphx_force_noalloc", "sphx_gradient",
            "sphx_alpha_c_update", "sphx_timestep", "sphx_kick", "sphx_drift",
-           "sphx_probe_read")
+           "sphx_probe_read", "sphx_grid_build_sets")
 
 _LIB = None
 
@@ -117,6 +117,7 @@ def _load():
     L.sphx_workspace_bytes.argtypes = [P(Params), i64]
     L.sphx_workspace_bytes.restype = C.c_size_t
     L.sphx_grid_build.argtypes = [vp, P(Particles), vp, P(vp)]
+    L.sphx_grid_build_sets.argtypes = [vp, P(Particles), P(C.c_int64), i32, vp, P(vp)]
     L.sphx_grid_destroy.argtypes = [vp]
     L.sphx_grid_destroy.restype = None
     L.sphx_tasks_build.argtypes = [vp, vp, P(Particles), vp, P(vp)]
@@ -151,7 +152,8 @@ def _load():
     L.sphx_profile_read.restype = i32
     L.sphx_last_error.argtypes = []
     L.sphx_last_error.restype = C.c_char_p
-    for name in ("sphx_ctx_create", "sphx_grid_build", "sphx_tasks_build", "sphx_iter_reset",
+    for name in ("sphx_ctx_create", "sphx_grid_build", "sphx_grid_build_sets",
+                 "sphx_tasks_build", "sphx_iter_reset",
                  "sphx_density", "sphx_ghost", "sphx_force", "sphx_step", "sphx_force_noalloc",
                  "sphx_gradient", "sphx_alpha_c_update", "sphx_timestep", "sphx_kick",
                  "sphx_drift"):
@@ -257,6 +259,26 @@ class DeviceParticles:
             np.ascontiguousarray(ps.active, np.uint8)).to(device)
         return cls(t, ps.n)
 
+    @classmethod
+    def concat(cls, parts):
+        """The particle sets `parts` one after another in new arrays (a batch
+        for sphx_grid_build_sets) and their n_sets + 1 offsets. The activity
+        mask is kept if any set has one (the others count as all active)."""
+        import torch
+        t = {}
+        for k in ("x", "y", "z", "vx", "vy", "vz", "m", "u", "h", "alpha_v", "alpha_c"):
+            t[k] = torch.cat([p.t[k] for p in parts])
+        if any(p.t["active"] is not None for p in parts):
+            t["active"] = torch.cat([
+                p.t["active"] if p.t["active"] is not None else
+                torch.ones((p.n,), dtype=torch.uint8, device=p.t["x"].device) for p in parts])
+        else:
+            t["active"] = None
+        off = [0]
+        for p in parts:
+            off.append(off[-1] + p.n)
+        return cls(t, off[-1]), off
+
     def view(self) -> Particles:
         p = Particles()
         p.n = self.n
@@ -275,7 +297,7 @@ class Outputs:
     """Caller-owned output arrays for the density, ghost and force passes
     (pressure=True: also the smoothed pressure and its h-derivative)."""
 
-    def __init__(self, n, device="cuda", pressure=False):
+    def __init__(self, n, device="cuda", pressure=False, n_sets=1):
         import torch
         f = lambda: torch.full((n,), float("nan"), dtype=torch.float32, device=device)
         self.d = {k: f() for k in DENS_F32 + (DENS_PE if pressure else ())}
@@ -285,7 +307,8 @@ class Outputs:
         self.f = {k: f() for k in FORCE_F32}
         self.f["nforce"] = torch.full((n,), -1, dtype=torch.int32, device=device)
         self.counters = torch.zeros((COUNTERS,), dtype=torch.int32, device=device)
-        self.sums = torch.zeros((6,), dtype=torch.float64, device=device)
+        # six FP64 conservation sums per particle set (sphx_grid_build_sets)
+        self.sums = torch.zeros((6 * n_sets,), dtype=torch.float64, device=device)
 
     def dens_view(self):
         o = DensityOut()
@@ -309,11 +332,21 @@ class Outputs:
 class Grid:
     handle = None
 
-    def __init__(self, ctx: Context, parts: DeviceParticles, stream=None):
+    def __init__(self, ctx: Context, parts: DeviceParticles, stream=None, sets=None):
+        """sets: None (one particle set), or the n_sets + 1 offsets of the
+        independent sets held in `parts` (sphx_grid_build_sets)."""
         self.ctx = ctx
         self.pv = parts.view()
         h = C.c_void_p()
-        _check(lib.sphx_grid_build(ctx.handle, C.byref(self.pv), _stream(stream), C.byref(h)))
+        if sets is None:
+            self.n_sets = 1
+            _check(lib.sphx_grid_build(ctx.handle, C.byref(self.pv), _stream(stream),
+                                       C.byref(h)))
+        else:
+            off = (C.c_int64 * len(sets))(*[int(v) for v in sets])
+            self.n_sets = len(sets) - 1
+            _check(lib.sphx_grid_build_sets(ctx.handle, C.byref(self.pv), off, self.n_sets,
+                                            _stream(stream), C.byref(h)))
         self.handle = h
 
     @property

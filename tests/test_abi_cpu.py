@@ -134,3 +134,16 @@ def test_ctx_create_rejects_unknown_kernel(sphx, kernel):
     h = C.c_void_p()
     assert sphx.lib.sphx_ctx_create(C.byref(p), 0, C.byref(h)) == sphx.E_INVALID
     assert "kernel" in sphx.last_error() and not h.value
+
+
+def test_grid_build_sets_rejects_null_arguments():
+    """The set grid build refuses NULL handles and offsets before any device
+    call (checked without a GPU)."""
+    import ctypes as C
+    from paper_2305_13380_amd import sphx
+    h = C.c_void_p()
+    pv = sphx.Particles()
+    off = (C.c_int64 * 2)(0, 0)
+    assert sphx.lib.sphx_grid_build_sets(None, C.byref(pv), off, 1, None, C.byref(h)) == \
+        sphx.E_INVALID
+    assert "NULL" in sphx.last_error()

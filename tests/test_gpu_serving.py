@@ -1,7 +1,8 @@
 """Continuous-batching serving: requests of different sizes and geometries
 overlap on the device, each on its own stream and grid.
 
-* every result of a request is bitwise the same alone and in the mix;
+* every result of a request is bitwise the same alone, in the mix, and in a
+  batch of requests run as one step over a grid of independent sets;
 * a tiny HBM budget makes requests wait (never an out-of-memory failure), and
   a request larger than the budget is rejected with a message;
 * latencies are completion minus arrival, and the percentiles are ordered;
@@ -43,10 +44,33 @@ def served():
     mix = serve.Server(n_slots=6, keep_outputs=True)
     res_mix = mix.run(spec, lambda k: dev[k])
     log("serving: mix run done, peak running %d" % mix.peak_running)
-    out = dict(reqs=reqs, alone=res_alone, mix=res_mix, mix_server=mix, dev=dev)
+    # batches of at most 150,000 particles on 2 slots: several batches, some
+    # of several requests, overlapping
+    batched = serve.Server(n_slots=2, keep_outputs=True, batch_particles=150000)
+    res_batch = batched.run(spec, lambda k: dev[k])
+    log("serving: batched run done, peak running %d" % batched.peak_running)
+    out = dict(reqs=reqs, alone=res_alone, mix=res_mix, mix_server=mix, dev=dev,
+               batch=res_batch, batch_server=batched)
     yield out
     alone.close()
     mix.close()
+    batched.close()
+
+
+def test_alone_equals_batch_bitwise(served):
+    """Requests run as batches (one grid of independent sets per batch) give
+    bitwise the results of each request alone, its FP64 sums included."""
+    assert served["batch_server"].peak_running > 2  # batches of several requests
+    starts = {}
+    for a, b in zip(served["alone"], served["batch"]):
+        assert a.error is None and b.error is None, (a.error, b.error)
+        assert b.status >= 0 and a.interactions == b.interactions
+        starts.setdefault(b.start, []).append(b.rid)
+        for key, va in a.outputs.items():
+            vb = b.outputs[key]
+            assert va.dtype == vb.dtype and va.shape == vb.shape
+            assert np.array_equal(va.view(np.uint8), vb.view(np.uint8)), (a.rid, key)
+    assert 1 < len(starts) < len(served["reqs"])  # several batches, not one per request
 
 
 def test_alone_equals_mix_bitwise(served):
