@@ -11,10 +11,12 @@ value = (N_dens + N_force) / seconds per step, with
   N_force = sum_i #{j != i : r_ij < max(H_i, H_j)}  (active receivers only).
 
 Then (unless --no-serving) the serving stream of 512 independent boxes of
-10^3..10^6 particles is run through the continuous-batching server and through
-the plain per-call form: saturated throughput, and p50/p99 latency under
-Poisson arrivals at 0.5 and 0.8 of the served form's saturated rate
-(top-level p50_ms/p99_ms are the served form at 0.8).
+10^3..10^6 particles is run through the continuous-batching server (requests
+overlapping in slots of one request each, and in batches, each batch one step
+over a grid of independent sets) and through the plain per-call form:
+saturated throughput, and p50/p99 latency under Poisson arrivals at 0.5 and
+0.8 of the first form's saturated rate (top-level p50_ms/p99_ms are the
+one-request-per-slot form at 0.8).
 
 Prints one JSON line.
 """
@@ -143,13 +145,20 @@ def cpu_baseline(ps, make_params, n_recv, seed=0):
             "host_cpus_usable": usable}
 
 
+# The batched serving form: slots and the most particles of one batch.
+BATCH_SLOTS = 6
+BATCH_PARTICLES = 1 << 23
+
+
 def serving_bench(slots, n_req, seed=4):
     """The serving stream: n_req independent periodic boxes (N log-uniform in
     [1e3, 1e6], lattice or lognormal by a seeded coin) with inputs resident in
-    HBM. Runs it saturated (all requests queued at t=0) with `slots` slots and
-    with one slot (the plain per-call form), then with seeded Poisson arrivals
-    at 0.5 and 0.8 times the served form's saturated request rate, for both
-    forms. Latency = completion - arrival."""
+    HBM. Runs it saturated (all requests queued at t=0) with `slots` slots of
+    one request each, in batches (BATCH_SLOTS slots, each running the waiting
+    requests as one step over a grid of independent sets), and with one slot
+    (the plain per-call form), then with seeded Poisson arrivals at 0.5 and
+    0.8 times the first form's saturated request rate, for all three forms.
+    Latency = completion - arrival."""
     import numpy as np
     import torch
     from paper_2305_13380_amd import inputs, serve, sphx
@@ -163,7 +172,9 @@ def serving_bench(slots, n_req, seed=4):
     n_tot = sum(d.n for d in dev)
     log("bench: serving: %d requests, %d particles generated and uploaded in %.1f s" % (
         n_req, n_tot, time.perf_counter() - t0))
-    servers = {"served": serve.Server(n_slots=slots), "per_call": serve.Server(n_slots=1)}
+    servers = {"served": serve.Server(n_slots=slots),
+               "batched": serve.Server(n_slots=BATCH_SLOTS, batch_particles=BATCH_PARTICLES),
+               "per_call": serve.Server(n_slots=1)}
     warm = [(k, 0.0, dev[k].n) for k in range(min(16, n_req))]
     for srv in servers.values():
         srv.run(warm, lambda k: dev[k])
@@ -195,13 +206,20 @@ def serving_bench(slots, n_req, seed=4):
                      "h iteration, ghost, force and FP64 sums, and copies back its "
                      "interaction counts"}
     sat, res_sat = run("served", None)
+    satb, _ = run("batched", None)
     sat1, _ = run("per_call", None)
-    out["saturated"] = {"served": sat, "per_call": sat1,
-                        "speedup": sat["requests_per_s"] / sat1["requests_per_s"]}
+    out["saturated"] = {"served": sat, "batched": satb, "per_call": sat1,
+                        "speedup": sat["requests_per_s"] / sat1["requests_per_s"],
+                        "batched_speedup": satb["requests_per_s"] / sat1["requests_per_s"]}
+    out["batched_form"] = {"slots": BATCH_SLOTS, "batch_particles": BATCH_PARTICLES,
+                           "what": "a free slot runs the requests waiting for it, in arrival "
+                                   "order up to batch_particles particles, as one step over "
+                                   "a grid of independent sets (sphx_grid_build_sets)"}
     out["interactions"] = sum(r.interactions for r in res_sat)
     for frac in (0.5, 0.8):
         rate = frac * sat["requests_per_s"]
         out["poisson_%.1f" % frac] = {"served": run("served", rate)[0],
+                                      "batched": run("batched", rate)[0],
                                       "per_call": run("per_call", rate)[0]}
     for srv in servers.values():
         srv.close()
