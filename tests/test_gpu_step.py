@@ -272,11 +272,11 @@ def test_step_rejects_null_outputs():
 
 @pytest.mark.parametrize("growth,region", [(1.02, 1.0), (1.6, 1.0), (1.6, 0.3)])
 def test_rebuild_in_place_matches_fresh_build(growth, region):
-    """Rebuilding a task list in place (one walk into the slot layout of the
-    previous build; the cells that outgrew their slot are walked again, the
-    others compacted from it) gives the same task list as a fresh build: a
-    fixed-h pass over either is bitwise the same. h grows by `growth` for the
-    particles with x < region: every cell fits, most outgrow, or a mix."""
+    """Rebuilding a task list in place (every cell walked into its slot of
+    the previous layout; a new layout when a cell outgrew its slot) gives the
+    same task list as a fresh build: a fixed-h pass over either is bitwise the
+    same. h grows by `growth` for the particles with x < region: every cell
+    fits, most outgrow, or a mix."""
     import torch
     from paper_2305_13380_amd import sphx
     ps = inputs.lognormal_box(16, 6000, 2.0, 41)
