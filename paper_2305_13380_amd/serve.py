@@ -245,7 +245,12 @@ class Server:
                 start = time.perf_counter() - t0
                 for r in rs:
                     r.start = start
-                _run_batch(self.sphx, self.ctxs[slot], parts, self.streams[slot], self.keep, rs)
+                if len(ks) == 1:  # (a batch of one needs no concatenation)
+                    _run_one(self.sphx, self.ctxs[slot], parts[0], self.streams[slot],
+                             self.keep, rs[0])
+                else:
+                    _run_batch(self.sphx, self.ctxs[slot], parts, self.streams[slot], self.keep,
+                               rs)
             except Exception as e:  # reported, never silent
                 for r in rs:
                     r.error = "%s: %s" % (type(e).__name__, e)
