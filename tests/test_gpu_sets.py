@@ -101,3 +101,25 @@ def test_sets_active_subsets():
             inputs.lattice_box(9, 4)]
     res, _ = sets_step(sets)
     same_as_alone(res, sets)
+
+
+def test_noalloc_force_refuses_a_grid_of_sets():
+    """The no-allocation force pass holds the sums' reduction of one set only:
+    a grid of several sets is refused before anything is enqueued."""
+    import ctypes as C
+    from paper_2305_13380_amd import sphx
+    sets = [inputs.lattice_box(8, 1), inputs.lattice_box(8, 2)]
+    ctx = sphx.Context()
+    dps = [sphx.DeviceParticles.from_set(ps, "cuda:0") for ps in sets]
+    dp, off = sphx.DeviceParticles.concat(dps)
+    out = sphx.Outputs(dp.n, "cuda:0", n_sets=2)
+    grid = sphx.Grid(ctx, dp, sets=off)
+    tasks = sphx.Tasks(ctx, grid, dp)
+    pv, dv, gv, fv = dp.view(), out.dens_view(), out.ghost_view(), out.force_view()
+    st = sphx.lib.sphx_force_noalloc(ctx.handle, grid.handle, tasks.handle, C.byref(pv),
+                                     C.byref(dv), C.byref(gv), C.byref(fv),
+                                     C.c_void_p(out.sums.data_ptr()), None)
+    assert st == sphx.E_INVALID and "several particle sets" in sphx.last_error()
+    tasks.close()
+    grid.close()
+    ctx.close()
