@@ -626,9 +626,15 @@ __global__ void k_state_clear(int64_t *__restrict__ state)
         state[threadIdx.x] = 0;
 }
 
-// state[kTaskTotal] = the tasks held, summed over the leaves' slots (one
-// block of kTotalThreads; no atomics on one word from every leaf).
-constexpr int kTotalThreads = 1024;
+// state[kTaskTotal] = the tasks held, summed over the leaves' slots: each
+// block adds its leaves' counts with one atomic (k_task_total_clear first).
+constexpr int kTotalThreads = 256;
+__global__ void k_task_total_clear(int64_t *__restrict__ state)
+{
+    if (threadIdx.x == 0)
+        state[kTaskTotal] = 0;
+}
+
 __global__ __launch_bounds__(kTotalThreads) void k_task_total(int64_t n_leaves,
                                                               const int32_t *__restrict__ slot,
                                                               const int32_t *__restrict__ end,
@@ -636,7 +642,8 @@ __global__ __launch_bounds__(kTotalThreads) void k_task_total(int64_t n_leaves,
 {
     __shared__ int64_t part[kTotalThreads / 64];
     int64_t v = 0;
-    for (int64_t I = threadIdx.x; I < n_leaves; I += kTotalThreads)
+    for (int64_t I = int64_t(blockIdx.x) * kTotalThreads + threadIdx.x; I < n_leaves;
+         I += int64_t(gridDim.x) * kTotalThreads)
         v += end[I] - slot[I];
     for (int o = 32; o > 0; o >>= 1)
         v += __shfl_xor(v, o, 64);
@@ -647,11 +654,25 @@ __global__ __launch_bounds__(kTotalThreads) void k_task_total(int64_t n_leaves,
         int64_t t = 0;
         for (int k = 0; k < kTotalThreads / 64; ++k)
             t += part[k];
-        state[kTaskTotal] = t;
+        if (t)
+            atomicAdd(reinterpret_cast<unsigned long long *>(state + kTaskTotal),
+                      (unsigned long long)t);
     }
 }
 
 }  // namespace
+
+// state[kTaskTotal] summed over the slots (two launches; capturable).
+static sphx_status total_launch(int64_t nl, sphx_tasks *t, hipStream_t s)
+{
+    k_task_total_clear<<<1, 64, 0, s>>>(t->state);
+    SPHX_HIP(hipGetLastError());
+    const unsigned nb = unsigned(std::min<int64_t>((nl + kTotalThreads - 1) / kTotalThreads + 1,
+                                                    1024));
+    k_task_total<<<nb, kTotalThreads, 0, s>>>(nl, t->slot, t->end, t->state);
+    SPHX_HIP(hipGetLastError());
+    return SPHX_OK;
+}
 
 // The tree view of a grid with the periodic box of the context.
 static TreeView tree_view(const sphx_ctx *ctx, const sphx_grid *g)
@@ -745,10 +766,8 @@ static sphx_status walk_slots_launch(const sphx_ctx *ctx, const sphx_grid *g, sp
 static sphx_status read_state(sphx_ctx *ctx, sphx_tasks *t, hipStream_t s,
                               int64_t st[kTaskStateWords], bool total = true)
 {
-    if (total) {
-        k_task_total<<<1, kTotalThreads, 0, s>>>(t->grid->n_leaves, t->slot, t->end, t->state);
-        SPHX_HIP(hipGetLastError());
-    }
+    if (total)
+        SPHX_TRY(total_launch(t->grid->n_leaves, t, s));
     int64_t *h = reinterpret_cast<int64_t *>(ctx->h_pinned + kPinnedBytes - 64);
     SPHX_HIP(hipMemcpyAsync(h, t->state, kTaskStateWords * sizeof(int64_t),
                             hipMemcpyDeviceToHost, s));
@@ -998,9 +1017,7 @@ sphx_status tasks_full_async(const sphx_ctx *ctx, sphx_grid *g, sphx_tasks *t,
 
 sphx_status tasks_total_async(const sphx_grid *g, sphx_tasks *t, hipStream_t s)
 {
-    k_task_total<<<1, kTotalThreads, 0, s>>>(g->n_leaves, t->slot, t->end, t->state);
-    SPHX_HIP(hipGetLastError());
-    return SPHX_OK;
+    return total_launch(g->n_leaves, t, s);
 }
 
 }  // namespace sphx
