@@ -96,6 +96,10 @@ def lib():
                                   C.c_int64, _nullable(_ip), _nullable(_ip), _nullable(_ip)]
                                   + [_dp] * 3 + [_nullable(_dp)])
         L.or_gradient.restype = C.c_int64
+        L.or_gdf.argtypes = ([C.c_int64] + [_dp] * 10 + [C.c_int, C.c_double, C.c_int,
+                             C.c_double, C.c_int64, _nullable(_ip), _nullable(_ip),
+                             _nullable(_ip), _dp, _dp])
+        L.or_gdf.restype = None
         L.or_alpha_c_update.argtypes = ([C.c_int64] + [_dp] * 5 + [C.c_double] * 6 + [_dp])
         L.or_alpha_c_update.restype = None
         L.or_dt_cfl.argtypes = [C.c_int64, _dp, _dp, C.c_double, C.c_double, _dp]
@@ -162,11 +166,15 @@ class Params:
     # with the mean alpha_c and speed c_i + c_j + mu; its conduction parameter
     # evolves with beta_c = 0.01 and no shock limiter, its viscosity switch
     # with ell = 0.25)
+    # "gdf": the Gasoline-2-like flavour of Appendix A (geometric density
+    # average force: both pressures over rho_i rho_j on the mean gradient,
+    # the GDF correction f and the dimensional conduction parameter from the
+    # shear tensor, both from gdf(); the density flavours' viscosity)
     flavour: str = "energy"
 
     def flavour_id(self) -> int:
         return {"energy": 0, "entropy": 1, "phantom": 2, "pressure_energy": 3,
-                "anarchy_pu": 4}[self.flavour]
+                "anarchy_pu": 4, "gdf": 5}[self.flavour]
 
     def smoothed_pressure(self) -> bool:
         return self.flavour in ("pressure_energy", "anarchy_pu")
@@ -696,6 +704,28 @@ def gradient(ps, h, rho, P, params: Params, recv=None, mode="auto", c=None):
                               None if c is None else _f64(c))
     out["total"] = int(total)
     return out
+
+
+# Conduction constant of the GDF flavour (Appendix A).
+GDF_C = 0.03
+
+
+def gdf(ps, h, rho, params: Params, recv=None, mode="auto"):
+    """The GDF flavour's correction f and conduction parameter alpha_c
+    (or_gdf) for the receivers, from every particle's h and rho."""
+    mode = _resolve_mode(mode, ps.n)
+    h = _f64(h)
+    r, nrecv = _recv_arr(recv, ps.n)
+    off = idx = None
+    if mode == "tree":
+        off, idx = density_candidates(ps, h, params, r)
+    f = np.zeros(nrecv)
+    ac = np.zeros(nrecv)
+    x, y, z = _pos(ps)
+    lib().or_gdf(ps.n, x, y, z, _f64(ps.vx), _f64(ps.vy), _f64(ps.vz), _f64(ps.m), h,
+                 _f64(rho), _f64(ps.box), int(params.periodic), float(params.gamma_k),
+                 params.kernel_id(), float(GDF_C), nrecv, r, off, idx, f, ac)
+    return f, ac
 
 
 def alpha_c_update(alpha, lap_u, u, h, vc, avmax, dt, params: Params,

@@ -70,6 +70,13 @@
  *    du/dt is the energy-conserving partner of the printed acceleration;
  *    the sound speed is sqrt(gamma P_hat / rho); the viscosity is that of
  *    the density flavours and there is no conduction.
+ *  - GDF (Appendix A): the mean gradient is G / 2 with G = f_i W'_i + f_j
+ *    W'_j (f the geometric-density correction); |S| is the square root of
+ *    the summed squares of the trace-free shear (the paper prints the plain
+ *    sum); the conduction term is taken with the sign that carries heat
+ *    from hot to cold; a receiver without neighbours gets f = 1 and
+ *    alpha_c = 0; the viscosity is that of the density flavours and the
+ *    alpha_V evolution from the shock detector is not built.
  */
 #include <math.h>
 #include <stddef.h>
@@ -440,6 +447,14 @@ void or_ghost(int64_t n, const double *rho, const double *rho_dh, const double *
  * with this acceleration), the same viscosity as the density flavours (f,
  * rho and c of the ghost) and no conduction. F is read only for flavours 3
  * and 4.
+ * flavour 5 (Gasoline-2-like GDF, Appendix A): f holds the GDF correction
+ * of or_gdf and alpha_c its conduction parameter; with the mean gradient
+ * G / 2,
+ *   a_i  -= m_j [(P_i + P_j) G / (2 rho_i rho_j) + nu G / 2] e
+ *   du_i += m_j [P_i G / (2 rho_i rho_j) + nu G / 4] (v_ij . e)
+ *           + m_j (alpha_c,i + alpha_c,j)(u_i - u_j) G / ((rho_i + rho_j) r)
+ * and the density flavours' viscosity (the paper prints no GDF viscosity
+ * force; its alpha_V evolution from a shock detector is not built here).
  * flavour 4 (Anarchy-PU, Appendix A): flavour 3 plus conduction with the
  * arithmetic mean alpha_c,ij = (alpha_c,i + alpha_c,j) / 2 and the speed
  * v_c,ij = c_i + c_j + mu (mu <= 0 as in the viscosity):
@@ -458,6 +473,7 @@ int64_t or_force(int64_t n, const double *x, const double *y, const double *z,
 {
     const int entropy = flavour == 1, phantom = flavour == 2;
     const int pe = flavour == 3 || flavour == 4, anarchy = flavour == 4;
+    const int gdf = flavour == 5;
     const double gm1sq = (gamma_gas - 1.0) * (gamma_gas - 1.0);
     int64_t total = 0;
 #pragma omp parallel for schedule(dynamic, 16) reduction(+ : total)
@@ -511,13 +527,29 @@ int64_t or_force(int64_t n, const double *x, const double *y, const double *z,
                 Agj = r < Hj ? K * fji * gj / P[j] : 0.0;
             }
             double G = fgi + fgj;
+            if (gdf) {
+                /* GDF (Appendix A): both pressures over rho_i rho_j on the
+                 * mean gradient G / 2 (f the GDF correction); du/dt takes
+                 * the receiver's pressure alone */
+                double pij = 0.5 * G / (rho[i] * rho[j]);
+                Agi = P[i] * pij;
+                Agj = P[j] * pij;
+            }
             double acc = Agi + Agj + 0.5 * nu * G;
             s_ax -= m[j] * acc * ex;
             s_ay -= m[j] * acc * ey;
             s_az -= m[j] * acc * ez;
             s_du += m[j] * (Agi + 0.25 * nu * G) * vdote;
             s_visc += m[j] * 0.25 * nu * G * vdote;
-            if (anarchy) {
+            if (gdf) {
+                /* GDF conduction (Appendix A): alpha_c dimensional, the pair
+                 * term (alpha_c,i + alpha_c,j)(u_i - u_j)(x_ij . mean
+                 * gradient) / (0.5 (rho_i + rho_j) r^2), x_ij . mean gradient
+                 * = r G / 2; taken with the sign that carries heat from the
+                 * hotter particle to the colder (G < 0) */
+                s_du += m[j] * (alpha_c[i] + alpha_c[j]) * (u[i] - u[j]) * G /
+                        ((rho[i] + rho[j]) * r);
+            } else if (anarchy) {
                 /* Anarchy-PU (Appendix A): mean alpha_c and the signal speed
                  * with the sign of mu reversed (and no beta) */
                 double v_c = c[i] + c[j] + mu;
@@ -813,6 +845,74 @@ int64_t or_gradient(int64_t n, const double *x, const double *y, const double *z
         total += cnt;
     }
     return total;
+}
+
+/*
+ * Gasoline-2-like (GDF) flavour, Appendix A: the geometric density average
+ * correction f_i and the conduction parameter alpha_c,i from the trace-free
+ * shear tensor. For receiver k (particle i) over every j with r_ij < H_i
+ * (W_ij = W(r_ij, h_i); the receiver itself adds nothing: r = 0):
+ *   S1 = sum_j m_j r_ij^2 W_ij,  S2 = sum_j (m_j / rho_j) r_ij^2 W_ij,
+ *   V_ab = sum_j (v_a,i - v_a,j)(x_b,i - x_b,j) m_j W_ij / (S1 / 3),
+ *   f_i = (S1 / rho_i) / S2,
+ *   S_ab = (V_ab + V_ba) / 2 - delta_ab (V_xx + V_yy + V_zz) / 3,
+ *   alpha_c,i = C |S| h_i^2 with |S| = sqrt(sum_ab S_ab^2)
+ * (the paper prints |S| as the plain sum of squares; its square root is the
+ * reading that gives alpha_c the dimension of a diffusivity, which the
+ * conduction term of the energy equation requires). A receiver without a
+ * neighbour at r > 0 gets f = 1 and alpha_c = 0.
+ */
+void or_gdf(int64_t n, const double *x, const double *y, const double *z,
+            const double *vx, const double *vy, const double *vz, const double *m,
+            const double *h, const double *rho, const double *box, int periodic,
+            double gamma_k, int kernel, double C, int64_t nrecv, const int64_t *recv,
+            const int64_t *cand_off, const int64_t *cand_idx, double *f_out,
+            double *alpha_c_out)
+{
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t k = 0; k < nrecv; ++k) {
+        int64_t i = recv ? recv[k] : k;
+        double Hi = gamma_k * h[i];
+        double S1 = 0.0, S2 = 0.0;
+        double V[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+        int64_t jb = cand_off ? cand_off[k] : 0;
+        int64_t je = cand_off ? cand_off[k + 1] : n;
+        for (int64_t q = jb; q < je; ++q) {
+            int64_t j = cand_off ? cand_idx[q] : q;
+            double d[3] = {min_image(x[i] - x[j], box[0], periodic),
+                           min_image(y[i] - y[j], box[1], periodic),
+                           min_image(z[i] - z[j], box[2], periodic)};
+            double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+            double r = sqrt(r2);
+            if (!(r < Hi))
+                continue;
+            double w, dwdr, dwdh;
+            or_kernel(kernel, r, h[i], gamma_k, &w, &dwdr, &dwdh);
+            double dv[3] = {vx[i] - vx[j], vy[i] - vy[j], vz[i] - vz[j]};
+            S1 += m[j] * r2 * w;
+            S2 += m[j] / rho[j] * r2 * w;
+            for (int a2 = 0; a2 < 3; ++a2)
+                for (int b2 = 0; b2 < 3; ++b2)
+                    V[a2][b2] += dv[a2] * d[b2] * m[j] * w;
+        }
+        if (!(S1 > 0.0) || !(S2 > 0.0)) {
+            f_out[k] = 1.0;
+            alpha_c_out[k] = 0.0;
+            continue;
+        }
+        for (int a2 = 0; a2 < 3; ++a2)
+            for (int b2 = 0; b2 < 3; ++b2)
+                V[a2][b2] /= S1 / 3.0;
+        double tr = V[0][0] + V[1][1] + V[2][2];
+        double s2 = 0.0;
+        for (int a2 = 0; a2 < 3; ++a2)
+            for (int b2 = 0; b2 < 3; ++b2) {
+                double sab = 0.5 * (V[a2][b2] + V[b2][a2]) - (a2 == b2 ? tr / 3.0 : 0.0);
+                s2 += sab * sab;
+            }
+        f_out[k] = (S1 / rho[i]) / S2;
+        alpha_c_out[k] = C * sqrt(s2) * h[i] * h[i];
+    }
 }
 
 /*
