@@ -352,7 +352,8 @@ def step_leg(name, params, steps=5, warmup=1, flavour=None, graph=-1):
     resident): the Sedov box and the large box with its active subset (after
     an untimed all-active step that gives the inactive particles their
     state), or the headline box with another SPH flavour (the density-entropy
-    one with A set from u, the smoothed-pressure ones on the same u)."""
+    one with A set from u, the smoothed-pressure and GDF ones on the same
+    u)."""
     import numpy as np
     import torch
     from paper_2305_13380_amd import inputs, sphx
@@ -384,6 +385,10 @@ def step_leg(name, params, steps=5, warmup=1, flavour=None, graph=-1):
         params.flavour = sphx.FLAVOURS[flavour]
         params.density_balance = 0
         params.neighbour_lists = 0
+    elif flavour == "gdf":
+        # the density flavours' loops, then the GDF loop inside the step
+        params = type(params).from_buffer_copy(params)
+        params.flavour = sphx.FLAVOURS[flavour]
     dp = sphx.DeviceParticles.from_set(ps, "cuda:0")
     out = sphx.Outputs(ps.n, "cuda:0")
     if dp.t["active"] is not None:
@@ -645,7 +650,7 @@ def main():
                     help="skip the direct-summation gravity timing on the workload")
     ap.add_argument("--no-legs", action="store_true",
                     help="skip the other workloads of the step (Sedov box, large box, "
-                         "the density-entropy, pressure-energy and Anarchy-PU flavours) "
+                         "the density-entropy, pressure-energy, Anarchy-PU and GDF flavours) "
                          "and the multi-step SPHENIX run")
     ap.add_argument("--serving-requests", type=int, default=512)
     ap.add_argument("--serving-slots", type=int, default=8)
@@ -893,6 +898,8 @@ def main():
                                                   flavour="pressure_energy", graph=args.graph),
             "clustered_anarchy_pu": step_leg("clustered", params, steps=5, flavour="anarchy_pu",
                                              graph=args.graph),
+            "clustered_gdf": step_leg("clustered", params, steps=5, flavour="gdf",
+                                      graph=args.graph),
         }
         line["sphenix_run"] = sphenix_leg(params)
     if not args.no_fof:

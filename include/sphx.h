@@ -131,7 +131,17 @@ typedef struct sphx_params {
      * flavour, with its restrictions, plus conduction with the mean
      * (alpha_c,i + alpha_c,j)/2 and the speed c_i + c_j + mu_ij; in
      * sphx_gradient the same pair speed, in sphx_alpha_c_update beta_c =
-     * 0.01 and no shock limiter, in sphx_alpha_v_update the length 0.25). */
+     * 0.01 and no shock limiter, in sphx_alpha_v_update the length 0.25) or
+     * SPHX_FLAVOUR_GDF (the Gasoline-2-like flavour of Appendix A: the
+     * geometric density average force, (P_i + P_j) / (rho_i rho_j) on the
+     * mean gradient (f_i W'_i + f_j W'_j) / 2 with the correction f of
+     * sphx_gdf in sphx_ghost_out.f, du/dt with P_i alone, the density
+     * flavours' viscosity, and the conduction m_j (alpha_c,i + alpha_c,j)
+     * (u_i - u_j) G / ((rho_i + rho_j) r) with alpha_c = 0.03 |S| h^2 from
+     * the trace-free shear S, carried in sphx_ghost_out.A. sphx_force reads
+     * f and alpha_c from *gst; sphx_step forms both after the h iteration
+     * and returns them there. The alpha_V evolution of the printed scheme
+     * is not part of it). */
     int32_t flavour;
 } sphx_params;
 
@@ -140,6 +150,7 @@ typedef struct sphx_params {
 #define SPHX_FLAVOUR_PHANTOM 2
 #define SPHX_FLAVOUR_PRESSURE_ENERGY 3
 #define SPHX_FLAVOUR_ANARCHY_PU 4
+#define SPHX_FLAVOUR_GDF 5
 
 #define SPHX_KERNEL_WENDLAND_C2 0
 #define SPHX_KERNEL_WENDLAND_C4 1
@@ -477,6 +488,28 @@ sphx_status sphx_alpha_v_update(sphx_ctx *ctx, int64_t n, const float *div_old,
 sphx_status sphx_gradient(sphx_ctx *ctx, sphx_grid *grid, const sphx_tasks *tasks,
                           const sphx_particles *in, const float *rho, const float *P,
                           float *lap_u, float *v_c, float *alpha_v_max, void *stream);
+
+/* The GDF flavour's per-particle quantities (Appendix A), for every active
+ * receiver i over the j with r_ij < H_i (W_ij = W(r_ij, h_i); FP32 arithmetic
+ * in the cell frame):
+ *   f[i]       = (S1 / rho_i) / S2, S1 = sum_j m_j r_ij^2 W_ij,
+ *                S2 = sum_j (m_j / rho_j) r_ij^2 W_ij (the geometric density
+ *                average correction of the force law);
+ *   alpha_c[i] = 0.03 |S| h_i^2, S the trace-free symmetric part of
+ *                V_ab = sum_j (v_a,i - v_a,j)(x_b,i - x_b,j) m_j W_ij / (S1 / 3)
+ *                and |S| the square root of its summed squares (the paper
+ *                prints the plain sum; the root gives alpha_c the dimension
+ *                of a diffusivity).
+ * A receiver with no neighbour at r > 0 gets f = 1 and alpha_c = 0. Reads
+ * positions, velocities and masses of the grid (as copied at its build), and
+ * h (in) and rho (device, caller order, n FP32: e.g. sphx_density_out.rho)
+ * of every particle. Outputs: device FP32 arrays of n in caller order,
+ * written for active particles only (for SPHX_FLAVOUR_GDF's force pass,
+ * sphx_ghost_out.f and .A). Any flavour may call it. Uses the grid's scratch
+ * (not safe concurrently with another call on the same grid). Asynchronous. */
+sphx_status sphx_gdf(sphx_ctx *ctx, sphx_grid *grid, const sphx_tasks *tasks,
+                     const sphx_particles *in, const float *rho, float *f, float *alpha_c,
+                     void *stream);
 
 /* SPHENIX conduction parameter over a step dt (Section 3.3), per active
  * particle i < n (active NULL: all): the evolution equation

@@ -184,7 +184,7 @@ sphx_status sphx_ctx_create(const sphx_params *p, int hip_device, sphx_ctx **out
     }
     if (p->flavour != SPHX_FLAVOUR_DENSITY_ENERGY && p->flavour != SPHX_FLAVOUR_DENSITY_ENTROPY &&
         p->flavour != SPHX_FLAVOUR_PHANTOM && p->flavour != SPHX_FLAVOUR_PRESSURE_ENERGY &&
-        p->flavour != SPHX_FLAVOUR_ANARCHY_PU) {
+        p->flavour != SPHX_FLAVOUR_ANARCHY_PU && p->flavour != SPHX_FLAVOUR_GDF) {
         set_error("sphx_ctx_create: unknown flavour (SPHX_FLAVOUR_*)");
         return SPHX_E_INVALID;
     }
@@ -362,6 +362,20 @@ sphx_status sphx_gradient(sphx_ctx *ctx, sphx_grid *grid, const sphx_tasks *task
     SPHX_HIP(hipSetDevice(ctx->device));
     return gradient_launch(ctx, grid, tasks, in, rho, P, lap_u, v_c, alpha_v_max,
                            as_stream(stream));
+}
+
+sphx_status sphx_gdf(sphx_ctx *ctx, sphx_grid *grid, const sphx_tasks *tasks,
+                     const sphx_particles *in, const float *rho, float *f, float *alpha_c,
+                     void *stream)
+{
+    SPHX_TRY(check_handles(ctx, grid, tasks, in));
+    SPHX_TRY(check_particles(in, false));
+    if (!tasks || (in->n && (!rho || !f || !alpha_c))) {
+        set_error("sphx_gdf: NULL task list, rho or output array");
+        return SPHX_E_INVALID;
+    }
+    SPHX_HIP(hipSetDevice(ctx->device));
+    return gdf_launch(ctx, grid, tasks, in, rho, f, alpha_c, as_stream(stream));
 }
 
 sphx_status sphx_alpha_c_update(sphx_ctx *ctx, int64_t n, const float *lap_u, const float *u,

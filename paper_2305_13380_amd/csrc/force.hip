@@ -69,7 +69,12 @@ struct StepOut {
 // (gamma - 1)^2 u / P, so that with R = Q F the pair needs only
 // g_i (Q_i m_j u_j - R_i) + g_j (Q_j m_j u_i - R_j m_j / m_i); 4 Anarchy-PU,
 // Appendix A: 3 plus conduction with the mean alpha_c and the speed c_i +
-// c_j + mu, its source alpha_c staged where the other flavours keep P_j).
+// c_j + mu, its source alpha_c staged where the other flavours keep P_j); 5
+// GDF, Appendix A: f is the geometric-density correction and A holds
+// alpha_c; the pressure terms are (P_i + P_j) G / (2 rho_i rho_j) on the mean
+// gradient G / 2, du/dt takes P_i alone plus the conduction m_j (alpha_c,i +
+// alpha_c,j)(u_i - u_j) G / ((rho_i + rho_j) r), with the density flavours'
+// viscosity).
 template <int CAP, int NW, int K, int FLAV>
 __global__ __launch_bounds__(64 * NW) void k_force(
     int64_t n_leaves, int64_t nb_padded, const int32_t *__restrict__ order,
@@ -174,7 +179,7 @@ __global__ __launch_bounds__(64 * NW) void k_force(
     const float fi = gi1.x, Bi = gi1.y, Ai = gi1.z;
     // pressure-energy: the receiver's Q, R = Q F, u and 1/m (else unused)
     const float Qi = gi1.w, Ri = gi1.w * gi1.z, ui_ = vi.w;
-    const float inv_mi = FLAV >= 3 ? fast_rcp(pi.w) : 0.0f;
+    const float inv_mi = FLAV == 3 || FLAV == 4 ? fast_rcp(pi.w) : 0.0f;
     const float acPi = ai.y * Pi;
 
     float ax = 0.f, ay = 0.f, az = 0.f, du = 0.f, duv = 0.f;
@@ -225,10 +230,15 @@ __global__ __launch_bounds__(64 * NW) void k_force(
         const float m = v.w;
         // the pressure terms of i and j (pressure-energy: already times m_j,
         // with the source's b.y = m_j Q_j, c2.x = m_j R_j, c2.y = m_j u_j)
-        const float Agi = in_i ? (FLAV >= 3 ? gi * (Qi * c2.y - Ri) : Ai * gi) : 0.0f;
-        const float Agj = in_j ? (FLAV >= 3 ? gj * (b.y * ui_ - c2.x * inv_mi) : b.y * gj) : 0.0f;
-        const float macc =
-            FLAV >= 3 ? Agi + Agj + m * (0.5f * nu * G) : m * (Agi + Agj + 0.5f * nu * G);
+        const float Agi =
+            in_i ? (FLAV == 3 || FLAV == 4 ? gi * (Qi * c2.y - Ri) : Ai * gi) : 0.0f;
+        const float Agj =
+            in_j ? (FLAV == 3 || FLAV == 4 ? gj * (b.y * ui_ - c2.x * inv_mi) : b.y * gj) : 0.0f;
+        // GDF: P / (rho_i rho_j) on the mean gradient (0 when G is)
+        const float pij = FLAV == 5 ? 0.5f * G * fast_rcp(rhoi * a.z) : 0.0f;
+        const float macc = FLAV == 5   ? m * ((Pi + a.w) * pij + 0.5f * nu * G)
+                           : FLAV >= 3 ? Agi + Agj + m * (0.5f * nu * G)
+                                       : m * (Agi + Agj + 0.5f * nu * G);
         const float psum = Pi + a.w;
         const float ac =
             FLAV == 2 ? 1.0f : (psum > 0.0f ? (acPi + c2.x) * fast_rcp(psum) : 0.0f);
@@ -239,7 +249,11 @@ __global__ __launch_bounds__(64 * NW) void k_force(
         // c_i + c_j + mu, with m_j (u_i - u_j) = m_j u_i - c2.y
         const float cond4 =
             FLAV == 4 ? 0.5f * (ai.y + a.w) * (ci + a.y + mu) * (m * ui_ - c2.y) * G * irs : 0.0f;
-        const float dui = FLAV == 4   ? Agi * vdote + dvi + cond4
+        // GDF conduction: alpha_c,i in A_i, alpha_c,j in b.y; 1/r = 0 off the list
+        const float dui = FLAV == 5
+                              ? m * ((Pi * pij + 0.25f * nu * G) * vdote +
+                                     (Ai + b.y) * (vi.w - c2.y) * G * irs * rinv)
+                          : FLAV == 4 ? Agi * vdote + dvi + cond4
                           : FLAV == 3 ? Agi * vdote + dvi
                           : FLAV == 1 ? m * Agi * vdote + dvi
                                       : m * (Agi + 0.25f * nu * G) * vdote +
@@ -336,7 +350,7 @@ __global__ __launch_bounds__(64 * NW) void k_force(
             // (Anarchy-PU keeps alpha_c,j in place of P_j, which its pair
             // terms do not read)
             ca[pos] = make_float4(fast_rcp(Hj), h0.w, h0.y, FLAV == 4 ? a.y : h0.z);
-            if (FLAV >= 3) {
+            if (FLAV == 3 || FLAV == 4) {
                 // m_j Q_j, m_j R_j = m_j Q_j F_j, m_j u_j
                 cb[pos] = make_float4(h1.x, p.w * h1.w, h1.y, a.x);
                 cc[pos] = make_float2(p.w * h1.w * h1.z, p.w * v.w);
@@ -665,6 +679,8 @@ sphx_status force_launch(const sphx_ctx *ctx, const sphx_grid *g, const sphx_tas
             state_ready ? in->active : nullptr, g->g0, g->g1);
         SPHX_HIP(hipGetLastError());
     }
+    if (state_ready && ctx->p.flavour == SPHX_FLAVOUR_GDF)
+        SPHX_TRY(gdf_step_launch(ctx, g, t, in, gate, s));
     k_leaf_hmax<<<unsigned(g->n_leaves), 64, 0, s>>>(g->n_leaves, g->leaf_start, g->g0,
                                                       float(ctx->p.gamma_k), g->leaf_hmax, gate);
     SPHX_HIP(hipGetLastError());
@@ -692,6 +708,9 @@ sphx_status force_launch(const sphx_ctx *ctx, const sphx_grid *g, const sphx_tas
                                                               far, gate, so, fsum, s)));
     } else if (ctx->p.flavour == SPHX_FLAVOUR_ANARCHY_PU) {
         SPHX_WITH_KERNEL(ctx->p.kernel, (force_shapes<KK, 4>(tile, waves, nbp, ctx, g, t, in, o,
+                                                              far, gate, so, fsum, s)));
+    } else if (ctx->p.flavour == SPHX_FLAVOUR_GDF) {
+        SPHX_WITH_KERNEL(ctx->p.kernel, (force_shapes<KK, 5>(tile, waves, nbp, ctx, g, t, in, o,
                                                               far, gate, so, fsum, s)));
     } else {
         SPHX_WITH_KERNEL(ctx->p.kernel, (force_shapes<KK, 0>(tile, waves, nbp, ctx, g, t, in, o,

@@ -14,9 +14,16 @@
 // * the step size: the CFL step c_cfl H_i / v_sig,i, capped at Delta times
 //   the smallest CFL step among the force-loop neighbours (r < max(H_i, H_j)),
 //   and the smallest limited step over the active particles;
-// * the leapfrog operators: a (half) kick of v and u, a drift of x.
+// * the leapfrog operators: a (half) kick of v and u, a drift of x;
+// * the GDF flavour's loop (Appendix A): for every active receiver i over j
+//   with r_ij < H_i, the geometric-density correction f_i = (S1 / rho_i) /
+//   S2 with S1 = sum_j m_j r^2 W_ij and S2 = sum_j (m_j / rho_j) r^2 W_ij,
+//   and the conduction parameter alpha_c,i = C |S| h_i^2 from the
+//   trace-free symmetric part S of V_ab = sum_j (v_a,i - v_a,j)(x_b,i -
+//   x_b,j) m_j W_ij / (S1 / 3), |S| the square root of its summed squares
+//   (f = 1 and alpha_c = 0 for a receiver with no neighbour at r > 0).
 //
-// The two neighbour loops run one wave per receiving cell, one receiver per
+// The neighbour loops run one wave per receiving cell, one receiver per
 // lane; each task's sources are staged in LDS in the receiver cell's FP32
 // frame, and a source that no lane uses is skipped by a wave-uniform branch.
 // Both are run once per step (the h iteration runs its density loop several
@@ -133,6 +140,137 @@ __global__ __launch_bounds__(64) void k_gradient(
         lap_u[gi] = 2.0f * lap;
         vc[gi] = vcm;
         avmax[gi] = avm;
+    }
+}
+
+// Sorted (h, rho) of every particle for the GDF loop (z, w unused).
+__global__ __launch_bounds__(kElemThreads) void k_hrho_state(int64_t n,
+                                                             const int32_t *__restrict__ perm,
+                                                             const float *__restrict__ h,
+                                                             const float *__restrict__ rho,
+                                                             float4 *__restrict__ st)
+{
+    const int64_t s = int64_t(blockIdx.x) * kElemThreads + threadIdx.x;
+    if (s >= n)
+        return;
+    const int32_t i = perm[s];
+    st[s] = make_float4(h[i], rho[i], 0.0f, 0.0f);
+}
+
+// The GDF loop. W_ij = W(r_ij, h_i) carries the factor kW H_i^-3 in every
+// sum, and it cancels in f and in V / (S1 / 3): the sums take w(u) alone.
+// st: sorted (h, rho) of every particle. Outputs for the active receivers:
+// f and alpha_c in caller order (f_out, ac_out) and, inside a step, in the
+// sorted force state (g1.x = f, g1.z = alpha_c, the flavour's slots of f
+// and A); null pointers are not written. gate: a captured step whose
+// iteration is not finished returns at once.
+template <int K>
+__global__ __launch_bounds__(64) void k_gdf(
+    int64_t n_leaves, const int32_t *__restrict__ leaf_start, const int32_t *__restrict__ perm,
+    const float4 *__restrict__ q0, const float4 *__restrict__ q1,
+    const float4 *__restrict__ st, const uint8_t *__restrict__ active,
+    const int32_t *__restrict__ tbeg, const int32_t *__restrict__ tend,
+    const Task *__restrict__ task, const float4 *__restrict__ ext, float gamma_k, float C,
+    const int32_t *__restrict__ gate, float *__restrict__ f_out, float *__restrict__ ac_out,
+    float4 *__restrict__ g1)
+{
+    if (gate && *gate)
+        return;
+    const int64_t L = blockIdx.x;
+    if (L >= n_leaves)
+        return;
+    const int lane = threadIdx.x;
+    const int32_t s0 = leaf_start[L], cnt = leaf_start[L + 1] - s0;
+    const bool valid = lane < cnt;
+    const int32_t s = s0 + (valid ? lane : 0);
+    const int32_t gi = perm[s];
+    const bool act = valid && (!active || active[gi] != 0);
+    if (!__any(act))
+        return;
+    const float4 pi = q0[s];  // x, y, z (cell frame), m
+    const float4 vi = q1[s];  // vx, vy, vz, u
+    const float4 si = st[s];  // h, rho
+    const float Hi = gamma_k * si.x;
+    const float H2 = act ? Hi * Hi : -1.0f;
+    const float invH = fast_rcp(Hi);
+    const float inf = __builtin_inff();
+    float3 lo = make_float3(act ? pi.x : inf, act ? pi.y : inf, act ? pi.z : inf);
+    float3 hb = make_float3(act ? pi.x : -inf, act ? pi.y : -inf, act ? pi.z : -inf);
+    lo.x = wave_minf(lo.x);
+    lo.y = wave_minf(lo.y);
+    lo.z = wave_minf(lo.z);
+    hb.x = wave_maxf(hb.x);
+    hb.y = wave_maxf(hb.y);
+    hb.z = wave_maxf(hb.z);
+    const float R = wave_maxf(act ? Hi : 0.0f);
+    const float R2 = R * R;
+
+    __shared__ float4 sp[kLeafMax], sv[kLeafMax];
+    float S1 = 0.0f, S2 = 0.0f;
+    float V[3][3] = {{0.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 0.0f}};
+    const int32_t ta = tbeg[L], tb = tend[L];
+    for (int32_t t = ta; t < tb; ++t) {
+        const Task tk = task[t];
+        if (task_box_dist2(tk.ox, tk.oy, tk.oz, ext[tk.j], lo, hb) >= R2)
+            continue;
+        __syncthreads();  // (one wave per block) the previous task's sources are read
+        if (lane < tk.jc) {
+            float4 p = q0[tk.j0 + lane];
+            p.x += tk.ox;
+            p.y += tk.oy;
+            p.z += tk.oz;
+            sp[lane] = p;
+            const float4 v = q1[tk.j0 + lane];
+            // (vx, vy, vz, m_j / rho_j)
+            sv[lane] = make_float4(v.x, v.y, v.z, p.w / st[tk.j0 + lane].y);
+        }
+        __syncthreads();
+        for (int k = 0; k < tk.jc; ++k) {
+            const float4 p = sp[k];
+            const float d[3] = {pi.x - p.x, pi.y - p.y, pi.z - p.z};
+            const float r2 = dist2(d[0], d[1], d[2]);
+            // r < H_i (the receiver itself, at r = 0, adds exactly zero)
+            const bool on = r2 < H2;
+            if (!__any(on))
+                continue;
+            const float4 v = sv[k];
+            const float u = fminf(fast_sqrt(r2) * invH, 1.0f);
+            const float wt = on ? Kern<K>::w(u) : 0.0f;
+            const float mw = p.w * wt;
+            S1 += mw * r2;
+            S2 += v.w * wt * r2;
+            const float dv[3] = {vi.x - v.x, vi.y - v.y, vi.z - v.z};
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int b = 0; b < 3; ++b)
+                    V[a][b] += dv[a] * (d[b] * mw);
+        }
+    }
+    if (!act)
+        return;
+    float f = 1.0f, ac = 0.0f;
+    if (S1 > 0.0f && S2 > 0.0f) {
+        f = (S1 / si.y) / S2;
+        const float k3 = 3.0f / S1;
+        const float tr = (V[0][0] + V[1][1] + V[2][2]) * (1.0f / 3.0f);
+        float ss = 0.0f;
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                const float sab = 0.5f * (V[a][b] + V[b][a]) - (a == b ? tr : 0.0f);
+                ss += sab * sab;
+            }
+        ac = C * (k3 * sqrtf(ss)) * (si.x * si.x);
+    }
+    if (f_out)
+        f_out[gi] = f;
+    if (ac_out)
+        ac_out[gi] = ac;
+    if (g1) {
+        g1[s].x = f;
+        g1[s].z = ac;
     }
 }
 
@@ -344,6 +482,38 @@ sphx_status gradient_launch(const sphx_ctx *ctx, sphx_grid *g, const sphx_tasks 
                          avmax,
                          ctx->p.flavour == SPHX_FLAVOUR_ANARCHY_PU ? float(ctx->p.gamma_gas)
                                                                    : 0.0f)));
+    SPHX_HIP(hipGetLastError());
+    return SPHX_OK;
+}
+
+sphx_status gdf_launch(const sphx_ctx *ctx, sphx_grid *g, const sphx_tasks *t,
+                       const sphx_particles *in, const float *rho, float *f, float *alpha_c,
+                       hipStream_t s)
+{
+    if (g->n == 0 || g->n_leaves == 0)
+        return SPHX_OK;
+    k_hrho_state<<<elem_blocks(g->n), kElemThreads, 0, s>>>(g->n, g->perm, in->h, rho, g->g2);
+    SPHX_HIP(hipGetLastError());
+    SPHX_WITH_KERNEL(ctx->p.kernel,
+                     (k_gdf<KK><<<unsigned(g->n_leaves), 64, 0, s>>>(
+                         g->n_leaves, g->leaf_start, g->perm, g->q0, g->q1, g->g2, in->active,
+                         t->slot, t->end, t->task, g->leaf_ext, float(ctx->p.gamma_k),
+                         float(kGdfC), nullptr, f, alpha_c, nullptr)));
+    SPHX_HIP(hipGetLastError());
+    return SPHX_OK;
+}
+
+sphx_status gdf_step_launch(const sphx_ctx *ctx, const sphx_grid *g, const sphx_tasks *t,
+                            const sphx_particles *in, const int32_t *gate, hipStream_t s)
+{
+    if (g->n == 0 || g->n_leaves == 0)
+        return SPHX_OK;
+    // (h, rho) of the force state g0 = (h, rho, P, c); f and alpha_c into g1
+    SPHX_WITH_KERNEL(ctx->p.kernel,
+                     (k_gdf<KK><<<unsigned(g->n_leaves), 64, 0, s>>>(
+                         g->n_leaves, g->leaf_start, g->perm, g->q0, g->q1, g->g0, in->active,
+                         t->slot, t->end, t->task, g->leaf_ext, float(ctx->p.gamma_k),
+                         float(kGdfC), gate, nullptr, nullptr, g->g1)));
     SPHX_HIP(hipGetLastError());
     return SPHX_OK;
 }

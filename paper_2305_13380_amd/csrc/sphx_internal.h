@@ -40,6 +40,8 @@ __host__ __device__ inline bool smoothed_pressure(int flavour)
 {
     return flavour == SPHX_FLAVOUR_PRESSURE_ENERGY || flavour == SPHX_FLAVOUR_ANARCHY_PU;
 }
+// The GDF flavour's conduction constant C of alpha_c = C |S| h^2 (Appendix A).
+constexpr double kGdfC = 0.03;
 constexpr int kTreeFan = 8;     // tree over leaves: groups of 8 consecutive nodes
 constexpr int kMaxLevels = 24;
 constexpr int kMortonBits = 21; // bits per axis of the 63-bit Morton key
@@ -360,6 +362,14 @@ sphx_status noalloc_scratch(int device, double **out);
 sphx_status gradient_launch(const sphx_ctx *ctx, sphx_grid *g, const sphx_tasks *t,
                             const sphx_particles *in, const float *rho, const float *P,
                             float *lap_u, float *vc, float *avmax, hipStream_t s);
+// The GDF loop: standalone, into caller-order f and alpha_c (from the
+// caller's h and rho); inside a step, into the force state g1 (from g0,
+// complete for every particle), gated like the force pass.
+sphx_status gdf_launch(const sphx_ctx *ctx, sphx_grid *g, const sphx_tasks *t,
+                       const sphx_particles *in, const float *rho, float *f, float *alpha_c,
+                       hipStream_t s);
+sphx_status gdf_step_launch(const sphx_ctx *ctx, const sphx_grid *g, const sphx_tasks *t,
+                            const sphx_particles *in, const int32_t *gate, hipStream_t s);
 sphx_status alpha_c_launch(const sphx_ctx *ctx, int64_t n, const float *lap_u, const float *u,
                            const float *h, const float *vc, const float *avmax,
                            const uint8_t *active, double dt, float *alpha, hipStream_t s);

@@ -81,7 +81,7 @@ SYMBOLS = ("sphx_params_default", "sphx_ctx_create", "sphx_ctx_destroy", "sphx_w
            "sphx_profile_read", "sphx_autotune", "sphx_params_set_kernel", "sphx_fof",
            "sphx_gravity", "sphx_alpha_v_update", "sphx_force_noalloc", "sphx_gradient",
            "sphx_alpha_c_update", "sphx_timestep", "sphx_kick", "sphx_drift",
-           "sphx_probe_read", "sphx_grid_build_sets")
+           "sphx_probe_read", "sphx_grid_build_sets", "sphx_gdf")
 
 _LIB = None
 
@@ -130,6 +130,7 @@ def _load():
                              vp, vp]
     L.sphx_force_noalloc.argtypes = L.sphx_force.argtypes
     L.sphx_gradient.argtypes = [vp, vp, vp, P(Particles), vp, vp, vp, vp, vp, vp]
+    L.sphx_gdf.argtypes = [vp, vp, vp, P(Particles), vp, vp, vp, vp]
     L.sphx_probe_read.argtypes = [vp, P(C.c_uint64), i32]
     L.sphx_probe_read.restype = i32
     L.sphx_alpha_c_update.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, C.c_double, vp, vp]
@@ -156,7 +157,7 @@ def _load():
                  "sphx_tasks_build", "sphx_iter_reset",
                  "sphx_density", "sphx_ghost", "sphx_force", "sphx_step", "sphx_force_noalloc",
                  "sphx_gradient", "sphx_alpha_c_update", "sphx_timestep", "sphx_kick",
-                 "sphx_drift"):
+                 "sphx_drift", "sphx_gdf"):
         getattr(L, name).restype = i32
     _LIB = L
     return L
@@ -176,7 +177,7 @@ def _check(status):
 
 
 FLAVOURS = {"energy": 0, "entropy": 1, "phantom": 2,  # SPHX_FLAVOUR_*
-            "pressure_energy": 3, "anarchy_pu": 4}
+            "pressure_energy": 3, "anarchy_pu": 4, "gdf": 5}
 
 
 def default_params(**kw) -> Params:
@@ -507,6 +508,23 @@ def gradient(ctx, grid, tasks, parts, out: Outputs, stream=None):
                              _ptr(out.d["rho"]), _ptr(out.g["P"]), _ptr(res[0]), _ptr(res[1]),
                              _ptr(res[2]), _stream(stream)))
     return tuple(res)
+
+
+def gdf(ctx, grid, tasks, parts, rho, f=None, alpha_c=None, stream=None):
+    """The GDF flavour's correction f and conduction parameter alpha_c
+    (sphx_gdf) from the particles' h and the device tensor rho: returns
+    device tensors (f, alpha_c), written for the active particles (given
+    tensors are filled in place; new ones start as NaN)."""
+    import torch
+    dev = parts.t["x"].device
+    if f is None:
+        f = torch.full((parts.n,), float("nan"), dtype=torch.float32, device=dev)
+    if alpha_c is None:
+        alpha_c = torch.full((parts.n,), float("nan"), dtype=torch.float32, device=dev)
+    pv = parts.view()
+    _check(lib.sphx_gdf(ctx.handle, grid.handle, tasks.handle, C.byref(pv), _ptr(rho),
+                        _ptr(f), _ptr(alpha_c), _stream(stream)))
+    return f, alpha_c
 
 
 def alpha_c_update(ctx, alpha_c, lap_u, u, h, v_c, alpha_v_max, dt, active=None, stream=None):

@@ -71,7 +71,7 @@ def test_ctx_create_rejects_invalid_params(sphx, field, value):
 
 
 @pytest.mark.parametrize("extra", [{"density_balance": 1}, {"density_balance": 2},
-                                   {"neighbour_lists": 1}, {"flavour": 5},
+                                   {"neighbour_lists": 1}, {"flavour": 6},
                                    {"flavour": "anarchy_pu", "density_balance": 2},
                                    {"flavour": "anarchy_pu", "neighbour_lists": 1}])
 def test_ctx_create_rejects_loops_the_pressure_flavour_lacks(sphx, extra):

@@ -1,0 +1,151 @@
+"""GPU GDF flavour (the Gasoline-2-like flavour of Appendix A) against the
+oracle:
+
+* the GDF loop alone (sphx_gdf): the geometric-density correction f and
+  the conduction parameter alpha_c = C |S| h^2, given the GPU's own h and rho
+  (their parity is checked by the step tests);
+* whole steps: the h iteration, then f and alpha_c formed inside the step,
+  and the GDF forces with the conduction term, against the oracle's chain
+  (density, ghost, GDF quantities, force) at the step's own h;
+* the standalone force pass fed with the step's f and alpha_c repeats the
+  step's forces bitwise, and a captured step repeats the pass-by-pass one.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2305_13380_amd import inputs
+
+from helpers import check_density, check_force, gpu_step, rms
+
+pytestmark = pytest.mark.gpu
+PG = oracle.Params(flavour="gdf")
+FL = {"flavour": "gdf"}
+GDF_TOL = 1e-4
+
+CASES = {
+    "lattice16_shear": lambda: inputs.lattice_box(16, 52, u="logu", sigma_v=0.2),
+    "lognormal_6000": lambda: inputs.lognormal_box(16, 6000, 2.0, 61, sigma_v=0.3),
+    "sedov16": lambda: inputs.sedov_box(16, 2, n_hot=8),
+}
+
+
+def check_gdf(f, ac, f_ref, ac_ref, where):
+    """f: a ratio of sums of positive terms, relative error. alpha_c: the
+    norm of a sum with cancellation, on the scale max(|ref|, rms(ref))."""
+    e = np.abs(f.astype(np.float64) - f_ref)
+    assert np.all(e <= GDF_TOL * np.abs(f_ref)), "%s f: %d mismatches, worst %.3g" % (
+        where, int((e > GDF_TOL * np.abs(f_ref)).sum()), (e / np.abs(f_ref)).max())
+    s = np.maximum(np.abs(ac_ref), rms(ac_ref)) + 1e-30
+    e = np.abs(ac.astype(np.float64) - ac_ref)
+    assert np.all(e <= GDF_TOL * s), "%s alpha_c: %d mismatches, worst %.3g" % (
+        where, int((e > GDF_TOL * s).sum()), (e / s).max())
+
+
+def oracle_chain(ps, h):
+    """Density, ghost, GDF f and alpha_c and the GDF force at the given h."""
+    d = oracle.density(ps, h, PG)
+    g = dict(oracle.ghost(d, ps.u, h, PG))
+    f, ac = oracle.gdf(ps, h, d["rho"], PG)
+    g["f"] = f
+    q = ps.copy()
+    q.alpha_c = ac.astype(np.float32)
+    fo = oracle.force(q, h, g, d["rho"], PG)
+    ref = {k: v for k, v in d.items() if k != "total"}
+    ref.update({k: v for k, v in fo.items() if k != "total"})
+    return ref, f, ac
+
+
+@pytest.mark.parametrize("case", ["lognormal", "lattice_shear"])
+def test_gdf_loop_matches_oracle(case):
+    import torch
+    from paper_2305_13380_amd import sphx
+    if case == "lognormal":
+        ps = inputs.lognormal_box(16, 6000, 2.0, 71, sigma_v=0.3)
+    else:
+        ps = inputs.lattice_box(16, 72, u="logu", sigma_v=0.2)
+    print("gdf loop: %s N=%d" % (case, ps.n), flush=True)
+    ctx = sphx.Context(sphx.default_params(), 0)
+    dp = sphx.DeviceParticles.from_set(ps)
+    out = sphx.Outputs(ps.n)
+    grid = sphx.Grid(ctx, dp)
+    tasks = sphx.Tasks(ctx, grid, dp)
+    st, _ = sphx.step(ctx, grid, tasks, dp, out)
+    assert st >= 0
+    f, ac = sphx.gdf(ctx, grid, tasks, dp, out.d["rho"])
+    torch.cuda.synchronize()
+    h = dp.t["h"].cpu().numpy().astype(np.float64)
+    rho = out.d["rho"].cpu().numpy().astype(np.float64)
+    f_ref, ac_ref = oracle.gdf(ps, h, rho, PG)
+    if case == "lognormal":
+        assert np.abs(f_ref - 1.0).max() > 1e-2  # a correction that is not trivial
+    assert ac_ref.min() > 0.0
+    check_gdf(f.cpu().numpy(), ac.cpu().numpy(), f_ref, ac_ref, "gdf loop %s" % case)
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_gdf_step_matches_oracle(case):
+    ps = CASES[case]()
+    if case == "sedov16":
+        ps.vx[:] = np.random.default_rng(5).normal(0, 0.5, ps.n).astype(np.float32)
+    print("gdf flavour step:", case, "N=%d" % ps.n, flush=True)
+    g = gpu_step(ps, params=FL)
+    assert g["status"] >= 0 and g["info"].unconverged == 0
+    h = g["h"].astype(np.float64)
+    ref, f_ref, ac_ref = oracle_chain(ps, h)
+    recv = np.arange(ps.n)
+    where = "gdf %s at its h" % case
+    check_density(g, ref, ps, h, recv, PG, where)
+    # the step returns the GDF f in f and alpha_c in A
+    check_gdf(g["f"], g["A"], f_ref, ac_ref, where)
+    check_force(g, ref, ps, h, recv, PG, where)
+    s_ref = oracle.sums(ps.m, ps.vx, ps.vy, ps.vz, ref["ax"], ref["ay"], ref["az"], ref["du"])
+    s = g["sums"]
+    assert np.abs(s[:3]).max() < 2e-5 * s[4]
+    np.testing.assert_allclose(s[4:], s_ref[4:], rtol=1e-4)
+    assert abs(s[3] - s_ref[3]) <= 1e-4 * (s_ref[4] * 1.0 + s_ref[5])
+
+
+def test_gdf_conduction_is_on():
+    """The conduction term changes du/dt where u varies (the step's du/dt
+    differs from the oracle's with alpha_c = 0 by far more than the
+    tolerance), so the step's alpha_c reaches the force pass."""
+    ps = CASES["lattice16_shear"]()
+    g = gpu_step(ps, params=FL)
+    h = g["h"].astype(np.float64)
+    ref, f_ref, _ = oracle_chain(ps, h)
+    d = oracle.density(ps, h, PG)
+    gs = dict(oracle.ghost(d, ps.u, h, PG))
+    gs["f"] = f_ref
+    q = ps.copy()
+    q.alpha_c = np.zeros(ps.n, np.float32)
+    fo0 = oracle.force(q, h, gs, d["rho"], PG)
+    gap = np.abs(ref["du"] - fo0["du"])
+    assert gap.max() > 100 * GDF_TOL * rms(ref["du"])
+    e = np.abs(g["du_dt"] - ref["du"])
+    assert e.max() < 0.01 * gap.max()
+
+
+def test_gdf_force_alone_and_captured_step_repeat_the_step():
+    import torch
+    from paper_2305_13380_amd import sphx
+    ps = inputs.lognormal_box(16, 6000, 2.0, 73, sigma_v=0.3)
+    print("gdf standalone force and captured step N=%d" % ps.n, flush=True)
+    ctx = sphx.Context(sphx.default_params(**FL), 0)
+    dp = sphx.DeviceParticles.from_set(ps)
+    out = sphx.Outputs(ps.n)
+    grid = sphx.Grid(ctx, dp)
+    tasks = sphx.Tasks(ctx, grid, dp)
+    st, _ = sphx.step(ctx, grid, tasks, dp, out)
+    assert st >= 0
+    torch.cuda.synchronize()
+    a = {k: v.cpu().numpy().copy() for k, v in {**out.g, **out.f}.items()}
+    # the force pass alone, from the step's f and alpha_c (in f and A)
+    sphx.force(ctx, grid, tasks, dp, out)
+    torch.cuda.synchronize()
+    for k in ("ax", "ay", "az", "du_dt", "v_sig"):
+        np.testing.assert_array_equal(out.f[k].cpu().numpy(), a[k], err_msg=k)
+    b = gpu_step(ps, params=FL)
+    c = gpu_step(ps, params=dict(FL, graph_passes=4))
+    for k in ("h", "f", "A", "ax", "ay", "az", "du_dt", "v_sig"):
+        np.testing.assert_array_equal(b[k], c[k], err_msg=k)
