@@ -23,11 +23,12 @@
 //   x_b,j) m_j W_ij / (S1 / 3), |S| the square root of its summed squares
 //   (f = 1 and alpha_c = 0 for a receiver with no neighbour at r > 0).
 //
-// The neighbour loops run one wave per receiving cell, one receiver per
-// lane; each task's sources are staged in LDS in the receiver cell's FP32
-// frame, and a source that no lane uses is skipped by a wave-uniform branch.
-// Both are run once per step (the h iteration runs its density loop several
-// times), so they keep this plain shape.
+// The neighbour loops run one wave per receiving cell, with the sources in
+// LDS in the receiver cell's FP32 frame. The gradient and GDF loops cull
+// each source against the receivers' box and sweep a buffer of survivors
+// with several lanes per receiver in sparse cells (the shape is described
+// before the gradient loop); the step limiter, one receiver per lane, skips
+// a source that no lane uses by a wave-uniform branch.
 #include "kernel_shapes.h"
 #include "pairs.h"
 
@@ -49,6 +50,66 @@ __global__ __launch_bounds__(kElemThreads) void k_grad_state(
     st[s] = make_float4(h[i], rho[i], P[i], av[i]);
 }
 
+// Both neighbour loops below take one wave per receiving cell. The sources
+// of each task are culled against the receivers' box grown by their largest
+// H and the survivors appended to an LDS candidate buffer of kCandCap slots;
+// a full buffer is swept by every lane. With n active receivers, each gets
+// nrep lanes (the largest power of two with nrep n <= 64) and replica r
+// tests the slots r, r + nrep, ...; the slots that pass its receiver's test
+// go to the lane's own list (8-bit slot numbers in LDS), and the pair terms
+// are evaluated over the lists, four entries a round, whenever one is
+// nearly full and at the end of the sweep (an entry past a lane's list adds
+// exactly zero). The replicas' results meet in a butterfly. Slot kCandCap
+// holds a source beyond every support (cell-frame coordinates are below the
+// box size) that replicas past the buffer read.
+constexpr int kCandCap = 128;
+constexpr float kFarSource = 1e15f;
+
+// The sources of the tasks [ta, te) that lie within R of the receivers' box
+// [lo, hb]: the task records are fetched 64 at a time (one per lane), a
+// cell beyond R is dropped as a whole, and the sources of four tasks are
+// loaded together; emit(p, keep, sj) takes each task's sources in turn (p in
+// the receiving cell's frame, keep: this lane holds a source within R, sj
+// its sorted index). Every lane runs emit the same number of times.
+template <class Emit>
+__device__ __forceinline__ void near_sources(const Task *__restrict__ task, int32_t ta,
+                                             int32_t te, const float4 *__restrict__ ext,
+                                             const float4 *__restrict__ q0, float3 lo,
+                                             float3 hb, float R2, int lane, Emit &&emit)
+{
+    for (int32_t t0 = ta; t0 < te; t0 += 64) {
+        const int nb = min(64, te - t0);
+        TaskRegs tr;
+        tr.load(task, t0 + lane, lane < nb);
+        if (lane < nb &&
+            task_box_dist2(tr.b.x, tr.b.y, tr.b.z, ext[tr.a.w], lo, hb) >= R2)
+            tr.a.y = 0;
+        for (int u = 0; u < nb; u += 4) {
+            int j0[4], jc[4];
+            float4 p[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int k = min(u + q, nb - 1);
+                j0[q] = bcast(tr.a.x, k);
+                jc[q] = (u + q < nb) ? bcast(tr.a.y, k) : 0;
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                p[q] = lane < jc[q] ? q0[j0[q] + lane] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int k = min(u + q, nb - 1);
+                p[q].x += bcastf(tr.b.x, k);
+                p[q].y += bcastf(tr.b.y, k);
+                p[q].z += bcastf(tr.b.z, k);
+                const bool keep =
+                    lane < jc[q] && box_dist2(p[q].x, p[q].y, p[q].z, lo, hb) < R2;
+                emit(p[q], keep, j0[q] + lane);
+            }
+        }
+    }
+}
+
 template <int K>
 __global__ __launch_bounds__(64) void k_gradient(
     int64_t n_leaves, const int32_t *__restrict__ leaf_start, const int32_t *__restrict__ perm,
@@ -66,77 +127,143 @@ __global__ __launch_bounds__(64) void k_gradient(
     const int32_t s0 = leaf_start[L], cnt = leaf_start[L + 1] - s0;
     const bool valid = lane < cnt;
     const int32_t s = s0 + (valid ? lane : 0);
-    const int32_t gi = perm[s];
-    const bool act = valid && (!active || active[gi] != 0);
-    if (!__any(act))
+    const bool act = valid && (!active || active[perm[s]] != 0);
+    const uint64_t amask = __ballot(act);
+    if (amask == 0)
         return;
-    const float4 pi = q0[s];  // x, y, z (cell frame), m
-    const float4 vi = q1[s];  // vx, vy, vz, u
-    const float4 si = st[s];  // h, rho, P, alpha_V
-    // Anarchy-PU (anarchy_gamma = the gas gamma, else 0): the sound speed
-    const float ci = anarchy_gamma > 0.0f ? sqrtf(anarchy_gamma * si.z / si.y) : 0.0f;
-    const float Hi = gamma_k * si.x;
-    const float H2 = act ? Hi * Hi : -1.0f;
-    const float invH = fast_rcp(Hi);
-    const float invH5 = (invH * invH) * (invH * invH) * invH;
-    constexpr float kD = Kern<K>::kD;
+    const float4 pown = q0[s];
+    const float Hown = gamma_k * st[s].x;
     const float inf = __builtin_inff();
-    float3 lo = make_float3(act ? pi.x : inf, act ? pi.y : inf, act ? pi.z : inf);
-    float3 hb = make_float3(act ? pi.x : -inf, act ? pi.y : -inf, act ? pi.z : -inf);
+    float3 lo = make_float3(act ? pown.x : inf, act ? pown.y : inf, act ? pown.z : inf);
+    float3 hb = make_float3(act ? pown.x : -inf, act ? pown.y : -inf, act ? pown.z : -inf);
     lo.x = wave_minf(lo.x);
     lo.y = wave_minf(lo.y);
     lo.z = wave_minf(lo.z);
     hb.x = wave_maxf(hb.x);
     hb.y = wave_maxf(hb.y);
     hb.z = wave_maxf(hb.z);
-    const float R = wave_maxf(act ? Hi : 0.0f);
+    const float R = wave_maxf(act ? Hown : 0.0f);
     const float R2 = R * R;
 
-    __shared__ float4 sp[kLeafMax], sv[kLeafMax], ss[kLeafMax];
-    float lap = 0.0f, vcm = 0.0f, avm = si.w;
-    const int32_t ta = tbeg[L], tb = tend[L];
-    for (int32_t t = ta; t < tb; ++t) {
-        const Task tk = task[t];
-        if (task_box_dist2(tk.ox, tk.oy, tk.oz, ext[tk.j], lo, hb) >= R2)
-            continue;
-        __syncthreads();  // (one wave per block) the previous task's sources are read
-        if (lane < tk.jc) {
-            float4 p = q0[tk.j0 + lane];
-            p.x += tk.ox;
-            p.y += tk.oy;
-            p.z += tk.oz;
-            sp[lane] = p;
-            sv[lane] = q1[tk.j0 + lane];
-            ss[lane] = st[tk.j0 + lane];
-        }
-        __syncthreads();
-        for (int k = 0; k < tk.jc; ++k) {
-            const float4 p = sp[k];
-            const float dx = pi.x - p.x, dy = pi.y - p.y, dz = pi.z - p.z;
-            const float r2 = dist2(dx, dy, dz);
-            // j != i, 0 < r < H_i (the receiver itself is at r = 0)
-            const bool on = r2 < H2 && r2 > 0.0f;
-            if (!__any(on))
-                continue;
-            const float4 v = sv[k];
-            const float4 sj = ss[k];
-            const float rinv = on ? fast_rsq(r2) : 0.0f;
-            const float r = r2 * rinv;
-            const float u = fminf(r * invH, 1.0f);
-            // dW/dr / r = -kD H^-5 phi(u)
-            const float wr = -kD * invH5 * Kern<K>::phi(u);
-            const float dl = p.w / sj.y * (vi.w - v.w) * wr;
-            const float vdx = (vi.x - v.x) * dx + (vi.y - v.y) * dy + (vi.z - v.z) * dz;
-            const float vcij =
-                anarchy_gamma > 0.0f
-                    ? ci + sqrtf(anarchy_gamma * sj.z / sj.y) + fminf(vdx, 0.0f) * rinv
-                    : fabsf(vdx) * rinv + fast_sqrt(2.0f * fabsf(si.z - sj.z) / (si.y + sj.y));
-            lap += on ? dl : 0.0f;
-            vcm = on ? fmaxf(vcm, vcij) : vcm;
-            avm = on ? fmaxf(avm, sj.w) : avm;
-        }
+    const int n_act = __popcll(amask);
+    int nrep = 1;
+    while (2 * nrep * n_act <= 64)
+        nrep *= 2;
+    __shared__ uint8_t rmap[64];
+    // x, y, z (receiver cell frame), m; vx, vy, vz, u; rho, P, alpha_V, c
+    // (c: Anarchy-PU's sound speed, else 0)
+    __shared__ float4 cp[kCandCap + 1], cv[kCandCap + 1], cs[kCandCap + 1];
+    __shared__ uint32_t lst[kListStride * 16];
+    uint8_t *my_list = reinterpret_cast<uint8_t *>(lst) + lane * kListStride;
+    if (act)
+        rmap[lanes_below(amask)] = uint8_t(lane);
+    if (lane == 0) {
+        cp[kCandCap] = make_float4(kFarSource, kFarSource, kFarSource, 0.0f);
+        cv[kCandCap] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        cs[kCandCap] = make_float4(1.0f, 0.0f, 0.0f, 0.0f);
     }
-    if (act) {
+    __syncthreads();
+    const int k = lane / nrep;
+    const bool ract = k < n_act;
+    const int32_t sr = s0 + (ract ? int(rmap[k]) : 0);
+    const int rj = lane & (nrep - 1);
+    const float4 pi = q0[sr];  // x, y, z (cell frame), m
+    const float4 vi = q1[sr];  // vx, vy, vz, u
+    const float4 si = st[sr];  // h, rho, P, alpha_V
+    // Anarchy-PU (anarchy_gamma = the gas gamma, else 0): the sound speed
+    const float ci = anarchy_gamma > 0.0f ? sqrtf(anarchy_gamma * si.z / si.y) : 0.0f;
+    const float Hi = gamma_k * si.x;
+    const float H2 = ract ? Hi * Hi : -1.0f;
+    const float invH = fast_rcp(Hi);
+    const float invH5 = (invH * invH) * (invH * invH) * invH;
+    constexpr float kD = Kern<K>::kD;
+
+    float lap = 0.0f, vcm = 0.0f, avm = si.w;
+    int nc = 0;    // candidates in the buffer (wave-uniform)
+    int myn = 0;   // this lane's list length
+    // One listed pair (on = false: past the list, reading slot 0, adds nothing).
+    auto pair = [&](int c, bool on) __attribute__((always_inline)) {
+        const float4 p = cp[c];
+        const float dx = pi.x - p.x, dy = pi.y - p.y, dz = pi.z - p.z;
+        const float r2 = dist2(dx, dy, dz);
+        const float4 v = cv[c];
+        const float4 sj = cs[c];
+        const float rinv = on ? fast_rsq(r2) : 0.0f;
+        const float r = r2 * rinv;
+        const float u = fminf(r * invH, 1.0f);
+        // dW/dr / r = -kD H^-5 phi(u)
+        const float wr = -kD * invH5 * Kern<K>::phi(u);
+        const float dl = p.w / sj.x * (vi.w - v.w) * wr;
+        const float vdx = (vi.x - v.x) * dx + (vi.y - v.y) * dy + (vi.z - v.z) * dz;
+        const float vcij =
+            anarchy_gamma > 0.0f
+                ? ci + sj.w + fminf(vdx, 0.0f) * rinv
+                : fabsf(vdx) * rinv + fast_sqrt(2.0f * fabsf(si.z - sj.y) / (si.y + sj.x));
+        lap += on ? dl : 0.0f;
+        vcm = on ? fmaxf(vcm, vcij) : vcm;
+        avm = on ? fmaxf(avm, sj.z) : avm;
+    };
+    auto compute = [&]() __attribute__((always_inline)) {
+        for (int k4 = 0; __any(k4 < myn); k4 += 4) {
+            const uint32_t four = *reinterpret_cast<const uint32_t *>(my_list + k4);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const bool listed = k4 + q < myn;
+                pair(listed ? int((four >> (8 * q)) & 0xffu) : 0, listed);
+            }
+        }
+        myn = 0;
+    };
+    auto sweep = [&]() __attribute__((always_inline)) {
+        __syncthreads();  // (one wave per block) the candidates are written
+        const int m_end = (nc + nrep - 1) / nrep;
+        for (int m = 0; m < m_end; m += 4) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int c0 = rj + (m + q) * nrep;
+                const int c = c0 < nc ? c0 : kCandCap;
+                const float4 p = cp[c];
+                const float r2 = dist2(pi.x - p.x, pi.y - p.y, pi.z - p.z);
+                // j != i, 0 < r < H_i (the receiver itself is at r = 0)
+                my_list[myn] = uint8_t(c);
+                myn += (r2 < H2 && r2 > 0.0f) ? 1 : 0;
+            }
+            if (__any(myn > kListMax - 4))
+                compute();
+        }
+        compute();
+        __syncthreads();  // the sweep has read the buffer
+        nc = 0;
+    };
+
+    near_sources(task, tbeg[L], tend[L], ext, q0, lo, hb, R2, lane,
+                 [&](const float4 &p, bool keep, int32_t j) __attribute__((always_inline)) {
+                     const uint64_t mask = __ballot(keep);
+                     if (mask == 0)
+                         return;
+                     const int tot = __popcll(mask);
+                     if (nc + tot > kCandCap)
+                         sweep();
+                     if (keep) {
+                         const int pos = nc + lanes_below(mask);
+                         const float4 sj = st[j];
+                         cp[pos] = p;
+                         cv[pos] = q1[j];
+                         cs[pos] = make_float4(
+                             sj.y, sj.z, sj.w,
+                             anarchy_gamma > 0.0f ? sqrtf(anarchy_gamma * sj.z / sj.y) : 0.0f);
+                     }
+                     nc += tot;
+                 });
+    if (nc > 0)
+        sweep();
+    for (int o = 1; o < nrep; o <<= 1) {
+        lap += __shfl_xor(lap, o, 64);
+        vcm = fmaxf(vcm, __shfl_xor(vcm, o, 64));
+        avm = fmaxf(avm, __shfl_xor(avm, o, 64));
+    }
+    if (ract && rj == 0) {
+        const int32_t gi = perm[sr];
         lap_u[gi] = 2.0f * lap;
         vc[gi] = vcm;
         avmax[gi] = avm;
@@ -164,6 +291,7 @@ __global__ __launch_bounds__(kElemThreads) void k_hrho_state(int64_t n,
 // sorted force state (g1.x = f, g1.z = alpha_c, the flavour's slots of f
 // and A); null pointers are not written. gate: a captured step whose
 // iteration is not finished returns at once.
+// (The loop shape is the gradient loop's.)
 template <int K>
 __global__ __launch_bounds__(64) void k_gdf(
     int64_t n_leaves, const int32_t *__restrict__ leaf_start, const int32_t *__restrict__ perm,
@@ -183,71 +311,142 @@ __global__ __launch_bounds__(64) void k_gdf(
     const int32_t s0 = leaf_start[L], cnt = leaf_start[L + 1] - s0;
     const bool valid = lane < cnt;
     const int32_t s = s0 + (valid ? lane : 0);
-    const int32_t gi = perm[s];
-    const bool act = valid && (!active || active[gi] != 0);
-    if (!__any(act))
+    const bool act = valid && (!active || active[perm[s]] != 0);
+    const uint64_t amask = __ballot(act);
+    if (amask == 0)
         return;
-    const float4 pi = q0[s];  // x, y, z (cell frame), m
-    const float4 vi = q1[s];  // vx, vy, vz, u
-    const float4 si = st[s];  // h, rho
-    const float Hi = gamma_k * si.x;
-    const float H2 = act ? Hi * Hi : -1.0f;
-    const float invH = fast_rcp(Hi);
+
+    // the receivers' box and largest H (over the active particles)
+    const float4 pown = q0[s];
+    const float Hown = gamma_k * st[s].x;
     const float inf = __builtin_inff();
-    float3 lo = make_float3(act ? pi.x : inf, act ? pi.y : inf, act ? pi.z : inf);
-    float3 hb = make_float3(act ? pi.x : -inf, act ? pi.y : -inf, act ? pi.z : -inf);
+    float3 lo = make_float3(act ? pown.x : inf, act ? pown.y : inf, act ? pown.z : inf);
+    float3 hb = make_float3(act ? pown.x : -inf, act ? pown.y : -inf, act ? pown.z : -inf);
     lo.x = wave_minf(lo.x);
     lo.y = wave_minf(lo.y);
     lo.z = wave_minf(lo.z);
     hb.x = wave_maxf(hb.x);
     hb.y = wave_maxf(hb.y);
     hb.z = wave_maxf(hb.z);
-    const float R = wave_maxf(act ? Hi : 0.0f);
+    const float R = wave_maxf(act ? Hown : 0.0f);
     const float R2 = R * R;
 
-    __shared__ float4 sp[kLeafMax], sv[kLeafMax];
+    // lanes -> (receiver, replica)
+    const int n_act = __popcll(amask);
+    int nrep = 1;
+    while (2 * nrep * n_act <= 64)
+        nrep *= 2;
+    __shared__ uint8_t rmap[64];
+    // x, y, z (receiver cell frame), m; and vx, vy, vz, m / rho. Slot kCandCap
+    // is a source beyond every support that replicas past the buffer read.
+    __shared__ float4 cp[kCandCap + 1], cv[kCandCap + 1];
+    __shared__ uint32_t lst[kListStride * 16];
+    uint8_t *my_list = reinterpret_cast<uint8_t *>(lst) + lane * kListStride;
+    if (act)
+        rmap[lanes_below(amask)] = uint8_t(lane);
+    if (lane == 0) {
+        // (finite: its zero weight times its distance stays zero)
+        cp[kCandCap] = make_float4(kFarSource, kFarSource, kFarSource, 0.0f);
+        cv[kCandCap] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    }
+    __syncthreads();
+    const int k = lane / nrep;
+    const bool ract = k < n_act;
+    const int32_t sr = s0 + (ract ? int(rmap[k]) : 0);
+    const int rj = lane & (nrep - 1);
+    const float4 pi = q0[sr];  // x, y, z (cell frame), m
+    const float4 vi = q1[sr];  // vx, vy, vz, u
+    const float4 si = st[sr];  // h, rho
+    const float Hi = gamma_k * si.x;
+    const float H2 = ract ? Hi * Hi : -1.0f;
+    const float invH = fast_rcp(Hi);
+
     float S1 = 0.0f, S2 = 0.0f;
     float V[3][3] = {{0.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 0.0f}};
-    const int32_t ta = tbeg[L], tb = tend[L];
-    for (int32_t t = ta; t < tb; ++t) {
-        const Task tk = task[t];
-        if (task_box_dist2(tk.ox, tk.oy, tk.oz, ext[tk.j], lo, hb) >= R2)
-            continue;
-        __syncthreads();  // (one wave per block) the previous task's sources are read
-        if (lane < tk.jc) {
-            float4 p = q0[tk.j0 + lane];
-            p.x += tk.ox;
-            p.y += tk.oy;
-            p.z += tk.oz;
-            sp[lane] = p;
-            const float4 v = q1[tk.j0 + lane];
-            // (vx, vy, vz, m_j / rho_j)
-            sv[lane] = make_float4(v.x, v.y, v.z, p.w / st[tk.j0 + lane].y);
-        }
-        __syncthreads();
-        for (int k = 0; k < tk.jc; ++k) {
-            const float4 p = sp[k];
-            const float d[3] = {pi.x - p.x, pi.y - p.y, pi.z - p.z};
-            const float r2 = dist2(d[0], d[1], d[2]);
-            // r < H_i (the receiver itself, at r = 0, adds exactly zero)
-            const bool on = r2 < H2;
-            if (!__any(on))
-                continue;
-            const float4 v = sv[k];
-            const float u = fminf(fast_sqrt(r2) * invH, 1.0f);
-            const float wt = on ? Kern<K>::w(u) : 0.0f;
-            const float mw = p.w * wt;
-            S1 += mw * r2;
-            S2 += v.w * wt * r2;
-            const float dv[3] = {vi.x - v.x, vi.y - v.y, vi.z - v.z};
+    int nc = 0;   // candidates in the buffer (wave-uniform)
+    int myn = 0;  // this lane's list length
+    // One listed pair (on = false: past the list, reading slot 0, adds
+    // exactly zero: its weight is 0 and every term carries it). The
+    // receiver itself, at r = 0, adds exactly zero too.
+    auto pair = [&](int c, bool on) __attribute__((always_inline)) {
+        const float4 p = cp[c];
+        const float d[3] = {pi.x - p.x, pi.y - p.y, pi.z - p.z};
+        const float r2 = dist2(d[0], d[1], d[2]);
+        const float4 v = cv[c];
+        const float u = fminf(fast_sqrt(r2) * invH, 1.0f);
+        const float wt = on ? Kern<K>::w(u) : 0.0f;
+        const float mw = p.w * wt;
+        S1 += mw * r2;
+        S2 += v.w * wt * r2;
+        const float dv[3] = {vi.x - v.x, vi.y - v.y, vi.z - v.z};
 #pragma unroll
-            for (int a = 0; a < 3; ++a)
+        for (int a = 0; a < 3; ++a)
 #pragma unroll
-                for (int b = 0; b < 3; ++b)
-                    V[a][b] += dv[a] * (d[b] * mw);
+            for (int b = 0; b < 3; ++b)
+                V[a][b] += dv[a] * (d[b] * mw);
+    };
+    auto compute = [&]() __attribute__((always_inline)) {
+        for (int k4 = 0; __any(k4 < myn); k4 += 4) {
+            const uint32_t four = *reinterpret_cast<const uint32_t *>(my_list + k4);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const bool listed = k4 + q < myn;
+                pair(listed ? int((four >> (8 * q)) & 0xffu) : 0, listed);
+            }
         }
+        myn = 0;
+    };
+    auto sweep = [&]() __attribute__((always_inline)) {
+        __syncthreads();  // (one wave per block) the candidates are written
+        const int m_end = (nc + nrep - 1) / nrep;
+        for (int m = 0; m < m_end; m += 4) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int c0 = rj + (m + q) * nrep;
+                const int c = c0 < nc ? c0 : kCandCap;
+                const float4 p = cp[c];
+                const float r2 = dist2(pi.x - p.x, pi.y - p.y, pi.z - p.z);
+                // r < H_i
+                my_list[myn] = uint8_t(c);
+                myn += r2 < H2 ? 1 : 0;
+            }
+            if (__any(myn > kListMax - 4))
+                compute();
+        }
+        compute();
+        __syncthreads();  // the sweep has read the buffer
+        nc = 0;
+    };
+
+    near_sources(task, tbeg[L], tend[L], ext, q0, lo, hb, R2, lane,
+                 [&](const float4 &p, bool keep, int32_t j) __attribute__((always_inline)) {
+                     const uint64_t mask = __ballot(keep);
+                     if (mask == 0)
+                         return;
+                     const int tot = __popcll(mask);
+                     if (nc + tot > kCandCap)
+                         sweep();
+                     if (keep) {
+                         const int pos = nc + lanes_below(mask);
+                         const float4 v = q1[j];
+                         cp[pos] = p;
+                         cv[pos] = make_float4(v.x, v.y, v.z, p.w / st[j].y);
+                     }
+                     nc += tot;
+                 });
+    if (nc > 0)
+        sweep();
+    // the replicas' partial sums (every replica ends with the totals)
+    for (int o = 1; o < nrep; o <<= 1) {
+        S1 += __shfl_xor(S1, o, 64);
+        S2 += __shfl_xor(S2, o, 64);
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b)
+                V[a][b] += __shfl_xor(V[a][b], o, 64);
     }
-    if (!act)
+    if (!ract || rj != 0)
         return;
     float f = 1.0f, ac = 0.0f;
     if (S1 > 0.0f && S2 > 0.0f) {
@@ -264,13 +463,14 @@ __global__ __launch_bounds__(64) void k_gdf(
             }
         ac = C * (k3 * sqrtf(ss)) * (si.x * si.x);
     }
+    const int32_t gi = perm[sr];
     if (f_out)
         f_out[gi] = f;
     if (ac_out)
         ac_out[gi] = ac;
     if (g1) {
-        g1[s].x = f;
-        g1[s].z = ac;
+        g1[sr].x = f;
+        g1[sr].z = ac;
     }
 }
 
