@@ -634,6 +634,9 @@ def main():
                     help="particles per leaf cell (8..64)")
     ap.add_argument("--kernel", default="wendland_c2", choices=sorted(KERNEL_NAMES),
                     help="smoothing kernel (default Wendland C2)")
+    ap.add_argument("--flavour", default="energy", choices=["energy", "gdf"],
+                    help="SPH flavour of the timed step: density-energy (default) or GDF "
+                         "(the same density loop, then the GDF loop and its force law)")
     ap.add_argument("--no-tune", action="store_true",
                     help="default loop shapes instead of the autotuner's")
     ap.add_argument("--shape", default="", metavar="DT,DW,FT,FW[,DB]",
@@ -683,7 +686,8 @@ def main():
     log("bench: %s: N=%d generated in %.1f s" % (args.config, ps.n, time.perf_counter() - t0))
 
     dev = "cuda:0"
-    params = sphx.default_params(leaf_max=args.leaf_max, skin=args.skin, kernel=args.kernel)
+    params = sphx.default_params(leaf_max=args.leaf_max, skin=args.skin, kernel=args.kernel,
+                                 flavour=args.flavour)
     dp = sphx.DeviceParticles.from_set(ps, dev)
     out = sphx.Outputs(ps.n, dev)
     stream = torch.cuda.current_stream()
@@ -850,7 +854,8 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": desc, "n_particles": ps.n, "seed": ps.meta.get("seed"),
-                   "kernel": KERNEL_NAMES[args.kernel], "eta": ps.eta, "h_tol": 1e-4,
+                   "kernel": KERNEL_NAMES[args.kernel], "flavour": args.flavour,
+                   "eta": ps.eta, "h_tol": 1e-4,
                    "positions": "f64 (cell offsets f64, pair arithmetic f32)",
                    "n_dens": n_dens, "n_force": n_force, "density_passes": passes,
                    "task_rebuilds_per_step": infos[-1][1], "unconverged": infos[-1][2],
