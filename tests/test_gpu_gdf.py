@@ -8,7 +8,10 @@ oracle:
   and the GDF forces with the conduction term, against the oracle's chain
   (density, ghost, GDF quantities, force) at the step's own h;
 * the standalone force pass fed with the step's f and alpha_c repeats the
-  step's forces bitwise, and a captured step repeats the pass-by-pass one.
+  step's forces bitwise, and a captured step repeats the pass-by-pass one;
+* an active subset, whose inactive sources keep their previous f and
+  alpha_c, against the oracle at the step's own h;
+* the loop with other kernels of the family.
 """
 import numpy as np
 import pytest
@@ -149,3 +152,99 @@ def test_gdf_force_alone_and_captured_step_repeat_the_step():
     c = gpu_step(ps, params=dict(FL, graph_passes=4))
     for k in ("h", "f", "A", "ax", "ay", "az", "du_dt", "v_sig"):
         np.testing.assert_array_equal(b[k], c[k], err_msg=k)
+
+
+def test_gdf_active_subset_step():
+    """Only active particles receive. Inactive ones are sources that keep the
+    state of a previous all-active step, including their GDF f and alpha_c
+    (read back from sphx_ghost_out.f and .A). Every output of the active
+    step is checked against the oracle at the step's own h: the receivers at
+    their final h with the new u, the inactive sources at their step-1 h."""
+    import torch
+    from paper_2305_13380_amd import sphx
+    ps = inputs.lognormal_box(16, 5000, 2.0, 23, sigma_v=0.3,
+                              time_bins=(0.1, 0.2, 0.3, 0.4))
+    print("gdf active subset N=%d" % ps.n, flush=True)
+    act = ps.active.astype(bool)
+    all_on = ps.copy()
+    all_on.active = None
+    ctx = sphx.Context(sphx.default_params(**FL), 0)
+    dp = sphx.DeviceParticles.from_set(all_on)
+    out = sphx.Outputs(ps.n)
+    grid = sphx.Grid(ctx, dp)
+    tasks = sphx.Tasks(ctx, grid, dp)
+    st1, _ = sphx.step(ctx, grid, tasks, dp, out)
+    assert st1 >= 0
+    h1 = dp.t["h"].cpu().numpy()
+    step1 = {k: v.cpu().numpy() for k, v in {**out.d, **out.g, **out.f}.items()}
+    dp.t["active"] = torch.from_numpy(ps.active).cuda()
+    q = ps.copy()
+    q.h = h1.copy()
+    q.u = q.u * np.float32(1.5)
+    dp.t["u"] = torch.from_numpy(q.u).cuda()
+    grid2 = sphx.Grid(ctx, dp)
+    tasks2 = sphx.Tasks(ctx, grid2, dp)
+    st, info = sphx.step(ctx, grid2, tasks2, dp, out)
+    torch.cuda.synchronize()
+    assert st >= 0 and info.unconverged == 0
+    g = {k: v.cpu().numpy() for k, v in {**out.d, **out.g, **out.f}.items()}
+    g["du"], g["vsig"] = g["du_dt"], g["v_sig"]
+    hg = dp.t["h"].cpu().numpy().astype(np.float64)
+    ridx = np.nonzero(act)[0]
+    for k in g:  # the inactive particles' outputs are untouched
+        if k in step1:
+            assert np.array_equal(g[k][~act], step1[k][~act]), k
+    # the oracle: step-1 state of everything at h1 with the step-1 u
+    h1d = h1.astype(np.float64)
+    d1 = oracle.density(ps, h1d, PG)
+    s1 = dict(oracle.ghost(d1, ps.u, h1d, PG))
+    f1, ac1 = oracle.gdf(ps, h1d, d1["rho"], PG)
+    # the receivers at their final h with the new u
+    d2 = oracle.density(q, hg, PG, recv=ridx)
+    g2 = oracle.ghost(d2, q.u[ridx], hg[ridx], PG)
+    rho = d1["rho"].copy()
+    rho[ridx] = d2["rho"]
+    f2, ac2 = oracle.gdf(q, hg, rho, PG, recv=ridx)
+    state = {k: s1[k].copy() for k in ("P", "c", "balsara")}
+    for k in state:
+        state[k][ridx] = g2[k]
+    state["f"] = f1.copy()
+    state["f"][ridx] = f2
+    qa = q.copy()
+    ac = ac1.copy()
+    ac[ridx] = ac2
+    qa.alpha_c = ac.astype(np.float32)
+    fo = oracle.force(qa, hg, state, rho, PG, recv=ridx)
+    ref = {**{k: v for k, v in d2.items() if k != "total"}, **g2,
+           **{k: v for k, v in fo.items() if k != "total"}}
+    where = "gdf active step at its h"
+    check_density(g, ref, q, hg, ridx, PG, where)
+    check_gdf(g["f"][ridx], g["A"][ridx], f2, ac2, where)
+    check_force(g, ref, q, hg, ridx, PG, where)
+
+
+@pytest.mark.parametrize("name", ["wendland_c6", "cubic_spline", "quintic_spline"])
+def test_gdf_loop_other_kernels(name):
+    """The GDF loop with the other kernels of the family (the bare w(u) of
+    each, its normalisation cancelling), at the step's own h and rho."""
+    import torch
+    from paper_2305_13380_amd import sphx
+    ps = inputs.lognormal_box(16, 6000, 2.0, 75, sigma_v=0.3)
+    print("gdf loop, kernel %s N=%d" % (name, ps.n), flush=True)
+    P = oracle.Params.with_kernel(name, flavour="gdf")
+    ctx = sphx.Context(sphx.default_params(kernel=name, **FL), 0)
+    dp = sphx.DeviceParticles.from_set(ps)
+    out = sphx.Outputs(ps.n)
+    grid = sphx.Grid(ctx, dp)
+    tasks = sphx.Tasks(ctx, grid, dp)
+    st, _ = sphx.step(ctx, grid, tasks, dp, out)
+    assert st >= 0
+    f, ac = sphx.gdf(ctx, grid, tasks, dp, out.d["rho"])
+    torch.cuda.synchronize()
+    h = dp.t["h"].cpu().numpy().astype(np.float64)
+    rho = out.d["rho"].cpu().numpy().astype(np.float64)
+    f_ref, ac_ref = oracle.gdf(ps, h, rho, P)
+    check_gdf(f.cpu().numpy(), ac.cpu().numpy(), f_ref, ac_ref, "gdf loop %s" % name)
+    # the step's own f and alpha_c are the loop's (the same inputs)
+    np.testing.assert_array_equal(out.g["f"].cpu().numpy(), f.cpu().numpy())
+    np.testing.assert_array_equal(out.g["A"].cpu().numpy(), ac.cpu().numpy())
