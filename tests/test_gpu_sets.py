@@ -123,3 +123,14 @@ def test_noalloc_force_refuses_a_grid_of_sets():
     tasks.close()
     grid.close()
     ctx.close()
+
+
+def test_sets_gdf_step_equals_each_set_alone():
+    """The GDF flavour on a grid of sets: its loop and force law per set are
+    bitwise the ones each set gets alone (f and alpha_c included)."""
+    sets = mixed_sets()
+    for ps in sets:
+        ps.vx[:] = np.random.default_rng(ps.n).normal(0, 0.3, ps.n).astype(np.float32)
+    res, info = sets_step(sets, params={"flavour": "gdf"})
+    assert info.passes >= 2
+    same_as_alone(res, sets, params={"flavour": "gdf"}, where="gdf")
