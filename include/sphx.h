@@ -143,6 +143,15 @@ typedef struct sphx_params {
      * and returns them there. The alpha_V evolution of the printed scheme
      * is not part of it). */
     int32_t flavour;
+    /* 1: a destroyed grid's device buffers stay with its context and serve
+     * the context's next grid build on the same stream (a buffer of between
+     * the requested size and twice it); what that build does not take is
+     * released at its end, and any rest at sphx_ctx_destroy. For runs that
+     * build a new grid of one particle set every step, whose builds then
+     * allocate little or nothing. Grids built so must be destroyed before
+     * their context. Default 0: a grid's buffers are released when it is
+     * destroyed. */
+    int32_t recycle_workspace;
 } sphx_params;
 
 #define SPHX_FLAVOUR_DENSITY_ENERGY 0

@@ -4,11 +4,18 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <string>
 
 #include "kernel_shapes.h"
 #include "sphx_internal.h"
+
+uint64_t next_serial()
+{
+    static std::atomic<uint64_t> counter{0};
+    return ++counter;
+}
 
 namespace sphx {
 
@@ -132,6 +139,7 @@ void sphx_params_default(sphx_params *p)
     p->density_balance = 0;
     p->kernel = SPHX_KERNEL_WENDLAND_C2;
     p->flavour = SPHX_FLAVOUR_DENSITY_ENERGY;
+    p->recycle_workspace = 0;
 }
 
 sphx_status sphx_params_set_kernel(sphx_params *p, int32_t kernel)
@@ -255,6 +263,7 @@ void sphx_ctx_destroy(sphx_ctx *ctx)
     if (!ctx)
         return;
     step_graph_free(ctx->graph);
+    release_spares(ctx);
     (void)hipFree(ctx->d_counters);
     (void)hipFree(ctx->d_sums);
     (void)hipHostFree(ctx->h_pinned);

@@ -222,7 +222,9 @@ sphx_status step_graph_run(sphx_ctx *ctx, sphx_grid *grid, sphx_tasks *t, const 
         gst->curl_v, gst->converged, out->ax, out->ay, out->az, out->du_dt, out->v_sig,
         out->nforce, sums6, reinterpret_cast<const void *>(intptr_t(passes)),
         reinterpret_cast<const void *>(intptr_t(grid->n)),
-        reinterpret_cast<const void *>(intptr_t(grid->n_leaves))};
+        reinterpret_cast<const void *>(intptr_t(grid->n_leaves)),
+        reinterpret_cast<const void *>(uintptr_t(grid->serial)),
+        reinterpret_cast<const void *>(uintptr_t(t->serial))};
     if (!G->exec || key != G->key) {
         if (G->exec) {
             (void)hipGraphExecDestroy(G->exec);

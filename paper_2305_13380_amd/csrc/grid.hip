@@ -413,7 +413,48 @@ sphx_status dalloc(T **p, size_t count, hipStream_t s)
 
 inline unsigned blocks(int64_t n, int t) { return unsigned((n + t - 1) / t); }
 
+// A buffer of the grid. With recycle_workspace: a spare of the context
+// (freed there on this stream) whose size lies in [bytes, 2 bytes], the
+// smallest such, else a new allocation; either way recorded in g->owned.
+template <class T>
+sphx_status galloc(sphx_grid *g, T **p, size_t count, hipStream_t s)
+{
+    *p = nullptr;
+    if (count == 0)
+        count = 1;
+    const size_t bytes = count * sizeof(T);
+    if (!g->recycle) {
+        SPHX_HIP(dmalloc((void **)p, bytes, s));
+        return SPHX_OK;
+    }
+    auto &sp = g->ctx->spare;
+    if (s == g->ctx->spare_stream) {
+        size_t pick = sp.size();
+        for (size_t k = 0; k < sp.size(); ++k) {
+            const size_t b = sp[k].second;
+            if (b >= bytes && b / 2 <= bytes && (pick == sp.size() || b < sp[pick].second))
+                pick = k;
+        }
+        if (pick < sp.size()) {
+            *p = static_cast<T *>(sp[pick].first);
+            g->owned.push_back(sp[pick]);
+            sp.erase(sp.begin() + pick);
+            return SPHX_OK;
+        }
+    }
+    SPHX_HIP(dmalloc((void **)p, bytes, s));
+    g->owned.emplace_back(static_cast<void *>(*p), bytes);
+    return SPHX_OK;
+}
+
 }  // namespace
+
+void release_spares(sphx_ctx *ctx)
+{
+    for (auto &b : ctx->spare)
+        dfree(b.first, ctx->spare_stream);
+    ctx->spare.clear();
+}
 
 size_t grid_bytes(int64_t n)
 {
@@ -431,6 +472,21 @@ void grid_free(sphx_grid *g)
 {
     if (!g)
         return;
+    if (g->recycle) {
+        // the grid's own buffers become the context's spares (an older
+        // grid's leftovers are freed first); the rest is freed below
+        release_spares(g->ctx);
+        g->ctx->spare = std::move(g->owned);
+        g->ctx->spare_stream = g->stream;
+    }
+    auto spare = [&](void *p) {
+        if (!g->recycle)
+            return false;
+        for (auto &b : g->ctx->spare)
+            if (b.first == p)
+                return true;
+        return false;
+    };
     void *ptrs[] = {g->keys,    g->perm,     g->leaf_of,  g->q0,      g->q1,     g->qa,
                     g->need,    g->g0,       g->g1,       g->g2,       g->leaf_start, g->leaf_org,
                     g->node_lo,
@@ -440,7 +496,8 @@ void grid_free(sphx_grid *g)
                     g->leaf_ext, g->leaf_hmax, g->hlo, g->hhi, g->set_start, g->set_of,
                     g->set_leaf, g->leaf_set};
     for (void *p : ptrs)
-        dfree(p, g->stream);
+        if (!spare(p))
+            dfree(p, g->stream);
     delete g;
 }
 
@@ -470,11 +527,13 @@ sphx_status grid_build(sphx_ctx *ctx, const sphx_particles *in, hipStream_t s, s
     const sphx_params &P = ctx->p;
     const int64_t n = in->n;
     sphx_grid *g = new sphx_grid();
+    g->serial = next_serial();
     *out = nullptr;
     g->ctx = ctx;
     g->stream = s;
     g->n = n;
     g->n_sets = sets ? n_sets : 1;
+    g->recycle = P.recycle_workspace != 0;
     struct Guard {
         sphx_grid *g;
         bool keep = false;
@@ -485,34 +544,34 @@ sphx_status grid_build(sphx_ctx *ctx, const sphx_particles *in, hipStream_t s, s
         }
     } guard{g};
 
-    SPHX_TRY(dalloc(&g->d_status, 4, s));
+    SPHX_TRY(galloc(g, &g->d_status, 4, s));
     SPHX_HIP(hipMemsetAsync(g->d_status, 0, 4 * sizeof(int32_t), s));
-    SPHX_TRY(dalloc(&g->keys, n, s));
-    SPHX_TRY(dalloc(&g->keys_in, n, s));
-    SPHX_TRY(dalloc(&g->perm, n, s));
-    SPHX_TRY(dalloc(&g->idx_in, n, s));
-    SPHX_TRY(dalloc(&g->leaf_of, n, s));
-    SPHX_TRY(dalloc(&g->flags, 2 * n, s));
-    SPHX_TRY(dalloc(&g->q0, n, s));
-    SPHX_TRY(dalloc(&g->q1, n, s));
-    SPHX_TRY(dalloc(&g->qa, n, s));
-    SPHX_TRY(dalloc(&g->need, n, s));
-    SPHX_TRY(dalloc(&g->g0, n, s));
-    SPHX_TRY(dalloc(&g->g1, n, s));
-    SPHX_TRY(dalloc(&g->g2, n, s));
-    SPHX_TRY(dalloc(&g->hs, n, s));
-    SPHX_TRY(dalloc(&g->hlo, n, s));
-    SPHX_TRY(dalloc(&g->hhi, n, s));
-    SPHX_TRY(dalloc(&g->d0, n, s));
-    SPHX_TRY(dalloc(&g->d1, n, s));
+    SPHX_TRY(galloc(g, &g->keys, n, s));
+    SPHX_TRY(galloc(g, &g->keys_in, n, s));
+    SPHX_TRY(galloc(g, &g->perm, n, s));
+    SPHX_TRY(galloc(g, &g->idx_in, n, s));
+    SPHX_TRY(galloc(g, &g->leaf_of, n, s));
+    SPHX_TRY(galloc(g, &g->flags, 2 * n, s));
+    SPHX_TRY(galloc(g, &g->q0, n, s));
+    SPHX_TRY(galloc(g, &g->q1, n, s));
+    SPHX_TRY(galloc(g, &g->qa, n, s));
+    SPHX_TRY(galloc(g, &g->need, n, s));
+    SPHX_TRY(galloc(g, &g->g0, n, s));
+    SPHX_TRY(galloc(g, &g->g1, n, s));
+    SPHX_TRY(galloc(g, &g->g2, n, s));
+    SPHX_TRY(galloc(g, &g->hs, n, s));
+    SPHX_TRY(galloc(g, &g->hlo, n, s));
+    SPHX_TRY(galloc(g, &g->hhi, n, s));
+    SPHX_TRY(galloc(g, &g->d0, n, s));
+    SPHX_TRY(galloc(g, &g->d1, n, s));
     if (smoothed_pressure(P.flavour))
-        SPHX_TRY(dalloc(&g->d2, n, s));
+        SPHX_TRY(galloc(g, &g->d2, n, s));
     if (sets) {
         std::vector<int32_t> h_sets(size_t(n_sets) + 1);
         for (int32_t b = 0; b <= n_sets; ++b)
             h_sets[b] = int32_t(sets[b]);
-        SPHX_TRY(dalloc(&g->set_start, n_sets + 1, s));
-        SPHX_TRY(dalloc(&g->set_leaf, n_sets + 1, s));
+        SPHX_TRY(galloc(g, &g->set_start, n_sets + 1, s));
+        SPHX_TRY(galloc(g, &g->set_leaf, n_sets + 1, s));
         SPHX_HIP(hipMemcpyAsync(g->set_start, h_sets.data(), h_sets.size() * sizeof(int32_t),
                                 hipMemcpyHostToDevice, s));
         // (the copy reads the host array before this call returns)
@@ -522,11 +581,13 @@ sphx_status grid_build(sphx_ctx *ctx, const sphx_particles *in, hipStream_t s, s
     if (n == 0) {
         g->n_leaves = 0;
         g->n_levels = 0;
-        SPHX_TRY(dalloc(&g->leaf_start, 1, s));
+        SPHX_TRY(galloc(g, &g->leaf_start, 1, s));
         SPHX_HIP(hipMemsetAsync(g->leaf_start, 0, sizeof(int32_t), s));
         if (sets)
             SPHX_HIP(hipMemsetAsync(g->set_leaf, 0, (size_t(n_sets) + 1) * sizeof(int32_t), s));
-        SPHX_TRY(dalloc(&g->fsum, 6 * 128 * int64_t(g->n_sets), s));
+        SPHX_TRY(galloc(g, &g->fsum, 6 * 128 * int64_t(g->n_sets), s));
+        if (g->recycle)
+            release_spares(ctx);
         guard.keep = true;
         *out = g;
         return SPHX_OK;
@@ -552,12 +613,12 @@ sphx_status grid_build(sphx_ctx *ctx, const sphx_particles *in, hipStream_t s, s
     SPHX_HIP(rocprim::inclusive_scan(nullptr, tmp2, g->flags, g->flags + n, size_t(n),
                                      rocprim::plus<uint32_t>(), s));
     g->sort_tmp_bytes = tmp > tmp2 ? tmp : tmp2;
-    SPHX_HIP(dmalloc(&g->sort_tmp, g->sort_tmp_bytes, s));
+    SPHX_TRY(galloc(g, reinterpret_cast<char **>(&g->sort_tmp), g->sort_tmp_bytes, s));
     if (sets) {
         SPHX_HIP(rocprim::segmented_radix_sort_pairs(
             g->sort_tmp, tmp, g->keys_in, g->keys, g->idx_in, g->perm, unsigned(n),
             unsigned(n_sets), g->set_start, g->set_start + 1, 0, 63, s));
-        SPHX_TRY(dalloc(&g->set_of, n, s));
+        SPHX_TRY(galloc(g, &g->set_of, n, s));
         k_set_of<<<blocks(n, 256), 256, 0, s>>>(n, g->set_start, n_sets, g->set_of);
         SPHX_HIP(hipGetLastError());
     } else {
@@ -578,7 +639,7 @@ sphx_status grid_build(sphx_ctx *ctx, const sphx_particles *in, hipStream_t s, s
     // Octree leaves -> parents -> packed cells. flags[0, n) holds the leaf
     // starts, flags[n, 2n) their inclusive scan; the cell starts then reuse
     // flags[0, n) (cleared first) and their scan flags[n, 2n).
-    SPHX_TRY(dalloc(&g->leaf_start, n + 1, s));
+    SPHX_TRY(galloc(g, &g->leaf_start, n + 1, s));
     int32_t *par_lvl = nullptr;
     uint64_t *par_pfx = nullptr;
     SPHX_TRY(dalloc(&par_lvl, n, s));
@@ -641,16 +702,16 @@ sphx_status grid_build(sphx_ctx *ctx, const sphx_particles *in, hipStream_t s, s
     }
     g->n_levels = lev;
     g->n_nodes = off;
-    SPHX_TRY(dalloc(&g->leaf_org, 3 * nl, s));
-    SPHX_TRY(dalloc(&g->leaf_ext, nl, s));
-    SPHX_TRY(dalloc(&g->leaf_hmax, nl, s));
-    SPHX_TRY(dalloc(&g->node_lo, 3 * off, s));
-    SPHX_TRY(dalloc(&g->node_hi, 3 * off, s));
-    SPHX_TRY(dalloc(&g->node_r, off, s));
+    SPHX_TRY(galloc(g, &g->leaf_org, 3 * nl, s));
+    SPHX_TRY(galloc(g, &g->leaf_ext, nl, s));
+    SPHX_TRY(galloc(g, &g->leaf_hmax, nl, s));
+    SPHX_TRY(galloc(g, &g->node_lo, 3 * off, s));
+    SPHX_TRY(galloc(g, &g->node_hi, 3 * off, s));
+    SPHX_TRY(galloc(g, &g->node_r, off, s));
     // + the parts of each set's reduction of the sums
-    SPHX_TRY(dalloc(&g->fsum, 6 * (nl + 128 * int64_t(g->n_sets)), s));
+    SPHX_TRY(galloc(g, &g->fsum, 6 * (nl + 128 * int64_t(g->n_sets)), s));
     if (sets) {
-        SPHX_TRY(dalloc(&g->leaf_set, nl > 0 ? nl : 1, s));
+        SPHX_TRY(galloc(g, &g->leaf_set, nl > 0 ? nl : 1, s));
         k_set_leaves<<<blocks(std::max<int64_t>(nl, int64_t(n_sets) + 1), 256), 256, 0, s>>>(
             n, n_sets, g->set_start, g->leaf_of, g->leaf_start, g->set_of, g->d_status + 1,
             g->set_leaf, g->leaf_set);
@@ -671,6 +732,8 @@ sphx_status grid_build(sphx_ctx *ctx, const sphx_particles *in, hipStream_t s, s
         SPHX_HIP(hipGetLastError());
     }
     SPHX_TRY(iter_reset(g, in, s));
+    if (g->recycle)
+        release_spares(ctx);  // the spares this build did not take
     guard.keep = true;
     *out = g;
     return SPHX_OK;

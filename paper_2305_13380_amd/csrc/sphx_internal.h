@@ -119,11 +119,24 @@ struct sphx_ctx {
     unsigned char *h_pinned = nullptr;  // kPinnedBytes
     hipEvent_t ev_wait = nullptr;
     double *noalloc_sums = nullptr;  // this device's fixed workspace (sphx_force_noalloc)
+    // recycle_workspace: the buffers (pointer, bytes) of the last destroyed
+    // grid, freed on spare_stream unless the next build there takes them
+    std::vector<std::pair<void *, size_t>> spare;
+    hipStream_t spare_stream = nullptr;
 };
+
+// A number no other grid or task list of the process has had (a captured
+// step is keyed on it: a new object can reuse a freed one's addresses).
+uint64_t next_serial();
 
 struct sphx_grid {
     sphx_ctx *ctx;
+    uint64_t serial;
     hipStream_t stream;  // the stream the grid was built on (its memory is freed there)
+    // recycle_workspace: the buffers of the build, handed back to the
+    // context's spares when the grid is destroyed
+    bool recycle = false;
+    std::vector<std::pair<void *, size_t>> owned;
     int64_t n;
     int64_t n_leaves;
     int n_levels;
@@ -201,6 +214,7 @@ struct sphx_grid {
 
 struct sphx_tasks {
     sphx_grid *grid;
+    uint64_t serial;
     hipStream_t stream;  // the stream of the last build (its memory is freed there)
     int64_t n_tasks;     // tasks held (host copy, as of the last build or captured step)
     int64_t cap;         // task records allocated
@@ -249,6 +263,8 @@ hipError_t wait_stream(sphx_ctx *ctx, hipStream_t s);
 sphx_status grid_build(sphx_ctx *ctx, const sphx_particles *in, hipStream_t s, sphx_grid **out,
                        const int64_t *sets = nullptr, int32_t n_sets = 1);
 void grid_free(sphx_grid *g);
+// Frees the context's spare buffers (recycle_workspace) on their stream.
+void release_spares(sphx_ctx *ctx);
 sphx_status iter_reset(sphx_grid *g, const sphx_particles *in, hipStream_t s);
 sphx_status refresh_h(sphx_grid *g, const sphx_particles *in, hipStream_t s);
 size_t grid_bytes(int64_t n);

@@ -907,6 +907,7 @@ sphx_status tasks_build(sphx_ctx *ctx, sphx_grid *g, const sphx_particles *in, h
     bool fresh = false;
     if (!t) {
         t = new sphx_tasks();
+        t->serial = next_serial();
         t->grid = g;
         t->stream = s;
         fresh = true;

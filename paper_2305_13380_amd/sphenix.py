@@ -29,7 +29,11 @@ class SphenixRun:
         import torch
         from paper_2305_13380_amd import sphx
         self.sphx = sphx
-        self.ctx = sphx.Context(params, 0)
+        # a new grid of the same set every step: its builds reuse the last
+        # grid's buffers instead of allocating
+        p = sphx.default_params() if params is None else type(params).from_buffer_copy(params)
+        p.recycle_workspace = 1
+        self.ctx = sphx.Context(p, 0)
         self.dp = sphx.DeviceParticles.from_set(ps, device)
         self.out = sphx.Outputs(ps.n, device)
         self.n = ps.n

@@ -37,7 +37,8 @@ class Params(C.Structure):
                 ("neighbour_lists", C.c_int32), ("density_tile", C.c_int32),
                 ("density_waves", C.c_int32), ("force_tile", C.c_int32),
                 ("force_waves", C.c_int32), ("graph_passes", C.c_int32),
-                ("density_balance", C.c_int32), ("kernel", C.c_int32), ("flavour", C.c_int32)]
+                ("density_balance", C.c_int32), ("kernel", C.c_int32), ("flavour", C.c_int32),
+                ("recycle_workspace", C.c_int32)]
 
 
 # Smoothing kernels (SPHX_KERNEL_* of sphx.h), by name.
