@@ -24,11 +24,11 @@
 //   (f = 1 and alpha_c = 0 for a receiver with no neighbour at r > 0).
 //
 // The neighbour loops run one wave per receiving cell, with the sources in
-// LDS in the receiver cell's FP32 frame. The gradient and GDF loops cull
-// each source against the receivers' box and sweep a buffer of survivors
-// with several lanes per receiver in sparse cells (the shape is described
-// before the gradient loop); the step limiter, one receiver per lane, skips
-// a source that no lane uses by a wave-uniform branch.
+// LDS in the receiver cell's FP32 frame. They cull each source against the
+// receivers' box and sweep a buffer of survivors with several lanes per
+// receiver in sparse cells (the shape is described before the gradient
+// loop); the gradient and GDF loops evaluate their pairs over per-lane
+// lists, the step limiter (a compare and a minimum per pair) directly.
 #include "kernel_shapes.h"
 #include "pairs.h"
 
@@ -536,62 +536,135 @@ __global__ __launch_bounds__(64) void k_dt_limit(
     const int32_t s0 = leaf_start[L], cnt = leaf_start[L + 1] - s0;
     const bool valid = lane < cnt;
     const int32_t s = s0 + (valid ? lane : 0);
-    const int32_t gi = perm[s];
-    const bool act = valid && (!active || active[gi] != 0);
-    if (!__any(act))
+    const bool act = valid && (!active || active[perm[s]] != 0);
+    const uint64_t amask = __ballot(act);
+    if (amask == 0)
         return;
-    const float4 pi = q0[s];
-    const float4 si = st[s];
-    const float Hi = gamma_k * si.x;
-    const float H2 = act ? Hi * Hi : -1.0f;
+    const float4 pown = q0[s];
+    const float Hown = gamma_k * st[s].x;
     const float inf = __builtin_inff();
-    float3 lo = make_float3(act ? pi.x : inf, act ? pi.y : inf, act ? pi.z : inf);
-    float3 hb = make_float3(act ? pi.x : -inf, act ? pi.y : -inf, act ? pi.z : -inf);
+    float3 lo = make_float3(act ? pown.x : inf, act ? pown.y : inf, act ? pown.z : inf);
+    float3 hb = make_float3(act ? pown.x : -inf, act ? pown.y : -inf, act ? pown.z : -inf);
     lo.x = wave_minf(lo.x);
     lo.y = wave_minf(lo.y);
     lo.z = wave_minf(lo.z);
     hb.x = wave_maxf(hb.x);
     hb.y = wave_maxf(hb.y);
     hb.z = wave_maxf(hb.z);
-    const float R = wave_maxf(act ? Hi : 0.0f);
+    const float R = wave_maxf(act ? Hown : 0.0f);
     const float R2 = R * R;
-    __shared__ float4 sp[kLeafMax];
-    __shared__ float2 ss[kLeafMax];
+
+    const int n_act = __popcll(amask);
+    int nrep = 1;
+    while (2 * nrep * n_act <= 64)
+        nrep *= 2;
+    __shared__ uint8_t rmap[64];
+    // x, y, z (receiver cell frame), H_j^2; and delta dt_j with the sorted
+    // index of a source met in the unshifted self task (else -1)
+    __shared__ float4 cp[kCandCap + 1];
+    __shared__ float cdt[kCandCap + 1];
+    __shared__ int32_t cself[kCandCap + 1];
+    if (act)
+        rmap[lanes_below(amask)] = uint8_t(lane);
+    if (lane == 0) {
+        cp[kCandCap] = make_float4(kFarSource, kFarSource, kFarSource, 0.0f);
+        cdt[kCandCap] = inf;
+        cself[kCandCap] = -1;
+    }
+    __syncthreads();
+    const int k = lane / nrep;
+    const bool ract = k < n_act;
+    const int32_t sr = s0 + (ract ? int(rmap[k]) : 0);
+    const int rj = lane & (nrep - 1);
+    const float4 pi = q0[sr];
+    const float4 si = st[sr];  // h, CFL step
+    const float Hi = gamma_k * si.x;
+    const float H2 = ract ? Hi * Hi : -1.0f;
+
     float lim = si.y;
-    const int32_t ta = tbeg[L], tb = tend[L];
-    for (int32_t t = ta; t < tb; ++t) {
-        const Task tk = task[t];
-        // a source cell reaches the receivers within max(R, its largest H)
-        const float rj = hmax[tk.j];
-        if (task_box_dist2(tk.ox, tk.oy, tk.oz, ext[tk.j], lo, hb) >= fmaxf(R2, rj * rj))
-            continue;
-        __syncthreads();
-        if (lane < tk.jc) {
-            float4 p = q0[tk.j0 + lane];
-            p.x += tk.ox;
-            p.y += tk.oy;
-            p.z += tk.oz;
-            sp[lane] = p;
-            const float4 sj = st[tk.j0 + lane];
-            ss[lane] = make_float2(gamma_k * sj.x, sj.y);
-        }
-        __syncthreads();
-        // the receiver itself: in the unshifted self task, at its own slot
-        const int own = (tk.self && valid) ? s - tk.j0 : -1;
-        for (int k = 0; k < tk.jc; ++k) {
-            const float4 p = sp[k];
-            const float2 sj = ss[k];
+    int nc = 0;  // candidates in the buffer (wave-uniform)
+    auto sweep = [&]() __attribute__((always_inline)) {
+        __syncthreads();  // (one wave per block) the candidates are written
+        const int m_end = (nc + nrep - 1) / nrep;
+        for (int m = 0; m < m_end; ++m) {
+            const int c0 = rj + m * nrep;
+            const int c = c0 < nc ? c0 : kCandCap;
+            const float4 p = cp[c];
             const float r2 = dist2(pi.x - p.x, pi.y - p.y, pi.z - p.z);
-            const bool on = k != own && r2 < fmaxf(H2, act ? sj.x * sj.x : -1.0f);
-            lim = on ? fminf(lim, delta * sj.y) : lim;
+            // j != i (the receiver itself, in the unshifted self task) with
+            // r < max(H_i, H_j)
+            const bool on = cself[c] != sr && r2 < fmaxf(H2, ract ? p.w : -1.0f);
+            lim = on ? fminf(lim, cdt[c]) : lim;
+        }
+        __syncthreads();  // the sweep has read the buffer
+        nc = 0;
+    };
+
+    // As near_sources, with the cull radius of a source cell max(R, its
+    // largest H) and of a source max(R, H_j).
+    const int32_t ta = tbeg[L], te = tend[L];
+    for (int32_t t0 = ta; t0 < te; t0 += 64) {
+        const int nb = min(64, te - t0);
+        TaskRegs tr;
+        tr.load(task, t0 + lane, lane < nb);
+        if (lane < nb) {
+            const float hj = hmax[tr.a.w];
+            if (task_box_dist2(tr.b.x, tr.b.y, tr.b.z, ext[tr.a.w], lo, hb) >= fmaxf(R2, hj * hj))
+                tr.a.y = 0;
+        }
+        for (int u = 0; u < nb; u += 4) {
+            int j0[4], jc[4], self[4];
+            float4 p[4];
+            float2 sj[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int kk = min(u + q, nb - 1);
+                j0[q] = bcast(tr.a.x, kk);
+                jc[q] = (u + q < nb) ? bcast(tr.a.y, kk) : 0;
+                self[q] = bcast(tr.a.z, kk);
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const bool in = lane < jc[q];
+                p[q] = in ? q0[j0[q] + lane] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                const float4 e = in ? st[j0[q] + lane] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                sj[q] = make_float2(e.x, e.y);
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int kk = min(u + q, nb - 1);
+                p[q].x += bcastf(tr.b.x, kk);
+                p[q].y += bcastf(tr.b.y, kk);
+                p[q].z += bcastf(tr.b.z, kk);
+                const float Hj = gamma_k * sj[q].x;
+                const bool keep = lane < jc[q] &&
+                                  box_dist2(p[q].x, p[q].y, p[q].z, lo, hb) < fmaxf(R2, Hj * Hj);
+                const uint64_t mask = __ballot(keep);
+                if (mask == 0)
+                    continue;
+                const int tot = __popcll(mask);
+                if (nc + tot > kCandCap)
+                    sweep();
+                if (keep) {
+                    const int pos = nc + lanes_below(mask);
+                    cp[pos] = make_float4(p[q].x, p[q].y, p[q].z, Hj * Hj);
+                    cdt[pos] = delta * sj[q].y;
+                    cself[pos] = self[q] ? j0[q] + lane : -1;
+                }
+                nc += tot;
+            }
         }
     }
-    if (act)
-        dt_out[gi] = lim;
-    float m = act ? lim : inf;
-    m = wave_minf(m);
-    if (lane == 0 && m < inf)
-        atomicMin(dt_min, __float_as_int(m));
+    if (nc > 0)
+        sweep();
+    for (int o = 1; o < nrep; o <<= 1)
+        lim = fminf(lim, __shfl_xor(lim, o, 64));
+    if (ract && rj == 0)
+        dt_out[perm[sr]] = lim;
+    float mn = ract ? lim : inf;
+    mn = wave_minf(mn);
+    if (lane == 0 && mn < inf)
+        atomicMin(dt_min, __float_as_int(mn));
 }
 
 __global__ void k_fill_inf(int32_t *p)
