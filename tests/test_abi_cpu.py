@@ -147,3 +147,31 @@ def test_grid_build_sets_rejects_null_arguments():
     assert sphx.lib.sphx_grid_build_sets(None, C.byref(pv), off, 1, None, C.byref(h)) == \
         sphx.E_INVALID
     assert "NULL" in sphx.last_error()
+
+
+def test_struct_layouts_match_the_header(sphx, tmp_path):
+    """Every struct the binding passes through the C-ABI has the header's
+    size and field offsets (a C program built from include/sphx.h prints
+    them), so no call reads or writes past a Python-side struct."""
+    import os
+    import subprocess
+    structs = {"sphx_params": sphx.Params, "sphx_particles": sphx.Particles,
+               "sphx_density_out": sphx.DensityOut, "sphx_ghost_out": sphx.GhostOut,
+               "sphx_force_out": sphx.ForceOut, "sphx_step_info": sphx.StepInfo}
+    lines = ['#include <stdio.h>', '#include "sphx.h"', "int main(void) {"]
+    for name, cls in structs.items():
+        lines.append('printf("%s %%zu\\n", sizeof(%s));' % (name, name))
+        for f in cls._fields_:
+            lines.append('printf("%s.%s %%zu\\n", offsetof(%s, %s));' % (name, f[0], name, f[0]))
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    subprocess.run(["gcc", "-I", inc, str(src), "-o", str(exe)], check=True)
+    got = dict(l.split() for l in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                 text=True).stdout.splitlines())
+    for name, cls in structs.items():
+        assert int(got[name]) == C.sizeof(cls), name
+        for f in cls._fields_:
+            assert int(got["%s.%s" % (name, f[0])]) == getattr(cls, f[0]).offset, (name, f[0])
