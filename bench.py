@@ -479,13 +479,15 @@ def sphenix_leg(params, n_steps=20):
     run.step()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    n_int = 0
+    # interactions summed on the device (no read-back inside the loop)
+    n_dev = torch.zeros((), dtype=torch.int64, device=run.out.d["nngb"].device)
     for _ in range(n_steps):
         run.step()
-        n_int += int(run.out.d["nngb"].to(torch.int64).sum() +
-                     run.out.f["nforce"].to(torch.int64).sum())
+        n_dev += run.out.d["nngb"].sum(dtype=torch.int64)
+        n_dev += run.out.f["nforce"].sum(dtype=torch.int64)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    n_int = int(n_dev.item())
     rec = {"workload": CONFIGS["sedov"][0] + ", multi-step SPHENIX", "steps": n_steps,
            "ms_per_step": wall / n_steps * 1e3, "interactions_per_s": n_int / wall,
            "t_end": run.state.t,
