@@ -30,9 +30,11 @@ class SphenixRun:
         from paper_2305_13380_amd import sphx
         self.sphx = sphx
         # a new grid of the same set every step: its builds reuse the last
-        # grid's buffers instead of allocating
+        # grid's buffers instead of allocating, and no step is captured (a
+        # captured step replays only on the grid it was recorded for)
         p = sphx.default_params() if params is None else type(params).from_buffer_copy(params)
         p.recycle_workspace = 1
+        p.graph_passes = 0
         self.ctx = sphx.Context(p, 0)
         self.dp = sphx.DeviceParticles.from_set(ps, device)
         self.out = sphx.Outputs(ps.n, device)
