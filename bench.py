@@ -346,14 +346,14 @@ def choose_graph(params, dp, out, h0, info):
     return (k if t_g < t_0 else 0), {"slots": k, "captured_ms": t_g, "pass_by_pass_ms": t_0}
 
 
-def step_leg(name, params, steps=5, warmup=1, flavour=None, graph=-1):
+def step_leg(name, params, steps=5, warmup=1, flavour=None, graph=-1, tune=False):
     """One more workload of the step, timed like the headline one (HIP events
     on the stream around `steps` whole steps from the generator's h, inputs
     resident): the Sedov box and the large box with its active subset (after
     an untimed all-active step that gives the inactive particles their
     state), or the headline box with another SPH flavour (the density-entropy
     one with A set from u, the smoothed-pressure and GDF ones on the same
-    u)."""
+    u); tune: the leg's loop shapes by the autotuner on its own workload."""
     import numpy as np
     import torch
     from paper_2305_13380_amd import inputs, sphx
@@ -404,6 +404,20 @@ def step_leg(name, params, steps=5, warmup=1, flavour=None, graph=-1):
         c1.close()
         dp.t["active"] = act
         dp.t["h"].copy_(torch.where(act.bool(), h_guess, dp.t["h"]))
+    shapes = None
+    if tune:
+        # the flavour's own loop shapes (its loops differ from the headline
+        # flavour's), by the autotuner on this workload at its initial h
+        c0 = sphx.Context(params, 0)
+        g0 = sphx.Grid(c0, dp)
+        k0 = sphx.Tasks(c0, g0, dp)
+        params = sphx.autotune(c0, g0, k0, dp, out, reps=3)
+        torch.cuda.synchronize()
+        k0.close()
+        g0.close()
+        c0.close()
+        shapes = {k: getattr(params, k) for k in ("density_tile", "density_waves",
+                                                  "density_balance", "force_tile", "force_waves")}
     h0 = dp.t["h"].clone()
     # the warm-up pass by pass, then the timed steps captured (graph_slots)
     p0 = type(params).from_buffer_copy(params)
@@ -450,6 +464,7 @@ def step_leg(name, params, steps=5, warmup=1, flavour=None, graph=-1):
            "n_force": n_force, "density_passes": infos[-1].passes,
            "task_rebuilds_per_step": infos[-1].task_rebuilds,
            "graph_passes": int(params.graph_passes), "graph_choice": choice, "steps": steps,
+           "loop_shapes": shapes if shapes is not None else "the headline's",
            "momentum_err_rel": float(np.abs(sums[:3]).max() / max(sums[4], 1e-300)),
            "timed": "HIP events on the stream around whole steps from the generator's h "
                     "(h iteration with task rebuilds, ghost, force, FP64 sums); inputs "
@@ -900,17 +915,21 @@ def main():
                     "loops' lane slots that evaluate a list entry"}
     del grid, tasks, out
     if not args.no_legs and args.config == "clustered":
+        # the flavour legs tune their own loop shapes unless the headline's
+        # were fixed (--no-tune, --shape)
+        tune_legs = not args.no_tune and not args.shape
         line["other_workloads"] = {
             "sedov": step_leg("sedov", params, steps=10, graph=args.graph),
             "large": step_leg("large", params, steps=3, graph=args.graph),
             "clustered_entropy": step_leg("clustered", params, steps=5, flavour="entropy",
-                                          graph=args.graph),
+                                          graph=args.graph, tune=tune_legs),
             "clustered_pressure_energy": step_leg("clustered", params, steps=5,
-                                                  flavour="pressure_energy", graph=args.graph),
+                                                  flavour="pressure_energy", graph=args.graph,
+                                                  tune=tune_legs),
             "clustered_anarchy_pu": step_leg("clustered", params, steps=5, flavour="anarchy_pu",
-                                             graph=args.graph),
+                                             graph=args.graph, tune=tune_legs),
             "clustered_gdf": step_leg("clustered", params, steps=5, flavour="gdf",
-                                      graph=args.graph),
+                                      graph=args.graph, tune=tune_legs),
         }
         line["sphenix_run"] = sphenix_leg(params)
     if not args.no_fof:
