@@ -149,8 +149,9 @@ typedef struct sphx_params {
      * released at its end, and any rest at sphx_ctx_destroy. For runs that
      * build a new grid of one particle set every step, whose builds then
      * allocate little or nothing. Grids built so must be destroyed before
-     * their context. Default 0: a grid's buffers are released when it is
-     * destroyed. */
+     * their context, and the stream of the last one destroyed must outlive
+     * the context (the buffers it leaves are freed on that stream). Default
+     * 0: a grid's buffers are released when it is destroyed. */
     int32_t recycle_workspace;
 } sphx_params;
 
