@@ -248,3 +248,31 @@ def test_gdf_loop_other_kernels(name):
     # the step's own f and alpha_c are the loop's (the same inputs)
     np.testing.assert_array_equal(out.g["f"].cpu().numpy(), f.cpu().numpy())
     np.testing.assert_array_equal(out.g["A"].cpu().numpy(), ac.cpu().numpy())
+
+
+@pytest.mark.parametrize("frac", [0.03, 0.4])
+def test_gdf_loop_sparse_active(frac):
+    """The GDF loop for a sparse set of active receivers (cells with few of
+    them give each several lanes, whose sums meet in a butterfly)."""
+    import torch
+    from paper_2305_13380_amd import sphx
+    ps = inputs.lognormal_box(16, 6000, 2.0, 77, sigma_v=0.3)
+    print("gdf loop, active fraction %g N=%d" % (frac, ps.n), flush=True)
+    ctx = sphx.Context(sphx.default_params(), 0)
+    dp = sphx.DeviceParticles.from_set(ps)
+    out = sphx.Outputs(ps.n)
+    grid = sphx.Grid(ctx, dp)
+    tasks = sphx.Tasks(ctx, grid, dp)
+    st, _ = sphx.step(ctx, grid, tasks, dp, out)
+    assert st >= 0
+    act = (np.random.default_rng(78).uniform(size=ps.n) < frac).astype(np.uint8)
+    dp.t["active"] = torch.from_numpy(act).cuda()
+    f, ac = sphx.gdf(ctx, grid, tasks, dp, out.d["rho"])
+    torch.cuda.synchronize()
+    h = dp.t["h"].cpu().numpy().astype(np.float64)
+    rho = out.d["rho"].cpu().numpy().astype(np.float64)
+    recv = np.nonzero(act)[0]
+    f_ref, ac_ref = oracle.gdf(ps, h, rho, PG, recv=recv)
+    fg, acg = f.cpu().numpy(), ac.cpu().numpy()
+    check_gdf(fg[recv], acg[recv], f_ref, ac_ref, "gdf loop, active %g" % frac)
+    assert np.all(np.isnan(fg[act == 0])) and np.all(np.isnan(acg[act == 0]))

@@ -176,6 +176,33 @@ def test_timestep_matches_oracle():
     np.testing.assert_allclose(g.min(), ref.min(), rtol=2e-6)
 
 
+@pytest.mark.parametrize("frac", [0.03, 0.4])
+def test_timestep_active_subset(frac):
+    """The step limiter for a sparse set of active receivers (cells with few
+    of them give each several lanes): their limited steps within the
+    oracle's at a support 1e-6 smaller and larger, the others untouched."""
+    import torch
+    from paper_2305_13380_amd import sphx
+    ps = inputs.lognormal_box(16, 6000, 2.0, 57, sigma_v=0.3)
+    print("timestep, active fraction %g N=%d" % (frac, ps.n), flush=True)
+    ctx, dp, out, grid, tasks = stepped(ps)
+    act = (np.random.default_rng(58).uniform(size=ps.n) < frac).astype(np.uint8)
+    dp.t["active"] = torch.from_numpy(act).cuda()
+    vs = out.f["v_sig"].clone()
+    vs[np.nonzero(act == 0)[0][:3].tolist()] *= 1e3  # inactive tiny steps still cap
+    dt, mn = sphx.timestep(ctx, grid, tasks, dp, vs, 0.2, 4.0)
+    torch.cuda.synchronize()
+    h = host(dp.t["h"])
+    recv = np.nonzero(act)[0]
+    cfl = oracle.dt_cfl(h, host(vs), P, 0.2)
+    lo = oracle.dt_limit(ps, h * (1 + 1e-6), cfl, P, recv=recv)
+    hi = oracle.dt_limit(ps, h * (1 - 1e-6), cfl, P, recv=recv)
+    g = host(dt)
+    assert np.all((g[recv] >= lo * (1 - 2e-6)) & (g[recv] <= hi * (1 + 2e-6)))
+    assert np.all(np.isnan(g[act == 0]))
+    assert float(mn.item()) == g[recv].min()
+
+
 def test_kick_and_drift_match_oracle():
     import torch
     from paper_2305_13380_amd import sphx
