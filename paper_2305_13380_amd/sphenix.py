@@ -111,3 +111,35 @@ class SphenixRun:
             self.grid.close()
             self.tasks = self.grid = None
         self.ctx.close()
+
+
+def _main():
+    """A SPHENIX run of the 64^3 Sedov box (one unit of energy in the central
+    particles): python -m paper_2305_13380_amd.sphenix [--steps N]."""
+    import argparse
+    import sys
+    import time
+    import torch
+    from paper_2305_13380_amd import inputs
+    ap = argparse.ArgumentParser(description=_main.__doc__.split("\n")[0])
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    a = ap.parse_args()
+    ps = inputs.config_sedov(2)
+    ps.alpha_v[:] = 0.1
+    ps.alpha_c[:] = 0.0
+    run = SphenixRun(ps, c_cfl=0.1)
+    for _ in range(a.warmup):
+        run.step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run.run(a.steps)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / max(a.steps, 1) * 1e3
+    print("sphenix: %d steps, %.3f ms per step, t = %.4g" % (a.steps, ms, run.state.t),
+          file=sys.stderr, flush=True)
+    run.close()
+
+
+if __name__ == "__main__":
+    _main()
