@@ -150,8 +150,8 @@ __global__ __launch_bounds__(64) void k_gradient(
     while (2 * nrep * n_act <= 64)
         nrep *= 2;
     __shared__ uint8_t rmap[64];
-    // x, y, z (receiver cell frame), m; vx, vy, vz, u; rho, P, alpha_V, c
-    // (c: Anarchy-PU's sound speed, else 0)
+    // x, y, z (receiver cell frame), m; vx, vy, vz, u; m / rho, P, alpha_V
+    // and Anarchy-PU's sound speed c (the other flavours: rho)
     __shared__ float4 cp[kCandCap + 1], cv[kCandCap + 1], cs[kCandCap + 1];
     __shared__ uint32_t lst[kListStride * 16];
     uint8_t *my_list = reinterpret_cast<uint8_t *>(lst) + lane * kListStride;
@@ -160,7 +160,7 @@ __global__ __launch_bounds__(64) void k_gradient(
     if (lane == 0) {
         cp[kCandCap] = make_float4(kFarSource, kFarSource, kFarSource, 0.0f);
         cv[kCandCap] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        cs[kCandCap] = make_float4(1.0f, 0.0f, 0.0f, 0.0f);
+        cs[kCandCap] = make_float4(0.0f, 0.0f, 0.0f, 1.0f);
     }
     __syncthreads();
     const int k = lane / nrep;
@@ -193,12 +193,13 @@ __global__ __launch_bounds__(64) void k_gradient(
         const float u = fminf(r * invH, 1.0f);
         // dW/dr / r = -kD H^-5 phi(u)
         const float wr = -kD * invH5 * Kern<K>::phi(u);
-        const float dl = p.w / sj.x * (vi.w - v.w) * wr;
+        const float dl = sj.x * (vi.w - v.w) * wr;
         const float vdx = (vi.x - v.x) * dx + (vi.y - v.y) * dy + (vi.z - v.z) * dz;
         const float vcij =
             anarchy_gamma > 0.0f
                 ? ci + sj.w + fminf(vdx, 0.0f) * rinv
-                : fabsf(vdx) * rinv + fast_sqrt(2.0f * fabsf(si.z - sj.y) / (si.y + sj.x));
+                : fabsf(vdx) * rinv +
+                      fast_sqrt(2.0f * fabsf(si.z - sj.y) * fast_rcp(si.y + sj.w));
         lap += on ? dl : 0.0f;
         vcm = on ? fmaxf(vcm, vcij) : vcm;
         avm = on ? fmaxf(avm, sj.z) : avm;
@@ -250,8 +251,8 @@ __global__ __launch_bounds__(64) void k_gradient(
                          cp[pos] = p;
                          cv[pos] = q1[j];
                          cs[pos] = make_float4(
-                             sj.y, sj.z, sj.w,
-                             anarchy_gamma > 0.0f ? sqrtf(anarchy_gamma * sj.z / sj.y) : 0.0f);
+                             p.w / sj.y, sj.z, sj.w,
+                             anarchy_gamma > 0.0f ? sqrtf(anarchy_gamma * sj.z / sj.y) : sj.y);
                      }
                      nc += tot;
                  });
