@@ -71,9 +71,11 @@
  *    the sound speed is sqrt(gamma P_hat / rho); the viscosity is that of
  *    the density flavours and there is no conduction.
  *  - GDF (Appendix A): the mean gradient is G / 2 with G = f_i W'_i + f_j
- *    W'_j (f the geometric-density correction); |S| is the square root of
- *    the summed squares of the trace-free shear (the paper prints the plain
- *    sum); the conduction term is taken with the sign that carries heat
+ *    W'_j (f the geometric-density correction), both terms gradients with
+ *    respect to the receiver's position (the printed second term carries
+ *    the source's); |S| is the square root of the summed squares of the
+ *    trace-free shear (the paper prints the plain sum), the divergence
+ *    removed from its diagonal being the trace of the same tensor V; the conduction term is taken with the sign that carries heat
  *    from hot to cold; a receiver without neighbours gets f = 1 and
  *    alpha_c = 0; the viscosity is that of the density flavours and the
  *    alpha_V evolution from the shock detector is not built.
