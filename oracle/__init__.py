@@ -99,6 +99,13 @@ def lib():
         L.or_gdf.argtypes = ([C.c_int64] + [_dp] * 10 + [C.c_int, C.c_double, C.c_int,
                              C.c_double, C.c_int64, _nullable(_ip), _nullable(_ip),
                              _nullable(_ip), _dp, _dp])
+        L.or_gdf_detector.argtypes = ([C.c_int64] + [_dp] * 10 + [C.c_int, C.c_double,
+                                      C.c_int, C.c_double, C.c_int64, _nullable(_ip),
+                                      _nullable(_ip), _nullable(_ip), _dp])
+        L.or_gdf_detector.restype = None
+        L.or_gdf_alpha_v_update.argtypes = [C.c_int64] + [_dp] * 6 + [C.c_double,
+                                                                      C.c_double, _dp]
+        L.or_gdf_alpha_v_update.restype = None
         L.or_gdf.restype = None
         L.or_alpha_c_update.argtypes = ([C.c_int64] + [_dp] * 5 + [C.c_double] * 6 + [_dp])
         L.or_alpha_c_update.restype = None
@@ -726,6 +733,33 @@ def gdf(ps, h, rho, params: Params, recv=None, mode="auto"):
                  _f64(rho), _f64(ps.box), int(params.periodic), float(params.gamma_k),
                  params.kernel_id(), float(GDF_C), nrecv, r, off, idx, f, ac)
     return f, ac
+
+
+def gdf_detector(ps, h, params: Params, recv=None, mode="auto"):
+    """The GDF shock detector D of the receivers (or_gdf_detector)."""
+    mode = _resolve_mode(mode, ps.n)
+    h = _f64(h)
+    r, nrecv = _recv_arr(recv, ps.n)
+    off = idx = None
+    if mode == "tree":
+        off, idx = density_candidates(ps, h, params, r)
+    D = np.zeros(nrecv)
+    x, y, z = _pos(ps)
+    lib().or_gdf_detector(ps.n, x, y, z, _f64(ps.vx), _f64(ps.vy), _f64(ps.vz), _f64(ps.m),
+                          _f64(ps.u), h, _f64(ps.box), int(params.periodic),
+                          float(params.gamma_k), params.kernel_id(), float(params.gamma_gas),
+                          nrecv, r, off, idx, D)
+    return D
+
+
+def gdf_alpha_v_update(alpha, D_old, D_new, c, h, vsig, B, dt, alpha_max=SPHENIX_ALPHA_V_MAX):
+    """New GDF viscosity parameter of every particle after a step dt
+    (or_gdf_alpha_v_update; alpha_max read as SPHENIX's, which the paper
+    does not restate for this flavour)."""
+    a = _f64(alpha).copy()
+    lib().or_gdf_alpha_v_update(a.shape[0], _f64(D_old), _f64(D_new), _f64(c), _f64(h),
+                                _f64(vsig), _f64(B), float(dt), float(alpha_max), a)
+    return a
 
 
 def alpha_c_update(alpha, lap_u, u, h, vc, avmax, dt, params: Params,

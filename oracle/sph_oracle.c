@@ -918,6 +918,91 @@ void or_gdf(int64_t n, const double *x, const double *y, const double *z,
 }
 
 /*
+ * GDF shock detector (Appendix A). For receiver k (particle i) over every j
+ * with r_ij < H_i (W_ij = W(r_ij, h_i)):
+ *   grad P_i = (gamma - 1) sum_j m_j u_j (dW/dr)(r_ij, h_i) x_ij / r_ij
+ *              (x_ij = x_i - x_j; pairs at r = 0 have no direction),
+ *   n_i = grad P_i / |grad P_i|,  dv/dn_i = sum_ab n_a V_ab n_b with V the
+ *   velocity-gradient tensor of or_gdf, div v_i = V_xx + V_yy + V_zz,
+ *   D_i = 3/2 [dv/dn_i + max(-div v_i / 3, 0)].
+ * A receiver without a pressure gradient (|grad P| = 0) has no direction:
+ * dv/dn = 0 there; one without neighbours at r > 0 gets D = 0.
+ */
+void or_gdf_detector(int64_t n, const double *x, const double *y, const double *z,
+                     const double *vx, const double *vy, const double *vz, const double *m,
+                     const double *u, const double *h, const double *box, int periodic,
+                     double gamma_k, int kernel, double gamma_gas, int64_t nrecv,
+                     const int64_t *recv, const int64_t *cand_off, const int64_t *cand_idx,
+                     double *D_out)
+{
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t k = 0; k < nrecv; ++k) {
+        int64_t i = recv ? recv[k] : k;
+        double Hi = gamma_k * h[i];
+        double S1 = 0.0, gp[3] = {0, 0, 0};
+        double V[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+        int64_t jb = cand_off ? cand_off[k] : 0;
+        int64_t je = cand_off ? cand_off[k + 1] : n;
+        for (int64_t q = jb; q < je; ++q) {
+            int64_t j = cand_off ? cand_idx[q] : q;
+            double d[3] = {min_image(x[i] - x[j], box[0], periodic),
+                           min_image(y[i] - y[j], box[1], periodic),
+                           min_image(z[i] - z[j], box[2], periodic)};
+            double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+            double r = sqrt(r2);
+            if (!(r < Hi) || !(r > 0.0))
+                continue;
+            double w, dwdr, dwdh;
+            or_kernel(kernel, r, h[i], gamma_k, &w, &dwdr, &dwdh);
+            double dv[3] = {vx[i] - vx[j], vy[i] - vy[j], vz[i] - vz[j]};
+            S1 += m[j] * r2 * w;
+            for (int a2 = 0; a2 < 3; ++a2) {
+                gp[a2] += (gamma_gas - 1.0) * m[j] * u[j] * dwdr * d[a2] / r;
+                for (int b2 = 0; b2 < 3; ++b2)
+                    V[a2][b2] += dv[a2] * d[b2] * m[j] * w;
+            }
+        }
+        if (!(S1 > 0.0)) {
+            D_out[k] = 0.0;
+            continue;
+        }
+        for (int a2 = 0; a2 < 3; ++a2)
+            for (int b2 = 0; b2 < 3; ++b2)
+                V[a2][b2] /= S1 / 3.0;
+        double gn = sqrt(gp[0] * gp[0] + gp[1] * gp[1] + gp[2] * gp[2]);
+        double dvdn = 0.0;
+        if (gn > 0.0)
+            for (int a2 = 0; a2 < 3; ++a2)
+                for (int b2 = 0; b2 < 3; ++b2)
+                    dvdn += gp[a2] / gn * V[a2][b2] * gp[b2] / gn;
+        double div = V[0][0] + V[1][1] + V[2][2];
+        double comp = -div / 3.0;
+        D_out[k] = 1.5 * (dvdn + (comp > 0.0 ? comp : 0.0));
+    }
+}
+
+/*
+ * GDF viscosity parameter over a step dt (Appendix A): with dD/dt read as
+ * (D_new - D_old) / dt,
+ *   A_i = 2 h_i^2 B_i max(-dD/dt, 0),  alpha_loc = alpha_max A_i / (A_i + v_sig,i^2),
+ * and d alpha / dt = 0.2 c_i (alpha_loc - alpha) / h_i, linear with constant
+ * coefficients over the step, integrated exactly:
+ *   alpha = alpha_loc + (alpha - alpha_loc) exp(-0.2 c_i dt / h_i).
+ * alpha is updated in place.
+ */
+void or_gdf_alpha_v_update(int64_t n, const double *D_old, const double *D_new,
+                           const double *c, const double *h, const double *vsig,
+                           const double *B, double dt, double alpha_max, double *alpha)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        double dD = (D_new[i] - D_old[i]) / dt;
+        double A = 2.0 * h[i] * h[i] * B[i] * (dD < 0.0 ? -dD : 0.0);
+        double loc = A > 0.0 ? alpha_max * A / (A + vsig[i] * vsig[i]) : 0.0;
+        alpha[i] = loc + (alpha[i] - loc) * exp(-0.2 * c[i] * dt / h[i]);
+    }
+}
+
+/*
  * SPHENIX conduction parameter over a step dt (Section 3.3): the evolution
  * equation
  *   d alpha_c / dt = beta_c H lap_u / sqrt(u) - (alpha_c - alpha_c,min) vc / H

@@ -148,3 +148,56 @@ def test_conduction_carries_heat_from_hot_to_cold():
     edge = np.abs(o["du"]) > 1e-9 * np.abs(o["du"]).max()
     assert np.all(o["du"][hot & edge] < 0) and np.all(o["du"][~hot & edge] > 0)
     assert abs((ps.m * o["du"]).sum()) < 1e-12 * (ps.m * np.abs(o["du"])).sum()
+
+
+def linear_flow_with_gradient(A, g):
+    """linear_flow with u = 1 + g . x: the pressure gradient points along g
+    on the lattice (the kernel sum of a linear field is isotropic)."""
+    ps, p, d, inner = linear_flow(A)
+    x = np.stack([ps.x, ps.y, ps.z], 1)
+    ps.u = (1.0 + x @ np.asarray(g, np.float64)).astype(np.float32)
+    return ps, p, inner
+
+
+@pytest.mark.parametrize("A,g", [
+    ([[0.3, 1.0, 0.0], [0.2, -0.1, 0.5], [0.0, 0.4, 0.7]], [0.2, -0.1, 0.3]),
+    ([[-0.9, 0.1, 0.0], [0.3, -0.4, 0.2], [0.0, 0.1, -0.5]], [0.0, 0.0, 0.4]),
+])
+def test_shock_detector_of_a_linear_flow(A, g):
+    """D = 3/2 [n.A.n + max(-tr A / 3, 0)] with n along g: the detector's
+    projection on the pressure gradient and its compression term (a wrong
+    sign of the gradient or a dropped max fails one of the two flows)."""
+    ps, p, inner = linear_flow_with_gradient(A, g)
+    D = oracle.gdf_detector(ps, ps.h, p, recv=inner)
+    A = np.asarray(A, np.float64)
+    n = np.asarray(g, np.float64) / np.linalg.norm(g)
+    want = 1.5 * (n @ A @ n + max(-np.trace(A) / 3.0, 0.0))
+    # (u is stored in FP32: the gradient's direction carries its rounding)
+    assert np.allclose(D, want, rtol=2e-5, atol=1e-12)
+
+
+def test_switch_closed_form_and_limits():
+    """The viscosity parameter: the linear relaxation integrated exactly
+    (closed form), no source where D grows, and alpha_loc -> alpha_max for a
+    collapse much faster than v_sig^2 / h^2."""
+    rng = np.random.default_rng(7)
+    n = 500
+    a0 = rng.uniform(0, 2, n)
+    Dold = rng.normal(0, 5, n)
+    Dnew = rng.normal(0, 5, n)
+    c = rng.uniform(0.5, 2, n)
+    h = rng.uniform(0.01, 0.05, n)
+    vs = rng.uniform(1, 3, n)
+    B = rng.uniform(0, 1, n)
+    dt = 1e-3
+    a = oracle.gdf_alpha_v_update(a0, Dold, Dnew, c, h, vs, B, dt)
+    A = 2 * h * h * B * np.maximum(-(Dnew - Dold) / dt, 0)
+    loc = 2.0 * A / (A + vs * vs)
+    want = loc + (a0 - loc) * np.exp(-0.2 * c * dt / h)
+    assert np.allclose(a, want, rtol=1e-13, atol=0)
+    # D growing: pure decay
+    a = oracle.gdf_alpha_v_update(a0, Dold, Dold + 1.0, c, h, vs, B, dt)
+    assert np.allclose(a, a0 * np.exp(-0.2 * c * dt / h), rtol=1e-13)
+    # a collapse: alpha_loc close to alpha_max, reached after many decay times
+    a = oracle.gdf_alpha_v_update(np.zeros(n), Dold, Dold - 1e15, c, h, vs, np.ones(n), 1e3)
+    assert np.allclose(a, 2.0, rtol=1e-6)
