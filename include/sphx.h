@@ -510,16 +510,35 @@ sphx_status sphx_gradient(sphx_ctx *ctx, sphx_grid *grid, const sphx_tasks *task
  *                and |S| the square root of its summed squares (the paper
  *                prints the plain sum; the root gives alpha_c the dimension
  *                of a diffusivity).
+ * D != NULL also receives the shock detector of the flavour's viscosity switch,
+ *   D[i]       = 3/2 [n_i . V_i . n_i + max(-tr V_i / 3, 0)], n_i the direction
+ *                of grad P_i = (gamma - 1) sum_j m_j u_j grad_i W_ij (n.V.n = 0
+ *                without a gradient; D = 0 without neighbours at r > 0).
  * A receiver with no neighbour at r > 0 gets f = 1 and alpha_c = 0. Reads
  * positions, velocities and masses of the grid (as copied at its build), and
  * h (in) and rho (device, caller order, n FP32: e.g. sphx_density_out.rho)
- * of every particle. Outputs: device FP32 arrays of n in caller order,
- * written for active particles only (for SPHX_FLAVOUR_GDF's force pass,
- * sphx_ghost_out.f and .A). Any flavour may call it. Uses the grid's scratch
- * (not safe concurrently with another call on the same grid). Asynchronous. */
+ * of every particle, and u of the grid for D. Outputs: device FP32 arrays of
+ * n in caller order, written for active particles only (for
+ * SPHX_FLAVOUR_GDF's force pass, sphx_ghost_out.f and .A). Any flavour may
+ * call it. Uses the grid's scratch (not safe concurrently with another call
+ * on the same grid). Asynchronous. */
 sphx_status sphx_gdf(sphx_ctx *ctx, sphx_grid *grid, const sphx_tasks *tasks,
                      const sphx_particles *in, const float *rho, float *f, float *alpha_c,
-                     void *stream);
+                     float *D, void *stream);
+
+/* The GDF flavour's viscosity switch over a step dt (Appendix A), per active
+ * particle i < n (active NULL: all): with dD/dt = (D_new - D_old) / dt from
+ * the detector of sphx_gdf at the start and end of the step,
+ *   A_i = 2 h_i^2 B_i max(-dD/dt, 0),  alpha_loc = 2 A_i / (A_i + v_sig,i^2)
+ * (alpha_V,max = 2, SPHENIX's; B the Balsara switch), and alpha_v relaxes
+ * towards alpha_loc by d alpha/dt = 0.2 c_i (alpha_loc - alpha) / h_i,
+ * integrated exactly over the step. Device FP32 arrays of n; alpha_v is
+ * updated in place. Asynchronous. */
+sphx_status sphx_gdf_alpha_v_update(sphx_ctx *ctx, int64_t n, const float *D_old,
+                                    const float *D_new, const float *c, const float *h,
+                                    const float *v_sig, const float *balsara,
+                                    const uint8_t *active, double dt, float *alpha_v,
+                                    void *stream);
 
 /* SPHENIX conduction parameter over a step dt (Section 3.3), per active
  * particle i < n (active NULL: all): the evolution equation

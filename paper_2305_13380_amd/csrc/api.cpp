@@ -375,7 +375,7 @@ sphx_status sphx_gradient(sphx_ctx *ctx, sphx_grid *grid, const sphx_tasks *task
 
 sphx_status sphx_gdf(sphx_ctx *ctx, sphx_grid *grid, const sphx_tasks *tasks,
                      const sphx_particles *in, const float *rho, float *f, float *alpha_c,
-                     void *stream)
+                     float *D, void *stream)
 {
     SPHX_TRY(check_handles(ctx, grid, tasks, in));
     SPHX_TRY(check_particles(in, false));
@@ -384,7 +384,26 @@ sphx_status sphx_gdf(sphx_ctx *ctx, sphx_grid *grid, const sphx_tasks *tasks,
         return SPHX_E_INVALID;
     }
     SPHX_HIP(hipSetDevice(ctx->device));
-    return gdf_launch(ctx, grid, tasks, in, rho, f, alpha_c, as_stream(stream));
+    return gdf_launch(ctx, grid, tasks, in, rho, f, alpha_c, D, as_stream(stream));
+}
+
+sphx_status sphx_gdf_alpha_v_update(sphx_ctx *ctx, int64_t n, const float *D_old,
+                                    const float *D_new, const float *c, const float *h,
+                                    const float *v_sig, const float *balsara,
+                                    const uint8_t *active, double dt, float *alpha_v,
+                                    void *stream)
+{
+    if (!ctx || n < 0 || !(dt > 0.0) || !std::isfinite(dt)) {
+        set_error("sphx_gdf_alpha_v_update: need a context, n >= 0 and a finite dt > 0");
+        return SPHX_E_INVALID;
+    }
+    if (n > 0 && (!D_old || !D_new || !c || !h || !v_sig || !balsara || !alpha_v)) {
+        set_error("sphx_gdf_alpha_v_update: NULL array");
+        return SPHX_E_INVALID;
+    }
+    SPHX_HIP(hipSetDevice(ctx->device));
+    return gdf_alpha_v_launch(n, D_old, D_new, c, h, v_sig, balsara, active, dt, alpha_v,
+                              as_stream(stream));
 }
 
 sphx_status sphx_alpha_c_update(sphx_ctx *ctx, int64_t n, const float *lap_u, const float *u,

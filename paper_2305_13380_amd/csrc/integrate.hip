@@ -291,9 +291,12 @@ __global__ __launch_bounds__(kElemThreads) void k_hrho_state(int64_t n,
 // f and alpha_c in caller order (f_out, ac_out) and, inside a step, in the
 // sorted force state (g1.x = f, g1.z = alpha_c, the flavour's slots of f
 // and A); null pointers are not written. gate: a captured step whose
-// iteration is not finished returns at once.
-// (The loop shape is the gradient loop's.)
-template <int K>
+// iteration is not finished returns at once. DET: also the shock detector
+// D = 3/2 [n.V.n + max(-tr V / 3, 0)] into D_out (caller order), n along the
+// kernel sum of m_j u_j dW/dr x_ij / r_ij (the pressure gradient's
+// direction: its positive factors and its sign drop out of n.V.n; n.V.n = 0
+// without a gradient). (The loop shape is the gradient loop's.)
+template <int K, bool DET>
 __global__ __launch_bounds__(64) void k_gdf(
     int64_t n_leaves, const int32_t *__restrict__ leaf_start, const int32_t *__restrict__ perm,
     const float4 *__restrict__ q0, const float4 *__restrict__ q1,
@@ -301,7 +304,7 @@ __global__ __launch_bounds__(64) void k_gdf(
     const int32_t *__restrict__ tbeg, const int32_t *__restrict__ tend,
     const Task *__restrict__ task, const float4 *__restrict__ ext, float gamma_k, float C,
     const int32_t *__restrict__ gate, float *__restrict__ f_out, float *__restrict__ ac_out,
-    float4 *__restrict__ g1)
+    float4 *__restrict__ g1, float *__restrict__ D_out)
 {
     if (gate && *gate)
         return;
@@ -341,6 +344,7 @@ __global__ __launch_bounds__(64) void k_gdf(
     // x, y, z (receiver cell frame), m; and vx, vy, vz, m / rho. Slot kCandCap
     // is a source beyond every support that replicas past the buffer read.
     __shared__ float4 cp[kCandCap + 1], cv[kCandCap + 1];
+    __shared__ float cu[DET ? kCandCap + 1 : 1];  // m_j u_j
     __shared__ uint32_t lst[kListStride * 16];
     uint8_t *my_list = reinterpret_cast<uint8_t *>(lst) + lane * kListStride;
     if (act)
@@ -349,6 +353,8 @@ __global__ __launch_bounds__(64) void k_gdf(
         // (finite: its zero weight times its distance stays zero)
         cp[kCandCap] = make_float4(kFarSource, kFarSource, kFarSource, 0.0f);
         cv[kCandCap] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        if constexpr (DET)
+            cu[kCandCap] = 0.0f;
     }
     __syncthreads();
     const int k = lane / nrep;
@@ -364,6 +370,7 @@ __global__ __launch_bounds__(64) void k_gdf(
 
     float S1 = 0.0f, S2 = 0.0f;
     float V[3][3] = {{0.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 0.0f}};
+    float gp[3] = {0.0f, 0.0f, 0.0f};  // DET: the pressure gradient's direction
     int nc = 0;   // candidates in the buffer (wave-uniform)
     int myn = 0;  // this lane's list length
     // One listed pair (on = false: past the list, reading slot 0, adds
@@ -385,6 +392,15 @@ __global__ __launch_bounds__(64) void k_gdf(
 #pragma unroll
             for (int b = 0; b < 3; ++b)
                 V[a][b] += dv[a] * (d[b] * mw);
+        if constexpr (DET) {
+            // m_j u_j (-dW/dr) / r up to positive factors (0 at r = 0 and
+            // past the list)
+            const float rinv = on && r2 > 0.0f ? fast_rsq(r2) : 0.0f;
+            const float gw = cu[c] * Kern<K>::mdw(u) * rinv;
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+                gp[a] += gw * d[a];
+        }
     };
     auto compute = [&]() __attribute__((always_inline)) {
         for (int k4 = 0; __any(k4 < myn); k4 += 4) {
@@ -432,6 +448,8 @@ __global__ __launch_bounds__(64) void k_gdf(
                          const float4 v = q1[j];
                          cp[pos] = p;
                          cv[pos] = make_float4(v.x, v.y, v.z, p.w / st[j].y);
+                         if constexpr (DET)
+                             cu[pos] = p.w * v.w;
                      }
                      nc += tot;
                  });
@@ -446,6 +464,9 @@ __global__ __launch_bounds__(64) void k_gdf(
 #pragma unroll
             for (int b = 0; b < 3; ++b)
                 V[a][b] += __shfl_xor(V[a][b], o, 64);
+        if constexpr (DET)
+            for (int a = 0; a < 3; ++a)
+                gp[a] += __shfl_xor(gp[a], o, 64);
     }
     if (!ract || rj != 0)
         return;
@@ -465,6 +486,23 @@ __global__ __launch_bounds__(64) void k_gdf(
         ac = C * (k3 * sqrtf(ss)) * (si.x * si.x);
     }
     const int32_t gi = perm[sr];
+    if constexpr (DET) {
+        float D = 0.0f;
+        if (S1 > 0.0f) {
+            const float k3 = 3.0f / S1;
+            const float gn2 = gp[0] * gp[0] + gp[1] * gp[1] + gp[2] * gp[2];
+            float nvn = 0.0f;
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int b = 0; b < 3; ++b)
+                    nvn += gp[a] * V[a][b] * gp[b];
+            nvn = gn2 > 0.0f ? k3 * nvn / gn2 : 0.0f;
+            const float comp = -k3 * (V[0][0] + V[1][1] + V[2][2]) * (1.0f / 3.0f);
+            D = 1.5f * (nvn + fmaxf(comp, 0.0f));
+        }
+        D_out[gi] = D;
+    }
     if (f_out)
         f_out[gi] = f;
     if (ac_out)
@@ -762,17 +800,25 @@ sphx_status gradient_launch(const sphx_ctx *ctx, sphx_grid *g, const sphx_tasks 
 
 sphx_status gdf_launch(const sphx_ctx *ctx, sphx_grid *g, const sphx_tasks *t,
                        const sphx_particles *in, const float *rho, float *f, float *alpha_c,
-                       hipStream_t s)
+                       float *D, hipStream_t s)
 {
     if (g->n == 0 || g->n_leaves == 0)
         return SPHX_OK;
     k_hrho_state<<<elem_blocks(g->n), kElemThreads, 0, s>>>(g->n, g->perm, in->h, rho, g->g2);
     SPHX_HIP(hipGetLastError());
-    SPHX_WITH_KERNEL(ctx->p.kernel,
-                     (k_gdf<KK><<<unsigned(g->n_leaves), 64, 0, s>>>(
-                         g->n_leaves, g->leaf_start, g->perm, g->q0, g->q1, g->g2, in->active,
-                         t->slot, t->end, t->task, g->leaf_ext, float(ctx->p.gamma_k),
-                         float(kGdfC), nullptr, f, alpha_c, nullptr)));
+    if (D) {
+        SPHX_WITH_KERNEL(ctx->p.kernel,
+                         (k_gdf<KK, true><<<unsigned(g->n_leaves), 64, 0, s>>>(
+                             g->n_leaves, g->leaf_start, g->perm, g->q0, g->q1, g->g2, in->active,
+                             t->slot, t->end, t->task, g->leaf_ext, float(ctx->p.gamma_k),
+                             float(kGdfC), nullptr, f, alpha_c, nullptr, D)));
+    } else {
+        SPHX_WITH_KERNEL(ctx->p.kernel,
+                         (k_gdf<KK, false><<<unsigned(g->n_leaves), 64, 0, s>>>(
+                             g->n_leaves, g->leaf_start, g->perm, g->q0, g->q1, g->g2, in->active,
+                             t->slot, t->end, t->task, g->leaf_ext, float(ctx->p.gamma_k),
+                             float(kGdfC), nullptr, f, alpha_c, nullptr, nullptr)));
+    }
     SPHX_HIP(hipGetLastError());
     return SPHX_OK;
 }
@@ -784,10 +830,10 @@ sphx_status gdf_step_launch(const sphx_ctx *ctx, const sphx_grid *g, const sphx_
         return SPHX_OK;
     // (h, rho) of the force state g0 = (h, rho, P, c); f and alpha_c into g1
     SPHX_WITH_KERNEL(ctx->p.kernel,
-                     (k_gdf<KK><<<unsigned(g->n_leaves), 64, 0, s>>>(
+                     (k_gdf<KK, false><<<unsigned(g->n_leaves), 64, 0, s>>>(
                          g->n_leaves, g->leaf_start, g->perm, g->q0, g->q1, g->g0, in->active,
                          t->slot, t->end, t->task, g->leaf_ext, float(ctx->p.gamma_k),
-                         float(kGdfC), gate, nullptr, nullptr, g->g1)));
+                         float(kGdfC), gate, nullptr, nullptr, g->g1, nullptr)));
     SPHX_HIP(hipGetLastError());
     return SPHX_OK;
 }

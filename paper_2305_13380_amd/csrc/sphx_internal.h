@@ -383,7 +383,11 @@ sphx_status gradient_launch(const sphx_ctx *ctx, sphx_grid *g, const sphx_tasks 
 // complete for every particle), gated like the force pass.
 sphx_status gdf_launch(const sphx_ctx *ctx, sphx_grid *g, const sphx_tasks *t,
                        const sphx_particles *in, const float *rho, float *f, float *alpha_c,
-                       hipStream_t s);
+                       float *D, hipStream_t s);
+sphx_status gdf_alpha_v_launch(int64_t n, const float *D_old, const float *D_new,
+                               const float *c, const float *h, const float *vsig,
+                               const float *B, const uint8_t *active, double dt, float *alpha,
+                               hipStream_t s);
 sphx_status gdf_step_launch(const sphx_ctx *ctx, const sphx_grid *g, const sphx_tasks *t,
                             const sphx_particles *in, const int32_t *gate, hipStream_t s);
 sphx_status alpha_c_launch(const sphx_ctx *ctx, int64_t n, const float *lap_u, const float *u,

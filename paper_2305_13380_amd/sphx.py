@@ -82,7 +82,7 @@ SYMBOLS = ("sphx_params_default", "sphx_ctx_create", "sphx_ctx_destroy", "sphx_w
            "sphx_profile_read", "sphx_autotune", "sphx_params_set_kernel", "sphx_fof",
            "sphx_gravity", "sphx_alpha_v_update", "sphx_force_noalloc", "sphx_gradient",
            "sphx_alpha_c_update", "sphx_timestep", "sphx_kick", "sphx_drift",
-           "sphx_probe_read", "sphx_grid_build_sets", "sphx_gdf")
+           "sphx_probe_read", "sphx_grid_build_sets", "sphx_gdf", "sphx_gdf_alpha_v_update")
 
 _LIB = None
 
@@ -131,7 +131,8 @@ def _load():
                              vp, vp]
     L.sphx_force_noalloc.argtypes = L.sphx_force.argtypes
     L.sphx_gradient.argtypes = [vp, vp, vp, P(Particles), vp, vp, vp, vp, vp, vp]
-    L.sphx_gdf.argtypes = [vp, vp, vp, P(Particles), vp, vp, vp, vp]
+    L.sphx_gdf.argtypes = [vp, vp, vp, P(Particles), vp, vp, vp, vp, vp]
+    L.sphx_gdf_alpha_v_update.argtypes = [vp, i64] + [vp] * 7 + [C.c_double, vp, vp]
     L.sphx_probe_read.argtypes = [vp, P(C.c_uint64), i32]
     L.sphx_probe_read.restype = i32
     L.sphx_alpha_c_update.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, C.c_double, vp, vp]
@@ -158,7 +159,7 @@ def _load():
                  "sphx_tasks_build", "sphx_iter_reset",
                  "sphx_density", "sphx_ghost", "sphx_force", "sphx_step", "sphx_force_noalloc",
                  "sphx_gradient", "sphx_alpha_c_update", "sphx_timestep", "sphx_kick",
-                 "sphx_drift", "sphx_gdf"):
+                 "sphx_drift", "sphx_gdf", "sphx_gdf_alpha_v_update"):
         getattr(L, name).restype = i32
     _LIB = L
     return L
@@ -511,21 +512,35 @@ def gradient(ctx, grid, tasks, parts, out: Outputs, stream=None):
     return tuple(res)
 
 
-def gdf(ctx, grid, tasks, parts, rho, f=None, alpha_c=None, stream=None):
+def gdf(ctx, grid, tasks, parts, rho, f=None, alpha_c=None, stream=None, detector=False):
     """The GDF flavour's correction f and conduction parameter alpha_c
     (sphx_gdf) from the particles' h and the device tensor rho: returns
-    device tensors (f, alpha_c), written for the active particles (given
-    tensors are filled in place; new ones start as NaN)."""
+    device tensors (f, alpha_c), and the shock detector D as a third with
+    detector=True, written for the active particles (given tensors are
+    filled in place; new ones start as NaN)."""
     import torch
     dev = parts.t["x"].device
     if f is None:
         f = torch.full((parts.n,), float("nan"), dtype=torch.float32, device=dev)
     if alpha_c is None:
         alpha_c = torch.full((parts.n,), float("nan"), dtype=torch.float32, device=dev)
+    D = (torch.full((parts.n,), float("nan"), dtype=torch.float32, device=dev)
+         if detector else None)
     pv = parts.view()
     _check(lib.sphx_gdf(ctx.handle, grid.handle, tasks.handle, C.byref(pv), _ptr(rho),
-                        _ptr(f), _ptr(alpha_c), _stream(stream)))
-    return f, alpha_c
+                        _ptr(f), _ptr(alpha_c), _ptr(D), _stream(stream)))
+    return (f, alpha_c, D) if detector else (f, alpha_c)
+
+
+def gdf_alpha_v_update(ctx, alpha_v, D_old, D_new, c, h, v_sig, balsara, dt, active=None,
+                       stream=None):
+    """The GDF viscosity switch over a step dt (sphx_gdf_alpha_v_update):
+    updates the FP32 device tensor alpha_v in place."""
+    _check(lib.sphx_gdf_alpha_v_update(ctx.handle, int(alpha_v.numel()), _ptr(D_old),
+                                       _ptr(D_new), _ptr(c), _ptr(h), _ptr(v_sig),
+                                       _ptr(balsara), _ptr(active), float(dt), _ptr(alpha_v),
+                                       _stream(stream)))
+    return alpha_v
 
 
 def alpha_c_update(ctx, alpha_c, lap_u, u, h, v_c, alpha_v_max, dt, active=None, stream=None):

@@ -276,3 +276,59 @@ def test_gdf_loop_sparse_active(frac):
     fg, acg = f.cpu().numpy(), ac.cpu().numpy()
     check_gdf(fg[recv], acg[recv], f_ref, ac_ref, "gdf loop, active %g" % frac)
     assert np.all(np.isnan(fg[act == 0])) and np.all(np.isnan(acg[act == 0]))
+
+
+def test_gdf_detector_matches_oracle():
+    """The shock detector D of sphx_gdf against the oracle at the GPU's h, on
+    a jittered lattice in an open box with u = 1 + g . x (a pressure gradient
+    whose direction the sums fix well) and random velocities; receivers whose
+    support lies inside the box."""
+    import torch
+    from paper_2305_13380_amd import sphx
+    ps = inputs.lattice_box(16, 79, jitter=0.1, sigma_v=0.3)
+    x = np.stack([ps.x, ps.y, ps.z], 1)
+    ps.u = (1.0 + x @ np.array([0.3, -0.2, 0.4])).astype(np.float32)
+    print("gdf detector N=%d" % ps.n, flush=True)
+    ctx = sphx.Context(sphx.default_params(periodic=0), 0)
+    dp = sphx.DeviceParticles.from_set(ps)
+    out = sphx.Outputs(ps.n)
+    grid = sphx.Grid(ctx, dp)
+    tasks = sphx.Tasks(ctx, grid, dp)
+    st, _ = sphx.step(ctx, grid, tasks, dp, out)
+    assert st >= 0
+    _, _, D = sphx.gdf(ctx, grid, tasks, dp, out.d["rho"], detector=True)
+    torch.cuda.synchronize()
+    h = dp.t["h"].cpu().numpy().astype(np.float64)
+    p = oracle.Params(periodic=False)
+    H = p.gamma_k * h
+    inner = np.nonzero(np.all((x > H[:, None]) & (x < 1.0 - H[:, None]), axis=1))[0]
+    assert inner.size > 100
+    ref = oracle.gdf_detector(ps, h, p, recv=inner)
+    s = np.maximum(np.abs(ref), rms(ref))
+    e = np.abs(D.cpu().numpy()[inner].astype(np.float64) - ref)
+    assert np.all(e <= 1e-3 * s), "D: worst %.3g of its scale" % (e / s).max()
+    assert (ref > 0).sum() > 10 and (ref < 0).sum() > 10  # both signs exercised
+
+
+def test_gdf_switch_matches_oracle():
+    import torch
+    from paper_2305_13380_amd import sphx
+    rng = np.random.default_rng(80)
+    n = 30011
+    a0 = rng.uniform(0, 2, n).astype(np.float32)
+    Dold = rng.normal(0, 5, n).astype(np.float32)
+    Dnew = (Dold + rng.normal(0, 5, n)).astype(np.float32)
+    c = rng.uniform(0.5, 2, n).astype(np.float32)
+    h = rng.uniform(0.01, 0.05, n).astype(np.float32)
+    vs = rng.uniform(1, 3, n).astype(np.float32)
+    B = rng.uniform(0, 1, n).astype(np.float32)
+    act = (rng.uniform(size=n) < 0.7).astype(np.uint8)
+    ctx = sphx.Context(sphx.default_params(**FL), 0)
+    t = [torch.from_numpy(v).cuda() for v in (a0, Dold, Dnew, c, h, vs, B, act)]
+    sphx.gdf_alpha_v_update(ctx, t[0], t[1], t[2], t[3], t[4], t[5], t[6], 1e-3, active=t[7])
+    torch.cuda.synchronize()
+    got = t[0].cpu().numpy().astype(np.float64)
+    ref = oracle.gdf_alpha_v_update(a0, Dold, Dnew, c, h, vs, B, 1e-3)
+    on = act == 1
+    assert np.all(np.abs(got[on] - ref[on]) <= 2e-5 * np.abs(ref[on]) + 1e-7)
+    assert np.array_equal(got[~on], a0[~on].astype(np.float64))
