@@ -530,9 +530,10 @@ sphx_status sphx_gdf(sphx_ctx *ctx, sphx_grid *grid, const sphx_tasks *tasks,
  * particle i < n (active NULL: all): with dD/dt = (D_new - D_old) / dt from
  * the detector of sphx_gdf at the start and end of the step,
  *   A_i = 2 h_i^2 B_i max(-dD/dt, 0),  alpha_loc = 2 A_i / (A_i + v_sig,i^2)
- * (alpha_V,max = 2, SPHENIX's; B the Balsara switch), and alpha_v relaxes
- * towards alpha_loc by d alpha/dt = 0.2 c_i (alpha_loc - alpha) / h_i,
- * integrated exactly over the step. Device FP32 arrays of n; alpha_v is
+ * (alpha_V,max = 2, SPHENIX's; B the Balsara switch); alpha_v rises to
+ * alpha_loc at once where that is larger (as the SPHENIX switch does) and
+ * otherwise relaxes towards it by d alpha/dt = 0.2 c_i (alpha_loc - alpha) /
+ * h_i, integrated exactly over the step. Device FP32 arrays of n; alpha_v is
  * updated in place. Asynchronous. */
 sphx_status sphx_gdf_alpha_v_update(sphx_ctx *ctx, int64_t n, const float *D_old,
                                     const float *D_new, const float *c, const float *h,

@@ -985,7 +985,9 @@ void or_gdf_detector(int64_t n, const double *x, const double *y, const double *
  * GDF viscosity parameter over a step dt (Appendix A): with dD/dt read as
  * (D_new - D_old) / dt,
  *   A_i = 2 h_i^2 B_i max(-dD/dt, 0),  alpha_loc = alpha_max A_i / (A_i + v_sig,i^2),
- * and d alpha / dt = 0.2 c_i (alpha_loc - alpha) / h_i, linear with constant
+ * and, as the paper evolves it like the SPHENIX switch, alpha rises to
+ * alpha_loc at once when alpha_loc is larger and otherwise relaxes by
+ * d alpha / dt = 0.2 c_i (alpha_loc - alpha) / h_i, linear with constant
  * coefficients over the step, integrated exactly:
  *   alpha = alpha_loc + (alpha - alpha_loc) exp(-0.2 c_i dt / h_i).
  * alpha is updated in place.
@@ -998,7 +1000,10 @@ void or_gdf_alpha_v_update(int64_t n, const double *D_old, const double *D_new,
         double dD = (D_new[i] - D_old[i]) / dt;
         double A = 2.0 * h[i] * h[i] * B[i] * (dD < 0.0 ? -dD : 0.0);
         double loc = A > 0.0 ? alpha_max * A / (A + vsig[i] * vsig[i]) : 0.0;
-        alpha[i] = loc + (alpha[i] - loc) * exp(-0.2 * c[i] * dt / h[i]);
+        if (loc > alpha[i])
+            alpha[i] = loc;
+        else
+            alpha[i] = loc + (alpha[i] - loc) * exp(-0.2 * c[i] * dt / h[i]);
     }
 }
 

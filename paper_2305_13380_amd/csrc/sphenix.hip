@@ -30,8 +30,9 @@ __global__ __launch_bounds__(kSwitchThreads) void k_alpha_v(
 
 // The GDF flavour's viscosity parameter (Appendix A): dD/dt = (D_new -
 // D_old) / dt, A = 2 h^2 B max(-dD/dt, 0), alpha_loc = alpha_max A / (A +
-// v_sig^2), and alpha relaxes towards it as exp(-0.2 c dt / h) (the exact
-// solution over the step). Nine FP32 words per particle.
+// v_sig^2); alpha rises to it at once, as the SPHENIX switch does, or else
+// relaxes towards it as exp(-0.2 c dt / h) (the exact solution over the
+// step). Nine FP32 words per particle.
 __global__ __launch_bounds__(kSwitchThreads) void k_gdf_alpha_v(
     int64_t n, const float *__restrict__ D_old, const float *__restrict__ D_new,
     const float *__restrict__ c, const float *__restrict__ h, const float *__restrict__ vsig,
@@ -46,7 +47,8 @@ __global__ __launch_bounds__(kSwitchThreads) void k_gdf_alpha_v(
     const float A = 2.0f * hi * hi * B[i] * fmaxf(-dD, 0.0f);
     const float vs = vsig[i];
     const float loc = A > 0.0f ? alpha_max * A / (A + vs * vs) : 0.0f;
-    alpha[i] = loc + (alpha[i] - loc) * expf(-0.2f * c[i] * dt / hi);
+    const float a = alpha[i];
+    alpha[i] = loc > a ? loc : loc + (a - loc) * expf(-0.2f * c[i] * dt / hi);
 }
 
 }  // namespace

@@ -3,7 +3,9 @@ leapfrog of Section 2.4 and the step limiter of Section 3.4), sequencing the
 library's calls; every operation on particle data runs in its kernels.
 
 One global step (the smallest limited CFL step of the particles) and every
-particle active. Per step: half kick; drift, with v and u predicted to the
+particle active. With the GDF flavour (Appendix A) the switch follows that
+flavour's shock detector, held between steps, and the conduction parameter
+is the one its step forms. Per step: half kick; drift, with v and u predicted to the
 end of the drift by the previous derivatives; a new grid and task list, the
 h iteration, ghost and force pass (sphx_step) with the viscosity and
 conduction parameters of the step before; the viscosity switch; the gradient
@@ -45,7 +47,12 @@ class SphenixRun:
         self.u_pred = f()
         self.state = RunState()
         self.grid = self.tasks = None
+        # the GDF flavour (Appendix A): its switch follows its shock detector
+        # D (held between steps) and its conduction parameter is formed
+        # inside the step
+        self.gdf = p.flavour == sphx.FLAVOURS["gdf"]
         self._evaluate()
+        self.D = self._detector() if self.gdf else None
         self.dt = self._next_dt()
 
     # the particle set the library reads: positions and the predicted v, u
@@ -68,6 +75,11 @@ class SphenixRun:
         self.info = info
         return st, info
 
+    def _detector(self):
+        _, _, D = self.sphx.gdf(self.ctx, self.grid, self.tasks, self.parts, self.out.d["rho"],
+                                detector=True)
+        return D
+
     def _next_dt(self):
         dt, mn = self.sphx.timestep(self.ctx, self.grid, self.tasks, self.parts,
                                     self.out.f["v_sig"], self.c_cfl, self.delta)
@@ -87,10 +99,17 @@ class SphenixRun:
         st, info = self._evaluate(self.v_pred, self.u_pred)
         if st < 0:
             raise RuntimeError("step failed")
-        sphx.alpha_v_update(self.ctx, t["alpha_v"], div_old, o.g["div_v"], o.g["c"], t["h"],
-                            o.f["v_sig"], dt)
-        lap, vc, avmax = sphx.gradient(self.ctx, self.grid, self.tasks, self.parts, o)
-        sphx.alpha_c_update(self.ctx, t["alpha_c"], lap, self.u_pred, t["h"], vc, avmax, dt)
+        if self.gdf:
+            D = self._detector()
+            sphx.gdf_alpha_v_update(self.ctx, t["alpha_v"], self.D, D, o.g["c"], t["h"],
+                                    o.f["v_sig"], o.g["balsara"], dt)
+            self.D = D
+        else:
+            sphx.alpha_v_update(self.ctx, t["alpha_v"], div_old, o.g["div_v"], o.g["c"],
+                                t["h"], o.f["v_sig"], dt)
+            lap, vc, avmax = sphx.gradient(self.ctx, self.grid, self.tasks, self.parts, o)
+            sphx.alpha_c_update(self.ctx, t["alpha_c"], lap, self.u_pred, t["h"], vc, avmax,
+                                dt)
         sphx.kick(self.ctx, v, t["u"], a, o.f["du_dt"], 0.5 * dt)
         self.state.t += dt
         self.state.steps += 1

@@ -177,9 +177,10 @@ def test_shock_detector_of_a_linear_flow(A, g):
 
 
 def test_switch_closed_form_and_limits():
-    """The viscosity parameter: the linear relaxation integrated exactly
-    (closed form), no source where D grows, and alpha_loc -> alpha_max for a
-    collapse much faster than v_sig^2 / h^2."""
+    """The viscosity parameter: an immediate rise to alpha_loc, else the
+    linear relaxation integrated exactly (closed form); no source where D
+    grows; alpha_loc -> alpha_max for a collapse much faster than
+    v_sig^2 / h^2."""
     rng = np.random.default_rng(7)
     n = 500
     a0 = rng.uniform(0, 2, n)
@@ -193,11 +194,12 @@ def test_switch_closed_form_and_limits():
     a = oracle.gdf_alpha_v_update(a0, Dold, Dnew, c, h, vs, B, dt)
     A = 2 * h * h * B * np.maximum(-(Dnew - Dold) / dt, 0)
     loc = 2.0 * A / (A + vs * vs)
-    want = loc + (a0 - loc) * np.exp(-0.2 * c * dt / h)
+    want = np.where(loc > a0, loc, loc + (a0 - loc) * np.exp(-0.2 * c * dt / h))
     assert np.allclose(a, want, rtol=1e-13, atol=0)
+    assert (loc > a0).sum() > 50 and (loc < a0).sum() > 50  # both branches
     # D growing: pure decay
     a = oracle.gdf_alpha_v_update(a0, Dold, Dold + 1.0, c, h, vs, B, dt)
     assert np.allclose(a, a0 * np.exp(-0.2 * c * dt / h), rtol=1e-13)
     # a collapse: alpha_loc close to alpha_max, reached after many decay times
-    a = oracle.gdf_alpha_v_update(np.zeros(n), Dold, Dold - 1e15, c, h, vs, np.ones(n), 1e3)
+    a = oracle.gdf_alpha_v_update(np.zeros(n), Dold, Dold - 1e15, c, h, vs, np.ones(n), dt)
     assert np.allclose(a, 2.0, rtol=1e-6)
