@@ -134,7 +134,8 @@ class SphenixRun:
 
 def _main():
     """A SPHENIX run of the 64^3 Sedov box (one unit of energy in the central
-    particles): python -m paper_2305_13380_amd.sphenix [--steps N]."""
+    particles): python -m paper_2305_13380_amd.sphenix [--steps N]
+    [--flavour energy|gdf]."""
     import argparse
     import sys
     import time
@@ -143,11 +144,13 @@ def _main():
     ap = argparse.ArgumentParser(description=_main.__doc__.split("\n")[0])
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--flavour", default="energy", choices=["energy", "gdf"])
     a = ap.parse_args()
+    from paper_2305_13380_amd import sphx
     ps = inputs.config_sedov(2)
     ps.alpha_v[:] = 0.1
     ps.alpha_c[:] = 0.0
-    run = SphenixRun(ps, c_cfl=0.1)
+    run = SphenixRun(ps, sphx.default_params(flavour=a.flavour), c_cfl=0.1)
     for _ in range(a.warmup):
         run.step()
     torch.cuda.synchronize()
@@ -155,7 +158,8 @@ def _main():
     run.run(a.steps)
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) / max(a.steps, 1) * 1e3
-    print("sphenix: %d steps, %.3f ms per step, t = %.4g" % (a.steps, ms, run.state.t),
+    print("sphenix (%s): %d steps, %.3f ms per step, t = %.4g" % (a.flavour, a.steps, ms,
+                                                                 run.state.t),
           file=sys.stderr, flush=True)
     run.close()
 
